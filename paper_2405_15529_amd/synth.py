@@ -1,0 +1,126 @@
+"""Seeded synthetic snapshot matrices (host, numpy).
+
+This module only draws inputs; it holds none of the decomposition's
+arithmetic and is shared by the tests (oracle side and device side) and by
+the benchmark.  The paper's workloads are CFD fields (Table "test cases":
+2-D cylinder 1.78e5 x 151, Stanford diffuser 1.14e8 x 1808, ...) that are not
+available here; these generators stand in for them with the same structure
+(tall-skinny, smooth decaying spectrum plus noise, or a known spectrum).
+
+Haar-distributed orthogonal factors are drawn as the Q factor of a Gaussian
+matrix with the column signs fixed by sign(diag R) (Mezzadri, 2007), using
+numpy's LAPACK QR as a library primitive.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def haar(rng: np.random.Generator, m: int, n: int, dtype=np.float64) -> np.ndarray:
+    """m x n matrix with Haar-distributed orthonormal columns (m >= n)."""
+    if np.issubdtype(dtype, np.complexfloating):
+        G = (rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))) / np.sqrt(2.0)
+    else:
+        G = rng.standard_normal((m, n))
+    Q, R = np.linalg.qr(G)
+    d = np.diagonal(R)
+    ph = d / np.abs(d)
+    return np.ascontiguousarray(Q * ph[None, :])
+
+
+def known_spectrum(m: int, n: int, s, seed: int, dtype=np.float64):
+    """A = Q1 diag(s) Q2^T with Haar Q1 (m x n), Q2 (n x n).  Returns (A, Q1, Q2)."""
+    rng = np.random.default_rng(seed)
+    cplx = np.issubdtype(dtype, np.complexfloating)
+    Q1 = haar(rng, m, n, np.complex128 if cplx else np.float64)
+    Q2 = haar(rng, n, n, np.complex128 if cplx else np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    A = (Q1 * s[None, :]) @ (Q2.conj().T if cplx else Q2.T)
+    return np.ascontiguousarray(A.astype(dtype)), Q1, Q2
+
+
+def graded_spectrum(n: int, per_decade: float = 32.0) -> np.ndarray:
+    """s_i = 10^(-i/per_decade), i = 0..n-1 (sigma_1 = 1)."""
+    return 10.0 ** (-np.arange(n) / per_decade)
+
+
+def plain_pod_fp64(m: int = 20_000, n: int = 100, seed: int = 0, nmodes: int = 10,
+                   noise: float = 1e-3) -> np.ndarray:
+    """Sum of nmodes standing waves phi_k(x) sin(w_k t + th_k) with random unit
+    phi_k, amplitudes 10^(-k/3) (k = 1..nmodes), w_k ~ U[0.1, 5],
+    th_k ~ U[0, 2 pi), t_j = j, plus noise * N(0, 1).  Draw order: phi, w, th,
+    noise.  Row-major m x n FP64 (rows = points, columns = snapshots)."""
+    rng = np.random.default_rng(seed)
+    phi = rng.standard_normal((nmodes, m))
+    phi /= np.linalg.norm(phi, axis=1, keepdims=True)
+    w = rng.uniform(0.1, 5.0, nmodes)
+    th = rng.uniform(0.0, 2.0 * np.pi, nmodes)
+    t = np.arange(n, dtype=np.float64)
+    a = 10.0 ** (-np.arange(1, nmodes + 1) / 3.0)
+    temporal = a[:, None] * np.sin(w[:, None] * t[None, :] + th[:, None])  # nmodes x n
+    D = phi.T @ temporal
+    D += noise * rng.standard_normal((m, n))
+    return np.ascontiguousarray(D)
+
+
+def graded_fp64(m: int = 1_048_576, n: int = 256, seed: int = 1, per_decade: float = 32.0):
+    """A = Q1 diag(s) Q2^T, Haar Q1 (m x n), Q2 (n x n), s_i = 10^(-i/32).
+    Returns (A, s)."""
+    s = graded_spectrum(n, per_decade)
+    A, _, _ = known_spectrum(m, n, s, seed)
+    return A, s
+
+
+def travelling_waves(m: int, n: int, seed: int = 2, nwaves: int = 64, noise: float = 1e-4,
+                     dtype=np.float32) -> np.ndarray:
+    """Sum of nwaves travelling waves a_k cos(kappa_k x - w_k t + th_k) on a
+    periodic grid x_j = 2 pi j / m, t = 0..n-1, distinct integer wavenumbers
+    kappa_k ~ U{1..min(2048, m/2-1)}, w_k ~ U[0.1, 5], th_k ~ U[0, 2 pi),
+    a_k = 2^(-k/8), plus noise * N(0,1).  Row-major m x n."""
+    rng = np.random.default_rng(seed)
+    kmax = max(2, min(2048, m // 2 - 1))
+    kap = rng.choice(np.arange(1, kmax + 1), size=nwaves, replace=False).astype(np.float64)
+    w = rng.uniform(0.1, 5.0, nwaves)
+    th = rng.uniform(0.0, 2.0 * np.pi, nwaves)
+    a = 2.0 ** (-np.arange(nwaves) / 8.0)
+    x = 2.0 * np.pi * np.arange(m) / m
+    t = np.arange(n, dtype=np.float64)
+    # cos(kx - wt + th) = cos(kx) cos(wt - th) + sin(kx) sin(wt - th)
+    spatial_c = np.cos(np.outer(x, kap))  # m x nwaves
+    spatial_s = np.sin(np.outer(x, kap))
+    arg = np.outer(w, t) - th[:, None]  # nwaves x n
+    D = spatial_c @ (a[:, None] * np.cos(arg)) + spatial_s @ (a[:, None] * np.sin(arg))
+    D += noise * rng.standard_normal((m, n))
+    return np.ascontiguousarray(D.astype(dtype))
+
+
+def spod_field(m: int, nt: int, seed: int = 3, nmodes: int = 32, noise: float = 1e-3,
+               on_bins: int = 0, dtype=np.float32) -> np.ndarray:
+    """nmodes random unit spatial modes, each oscillating at its own random
+    frequency f_k ~ U(0, 0.5) cycles/sample (or, with on_bins = npwin > 0, at
+    random multiples of 1/npwin), phase th_k ~ U[0, 2 pi), amplitude
+    10^(-k/16), plus noise * N(0,1).  Row-major m x nt."""
+    rng = np.random.default_rng(seed)
+    phi = rng.standard_normal((nmodes, m))
+    phi /= np.linalg.norm(phi, axis=1, keepdims=True)
+    if on_bins:
+        f = rng.integers(1, on_bins // 2, nmodes) / float(on_bins)
+    else:
+        f = rng.uniform(0.0, 0.5, nmodes)
+    th = rng.uniform(0.0, 2.0 * np.pi, nmodes)
+    a = 10.0 ** (-np.arange(nmodes) / 16.0)
+    t = np.arange(nt, dtype=np.float64)
+    temporal = a[:, None] * np.cos(2.0 * np.pi * f[:, None] * t[None, :] + th[:, None])
+    D = phi.T @ temporal
+    D += noise * rng.standard_normal((m, nt))
+    return np.ascontiguousarray(D.astype(dtype))
+
+
+def uneven_batch(count: int = 64, seed: int = 4, m_lo: float = 5e4, m_hi: float = 2e6,
+                 n_lo: int = 32, n_hi: int = 512):
+    """Shapes of an uneven POD batch: m_i log-uniform in [m_lo, m_hi],
+    n_i uniform in [n_lo, n_hi].  Returns a list of (m_i, n_i)."""
+    rng = np.random.default_rng(seed)
+    ms = np.round(np.exp(rng.uniform(np.log(m_lo), np.log(m_hi), count))).astype(np.int64)
+    ns = rng.integers(n_lo, n_hi + 1, count)
+    return [(int(a), int(max(b, 1))) for a, b in zip(ms, ns)]
