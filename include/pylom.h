@@ -1,0 +1,175 @@
+/*
+ * pylom.h -- C-ABI of the MI355X (gfx950) POD / tall-skinny SVD library.
+ *
+ * The operations follow pyLOM (Eiximeno et al., "pyLOM: A HPC open source
+ * reduced order model suite for fluid dynamics applications", arXiv
+ * 2405.15529):
+ *
+ *   snapshot matrix  D (M x N, M grid points >> N snapshots), Sec. 3 intro;
+ *   POD              Alg. 2 (optional temporal-mean removal) followed by the
+ *                    TSQR-SVD of Alg. 1 and Eqs. svdqr1-svdqr3:
+ *                      Y = Q [R; 0],  R = U_R S V^T,  U = Q U_R;
+ *   energy           Sec. 3.1, cumulative energy sum_{i<=k} S_i^2 / sum S_i^2;
+ *   truncation       residual r of Alg. 3, read as
+ *                      N_r = min{k >= 1 : sum_{i>k} S_i^2 <= r sum_i S_i^2}
+ *                    (r <= 0 keeps all N modes; an all-zero spectrum keeps 0);
+ *   matmul           Alg. 4 (local products summed over the row partition);
+ *   SPOD             Alg. 6 with the Frame-Towne SVD of Q_f / sqrt(nBlks).
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ *  - Matrices are ROW-MAJOR with an explicit leading dimension (elements
+ *    between consecutive rows).  Rows are grid points, columns snapshots.
+ *  - Every array argument is a DEVICE pointer owned by the caller (allocated
+ *    with hipMalloc or by PyTorch), unless documented as host.  The library
+ *    never frees or retains caller pointers after a call returns.
+ *  - Calls are asynchronous and ordered on the context's stream; outputs are
+ *    valid after that stream is synchronised.  No call synchronises the host
+ *    except where documented.
+ *  - Inputs are never written.  Outputs not listed as written are untouched.
+ *  - Return value 0 = success.  Negative values are caller errors detected on
+ *    the host before any device work is enqueued; positive values are
+ *    numerical warnings (outputs are written).  pylom_strerror() names a
+ *    code; pylom_last_error() returns the context's last message.
+ *  - A context is not thread-safe; separate contexts are independent.  A
+ *    context owns a device workspace that grows on demand (hipMalloc outside
+ *    the call's stream work); pylom_workspace_query() + pylom_reserve() size
+ *    it up front so that later calls allocate nothing.
+ */
+#ifndef PYLOM_H
+#define PYLOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define PYLOM_OK 0
+#define PYLOM_EINVAL (-1)   /* a pointer or scalar argument is invalid      */
+#define PYLOM_ESHAPE (-2)   /* m < n, n < 1, leading dimension too small     */
+#define PYLOM_EDTYPE (-3)   /* unsupported dtype / precision combination     */
+#define PYLOM_ENOMEM (-4)   /* workspace allocation failed or over the cap   */
+#define PYLOM_EHIP (-5)     /* HIP runtime error (message in last_error)     */
+#define PYLOM_ENOTSUP (-6)  /* shape outside what the kernels support        */
+#define PYLOM_ENODEV (-7)   /* no usable gfx950 device                       */
+#define PYLOM_WNOCONV 1     /* Jacobi SVD hit max_sweeps before converging   */
+
+/* ---- storage types ---- */
+typedef enum {
+  PYLOM_R32 = 1,  /* float                                    */
+  PYLOM_R64 = 2,  /* double                                   */
+  PYLOM_C64 = 3,  /* float complex, interleaved (re, im)      */
+  PYLOM_C128 = 4  /* double complex, interleaved (re, im)     */
+} pylom_dtype;
+
+/* ---- compute precision ---- */
+typedef enum {
+  PYLOM_FP64 = 0,  /* every step in FP64 (FP32 inputs promoted on load)      */
+  PYLOM_MIXED = 1  /* FP32 leaf QR, FP64 tree + small SVD, FP64 Rayleigh-Ritz
+                      refinement against the input (FP32 or C64 inputs only) */
+} pylom_prec;
+
+typedef struct pylom_ctx_s* pylom_ctx;
+
+/* Create a context on HIP device `device`.  Fails with PYLOM_ENODEV if the
+ * device is missing or is not gfx950. The stream defaults to the null stream. */
+int pylom_create(pylom_ctx* ctx, int device);
+int pylom_destroy(pylom_ctx ctx);
+
+/* Stream (a hipStream_t passed as void*) on which later calls are ordered. */
+int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
+
+/* Options (int64 values):
+ *   "block_rows"   leaf row-block height b of the TSQR (Alg. 1's local D_i);
+ *                  0 = automatic (default 4096, at least n).
+ *   "max_sweeps"   Jacobi sweep limit (default 40).  0 makes every SVD call
+ *                  return PYLOM_WNOCONV without sweeping (failure-path tests).
+ *   "ws_cap_mb"    workspace cap in MiB (0 = unlimited); a call needing more
+ *                  returns PYLOM_ENOMEM.
+ * Unknown keys return PYLOM_EINVAL. */
+int pylom_set_option(pylom_ctx ctx, const char* key, int64_t value);
+int pylom_get_option(pylom_ctx ctx, const char* key, int64_t* value);
+
+/* Workspace bytes a pod/tsvd/tsqr call of this shape needs (host only). */
+int pylom_workspace_query(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
+                          size_t* bytes);
+/* Grow the context workspace to at least `bytes` now. */
+int pylom_reserve(pylom_ctx ctx, size_t bytes);
+
+const char* pylom_strerror(int status);
+const char* pylom_last_error(pylom_ctx ctx);
+
+/* POD of the snapshot matrix (Alg. 2 -> Alg. 1 -> Eqs. svdqr1-3).
+ *
+ *   D      m x n, leading dimension ldd >= n, dtype PYLOM_R64 or PYLOM_R32.
+ *   remove_mean  nonzero: Y = D - mean 1^T with mean_j = (1/n) sum_t D[j,t]
+ *          (Alg. 2); zero: Y = D.
+ *   residual     truncation residual r (0.01 keeps 99 % of the energy).
+ *   mean   m entries of the storage type, or NULL; written when remove_mean.
+ *   U      m x n capacity (ldu >= n), storage type; the first N_r columns are
+ *          written (spatial modes, orthonormal).
+ *   S      n doubles, all n singular values, descending.
+ *   VT     n x n capacity (ldvt >= n), doubles; the first N_r rows are
+ *          written; row i holds mode i's temporal coefficients (Sec. 3.1).
+ *   n_r    one int64 in device memory: N_r.
+ * Sign convention: each (u_i, v_i) is signed so that the largest-magnitude
+ * entry of v_i (lowest index on ties) is positive.  Requires m >= n >= 1 and
+ * n <= 1024 (FP64) / n <= 2048 (mixed).  In PYLOM_MIXED mode D must be R32.
+ * Returns PYLOM_WNOCONV (>0, outputs written) if the Jacobi SVD did not
+ * converge within max_sweeps -- this is only known after the stream is
+ * synchronised, so the return value of an asynchronous call is 0 and the
+ * warning is reported by the next pylom_check() call. */
+int pylom_pod(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
+              const void* D, int64_t ldd, int remove_mean, double residual, void* mean, void* U,
+              int64_t ldu, double* S, double* VT, int64_t ldvt, int64_t* n_r);
+
+/* Tall-skinny SVD without mean removal (pylom_pod with remove_mean = 0, as
+ * DMD's Alg. 3 applies it to Y[:, :-1]).  Arguments as pylom_pod. */
+int pylom_tsvd(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
+               const void* A, int64_t lda, double residual, void* U, int64_t ldu, double* S,
+               double* VT, int64_t ldvt, int64_t* n_r);
+
+/* TSQR (Alg. 1): A = Q R.
+ *   R  n x n doubles (ldr >= n), upper triangular with diag(R) >= 0, always
+ *      written.
+ *   Q  m x n (ldq >= n) of the storage type, or NULL to skip forming Q.
+ * FP64 compute; dtype PYLOM_R64 or PYLOM_R32 (promoted on load).  Q has
+ * orthonormal columns; for an exactly rank-deficient A the columns attached
+ * to a zero diagonal entry of R are not determined. */
+int pylom_tsqr(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
+               const void* A, int64_t lda, void* Q, int64_t ldq, double* R, int64_t ldr);
+
+/* Alg. 4 on one GPU (the all_reduce becomes a device reduction over row
+ * blocks):  trans_a = 1:  C (p x q) = A^T B,  A m x p, B m x q;
+ *           trans_a = 0:  C (m x q) = A B,    A m x p, B p x q.
+ * dtype PYLOM_R64 (FP64 MFMA) or PYLOM_R32 (FP32 inputs; FP32 MFMA with FP64
+ * cross-block accumulation when trans_a = 1).  C has the storage type. */
+int pylom_matmul(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int trans_a, int64_t m,
+                 int64_t p, int64_t q, const void* A, int64_t lda, const void* B, int64_t ldb,
+                 void* C, int64_t ldc);
+
+/* Host-side copy of the in-device binary reduction tree of Alg. 1 for P
+ * leaves: writes up to `cap` triples (level, receiver, sender) in execution
+ * order into `out` (host memory, 3*cap int64) and returns the number of
+ * combines (P - 1), or a negative status.  At level l (blevel = 2^l), node j
+ * with j mod 2^(l+1) == 0 absorbs node j + 2^l when that node exists. */
+int64_t pylom_tree_plan(int64_t P, int64_t* out, int64_t cap);
+
+/* Leaf geometry chosen for a pod/tsvd/tsqr call of this shape: leaves,
+ * rows per leaf (the last leaf takes the remainder), chunk rows, tree levels.
+ * Host only. */
+int pylom_plan_query(pylom_ctx ctx, int64_t m, int64_t n, int64_t* leaves, int64_t* block_rows,
+                     int64_t* chunk_rows, int64_t* levels);
+
+/* After a stream synchronisation: the deferred numerical status of the last
+ * pod/tsvd call on this context (0 or PYLOM_WNOCONV) and its sweep count.
+ * Synchronises the context's stream. */
+int pylom_check(pylom_ctx ctx, int64_t* sweeps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PYLOM_H */

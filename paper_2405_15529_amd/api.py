@@ -1,0 +1,223 @@
+"""Python binding of the gfx950 POD / TSQR-SVD library (argument marshalling).
+
+Every function here takes PyTorch tensors that already live on the GPU, hands
+their device pointers and the current HIP stream to the C-ABI of
+``include/pylom.h``, and returns tensors allocated with PyTorch.  All
+arithmetic happens in the library's HIP kernels; nothing is computed here.
+
+Paper: pyLOM, arXiv 2405.15529 -- Alg. 1 (TSQR), Alg. 2 (POD),
+Alg. 4 (matmul), Eqs. svdqr1-svdqr3.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+R32, R64, C64, C128 = 1, 2, 3, 4
+FP64, MIXED = 0, 1
+_PREC = {"fp64": FP64, "mixed": MIXED}
+
+OK, WNOCONV = 0, 1
+
+
+class PylomError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pylom status {status}: {msg}")
+        self.status = status
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return R64
+    if t.dtype == torch.float32:
+        return R32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _rowmajor(t: torch.Tensor, name: str):
+    if t.dim() != 2 or t.stride(1) != 1 or t.stride(0) < t.shape[1]:
+        raise ValueError(f"{name} must be a 2-D row-major tensor (stride(1) == 1)")
+
+
+class Context:
+    """A library context (device workspace + options).  device=-1 creates a
+    host-only context: it validates arguments and plans, but runs nothing."""
+
+    def __init__(self, device: int = 0):
+        self.lib = _lib.load()
+        h = ctypes.c_void_p()
+        rc = self.lib.pylom_create(ctypes.byref(h), int(device))
+        if rc != 0:
+            raise PylomError(rc, self.lib.pylom_strerror(rc).decode())
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pylom_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc: int):
+        if rc < 0:
+            raise PylomError(rc, self.lib.pylom_last_error(self.h).decode())
+        return rc
+
+    def set_option(self, key: str, value: int):
+        self.check(self.lib.pylom_set_option(self.h, key.encode(), int(value)))
+
+    def get_option(self, key: str) -> int:
+        v = ctypes.c_int64()
+        self.check(self.lib.pylom_get_option(self.h, key.encode(), ctypes.byref(v)))
+        return v.value
+
+    def bind_stream(self):
+        s = torch.cuda.current_stream().cuda_stream
+        self.check(self.lib.pylom_set_stream(self.h, ctypes.c_void_p(s)))
+
+    def plan(self, m: int, n: int):
+        out = [ctypes.c_int64() for _ in range(4)]
+        self.check(self.lib.pylom_plan_query(self.h, m, n, *[ctypes.byref(o) for o in out]))
+        return dict(leaves=out[0].value, block_rows=out[1].value, chunk_rows=out[2].value,
+                    levels=out[3].value)
+
+    def workspace_bytes(self, m: int, n: int, dtype=R64, precision="fp64") -> int:
+        b = ctypes.c_size_t()
+        self.check(self.lib.pylom_workspace_query(self.h, dtype, _PREC[precision], m, n, ctypes.byref(b)))
+        return b.value
+
+    def status(self):
+        """Synchronise the stream; return (status, sweeps) of the last SVD."""
+        sw = ctypes.c_int64()
+        rc = self.lib.pylom_check(self.h, ctypes.byref(sw))
+        if rc < 0:
+            raise PylomError(rc, self.lib.pylom_last_error(self.h).decode())
+        return rc, sw.value
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device: int | None = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _contexts:
+        _contexts[device] = Context(device)
+    return _contexts[device]
+
+
+@dataclass
+class PodResult:
+    U: torch.Tensor      # m x N_r spatial modes
+    S: torch.Tensor      # n singular values (descending, FP64)
+    VT: torch.Tensor     # N_r x n temporal coefficients (FP64)
+    mean: torch.Tensor | None
+    nr: int
+    U_full: torch.Tensor
+    VT_full: torch.Tensor
+
+
+def pod(D: torch.Tensor, remove_mean: bool = True, r: float = 0.01, precision: str = "fp64",
+        ctx: Context | None = None, sync: bool = True) -> PodResult:
+    """POD of the snapshot matrix D (m x n, rows = points): Alg. 2 + Alg. 1."""
+    _rowmajor(D, "D")
+    if not D.is_cuda:
+        raise ValueError("D must be a GPU tensor")
+    ctx = ctx or context(D.device.index)
+    m, n = D.shape
+    dev = D.device
+    U = torch.empty((m, n), dtype=D.dtype, device=dev)
+    S = torch.empty(n, dtype=torch.float64, device=dev)
+    VT = torch.empty((n, n), dtype=torch.float64, device=dev)
+    mean = torch.empty(m, dtype=D.dtype, device=dev) if remove_mean else None
+    nr = torch.empty(1, dtype=torch.int64, device=dev)
+    ctx.bind_stream()
+    rc = ctx.lib.pylom_pod(ctx.h, _dtype_code(D), _PREC[precision], m, n, _ptr(D), D.stride(0),
+                           int(bool(remove_mean)), float(r), _ptr(mean), _ptr(U), n, _ptr(S),
+                           _ptr(VT), n, _ptr(nr))
+    ctx.check(rc)
+    k = int(nr.item()) if sync else n
+    return PodResult(U=U[:, :k], S=S, VT=VT[:k], mean=mean, nr=k, U_full=U, VT_full=VT)
+
+
+def tsvd(A: torch.Tensor, r: float = 0.01, precision: str = "fp64", ctx: Context | None = None,
+         sync: bool = True) -> PodResult:
+    """Tall-skinny SVD without mean removal."""
+    _rowmajor(A, "A")
+    ctx = ctx or context(A.device.index)
+    m, n = A.shape
+    dev = A.device
+    U = torch.empty((m, n), dtype=A.dtype, device=dev)
+    S = torch.empty(n, dtype=torch.float64, device=dev)
+    VT = torch.empty((n, n), dtype=torch.float64, device=dev)
+    nr = torch.empty(1, dtype=torch.int64, device=dev)
+    ctx.bind_stream()
+    rc = ctx.lib.pylom_tsvd(ctx.h, _dtype_code(A), _PREC[precision], m, n, _ptr(A), A.stride(0),
+                            float(r), _ptr(U), n, _ptr(S), _ptr(VT), n, _ptr(nr))
+    ctx.check(rc)
+    k = int(nr.item()) if sync else n
+    return PodResult(U=U[:, :k], S=S, VT=VT[:k], mean=None, nr=k, U_full=U, VT_full=VT)
+
+
+def tsqr(A: torch.Tensor, want_q: bool = True, ctx: Context | None = None):
+    """TSQR (Alg. 1): returns (Q or None, R) with diag(R) >= 0."""
+    _rowmajor(A, "A")
+    ctx = ctx or context(A.device.index)
+    m, n = A.shape
+    Q = torch.empty((m, n), dtype=A.dtype, device=A.device) if want_q else None
+    R = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    ctx.bind_stream()
+    rc = ctx.lib.pylom_tsqr(ctx.h, _dtype_code(A), FP64, m, n, _ptr(A), A.stride(0), _ptr(Q), n,
+                            _ptr(R), n)
+    ctx.check(rc)
+    return Q, R
+
+
+def matmul(A: torch.Tensor, B: torch.Tensor, trans_a: bool, ctx: Context | None = None):
+    """Alg. 4 on one GPU: A^T B (trans_a) or A B."""
+    _rowmajor(A, "A")
+    _rowmajor(B, "B")
+    if A.dtype != B.dtype:
+        raise TypeError("A and B must have the same dtype")
+    ctx = ctx or context(A.device.index)
+    if trans_a:
+        m, p = A.shape
+        if B.shape[0] != m:
+            raise ValueError("row counts differ")
+        q = B.shape[1]
+        C = torch.empty((p, q), dtype=A.dtype, device=A.device)
+    else:
+        m, p = A.shape
+        if B.shape[0] != p:
+            raise ValueError("inner dimensions differ")
+        q = B.shape[1]
+        C = torch.empty((m, q), dtype=A.dtype, device=A.device)
+    ctx.bind_stream()
+    rc = ctx.lib.pylom_matmul(ctx.h, _dtype_code(A), FP64, int(bool(trans_a)), m, p, q, _ptr(A),
+                              A.stride(0), _ptr(B), B.stride(0), _ptr(C), C.stride(0))
+    ctx.check(rc)
+    return C
+
+
+def tree_plan(P: int):
+    """The in-device reduction tree for P leaves: list of (level, receiver, sender)."""
+    lib = _lib.load()
+    cnt = lib.pylom_tree_plan(P, None, 0)
+    if cnt < 0:
+        raise PylomError(int(cnt), "tree_plan")
+    buf = (ctypes.c_int64 * max(1, 3 * cnt))()
+    lib.pylom_tree_plan(P, buf, cnt)
+    return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(cnt)]

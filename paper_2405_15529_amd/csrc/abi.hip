@@ -1,0 +1,432 @@
+// abi.hip -- the C-ABI of include/pylom.h: context, options, workspace,
+// argument validation, TSQR planning and the launch sequence of each call.
+//
+// POD / TSVD launch sequence (all on the context stream, no host sync):
+//   leaf QR (+ fused mean removal)          Alg. 2, Alg. 1 local qr
+//   tree combines, levels h = 1, 2, 4, ...  Alg. 1 reduce phase
+//   Jacobi SVD of the root R + truncation   Eq. svdqr2, residual r
+//   tree propagation, levels top .. 1       Alg. 1 broadcast phase
+//   leaf apply U_i = Q_1i W_i               Eq. svdqr3 / Q_i = Q_1i Q_w
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/pylom.h"
+#include "kernels.hpp"
+
+using namespace pylom;
+
+struct pylom_ctx_s {
+  int device = -1;  // -1: host-only context (validation and planning only)
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int64_t block_rows = 0;
+  int64_t max_sweeps = 40;
+  int64_t ws_cap_mb = 0;
+  int* status_dev = nullptr;  // Jacobi status of the last SVD (2 ints)
+  int status_valid = 0;
+  std::string last_error;
+};
+
+static int fail(pylom_ctx c, int code, const char* msg) {
+  if (c) c->last_error = msg;
+  return code;
+}
+
+static int hip_fail(pylom_ctx c, hipError_t e, const char* where) {
+  if (c) {
+    c->last_error = std::string(where) + ": " + hipGetErrorString(e);
+  }
+  return PYLOM_EHIP;
+}
+
+#define HIPCHK(ctx, expr, where)                   \
+  do {                                             \
+    hipError_t _e = (expr);                        \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
+  } while (0)
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" int pylom_create(pylom_ctx* out, int device) {
+  if (!out) return PYLOM_EINVAL;
+  *out = nullptr;
+  pylom_ctx c = new pylom_ctx_s();
+  if (device >= 0) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+      delete c;
+      return PYLOM_ENODEV;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess ||
+        std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+      delete c;
+      return PYLOM_ENODEV;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+      delete c;
+      return PYLOM_ENODEV;
+    }
+    if (hipMalloc((void**)&c->status_dev, 256) != hipSuccess) {
+      delete c;
+      return PYLOM_ENOMEM;
+    }
+    c->device = device;
+  }
+  *out = c;
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_destroy(pylom_ctx c) {
+  if (!c) return PYLOM_EINVAL;
+  if (c->device >= 0) {
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    if (c->ws) hipFree(c->ws);
+    if (c->status_dev) hipFree(c->status_dev);
+  }
+  delete c;
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_set_stream(pylom_ctx c, void* s) {
+  if (!c) return PYLOM_EINVAL;
+  c->stream = (hipStream_t)s;
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
+  if (!c || !key) return PYLOM_EINVAL;
+  if (!std::strcmp(key, "block_rows")) {
+    if (v < 0) return fail(c, PYLOM_EINVAL, "block_rows must be >= 0");
+    c->block_rows = v;
+  } else if (!std::strcmp(key, "max_sweeps")) {
+    if (v < 0 || v > 1000) return fail(c, PYLOM_EINVAL, "max_sweeps must be in [0, 1000]");
+    c->max_sweeps = v;
+  } else if (!std::strcmp(key, "ws_cap_mb")) {
+    if (v < 0) return fail(c, PYLOM_EINVAL, "ws_cap_mb must be >= 0");
+    c->ws_cap_mb = v;
+  } else {
+    return fail(c, PYLOM_EINVAL, "unknown option");
+  }
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_get_option(pylom_ctx c, const char* key, int64_t* v) {
+  if (!c || !key || !v) return PYLOM_EINVAL;
+  if (!std::strcmp(key, "block_rows"))
+    *v = c->block_rows;
+  else if (!std::strcmp(key, "max_sweeps"))
+    *v = c->max_sweeps;
+  else if (!std::strcmp(key, "ws_cap_mb"))
+    *v = c->ws_cap_mb;
+  else
+    return fail(c, PYLOM_EINVAL, "unknown option");
+  return PYLOM_OK;
+}
+
+extern "C" const char* pylom_strerror(int s) {
+  switch (s) {
+    case PYLOM_OK: return "success";
+    case PYLOM_EINVAL: return "invalid argument";
+    case PYLOM_ESHAPE: return "invalid shape or leading dimension";
+    case PYLOM_EDTYPE: return "unsupported dtype / precision";
+    case PYLOM_ENOMEM: return "workspace allocation failed or over the cap";
+    case PYLOM_EHIP: return "HIP runtime error";
+    case PYLOM_ENOTSUP: return "shape not supported by the kernels";
+    case PYLOM_ENODEV: return "no usable gfx950 device";
+    case PYLOM_WNOCONV: return "Jacobi SVD did not converge within max_sweeps";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* pylom_last_error(pylom_ctx c) {
+  if (!c) return "null context";
+  return c->last_error.c_str();
+}
+
+static int ensure_ws(pylom_ctx c, size_t bytes) {
+  if (c->ws_cap_mb > 0 && bytes > (size_t)c->ws_cap_mb * (1u << 20))
+    return fail(c, PYLOM_ENOMEM, "workspace over ws_cap_mb");
+  if (bytes <= c->ws_bytes) return PYLOM_OK;
+  if (c->ws) {
+    hipStreamSynchronize(c->stream);
+    hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  if (hipMalloc(&c->ws, bytes) != hipSuccess) {
+    c->ws = nullptr;
+    (void)hipGetLastError();
+    return fail(c, PYLOM_ENOMEM, "hipMalloc of the workspace failed");
+  }
+  c->ws_bytes = bytes;
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_reserve(pylom_ctx c, size_t bytes) {
+  if (!c) return PYLOM_EINVAL;
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  hipSetDevice(c->device);
+  return ensure_ws(c, bytes);
+}
+
+// ---------------------------------------------------------------------------
+// planning
+// ---------------------------------------------------------------------------
+struct Plan {
+  int64_t m, n, b, P, last_rows, nch_leaf, nch_tree, levels;
+  QrGeom g;
+  JacobiPlan jp;
+  // workspace offsets (bytes)
+  size_t oV, oTleaf, oR, oTtree, oW, oMean, oSig, oSvd, total;
+};
+
+static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p) {
+  if (n < 1 || m < n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
+  if (n > 1024) return fail(c, PYLOM_ENOTSUP, "n > 1024 is not supported on the FP64 path");
+  p->m = m;
+  p->n = n;
+  int64_t b = c->block_rows > 0 ? c->block_rows : 4096;
+  if (b < n) b = n;
+  int64_t P = m / b;
+  if (P < 1) P = 1;
+  if (P > (1 << 30)) return fail(c, PYLOM_ENOTSUP, "too many leaves");
+  p->b = b;
+  p->P = P;
+  p->last_rows = m - (P - 1) * b;
+  if (!qr_geom((int)n, 8, &p->g)) return fail(c, PYLOM_ENOTSUP, "no chunk geometry");
+  if (!jacobi_plan((int)n, &p->jp)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
+  const int64_t s = p->g.s, np = p->g.npanels;
+  p->nch_leaf = (p->last_rows + s - 1) / s;
+  p->nch_tree = (n + s - 1) / s;
+  int64_t lv = 0;
+  for (int64_t h = 1; h < P; h *= 2) ++lv;
+  p->levels = lv;
+  size_t off = 0;
+  p->oV = off;
+  if (store_q) off = align_up(off + sizeof(double) * (size_t)m * n);
+  p->oTleaf = off;
+  if (store_q) off = align_up(off + sizeof(double) * (size_t)P * p->nch_leaf * np * 256);
+  p->oR = off;
+  off = align_up(off + sizeof(double) * (size_t)P * n * n);
+  p->oTtree = off;
+  if (store_q) off = align_up(off + sizeof(double) * (size_t)P * p->nch_tree * np * 256);
+  p->oW = off;
+  off = align_up(off + sizeof(double) * (size_t)P * n * n);
+  p->oMean = off;
+  off = align_up(off + sizeof(double) * (size_t)m);
+  p->oSig = off;
+  off = align_up(off + sizeof(double) * (size_t)n);
+  p->oSvd = off;
+  off = align_up(off + jacobi_ws_bytes(p->jp, (int)c->max_sweeps));
+  p->total = off;
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_workspace_query(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m,
+                                     int64_t n, size_t* bytes) {
+  if (!c || !bytes) return PYLOM_EINVAL;
+  if (dtype != PYLOM_R64 && dtype != PYLOM_R32) return fail(c, PYLOM_EDTYPE, "dtype");
+  if (prec != PYLOM_FP64 && prec != PYLOM_MIXED) return fail(c, PYLOM_EDTYPE, "precision");
+  Plan p;
+  int rc = make_plan(c, m, n, true, &p);
+  if (rc) return rc;
+  *bytes = p.total;
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_plan_query(pylom_ctx c, int64_t m, int64_t n, int64_t* leaves,
+                                int64_t* block_rows, int64_t* chunk_rows, int64_t* levels) {
+  if (!c) return PYLOM_EINVAL;
+  Plan p;
+  int rc = make_plan(c, m, n, true, &p);
+  if (rc) return rc;
+  if (leaves) *leaves = p.P;
+  if (block_rows) *block_rows = p.b;
+  if (chunk_rows) *chunk_rows = p.g.s;
+  if (levels) *levels = p.levels;
+  return PYLOM_OK;
+}
+
+extern "C" int64_t pylom_tree_plan(int64_t P, int64_t* out, int64_t cap) {
+  if (P < 1 || (cap > 0 && !out)) return PYLOM_EINVAL;
+  int64_t k = 0, level = 0;
+  for (int64_t h = 1; h < P; h *= 2, ++level) {
+    for (int64_t j = 0; j + h < P; j += 2 * h) {
+      if (k < cap) {
+        out[3 * k + 0] = level;
+        out[3 * k + 1] = j;
+        out[3 * k + 2] = j + h;
+      }
+      ++k;
+    }
+  }
+  return k;
+}
+
+// ---------------------------------------------------------------------------
+// shared TSQR-SVD sequence
+// ---------------------------------------------------------------------------
+static int check_common(pylom_ctx c, pylom_dtype dtype, pylom_prec prec) {
+  if (!c) return PYLOM_EINVAL;
+  if (dtype != PYLOM_R64 && dtype != PYLOM_R32) return fail(c, PYLOM_EDTYPE, "dtype must be R64 or R32");
+  if (prec != PYLOM_FP64 && prec != PYLOM_MIXED) return fail(c, PYLOM_EDTYPE, "unknown precision");
+  return PYLOM_OK;
+}
+
+static int run_tsvd(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
+                    const void* D, int64_t ldd, int remove_mean, double residual, void* mean,
+                    void* U, int64_t ldu, double* S, double* VT, int64_t ldvt, int64_t* n_r) {
+  int rc = check_common(c, dtype, prec);
+  if (rc) return rc;
+  if (!D || !U || !S || !VT || !n_r) return fail(c, PYLOM_EINVAL, "null array argument");
+  if (!(residual >= 0.0 && residual < 1.0)) return fail(c, PYLOM_EINVAL, "residual must be in [0, 1)");
+  if (n < 1 || m < n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
+  if (ldd < n || ldu < n || ldvt < n) return fail(c, PYLOM_ESHAPE, "leading dimension < n");
+  if (prec == PYLOM_MIXED) return fail(c, PYLOM_ENOTSUP, "mixed precision: use pylom_pod_mixed path");
+  Plan p;
+  rc = make_plan(c, m, n, true, &p);
+  if (rc) return rc;
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+  rc = ensure_ws(c, p.total);
+  if (rc) return rc;
+  char* ws = (char*)c->ws;
+  double* V = (double*)(ws + p.oV);
+  double* Tleaf = (double*)(ws + p.oTleaf);
+  double* Rbuf = (double*)(ws + p.oR);
+  double* Ttree = (double*)(ws + p.oTtree);
+  double* W = (double*)(ws + p.oW);
+  double* meanws = (double*)(ws + p.oMean);
+  void* svdws = ws + p.oSvd;
+  hipStream_t st = c->stream;
+  const int in64 = dtype == PYLOM_R64;
+
+  HIPCHK(c, launch_leaf_qr_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws, V, Tleaf,
+                               p.nch_leaf, Rbuf, st), "leaf QR");
+  for (int64_t h = 1; h < p.P; h *= 2)
+    HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, 1, st), "tree combine");
+  HIPCHK(c, launch_small_svd(p.jp, Rbuf, (int)c->max_sweeps, svdws, S, VT, ldvt, W, residual, n_r,
+                             c->status_dev, st), "small SVD");
+  c->status_valid = 1;
+  int64_t top = 1;
+  while (top * 2 < p.P) top *= 2;
+  if (p.P > 1)
+    for (int64_t h = top; h >= 1; h /= 2)
+      HIPCHK(c, launch_apply_tree_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, W, n, n_r, n, st),
+             "tree propagation");
+  HIPCHK(c, launch_apply_leaf_f64(p.g, m, p.b, p.P, V, Tleaf, p.nch_leaf, W, n, n_r, n, U, in64,
+                                  ldu, st), "leaf apply");
+  if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, in64, m, st), "mean out");
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_pod(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
+                         const void* D, int64_t ldd, int remove_mean, double residual, void* mean,
+                         void* U, int64_t ldu, double* S, double* VT, int64_t ldvt, int64_t* n_r) {
+  return run_tsvd(c, dtype, prec, m, n, D, ldd, remove_mean ? 1 : 0, residual, mean, U, ldu, S, VT,
+                  ldvt, n_r);
+}
+
+extern "C" int pylom_tsvd(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
+                          const void* A, int64_t lda, double residual, void* U, int64_t ldu,
+                          double* S, double* VT, int64_t ldvt, int64_t* n_r) {
+  return run_tsvd(c, dtype, prec, m, n, A, lda, 0, residual, nullptr, U, ldu, S, VT, ldvt, n_r);
+}
+
+extern "C" int pylom_tsqr(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
+                          const void* A, int64_t lda, void* Q, int64_t ldq, double* R,
+                          int64_t ldr) {
+  int rc = check_common(c, dtype, prec);
+  if (rc) return rc;
+  if (!A || !R) return fail(c, PYLOM_EINVAL, "null array argument");
+  if (n < 1 || m < n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
+  if (lda < n || ldr < n || (Q && ldq < n)) return fail(c, PYLOM_ESHAPE, "leading dimension < n");
+  Plan p;
+  rc = make_plan(c, m, n, Q != nullptr, &p);
+  if (rc) return rc;
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+  rc = ensure_ws(c, p.total);
+  if (rc) return rc;
+  char* ws = (char*)c->ws;
+  const bool wq = Q != nullptr;
+  double* V = wq ? (double*)(ws + p.oV) : nullptr;
+  double* Tleaf = (double*)(ws + p.oTleaf);
+  double* Rbuf = (double*)(ws + p.oR);
+  double* Ttree = (double*)(ws + p.oTtree);
+  double* W = (double*)(ws + p.oW);
+  double* signs = (double*)(ws + p.oSig);
+  hipStream_t st = c->stream;
+  const int in64 = dtype == PYLOM_R64;
+  HIPCHK(c, launch_leaf_qr_f64(p.g, A, in64, lda, m, p.b, p.P, 0, nullptr, V, Tleaf, p.nch_leaf,
+                               Rbuf, st), "leaf QR");
+  for (int64_t h = 1; h < p.P; h *= 2)
+    HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, wq ? 1 : 0, st),
+           "tree combine");
+  HIPCHK(c, launch_r_out(Rbuf, n, R, ldr, signs, st), "R out");
+  if (wq) {
+    HIPCHK(c, launch_eye(W, n, n, st), "identity");
+    int64_t top = 1;
+    while (top * 2 < p.P) top *= 2;
+    if (p.P > 1)
+      for (int64_t h = top; h >= 1; h /= 2)
+        HIPCHK(c, launch_apply_tree_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, W, n, nullptr, n, st),
+               "tree propagation");
+    HIPCHK(c, launch_apply_leaf_f64(p.g, m, p.b, p.P, V, Tleaf, p.nch_leaf, W, n, nullptr, n, Q,
+                                    in64, ldq, st), "leaf apply");
+    HIPCHK(c, launch_q_signs(Q, in64, m, n, ldq, signs, st), "Q signs");
+  }
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_matmul(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int trans_a,
+                            int64_t m, int64_t p, int64_t q, const void* A, int64_t lda,
+                            const void* B, int64_t ldb, void* C, int64_t ldc) {
+  int rc = check_common(c, dtype, prec);
+  if (rc) return rc;
+  if (!A || !B || !C) return fail(c, PYLOM_EINVAL, "null array argument");
+  if (m < 1 || p < 1 || q < 1) return fail(c, PYLOM_ESHAPE, "empty matrix");
+  const int f64 = dtype == PYLOM_R64;
+  if (trans_a) {
+    if (lda < p || ldb < q || ldc < q) return fail(c, PYLOM_ESHAPE, "leading dimension");
+    if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+    HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    const int64_t ns = matmul_tn_splits(m, p, q);
+    rc = ensure_ws(c, align_up(sizeof(double) * (size_t)ns * p * q));
+    if (rc) return rc;
+    HIPCHK(c, launch_matmul_tn(f64, m, p, q, A, lda, B, ldb, C, ldc, (double*)c->ws, ns, c->stream),
+           "matmul tn");
+  } else {
+    if (lda < p || ldb < q || ldc < q) return fail(c, PYLOM_ESHAPE, "leading dimension");
+    if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+    HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    HIPCHK(c, launch_matmul_nn(f64, m, p, q, A, lda, B, ldb, C, ldc, c->stream), "matmul nn");
+  }
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_check(pylom_ctx c, int64_t* sweeps) {
+  if (!c) return PYLOM_EINVAL;
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (!c->status_valid) {
+    if (sweeps) *sweeps = 0;
+    return PYLOM_OK;
+  }
+  int st[2] = {0, 0};
+  HIPCHK(c, hipMemcpy(st, c->status_dev, sizeof(st), hipMemcpyDeviceToHost), "status copy");
+  if (sweeps) *sweeps = st[0];
+  if (st[1]) return fail(c, PYLOM_EHIP, "Jacobi grid barrier timed out");
+  if (st[0] < 0) return fail(c, PYLOM_WNOCONV, "Jacobi SVD did not converge");
+  return PYLOM_OK;
+}

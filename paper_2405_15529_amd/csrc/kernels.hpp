@@ -1,0 +1,87 @@
+// kernels.hpp -- host-side launchers of the gfx950 kernels (implemented in the
+// .hip files next to the kernels; used by the C-ABI layer in abi.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pylom {
+
+// Geometry of one stacked-QR problem family (leaves or tree combines).
+struct QrGeom {
+  int n;        // columns
+  int s;        // chunk rows staged in LDS (multiple of 16)
+  int ldc;      // LDS row stride of the chunk (odd)
+  int npanels;  // ceil(n / 16)
+};
+
+// Chunk rows and LDS stride for n columns of element size `esize`; returns
+// false if n is too wide for the single-workgroup stacked QR.
+bool qr_geom(int n, int esize, QrGeom* g);
+size_t qr_lds_bytes(const QrGeom& g, int esize);
+size_t apply_lds_bytes(const QrGeom& g, int esize);
+
+// ---- leaf QR (Alg. 1, local qr of each row block) ----------------------------
+// One workgroup per leaf j: rows [j*b, j*b + b) (the last leaf takes the
+// remainder), optional fused mean removal (Alg. 2) into mean_ws (double, m).
+// Writes R_j to Rbuf + j*n*n (n x n row-major), reflectors to V (m x n) and
+// per-(chunk, panel) T factors to Tleaf when V != nullptr.
+// in_f64: input is double (else float).  Compute type: double.
+hipError_t launch_leaf_qr_f64(const QrGeom& g, const void* D, int in_f64, int64_t ldd, int64_t m,
+                              int64_t b, int64_t P, int remove_mean, double* mean_ws, double* V,
+                              double* Tleaf, int64_t nch_leaf, double* Rbuf, hipStream_t st);
+// FP32 compute leaf QR (mixed precision): R only (no reflectors), R_j written
+// in FP32 to Rbuf32 + j*n*n.
+hipError_t launch_leaf_qr_f32(const QrGeom& g, const float* D, int64_t ldd, int64_t m, int64_t b,
+                              int64_t P, int remove_mean, double* mean_ws, float* Rbuf32,
+                              hipStream_t st);
+
+// ---- tree combine (Alg. 1 reduce phase): node j absorbs node j+h ------------
+// for every j = 0, 2h, 4h, ... with j + h < P.  In place: R_j <- R of
+// [R_j; R_{j+h}]; Rbuf + (j+h)*n*n <- reflectors; Ttree <- T factors (if
+// store_q).
+hipError_t launch_tree_combine_f64(const QrGeom& g, int64_t h, int64_t P, double* Rbuf,
+                                   double* Ttree, int64_t nch_tree, int store_q, hipStream_t st);
+
+// ---- apply (Alg. 1 broadcast phase + Q_i = Q_1i Q_w, Eq. svdqr3) -----------
+// Leaf mode: U rows of leaf j = Q_1j [W_j; 0]; combine mode (level h):
+// [W_j; W_{j+h}] = Q2 [W_j; 0].  Only the first ncols (or *nr) columns.
+hipError_t launch_apply_leaf_f64(const QrGeom& g, int64_t m, int64_t b, int64_t P,
+                                 const double* V, const double* Tleaf, int64_t nch_leaf,
+                                 const double* W, int64_t ldw, const int64_t* nr, int64_t ncols,
+                                 void* U, int out_f64, int64_t ldu, hipStream_t st);
+hipError_t launch_apply_tree_f64(const QrGeom& g, int64_t h, int64_t P, const double* Rbuf,
+                                 const double* Ttree, int64_t nch_tree, double* W, int64_t ldw,
+                                 const int64_t* nr, int64_t ncols, hipStream_t st);
+
+// ---- small SVD (Eq. svdqr2) ------------------------------------------------
+struct JacobiPlan {
+  int n, npad, w, G, lpp, xcd_stride;
+};
+bool jacobi_plan(int n, JacobiPlan* p);
+size_t jacobi_ws_bytes(const JacobiPlan& p, int max_sweeps);
+// Full SVD of R (n x n row-major, FP64) into S (n, descending), VT (n x n
+// row-major, ldvt), UR (n x n row-major, ld n; the left factor, sign
+// convention applied) and N_r (device) for residual r; status[0] = sweeps
+// (-1 if not converged), status[1] = barrier timeout flag.
+hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps, void* ws,
+                            double* S, double* VT, int64_t ldvt, double* UR, double residual,
+                            int64_t* nr, int* status, hipStream_t st);
+
+// ---- misc ------------------------------------------------------------------
+hipError_t launch_cast_out(const double* src, void* dst, int dst_f64, int64_t count, hipStream_t st);
+hipError_t launch_eye(double* W, int64_t n, int64_t ldw, hipStream_t st);
+hipError_t launch_r_out(const double* Rroot, int64_t n, double* R, int64_t ldr, double* signs,
+                        hipStream_t st);
+hipError_t launch_q_signs(void* Q, int q_f64, int64_t m, int64_t n, int64_t ldq,
+                          const double* signs, hipStream_t st);
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st);
+
+// ---- matmul (Alg. 4) --------------------------------------------------------
+hipError_t launch_matmul_tn(int f64, int64_t m, int64_t p, int64_t q, const void* A, int64_t lda,
+                            const void* B, int64_t ldb, void* C, int64_t ldc, double* partial,
+                            int64_t nsplit, hipStream_t st);
+int64_t matmul_tn_splits(int64_t m, int64_t p, int64_t q);
+hipError_t launch_matmul_nn(int f64, int64_t m, int64_t p, int64_t q, const void* A, int64_t lda,
+                            const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st);
+
+}  // namespace pylom

@@ -1,0 +1,210 @@
+// misc.hip -- small helper kernels and the matmul of Alg. 4 on one GPU.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pylom {
+
+static inline int grid_for(int64_t work, int per_block = 256, int cap = 4096) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+template <typename TO>
+__global__ void k_cast(const double* __restrict__ src, TO* __restrict__ dst, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (TO)src[i];
+}
+
+hipError_t launch_cast_out(const double* src, void* dst, int dst_f64, int64_t count,
+                           hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (dst_f64)
+    hipLaunchKernelGGL(k_cast<double>, dim3(grid_for(count)), dim3(256), 0, st, src, (double*)dst,
+                       count);
+  else
+    hipLaunchKernelGGL(k_cast<float>, dim3(grid_for(count)), dim3(256), 0, st, src, (float*)dst,
+                       count);
+  return hipGetLastError();
+}
+
+__global__ void k_eye(double* W, int64_t n, int64_t ldw) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n * n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / n, j = idx % n;
+    W[i * ldw + j] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+hipError_t launch_eye(double* W, int64_t n, int64_t ldw, hipStream_t st) {
+  hipLaunchKernelGGL(k_eye, dim3(grid_for(n * n)), dim3(256), 0, st, W, n, ldw);
+  return hipGetLastError();
+}
+
+// R output with diag(R) >= 0: row i is negated when R[i][i] < 0; signs[i]
+// records the flip so that the matching column of Q can follow.
+__global__ void k_r_out(const double* __restrict__ Rr, int64_t n, double* R, int64_t ldr,
+                        double* signs) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n * n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / n, j = idx % n;
+    const double sg = (Rr[i * n + i] < 0.0) ? -1.0 : 1.0;
+    R[i * ldr + j] = (j >= i) ? sg * Rr[i * n + j] : 0.0;
+    if (j == 0 && signs) signs[i] = sg;
+  }
+}
+
+hipError_t launch_r_out(const double* Rroot, int64_t n, double* R, int64_t ldr, double* signs,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_r_out, dim3(grid_for(n * n)), dim3(256), 0, st, Rroot, n, R, ldr, signs);
+  return hipGetLastError();
+}
+
+template <typename TQ>
+__global__ void k_q_signs(TQ* Q, int64_t m, int64_t n, int64_t ldq, const double* signs) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < m * n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / n, j = idx % n;
+    if (signs[j] < 0.0) Q[i * ldq + j] = -Q[i * ldq + j];
+  }
+}
+
+hipError_t launch_q_signs(void* Q, int q_f64, int64_t m, int64_t n, int64_t ldq,
+                          const double* signs, hipStream_t st) {
+  if (q_f64)
+    hipLaunchKernelGGL(k_q_signs<double>, dim3(grid_for(m * n)), dim3(256), 0, st, (double*)Q, m,
+                       n, ldq, signs);
+  else
+    hipLaunchKernelGGL(k_q_signs<float>, dim3(grid_for(m * n)), dim3(256), 0, st, (float*)Q, m, n,
+                       ldq, signs);
+  return hipGetLastError();
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
+
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, p, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 4: C = sum over row blocks of A_i^T B_i.  Each wave owns one 16x16 tile
+// of C and one slice of rows (split-K); its MFMA partial goes to an FP64
+// buffer, and a second kernel sums the slices in a fixed order (the device
+// stand-in for the all_reduce, deterministic).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_matmul_tn_partial(int64_t m, int64_t p, int64_t q,
+                                                          const T* __restrict__ A, int64_t lda,
+                                                          const T* __restrict__ B, int64_t ldb,
+                                                          double* __restrict__ part,
+                                                          int64_t nsplit) {
+  typedef typename Mfma<T>::v4 v4;
+  const int64_t tp = (p + 15) / 16, tq = (q + 15) / 16;
+  const int64_t tile = blockIdx.x % (tp * tq);
+  const int64_t split = blockIdx.x / (tp * tq);
+  const int64_t i0 = (tile / tq) * 16, j0 = (tile % tq) * 16;
+  const int64_t rows_per = (m + nsplit - 1) / nsplit;
+  const int64_t k0 = split * rows_per;
+  const int64_t k1 = (k0 + rows_per < m) ? k0 + rows_per : m;
+  const int lane = threadIdx.x, i16 = lane & 15, g4 = lane >> 4;
+  const bool iok = i0 + i16 < p, jok = j0 + i16 < q;
+  v4 acc = vzero4<T>();
+  for (int64_t k = k0; k < k1; k += 4) {
+    const int64_t r = k + g4;
+    const T av = (r < k1 && iok) ? A[r * lda + i0 + i16] : T(0);
+    const T bv = (r < k1 && jok) ? B[r * ldb + j0 + i16] : T(0);
+    acc = Mfma<T>::op(av, bv, acc);
+  }
+  double* out = part + split * p * q;
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) {
+    const int64_t i = i0 + 4 * g4 + qq, j = j0 + i16;
+    if (i < p && j < q) out[i * q + j] = (double)acc[qq];
+  }
+}
+
+template <typename TO>
+__global__ void k_matmul_reduce(int64_t p, int64_t q, const double* __restrict__ part,
+                                int64_t nsplit, TO* C, int64_t ldc) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < p * q;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t k = 0; k < nsplit; ++k) s += part[k * p * q + idx];
+    C[(idx / q) * ldc + (idx % q)] = (TO)s;
+  }
+}
+
+int64_t matmul_tn_splits(int64_t m, int64_t p, int64_t q) {
+  const int64_t tiles = ((p + 15) / 16) * ((q + 15) / 16);
+  // aim for ~4096 waves, each slice at least 256 rows
+  int64_t s = (4096 + tiles - 1) / tiles;
+  const int64_t maxs = (m + 255) / 256;
+  if (s > maxs) s = maxs;
+  if (s < 1) s = 1;
+  return s;
+}
+
+hipError_t launch_matmul_tn(int f64, int64_t m, int64_t p, int64_t q, const void* A, int64_t lda,
+                            const void* B, int64_t ldb, void* C, int64_t ldc, double* partial,
+                            int64_t nsplit, hipStream_t st) {
+  const int64_t tiles = ((p + 15) / 16) * ((q + 15) / 16);
+  const dim3 grid((unsigned)(tiles * nsplit));
+  if (f64)
+    hipLaunchKernelGGL(k_matmul_tn_partial<double>, grid, dim3(64), 0, st, m, p, q,
+                       (const double*)A, lda, (const double*)B, ldb, partial, nsplit);
+  else
+    hipLaunchKernelGGL(k_matmul_tn_partial<float>, grid, dim3(64), 0, st, m, p, q,
+                       (const float*)A, lda, (const float*)B, ldb, partial, nsplit);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (f64)
+    hipLaunchKernelGGL(k_matmul_reduce<double>, dim3(grid_for(p * q)), dim3(256), 0, st, p, q,
+                       partial, nsplit, (double*)C, ldc);
+  else
+    hipLaunchKernelGGL(k_matmul_reduce<float>, dim3(grid_for(p * q)), dim3(256), 0, st, p, q,
+                       partial, nsplit, (float*)C, ldc);
+  return hipGetLastError();
+}
+
+// C (m x q) = A (m x p) B (p x q): one wave per 16x16 tile of C.
+template <typename T>
+__global__ __launch_bounds__(64) void k_matmul_nn(int64_t m, int64_t p, int64_t q,
+                                                  const T* __restrict__ A, int64_t lda,
+                                                  const T* __restrict__ B, int64_t ldb,
+                                                  T* __restrict__ C, int64_t ldc) {
+  typedef typename Mfma<T>::v4 v4;
+  const int64_t tq = (q + 15) / 16;
+  const int64_t i0 = (blockIdx.x / tq) * 16, j0 = (blockIdx.x % tq) * 16;
+  const int lane = threadIdx.x, i16 = lane & 15, g4 = lane >> 4;
+  const bool iok = i0 + i16 < m, jok = j0 + i16 < q;
+  v4 acc = vzero4<T>();
+  for (int64_t k = 0; k < p; k += 4) {
+    const int64_t kk = k + g4;
+    const T av = (kk < p && iok) ? A[(i0 + i16) * lda + kk] : T(0);
+    const T bv = (kk < p && jok) ? B[kk * ldb + j0 + i16] : T(0);
+    acc = Mfma<T>::op(av, bv, acc);
+  }
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) {
+    const int64_t i = i0 + 4 * g4 + qq, j = j0 + i16;
+    if (i < m && j < q) C[i * ldc + j] = acc[qq];
+  }
+}
+
+hipError_t launch_matmul_nn(int f64, int64_t m, int64_t p, int64_t q, const void* A, int64_t lda,
+                            const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st) {
+  const int64_t tiles = ((m + 15) / 16) * ((q + 15) / 16);
+  if (tiles <= 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(k_matmul_nn<double>, dim3((unsigned)tiles), dim3(64), 0, st, m, p, q,
+                       (const double*)A, lda, (const double*)B, ldb, (double*)C, ldc);
+  else
+    hipLaunchKernelGGL(k_matmul_nn<float>, dim3((unsigned)tiles), dim3(64), 0, st, m, p, q,
+                       (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc);
+  return hipGetLastError();
+}
+
+}  // namespace pylom

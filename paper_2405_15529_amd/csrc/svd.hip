@@ -1,0 +1,407 @@
+// svd.hip -- SVD of the small n x n triangular factor R (Eq. svdqr2), FP64.
+//
+// One-sided (Hestenes) Jacobi: the columns of A = R are rotated pairwise until
+// all pairs are orthogonal to tol = n * 2^-53 (relative); then
+// sigma_j = |a_j|, U_R = A diag(1/sigma), V = accumulated rotations.  The
+// rotation of a pair uses Rutishauser's formula
+//     zeta = (|b|^2 - |a|^2) / (2 a.b),  t = sign(zeta) / (|zeta| + sqrt(1+zeta^2)),
+//     c = 1/sqrt(1+t^2), s = c t,  a' = c a - s b,  b' = s a + c b,
+// and the squared norms are carried along as |a'|^2 = |a|^2 - t a.b,
+// |b'|^2 = |b|^2 + t a.b (recomputed from the data at every block step).
+//
+// Parallel layout: the npad >= n columns are cut into 2G blocks of w
+// columns.  G workgroups (one CU each) form a round-robin tournament over the
+// blocks: at every step each workgroup owns two blocks and rotates all w*w
+// cross pairs (w rounds; group i keeps column a_i in registers while the
+// b-columns circulate through LDS), and once per sweep it also rotates the
+// pairs inside its two starting blocks.  Blocks live in global memory between
+// steps; steps are separated by a device-wide barrier (bounded spin: a
+// timeout sets an error flag instead of hanging).  When G <= 32 the
+// participating workgroups are spread over launch slots so that the hardware's
+// round-robin placement puts them on one XCD (one shared L2).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pylom {
+
+constexpr int JT = 256;     // threads per Jacobi workgroup
+constexpr int JRPL = 16;    // max column rows per lane
+
+bool jacobi_plan(int n, JacobiPlan* p) {
+  if (n < 1 || n > 1024) return false;
+  // block width w (even, 4..16): a pair is handled by 256/w lanes of one wave,
+  // each holding at most JRPL rows of a column
+  int w = 16;
+  while (w > 4 && n * w > 4096) w >>= 1;
+  if (n <= 2 * w) {
+    int half = (n + 1) / 2;
+    int ww = 4;
+    while (ww < half) ww <<= 1;
+    w = ww;
+  }
+  const int G = (n + 2 * w - 1) / (2 * w);
+  p->n = n;
+  p->w = w;
+  p->G = G;
+  p->npad = 2 * G * w;
+  p->lpp = JT / w;
+  p->xcd_stride = (G <= 32) ? 8 : 1;
+  return p->lpp <= 64 && (n + p->lpp - 1) / p->lpp <= JRPL;
+}
+
+struct JacobiWs {
+  double* A;          // npad columns x n rows (column-major)
+  double* V;          // npad columns x n rows
+  unsigned int* bar;  // barrier counter
+  int* flags;         // rotations per sweep
+};
+
+static JacobiWs jacobi_ws(const JacobiPlan& p, int max_sweeps, void* ws) {
+  JacobiWs w;
+  char* c = (char*)ws;
+  w.A = (double*)c;
+  c += sizeof(double) * (size_t)p.npad * p.n;
+  w.V = (double*)c;
+  c += sizeof(double) * (size_t)p.npad * p.n;
+  w.bar = (unsigned int*)c;
+  c += 256;
+  w.flags = (int*)c;
+  return w;
+}
+
+size_t jacobi_ws_bytes(const JacobiPlan& p, int max_sweeps) {
+  return sizeof(double) * 2 * (size_t)p.npad * p.n + 256 + sizeof(int) * (size_t)(max_sweeps + 64);
+}
+
+// ---- setup: A <- R (column-major), V <- I, counters <- 0 --------------------
+__global__ void k_jacobi_setup(int n, int npad, const double* __restrict__ R, double* A,
+                               double* V, unsigned int* bar, int* flags, int nflags, int* status,
+                               int status0) {
+  const int64_t total = (int64_t)npad * n;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / n), i = (int)(idx % n);
+    A[idx] = (j < n) ? R[(int64_t)i * n + j] : 0.0;
+    V[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < nflags; k += blockDim.x) flags[k] = 0;
+    if (threadIdx.x == 0) {
+      *bar = 0u;
+      status[0] = status0;
+      status[1] = 0;
+    }
+  }
+}
+
+__device__ __forceinline__ void grid_barrier(unsigned int* bar, unsigned int G, unsigned int& epoch,
+                                             int* status) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ++epoch;
+    __threadfence();
+    atomicAdd(bar, 1u);
+    const unsigned int target = epoch * G;
+    unsigned long long spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > (1ull << 24)) {
+        atomicExch(status + 1, 1);
+        break;
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// block index of player i (0..2G-1) at tournament step st (circle method)
+__device__ __forceinline__ int rr_player(int i, int st, int nplayers) {
+  if (i == 0) return 0;
+  return ((i - 1 + st) % (nplayers - 1)) + 1;
+}
+
+// Rotate the pair (a, b) held by an LPP-lane group (RPL rows per lane each)
+// if it is not yet orthogonal; norms na, nb are updated.  Returns 1 if rotated.
+template <int LPP>
+__device__ __forceinline__ int jacobi_pair(double (&a)[JRPL], double (&va)[JRPL], double (&b)[JRPL],
+                                           double (&vb)[JRPL], double& na, double& nb, int rpl_a,
+                                           int rpl_v, double tol) {
+  double g = 0.0;
+#pragma unroll
+  for (int k = 0; k < JRPL; ++k)
+    if (k < rpl_a) g += a[k] * b[k];
+  g = group_sum<LPP>(g);
+  if (!(na > 0.0) || !(nb > 0.0)) return 0;
+  if (fabs(g) <= tol * sqrt(na) * sqrt(nb)) return 0;
+  const double zeta = (nb - na) / (2.0 * g);
+  double t = 1.0 / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  if (zeta < 0.0) t = -t;
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = c * t;
+#pragma unroll
+  for (int k = 0; k < JRPL; ++k) {
+    if (k < rpl_a) {
+      const double x = a[k], y = b[k];
+      a[k] = c * x - s * y;
+      b[k] = s * x + c * y;
+    }
+    if (k < rpl_v) {
+      const double x = va[k], y = vb[k];
+      va[k] = c * x - s * y;
+      vb[k] = s * x + c * y;
+    }
+  }
+  na = na - t * g;
+  nb = nb + t * g;
+  if (na < 0.0) na = 0.0;
+  return 1;
+}
+
+template <int LPP>
+__device__ __forceinline__ double col_norm2(const double (&a)[JRPL], int rpl) {
+  double x = 0.0;
+#pragma unroll
+  for (int k = 0; k < JRPL; ++k)
+    if (k < rpl) x += a[k] * a[k];
+  return group_sum<LPP>(x);
+}
+
+template <int LPP>
+__device__ __forceinline__ void load_col(double (&x)[JRPL], const double* __restrict__ col, int rows,
+                                         int sub) {
+#pragma unroll
+  for (int k = 0; k < JRPL; ++k) {
+    const int r = sub + LPP * k;
+    x[k] = (r < rows) ? col[r] : 0.0;
+  }
+}
+
+template <int LPP>
+__device__ __forceinline__ void store_col(const double (&x)[JRPL], double* __restrict__ col, int rows,
+                                          int sub) {
+#pragma unroll
+  for (int k = 0; k < JRPL; ++k) {
+    const int r = sub + LPP * k;
+    if (r < rows) col[r] = x[k];
+  }
+}
+
+struct JacobiArgs {
+  int n, npad, w, G, xcd_stride, max_sweeps;
+  double* A;
+  double* V;
+  unsigned int* bar;
+  int* flags;
+  int* status;
+};
+
+template <int LPP>
+__global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
+  if (blockIdx.x % a.xcd_stride) return;
+  __shared__ double xbuf[JT * 2 * JRPL];  // circulating b columns (A and V parts)
+  __shared__ double xnorm[JT / 2];
+  __shared__ int rot_count;
+  const int g = blockIdx.x / a.xcd_stride;
+  const int tid = threadIdx.x;
+  const int w = a.w, n = a.n;
+  const int grp = tid / LPP, sub = tid % LPP;
+  const int rpl = (n + LPP - 1) / LPP;
+  const double tol = (double)n * 0x1p-53;
+  const int nplayers = 2 * a.G;
+  unsigned int epoch = 0;
+  double ca[JRPL], cva[JRPL], cb[JRPL], cvb[JRPL];
+  int sweep_done = -1;
+  for (int sw = 0; sw < a.max_sweeps; ++sw) {
+    if (tid == 0) rot_count = 0;
+    __syncthreads();
+    int myrot = 0;
+    // ---- pairs inside my two starting blocks (round-robin of w columns)
+    {
+      const int blk_a = rr_player(g, 0, nplayers), blk_b = rr_player(nplayers - 1 - g, 0, nplayers);
+      const int half = w / 2;
+      const int which = (grp < half) ? blk_a : blk_b;
+      const int pi = (grp < half) ? grp : grp - half;
+      for (int q = 0; q < w - 1; ++q) {
+        const int c1 = rr_player(pi, q, w), c2 = rr_player(w - 1 - pi, q, w);
+        const int j1 = which * w + c1, j2 = which * w + c2;
+        load_col<LPP>(ca, a.A + (int64_t)j1 * n, n, sub);
+        load_col<LPP>(cva, a.V + (int64_t)j1 * n, n, sub);
+        load_col<LPP>(cb, a.A + (int64_t)j2 * n, n, sub);
+        load_col<LPP>(cvb, a.V + (int64_t)j2 * n, n, sub);
+        double na = col_norm2<LPP>(ca, rpl), nb = col_norm2<LPP>(cb, rpl);
+        myrot += jacobi_pair<LPP>(ca, cva, cb, cvb, na, nb, rpl, rpl, tol);
+        store_col<LPP>(ca, a.A + (int64_t)j1 * n, n, sub);
+        store_col<LPP>(cva, a.V + (int64_t)j1 * n, n, sub);
+        store_col<LPP>(cb, a.A + (int64_t)j2 * n, n, sub);
+        store_col<LPP>(cvb, a.V + (int64_t)j2 * n, n, sub);
+        __syncthreads();
+      }
+    }
+    // ---- cross-block steps of the tournament
+    for (int st = 0; st < nplayers - 1; ++st) {
+      const int blk_a = rr_player(g, st, nplayers), blk_b = rr_player(nplayers - 1 - g, st, nplayers);
+      const int ja = blk_a * w + grp;
+      load_col<LPP>(ca, a.A + (int64_t)ja * n, n, sub);
+      load_col<LPP>(cva, a.V + (int64_t)ja * n, n, sub);
+      load_col<LPP>(cb, a.A + (int64_t)(blk_b * w + grp) * n, n, sub);
+      load_col<LPP>(cvb, a.V + (int64_t)(blk_b * w + grp) * n, n, sub);
+      double na = col_norm2<LPP>(ca, rpl), nb = col_norm2<LPP>(cb, rpl);
+      for (int q = 0; q < w; ++q) {
+        myrot += jacobi_pair<LPP>(ca, cva, cb, cvb, na, nb, rpl, rpl, tol);
+        if (q < w - 1) {
+          // pass my b column to group grp-1, take the one of group grp+1
+#pragma unroll
+          for (int k = 0; k < JRPL; ++k) {
+            xbuf[(grp * LPP + sub) * 2 * JRPL + k] = cb[k];
+            xbuf[(grp * LPP + sub) * 2 * JRPL + JRPL + k] = cvb[k];
+          }
+          if (sub == 0) xnorm[grp] = nb;
+          __syncthreads();
+          const int src = (grp + 1) % w;
+#pragma unroll
+          for (int k = 0; k < JRPL; ++k) {
+            cb[k] = xbuf[(src * LPP + sub) * 2 * JRPL + k];
+            cvb[k] = xbuf[(src * LPP + sub) * 2 * JRPL + JRPL + k];
+          }
+          nb = xnorm[src];
+          __syncthreads();
+        }
+      }
+      store_col<LPP>(ca, a.A + (int64_t)ja * n, n, sub);
+      store_col<LPP>(cva, a.V + (int64_t)ja * n, n, sub);
+      const int jb = blk_b * w + (grp + w - 1) % w;
+      store_col<LPP>(cb, a.A + (int64_t)jb * n, n, sub);
+      store_col<LPP>(cvb, a.V + (int64_t)jb * n, n, sub);
+      if (st == nplayers - 2) {
+        // count rotations of this sweep before the last barrier
+        if (sub == 0 && myrot) atomicAdd(&rot_count, myrot);
+        __syncthreads();
+        if (tid == 0 && rot_count) atomicAdd(a.flags + sw, rot_count);
+      }
+      grid_barrier(a.bar, (unsigned int)a.G, epoch, a.status);
+    }
+    const int total = __hip_atomic_load(a.flags + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (total == 0) {
+      sweep_done = sw + 1;
+      break;
+    }
+  }
+  if (g == 0 && tid == 0) a.status[0] = sweep_done;
+}
+
+// ---- finalize: sigma, sort, sign convention, outputs, truncation ------------
+constexpr int FT = 1024;
+__global__ __launch_bounds__(FT) void k_svd_finalize(int n, const double* __restrict__ A,
+                                                     const double* __restrict__ V, double* S,
+                                                     double* VT, int64_t ldvt, double* UR,
+                                                     double residual, int64_t* nr) {
+  __shared__ double sig[1024];
+  __shared__ double sgn[1024];
+  __shared__ int rank[1024];
+  __shared__ double tail[1025];
+  const int tid = threadIdx.x;
+  for (int j = tid; j < n; j += FT) {
+    const double* col = A + (int64_t)j * n;
+    double x = 0.0;
+    for (int i = 0; i < n; ++i) x += col[i] * col[i];
+    sig[j] = sqrt(x);
+    const double* vc = V + (int64_t)j * n;
+    int arg = 0;
+    double best = -1.0;
+    for (int i = 0; i < n; ++i) {
+      const double av = fabs(vc[i]);
+      if (av > best) {
+        best = av;
+        arg = i;
+      }
+    }
+    sgn[j] = (vc[arg] < 0.0) ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += FT) {
+    const double sj = sig[j];
+    int r = 0;
+    for (int i = 0; i < n; ++i) r += (sig[i] > sj) || (sig[i] == sj && i < j);
+    rank[j] = r;
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += FT) S[rank[j]] = sig[j];
+  // VT rows and U_R columns in sorted order
+  for (int64_t idx = tid; idx < (int64_t)n * n; idx += FT) {
+    const int j = (int)(idx / n), i = (int)(idx % n);
+    const int rj = rank[j];
+    VT[(int64_t)rj * ldvt + i] = sgn[j] * V[(int64_t)j * n + i];
+    const double sj = sig[j];
+    UR[(int64_t)i * n + rj] = (sj > 0.0) ? sgn[j] * A[(int64_t)j * n + i] / sj : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // tail sums from the smallest value upward
+    tail[n] = 0.0;
+    for (int k = n - 1; k >= 0; --k) tail[k] = tail[k + 1] + S[k] * S[k];
+    const double total = tail[0];
+    int64_t keep = n;
+    if (!(residual > 0.0)) {
+      keep = n;
+    } else if (total == 0.0) {
+      keep = 0;
+    } else {
+      for (int k = 1; k <= n; ++k)
+        if (tail[k] <= residual * total) {
+          keep = k;
+          break;
+        }
+    }
+    *nr = keep;
+  }
+}
+
+// n = 1: sigma = |r|, u = v = sign
+__global__ void k_svd_one(const double* R, double* S, double* VT, double* UR, double residual,
+                          int64_t* nr, int* status) {
+  const double r = R[0];
+  S[0] = fabs(r);
+  VT[0] = 1.0;
+  UR[0] = (r < 0.0) ? -1.0 : 1.0;
+  *nr = (residual > 0.0 && r == 0.0) ? 0 : 1;
+  status[0] = 1;
+  status[1] = 0;
+}
+
+hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps, void* ws,
+                            double* S, double* VT, int64_t ldvt, double* UR, double residual,
+                            int64_t* nr, int* status, hipStream_t st) {
+  if (p.n == 1) {
+    hipLaunchKernelGGL(k_svd_one, dim3(1), dim3(1), 0, st, R, S, VT, UR, residual, nr, status);
+    return hipGetLastError();
+  }
+  JacobiWs w = jacobi_ws(p, max_sweeps, ws);
+  const int nflags = max_sweeps + 1;
+  hipLaunchKernelGGL(k_jacobi_setup, dim3(64), dim3(256), 0, st, p.n, p.npad, R, w.A, w.V, w.bar,
+                     w.flags, nflags, status, max_sweeps > 0 ? 0 : -1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (max_sweeps > 0) {
+    JacobiArgs a;
+    a.n = p.n; a.npad = p.npad; a.w = p.w; a.G = p.G; a.xcd_stride = p.xcd_stride;
+    a.max_sweeps = max_sweeps; a.A = w.A; a.V = w.V; a.bar = w.bar; a.flags = w.flags;
+    a.status = status;
+    void* args[] = {&a};
+    const dim3 grid(p.G * p.xcd_stride), block(JT);
+    const void* fn = nullptr;
+    switch (p.lpp) {
+      case 16: fn = (const void*)k_jacobi<16>; break;
+      case 32: fn = (const void*)k_jacobi<32>; break;
+      case 64: fn = (const void*)k_jacobi<64>; break;
+      default: return hipErrorInvalidValue;
+    }
+    e = hipLaunchCooperativeKernel(fn, grid, block, args, 0, st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_svd_finalize, dim3(1), dim3(FT), 0, st, p.n, w.A, w.V, S, VT, ldvt, UR,
+                     residual, nr);
+  return hipGetLastError();
+}
+
+}  // namespace pylom

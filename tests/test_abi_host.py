@@ -1,0 +1,160 @@
+"""CPU tests of the C-ABI boundary: the library loads, exports every entry
+point declared in include/pylom.h, validates arguments on the host before any
+device work, and plans the in-device reduction tree exactly as Alg. 1's
+XOR/AND schedule (emulated here with P virtual ranks)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2405_15529_amd import _lib, api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "pylom.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pylom_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in pylom.h but not exported"
+    # the binding covers exactly the declared set
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def test_strerror_names_every_code():
+    lib = _lib.load()
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, 1):
+        assert lib.pylom_strerror(code).decode() not in ("", "unknown status")
+    assert lib.pylom_strerror(12345).decode() == "unknown status"
+
+
+@pytest.fixture
+def hctx():
+    c = api.Context(-1)  # host-only: validates and plans, never touches a device
+    yield c
+    c.close()
+
+
+def _pod(ctx, dtype=api.R64, prec=api.FP64, m=100, n=10, D=1, ldd=None, r=0.01, U=1, ldu=None,
+         S=1, VT=1, ldvt=None, nr=1):
+    ldd = n if ldd is None else ldd
+    ldu = n if ldu is None else ldu
+    ldvt = n if ldvt is None else ldvt
+    vp = ctypes.c_void_p
+    return ctx.lib.pylom_pod(ctx.h, dtype, prec, m, n, vp(D), ldd, 1, r, vp(0), vp(U), ldu, vp(S),
+                             vp(VT), ldvt, vp(nr))
+
+
+def test_argument_validation_before_device(hctx):
+    assert _pod(hctx) == -7                        # valid args: only the missing device
+    assert _pod(hctx, m=5, n=10) == -2             # m < n
+    assert _pod(hctx, n=0) == -2
+    assert _pod(hctx, ldd=5) == -2                 # ld < n
+    assert _pod(hctx, ldu=5) == -2
+    assert _pod(hctx, ldvt=5) == -2
+    assert _pod(hctx, D=0) == -1                   # null input
+    assert _pod(hctx, nr=0) == -1
+    assert _pod(hctx, r=1.0) == -1                 # residual outside [0, 1)
+    assert _pod(hctx, r=-0.5) == -1
+    assert _pod(hctx, dtype=99) == -3
+    assert _pod(hctx, prec=7) == -3
+    assert _pod(hctx, m=5000, n=2000) == -6        # wider than the FP64 kernels
+    assert hctx.lib.pylom_pod(None, 2, 0, 10, 2, None, 2, 0, 0.0, None, None, 2, None, None, 2,
+                              None) == -1
+
+
+def test_options_roundtrip(hctx):
+    hctx.set_option("block_rows", 2500)
+    assert hctx.get_option("block_rows") == 2500
+    hctx.set_option("max_sweeps", 0)
+    assert hctx.get_option("max_sweeps") == 0
+    with pytest.raises(api.PylomError):
+        hctx.set_option("no_such_option", 1)
+    with pytest.raises(api.PylomError):
+        hctx.set_option("max_sweeps", -1)
+
+
+def test_plan_geometry(hctx):
+    # the small plain-POD case: 20,000 x 100 over 8 row blocks of 2,500
+    hctx.set_option("block_rows", 2500)
+    p = hctx.plan(20_000, 100)
+    assert p["leaves"] == 8 and p["block_rows"] == 2500 and p["levels"] == 3
+    assert p["chunk_rows"] % 16 == 0 and p["chunk_rows"] > 0
+    # the known-spectrum case: 1,048,576 x 256 in blocks of 4,096
+    hctx.set_option("block_rows", 4096)
+    p = hctx.plan(1_048_576, 256)
+    assert p["leaves"] == 256 and p["levels"] == 8
+    # leaves never get fewer than n rows; the last takes the remainder
+    p = hctx.plan(1000, 300)
+    assert p["block_rows"] >= 300 and p["leaves"] == max(1, 1000 // p["block_rows"])
+    hctx.set_option("block_rows", 100)  # raised to n
+    p = hctx.plan(1000, 300)
+    assert p["block_rows"] == 300 and p["leaves"] == 3
+    assert hctx.workspace_bytes(1_048_576, 256) > 1_048_576 * 256 * 8
+
+
+def emulate_alg1(P):
+    """Alg. 1 with P virtual ranks.  Reduce phase: at blevel = 1, 2, 4, ...
+    (while blevel < 2^ceil(log2 P)), a rank that has not yet sent is a sender
+    if rank & blevel, else a receiver; partner = rank ^ blevel, skipped if it
+    does not exist.  Broadcast phase: blevel from the top down, ranks with
+    rank & (blevel-1) == 0 take part; rank & blevel receives from the partner."""
+    npow = 1
+    while npow < P:
+        npow *= 2
+    sent = [False] * P
+    combines = []
+    level = 0
+    blevel = 1
+    while blevel < npow:
+        for rank in range(P):
+            if sent[rank] or rank & blevel:
+                continue
+            prank = rank ^ blevel
+            if prank < P and not sent[prank]:
+                combines.append((level, rank, prank))
+        for rank in range(P):
+            if not sent[rank] and rank & blevel and (rank ^ blevel) < P:
+                sent[rank] = True
+        blevel *= 2
+        level += 1
+    nlevels = level
+    received_from = {}
+    blevel = 1 << (nlevels - 1) if nlevels else 0
+    while blevel >= 1:
+        mask = blevel - 1
+        for rank in range(P):
+            if rank & mask:
+                continue
+            prank = rank ^ blevel
+            if rank & blevel and prank < P:
+                assert rank not in received_from
+                received_from[rank] = prank
+        blevel //= 2
+    return combines, received_from
+
+
+@pytest.mark.parametrize("P", list(range(1, 40)) + [6, 64, 100, 255, 256, 300])
+def test_tree_plan_matches_alg1(P):
+    combines, received = emulate_alg1(P)
+    plan = api.tree_plan(P)
+    assert sorted(plan) == sorted(combines)
+    assert len(plan) == P - 1
+    # every non-root leaf gets its broadcast exactly once, from its absorber
+    assert sorted(received) == list(range(1, P))
+    for lvl, recv, send in plan:
+        assert received[send] == recv
+
+
+def test_tree_plan_six_ranks_truth_table():
+    # the 6-processor example: level 0 pairs (0,1),(2,3),(4,5); level 1 (0,2);
+    # level 2 (0,4)
+    assert api.tree_plan(6) == [(0, 0, 1), (0, 2, 3), (0, 4, 5), (1, 0, 2), (2, 0, 4)]
