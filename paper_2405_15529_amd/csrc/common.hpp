@@ -17,8 +17,9 @@ constexpr int YLD = 17;
 
 // ---- MFMA 16x16x4 wrappers ------------------------------------------------
 // Lane layout (wave64): A (16x4): lane l holds A[l%16][l/16];
-// B (4x16): lane l holds B[l/16][l%16]; D (16x16): lane l holds
-// D[4*(l/16)+q][l%16] in element q.
+// B (4x16): lane l holds B[l/16][l%16]; D (16x16): element q of lane l holds
+// D[drow(l/16, q)][l%16], where drow = 4*(l/16)+q for f32 but 4*q+(l/16) for
+// f64 (checked on the device).
 template <typename T>
 struct Mfma;
 
@@ -28,6 +29,7 @@ struct Mfma<double> {
   static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int drow(int g4, int q) { return 4 * q + g4; }
 };
 
 template <>
@@ -36,6 +38,7 @@ struct Mfma<float> {
   static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int drow(int g4, int q) { return 4 * g4 + q; }
 };
 
 template <typename T>

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(64) void k_matmul_tn_partial(int64_t m, int64_t p, 
   double* out = part + split * p * q;
 #pragma unroll
   for (int qq = 0; qq < 4; ++qq) {
-    const int64_t i = i0 + 4 * g4 + qq, j = j0 + i16;
+    const int64_t i = i0 + Mfma<T>::drow(g4, qq), j = j0 + i16;
     if (i < p && j < q) out[i * q + j] = (double)acc[qq];
   }
 }
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(64) void k_matmul_nn(int64_t m, int64_t p, int64_t 
   }
 #pragma unroll
   for (int qq = 0; qq < 4; ++qq) {
-    const int64_t i = i0 + 4 * g4 + qq, j = j0 + i16;
+    const int64_t i = i0 + Mfma<T>::drow(g4, qq), j = j0 + i16;
     if (i < m && j < q) C[i * ldc + j] = acc[qq];
   }
 }

@@ -260,15 +260,17 @@ __device__ __forceinline__ void trailing_update(T* __restrict__ C, int ldc, int 
       const T bv = colok ? C[r * ldc + col] : T(0);
       y = Mfma<T>::op(av, bv, y);
     }
+    T head[4] = {T(0), T(0), T(0), T(0)};
     if (!internal) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = 4 * g4 + q;
-        if (colok && i < kw) y[q] += state[(int64_t)(k0 + i) * n + col];
+        const int i = Mfma<T>::drow(g4, q);
+        if (colok && i < kw) head[q] = state[(int64_t)(k0 + i) * n + col];
+        y[q] += head[q];
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) Yw[(4 * g4 + q) * YLD + i16] = y[q];
+    for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * YLD + i16] = y[q];
     wave_lds_sync();
     v4 z = vzero4<T>();
 #pragma unroll
@@ -279,13 +281,13 @@ __device__ __forceinline__ void trailing_update(T* __restrict__ C, int ldc, int 
     if (!internal) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = 4 * g4 + q;
-        if (colok && i < kw) state[(int64_t)(k0 + i) * n + col] = y[q] - z[q];
+        const int i = Mfma<T>::drow(g4, q);
+        if (colok && i < kw) state[(int64_t)(k0 + i) * n + col] = head[q] - z[q];
       }
     }
     wave_lds_sync();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) Yw[(4 * g4 + q) * YLD + i16] = z[q];
+    for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * YLD + i16] = z[q];
     wave_lds_sync();
     for (int mt = 0; mt < s / 16; ++mt) {
       v4 u = vzero4<T>();
@@ -296,7 +298,7 @@ __device__ __forceinline__ void trailing_update(T* __restrict__ C, int ldc, int 
       }
       if (colok) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) C[(16 * mt + 4 * g4 + q) * ldc + col] -= u[q];
+        for (int q = 0; q < 4; ++q) C[(16 * mt + Mfma<T>::drow(g4, q)) * ldc + col] -= u[q];
       }
     }
     wave_lds_sync();
@@ -550,20 +552,20 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
         }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Yp[wave * NB * YLD + (4 * g4 + q) * YLD + i16] = y[q];
+      for (int q = 0; q < 4; ++q) Yp[wave * NB * YLD + (Mfma<T>::drow(g4, q)) * YLD + i16] = y[q];
       __syncthreads();
       // full Y (every wave, redundantly), then T Y
       T yf[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = 4 * g4 + q;
+        const int i = Mfma<T>::drow(g4, q);
         T acc = Yp[i * YLD + i16] + Yp[NB * YLD + i * YLD + i16] + Yp[2 * NB * YLD + i * YLD + i16] +
                 Yp[3 * NB * YLD + i * YLD + i16];
         if (!internal && i < kw) acc += X[(k0 + i) * 17 + i16];
         yf[q] = acc;
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Yw[(4 * g4 + q) * YLD + i16] = yf[q];
+      for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * YLD + i16] = yf[q];
       wave_lds_sync();
       v4 ty = vzero4<T>();
 #pragma unroll
@@ -573,7 +575,7 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
       }
       wave_lds_sync();
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Yw[(4 * g4 + q) * YLD + i16] = ty[q];
+      for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * YLD + i16] = ty[q];
       wave_lds_sync();
       for (int mt = wave; mt < ntr; mt += 4) {
         v4 u = vzero4<T>();
@@ -583,14 +585,14 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
           u = Mfma<T>::op(Vp[(16 * mt + i16) * 17 + k], Yw[k * YLD + i16], u);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Z[(16 * mt + 4 * g4 + q) * 17 + i16] -= u[q];
+        for (int q = 0; q < 4; ++q) Z[(16 * mt + Mfma<T>::drow(g4, q)) * 17 + i16] -= u[q];
       }
       __syncthreads();
       // every wave has read the head rows of X for this panel: update them now
       if (!internal && wave == 0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int i = 4 * g4 + q;
+          const int i = Mfma<T>::drow(g4, q);
           if (i < kw) X[(k0 + i) * 17 + i16] -= ty[q];
         }
       }

@@ -56,9 +56,9 @@ def mode_errors(U, Uref, VT, VTref, Sref, nr, gap=1e-3):
     if nr > 0:
         A = U[:, :nr]
         B = Uref[:, :nr]
-        # |P_A - P_B|_2 = |A^T B_perp| ; computed via the singular values of A^T B
-        s = np.linalg.svd(A.T @ B, compute_uv=False)
-        proj = float(np.sqrt(max(0.0, 1.0 - np.min(s) ** 2)))
+        # sine of the largest principal angle: |A - B (B^T A)|_2 (a direct
+        # residual; sqrt(1 - cos^2) would amplify rounding to sqrt(eps))
+        proj = float(np.linalg.norm(A - B @ (B.T @ A), 2))
     return eu, ev, proj
 
 
