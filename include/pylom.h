@@ -89,6 +89,9 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
  *                  return PYLOM_WNOCONV without sweeping (failure-path tests).
  *   "ws_cap_mb"    workspace cap in MiB (0 = unlimited); a call needing more
  *                  returns PYLOM_ENOMEM.
+ *   "timing"       k > 0: record HIP events around the phases of every
+ *                  pod/tsvd call in a ring of k call slots (read back with
+ *                  pylom_phase_times); 0 = off (default).
  * Unknown keys return PYLOM_EINVAL. */
 int pylom_set_option(pylom_ctx ctx, const char* key, int64_t value);
 int pylom_get_option(pylom_ctx ctx, const char* key, int64_t* value);
@@ -163,6 +166,15 @@ int64_t pylom_tree_plan(int64_t P, int64_t* out, int64_t cap);
  * Host only. */
 int pylom_plan_query(pylom_ctx ctx, int64_t m, int64_t n, int64_t* leaves, int64_t* block_rows,
                      int64_t* chunk_rows, int64_t* levels);
+
+/* Mean phase durations (milliseconds) over the timed pod/tsvd calls made
+ * since the previous read (at most the last k, k = the "timing" option):
+ * out[0] leaf QR (+ fused mean removal), out[1] tree combines, out[2] small
+ * SVD + truncation, out[3] tree propagation, out[4] leaf apply
+ * U = Q_1i W_i (+ mean output).  Host array of `cap` doubles; returns the
+ * number of phases written (5) or a negative status.  Waits for the recorded
+ * events, then starts a new averaging window. */
+int pylom_phase_times(pylom_ctx ctx, double* out, int cap);
 
 /* After a stream synchronisation: the deferred numerical status of the last
  * pod/tsvd call on this context (0 or PYLOM_WNOCONV) and its sweep count.

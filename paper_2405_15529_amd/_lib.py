@@ -41,6 +41,7 @@ SIGNATURES = {
     "pylom_tree_plan": (I64, [I64, I64P, I64]),
     "pylom_plan_query": (ctypes.c_int, [VP, I64, I64, I64P, I64P, I64P, I64P]),
     "pylom_check": (ctypes.c_int, [VP, I64P]),
+    "pylom_phase_times": (ctypes.c_int, [VP, DP, ctypes.c_int]),
 }
 
 _lib = None

@@ -99,6 +99,16 @@ class Context:
         self.check(self.lib.pylom_workspace_query(self.h, dtype, _PREC[precision], m, n, ctypes.byref(b)))
         return b.value
 
+    PHASES = ("leaf_qr", "tree_combine", "small_svd", "tree_propagate", "leaf_apply")
+
+    def phase_times(self) -> dict:
+        """Per-phase milliseconds of the last timed pod/tsvd call (option 'timing')."""
+        buf = (ctypes.c_double * 5)()
+        rc = self.lib.pylom_phase_times(self.h, buf, 5)
+        if rc < 0:
+            raise PylomError(rc, self.lib.pylom_last_error(self.h).decode())
+        return {k: buf[i] for i, k in enumerate(self.PHASES)}
+
     def status(self):
         """Synchronise the stream; return (status, sweeps) of the last SVD."""
         sw = ctypes.c_int64()

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/pylom.h"
 #include "kernels.hpp"
@@ -28,6 +29,9 @@ struct pylom_ctx_s {
   int64_t ws_cap_mb = 0;
   int* status_dev = nullptr;  // Jacobi status of the last SVD (2 ints)
   int status_valid = 0;
+  int64_t timing = 0;         // number of per-call event slots (0 = off)
+  std::vector<hipEvent_t> ev;  // timing x 6 events
+  int64_t ev_calls = 0;        // timed calls since the last read
   std::string last_error;
 };
 
@@ -91,6 +95,8 @@ extern "C" int pylom_destroy(pylom_ctx c) {
     hipStreamSynchronize(c->stream);
     if (c->ws) hipFree(c->ws);
     if (c->status_dev) hipFree(c->status_dev);
+    for (hipEvent_t e : c->ev)
+      if (e) hipEventDestroy(e);
   }
   delete c;
   return PYLOM_OK;
@@ -113,6 +119,19 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
   } else if (!std::strcmp(key, "ws_cap_mb")) {
     if (v < 0) return fail(c, PYLOM_EINVAL, "ws_cap_mb must be >= 0");
     c->ws_cap_mb = v;
+  } else if (!std::strcmp(key, "timing")) {
+    if (v < 0 || v > 4096) return fail(c, PYLOM_EINVAL, "timing must be in [0, 4096]");
+    if (c->device >= 0) {
+      hipSetDevice(c->device);
+      hipStreamSynchronize(c->stream);
+      for (hipEvent_t e : c->ev)
+        if (e) hipEventDestroy(e);
+      c->ev.assign((size_t)v * 6, nullptr);
+      for (auto& e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) return fail(c, PYLOM_EHIP, "hipEventCreate");
+    }
+    c->timing = v;
+    c->ev_calls = 0;
   } else {
     return fail(c, PYLOM_EINVAL, "unknown option");
   }
@@ -127,6 +146,8 @@ extern "C" int pylom_get_option(pylom_ctx c, const char* key, int64_t* v) {
     *v = c->max_sweeps;
   else if (!std::strcmp(key, "ws_cap_mb"))
     *v = c->ws_cap_mb;
+  else if (!std::strcmp(key, "timing"))
+    *v = c->timing;
   else
     return fail(c, PYLOM_EINVAL, "unknown option");
   return PYLOM_OK;
@@ -309,23 +330,35 @@ static int run_tsvd(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, 
   void* svdws = ws + p.oSvd;
   hipStream_t st = c->stream;
   const int in64 = dtype == PYLOM_R64;
+  const bool tm = c->timing > 0 && !c->ev.empty();
+  hipEvent_t* evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * 6] : nullptr;
+#define MARK(i) \
+  if (tm) HIPCHK(c, hipEventRecord(evs[i], st), "hipEventRecord")
 
+  MARK(0);
   HIPCHK(c, launch_leaf_qr_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws, V, Tleaf,
                                p.nch_leaf, Rbuf, st), "leaf QR");
+  MARK(1);
   for (int64_t h = 1; h < p.P; h *= 2)
     HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, 1, st), "tree combine");
+  MARK(2);
   HIPCHK(c, launch_small_svd(p.jp, Rbuf, (int)c->max_sweeps, svdws, S, VT, ldvt, W, residual, n_r,
                              c->status_dev, st), "small SVD");
   c->status_valid = 1;
+  MARK(3);
   int64_t top = 1;
   while (top * 2 < p.P) top *= 2;
   if (p.P > 1)
     for (int64_t h = top; h >= 1; h /= 2)
       HIPCHK(c, launch_apply_tree_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, W, n, n_r, n, st),
              "tree propagation");
+  MARK(4);
   HIPCHK(c, launch_apply_leaf_f64(p.g, m, p.b, p.P, V, Tleaf, p.nch_leaf, W, n, n_r, n, U, in64,
                                   ldu, st), "leaf apply");
   if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, in64, m, st), "mean out");
+  MARK(5);
+#undef MARK
+  if (tm) ++c->ev_calls;
   return PYLOM_OK;
 }
 
@@ -412,6 +445,27 @@ extern "C" int pylom_matmul(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int
     HIPCHK(c, launch_matmul_nn(f64, m, p, q, A, lda, B, ldb, C, ldc, c->stream), "matmul nn");
   }
   return PYLOM_OK;
+}
+
+extern "C" int pylom_phase_times(pylom_ctx c, double* out, int cap) {
+  if (!c || (cap > 0 && !out)) return PYLOM_EINVAL;
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  if (c->timing <= 0 || c->ev_calls == 0) return fail(c, PYLOM_EINVAL, "no timed call recorded");
+  const int64_t nrec = c->ev_calls < c->timing ? c->ev_calls : c->timing;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t k = 0; k < nrec; ++k) {
+    const int64_t slot = (c->ev_calls - 1 - k) % c->timing;
+    hipEvent_t* e = &c->ev[(size_t)slot * 6];
+    HIPCHK(c, hipEventSynchronize(e[5]), "hipEventSynchronize");
+    for (int i = 0; i < 5; ++i) {
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, e[i], e[i + 1]), "hipEventElapsedTime");
+      acc[i] += ms;
+    }
+  }
+  for (int i = 0; i < 5 && i < cap; ++i) out[i] = acc[i] / (double)nrec;
+  c->ev_calls = 0;
+  return 5;
 }
 
 extern "C" int pylom_check(pylom_ctx c, int64_t* sweeps) {

@@ -124,3 +124,33 @@ def uneven_batch(count: int = 64, seed: int = 4, m_lo: float = 5e4, m_hi: float 
     ms = np.round(np.exp(rng.uniform(np.log(m_lo), np.log(m_hi), count))).astype(np.int64)
     ns = rng.integers(n_lo, n_hi + 1, count)
     return [(int(a), int(max(b, 1))) for a, b in zip(ms, ns)]
+
+
+def graded_fp64_device(m: int = 1_048_576, n: int = 256, seed: int = 1, per_decade: float = 32.0,
+                       device: str = "cuda", with_factors: bool = False):
+    """Device-side twin of ``graded_fp64`` for large m: A = Q1 diag(s) Q2^T.
+
+    Q1 is the Q factor of an m x n Gaussian matrix G (seeded numpy draw),
+    formed as G L^{-T} with L L^T = G^T G (positive-diagonal Cholesky, so it
+    is the same Haar-distributed factor as the QR with diag R > 0; G is
+    well conditioned, kappa ~ 1 + 2 sqrt(n/m)).  The Gram and the products run
+    as library GEMMs on the device; Q2 is drawn on the host.  Returns
+    (A, s) or (A, s, Q1, Q2) as torch tensors on `device`."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    G = torch.from_numpy(rng.standard_normal((m, n))).to(device)
+    Q2 = haar(rng, n, n)
+    gram = (G.T @ G).cpu().numpy()
+    L = np.linalg.cholesky(gram)
+    Linv_t = np.linalg.inv(L).T  # L^{-T}
+    s = graded_spectrum(n, per_decade)
+    Q1 = G @ torch.from_numpy(np.ascontiguousarray(Linv_t)).to(device)
+    del G
+    Q2d = torch.from_numpy(Q2).to(device)
+    A = (Q1 * torch.from_numpy(s).to(device)[None, :]) @ Q2d.T.contiguous()
+    A = A.contiguous()
+    if with_factors:
+        return A, s, Q1, Q2
+    del Q1
+    return A, s
