@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--block-rows", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=32768)
+    ap.add_argument("--cpu-rows", type=int, default=131072)
     return ap.parse_args()
 
 

@@ -113,6 +113,103 @@ __device__ __forceinline__ void wave_reduce16(const T (&in)[16], T (&out)[16], i
   for (int j = 0; j < 16; ++j) out[j] = readlane(h1, 4 * j);
 }
 
+// ---- DPP / permlane reductions (gfx950) ------------------------------------
+// DPP controls: row_ror:N = 0x120 + N, row_mirror = 0x140, row_half_mirror =
+// 0x141, quad_perm [3,2,1,0] = 0x1B, quad_perm [1,0,3,2] = 0xB1.
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// x + (x of the paired row): permlane16_swap pairs rows 0<->1 and 2<->3,
+// permlane32_swap pairs the two 32-lane halves.  Both results of the swap hold
+// {own, partner} in some order, so their sum is the pair total in every lane.
+__device__ __forceinline__ double perm16_pairsum(double x) {
+  const long long v = __double_as_longlong(x);
+  const auto lo = __builtin_amdgcn_permlane16_swap((int)(v & 0xffffffffll), (int)(v & 0xffffffffll), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((int)(v >> 32), (int)(v >> 32), false, false);
+  const double a = __longlong_as_double(((long long)hi[0] << 32) | (unsigned int)lo[0]);
+  const double b = __longlong_as_double(((long long)hi[1] << 32) | (unsigned int)lo[1]);
+  return a + b;
+}
+__device__ __forceinline__ double perm32_pairsum(double x) {
+  const long long v = __double_as_longlong(x);
+  const auto lo = __builtin_amdgcn_permlane32_swap((int)(v & 0xffffffffll), (int)(v & 0xffffffffll), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((int)(v >> 32), (int)(v >> 32), false, false);
+  const double a = __longlong_as_double(((long long)hi[0] << 32) | (unsigned int)lo[0]);
+  const double b = __longlong_as_double(((long long)hi[1] << 32) | (unsigned int)lo[1]);
+  return a + b;
+}
+__device__ __forceinline__ float perm16_pairsum(float x) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(x), __float_as_int(x), false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+__device__ __forceinline__ float perm32_pairsum(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(x), __float_as_int(x), false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+
+// Total over the 64 lanes, in every lane: rotations inside each 16-lane row,
+// then the two row-pair swaps.
+template <typename T>
+__device__ __forceinline__ T wave_sum_fast(T x) {
+  x += dpp<0x128>(x);
+  x += dpp<0x124>(x);
+  x += dpp<0x122>(x);
+  x += dpp<0x121>(x);
+  x = perm16_pairsum(x);
+  x = perm32_pairsum(x);
+  return x;
+}
+
+// Reduce 16 per-lane values over the wave; every lane gets all 16 totals.
+// Inside each row a halving exchange over involutive DPP pairings (mirror,
+// half mirror, quad 3210, quad 1032) leaves lane i with the row partial of
+// value i; the row-pair swaps add the four rows; readlane broadcasts.
+template <typename T>
+__device__ __forceinline__ void wave_reduce16_fast(const T (&in)[16], T (&out)[16], int lane) {
+  const int i = lane & 15;
+  const bool b3 = i >= 8, b2 = (i & 7) >= 4, b1 = (i & 3) >= 2, b0 = i & 1;
+  T h8[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const T keep = b3 ? in[8 + k] : in[k];
+    const T send = b3 ? in[k] : in[8 + k];
+    h8[k] = keep + dpp<0x140>(send);
+  }
+  T h4[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const T keep = b2 ? h8[4 + k] : h8[k];
+    const T send = b2 ? h8[k] : h8[4 + k];
+    h4[k] = keep + dpp<0x141>(send);
+  }
+  T h2[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const T keep = b1 ? h4[2 + k] : h4[k];
+    const T send = b1 ? h4[k] : h4[2 + k];
+    h2[k] = keep + dpp<0x1B>(send);
+  }
+  T h1;
+  {
+    const T keep = b0 ? h2[1] : h2[0];
+    const T send = b0 ? h2[0] : h2[1];
+    h1 = keep + dpp<0xB1>(send);
+  }
+  h1 = perm16_pairsum(h1);
+  h1 = perm32_pairsum(h1);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) out[j] = readlane(h1, j);
+}
+
 // Orders LDS accesses of one wave against each other (no cross-wave sync).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -36,20 +36,25 @@ namespace pylom {
 // ---------------------------------------------------------------------------
 // geometry
 // ---------------------------------------------------------------------------
-static const size_t kQrLdsBudget = 156 * 1024;  // bytes usable by one workgroup
+static const size_t kQrLdsBudget = 160 * 1024;  // bytes of LDS per workgroup (gfx950)
 
+// LDS of the QR kernel: chunk C (s x ldc), two reflector panels Vp (s x 17),
+// two T factors (16 x 16), four 16 x 16 Y tiles (the panel wave's also holds
+// its Gram matrix), the diagonal block Rd (16 x 17), the broadcast column vb
+// (64) and the 16 tau.
 size_t qr_lds_bytes(const QrGeom& g, int esize) {
-  size_t e = (size_t)g.s * g.ldc + (size_t)g.s * VPLD + (size_t)NB * TLD + 4 * (size_t)NB * YLD;
+  size_t e = (size_t)g.s * g.ldc + 2 * (size_t)g.s * VPLD + 2 * (size_t)NB * NB +
+             4 * (size_t)NB * NB + (size_t)NB * TLD + 64 + 16;
   return e * esize;
 }
 
 bool qr_geom(int n, int esize, QrGeom* g) {
   if (n < 1) return false;
   g->n = n;
-  g->ldc = (n % 2 == 1) ? n : n + 1;
+  g->ldc = n;  // column-per-lane panel access and MFMA operand walks are row-contiguous
   g->npanels = (n + NB - 1) / NB;
   int best = 0;
-  for (int s = 16; s <= 64; s += 16) {  // one chunk row per lane of the panel wave
+  for (int s = 16; s <= 64; s += 16) {
     QrGeom t = *g;
     t.s = s;
     if (qr_lds_bytes(t, esize) <= kQrLdsBudget) best = s;
@@ -93,225 +98,312 @@ struct QrArgs {
 // panel factorisation (one wave)
 // ---------------------------------------------------------------------------
 // Factors columns k0..k0+kw-1 of the stacked matrix.  Structured panel
-// (!internal): the head of column k is state row k, held as the 16x16 diagonal
-// block rd (lane jj keeps column jj), the tail is the whole chunk column.
-// Internal panel (leaf filling): the head is chunk row h = k - f.
+// (!INTERNAL): the head of column k is state row k (the 16x16 diagonal block,
+// staged in LDS as Rd), the tail is the whole chunk column.  Internal panel
+// (INTERNAL, leaf filling): the head is chunk row h = k - f.
+//
+// Layout: lane l = 16 g + j holds column j of the panel for the chunk rows
+// r = g + 4 t (t < RT = s/4), so a column norm or a column dot product is an
+// in-lane sum plus two row-pair swaps.  The reflector of the current column
+// is broadcast through LDS (vb).  One fused pass gives both v_k^T [head;
+// column j] for j > k (the update coefficients) and the Gram entries
+// v_j^T v_k for j < k (from which the compact-WY T factor is built).
+//
 // On exit: C holds the reflector tails (and, for internal panels, the new R
 // rows), Vp the exact reflectors (0 / 1 / tail), Tm the T factor, and the
-// state's diagonal block is updated (structured).
-template <typename T, int RPL>
-__device__ __forceinline__ void factor_panel(T* __restrict__ C, int ldc, int s, T* __restrict__ Vp,
-                             T* __restrict__ Tm, T* __restrict__ state, int n, int k0, int kw,
-                             bool internal, int f, int lane) {
-  T p[RPL][NB];
+// state's diagonal block is written back (structured).
+template <typename T, int RT, bool INTERNAL>
+__device__ __forceinline__ void factor_panel(T* __restrict__ C, int ldc, T* __restrict__ Vp,
+                                             T* __restrict__ Tm, T* __restrict__ state, int n,
+                                             int k0, int kw, int f, int lane,
+                                             const T (&rd4)[4], T* __restrict__ Rd,
+                                             T* __restrict__ Gm, T* __restrict__ vb,
+                                             T* __restrict__ taus) {
+  const int j = lane & 15, g = lane >> 4;
+  T p[RT];
 #pragma unroll
-  for (int i = 0; i < RPL; ++i) {
-    const int r = lane + 64 * i;
+  for (int t = 0; t < RT; ++t) p[t] = (j < kw) ? C[(g + 4 * t) * ldc + k0 + j] : T(0);
+  if (!INTERNAL) {
 #pragma unroll
-    for (int kk = 0; kk < NB; ++kk) p[i][kk] = (r < s && kk < kw) ? C[r * ldc + k0 + kk] : T(0);
+    for (int u = 0; u < 4; ++u) Rd[(g * 4 + u) * TLD + j] = rd4[u];
   }
-  T rd[NB];
 #pragma unroll
-  for (int kk = 0; kk < NB; ++kk)
-    rd[kk] = (!internal && lane < kw && kk <= lane) ? state[(int64_t)(k0 + kk) * n + k0 + lane] : T(0);
-  T tr[NB];
+  for (int u = 0; u < 4; ++u) Gm[(g * 4 + u) * NB + j] = T(0);
+  wave_lds_sync();
+#pragma unroll 1
+  for (int kk = 0; kk < kw; ++kk) {
+    const int h = INTERNAL ? (k0 + kk - f) : -1;
+    T alpha;
+    if (!INTERNAL) {
+      alpha = Rd[kk * TLD + kk];
+    } else {
+      T x = T(0);
 #pragma unroll
-  for (int jj = 0; jj < NB; ++jj) tr[jj] = T(0);
-
+      for (int t = 0; t < RT; ++t)
+        if (t == (h >> 2)) x = p[t];
+      alpha = readlane(x, ((h & 3) << 4) + kk);
+    }
+    // squared norm of the tail of column kk
+    T x2 = T(0);
 #pragma unroll
-  for (int kk = 0; kk < NB; ++kk) {
-    if (kk < kw) {
-      const int h = internal ? (k0 + kk - f) : -1;
-      T alpha;
-      if (!internal) {
-        alpha = readlane(rd[kk], kk);
-      } else {
-        T hv = p[0][kk];
+    for (int t = 0; t < RT; ++t) {
+      const int r = g + 4 * t;
+      if (!INTERNAL || r > h) x2 += p[t] * p[t];
+    }
+    x2 = perm32_pairsum(perm16_pairsum(x2));
+    const T sig = readlane(x2, kk);
+    T tau, beta, scal;
+    if (sig == T(0)) {
+      tau = T(0);
+      beta = alpha;
+      scal = T(0);
+    } else {
+      const T nrm = sqrt(alpha * alpha + sig);
+      beta = (alpha >= T(0)) ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scal = T(1) / (alpha - beta);
+    }
+    // reflector of column kk: exact values to vb, stored values back into p
+    if (j == kk) {
 #pragma unroll
-        for (int i = 1; i < RPL; ++i)
-          if ((h >> 6) == i) hv = p[i][kk];
-        alpha = readlane(hv, h & 63);
-      }
-      T x2 = T(0);
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = lane + 64 * i;
-        if (!internal || r > h) x2 += p[i][kk] * p[i][kk];
-      }
-      const T sig = wave_sum(x2);
-      T tau, beta, scal;
-      if (sig == T(0)) {
-        tau = T(0);
-        beta = alpha;
-        scal = T(0);
-      } else {
-        const T nrm = sqrt(alpha * alpha + sig);
-        beta = (alpha >= T(0)) ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scal = T(1) / (alpha - beta);
-      }
-      T v[RPL];
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = lane + 64 * i;
-        if (internal) {
-          v[i] = (r < h) ? T(0) : ((r == h) ? T(1) : p[i][kk] * scal);
-          if (r == h)
-            p[i][kk] = beta;
-          else if (r > h)
-            p[i][kk] = v[i];
+      for (int t = 0; t < RT; ++t) {
+        const int r = g + 4 * t;
+        T vx;
+        if (INTERNAL) {
+          vx = (r < h) ? T(0) : ((r == h) ? T(1) : p[t] * scal);
+          p[t] = (r == h) ? beta : ((r > h) ? vx : p[t]);
         } else {
-          v[i] = p[i][kk] * scal;
-          p[i][kk] = v[i];
+          vx = p[t] * scal;
+          p[t] = vx;
         }
+        vb[g * RT + t] = vx;
       }
-      if (!internal && lane == kk) rd[kk] = beta;
-      // partial products: Gram with earlier reflectors (T factor), and
-      // v^T [head; column] for the remaining panel columns
-      T part[NB];
+      if (g == 0) taus[kk] = tau;
+    }
+    if (!INTERNAL && lane == 0) Rd[kk * TLD + kk] = beta;
+    wave_lds_sync();
+    T v[RT];
 #pragma unroll
-      for (int jj = 0; jj < NB; ++jj) {
-        T acc = T(0);
-        if (jj < kk) {
-          const int hj = internal ? (k0 + jj - f) : -1;
+    for (int t = 0; t < RT; ++t) v[t] = vb[g * RT + t];
+    // fused pass: j > kk -> v^T [head; column j];  j < kk -> v_j^T v
+    const int hj = INTERNAL ? (k0 + j - f) : -1;
+    T d = T(0);
 #pragma unroll
-          for (int i = 0; i < RPL; ++i) {
-            const int r = lane + 64 * i;
-            T vj = internal ? ((r < hj) ? T(0) : ((r == hj) ? T(1) : p[i][jj])) : p[i][jj];
-            acc += vj * v[i];
-          }
-        } else if (jj > kk) {
+    for (int t = 0; t < RT; ++t) {
+      const int r = g + 4 * t;
+      T cj = p[t];
+      if (INTERNAL && j < kk) cj = (r < hj) ? T(0) : ((r == hj) ? T(1) : p[t]);
+      d += cj * v[t];
+    }
+    if (!INTERNAL && j > kk && g == 0) d += Rd[kk * TLD + j];
+    d = perm32_pairsum(perm16_pairsum(d));
+    if (j < kk && g == 0) Gm[kk * NB + j] = d;
+    if (j > kk) {
+      const T tw = tau * d;
 #pragma unroll
-          for (int i = 0; i < RPL; ++i) acc += v[i] * p[i][jj];
-          if (!internal && lane == jj) acc += rd[kk];
-        }
-        part[jj] = acc;
-      }
-      T w[NB];
-      wave_reduce16(part, w, lane);
-      // T(0:kk, kk) = -tau T(0:kk, 0:kk) (V(:,0:kk)^T v_kk),  T(kk,kk) = tau
-      T tcol = T(0);
+      for (int t = 0; t < RT; ++t) p[t] -= tw * v[t];
+      if (!INTERNAL && g == 0) Rd[kk * TLD + j] -= tw;
+    }
+    wave_lds_sync();
+  }
+  // compact-WY T (lane j < 16 builds row j): T(c,c) = tau_c,
+  // T(j,c) = -tau_c sum_{l=j}^{c-1} T(j,l) G(l,c).  Gm holds G transposed
+  // (Gm[c][l] = G(l,c)) so that a column is one contiguous read.
+  if (g == 0) {
+    T trow[NB];
 #pragma unroll
-      for (int l = 0; l < kk; ++l) tcol += tr[l] * w[l];
-      if (lane < kk)
-        tr[kk] = -tau * tcol;
-      else if (lane == kk)
-        tr[kk] = tau;
-      // apply H_kk^T to the remaining panel columns
+    for (int l = 0; l < NB; ++l) trow[l] = T(0);
+#pragma unroll 1
+    for (int c = 0; c < kw; ++c) {
+      T acc = T(0);
 #pragma unroll
-      for (int jj = kk + 1; jj < NB; ++jj) {
-        const T tw = tau * w[jj];
+      for (int l = 0; l < NB; ++l) acc += (l < c) ? trow[l] * Gm[c * NB + l] : T(0);
+      const T tc = taus[c];
+      const T val = (j < c) ? -tc * acc : ((j == c) ? tc : T(0));
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) p[i][jj] -= tw * v[i];
-        if (!internal && lane == jj) rd[kk] -= tw;
+      for (int l = 0; l < NB; ++l) trow[l] = (l == c) ? val : trow[l];
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Tm[j * NB + c] = trow[c];
+  }
+  // write back: C (tails and R rows), exact reflectors, state diagonal block
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int r = g + 4 * t;
+    T vx = T(0);
+    if (j < kw) {
+      C[r * ldc + k0 + j] = p[t];
+      if (INTERNAL) {
+        const int hk = k0 + j - f;
+        vx = (r < hk) ? T(0) : ((r == hk) ? T(1) : p[t]);
+      } else {
+        vx = p[t];
       }
     }
+    Vp[r * VPLD + j] = vx;
   }
-  // write back: C (tails and R rows), exact reflectors, T, state diagonal block
+  if (!INTERNAL) {
 #pragma unroll
-  for (int i = 0; i < RPL; ++i) {
-    const int r = lane + 64 * i;
-    if (r < s) {
-#pragma unroll
-      for (int kk = 0; kk < NB; ++kk) {
-        T vx = T(0);
-        if (kk < kw) {
-          C[r * ldc + k0 + kk] = p[i][kk];
-          if (internal) {
-            const int hk = k0 + kk - f;
-            vx = (r < hk) ? T(0) : ((r == hk) ? T(1) : p[i][kk]);
-          } else {
-            vx = p[i][kk];
-          }
-        }
-        Vp[r * VPLD + kk] = vx;
-      }
+    for (int u = 0; u < 4; ++u) {
+      const int kk = g * 4 + u;
+      if (kk <= j && j < kw) state[(int64_t)(k0 + kk) * n + k0 + j] = Rd[kk * TLD + j];
     }
   }
-  if (lane < NB) {
+  wave_lds_sync();
+}
+
+// Diagonal block of the state for the panel starting at k0: lane 16 g + j
+// holds rows 4 g .. 4 g + 3 of column j (upper triangle only).
+template <typename T>
+__device__ __forceinline__ void load_diag4(T (&rd)[4], const T* __restrict__ state, int n, int k0,
+                                           int lane) {
+  const int j = lane & 15, g = lane >> 4;
+  const int kw = (n - k0 < NB) ? n - k0 : NB;
 #pragma unroll
-    for (int jj = 0; jj < NB; ++jj) Tm[lane * TLD + jj] = tr[jj];
+  for (int u = 0; u < 4; ++u) {
+    const int kk = g * 4 + u;
+    rd[u] = (j < kw && kk <= j) ? state[(int64_t)(k0 + kk) * n + k0 + j] : T(0);
   }
-  if (!internal && lane < kw) {
+}
+
+// Head values (state rows k0..k0+15, the 16 columns from col0) in MFMA D
+// layout.
+template <typename T>
+__device__ __forceinline__ void load_head4(T (&hd)[4], const T* __restrict__ state, int n, int k0,
+                                           int kw, int col0, int lane) {
+  const int i16 = lane & 15, g4 = lane >> 4;
+  const int col = col0 + i16;
 #pragma unroll
-    for (int kk = 0; kk < NB; ++kk)
-      if (kk <= lane && kk < kw) state[(int64_t)(k0 + kk) * n + k0 + lane] = rd[kk];
+  for (int q = 0; q < 4; ++q) {
+    const int i = Mfma<T>::drow(g4, q);
+    hd[q] = (col < n && i < kw) ? state[(int64_t)(k0 + i) * n + col] : T(0);
   }
 }
 
 // ---------------------------------------------------------------------------
-// trailing update: [head; C(:, trail)] <- Q_p^T [head; C(:, trail)]
+// one trailing tile: [head; C(:, col0:col0+16)] <- Q_p^T [head; C(...)]
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void trailing_update(T* __restrict__ C, int ldc, int s, const T* __restrict__ Vp,
-                                const T* __restrict__ Tm, T* __restrict__ Yw, T* __restrict__ state,
-                                int n, int k0, int kw, bool internal, int wave, int lane) {
+template <typename T, int RT>
+__device__ __forceinline__ void tile_update(T* __restrict__ C, int ldc, const T* __restrict__ Vp,
+                                            const T* __restrict__ Tm, T* __restrict__ Yw,
+                                            T* __restrict__ state, int n, int k0, int kw,
+                                            bool internal, int col0, const T (&head)[4],
+                                            int lane) {
   typedef typename Mfma<T>::v4 v4;
-  const int cb = k0 + kw;
-  const int ntiles = (n - cb + 15) / 16;
+  constexpr int S = 4 * RT;  // chunk rows
   const int i16 = lane & 15, g4 = lane >> 4;
-  for (int t = wave; t < ntiles; t += 4) {
-    const int col = cb + 16 * t + i16;
-    const bool colok = col < n;
-    v4 y = vzero4<T>();
-    for (int kb = 0; kb < s / 4; ++kb) {
-      const int r = 4 * kb + g4;
-      const T av = Vp[r * VPLD + i16];
-      const T bv = colok ? C[r * ldc + col] : T(0);
-      y = Mfma<T>::op(av, bv, y);
+  const int col = col0 + i16;
+  const bool colok = col < n;
+  // Y = V^T C(:, tile): operands batched, two independent accumulators
+  v4 y0 = vzero4<T>(), y1 = vzero4<T>();
+#pragma unroll
+  for (int kb0 = 0; kb0 < S / 4; kb0 += 4) {
+    T av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = 4 * (kb0 + u) + g4;
+      av[u] = Vp[r * VPLD + i16];
+      bv[u] = colok ? C[r * ldc + col] : T(0);
     }
-    T head[4] = {T(0), T(0), T(0), T(0)};
-    if (!internal) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = Mfma<T>::drow(g4, q);
-        if (colok && i < kw) head[q] = state[(int64_t)(k0 + i) * n + col];
-        y[q] += head[q];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * YLD + i16] = y[q];
-    wave_lds_sync();
-    v4 z = vzero4<T>();
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      const int k = 4 * kb + g4;
-      z = Mfma<T>::op(Tm[k * TLD + i16], Yw[k * YLD + i16], z);  // (T^T Y)
-    }
-    if (!internal) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = Mfma<T>::drow(g4, q);
-        if (colok && i < kw) state[(int64_t)(k0 + i) * n + col] = head[q] - z[q];
-      }
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * YLD + i16] = z[q];
-    wave_lds_sync();
-    for (int mt = 0; mt < s / 16; ++mt) {
-      v4 u = vzero4<T>();
-#pragma unroll
-      for (int kb = 0; kb < 4; ++kb) {
-        const int k = 4 * kb + g4;
-        u = Mfma<T>::op(Vp[(16 * mt + i16) * VPLD + k], Yw[k * YLD + i16], u);
-      }
-      if (colok) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) C[(16 * mt + Mfma<T>::drow(g4, q)) * ldc + col] -= u[q];
-      }
-    }
-    wave_lds_sync();
+    y0 = Mfma<T>::op(av[0], bv[0], y0);
+    y1 = Mfma<T>::op(av[1], bv[1], y1);
+    y0 = Mfma<T>::op(av[2], bv[2], y0);
+    y1 = Mfma<T>::op(av[3], bv[3], y1);
   }
+  T y[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) y[q] = y0[q] + y1[q] + (internal ? T(0) : head[q]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * NB + i16] = y[q];
+  wave_lds_sync();
+  v4 z = vzero4<T>();
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    const int k = 4 * kb + g4;
+    z = Mfma<T>::op(Tm[k * NB + i16], Yw[k * NB + i16], z);  // (T^T Y)
+  }
+  if (!internal) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = Mfma<T>::drow(g4, q);
+      if (colok && i < kw) state[(int64_t)(k0 + i) * n + col] = head[q] - z[q];
+    }
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * NB + i16] = z[q];
+  wave_lds_sync();
+  // C(:, tile) -= V Z: the S/16 row tiles are independent accumulations
+  T zb[4];
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) zb[kb] = Yw[(4 * kb + g4) * NB + i16];
+  v4 u[S / 16];
+  T a[S / 16][4];
+#pragma unroll
+  for (int m = 0; m < S / 16; ++m)
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) a[m][kb] = Vp[(16 * m + i16) * VPLD + 4 * kb + g4];
+#pragma unroll
+  for (int m = 0; m < S / 16; ++m) u[m] = vzero4<T>();
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+    for (int m = 0; m < S / 16; ++m) u[m] = Mfma<T>::op(a[m][kb], zb[kb], u[m]);
+  if (colok) {
+#pragma unroll
+    for (int m = 0; m < S / 16; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) C[(16 * m + Mfma<T>::drow(g4, q)) * ldc + col] -= u[m][q];
+  }
+  wave_lds_sync();
 }
 
 // ---------------------------------------------------------------------------
 // chunk loads
 // ---------------------------------------------------------------------------
+// Rows i = wave, wave + 4, ... of the chunk, LB rows per batch with all their
+// loads issued before any is consumed; optional row-mean removal (Alg. 2).
 template <typename T, typename TI>
 __device__ __forceinline__ void load_chunk(T* __restrict__ C, int ldc, int s, int sc, int n,
-                           const TI* __restrict__ src, int64_t ld_src, int remove_mean,
-                           double* __restrict__ mean_out, int wave, int lane) {
+                                           const TI* __restrict__ src, int64_t ld_src,
+                                           int remove_mean, double* __restrict__ mean_out,
+                                           int wave, int lane) {
+  constexpr int LB = 4;    // rows per batch and wave
+  constexpr int NCOL = 4;  // columns per lane and row held in registers (n <= 256)
+  if (n <= 64 * NCOL) {
+    for (int i0 = wave; i0 < s; i0 += 4 * LB) {
+      TI x[LB][NCOL];
+#pragma unroll
+      for (int b = 0; b < LB; ++b) {
+        const int i = i0 + 4 * b;
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) {
+          const int col = lane + 64 * c;
+          x[b][c] = (i < sc && col < n) ? src[(int64_t)i * ld_src + col] : TI(0);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < LB; ++b) {
+        const int i = i0 + 4 * b;
+        if (i >= s) continue;
+        double mu = 0.0;
+        if (remove_mean && i < sc) {
+          double acc = 0.0;
+#pragma unroll
+          for (int c = 0; c < NCOL; ++c) acc += (double)x[b][c];
+          acc = wave_sum_fast(acc);
+          mu = acc / (double)n;
+          if (lane == 0 && mean_out) mean_out[i] = mu;
+        }
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) {
+          const int col = lane + 64 * c;
+          if (col < n) C[i * ldc + col] = (i < sc) ? (T)((double)x[b][c] - mu) : T(0);
+        }
+      }
+    }
+    return;
+  }
   for (int i = wave; i < s; i += 4) {
     if (i >= sc) {
       for (int col = lane; col < n; col += 64) C[i * ldc + col] = T(0);
@@ -321,7 +413,7 @@ __device__ __forceinline__ void load_chunk(T* __restrict__ C, int ldc, int s, in
     if (remove_mean) {
       double acc = 0.0;
       for (int col = lane; col < n; col += 64) acc += (double)row[col];
-      acc = wave_sum(acc);
+      acc = wave_sum_fast(acc);
       const double mu = acc / (double)n;
       for (int col = lane; col < n; col += 64) C[i * ldc + col] = (T)((double)row[col] - mu);
       if (lane == 0 && mean_out) mean_out[i] = mu;
@@ -334,16 +426,27 @@ __device__ __forceinline__ void load_chunk(T* __restrict__ C, int ldc, int s, in
 // ---------------------------------------------------------------------------
 // the stacked QR kernel (leaf or combine)
 // ---------------------------------------------------------------------------
-template <typename T, typename TI, int RPL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_stacked_qr(QrArgs<T, TI> a) {
+// Per chunk the panels are pipelined: in step p, wave 0 first applies panel
+// p-1 to the 16 columns of panel p (look-ahead) and then factors panel p,
+// while waves 1..3 apply panel p-1 to the remaining trailing columns.  The
+// reflectors and T of consecutive panels alternate between two LDS buffers.
+template <typename T, typename TI, int RT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_stacked_qr(QrArgs<T, TI> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int n = a.n, s = a.s, ldc = a.ldc, npan = a.npanels;
+  constexpr int S = 4 * RT;
+  const int n = a.n, ldc = a.ldc, npan = a.npanels;
   T* C = reinterpret_cast<T*>(smem);
-  T* Vp = C + (size_t)s * ldc;
-  T* Tm = Vp + (size_t)s * VPLD;
-  T* Yb = Tm + NB * TLD;
+  T* Vp0 = C + (size_t)S * ldc;
+  T* Tm0 = Vp0 + 2 * (size_t)S * VPLD;
+  T* Yb = Tm0 + 2 * NB * NB;
+  T* Rd = Yb + 4 * NB * NB;
+  T* vb = Rd + NB * TLD;
+  T* taus = vb + 64;
+  T* Gm = Yb;  // the panel wave's Y tile doubles as its Gram scratch
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool leaf = (a.mode == 0);
+  T* Yw = Yb + wave * NB * NB;
 
   const TI* srcI = nullptr;
   const T* srcT = nullptr;
@@ -352,35 +455,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   T* state;
   T* tout;
   if (leaf) {
-    const int64_t j = blockIdx.x;
-    row0 = j * a.b;
-    rows = (j == a.P - 1) ? (a.m - row0) : a.b;
+    const int64_t jl = blockIdx.x;
+    row0 = jl * a.b;
+    rows = (jl == a.P - 1) ? (a.m - row0) : a.b;
     srcI = a.D + row0 * a.ldd;
     ld_src = a.ldd;
     vout = a.store_q ? a.V + row0 * n : nullptr;
-    state = a.Rbuf + j * (int64_t)n * n;
-    tout = a.store_q ? a.Tleaf + j * a.nch_leaf * npan * (NB * NB) : nullptr;
+    state = a.Rbuf + jl * (int64_t)n * n;
+    tout = a.store_q ? a.Tleaf + jl * a.nch_leaf * npan * (NB * NB) : nullptr;
   } else {
-    const int64_t j = (int64_t)blockIdx.x * 2 * a.h;
-    const int64_t jb = j + a.h;
+    const int64_t jn = (int64_t)blockIdx.x * 2 * a.h;
+    const int64_t jb = jn + a.h;
     srcT = a.Rbuf + jb * (int64_t)n * n;
     ld_src = n;
     rows = n;
     vout = a.store_q ? const_cast<T*>(srcT) : nullptr;
-    state = a.Rbuf + j * (int64_t)n * n;
+    state = a.Rbuf + jn * (int64_t)n * n;
     tout = a.store_q ? a.Ttree + jb * a.nch_tree * npan * (NB * NB) : nullptr;
   }
-  const int nch = (int)((rows + s - 1) / s);
+  const int nch = (int)((rows + S - 1) / S);
   int f = leaf ? 0 : n;
   for (int c = 0; c < nch; ++c) {
-    const int64_t r0 = (int64_t)c * s;
-    const int sc = (int)((rows - r0) < s ? (rows - r0) : s);
+    const int64_t r0 = (int64_t)c * S;
+    const int sc = (int)((rows - r0) < S ? (rows - r0) : S);
     if (leaf)
-      load_chunk<T, TI>(C, ldc, s, sc, n, srcI + r0 * ld_src, ld_src, a.remove_mean,
+      load_chunk<T, TI>(C, ldc, S, sc, n, srcI + r0 * ld_src, ld_src, a.remove_mean,
                         a.mean_ws ? a.mean_ws + row0 + r0 : nullptr, wave, lane);
     else
-      load_chunk<T, T>(C, ldc, s, sc, n, srcT + r0 * ld_src, ld_src, 0, nullptr, wave, lane);
-    __syncthreads();
+      load_chunk<T, T>(C, ldc, S, sc, n, srcT + r0 * ld_src, ld_src, 0, nullptr, wave, lane);
     int p_lo, p_hi;
     if (leaf) {
       const int lim = (f + sc < n) ? f + sc : n;
@@ -390,20 +492,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       p_lo = (int)(r0 / NB);
       p_hi = npan;
     }
-    for (int p = p_lo; p < p_hi; ++p) {
-      const int k0 = p * NB;
-      const int kw = (n - k0 < NB) ? n - k0 : NB;
-      const bool internal = leaf && (k0 >= f);
+    // panel wave prefetches: diagonal block of the first panel
+    T rd4[4] = {T(0), T(0), T(0), T(0)};
+    T hd4[4] = {T(0), T(0), T(0), T(0)};
+    if (wave == 0 && !(leaf && p_lo * NB >= f)) load_diag4<T>(rd4, state, n, p_lo * NB, lane);
+    __syncthreads();
+    for (int p = p_lo; p <= p_hi; ++p) {
+      const int kp = (p - 1) * NB;  // previous panel (its reflectors are applied now)
+      const int kwp = (n - kp < NB) ? n - kp : NB;
+      const bool int_prev = leaf && (kp >= f);
+      T* Vprev = Vp0 + ((p - 1) & 1) * S * VPLD;
+      T* Tprev = Tm0 + ((p - 1) & 1) * NB * NB;
       if (wave == 0) {
-        factor_panel<T, RPL>(C, ldc, s, Vp, Tm, state, n, k0, kw, internal, f, lane);
-        if (tout) {
-          T* tp = tout + ((int64_t)c * npan + p) * (NB * NB);
-          for (int e = lane; e < NB * NB; e += 64) tp[e] = Tm[(e / NB) * TLD + (e % NB)];
+        if (p > p_lo && p < npan)
+          tile_update<T, RT>(C, ldc, Vprev, Tprev, Yw, state, n, kp, kwp, int_prev, p * NB, hd4,
+                             lane);
+        if (p < p_hi) {
+          const int k0 = p * NB;
+          const int kw = (n - k0 < NB) ? n - k0 : NB;
+          const bool internal = leaf && (k0 >= f);
+          T* Vcur = Vp0 + (p & 1) * S * VPLD;
+          T* Tcur = Tm0 + (p & 1) * NB * NB;
+          // prefetch for the next step: head values of this panel's rows over the
+          // next panel's columns, and the next panel's diagonal block
+          T rd_next[4] = {T(0), T(0), T(0), T(0)};
+          if (!internal && p + 1 < npan) load_head4<T>(hd4, state, n, k0, kw, (p + 1) * NB, lane);
+          if (p + 1 < p_hi && !(leaf && (p + 1) * NB >= f))
+            load_diag4<T>(rd_next, state, n, (p + 1) * NB, lane);
+          if (internal)
+            factor_panel<T, RT, true>(C, ldc, Vcur, Tcur, state, n, k0, kw, f, lane, rd4, Rd, Gm,
+                                      vb, taus);
+          else
+            factor_panel<T, RT, false>(C, ldc, Vcur, Tcur, state, n, k0, kw, f, lane, rd4, Rd,
+                                       Gm, vb, taus);
+          if (tout) {
+            T* tp = tout + ((int64_t)c * npan + p) * (NB * NB);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) tp[lane + 64 * e] = Tcur[lane + 64 * e];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) rd4[u] = rd_next[u];
+        }
+      } else if (p > p_lo) {
+        for (int t = p + wave; t < npan; t += 3) {
+          T hd[4] = {T(0), T(0), T(0), T(0)};
+          if (!int_prev) load_head4<T>(hd, state, n, kp, kwp, t * NB, lane);
+          tile_update<T, RT>(C, ldc, Vprev, Tprev, Yw, state, n, kp, kwp, int_prev, t * NB, hd,
+                             lane);
         }
       }
-      __syncthreads();
-      trailing_update<T>(C, ldc, s, Vp, Tm, Yb + wave * NB * YLD, state, n, k0, kw, internal,
-                         wave, lane);
       __syncthreads();
     }
     if (leaf && f < n) {
@@ -455,9 +592,11 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = a.n, s = a.s, npan = a.npanels;
   const int64_t ncols = a.nr ? *a.nr : a.ncols;
-  const int ntiles = (int)((a.ncols + 15) / 16);
-  const int tile = blockIdx.x % ntiles;
-  const int64_t prob = blockIdx.x / ntiles;
+  // tile-major block order: the active (tile < N_r / 16) blocks are the first
+  // ones and spread over all XCDs
+  const int64_t nprob = a.mode == 0 ? a.P : (a.P - a.h + 2 * a.h - 1) / (2 * a.h);
+  const int tile = (int)(blockIdx.x / nprob);
+  const int64_t prob = blockIdx.x % nprob;
   if ((int64_t)tile * 16 >= ncols) return;
   const int c0 = tile * 16;
   const bool leaf = (a.mode == 0);
@@ -499,47 +638,77 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
   }
   __syncthreads();
   const int ntr = s / 16;
+  // panel range of chunk c (same rule as the factorisation)
+  auto prange = [&](int64_t c, int& plo, int& phi, int& fc, int& scc) {
+    const int64_t r0 = c * s;
+    scc = (int)((rows - r0) < s ? (rows - r0) : s);
+    fc = leaf ? (int)((r0 < n) ? r0 : n) : n;
+    if (leaf) {
+      const int lim = (fc + scc < n) ? fc + scc : n;
+      plo = 0;
+      phi = (lim + NB - 1) / NB;
+    } else {
+      plo = (int)(r0 / NB);
+      phi = npan;
+    }
+  };
+  // register prefetch of one panel's raw reflector values (s x 16) and T
+  constexpr int VPT = 4;  // values per thread for s <= 64
+  T vreg[VPT];
+  T treg;
+  auto fetch = [&](int64_t c, int p) {
+    int plo, phi, fc, scc;
+    prange(c, plo, phi, fc, scc);
+    const int k0 = p * NB, kw = (n - k0 < NB) ? n - k0 : NB;
+    const int64_t r0 = c * s;
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int idx = tid + 256 * u;
+      const int r = idx >> 4, kk = idx & 15;
+      vreg[u] = (r < scc && kk < kw) ? Vsrc[(r0 + r) * n + k0 + kk] : T(0);
+    }
+    treg = Tsrc[(c * npan + p) * (NB * NB) + tid];
+  };
+  {
+    int plo, phi, fc, scc;
+    prange(nch - 1, plo, phi, fc, scc);
+    fetch(nch - 1, phi - 1);
+  }
   for (int64_t c = nch - 1; c >= 0; --c) {
     const int64_t r0 = c * s;
-    const int sc = (int)((rows - r0) < s ? (rows - r0) : s);
-    const int f = leaf ? (int)((r0 < n) ? r0 : n) : n;
+    int p_lo, p_hi, f, sc;
+    prange(c, p_lo, p_hi, f, sc);
     const int nf = (leaf && f < n) ? ((sc < n - f) ? sc : n - f) : 0;
     for (int idx = tid; idx < s * 16; idx += 256) {
       const int r = idx >> 4, cc = idx & 15;
       Z[r * 17 + cc] = (r < nf) ? X[(f + r) * 17 + cc] : T(0);
     }
-    int p_lo, p_hi;
-    if (leaf) {
-      const int lim = (f + sc < n) ? f + sc : n;
-      p_lo = 0;
-      p_hi = (lim + NB - 1) / NB;
-    } else {
-      p_lo = (int)(r0 / NB);
-      p_hi = npan;
-    }
     for (int p = p_hi - 1; p >= p_lo; --p) {
       const int k0 = p * NB;
       const int kw = (n - k0 < NB) ? n - k0 : NB;
       const bool internal = leaf && (k0 >= f);
-      // stage exact reflectors and T
-      for (int idx = tid; idx < s * NB; idx += 256) {
+      // stage the prefetched panel as exact reflectors (0 / 1 / tail)
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        const int idx = tid + 256 * u;
         const int r = idx >> 4, kk = idx & 15;
-        T vx = T(0);
-        if (r < sc && kk < kw) {
-          const T raw = Vsrc[(r0 + r) * n + k0 + kk];
-          if (internal) {
+        if (r < s) {
+          T vx = vreg[u];
+          if (internal && r < sc && kk < kw) {
             const int hk = k0 + kk - f;
-            vx = (r < hk) ? T(0) : ((r == hk) ? T(1) : raw);
-          } else {
-            vx = raw;
+            vx = (r < hk) ? T(0) : ((r == hk) ? T(1) : vreg[u]);
           }
+          Vp[r * 17 + kk] = vx;
         }
-        Vp[r * 17 + kk] = vx;
       }
-      {
-        const T* tp = Tsrc + (c * npan + p) * (NB * NB);
-        const int e = tid;  // 256 = 16 x 16
-        Tm[(e >> 4) * TLD + (e & 15)] = tp[e];
+      Tm[(tid >> 4) * TLD + (tid & 15)] = treg;
+      // prefetch the next panel in processing order
+      if (p > p_lo) {
+        fetch(c, p - 1);
+      } else if (c > 0) {
+        int plo2, phi2, f2, sc2;
+        prange(c - 1, plo2, phi2, f2, sc2);
+        fetch(c - 1, phi2 - 1);
       }
       __syncthreads();
       // partial Y = V^T Z over this wave's row tiles
@@ -624,20 +793,25 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T, typename TI, int RPL>
+template <typename T, typename TI, int RT>
 static hipError_t launch_qr_t(const QrArgs<T, TI>& a, int grid, size_t lds, hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_stacked_qr<T, TI, RPL>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_stacked_qr<T, TI, RT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_stacked_qr<T, TI, RPL>), dim3(grid), dim3(256), lds, st, a);
+  hipLaunchKernelGGL((k_stacked_qr<T, TI, RT>), dim3(grid), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
 template <typename T, typename TI>
 static hipError_t launch_qr_any(const QrArgs<T, TI>& a, int grid, size_t lds, hipStream_t st) {
   if (grid <= 0) return hipSuccess;
-  if (a.s > 64) return hipErrorInvalidValue;
-  return launch_qr_t<T, TI, 1>(a, grid, lds, st);
+  switch (a.s) {
+    case 16: return launch_qr_t<T, TI, 4>(a, grid, lds, st);
+    case 32: return launch_qr_t<T, TI, 8>(a, grid, lds, st);
+    case 48: return launch_qr_t<T, TI, 12>(a, grid, lds, st);
+    case 64: return launch_qr_t<T, TI, 16>(a, grid, lds, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_leaf_qr_f64(const QrGeom& g, const void* D, int in_f64, int64_t ldd, int64_t m,
@@ -699,6 +873,7 @@ hipError_t launch_apply_leaf_f64(const QrGeom& g, int64_t m, int64_t b, int64_t 
                                  void* U, int out_f64, int64_t ldu, hipStream_t st) {
   const int ntiles = (int)((ncols + 15) / 16);
   const size_t lds = apply_lds_bytes(g, 8);
+  if (P < 1) return hipErrorInvalidValue;
   if (out_f64) {
     ApplyArgs<double, double> a{};
     a.n = g.n; a.s = g.s; a.npanels = g.npanels; a.mode = 0; a.nr = nr; a.ncols = ncols;
@@ -718,9 +893,10 @@ hipError_t launch_apply_tree_f64(const QrGeom& g, int64_t h, int64_t P, const do
                                  const int64_t* nr, int64_t ncols, hipStream_t st) {
   const int ntiles = (int)((ncols + 15) / 16);
   const int64_t ncomb = (P - h + 2 * h - 1) / (2 * h);
+  if (P < 2 || h < 1 || ncomb < 1) return hipErrorInvalidValue;
   ApplyArgs<double, double> a{};
   a.n = g.n; a.s = g.s; a.npanels = g.npanels; a.mode = 1; a.nr = nr; a.ncols = ncols;
-  a.h = h; a.Rbuf = Rbuf; a.Ttree = Ttree; a.nch_tree = nch_tree; a.W = W; a.ldw = ldw;
+  a.P = P; a.h = h; a.Rbuf = Rbuf; a.Ttree = Ttree; a.nch_tree = nch_tree; a.W = W; a.ldw = ldw;
   return launch_apply_t(a, (int)(ncomb * ntiles), apply_lds_bytes(g, 8), st);
 }
 
