@@ -120,6 +120,19 @@ __device__ __forceinline__ void grid_barrier(unsigned int* bar, unsigned int G, 
   __syncthreads();
 }
 
+// Sum over an LPP-lane group (LPP = 16, 32 or 64): DPP rotations inside the
+// 16-lane row, then the row-pair swaps.
+template <int LPP>
+__device__ __forceinline__ double gsum(double x) {
+  x += dpp<0x128>(x);
+  x += dpp<0x124>(x);
+  x += dpp<0x122>(x);
+  x += dpp<0x121>(x);
+  if (LPP >= 32) x = perm16_pairsum(x);
+  if (LPP >= 64) x = perm32_pairsum(x);
+  return x;
+}
+
 // block index of player i (0..2G-1) at tournament step st (circle method)
 __device__ __forceinline__ int rr_player(int i, int st, int nplayers) {
   if (i == 0) return 0;
@@ -136,7 +149,7 @@ __device__ __forceinline__ int jacobi_pair(double (&a)[JRPL], double (&va)[JRPL]
 #pragma unroll
   for (int k = 0; k < JRPL; ++k)
     if (k < rpl_a) g += a[k] * b[k];
-  g = group_sum<LPP>(g);
+  g = gsum<LPP>(g);
   if (!(na > 0.0) || !(nb > 0.0)) return 0;
   if (fabs(g) <= tol * sqrt(na) * sqrt(nb)) return 0;
   const double zeta = (nb - na) / (2.0 * g);
@@ -169,7 +182,7 @@ __device__ __forceinline__ double col_norm2(const double (&a)[JRPL], int rpl) {
 #pragma unroll
   for (int k = 0; k < JRPL; ++k)
     if (k < rpl) x += a[k] * a[k];
-  return group_sum<LPP>(x);
+  return gsum<LPP>(x);
 }
 
 template <int LPP>
@@ -204,8 +217,8 @@ struct JacobiArgs {
 template <int LPP>
 __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
   if (blockIdx.x % a.xcd_stride) return;
-  __shared__ double xbuf[JT * 2 * JRPL];  // circulating b columns (A and V parts)
-  __shared__ double xnorm[JT / 2];
+  __shared__ double xbuf[2][JT * 2 * JRPL];  // circulating b columns (A and V parts), 2 buffers
+  __shared__ double xnorm[2][JT / 2];
   __shared__ int rot_count;
   const int g = blockIdx.x / a.xcd_stride;
   const int tid = threadIdx.x;
@@ -255,22 +268,23 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
       for (int q = 0; q < w; ++q) {
         myrot += jacobi_pair<LPP>(ca, cva, cb, cvb, na, nb, rpl, rpl, tol);
         if (q < w - 1) {
-          // pass my b column to group grp-1, take the one of group grp+1
+          // pass my b column to group grp-1, take the one of group grp+1; the
+          // two buffers alternate, so one barrier per round suffices
+          double* xb = xbuf[q & 1];
 #pragma unroll
           for (int k = 0; k < JRPL; ++k) {
-            xbuf[(grp * LPP + sub) * 2 * JRPL + k] = cb[k];
-            xbuf[(grp * LPP + sub) * 2 * JRPL + JRPL + k] = cvb[k];
+            xb[(grp * LPP + sub) * 2 * JRPL + k] = cb[k];
+            xb[(grp * LPP + sub) * 2 * JRPL + JRPL + k] = cvb[k];
           }
-          if (sub == 0) xnorm[grp] = nb;
+          if (sub == 0) xnorm[q & 1][grp] = nb;
           __syncthreads();
           const int src = (grp + 1) % w;
 #pragma unroll
           for (int k = 0; k < JRPL; ++k) {
-            cb[k] = xbuf[(src * LPP + sub) * 2 * JRPL + k];
-            cvb[k] = xbuf[(src * LPP + sub) * 2 * JRPL + JRPL + k];
+            cb[k] = xb[(src * LPP + sub) * 2 * JRPL + k];
+            cvb[k] = xb[(src * LPP + sub) * 2 * JRPL + JRPL + k];
           }
-          nb = xnorm[src];
-          __syncthreads();
+          nb = xnorm[q & 1][src];
         }
       }
       store_col<LPP>(ca, a.A + (int64_t)ja * n, n, sub);

@@ -206,25 +206,57 @@ __device__ __forceinline__ void factor_panel(T* __restrict__ C, int ldc, T* __re
     }
     wave_lds_sync();
   }
-  // compact-WY T (lane j < 16 builds row j): T(c,c) = tau_c,
-  // T(j,c) = -tau_c sum_{l=j}^{c-1} T(j,l) G(l,c).  Gm holds G transposed
-  // (Gm[c][l] = G(l,c)) so that a column is one contiguous read.
-  if (g == 0) {
-    T trow[NB];
+  // compact-WY T by recursive doubling: with T = diag(tau) for blocks of
+  // size 1, each level joins adjacent diagonal blocks A, B of size bs,
+  //   T(A,B) = -T(A,A) G(A,B) T(B,B)      (G = V^T V, Gm holds G^T),
+  // which is T_new = M - M Gb M with M the current block-diagonal T and Gb
+  // the G entries of the (A,B) blocks: two 16x16 MFMA products per level.
+  {
+    typedef typename Mfma<T>::v4 v4;
+    const int i16 = lane & 15, g4 = lane >> 4;
+    T* Pb = Rd;  // the diagonal block is back in registers' callers: reuse as scratch
+    // Rd still holds the diagonal block of R; write it back first
+    if (!INTERNAL) {
 #pragma unroll
-    for (int l = 0; l < NB; ++l) trow[l] = T(0);
-#pragma unroll 1
-    for (int c = 0; c < kw; ++c) {
-      T acc = T(0);
-#pragma unroll
-      for (int l = 0; l < NB; ++l) acc += (l < c) ? trow[l] * Gm[c * NB + l] : T(0);
-      const T tc = taus[c];
-      const T val = (j < c) ? -tc * acc : ((j == c) ? tc : T(0));
-#pragma unroll
-      for (int l = 0; l < NB; ++l) trow[l] = (l == c) ? val : trow[l];
+      for (int u = 0; u < 4; ++u) {
+        const int kk = g * 4 + u;
+        if (kk <= j && j < kw) state[(int64_t)(k0 + kk) * n + k0 + j] = Rd[kk * TLD + j];
+      }
     }
+    wave_lds_sync();
 #pragma unroll
-    for (int c = 0; c < NB; ++c) Tm[j * NB + c] = trow[c];
+    for (int q = 0; q < 4; ++q) {
+      const int r = Mfma<T>::drow(g4, q);
+      Tm[r * NB + i16] = (r == i16 && r < kw) ? taus[r] : T(0);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int bs = 1; bs < NB; bs *= 2) {
+      // P = M Gb
+      v4 acc = vzero4<T>();
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        const int k = 4 * kb + g4;
+        const bool msk = (k / (2 * bs) == i16 / (2 * bs)) && (k % (2 * bs) < bs) &&
+                         (i16 % (2 * bs) >= bs);
+        const T gb = msk ? Gm[i16 * NB + k] : T(0);
+        acc = Mfma<T>::op(Tm[i16 * NB + k], gb, acc);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Pb[Mfma<T>::drow(g4, q) * TLD + i16] = acc[q];
+      wave_lds_sync();
+      // T -= P M
+      v4 acc2 = vzero4<T>();
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        const int k = 4 * kb + g4;
+        acc2 = Mfma<T>::op(Pb[i16 * TLD + k], Tm[k * NB + i16], acc2);
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Tm[Mfma<T>::drow(g4, q) * NB + i16] -= acc2[q];
+      wave_lds_sync();
+    }
   }
   // write back: C (tails and R rows), exact reflectors, state diagonal block
 #pragma unroll
@@ -241,13 +273,6 @@ __device__ __forceinline__ void factor_panel(T* __restrict__ C, int ldc, T* __re
       }
     }
     Vp[r * VPLD + j] = vx;
-  }
-  if (!INTERNAL) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int kk = g * 4 + u;
-      if (kk <= j && j < kw) state[(int64_t)(k0 + kk) * n + k0 + j] = Rd[kk * TLD + j];
-    }
   }
   wave_lds_sync();
 }
