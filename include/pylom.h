@@ -69,7 +69,7 @@ typedef enum {
 typedef enum {
   PYLOM_FP64 = 0,  /* every step in FP64 (FP32 inputs promoted on load)      */
   PYLOM_MIXED = 1  /* FP32 leaf QR, FP64 tree + small SVD, FP64 Rayleigh-Ritz
-                      refinement against the input (FP32 or C64 inputs only) */
+                      refinement against the input (R32 storage only) */
 } pylom_prec;
 
 typedef struct pylom_ctx_s* pylom_ctx;
@@ -120,7 +120,15 @@ const char* pylom_last_error(pylom_ctx ctx);
  *   n_r    one int64 in device memory: N_r.
  * Sign convention: each (u_i, v_i) is signed so that the largest-magnitude
  * entry of v_i (lowest index on ties) is positive.  Requires m >= n >= 1 and
- * n <= 1024 (FP64) / n <= 2048 (mixed).  In PYLOM_MIXED mode D must be R32.
+ * n <= 1024.
+ * PYLOM_MIXED (D must be R32): FP32 leaf QR without reflector storage, FP64
+ * tree and SVD of R, then a Rayleigh-Ritz refinement against D in FP64 on the
+ * k = min(n, N0 + max(8, N0/4)) leading right singular vectors V_k of that SVD
+ * (N0 = its truncation): Z = (D - mean 1^T) V_k, the Jacobi eigenpairs
+ * (lambda, w) of Z^T Z give S[i] = sqrt(lambda_i) (i < k; S[i] for i >= k is
+ * the unrefined value), v_i = V_k w_i, u_i = Z w_i / S[i]; N_r <= k.  The call
+ * synchronises the stream once, after the first SVD, to read N0.  Modes with
+ * S[i] = 0 get a zero U column.
  * Returns PYLOM_WNOCONV (>0, outputs written) if the Jacobi SVD did not
  * converge within max_sweeps -- this is only known after the stream is
  * synchronised, so the return value of an asynchronous call is 0 and the
@@ -171,7 +179,10 @@ int pylom_plan_query(pylom_ctx ctx, int64_t m, int64_t n, int64_t* leaves, int64
  * since the previous read (at most the last k, k = the "timing" option):
  * out[0] leaf QR (+ fused mean removal), out[1] tree combines, out[2] small
  * SVD + truncation, out[3] tree propagation, out[4] leaf apply
- * U = Q_1i W_i (+ mean output).  Host array of `cap` doubles; returns the
+ * U = Q_1i W_i (+ mean output).  For PYLOM_MIXED calls out[3] is the
+ * refinement (projection Z = (D - mean 1^T) V_k, Gram, its eigen-solve and
+ * the refined spectrum) and out[4] forms U = Z M; the host read-back of N0
+ * between out[2] and out[3] is in neither.  Host array of `cap` doubles; returns the
  * number of phases written (5) or a negative status.  Waits for the recorded
  * events, then starts a new averaging window. */
 int pylom_phase_times(pylom_ctx ctx, double* out, int cap);

@@ -27,8 +27,9 @@ struct pylom_ctx_s {
   int64_t block_rows = 0;
   int64_t max_sweeps = 40;
   int64_t ws_cap_mb = 0;
-  int* status_dev = nullptr;  // Jacobi status of the last SVD (2 ints)
+  int* status_dev = nullptr;  // Jacobi status pairs (sweeps, barrier timeout) of the last call
   int status_valid = 0;
+  int status_pairs = 1;        // 2 after a mixed-precision call (SVD of R + Gram eigen)
   int64_t timing = 0;         // number of per-call event slots (0 = off)
   std::vector<hipEvent_t> ev;  // timing x 6 events
   int64_t ev_calls = 0;        // timed calls since the last read
@@ -208,11 +209,18 @@ struct Plan {
   JacobiPlan jp;
   // workspace offsets (bytes)
   size_t oV, oTleaf, oR, oTtree, oW, oMean, oSig, oSvd, total;
+  // mixed precision only: FP32 leaf R, first SVD, refinement buffers
+  bool mixed;
+  size_t oR32, oS0, oVT0, oNr0, oZ, oG, oPart, oLam, oWT, oUR2, oNr2, oM, oSvd2;
+  size_t part_bytes;
 };
 
-static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p) {
+static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
+                     bool mixed = false) {
   if (n < 1 || m < n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
-  if (n > 1024) return fail(c, PYLOM_ENOTSUP, "n > 1024 is not supported on the FP64 path");
+  if (n > 1024) return fail(c, PYLOM_ENOTSUP, "n > 1024 is not supported");
+  p->mixed = mixed;
+  if (mixed) store_q = false;
   p->m = m;
   p->n = n;
   int64_t b = c->block_rows > 0 ? c->block_rows : 4096;
@@ -248,6 +256,46 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p) {
   off = align_up(off + sizeof(double) * (size_t)n);
   p->oSvd = off;
   off = align_up(off + jacobi_ws_bytes(p->jp, (int)c->max_sweeps));
+  if (mixed) {
+    // the refinement subspace k (<= n) is known only after the first SVD:
+    // size every k-dependent buffer for the largest k
+    size_t svd2 = 0, part = 0;
+    for (int64_t k = 1; k <= n; ++k) {
+      JacobiPlan jk;
+      if (!jacobi_plan((int)k, &jk)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
+      const size_t wb = jacobi_ws_bytes(jk, (int)c->max_sweeps);
+      if (wb > svd2) svd2 = wb;
+      const size_t pb = sizeof(double) * (size_t)matmul_tn_splits(m, k, k) * k * k;
+      if (pb > part) part = pb;
+    }
+    p->part_bytes = part;
+    p->oR32 = off;
+    off = align_up(off + sizeof(float) * (size_t)p->P * n * n);
+    p->oS0 = off;
+    off = align_up(off + sizeof(double) * (size_t)n);
+    p->oVT0 = off;
+    off = align_up(off + sizeof(double) * (size_t)n * n);
+    p->oNr0 = off;
+    off = align_up(off + sizeof(int64_t));
+    p->oZ = off;
+    off = align_up(off + sizeof(double) * (size_t)m * n);
+    p->oG = off;
+    off = align_up(off + sizeof(double) * (size_t)n * n);
+    p->oPart = off;
+    off = align_up(off + part);
+    p->oLam = off;
+    off = align_up(off + sizeof(double) * (size_t)n);
+    p->oWT = off;
+    off = align_up(off + sizeof(double) * (size_t)n * n);
+    p->oUR2 = off;
+    off = align_up(off + sizeof(double) * (size_t)n * n);
+    p->oNr2 = off;
+    off = align_up(off + sizeof(int64_t));
+    p->oM = off;
+    off = align_up(off + sizeof(double) * (size_t)n * n);
+    p->oSvd2 = off;
+    off = align_up(off + svd2);
+  }
   p->total = off;
   return PYLOM_OK;
 }
@@ -258,7 +306,7 @@ extern "C" int pylom_workspace_query(pylom_ctx c, pylom_dtype dtype, pylom_prec 
   if (dtype != PYLOM_R64 && dtype != PYLOM_R32) return fail(c, PYLOM_EDTYPE, "dtype");
   if (prec != PYLOM_FP64 && prec != PYLOM_MIXED) return fail(c, PYLOM_EDTYPE, "precision");
   Plan p;
-  int rc = make_plan(c, m, n, true, &p);
+  int rc = make_plan(c, m, n, true, &p, prec == PYLOM_MIXED);
   if (rc) return rc;
   *bytes = p.total;
   return PYLOM_OK;
@@ -303,6 +351,94 @@ static int check_common(pylom_ctx c, pylom_dtype dtype, pylom_prec prec) {
   return PYLOM_OK;
 }
 
+// Mixed precision (FP32 storage): FP32 leaf QR (R only), FP64 tree and SVD of
+// R, then the Rayleigh-Ritz refinement against the input on the k leading
+// right singular vectors, k = N_r0 + max(8, N_r0 / 4) (at most n).  The host
+// reads N_r0 once (one stream synchronisation) to size the refinement.
+static int run_mixed(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, const void* D,
+                     int64_t ldd, int remove_mean, double residual, void* mean, void* U,
+                     int64_t ldu, double* S, double* VT, int64_t ldvt, int64_t* n_r) {
+  if (dtype != PYLOM_R32) return fail(c, PYLOM_EDTYPE, "mixed precision needs R32 storage");
+  Plan p;
+  int rc = make_plan(c, m, n, false, &p, true);
+  if (rc) return rc;
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+  rc = ensure_ws(c, p.total);
+  if (rc) return rc;
+  char* ws = (char*)c->ws;
+  double* Rbuf = (double*)(ws + p.oR);
+  float* R32 = (float*)(ws + p.oR32);
+  double* meanws = (double*)(ws + p.oMean);
+  double* S0 = (double*)(ws + p.oS0);
+  double* VT0 = (double*)(ws + p.oVT0);
+  double* UR0 = (double*)(ws + p.oW);
+  int64_t* nr0 = (int64_t*)(ws + p.oNr0);
+  double* Z = (double*)(ws + p.oZ);
+  double* G = (double*)(ws + p.oG);
+  double* part = (double*)(ws + p.oPart);
+  double* lam = (double*)(ws + p.oLam);
+  double* WT = (double*)(ws + p.oWT);
+  double* UR2 = (double*)(ws + p.oUR2);
+  int64_t* nr2 = (int64_t*)(ws + p.oNr2);
+  double* M = (double*)(ws + p.oM);
+  hipStream_t st = c->stream;
+  const bool tm = c->timing > 0 && !c->ev.empty();
+  hipEvent_t* evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * 6] : nullptr;
+#define MARK(i) \
+  if (tm) HIPCHK(c, hipEventRecord(evs[i], st), "hipEventRecord")
+
+  MARK(0);
+  HIPCHK(c, launch_leaf_qr_f32(p.g, (const float*)D, ldd, m, p.b, p.P, remove_mean, meanws, R32,
+                               st), "leaf QR (FP32)");
+  HIPCHK(c, launch_cast_f32_f64(R32, Rbuf, p.P * n * n, st), "R to FP64");
+  MARK(1);
+  for (int64_t h = 1; h < p.P; h *= 2)
+    HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, Rbuf, nullptr, p.nch_tree, 0, st),
+           "tree combine");
+  MARK(2);
+  HIPCHK(c, launch_small_svd(p.jp, Rbuf, (int)c->max_sweeps, ws + p.oSvd, S0, VT0, n, UR0,
+                             residual, nr0, c->status_dev, st), "small SVD");
+  c->status_valid = 1;
+  c->status_pairs = 1;
+  int64_t nr_first = 0;
+  HIPCHK(c, hipMemcpyAsync(&nr_first, nr0, sizeof(int64_t), hipMemcpyDeviceToHost, st),
+         "N_r read-back");
+  HIPCHK(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+  MARK(3);
+  if (nr_first <= 0) {
+    // all-zero spectrum: nothing to refine, no mode is kept
+    HIPCHK(c, hipMemcpyAsync(S, S0, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st),
+           "S copy");
+    HIPCHK(c, launch_set_i64(n_r, 0, st), "N_r");
+  } else {
+    int64_t over = nr_first / 4;
+    if (over < 8) over = 8;
+    const int64_t k = (nr_first + over < n) ? nr_first + over : n;
+    JacobiPlan jk;
+    if (!jacobi_plan((int)k, &jk)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
+    const int64_t ns = matmul_tn_splits(m, k, k);
+    if (sizeof(double) * (size_t)ns * k * k > p.part_bytes)
+      return fail(c, PYLOM_ENOTSUP, "Gram partials exceed the planned workspace");
+    HIPCHK(c, launch_rr_project(0, m, (int)n, (int)k, D, ldd, remove_mean ? meanws : nullptr, VT0,
+                                Z, st), "Rayleigh-Ritz projection");
+    HIPCHK(c, launch_matmul_tn(1, m, k, k, Z, k, Z, k, G, k, part, ns, st), "Gram");
+    HIPCHK(c, launch_small_svd(jk, G, (int)c->max_sweeps, ws + p.oSvd2, lam, WT, k, UR2, 0.0, nr2,
+                               c->status_dev + 2, st), "Gram eigen-decomposition");
+    c->status_pairs = 2;
+    HIPCHK(c, launch_rr_finish((int)n, (int)k, S0, lam, residual, S, n_r, WT, VT0, VT, ldvt, M,
+                               st), "refined spectrum");
+    MARK(4);
+    HIPCHK(c, launch_rr_form_u(0, m, (int)k, Z, M, n_r, U, ldu, st), "form U");
+  }
+  if (!(nr_first > 0) && tm) HIPCHK(c, hipEventRecord(evs[4], st), "hipEventRecord");
+  if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, 0, m, st), "mean out");
+  MARK(5);
+#undef MARK
+  if (tm) ++c->ev_calls;
+  return PYLOM_OK;
+}
+
 static int run_tsvd(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
                     const void* D, int64_t ldd, int remove_mean, double residual, void* mean,
                     void* U, int64_t ldu, double* S, double* VT, int64_t ldvt, int64_t* n_r) {
@@ -312,7 +448,8 @@ static int run_tsvd(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, 
   if (!(residual >= 0.0 && residual < 1.0)) return fail(c, PYLOM_EINVAL, "residual must be in [0, 1)");
   if (n < 1 || m < n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
   if (ldd < n || ldu < n || ldvt < n) return fail(c, PYLOM_ESHAPE, "leading dimension < n");
-  if (prec == PYLOM_MIXED) return fail(c, PYLOM_ENOTSUP, "mixed precision: use pylom_pod_mixed path");
+  if (prec == PYLOM_MIXED)
+    return run_mixed(c, dtype, m, n, D, ldd, remove_mean, residual, mean, U, ldu, S, VT, ldvt, n_r);
   Plan p;
   rc = make_plan(c, m, n, true, &p);
   if (rc) return rc;
@@ -345,6 +482,7 @@ static int run_tsvd(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, 
   HIPCHK(c, launch_small_svd(p.jp, Rbuf, (int)c->max_sweeps, svdws, S, VT, ldvt, W, residual, n_r,
                              c->status_dev, st), "small SVD");
   c->status_valid = 1;
+  c->status_pairs = 1;
   MARK(3);
   int64_t top = 1;
   while (top * 2 < p.P) top *= 2;
@@ -477,10 +615,13 @@ extern "C" int pylom_check(pylom_ctx c, int64_t* sweeps) {
     if (sweeps) *sweeps = 0;
     return PYLOM_OK;
   }
-  int st[2] = {0, 0};
-  HIPCHK(c, hipMemcpy(st, c->status_dev, sizeof(st), hipMemcpyDeviceToHost), "status copy");
+  int st[4] = {0, 0, 0, 0};
+  HIPCHK(c, hipMemcpy(st, c->status_dev, sizeof(int) * 2 * c->status_pairs, hipMemcpyDeviceToHost),
+         "status copy");
   if (sweeps) *sweeps = st[0];
-  if (st[1]) return fail(c, PYLOM_EHIP, "Jacobi grid barrier timed out");
-  if (st[0] < 0) return fail(c, PYLOM_WNOCONV, "Jacobi SVD did not converge");
+  for (int k = 0; k < c->status_pairs; ++k) {
+    if (st[2 * k + 1]) return fail(c, PYLOM_EHIP, "Jacobi grid barrier timed out");
+    if (st[2 * k] < 0) return fail(c, PYLOM_WNOCONV, "Jacobi SVD did not converge");
+  }
   return PYLOM_OK;
 }

@@ -84,4 +84,17 @@ int64_t matmul_tn_splits(int64_t m, int64_t p, int64_t q);
 hipError_t launch_matmul_nn(int f64, int64_t m, int64_t p, int64_t q, const void* A, int64_t lda,
                             const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st);
 
+// ---- mixed precision: Rayleigh-Ritz refinement against the input ------------
+hipError_t launch_cast_f32_f64(const float* src, double* dst, int64_t count, hipStream_t st);
+// Z (m x k, ld k) = (A - mu 1^T) V_k with V_k[t][j] = VT0[j * n + t].
+hipError_t launch_rr_project(int in_f64, int64_t m, int n, int k, const void* A, int64_t lda,
+                             const double* mu, const double* VT0, double* Z, hipStream_t st);
+// S, N_r (capped at k), VT rows c < N_r and M (k x k) from the Gram eigenpairs.
+hipError_t launch_rr_finish(int n, int k, const double* S0, const double* lam, double residual,
+                            double* S, int64_t* nr, const double* WT, const double* VT0,
+                            double* VT, int64_t ldvt, double* M, hipStream_t st);
+// U[:, c] = Z M[:, c] for c < N_r.
+hipError_t launch_rr_form_u(int out_f64, int64_t m, int k, const double* Z, const double* M,
+                            const int64_t* nr, void* U, int64_t ldu, hipStream_t st);
+
 }  // namespace pylom

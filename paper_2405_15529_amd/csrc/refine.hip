@@ -1,0 +1,257 @@
+// Mixed-precision POD: refinement of the FP32-QR spectrum against the input.
+//
+// The leaf QR of the mixed path runs in FP32, so R (and the SVD of R) carries
+// errors of order u32 * sigma_1.  The spectrum is won back by a Rayleigh-Ritz
+// step on the leading right singular vectors V_k of that SVD, computed against
+// the input itself in FP64:
+//
+//   Z  = (A - mu 1^T) V_k          (m x k, FP64 accumulation, A read once)
+//   G  = Z^T Z = W diag(lambda) W^T (k x k Gram, its Jacobi eigen-decomposition)
+//   sigma_c = sqrt(lambda_c),  v_c = V_k w_c,  u_c = Z w_c / sigma_c.
+//
+// Because the u_c are formed from A V_k, their orthogonality and the Ritz
+// values carry FP64 rounding of the Gram (relative error about
+// u64 (sigma_1 / sigma_c)^2) plus the quadratic Ritz error in the angle
+// between span(V_k) and the exact singular subspace; neither depends on the
+// FP32 backward error except through that angle.  This replaces the
+// reflector apply of Eq. svdqr3 in the mixed path (the Q of the FP32 QR is
+// never formed).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pylom {
+
+namespace {
+constexpr int GR = 64;   // rows per workgroup
+constexpr int GC = 64;   // columns per workgroup
+constexpr int GK = 32;   // K slab staged in LDS
+constexpr int ALD = GK + 1;
+constexpr int BLD = GC + 1;
+}  // namespace
+
+__global__ void k_cast_f32_f64(const float* __restrict__ src, double* __restrict__ dst,
+                               int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (double)src[i];
+}
+
+// C (m x nc) = (A - mu 1^T) (m x K) * B (K x nc), FP64 MFMA on promoted tiles.
+// B(t, j) = Bs[j * ldb + t] when BT (B given by rows of its transpose), else
+// Bs[t * ldb + j].  nc = min(nc_host, *nc_dev) when nc_dev is given.
+// Grid: (ceil(m / 64), ceil(nc_host / 64)); 256 threads, wave w owns rows
+// 16w..16w+15 of the tile and all four 16-column MFMA tiles.
+template <typename TI, typename TO, bool BT>
+__global__ __launch_bounds__(256) void k_tall_gemm(int64_t m, int K, int nc_host,
+                                                   const int64_t* __restrict__ nc_dev,
+                                                   const TI* __restrict__ A, int64_t lda,
+                                                   const double* __restrict__ mu,
+                                                   const double* __restrict__ Bs, int64_t ldb,
+                                                   TO* __restrict__ C, int64_t ldc) {
+  __shared__ double As[GR * ALD];
+  __shared__ double Bsh[GK * BLD];
+  int nc = nc_host;
+  if (nc_dev) {
+    const int64_t d = *nc_dev;
+    nc = (int)(d < nc ? d : nc);
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * GR;
+  const int j0 = blockIdx.y * GC;
+  if (j0 >= nc) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  typedef Mfma<double>::v4 v4;
+  v4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = vzero4<double>();
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    // stage A slab (64 x 32): consecutive threads walk a row
+#pragma unroll
+    for (int e = 0; e < (GR * GK) / 256; ++e) {
+      const int idx = tid + 256 * e;
+      const int r = idx / GK, c = idx % GK;
+      const int64_t gr = r0 + r;
+      const int gc = k0 + c;
+      double v = 0.0;
+      if (gr < m && gc < K) {
+        v = (double)A[gr * lda + gc];
+        if (mu) v -= mu[gr];
+      }
+      As[r * ALD + c] = v;
+    }
+    // stage B slab (32 x 64)
+#pragma unroll
+    for (int e = 0; e < (GK * GC) / 256; ++e) {
+      const int idx = tid + 256 * e;
+      int t, j;
+      if (BT) {
+        j = idx / GK;
+        t = idx % GK;
+      } else {
+        t = idx / GC;
+        j = idx % GC;
+      }
+      const int gt = k0 + t, gj = j0 + j;
+      double v = 0.0;
+      if (gt < K && gj < nc) v = BT ? Bs[(int64_t)gj * ldb + gt] : Bs[(int64_t)gt * ldb + gj];
+      Bsh[t * BLD + j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kb = 0; kb < GK; kb += 4) {
+      const double av = As[(wave * 16 + i16) * ALD + kb + g4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double bv = Bsh[(kb + g4) * BLD + c * 16 + i16];
+        acc[c] = Mfma<double>::op(av, bv, acc[c]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int col = j0 + c * 16 + i16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = r0 + wave * 16 + Mfma<double>::drow(g4, q);
+      if (row < m && col < nc) C[row * ldc + col] = (TO)acc[c][q];
+    }
+  }
+}
+
+// Refined spectrum: S[c] = sqrt(lambda_c) for c < k, the unrefined S0[c] for
+// c >= k; N_r from the residual-energy rule on S (tail sums from the smallest
+// value upward), capped at k.  One workgroup.
+__global__ __launch_bounds__(256) void k_rr_spectrum(int n, int k, const double* __restrict__ S0,
+                                                     const double* __restrict__ lam,
+                                                     double residual, double* __restrict__ S,
+                                                     int64_t* __restrict__ nr) {
+  __shared__ double tail[1025];
+  const int tid = threadIdx.x;
+  for (int c = tid; c < n; c += 256) {
+    double s = S0[c];
+    if (c < k) {
+      const double l = lam[c];
+      s = l > 0.0 ? sqrt(l) : 0.0;
+    }
+    S[c] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    tail[n] = 0.0;
+    for (int c = n - 1; c >= 0; --c) tail[c] = tail[c + 1] + S[c] * S[c];
+    const double total = tail[0];
+    int64_t keep = n;
+    if (!(residual > 0.0)) {
+      keep = n;
+    } else if (total == 0.0) {
+      keep = 0;
+    } else {
+      for (int c = 1; c <= n; ++c)
+        if (tail[c] <= residual * total) {
+          keep = c;
+          break;
+        }
+    }
+    if (keep > k) keep = k;
+    *nr = keep;
+  }
+}
+
+// Refined right vectors and the mode-forming matrix, one workgroup per mode c
+// (c < N_r): v = V_k w_c (VT row c), signed so that its largest-|.| entry
+// (lowest index on ties) is positive; M[:, c] = sign * w_c / sigma_c.
+// WT holds w_c as row c (k x k, ld k); VT0 holds V^T of the first SVD (ld n).
+__global__ __launch_bounds__(256) void k_rr_vectors(int n, int k, const double* __restrict__ WT,
+                                                    const double* __restrict__ VT0,
+                                                    const double* __restrict__ S,
+                                                    const int64_t* __restrict__ nr,
+                                                    double* __restrict__ VT, int64_t ldvt,
+                                                    double* __restrict__ M) {
+  __shared__ double v[1024];
+  __shared__ double best_v[256];
+  __shared__ int best_i[256];
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (c >= *nr) return;
+  const double* w = WT + (int64_t)c * k;
+  double bv = -1.0;
+  int bi = n;
+  for (int t = tid; t < n; t += 256) {
+    double x = 0.0;
+    for (int j = 0; j < k; ++j) x += w[j] * VT0[(int64_t)j * n + t];
+    v[t] = x;
+    const double ax = fabs(x);
+    if (ax > bv) {  // t increases along this thread's walk: first max kept
+      bv = ax;
+      bi = t;
+    }
+  }
+  best_v[tid] = bv;
+  best_i[tid] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double ov = best_v[tid + s];
+      const int oi = best_i[tid + s];
+      if (ov > best_v[tid] || (ov == best_v[tid] && oi < best_i[tid])) {
+        best_v[tid] = ov;
+        best_i[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const double sgn = (v[best_i[0]] < 0.0) ? -1.0 : 1.0;
+  for (int t = tid; t < n; t += 256) VT[(int64_t)c * ldvt + t] = sgn * v[t];
+  const double sc = S[c];
+  for (int j = tid; j < k; j += 256) M[(int64_t)j * k + c] = (sc > 0.0) ? sgn * w[j] / sc : 0.0;
+}
+
+hipError_t launch_cast_f32_f64(const float* src, double* dst, int64_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  int64_t g = (count + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_cast_f32_f64, dim3((unsigned)g), dim3(256), 0, st, src, dst, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_rr_project(int in_f64, int64_t m, int n, int k, const void* A, int64_t lda,
+                             const double* mu, const double* VT0, double* Z, hipStream_t st) {
+  if (m <= 0 || k <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((m + GR - 1) / GR), (unsigned)((k + GC - 1) / GC));
+  if (in_f64)
+    hipLaunchKernelGGL((k_tall_gemm<double, double, true>), grid, dim3(256), 0, st, m, n, k,
+                       (const int64_t*)nullptr, (const double*)A, lda, mu, VT0, (int64_t)n, Z,
+                       (int64_t)k);
+  else
+    hipLaunchKernelGGL((k_tall_gemm<float, double, true>), grid, dim3(256), 0, st, m, n, k,
+                       (const int64_t*)nullptr, (const float*)A, lda, mu, VT0, (int64_t)n, Z,
+                       (int64_t)k);
+  return hipGetLastError();
+}
+
+hipError_t launch_rr_finish(int n, int k, const double* S0, const double* lam, double residual,
+                            double* S, int64_t* nr, const double* WT, const double* VT0,
+                            double* VT, int64_t ldvt, double* M, hipStream_t st) {
+  hipLaunchKernelGGL(k_rr_spectrum, dim3(1), dim3(256), 0, st, n, k, S0, lam, residual, S, nr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rr_vectors, dim3((unsigned)k), dim3(256), 0, st, n, k, WT, VT0, S,
+                     (const int64_t*)nr, VT, ldvt, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_rr_form_u(int out_f64, int64_t m, int k, const double* Z, const double* M,
+                            const int64_t* nr, void* U, int64_t ldu, hipStream_t st) {
+  if (m <= 0 || k <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((m + GR - 1) / GR), (unsigned)((k + GC - 1) / GC));
+  if (out_f64)
+    hipLaunchKernelGGL((k_tall_gemm<double, double, false>), grid, dim3(256), 0, st, m, k, k, nr,
+                       Z, (int64_t)k, (const double*)nullptr, M, (int64_t)k, (double*)U, ldu);
+  else
+    hipLaunchKernelGGL((k_tall_gemm<double, float, false>), grid, dim3(256), 0, st, m, k, k, nr, Z,
+                       (int64_t)k, (const double*)nullptr, M, (int64_t)k, (float*)U, ldu);
+  return hipGetLastError();
+}
+
+}  // namespace pylom

@@ -271,18 +271,19 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
           // pass my b column to group grp-1, take the one of group grp+1; the
           // two buffers alternate, so one barrier per round suffices
           double* xb = xbuf[q & 1];
+          // k-major slots: consecutive lanes touch consecutive doubles
 #pragma unroll
           for (int k = 0; k < JRPL; ++k) {
-            xb[(grp * LPP + sub) * 2 * JRPL + k] = cb[k];
-            xb[(grp * LPP + sub) * 2 * JRPL + JRPL + k] = cvb[k];
+            xb[k * JT + tid] = cb[k];
+            xb[(JRPL + k) * JT + tid] = cvb[k];
           }
           if (sub == 0) xnorm[q & 1][grp] = nb;
           __syncthreads();
           const int src = (grp + 1) % w;
 #pragma unroll
           for (int k = 0; k < JRPL; ++k) {
-            cb[k] = xb[(src * LPP + sub) * 2 * JRPL + k];
-            cvb[k] = xb[(src * LPP + sub) * 2 * JRPL + JRPL + k];
+            cb[k] = xb[k * JT + src * LPP + sub];
+            cvb[k] = xb[(JRPL + k) * JT + src * LPP + sub];
           }
           nb = xnorm[q & 1][src];
         }

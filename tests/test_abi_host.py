@@ -66,7 +66,10 @@ def test_argument_validation_before_device(hctx):
     assert _pod(hctx, r=-0.5) == -1
     assert _pod(hctx, dtype=99) == -3
     assert _pod(hctx, prec=7) == -3
-    assert _pod(hctx, m=5000, n=2000) == -6        # wider than the FP64 kernels
+    assert _pod(hctx, m=5000, n=2000) == -6        # wider than the kernels
+    assert _pod(hctx, prec=api.MIXED) == -3        # mixed precision needs FP32 storage
+    assert _pod(hctx, dtype=api.R32, prec=api.MIXED) == -7
+    assert _pod(hctx, dtype=api.R32, prec=api.MIXED, m=5000, n=2000) == -6
     assert hctx.lib.pylom_pod(None, 2, 0, 10, 2, None, 2, 0, 0.0, None, None, 2, None, None, 2,
                               None) == -1
 

@@ -1,0 +1,163 @@
+"""GPU parity of the mixed-precision POD path (FP32 leaf QR, FP64 tree + SVD,
+FP64 Rayleigh-Ritz refinement against the input) against the FP64 oracle run
+on the same FP32 buffer promoted exactly to FP64.
+
+Bars: retained sigma relative error <= 1e-6 and |U^T U - I|_F <= 1e-6 over
+the retained modes.  For the vectors (no stated bar) the tests use 1e-5 on
+well-separated modes and on the projector distance of the retained span:
+the refinement error of mode i is about
+u32 * sigma_1 * kappa / gap_i squared (Ritz error in the subspace angle) plus
+FP64 rounding, and the FP32 rounding of U on output adds u32 per entry.
+N_r may differ by one where the tail energy sits within 1e-5 of r.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_15529_amd import synth
+from tests import checks
+
+pytestmark = pytest.mark.gpu
+
+SREL = 1e-6
+ORTH = 1e-6
+VEC = 1e-5
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_mixed(D32, remove_mean, r, block_rows):
+    import torch
+    from paper_2405_15529_amd import api
+    ctx = api.Context(0)
+    ctx.set_option("block_rows", block_rows)
+    Dg = torch.from_numpy(np.ascontiguousarray(D32)).cuda()
+    out = api.pod(Dg, remove_mean=remove_mean, r=r, precision="mixed", ctx=ctx)
+    rc, sweeps = ctx.status()
+    res = dict(U=out.U_full.cpu().numpy().astype(np.float64), S=out.S.cpu().numpy(),
+               VT=out.VT_full.cpu().numpy(), nr=out.nr, rc=rc, sweeps=sweeps,
+               mean=None if out.mean is None else out.mean.cpu().numpy().astype(np.float64))
+    ctx.close()
+    return res
+
+
+def assert_mixed_parity(g, ref, r):
+    assert g["rc"] == 0
+    nr = g["nr"]
+    assert checks.nr_agrees(nr, ref["nr"], ref["S"], r, tie=1e-5), (nr, ref["nr"])
+    k = min(nr, ref["nr"])
+    if k == 0:
+        return
+    rel, _ = checks.sigma_errors(g["S"], ref["S"], k)
+    say(f"    sigma rel err (retained) {rel:.3e}")
+    assert rel <= SREL, rel
+    live = [i for i in range(k) if ref["S"][i] > 1e3 * len(ref["S"]) * checks.EPS64 * ref["S"][0]]
+    if live:
+        oe = checks.orth_error(g["U"][:, live])
+        say(f"    |U^T U - I|_F {oe:.3e}")
+        assert oe <= ORTH, oe
+    eu, ev, proj = checks.mode_errors(g["U"], ref["U"], g["VT"], ref["VT"], ref["S"], len(live),
+                                      gap=1e-2)
+    say(f"    mode errors u {eu:.3e} v {ev:.3e} span {proj:.3e}")
+    assert eu <= VEC and ev <= VEC and proj <= VEC, (eu, ev, proj)
+    assert checks.sign_convention_holds(g["VT"], nr)
+
+
+SHAPES = [
+    # (m, n, block_rows, remove_mean): several chunks and panels, ragged
+    # tails, non-power-of-two leaf counts, single leaf, square, one column
+    (1000, 37, 200, True),
+    (4099, 48, 512, False),
+    (6000, 130, 600, True),
+    (200, 200, 200, False),
+    (300, 1, 64, False),
+    (2500, 5, 100, True),
+]
+
+
+@pytest.mark.parametrize("m,n,b,rm", SHAPES)
+def test_mixed_small_shapes(m, n, b, rm):
+    say(f"[gpu] mixed small m={m} n={n} b={b} rm={rm}")
+    rng = np.random.default_rng(m * 11 + n)
+    D = (rng.standard_normal((m, n)) * np.exp(-np.arange(n) / 7.0)[None, :] + 0.3)
+    D32 = D.astype(np.float32)
+    r = 0.05
+    ref = oracle.pod(D32.astype(np.float64), remove_mean=rm, r=r)
+    g = run_mixed(D32, rm, r, b)
+    assert_mixed_parity(g, ref, r)
+    if rm:
+        # the mean is accumulated in FP64 and returned in the storage type
+        # (rounded once: within one FP32 ulp of the FP64 mean)
+        np.testing.assert_allclose(g["mean"], ref["mean"], rtol=2.0 ** -23, atol=0)
+
+
+def test_mixed_plain_small_case():
+    say("[gpu] mixed plain 20000x100 b=2500")
+    D32 = synth.plain_pod_fp64(m=20_000, n=100, seed=0).astype(np.float32)
+    ref = oracle.pod(D32.astype(np.float64), remove_mean=True, r=0.01)
+    g = run_mixed(D32, True, 0.01, 2500)
+    assert_mixed_parity(g, ref, 0.01)
+
+
+def test_mixed_known_spectrum_vs_oracle():
+    say("[gpu] mixed known spectrum 32768x128 b=4096")
+    A, s = synth.graded_fp64(m=32768, n=128, seed=6)
+    A32 = A.astype(np.float32)
+    ref = oracle.pod(A32.astype(np.float64), remove_mean=False, r=0.01)
+    g = run_mixed(A32, False, 0.01, 4096)
+    assert_mixed_parity(g, ref, 0.01)
+
+
+def test_mixed_keep_all_modes():
+    # r = 0 keeps every mode: the refinement subspace is the whole space
+    say("[gpu] mixed r=0 4000x64")
+    s = 2.0 ** (-np.arange(64) / 8.0)
+    A, _, _ = synth.known_spectrum(4000, 64, s, seed=21)
+    A32 = A.astype(np.float32)
+    ref = oracle.pod(A32.astype(np.float64), remove_mean=False, r=0.0)
+    g = run_mixed(A32, False, 0.0, 1000)
+    assert g["nr"] == 64
+    assert_mixed_parity(g, ref, 0.0)
+
+
+def test_mixed_constant_field_keeps_nothing():
+    say("[gpu] mixed constant field")
+    D32 = np.full((3000, 20), 0.625, dtype=np.float32)
+    g = run_mixed(D32, True, 0.01, 500)
+    assert g["rc"] == 0
+    assert g["nr"] == 0
+    assert np.all(g["S"] == 0.0)
+    assert np.all(g["mean"] == 0.625)
+
+
+def test_mixed_matches_fp64_gpu_at_scale():
+    # larger shape, against the exact spectrum and the FP64 GPU path
+    import torch
+    from paper_2405_15529_amd import api
+    say("[gpu] mixed vs FP64 262144x256 b=4096")
+    m, n = 262144, 256
+    A, s = synth.graded_fp64_device(m=m, n=n, seed=7)
+    ctx = api.Context(0)
+    ctx.set_option("block_rows", 4096)
+    A32 = A.float().contiguous()
+    g32 = api.pod(A32, remove_mean=False, r=0.01, precision="mixed", ctx=ctx)
+    rc32, _ = ctx.status()
+    g64 = api.pod(A32.double().contiguous(), remove_mean=False, r=0.01, ctx=ctx)
+    rc64, _ = ctx.status()
+    assert rc32 == 0 and rc64 == 0
+    S32, S64 = g32.S.cpu().numpy(), g64.S.cpu().numpy()
+    k = min(g32.nr, g64.nr)
+    assert abs(g32.nr - g64.nr) <= 1 and g64.nr in (32, 33)
+    rel = np.max(np.abs(S32[:k] - S64[:k]) / S64[:k])
+    say(f"    sigma rel err vs FP64 GPU {rel:.3e}; vs exact {np.max(np.abs(S32[:k] - s[:k]) / s[:k]):.3e}")
+    assert rel <= SREL
+    U = g32.U.double()
+    oe = torch.linalg.norm(U.T @ U - torch.eye(U.shape[1], dtype=torch.float64, device=U.device)).item()
+    say(f"    |U^T U - I|_F {oe:.3e}")
+    assert oe <= ORTH
+    ctx.close()
