@@ -6,9 +6,11 @@ Default workload: the known-spectrum FP64 POD, A = Q1 diag(s) Q2^T,
 m = 1,048,576, n = 256, s_i = 10^(-i/32), row blocks of 4,096 (256 leaves,
 8 tree levels), 99 % energy truncation.
 
-Prints one JSON line.  value = algorithmic TFLOP/s of the whole step,
-F = 2 m n^2 + 2 m n N_r (TSQR leaf term + U = Q U_R); the roofline object
-rates the dominant kernel (the leaf QR, 2 m n^2 flops per launch) against the
+Prints one JSON line.  value = algorithmic TFLOP/s of the whole FP64 step,
+F = 2 m n^2 + 2 m n N_r (TSQR leaf term + U = Q U_R); "mixed" times the
+mixed-precision path on the FP32 copy of the same matrix with the same F
+(speed-up and sigma error against the FP64 run); the roofline object rates
+the dominant kernel (the FP64 leaf QR, 2 m n^2 flops per launch) against the
 FP64 MFMA peak; cpu_baseline times the CPU oracle on a bounded row sample of
 the same workload.
 """
@@ -59,11 +61,60 @@ def cpu_baseline(n: int, rows: int, r: float):
                 seconds=dt)
 
 
+def timed_pod(api, ctx, A, m, n, r, precision, steps, warmup):
+    """Run pylom_pod `warmup` + `steps` times on the resident A; returns the
+    mean ms per call (HIP events on the library stream), phase means and the
+    outputs of the last call."""
+    import ctypes
+    import torch
+
+    dev = A.device
+    lib = ctx.lib
+    prec = api.FP64 if precision == "fp64" else api.MIXED
+    dt = api.R64 if A.dtype == torch.float64 else api.R32
+    ctx.check(lib.pylom_reserve(ctx.h, ctx.workspace_bytes(m, n, dt, precision)))
+    U = torch.empty((m, n), dtype=A.dtype, device=dev)
+    S = torch.empty(n, dtype=torch.float64, device=dev)
+    VT = torch.empty((n, n), dtype=torch.float64, device=dev)
+    nr_d = torch.empty(1, dtype=torch.int64, device=dev)
+    vp = ctypes.c_void_p
+
+    def step():
+        rc = lib.pylom_pod(ctx.h, dt, prec, m, n, vp(A.data_ptr()), n, 0, r, vp(0),
+                           vp(U.data_ptr()), n, vp(S.data_ptr()), vp(VT.data_ptr()), n,
+                           vp(nr_d.data_ptr()))
+        if rc != 0:
+            raise RuntimeError(lib.pylom_last_error(ctx.h).decode())
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.status()
+    if warmup:
+        ctx.phase_times()  # drop warm-up samples
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for _ in range(steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1) / steps
+    phases = ctx.phase_times()
+    rc, sweeps = ctx.status()
+    return dict(ms=ms, wall=wall, phases=phases, rc=rc, sweeps=sweeps, U=U, S=S, VT=VT,
+                nr=int(nr_d.item()))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    import numpy as np
     import torch
     from paper_2405_15529_amd import api, synth
 
@@ -74,56 +125,56 @@ def main():
     ctx.set_option("block_rows", args.block_rows)
     ctx.set_option("timing", max(1, args.steps))
     ctx.bind_stream()
-    lib = ctx.lib
-    ws = ctx.workspace_bytes(m, n)
-    ctx.check(lib.pylom_reserve(ctx.h, ws))
-    U = torch.empty((m, n), dtype=torch.float64, device=dev)
-    S = torch.empty(n, dtype=torch.float64, device=dev)
-    VT = torch.empty((n, n), dtype=torch.float64, device=dev)
-    nr_d = torch.empty(1, dtype=torch.int64, device=dev)
-    import ctypes
-    vp = ctypes.c_void_p
 
-    def step():
-        rc = lib.pylom_pod(ctx.h, api.R64, api.FP64, m, n, vp(A.data_ptr()), n, 0, r, vp(0),
-                           vp(U.data_ptr()), n, vp(S.data_ptr()), vp(VT.data_ptr()), n,
-                           vp(nr_d.data_ptr()))
-        if rc != 0:
-            raise RuntimeError(lib.pylom_last_error(ctx.h).decode())
+    def orth_err(U, k):
+        Ur = U[:, :k].double()
+        return float(torch.linalg.norm(Ur.T @ Ur - torch.eye(k, dtype=torch.float64,
+                                                               device=dev)).item())
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    rc, sweeps = ctx.status()
-    ctx.phase_times() if args.warmup else None  # drop warm-up samples
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    t0.record()
-    for _ in range(args.steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = t0.elapsed_time(t1) / args.steps
-    phases = ctx.phase_times()
-    rc, sweeps = ctx.status()
-    nr = int(nr_d.item())
-    # accuracy against the known spectrum (retained modes: relative; all: normwise)
-    S_h = S.cpu().numpy()
-    import numpy as np
+    # FP64 path on the FP64 matrix (the named workload)
+    f = timed_pod(api, ctx, A, m, n, r, "fp64", args.steps, args.warmup)
+    nr = f["nr"]
+    S_h = f["S"].cpu().numpy()
     sig_rel = float(np.max(np.abs(S_h[:nr] - s[:nr]) / s[:nr])) if nr else 0.0
     sig_norm = float(np.max(np.abs(S_h - s)) / s[0])
-    Ur = U[:, :nr]
-    orth = float(torch.linalg.norm(Ur.T @ Ur - torch.eye(nr, dtype=torch.float64, device=dev)).item())
+    orth = orth_err(f["U"], nr)
+    del f["U"]
 
     flops = 2.0 * m * n * n + 2.0 * m * n * nr
-    bytes_ = 2.0 * 8 * m * n + 8.0 * m * nr
+    bytes64 = 2.0 * 8 * m * n + 8.0 * m * nr
+    ms = f["ms"]
     tflops = flops / (ms * 1e-3) / 1e12
-    gbps = bytes_ / (ms * 1e-3) / 1e9
-    leaf_ms = phases["leaf_qr"]
+    gbps = bytes64 / (ms * 1e-3) / 1e9
+    leaf_ms = f["phases"]["leaf_qr"]
     leaf_tflops = 2.0 * m * n * n / (leaf_ms * 1e-3) / 1e12
+
+    # mixed path on the FP32 copy of the same matrix
+    A32 = A.float().contiguous()
+    del A
+    x = timed_pod(api, ctx, A32, m, n, r, "mixed", args.steps, args.warmup)
+    nrx = x["nr"]
+    Sx = x["S"].cpu().numpy()
+    kx = min(nrx, nr)
+    mixed = {
+        "precision": "mixed (FP32 leaf QR, FP64 tree + SVD, FP64 Rayleigh-Ritz refinement)",
+        "storage": "f32",
+        "ms_per_step": round(x["ms"], 4),
+        "tflops": round(flops / (x["ms"] * 1e-3) / 1e12, 4),
+        "gbps": round((2.0 * 4 * m * n + 4.0 * m * nrx) / (x["ms"] * 1e-3) / 1e9, 2),
+        "speedup_vs_fp64": round(ms / x["ms"], 3),
+        "n_r": nrx,
+        "sigma_rel_err_vs_fp64_run": float(np.max(np.abs(Sx[:kx] - S_h[:kx]) / S_h[:kx])) if kx else 0.0,
+        "sigma_rel_err_vs_exact": float(np.max(np.abs(Sx[:kx] - s[:kx]) / s[:kx])) if kx else 0.0,
+        "orth_err_U": orth_err(x["U"], nrx),
+        "jacobi_sweeps_first": x["sweeps"],
+        "phase_ms": {"leaf_qr_fp32": round(x["phases"]["leaf_qr"], 4),
+                     "tree_combine": round(x["phases"]["tree_combine"], 4),
+                     "small_svd": round(x["phases"]["small_svd"], 4),
+                     "refine_project_gram_eig": round(x["phases"]["tree_propagate"], 4),
+                     "form_u": round(x["phases"]["leaf_apply"], 4)},
+    }
+    del x["U"]
+
     out = {
         "metric": "POD TSQR-SVD GB/s & TFLOP/s: mixed-precision vs FP64 at sigma rel err <=1e-6",
         "value": round(tflops, 4),
@@ -145,13 +196,14 @@ def main():
         "sigma_rel_err_retained": sig_rel,
         "sigma_err_normwise": sig_norm,
         "orth_err_U": orth,
-        "jacobi_sweeps": sweeps,
-        "phase_ms": {k: round(v, 4) for k, v in phases.items()},
-        "roofline": {"bound": "mfma", "kernel": "k_stacked_qr (leaf QR)",
+        "jacobi_sweeps": f["sweeps"],
+        "phase_ms": {k: round(v, 4) for k, v in f["phases"].items()},
+        "mixed": mixed,
+        "roofline": {"bound": "mfma", "kernel": "k_stacked_qr (leaf QR, FP64)",
                      "achieved": round(leaf_tflops, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(leaf_tflops / FP64_PEAK_TFLOPS, 4),
                      "traffic": None},
-        "wall_s": round(wall, 3),
+        "wall_s": round(f["wall"] + x["wall"], 3),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_rows, r)
