@@ -162,6 +162,41 @@ int pylom_matmul(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int trans_a,
                  int64_t p, int64_t q, const void* A, int64_t lda, const void* B, int64_t ldb,
                  void* C, int64_t ldc);
 
+/* SPOD (Alg. 6; Sec. 2.3, Eq. csdimp with the SVD of the spectral matrix).
+ *
+ *   D       m x nt FP32 snapshots (rows = points, ldd >= nt), device.
+ *   spectra PYLOM_C64: FFT and spectral storage in FP32, modes complex64;
+ *           PYLOM_C128: FFT and storage in FP64, modes complex128.
+ *   prec    PYLOM_FP64 (the TSQR-SVD of every frequency runs in FP64).
+ *   npwin   block length, a power of two in [4, 4096]; nolap overlap
+ *           (0 <= nolap < npwin); nBlks = (nt - nolap) / (npwin - nolap),
+ *           1 <= nBlks <= 16; block b starts at sample b (npwin - nolap).
+ *   window  0 = Hann, 1 = Hamming (the paper's), both
+ *           a0 - a1 cos(2 pi j / (npwin - 1)), j = 0..npwin-1.
+ *   remove_mean  subtract each point's temporal mean over all nt samples.
+ * Per point and block: q_f = c_f DFT_f(w x) / sum(w) / sqrt(nBlks) for
+ * f = 0..npwin/2 (nfreq values), DFT_f(x) = sum_j x_j exp(-2 pi i j f/npwin),
+ * c_f = 2 for 0 < f < npwin/2 and 1 otherwise.  For every frequency the thin
+ * SVD Q_f = U_f S_f V_f^H of the m x nBlks matrix (all nBlks modes kept) is
+ * computed by the TSQR-SVD of its real 2m x 2nBlks realification, all
+ * frequencies in one batch.
+ * Outputs (device): modes  nfreq x m x nBlks complex (interleaved re, im),
+ *           modes[f][p][c] = U_f[p][c], each mode's phase fixed so that the
+ *           largest-|.| entry of v_c (lowest index on ties) is real > 0;
+ *         L      nfreq x nBlks doubles, L[f][c] = S_f[c]^2, descending in c;
+ *         freqs  nfreq doubles f / (dt npwin), or NULL;
+ *         order  nfreq int64, the frequencies sorted by L[f][0] descending
+ *                (ties by ascending f), or NULL.
+ * The Jacobi status is reported by pylom_check (largest sweep count). */
+int pylom_spod(pylom_ctx ctx, pylom_dtype spectra, pylom_prec prec, int64_t m, int64_t nt,
+               const float* D, int64_t ldd, double dt, int64_t npwin, int64_t nolap, int window,
+               int remove_mean, void* modes, double* L, double* freqs, int64_t* order);
+
+/* Number of Welch blocks and frequencies, and the workspace bytes, of a
+ * pylom_spod call of this shape (host only). */
+int pylom_spod_query(pylom_ctx ctx, pylom_dtype spectra, int64_t m, int64_t nt, int64_t npwin,
+                     int64_t nolap, int64_t* nblocks, int64_t* nfreq, size_t* bytes);
+
 /* Host-side copy of the in-device binary reduction tree of Alg. 1 for P
  * leaves: writes up to `cap` triples (level, receiver, sender) in execution
  * order into `out` (host memory, 3*cap int64) and returns the number of
@@ -175,16 +210,22 @@ int64_t pylom_tree_plan(int64_t P, int64_t* out, int64_t cap);
 int pylom_plan_query(pylom_ctx ctx, int64_t m, int64_t n, int64_t* leaves, int64_t* block_rows,
                      int64_t* chunk_rows, int64_t* levels);
 
-/* Mean phase durations (milliseconds) over the timed pod/tsvd calls made
- * since the previous read (at most the last k, k = the "timing" option):
- * out[0] leaf QR (+ fused mean removal), out[1] tree combines, out[2] small
- * SVD + truncation, out[3] tree propagation, out[4] leaf apply
- * U = Q_1i W_i (+ mean output).  For PYLOM_MIXED calls out[3] is the
- * refinement (projection Z = (D - mean 1^T) V_k, Gram, its eigen-solve and
- * the refined spectrum) and out[4] forms U = Z M; the host read-back of N0
- * between out[2] and out[3] is in neither.  Host array of `cap` doubles; returns the
- * number of phases written (5) or a negative status.  Waits for the recorded
- * events, then starts a new averaging window. */
+/* Mean phase durations (milliseconds) over the timed pod/tsvd/spod calls
+ * made since the previous read (at most the last k, k = the "timing"
+ * option):
+ *   out[0] leaf QR (+ fused mean removal)
+ *   out[1] tree combines
+ *   out[2] small SVD + truncation
+ *   out[3] tree propagation
+ *   out[4] leaf apply U = Q_1i W_i (+ mean output; for SPOD also the modes,
+ *          energies and frequency order)
+ *   out[5] the SPOD front end (windowed FFT); 0 for pod/tsvd.
+ * For PYLOM_MIXED calls out[3] is the refinement (projection
+ * Z = (D - mean 1^T) V_k, Gram, its eigen-solve, refined spectrum) and out[4]
+ * forms U = Z M; the host read-back of N0 between them is in neither.
+ * `out` is a host array of `cap` doubles; returns the number of phases (6)
+ * or a negative status.  Waits for the recorded events, then starts a new
+ * averaging window. */
 int pylom_phase_times(pylom_ctx ctx, double* out, int cap);
 
 /* After a stream synchronisation: the deferred numerical status of the last

@@ -42,6 +42,10 @@ SIGNATURES = {
     "pylom_plan_query": (ctypes.c_int, [VP, I64, I64, I64P, I64P, I64P, I64P]),
     "pylom_check": (ctypes.c_int, [VP, I64P]),
     "pylom_phase_times": (ctypes.c_int, [VP, DP, ctypes.c_int]),
+    "pylom_spod": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int, I64, I64, VP, I64, ctypes.c_double,
+                                  I64, I64, ctypes.c_int, ctypes.c_int, VP, VP, VP, VP]),
+    "pylom_spod_query": (ctypes.c_int, [VP, ctypes.c_int, I64, I64, I64, I64, I64P, I64P,
+                                        ctypes.POINTER(ctypes.c_size_t)]),
 }
 
 _lib = None

@@ -99,12 +99,13 @@ class Context:
         self.check(self.lib.pylom_workspace_query(self.h, dtype, _PREC[precision], m, n, ctypes.byref(b)))
         return b.value
 
-    PHASES = ("leaf_qr", "tree_combine", "small_svd", "tree_propagate", "leaf_apply")
+    PHASES = ("leaf_qr", "tree_combine", "small_svd", "tree_propagate", "leaf_apply",
+              "front_end")
 
     def phase_times(self) -> dict:
-        """Per-phase milliseconds of the last timed pod/tsvd call (option 'timing')."""
-        buf = (ctypes.c_double * 5)()
-        rc = self.lib.pylom_phase_times(self.h, buf, 5)
+        """Mean per-phase milliseconds of the timed calls since the last read."""
+        buf = (ctypes.c_double * 6)()
+        rc = self.lib.pylom_phase_times(self.h, buf, 6)
         if rc < 0:
             raise PylomError(rc, self.lib.pylom_last_error(self.h).decode())
         return {k: buf[i] for i, k in enumerate(self.PHASES)}
@@ -231,3 +232,51 @@ def tree_plan(P: int):
     buf = (ctypes.c_int64 * max(1, 3 * cnt))()
     lib.pylom_tree_plan(P, buf, cnt)
     return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(cnt)]
+
+
+WINDOWS = {"hann": 0, "hamming": 1}
+
+
+@dataclass
+class SpodResult:
+    modes: torch.Tensor   # nfreq x m x nblk complex spatial modes (phase-fixed)
+    L: torch.Tensor       # nfreq x nblk energies (S^2), descending per frequency
+    f: torch.Tensor       # nfreq frequencies f / (dt npwin)
+    order: torch.Tensor   # nfreq frequency indices by leading energy
+
+
+def spod_query(m: int, nt: int, npwin: int, nolap: int, spectra: str = "c64",
+               ctx: Context | None = None):
+    """(nblocks, nfreq, workspace bytes) of a pylom_spod call of this shape."""
+    ctx = ctx or Context(-1)
+    nb, nf, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+    code = C64 if spectra == "c64" else C128
+    ctx.check(ctx.lib.pylom_spod_query(ctx.h, code, m, nt, npwin, nolap, ctypes.byref(nb),
+                                       ctypes.byref(nf), ctypes.byref(b)))
+    return nb.value, nf.value, b.value
+
+
+def spod(D: torch.Tensor, dt: float = 1.0, npwin: int = 256, nolap: int = 128,
+         window: str = "hann", remove_mean: bool = True, spectra: str = "c64",
+         ctx: Context | None = None) -> SpodResult:
+    """SPOD of the FP32 snapshot matrix D (m x nt, rows = points): Alg. 6 with
+    the SVD of every frequency's spectral matrix, all frequencies in one batch."""
+    _rowmajor(D, "D")
+    if D.dtype != torch.float32 or not D.is_cuda:
+        raise ValueError("D must be a float32 GPU tensor")
+    ctx = ctx or context(D.device.index)
+    m, nt = D.shape
+    nb, nf, _ = spod_query(m, nt, npwin, nolap, spectra, ctx)
+    cdt = torch.complex64 if spectra == "c64" else torch.complex128
+    dev = D.device
+    modes = torch.empty((nf, m, nb), dtype=cdt, device=dev)
+    L = torch.empty((nf, nb), dtype=torch.float64, device=dev)
+    f = torch.empty(nf, dtype=torch.float64, device=dev)
+    order = torch.empty(nf, dtype=torch.int64, device=dev)
+    ctx.bind_stream()
+    code = C64 if spectra == "c64" else C128
+    rc = ctx.lib.pylom_spod(ctx.h, code, FP64, m, nt, _ptr(D), D.stride(0), float(dt), npwin,
+                            nolap, WINDOWS[window], int(bool(remove_mean)), _ptr(modes), _ptr(L),
+                            _ptr(f), _ptr(order))
+    ctx.check(rc)
+    return SpodResult(modes=modes, L=L, f=f, order=order)

@@ -56,6 +56,9 @@ static int hip_fail(pylom_ctx c, hipError_t e, const char* where) {
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+constexpr int kEvPerSlot = 7;  // timing events recorded per call
+constexpr int kPhases = 6;     // phases reported by pylom_phase_times
+
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
@@ -127,7 +130,7 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
       hipStreamSynchronize(c->stream);
       for (hipEvent_t e : c->ev)
         if (e) hipEventDestroy(e);
-      c->ev.assign((size_t)v * 6, nullptr);
+      c->ev.assign((size_t)v * kEvPerSlot, nullptr);
       for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) return fail(c, PYLOM_EHIP, "hipEventCreate");
     }
@@ -384,19 +387,20 @@ static int run_mixed(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, const
   double* M = (double*)(ws + p.oM);
   hipStream_t st = c->stream;
   const bool tm = c->timing > 0 && !c->ev.empty();
-  hipEvent_t* evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * 6] : nullptr;
-#define MARK(i) \
-  if (tm) HIPCHK(c, hipEventRecord(evs[i], st), "hipEventRecord")
+  hipEvent_t* evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * kEvPerSlot] : nullptr;
+#define EVREC(j) \
+  if (tm) HIPCHK(c, hipEventRecord(evs[j], st), "hipEventRecord")
 
-  MARK(0);
+  EVREC(0);
+  EVREC(1);
   HIPCHK(c, launch_leaf_qr_f32(p.g, (const float*)D, ldd, m, p.b, p.P, remove_mean, meanws, R32,
                                st), "leaf QR (FP32)");
   HIPCHK(c, launch_cast_f32_f64(R32, Rbuf, p.P * n * n, st), "R to FP64");
-  MARK(1);
+  EVREC(2);
   for (int64_t h = 1; h < p.P; h *= 2)
     HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, Rbuf, nullptr, p.nch_tree, 0, st),
            "tree combine");
-  MARK(2);
+  EVREC(3);
   HIPCHK(c, launch_small_svd(p.jp, Rbuf, (int)c->max_sweeps, ws + p.oSvd, S0, VT0, n, UR0,
                              residual, nr0, c->status_dev, st), "small SVD");
   c->status_valid = 1;
@@ -405,7 +409,7 @@ static int run_mixed(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, const
   HIPCHK(c, hipMemcpyAsync(&nr_first, nr0, sizeof(int64_t), hipMemcpyDeviceToHost, st),
          "N_r read-back");
   HIPCHK(c, hipStreamSynchronize(st), "hipStreamSynchronize");
-  MARK(3);
+  EVREC(4);
   if (nr_first <= 0) {
     // all-zero spectrum: nothing to refine, no mode is kept
     HIPCHK(c, hipMemcpyAsync(S, S0, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st),
@@ -428,13 +432,13 @@ static int run_mixed(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, const
     c->status_pairs = 2;
     HIPCHK(c, launch_rr_finish((int)n, (int)k, S0, lam, residual, S, n_r, WT, VT0, VT, ldvt, M,
                                st), "refined spectrum");
-    MARK(4);
+    EVREC(5);
     HIPCHK(c, launch_rr_form_u(0, m, (int)k, Z, M, n_r, U, ldu, st), "form U");
   }
-  if (!(nr_first > 0) && tm) HIPCHK(c, hipEventRecord(evs[4], st), "hipEventRecord");
+  if (!(nr_first > 0) && tm) HIPCHK(c, hipEventRecord(evs[5], st), "hipEventRecord");
   if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, 0, m, st), "mean out");
-  MARK(5);
-#undef MARK
+  EVREC(6);
+#undef EVREC
   if (tm) ++c->ev_calls;
   return PYLOM_OK;
 }
@@ -468,34 +472,35 @@ static int run_tsvd(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, 
   hipStream_t st = c->stream;
   const int in64 = dtype == PYLOM_R64;
   const bool tm = c->timing > 0 && !c->ev.empty();
-  hipEvent_t* evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * 6] : nullptr;
-#define MARK(i) \
-  if (tm) HIPCHK(c, hipEventRecord(evs[i], st), "hipEventRecord")
+  hipEvent_t* evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * kEvPerSlot] : nullptr;
+#define EVREC(j) \
+  if (tm) HIPCHK(c, hipEventRecord(evs[j], st), "hipEventRecord")
 
-  MARK(0);
+  EVREC(0);
+  EVREC(1);
   HIPCHK(c, launch_leaf_qr_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws, V, Tleaf,
                                p.nch_leaf, Rbuf, st), "leaf QR");
-  MARK(1);
+  EVREC(2);
   for (int64_t h = 1; h < p.P; h *= 2)
     HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, 1, st), "tree combine");
-  MARK(2);
+  EVREC(3);
   HIPCHK(c, launch_small_svd(p.jp, Rbuf, (int)c->max_sweeps, svdws, S, VT, ldvt, W, residual, n_r,
                              c->status_dev, st), "small SVD");
   c->status_valid = 1;
   c->status_pairs = 1;
-  MARK(3);
+  EVREC(4);
   int64_t top = 1;
   while (top * 2 < p.P) top *= 2;
   if (p.P > 1)
     for (int64_t h = top; h >= 1; h /= 2)
       HIPCHK(c, launch_apply_tree_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, W, n, n_r, n, st),
              "tree propagation");
-  MARK(4);
+  EVREC(5);
   HIPCHK(c, launch_apply_leaf_f64(p.g, m, p.b, p.P, V, Tleaf, p.nch_leaf, W, n, n_r, n, U, in64,
                                   ldu, st), "leaf apply");
   if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, in64, m, st), "mean out");
-  MARK(5);
-#undef MARK
+  EVREC(6);
+#undef EVREC
   if (tm) ++c->ev_calls;
   return PYLOM_OK;
 }
@@ -585,25 +590,193 @@ extern "C" int pylom_matmul(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int
   return PYLOM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// SPOD: FFT front end + one batch of realified TSQR-SVD problems
+// ---------------------------------------------------------------------------
+struct SpodPlan {
+  int64_t m, nt, npwin, nolap, nb, nf, n, M2, b, P, nch_leaf, nch_tree, levels;
+  int e_f64;
+  QrGeom g;
+  JacobiPlan jp;
+  size_t oE, oV, oTleaf, oR, oTtree, oW, oSvd, oS, oVT, oUR, oNr, oSt, oUe, total;
+  size_t svd_stride;
+};
+
+static int make_spod_plan(pylom_ctx c, pylom_dtype spectra, int64_t m, int64_t nt, int64_t npwin,
+                          int64_t nolap, SpodPlan* p) {
+  if (spectra != PYLOM_C64 && spectra != PYLOM_C128)
+    return fail(c, PYLOM_EDTYPE, "spectra must be C64 or C128");
+  if (npwin < 4 || npwin > 4096 || (npwin & (npwin - 1)))
+    return fail(c, PYLOM_ENOTSUP, "npwin must be a power of two in [4, 4096]");
+  if (nolap < 0 || nolap >= npwin) return fail(c, PYLOM_EINVAL, "need 0 <= nolap < npwin");
+  if (nt < npwin) return fail(c, PYLOM_ESHAPE, "need nt >= npwin");
+  const int64_t nb = (nt - nolap) / (npwin - nolap);
+  if (nb < 1) return fail(c, PYLOM_ESHAPE, "no complete Welch block");
+  if (nb > 16) return fail(c, PYLOM_ENOTSUP, "more than 16 Welch blocks");
+  if (m < nb) return fail(c, PYLOM_ESHAPE, "need m >= number of blocks");
+  p->m = m; p->nt = nt; p->npwin = npwin; p->nolap = nolap; p->nb = nb;
+  p->nf = npwin / 2 + 1;
+  p->n = 2 * nb;
+  p->M2 = 2 * m;
+  p->e_f64 = spectra == PYLOM_C128;
+  if (spod_fft_lds_bytes((int)npwin, (int)nb, p->e_f64 ? 8 : 4) > (size_t)160 * 1024)
+    return fail(c, PYLOM_ENOTSUP, "npwin x blocks too large for the FFT staging");
+  const int64_t n = p->n;
+  int64_t b = c->block_rows > 0 ? c->block_rows : 4096;
+  if (b < n) b = n;
+  int64_t P = p->M2 / b;
+  if (P < 1) P = 1;
+  p->b = b;
+  p->P = P;
+  if (!qr_geom((int)n, 8, &p->g)) return fail(c, PYLOM_ENOTSUP, "no chunk geometry");
+  if (!jacobi_plan((int)n, &p->jp) || p->jp.G != 1)
+    return fail(c, PYLOM_ENOTSUP, "no single-workgroup Jacobi plan");
+  const int64_t last = p->M2 - (P - 1) * b;
+  const int64_t s = p->g.s, np = p->g.npanels, nf = p->nf;
+  p->nch_leaf = (last + s - 1) / s;
+  p->nch_tree = (n + s - 1) / s;
+  int64_t lv = 0;
+  for (int64_t h = 1; h < P; h *= 2) ++lv;
+  p->levels = lv;
+  p->svd_stride = jacobi_ws_stride(p->jp, (int)c->max_sweeps);
+  const size_t es = p->e_f64 ? 8 : 4;
+  size_t off = 0;
+  p->oE = off;     off = align_up(off + es * (size_t)nf * p->M2 * n);
+  p->oV = off;     off = align_up(off + 8 * (size_t)nf * p->M2 * n);
+  p->oTleaf = off; off = align_up(off + 8 * (size_t)nf * P * p->nch_leaf * np * 256);
+  p->oR = off;     off = align_up(off + 8 * (size_t)nf * P * n * n);
+  p->oTtree = off; off = align_up(off + 8 * (size_t)nf * P * p->nch_tree * np * 256);
+  p->oW = off;     off = align_up(off + 8 * (size_t)nf * P * n * n);
+  p->oSvd = off;   off = align_up(off + p->svd_stride * (size_t)nf);
+  p->oS = off;     off = align_up(off + 8 * (size_t)nf * n);
+  p->oVT = off;    off = align_up(off + 8 * (size_t)nf * n * n);
+  p->oUR = off;    off = align_up(off + 8 * (size_t)nf * n * n);
+  p->oNr = off;    off = align_up(off + 8 * (size_t)nf);
+  p->oSt = off;    off = align_up(off + 8 * (size_t)nf);
+  p->oUe = off;    off = align_up(off + 8 * (size_t)nf * p->M2 * nb);
+  p->total = off;
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_spod_query(pylom_ctx c, pylom_dtype spectra, int64_t m, int64_t nt,
+                                int64_t npwin, int64_t nolap, int64_t* nblocks, int64_t* nfreq,
+                                size_t* bytes) {
+  if (!c) return PYLOM_EINVAL;
+  SpodPlan p;
+  const int rc = make_spod_plan(c, spectra, m, nt, npwin, nolap, &p);
+  if (rc) return rc;
+  if (nblocks) *nblocks = p.nb;
+  if (nfreq) *nfreq = p.nf;
+  if (bytes) *bytes = p.total;
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_spod(pylom_ctx c, pylom_dtype spectra, pylom_prec prec, int64_t m,
+                          int64_t nt, const float* D, int64_t ldd, double dt, int64_t npwin,
+                          int64_t nolap, int window, int remove_mean, void* modes, double* L,
+                          double* freqs, int64_t* order) {
+  if (!c) return PYLOM_EINVAL;
+  if (prec != PYLOM_FP64) return fail(c, PYLOM_ENOTSUP, "SPOD runs the FP64 TSQR-SVD only");
+  if (!D || !modes || !L) return fail(c, PYLOM_EINVAL, "null array argument");
+  if (!(dt > 0.0)) return fail(c, PYLOM_EINVAL, "dt must be > 0");
+  if (window != 0 && window != 1) return fail(c, PYLOM_EINVAL, "window must be 0 (Hann) or 1 (Hamming)");
+  if (m < 1 || nt < 1) return fail(c, PYLOM_ESHAPE, "empty snapshot matrix");
+  if (ldd < nt) return fail(c, PYLOM_ESHAPE, "leading dimension < nt");
+  SpodPlan p;
+  int rc = make_spod_plan(c, spectra, m, nt, npwin, nolap, &p);
+  if (rc) return rc;
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+  rc = ensure_ws(c, p.total);
+  if (rc) return rc;
+  char* ws = (char*)c->ws;
+  void* E = ws + p.oE;
+  double* V = (double*)(ws + p.oV);
+  double* Tleaf = (double*)(ws + p.oTleaf);
+  double* R = (double*)(ws + p.oR);
+  double* Ttree = (double*)(ws + p.oTtree);
+  double* W = (double*)(ws + p.oW);
+  double* S = (double*)(ws + p.oS);
+  double* VTb = (double*)(ws + p.oVT);
+  double* URb = (double*)(ws + p.oUR);
+  int64_t* nr = (int64_t*)(ws + p.oNr);
+  int* st_each = (int*)(ws + p.oSt);
+  double* Ue = (double*)(ws + p.oUe);
+  hipStream_t st = c->stream;
+  const int64_t n = p.n, nb = p.nb, nf = p.nf, M2 = p.M2, P = p.P, np = p.g.npanels;
+  const bool tm = c->timing > 0 && !c->ev.empty();
+  hipEvent_t* evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * kEvPerSlot] : nullptr;
+#define EVREC(j) \
+  if (tm) HIPCHK(c, hipEventRecord(evs[j], st), "hipEventRecord")
+
+  EVREC(0);
+  HIPCHK(c, launch_spod_fft(p.e_f64, m, nt, D, ldd, (int)npwin, (int)nolap, (int)nb, window,
+                            remove_mean, E, n, M2 * n, st), "SPOD front end");
+  EVREC(1);
+  Batch bl;
+  bl.count = nf;
+  bl.sD = M2 * n;
+  bl.sV = M2 * n;
+  bl.sTleaf = P * p.nch_leaf * np * 256;
+  bl.sR = P * n * n;
+  bl.sTtree = P * p.nch_tree * np * 256;
+  bl.sW = P * n * n;
+  bl.sU = M2 * nb;
+  HIPCHK(c, launch_leaf_qr_f64(p.g, E, p.e_f64, n, M2, p.b, P, 0, nullptr, V, Tleaf, p.nch_leaf, R,
+                               st, bl), "leaf QR");
+  EVREC(2);
+  for (int64_t h = 1; h < P; h *= 2)
+    HIPCHK(c, launch_tree_combine_f64(p.g, h, P, R, Ttree, p.nch_tree, 1, st, bl), "tree combine");
+  EVREC(3);
+  HIPCHK(c, launch_small_svd_batched(p.jp, nf, R, P * n * n, (int)c->max_sweeps, ws + p.oSvd, S, n,
+                                     VTb, n, n * n, URb, n * n, 0.0, nr, st_each, c->status_dev,
+                                     st), "batched SVD");
+  c->status_valid = 1;
+  c->status_pairs = 1;
+  HIPCHK(c, launch_select_even((int)n, (int)nb, nf, URb, n * n, W, n, P * n * n, st), "root W");
+  EVREC(4);
+  int64_t top = 1;
+  while (top * 2 < P) top *= 2;
+  if (P > 1)
+    for (int64_t h = top; h >= 1; h /= 2)
+      HIPCHK(c, launch_apply_tree_f64(p.g, h, P, R, Ttree, p.nch_tree, W, n, nullptr, nb, st, bl),
+             "tree propagation");
+  EVREC(5);
+  HIPCHK(c, launch_apply_leaf_f64(p.g, M2, p.b, P, V, Tleaf, p.nch_leaf, W, n, nullptr, nb, Ue, 1,
+                                  nb, st, bl), "leaf apply");
+  HIPCHK(c, launch_spod_modes(p.e_f64, m, (int)nb, nf, Ue, M2 * nb, VTb, n * n, S, n, modes, L, st),
+         "modes");
+  HIPCHK(c, launch_spod_order((int)nf, (int)nb, dt, (int)npwin, L, freqs, order, st), "order");
+  EVREC(6);
+#undef EVREC
+  if (tm) ++c->ev_calls;
+  return PYLOM_OK;
+}
+
 extern "C" int pylom_phase_times(pylom_ctx c, double* out, int cap) {
   if (!c || (cap > 0 && !out)) return PYLOM_EINVAL;
   if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
   if (c->timing <= 0 || c->ev_calls == 0) return fail(c, PYLOM_EINVAL, "no timed call recorded");
   const int64_t nrec = c->ev_calls < c->timing ? c->ev_calls : c->timing;
-  double acc[5] = {0, 0, 0, 0, 0};
+  // events per slot: e0 call start, e1 after the front end (SPOD FFT; none
+  // for POD), e2..e6 after leaf QR, tree, SVD, propagation, apply
+  double acc[kPhases] = {0, 0, 0, 0, 0, 0};
   for (int64_t k = 0; k < nrec; ++k) {
     const int64_t slot = (c->ev_calls - 1 - k) % c->timing;
-    hipEvent_t* e = &c->ev[(size_t)slot * 6];
-    HIPCHK(c, hipEventSynchronize(e[5]), "hipEventSynchronize");
-    for (int i = 0; i < 5; ++i) {
+    hipEvent_t* e = &c->ev[(size_t)slot * kEvPerSlot];
+    HIPCHK(c, hipEventSynchronize(e[kEvPerSlot - 1]), "hipEventSynchronize");
+    for (int i = 0; i < kPhases; ++i) {
       float ms = 0.f;
-      HIPCHK(c, hipEventElapsedTime(&ms, e[i], e[i + 1]), "hipEventElapsedTime");
+      if (i < 5)
+        HIPCHK(c, hipEventElapsedTime(&ms, e[i + 1], e[i + 2]), "hipEventElapsedTime");
+      else
+        HIPCHK(c, hipEventElapsedTime(&ms, e[0], e[1]), "hipEventElapsedTime");
       acc[i] += ms;
     }
   }
-  for (int i = 0; i < 5 && i < cap; ++i) out[i] = acc[i] / (double)nrec;
+  for (int i = 0; i < kPhases && i < cap; ++i) out[i] = acc[i] / (double)nrec;
   c->ev_calls = 0;
-  return 5;
+  return kPhases;
 }
 
 extern "C" int pylom_check(pylom_ctx c, int64_t* sweeps) {

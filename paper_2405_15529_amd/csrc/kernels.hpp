@@ -14,6 +14,13 @@ struct QrGeom {
   int npanels;  // ceil(n / 16)
 };
 
+// A batch of same-shape problems (blockIdx.y = problem): element strides
+// between the buffers of consecutive problems.  count = 1 is one problem.
+struct Batch {
+  int64_t count = 1;
+  int64_t sD = 0, sMean = 0, sV = 0, sTleaf = 0, sR = 0, sTtree = 0, sW = 0, sU = 0;
+};
+
 // Chunk rows and LDS stride for n columns of element size `esize`; returns
 // false if n is too wide for the single-workgroup stacked QR.
 bool qr_geom(int n, int esize, QrGeom* g);
@@ -28,19 +35,21 @@ size_t apply_lds_bytes(const QrGeom& g, int esize);
 // in_f64: input is double (else float).  Compute type: double.
 hipError_t launch_leaf_qr_f64(const QrGeom& g, const void* D, int in_f64, int64_t ldd, int64_t m,
                               int64_t b, int64_t P, int remove_mean, double* mean_ws, double* V,
-                              double* Tleaf, int64_t nch_leaf, double* Rbuf, hipStream_t st);
+                              double* Tleaf, int64_t nch_leaf, double* Rbuf, hipStream_t st,
+                              const Batch& bt = Batch());
 // FP32 compute leaf QR (mixed precision): R only (no reflectors), R_j written
 // in FP32 to Rbuf32 + j*n*n.
 hipError_t launch_leaf_qr_f32(const QrGeom& g, const float* D, int64_t ldd, int64_t m, int64_t b,
                               int64_t P, int remove_mean, double* mean_ws, float* Rbuf32,
-                              hipStream_t st);
+                              hipStream_t st, const Batch& bt = Batch());
 
 // ---- tree combine (Alg. 1 reduce phase): node j absorbs node j+h ------------
 // for every j = 0, 2h, 4h, ... with j + h < P.  In place: R_j <- R of
 // [R_j; R_{j+h}]; Rbuf + (j+h)*n*n <- reflectors; Ttree <- T factors (if
 // store_q).
 hipError_t launch_tree_combine_f64(const QrGeom& g, int64_t h, int64_t P, double* Rbuf,
-                                   double* Ttree, int64_t nch_tree, int store_q, hipStream_t st);
+                                   double* Ttree, int64_t nch_tree, int store_q, hipStream_t st,
+                                   const Batch& bt = Batch());
 
 // ---- apply (Alg. 1 broadcast phase + Q_i = Q_1i Q_w, Eq. svdqr3) -----------
 // Leaf mode: U rows of leaf j = Q_1j [W_j; 0]; combine mode (level h):
@@ -48,10 +57,12 @@ hipError_t launch_tree_combine_f64(const QrGeom& g, int64_t h, int64_t P, double
 hipError_t launch_apply_leaf_f64(const QrGeom& g, int64_t m, int64_t b, int64_t P,
                                  const double* V, const double* Tleaf, int64_t nch_leaf,
                                  const double* W, int64_t ldw, const int64_t* nr, int64_t ncols,
-                                 void* U, int out_f64, int64_t ldu, hipStream_t st);
+                                 void* U, int out_f64, int64_t ldu, hipStream_t st,
+                                 const Batch& bt = Batch());
 hipError_t launch_apply_tree_f64(const QrGeom& g, int64_t h, int64_t P, const double* Rbuf,
                                  const double* Ttree, int64_t nch_tree, double* W, int64_t ldw,
-                                 const int64_t* nr, int64_t ncols, hipStream_t st);
+                                 const int64_t* nr, int64_t ncols, hipStream_t st,
+                                 const Batch& bt = Batch());
 
 // ---- small SVD (Eq. svdqr2) ------------------------------------------------
 struct JacobiPlan {
@@ -66,6 +77,17 @@ size_t jacobi_ws_bytes(const JacobiPlan& p, int max_sweeps);
 hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps, void* ws,
                             double* S, double* VT, int64_t ldvt, double* UR, double residual,
                             int64_t* nr, int* status, hipStream_t st);
+
+// Same for `count` problems of one size n <= 32 (one workgroup each; G == 1):
+// problem k reads R + k*sR, uses the workspace slice ws + k*jacobi_ws_stride,
+// writes S + k*sS, VT + k*sVT, UR + k*sUR, nr[k] and status_each[2k..2k+1];
+// status[0..1] receives the reduced status (max sweeps or -1, timeout flag).
+size_t jacobi_ws_stride(const JacobiPlan& p, int max_sweeps);
+hipError_t launch_small_svd_batched(const JacobiPlan& p, int64_t count, const double* R,
+                                    int64_t sR, int max_sweeps, void* ws, double* S, int64_t sS,
+                                    double* VT, int64_t ldvt, int64_t sVT, double* UR,
+                                    int64_t sUR, double residual, int64_t* nr, int* status_each,
+                                    int* status, hipStream_t st);
 
 // ---- misc ------------------------------------------------------------------
 hipError_t launch_cast_out(const double* src, void* dst, int dst_f64, int64_t count, hipStream_t st);
@@ -96,5 +118,21 @@ hipError_t launch_rr_finish(int n, int k, const double* S0, const double* lam, d
 // U[:, c] = Z M[:, c] for c < N_r.
 hipError_t launch_rr_form_u(int out_f64, int64_t m, int k, const double* Z, const double* M,
                             const int64_t* nr, void* U, int64_t ldu, hipStream_t st);
+
+// ---- SPOD (Alg. 6): front end, realified batch back end ----------------------
+size_t spod_fft_lds_bytes(int npwin, int nb, int esize);
+// Windowed one-sided FFT of every Welch block of every point of D (m x nt,
+// FP32), written as the realification of each frequency's m x nb spectral
+// matrix: E + f*sE is 2m x 2nb (ld ldE) in FP64 (e_f64) or FP32.
+hipError_t launch_spod_fft(int e_f64, int64_t m, int64_t nt, const float* D, int64_t ldd,
+                           int npwin, int nolap, int nb, int window, int remove_mean, void* E,
+                           int64_t ldE, int64_t sE, hipStream_t st);
+hipError_t launch_select_even(int n, int nb, int64_t count, const double* UR, int64_t sUR,
+                              double* W, int64_t ldw, int64_t sW, hipStream_t st);
+hipError_t launch_spod_modes(int out_f64, int64_t m, int nb, int64_t nf, const double* Ue,
+                             int64_t sUe, const double* VT, int64_t sVT, const double* S,
+                             int64_t sS, void* modes, double* L, hipStream_t st);
+hipError_t launch_spod_order(int nf, int nb, double dt, int npwin, const double* L, double* freqs,
+                             int64_t* order, hipStream_t st);
 
 }  // namespace pylom

@@ -12,7 +12,8 @@
 // (Rutishauser): zeta = (|b|^2 - |a|^2) / (2 a.b),
 // t = sign(zeta) / (|zeta| + sqrt(1+zeta^2)), c = 1/sqrt(1+t^2), s = c t,
 // a' = c a - s b, b' = s a + c b, with |a'|^2 = |a|^2 - t a.b and
-// |b'|^2 = |b|^2 + t a.b carried along (recomputed at every block step).
+// |b'|^2 = |b|^2 + t a.b carried along (recomputed at every block step and
+// after any rotation whose update cancels).
 //
 // Parallel layout: the npad >= n columns are cut into 2G blocks of w
 // columns.  G workgroups (one CU each) form a round-robin tournament over the
@@ -81,7 +82,18 @@ size_t jacobi_ws_bytes(const JacobiPlan& p, int max_sweeps) {
 // ---- setup: A <- R^T (column j = row j of R), V <- I, counters <- 0 ---------
 __global__ void k_jacobi_setup(int n, int npad, const double* __restrict__ R, double* A,
                                double* V, unsigned int* bar, int* flags, int nflags, int* status,
-                               int status0) {
+                               int status0, int64_t sR, int64_t sWs) {
+  if (blockIdx.y) {
+    // batch: problem blockIdx.y has its own R (stride sR doubles) and its own
+    // workspace slice (stride sWs bytes)
+    const int64_t pb = blockIdx.y;
+    R += pb * sR;
+    A = (double*)((char*)A + pb * sWs);
+    V = (double*)((char*)V + pb * sWs);
+    bar = (unsigned int*)((char*)bar + pb * sWs);
+    flags = (int*)((char*)flags + pb * sWs);
+    status += 2 * pb;
+  }
   const int64_t total = (int64_t)npad * n;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -139,6 +151,15 @@ __device__ __forceinline__ int rr_player(int i, int st, int nplayers) {
   return ((i - 1 + st) % (nplayers - 1)) + 1;
 }
 
+template <int LPP>
+__device__ __forceinline__ double col_norm2(const double (&a)[JRPL], int rpl) {
+  double x = 0.0;
+#pragma unroll
+  for (int k = 0; k < JRPL; ++k)
+    if (k < rpl) x += a[k] * a[k];
+  return gsum<LPP>(x);
+}
+
 // Rotate the pair (a, b) held by an LPP-lane group (RPL rows per lane each)
 // if it is not yet orthogonal; norms na, nb are updated.  Returns 1 if rotated.
 template <int LPP>
@@ -153,7 +174,13 @@ __device__ __forceinline__ int jacobi_pair(double (&a)[JRPL], double (&va)[JRPL]
   if (!(na > 0.0) || !(nb > 0.0)) return 0;
   if (fabs(g) <= tol * sqrt(na) * sqrt(nb)) return 0;
   const double zeta = (nb - na) / (2.0 * g);
-  double t = 1.0 / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double az = fabs(zeta);
+  // |zeta| > 1e150 (columns of very different tiny norms, as rank-deficient
+  // R produces): zeta^2 would overflow and t become 0, an identity rotation
+  // that still counts as one and stalls convergence; there t = 1/(2|zeta|)
+  // to full precision
+  double t = (az > 1e150) ? 0.5 / az : 1.0 / (az + sqrt(1.0 + zeta * zeta));
+  if (!(t > 0.0)) return 0;  // zeta = inf: no representable rotation
   if (zeta < 0.0) t = -t;
   const double c = 1.0 / sqrt(1.0 + t * t);
   const double s = c * t;
@@ -170,19 +197,19 @@ __device__ __forceinline__ int jacobi_pair(double (&a)[JRPL], double (&va)[JRPL]
       vb[k] = s * x + c * y;
     }
   }
-  na = na - t * g;
-  nb = nb + t * g;
-  if (na < 0.0) na = 0.0;
+  const double na2 = na - t * g, nb2 = nb + t * g;
+  if (na2 < 0.5 * na || nb2 < 0.5 * nb) {
+    // the update cancels (a column nearly parallel to a much longer one, as
+    // in rank-deficient R): carried norms would lose all accuracy and stall
+    // the convergence test, so recompute both from the rotated columns.
+    // The branch is uniform over the group (its inputs are group sums).
+    na = col_norm2<LPP>(a, rpl_a);
+    nb = col_norm2<LPP>(b, rpl_a);
+  } else {
+    na = na2;
+    nb = nb2;
+  }
   return 1;
-}
-
-template <int LPP>
-__device__ __forceinline__ double col_norm2(const double (&a)[JRPL], int rpl) {
-  double x = 0.0;
-#pragma unroll
-  for (int k = 0; k < JRPL; ++k)
-    if (k < rpl) x += a[k] * a[k];
-  return gsum<LPP>(x);
 }
 
 template <int LPP>
@@ -212,11 +239,20 @@ struct JacobiArgs {
   unsigned int* bar;
   int* flags;
   int* status;
+  int64_t sWs;  // batch: workspace slice stride in bytes (problem = blockIdx.y)
 };
 
 template <int LPP>
 __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
   if (blockIdx.x % a.xcd_stride) return;
+  if (blockIdx.y) {
+    const int64_t pb = blockIdx.y;
+    a.A = (double*)((char*)a.A + pb * a.sWs);
+    a.V = (double*)((char*)a.V + pb * a.sWs);
+    a.bar = (unsigned int*)((char*)a.bar + pb * a.sWs);
+    a.flags = (int*)((char*)a.flags + pb * a.sWs);
+    a.status += 2 * pb;
+  }
   __shared__ double xbuf[2][JT * 2 * JRPL];  // circulating b columns (A and V parts), 2 buffers
   __shared__ double xnorm[2][JT / 2];
   __shared__ int rot_count;
@@ -318,7 +354,17 @@ constexpr int FT = 1024;
 __global__ __launch_bounds__(FT) void k_svd_finalize(int n, const double* __restrict__ A,
                                                      const double* __restrict__ V, double* S,
                                                      double* VT, int64_t ldvt, double* UR,
-                                                     double residual, int64_t* nr) {
+                                                     double residual, int64_t* nr, int64_t sWs,
+                                                     int64_t sS, int64_t sVT, int64_t sUR) {
+  if (blockIdx.y) {
+    const int64_t pb = blockIdx.y;
+    A = (const double*)((const char*)A + pb * sWs);
+    V = (const double*)((const char*)V + pb * sWs);
+    S += pb * sS;
+    VT += pb * sVT;
+    UR += pb * sUR;
+    nr += pb;
+  }
   __shared__ double sig[1024];
   __shared__ double sgn[1024];
   __shared__ int rank[1024];
@@ -400,7 +446,7 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
   JacobiWs w = jacobi_ws(p, max_sweeps, ws);
   const int nflags = max_sweeps + 1;
   hipLaunchKernelGGL(k_jacobi_setup, dim3(64), dim3(256), 0, st, p.n, p.npad, R, w.A, w.V, w.bar,
-                     w.flags, nflags, status, max_sweeps > 0 ? 0 : -1);
+                     w.flags, nflags, status, max_sweeps > 0 ? 0 : -1, (int64_t)0, (int64_t)0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (max_sweeps > 0) {
@@ -408,6 +454,7 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
     a.n = p.n; a.npad = p.npad; a.w = p.w; a.G = p.G; a.xcd_stride = p.xcd_stride;
     a.max_sweeps = max_sweeps; a.A = w.A; a.V = w.V; a.bar = w.bar; a.flags = w.flags;
     a.status = status;
+    a.sWs = 0;
     void* args[] = {&a};
     const dim3 grid(p.G * p.xcd_stride), block(JT);
     const void* fn = nullptr;
@@ -421,7 +468,75 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_svd_finalize, dim3(1), dim3(FT), 0, st, p.n, w.A, w.V, S, VT, ldvt, UR,
-                     residual, nr);
+                     residual, nr, (int64_t)0, (int64_t)0, (int64_t)0, (int64_t)0);
+  return hipGetLastError();
+}
+
+size_t jacobi_ws_stride(const JacobiPlan& p, int max_sweeps) {
+  return (jacobi_ws_bytes(p, max_sweeps) + 255) & ~(size_t)255;
+}
+
+// Status of a batch: sweeps = the largest count, -1 if any problem did not
+// converge; the barrier flag is the OR over problems.
+__global__ void k_status_reduce(int64_t count, const int* __restrict__ st, int* out) {
+  __shared__ int smax, sneg, stmo;
+  if (threadIdx.x == 0) {
+    smax = 0;
+    sneg = 0;
+    stmo = 0;
+  }
+  __syncthreads();
+  for (int64_t k = threadIdx.x; k < count; k += blockDim.x) {
+    const int sw = st[2 * k];
+    if (sw < 0) atomicOr(&sneg, 1);
+    else atomicMax(&smax, sw);
+    if (st[2 * k + 1]) atomicOr(&stmo, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = sneg ? -1 : smax;
+    out[1] = stmo;
+  }
+}
+
+hipError_t launch_small_svd_batched(const JacobiPlan& p, int64_t count, const double* R,
+                                    int64_t sR, int max_sweeps, void* ws, double* S, int64_t sS,
+                                    double* VT, int64_t ldvt, int64_t sVT, double* UR,
+                                    int64_t sUR, double residual, int64_t* nr, int* status_each,
+                                    int* status, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (p.G != 1 || p.n < 2 || count > 65535) return hipErrorInvalidValue;
+  const int64_t wsb = (int64_t)jacobi_ws_stride(p, max_sweeps);
+  JacobiWs w = jacobi_ws(p, max_sweeps, ws);
+  const int nflags = max_sweeps + 1;
+  hipLaunchKernelGGL(k_jacobi_setup, dim3(8, (unsigned)count), dim3(256), 0, st, p.n, p.npad, R,
+                     w.A, w.V, w.bar, w.flags, nflags, status_each, max_sweeps > 0 ? 0 : -1, sR,
+                     wsb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (max_sweeps > 0) {
+    // one workgroup per problem: no device-wide barrier is involved, so a
+    // plain launch is enough
+    JacobiArgs a;
+    a.n = p.n; a.npad = p.npad; a.w = p.w; a.G = 1; a.xcd_stride = 1;
+    a.max_sweeps = max_sweeps; a.A = w.A; a.V = w.V; a.bar = w.bar; a.flags = w.flags;
+    a.status = status_each;
+    a.sWs = wsb;
+    const dim3 grid(1, (unsigned)count), block(JT);
+    switch (p.lpp) {
+      case 16: hipLaunchKernelGGL(k_jacobi<16>, grid, block, 0, st, a); break;
+      case 32: hipLaunchKernelGGL(k_jacobi<32>, grid, block, 0, st, a); break;
+      case 64: hipLaunchKernelGGL(k_jacobi<64>, grid, block, 0, st, a); break;
+      default: return hipErrorInvalidValue;
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_svd_finalize, dim3(1, (unsigned)count), dim3(FT), 0, st, p.n, w.A, w.V, S,
+                     VT, ldvt, UR, residual, nr, wsb, sS, sVT, sUR);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_status_reduce, dim3(1), dim3(256), 0, st, count, status_each, status);
   return hipGetLastError();
 }
 

@@ -92,6 +92,8 @@ struct QrArgs {
   int64_t nch_tree;
   // both
   T* Rbuf;
+  // batch strides (elements), problem = blockIdx.y
+  int64_t bsD, bsMean, bsV, bsTleaf, bsR, bsTtree;
 };
 
 // ---------------------------------------------------------------------------
@@ -459,6 +461,15 @@ template <typename T, typename TI, int RT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_stacked_qr(QrArgs<T, TI> a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (blockIdx.y) {
+    const int64_t pb = blockIdx.y;
+    if (a.D) a.D += pb * a.bsD;
+    if (a.mean_ws) a.mean_ws += pb * a.bsMean;
+    if (a.V) a.V += pb * a.bsV;
+    if (a.Tleaf) a.Tleaf += pb * a.bsTleaf;
+    if (a.Ttree) a.Ttree += pb * a.bsTtree;
+    a.Rbuf += pb * a.bsR;
+  }
   constexpr int S = 4 * RT;
   const int n = a.n, ldc = a.ldc, npan = a.npanels;
   T* C = reinterpret_cast<T*>(smem);
@@ -609,12 +620,23 @@ struct ApplyArgs {
   // state tiles
   T* W;
   int64_t ldw;
+  // batch strides (elements), problem = blockIdx.y
+  int64_t bsV, bsTleaf, bsR, bsTtree, bsW, bsU;
 };
 
 template <typename T, typename TO>
 __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
   typedef typename Mfma<T>::v4 v4;
   extern __shared__ __align__(16) unsigned char smem[];
+  if (blockIdx.y) {
+    const int64_t pb = blockIdx.y;
+    if (a.V) a.V += pb * a.bsV;
+    if (a.Tleaf) a.Tleaf += pb * a.bsTleaf;
+    if (a.Rbuf) a.Rbuf += pb * a.bsR;
+    if (a.Ttree) a.Ttree += pb * a.bsTtree;
+    if (a.U) a.U += pb * a.bsU;
+    a.W += pb * a.bsW;
+  }
   const int n = a.n, s = a.s, npan = a.npanels;
   const int64_t ncols = a.nr ? *a.nr : a.ncols;
   // tile-major block order: the active (tile < N_r / 16) blocks are the first
@@ -819,29 +841,45 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T, typename TI, int RT>
-static hipError_t launch_qr_t(const QrArgs<T, TI>& a, int grid, size_t lds, hipStream_t st) {
+static hipError_t launch_qr_t(const QrArgs<T, TI>& a, int grid, int gy, size_t lds,
+                              hipStream_t st) {
   hipError_t e = hipFuncSetAttribute((const void*)k_stacked_qr<T, TI, RT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_stacked_qr<T, TI, RT>), dim3(grid), dim3(256), lds, st, a);
+  hipLaunchKernelGGL((k_stacked_qr<T, TI, RT>), dim3(grid, gy), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
 template <typename T, typename TI>
-static hipError_t launch_qr_any(const QrArgs<T, TI>& a, int grid, size_t lds, hipStream_t st) {
-  if (grid <= 0) return hipSuccess;
+static hipError_t launch_qr_any(const QrArgs<T, TI>& a, int grid, size_t lds, hipStream_t st,
+                                int64_t gy = 1) {
+  if (grid <= 0 || gy <= 0) return hipSuccess;
+  if (gy > 65535) return hipErrorInvalidValue;
   switch (a.s) {
-    case 16: return launch_qr_t<T, TI, 4>(a, grid, lds, st);
-    case 32: return launch_qr_t<T, TI, 8>(a, grid, lds, st);
-    case 48: return launch_qr_t<T, TI, 12>(a, grid, lds, st);
-    case 64: return launch_qr_t<T, TI, 16>(a, grid, lds, st);
+    case 16: return launch_qr_t<T, TI, 4>(a, grid, (int)gy, lds, st);
+    case 32: return launch_qr_t<T, TI, 8>(a, grid, (int)gy, lds, st);
+    case 48: return launch_qr_t<T, TI, 12>(a, grid, (int)gy, lds, st);
+    case 64: return launch_qr_t<T, TI, 16>(a, grid, (int)gy, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
 
+template <typename QA>
+static void set_qr_batch(QA& a, const Batch& bt) {
+  a.bsD = bt.sD; a.bsMean = bt.sMean; a.bsV = bt.sV; a.bsTleaf = bt.sTleaf; a.bsR = bt.sR;
+  a.bsTtree = bt.sTtree;
+}
+
+template <typename AA>
+static void set_apply_batch(AA& a, const Batch& bt) {
+  a.bsV = bt.sV; a.bsTleaf = bt.sTleaf; a.bsR = bt.sR; a.bsTtree = bt.sTtree; a.bsW = bt.sW;
+  a.bsU = bt.sU;
+}
+
 hipError_t launch_leaf_qr_f64(const QrGeom& g, const void* D, int in_f64, int64_t ldd, int64_t m,
                               int64_t b, int64_t P, int remove_mean, double* mean_ws, double* V,
-                              double* Tleaf, int64_t nch_leaf, double* Rbuf, hipStream_t st) {
+                              double* Tleaf, int64_t nch_leaf, double* Rbuf, hipStream_t st,
+                              const Batch& bt) {
   const size_t lds = qr_lds_bytes(g, 8);
   if (in_f64) {
     QrArgs<double, double> a{};
@@ -850,7 +888,8 @@ hipError_t launch_leaf_qr_f64(const QrGeom& g, const void* D, int in_f64, int64_
     a.D = (const double*)D; a.ldd = ldd; a.m = m; a.b = b; a.P = P;
     a.remove_mean = remove_mean; a.mean_ws = mean_ws; a.V = V; a.Tleaf = Tleaf;
     a.nch_leaf = nch_leaf; a.Rbuf = Rbuf;
-    return launch_qr_any(a, (int)P, lds, st);
+    set_qr_batch(a, bt);
+    return launch_qr_any(a, (int)P, lds, st, bt.count);
   }
   QrArgs<double, float> a{};
   a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.mode = 0;
@@ -858,44 +897,51 @@ hipError_t launch_leaf_qr_f64(const QrGeom& g, const void* D, int in_f64, int64_
   a.D = (const float*)D; a.ldd = ldd; a.m = m; a.b = b; a.P = P;
   a.remove_mean = remove_mean; a.mean_ws = mean_ws; a.V = V; a.Tleaf = Tleaf;
   a.nch_leaf = nch_leaf; a.Rbuf = Rbuf;
-  return launch_qr_any(a, (int)P, lds, st);
+  set_qr_batch(a, bt);
+  return launch_qr_any(a, (int)P, lds, st, bt.count);
 }
 
 hipError_t launch_leaf_qr_f32(const QrGeom& g, const float* D, int64_t ldd, int64_t m, int64_t b,
                               int64_t P, int remove_mean, double* mean_ws, float* Rbuf32,
-                              hipStream_t st) {
+                              hipStream_t st, const Batch& bt) {
   QrArgs<float, float> a{};
   a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.mode = 0; a.store_q = 0;
   a.D = D; a.ldd = ldd; a.m = m; a.b = b; a.P = P;
   a.remove_mean = remove_mean; a.mean_ws = mean_ws; a.Rbuf = Rbuf32;
-  return launch_qr_any(a, (int)P, qr_lds_bytes(g, 4), st);
+  set_qr_batch(a, bt);
+  return launch_qr_any(a, (int)P, qr_lds_bytes(g, 4), st, bt.count);
 }
 
 hipError_t launch_tree_combine_f64(const QrGeom& g, int64_t h, int64_t P, double* Rbuf,
-                                   double* Ttree, int64_t nch_tree, int store_q, hipStream_t st) {
+                                   double* Ttree, int64_t nch_tree, int store_q, hipStream_t st,
+                                   const Batch& bt) {
   QrArgs<double, double> a{};
   a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.mode = 1;
   a.store_q = store_q; a.h = h; a.Ttree = Ttree; a.nch_tree = nch_tree; a.Rbuf = Rbuf;
   // combines at this level: j = 0, 2h, 4h, ... with j + h < P
   const int64_t ncomb = (P - h + 2 * h - 1) / (2 * h);
-  return launch_qr_any(a, (int)ncomb, qr_lds_bytes(g, 8), st);
+  set_qr_batch(a, bt);
+  return launch_qr_any(a, (int)ncomb, qr_lds_bytes(g, 8), st, bt.count);
 }
 
 template <typename TO>
 static hipError_t launch_apply_t(const ApplyArgs<double, TO>& a, int grid, size_t lds,
-                                 hipStream_t st) {
-  if (grid <= 0) return hipSuccess;
+                                 hipStream_t st, int64_t gy = 1) {
+  if (grid <= 0 || gy <= 0) return hipSuccess;
+  if (gy > 65535) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute((const void*)k_stacked_apply<double, TO>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_stacked_apply<double, TO>), dim3(grid), dim3(256), lds, st, a);
+  hipLaunchKernelGGL((k_stacked_apply<double, TO>), dim3(grid, (unsigned)gy), dim3(256), lds, st,
+                     a);
   return hipGetLastError();
 }
 
 hipError_t launch_apply_leaf_f64(const QrGeom& g, int64_t m, int64_t b, int64_t P,
                                  const double* V, const double* Tleaf, int64_t nch_leaf,
                                  const double* W, int64_t ldw, const int64_t* nr, int64_t ncols,
-                                 void* U, int out_f64, int64_t ldu, hipStream_t st) {
+                                 void* U, int out_f64, int64_t ldu, hipStream_t st,
+                                 const Batch& bt) {
   const int ntiles = (int)((ncols + 15) / 16);
   const size_t lds = apply_lds_bytes(g, 8);
   if (P < 1) return hipErrorInvalidValue;
@@ -904,25 +950,29 @@ hipError_t launch_apply_leaf_f64(const QrGeom& g, int64_t m, int64_t b, int64_t 
     a.n = g.n; a.s = g.s; a.npanels = g.npanels; a.mode = 0; a.nr = nr; a.ncols = ncols;
     a.m = m; a.b = b; a.P = P; a.V = V; a.Tleaf = Tleaf; a.nch_leaf = nch_leaf;
     a.U = (double*)U; a.ldu = ldu; a.W = const_cast<double*>(W); a.ldw = ldw;
-    return launch_apply_t(a, (int)(P * ntiles), lds, st);
+    set_apply_batch(a, bt);
+    return launch_apply_t(a, (int)(P * ntiles), lds, st, bt.count);
   }
   ApplyArgs<double, float> a{};
   a.n = g.n; a.s = g.s; a.npanels = g.npanels; a.mode = 0; a.nr = nr; a.ncols = ncols;
   a.m = m; a.b = b; a.P = P; a.V = V; a.Tleaf = Tleaf; a.nch_leaf = nch_leaf;
   a.U = (float*)U; a.ldu = ldu; a.W = const_cast<double*>(W); a.ldw = ldw;
-  return launch_apply_t(a, (int)(P * ntiles), lds, st);
+  set_apply_batch(a, bt);
+  return launch_apply_t(a, (int)(P * ntiles), lds, st, bt.count);
 }
 
 hipError_t launch_apply_tree_f64(const QrGeom& g, int64_t h, int64_t P, const double* Rbuf,
                                  const double* Ttree, int64_t nch_tree, double* W, int64_t ldw,
-                                 const int64_t* nr, int64_t ncols, hipStream_t st) {
+                                 const int64_t* nr, int64_t ncols, hipStream_t st,
+                                 const Batch& bt) {
   const int ntiles = (int)((ncols + 15) / 16);
   const int64_t ncomb = (P - h + 2 * h - 1) / (2 * h);
   if (P < 2 || h < 1 || ncomb < 1) return hipErrorInvalidValue;
   ApplyArgs<double, double> a{};
   a.n = g.n; a.s = g.s; a.npanels = g.npanels; a.mode = 1; a.nr = nr; a.ncols = ncols;
   a.P = P; a.h = h; a.Rbuf = Rbuf; a.Ttree = Ttree; a.nch_tree = nch_tree; a.W = W; a.ldw = ldw;
-  return launch_apply_t(a, (int)(ncomb * ntiles), apply_lds_bytes(g, 8), st);
+  set_apply_batch(a, bt);
+  return launch_apply_t(a, (int)(ncomb * ntiles), apply_lds_bytes(g, 8), st, bt.count);
 }
 
 }  // namespace pylom

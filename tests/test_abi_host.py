@@ -161,3 +161,38 @@ def test_tree_plan_six_ranks_truth_table():
     # the 6-processor example: level 0 pairs (0,1),(2,3),(4,5); level 1 (0,2);
     # level 2 (0,4)
     assert api.tree_plan(6) == [(0, 0, 1), (0, 2, 3), (0, 4, 5), (1, 0, 2), (2, 0, 4)]
+
+
+def test_spod_query_and_validation(hctx):
+    nb, nf, ws = api.spod_query(262144, 2048, 256, 128, "c64", hctx)
+    assert (nb, nf) == (15, 129)          # floor((2048 - 128) / 128) blocks, npwin/2 + 1 bins
+    assert ws > 129 * 2 * 262144 * 30 * 4  # at least the realified FP32 spectra
+    assert api.spod_query(1000, 512, 64, 32, "c128", hctx)[:2] == (15, 33)
+    assert api.spod_query(1000, 100, 64, 0, "c64", hctx)[:2] == (1, 33)
+    lib, h = hctx.lib, hctx.h
+    nbv, nfv, wsv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+
+    def q(m=1000, nt=512, npwin=64, nolap=32, spectra=api.C64):
+        return lib.pylom_spod_query(h, spectra, m, nt, npwin, nolap, ctypes.byref(nbv),
+                                    ctypes.byref(nfv), ctypes.byref(wsv))
+    assert q() == 0
+    assert q(npwin=48) == -6               # not a power of two
+    assert q(npwin=8192) == -6
+    assert q(nolap=64) == -1               # overlap >= window
+    assert q(nolap=-1) == -1
+    assert q(nt=32) == -2                  # shorter than one window
+    assert q(nt=4096) == -6                # more than 16 blocks
+    assert q(m=10) == -2                   # fewer points than blocks
+    assert q(spectra=api.R64) == -3
+    vp = ctypes.c_void_p
+
+    def run(prec=api.FP64, D=1, dt=1.0, window=0, modes=1, L=1, ldd=512):
+        return lib.pylom_spod(h, api.C64, prec, 1000, 512, vp(D), ldd, dt, 64, 32, window, 1,
+                              vp(modes), vp(L), vp(0), vp(0))
+    assert run() == -7                     # valid: only the device is missing
+    assert run(prec=api.MIXED) == -6
+    assert run(D=0) == -1
+    assert run(modes=0) == -1
+    assert run(dt=0.0) == -1
+    assert run(window=3) == -1
+    assert run(ldd=100) == -2

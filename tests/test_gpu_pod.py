@@ -198,3 +198,19 @@ def test_max_sweeps_zero_reports_nonconvergence():
     rc, sweeps = ctx.status()
     assert rc == 1 and sweeps == -1
     ctx.close()
+
+
+def test_pod_exactly_repeated_columns_converges():
+    # columns repeated exactly make R geometrically graded (diagonal down to
+    # ~1e-100): the Jacobi rotation must stay representable and converge
+    say("[gpu] pod repeated columns 3000x24 r=0")
+    rng = np.random.default_rng(31)
+    x, y = rng.standard_normal(3000), rng.standard_normal(3000)
+    D = np.column_stack([x] * 12 + [y] * 12)
+    g = run_pod(D, False, 0.0, 1000)
+    assert g["rc"] == 0, g["rc"]
+    S = g["S"]
+    ref = np.linalg.svd(np.column_stack([x, y]) * np.sqrt(12.0), compute_uv=False)
+    np.testing.assert_allclose(S[:2], ref, rtol=1e-13)
+    assert np.all(S[2:] <= 1e-13 * S[0])
+    assert checks.orth_error(g["U"]) <= 1e-12
