@@ -85,7 +85,7 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
 /* Options (int64 values):
  *   "block_rows"   leaf row-block height b of the TSQR (Alg. 1's local D_i);
  *                  0 = automatic (default 4096, at least n).
- *   "max_sweeps"   Jacobi sweep limit (default 40).  0 makes every SVD call
+ *   "max_sweeps"   Jacobi sweep limit (default 60).  0 makes every SVD call
  *                  return PYLOM_WNOCONV without sweeping (failure-path tests).
  *   "ws_cap_mb"    workspace cap in MiB (0 = unlimited); a call needing more
  *                  returns PYLOM_ENOMEM.

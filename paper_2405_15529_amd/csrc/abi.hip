@@ -25,7 +25,7 @@ struct pylom_ctx_s {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   int64_t block_rows = 0;
-  int64_t max_sweeps = 40;
+  int64_t max_sweeps = 60;
   int64_t ws_cap_mb = 0;
   int* status_dev = nullptr;  // Jacobi status pairs (sweeps, barrier timeout) of the last call
   int status_valid = 0;

@@ -147,6 +147,32 @@ __device__ __forceinline__ double perm32_pairsum(double x) {
   const double b = __longlong_as_double(((long long)hi[1] << 32) | (unsigned int)lo[1]);
   return a + b;
 }
+// Pair maxima over the same row pairings (the two outputs of a swap are the
+// lane's own value and its partner's).
+__device__ __forceinline__ double perm16_pairmax(double x) {
+  const long long v = __double_as_longlong(x);
+  const auto lo = __builtin_amdgcn_permlane16_swap((int)(v & 0xffffffffll), (int)(v & 0xffffffffll), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((int)(v >> 32), (int)(v >> 32), false, false);
+  const double a = __longlong_as_double(((long long)hi[0] << 32) | (unsigned int)lo[0]);
+  const double b = __longlong_as_double(((long long)hi[1] << 32) | (unsigned int)lo[1]);
+  return fmax(a, b);
+}
+__device__ __forceinline__ double perm32_pairmax(double x) {
+  const long long v = __double_as_longlong(x);
+  const auto lo = __builtin_amdgcn_permlane32_swap((int)(v & 0xffffffffll), (int)(v & 0xffffffffll), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((int)(v >> 32), (int)(v >> 32), false, false);
+  const double a = __longlong_as_double(((long long)hi[0] << 32) | (unsigned int)lo[0]);
+  const double b = __longlong_as_double(((long long)hi[1] << 32) | (unsigned int)lo[1]);
+  return fmax(a, b);
+}
+__device__ __forceinline__ float perm16_pairmax(float x) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(x), __float_as_int(x), false, false);
+  return fmaxf(__int_as_float(r[0]), __int_as_float(r[1]));
+}
+__device__ __forceinline__ float perm32_pairmax(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(x), __float_as_int(x), false, false);
+  return fmaxf(__int_as_float(r[0]), __int_as_float(r[1]));
+}
 __device__ __forceinline__ float perm16_pairsum(float x) {
   const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(x), __float_as_int(x), false, false);
   return __int_as_float(r[0]) + __int_as_float(r[1]);

@@ -105,6 +105,7 @@ __global__ void k_jacobi_setup(int n, int npad, const double* __restrict__ R, do
     for (int k = threadIdx.x; k < nflags; k += blockDim.x) flags[k] = 0;
     if (threadIdx.x == 0) {
       *bar = 0u;
+      *reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(bar) + 64) = 0ull;
       status[0] = status0;
       status[1] = 0;
     }
@@ -266,6 +267,41 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
   unsigned int epoch = 0;
   double ca[JRPL], cva[JRPL], cb[JRPL], cvb[JRPL];
   int sweep_done = -1;
+  // Deflation: columns of R^T (rows of R) whose norm is at most 2^-53 times
+  // the largest are rounding noise (rank-deficient input leaves them graded
+  // down to the underflow range, where Jacobi would spend dozens of sweeps
+  // orthogonalising them); they are set to zero, a perturbation of R within
+  // the QR's own backward error.  The maximum is combined with an atomic max
+  // on the bit pattern (non-negative doubles order like integers), which
+  // does not depend on the order of arrival.
+  {
+    unsigned long long* cmax =
+        reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(a.bar) + 64);
+    const int blk0 = rr_player(g, 0, nplayers), blk1 = rr_player(nplayers - 1 - g, 0, nplayers);
+    double nr2[2];
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      const int jc = (hb ? blk1 : blk0) * w + grp;
+      load_col<LPP>(ca, a.A + (int64_t)jc * n, n, sub);
+      nr2[hb] = col_norm2<LPP>(ca, rpl);
+    }
+    if (sub == 0)
+      atomicMax(cmax, (unsigned long long)__double_as_longlong(nr2[0] > nr2[1] ? nr2[0] : nr2[1]));
+    grid_barrier(a.bar, (unsigned int)a.G, epoch, a.status);
+    const double mx = __longlong_as_double(
+        (long long)__hip_atomic_load(cmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const double thr2 = mx * 0x1p-106;
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      if (nr2[hb] > 0.0 && nr2[hb] <= thr2) {
+        const int jc = (hb ? blk1 : blk0) * w + grp;
+#pragma unroll
+        for (int k = 0; k < JRPL; ++k) ca[k] = 0.0;
+        store_col<LPP>(ca, a.A + (int64_t)jc * n, n, sub);
+      }
+    }
+    __syncthreads();
+  }
   for (int sw = 0; sw < a.max_sweeps; ++sw) {
     if (tid == 0) rot_count = 0;
     __syncthreads();

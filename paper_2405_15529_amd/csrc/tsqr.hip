@@ -73,6 +73,22 @@ size_t apply_lds_bytes(const QrGeom& g, int esize) {
 // ---------------------------------------------------------------------------
 // kernel arguments
 // ---------------------------------------------------------------------------
+// Thresholds below which a Householder column is renormalised with an exact
+// power-of-two scale before its norm is formed (x2: squared tail norm; root:
+// |head|; max_exp: the largest scale exponent that is representable).
+template <typename T>
+struct Tiny;
+template <>
+struct Tiny<double> {
+  static constexpr double x2 = 0x1p-960, root = 0x1p-480;
+  static constexpr int max_exp = 1022;  // largest representable scale 2^k
+};
+template <>
+struct Tiny<float> {
+  static constexpr float x2 = 0x1p-100f, root = 0x1p-50f;
+  static constexpr int max_exp = 126;
+};
+
 template <typename T, typename TI>
 struct QrArgs {
   int n, s, ldc, npanels;
@@ -153,17 +169,53 @@ __device__ __forceinline__ void factor_panel(T* __restrict__ C, int ldc, T* __re
       if (!INTERNAL || r > h) x2 += p[t] * p[t];
     }
     x2 = perm32_pairsum(perm16_pairsum(x2));
-    const T sig = readlane(x2, kk);
+    T sig = readlane(x2, kk);
     T tau, beta, scal;
+    T sc = T(1);  // power-of-two rescaling of a tiny column (exact)
+    if (sig < Tiny<T>::x2 && fabs(alpha) < Tiny<T>::root) {
+      // both the head and the tail are tiny (rank-deficient input leaves
+      // columns of rounding noise that shrink geometrically): squares in
+      // the subnormal range keep few significant bits and tau would no
+      // longer match v, so the column is scaled by the power of two that
+      // brings max(|alpha|, |x|) into [0.5, 1) before its norm is formed
+      // (as LAPACK's reflector generator does).  Wave-uniform branch: sig
+      // and alpha are broadcast values.
+      T amax = T(0);
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int r = g + 4 * t;
+        if (!INTERNAL || r > h) amax = fmax(amax, fabs(p[t]));
+      }
+      amax = perm32_pairmax(perm16_pairmax(amax));
+      amax = fmax(readlane(amax, kk), fabs(alpha));
+      if (amax > T(0)) {
+        int e;
+        frexp(amax, &e);  // amax = f 2^e, f in [0.5, 1)
+        sc = ldexp(T(1), (-e < Tiny<T>::max_exp) ? -e : Tiny<T>::max_exp);
+      }
+      T xs2 = T(0);
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int r = g + 4 * t;
+        const T xs = p[t] * sc;
+        if (!INTERNAL || r > h) xs2 += xs * xs;
+      }
+      xs2 = perm32_pairsum(perm16_pairsum(xs2));
+      sig = readlane(xs2, kk);
+    }
     if (sig == T(0)) {
       tau = T(0);
       beta = alpha;
       scal = T(0);
     } else {
-      const T nrm = sqrt(alpha * alpha + sig);
-      beta = (alpha >= T(0)) ? -nrm : nrm;
-      tau = (beta - alpha) / beta;
-      scal = T(1) / (alpha - beta);
+      // scaled head as and norm nrm >= max(|as|, |x sc|): v = (x sc) / (as - bs)
+      // has entries of magnitude <= 1, whatever the scale
+      const T as = alpha * sc;
+      const T nrm = sqrt(as * as + sig);
+      const T bs = (as >= T(0)) ? -nrm : nrm;
+      tau = (bs - as) / bs;
+      scal = T(1) / (as - bs);
+      beta = bs / sc;
     }
     // reflector of column kk: exact values to vb, stored values back into p
     if (j == kk) {
@@ -172,10 +224,10 @@ __device__ __forceinline__ void factor_panel(T* __restrict__ C, int ldc, T* __re
         const int r = g + 4 * t;
         T vx;
         if (INTERNAL) {
-          vx = (r < h) ? T(0) : ((r == h) ? T(1) : p[t] * scal);
+          vx = (r < h) ? T(0) : ((r == h) ? T(1) : (p[t] * sc) * scal);
           p[t] = (r == h) ? beta : ((r > h) ? vx : p[t]);
         } else {
-          vx = p[t] * scal;
+          vx = (p[t] * sc) * scal;
           p[t] = vx;
         }
         vb[g * RT + t] = vx;
