@@ -84,11 +84,13 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
 
 /* Options (int64 values):
  *   "block_rows"   leaf row-block height b of the TSQR (Alg. 1's local D_i);
- *                  0 = automatic (default 4096, at least n).
+ *                  0 = automatic (pylom_tune_block_rows; at least n).
  *   "max_sweeps"   Jacobi sweep limit (default 60).  0 makes every SVD call
  *                  return PYLOM_WNOCONV without sweeping (failure-path tests).
  *   "ws_cap_mb"    workspace cap in MiB (0 = unlimited); a call needing more
  *                  returns PYLOM_ENOMEM.
+ *   "streams"      concurrent HIP streams of pylom_pod_batched (1..16,
+ *                  default 4).
  *   "timing"       k > 0: record HIP events around the phases of every
  *                  pod/tsvd call in a ring of k call slots (read back with
  *                  pylom_phase_times); 0 = off (default).
@@ -161,6 +163,46 @@ int pylom_tsqr(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t m, int
 int pylom_matmul(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int trans_a, int64_t m,
                  int64_t p, int64_t q, const void* A, int64_t lda, const void* B, int64_t ldb,
                  void* C, int64_t ldc);
+
+/* One instance of a batched POD (the arguments of pylom_pod). */
+typedef struct {
+  int64_t m, n;        /* shape, m >= n >= 1, n <= 1024                      */
+  const void* D;       /* m x n snapshots (storage type of the batch), ldd   */
+  int64_t ldd;
+  int remove_mean;     /* Alg. 2 mean removal                                 */
+  double residual;     /* truncation residual r in [0, 1)                     */
+  void* mean;          /* m entries of the storage type, or NULL              */
+  void* U;             /* m x n capacity, ldu >= n                            */
+  int64_t ldu;
+  double* S;           /* n                                                   */
+  double* VT;          /* n x n capacity, ldvt >= n                           */
+  int64_t ldvt;
+  int64_t* n_r;        /* one int64 (device)                                  */
+} pylom_problem;
+
+/* A batch of POD instances of uneven shapes (Alg. 2 + Alg. 1 + Eqs. svdqr1-3
+ * for each), with the same dtype and precision.  `problems` is a host array
+ * of `count` descriptors; every pointer inside is a device pointer, as for
+ * pylom_pod, and the results are those of `count` pylom_pod calls.
+ * Each instance's leaf height is the "block_rows" option when set, else the
+ * library's autotuned choice (see pylom_tune_block_rows).  Instances are
+ * spread over "streams" (option, default 4) concurrent HIP streams with
+ * workspaces of their own, forked from and joined back into the context
+ * stream.  use_graph != 0 captures the whole launch sequence into a HIP graph
+ * on the first call with a given problem list (pointers and shapes) and
+ * replays it on later calls (no per-kernel launch cost); PYLOM_MIXED batches
+ * run as two graphs around one host read-back of every instance's N0.
+ * All validation happens before any launch; PYLOM_WNOCONV is reported by
+ * pylom_check if any instance's Jacobi SVD did not converge. */
+int pylom_pod_batched(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t count,
+                      const pylom_problem* problems, int use_graph);
+
+/* The leaf height b chosen for an m x n problem when "block_rows" is 0: the
+ * minimiser, over b in {128, 256, ..., 32768} with b >= n, of a latency model
+ * of the stacked QR (leaf critical path of ceil(b / s) chunks, waves of leaves
+ * over the device's compute units, ceil(log2 P) dependent tree levels and one
+ * launch per level).  Host only. */
+int64_t pylom_tune_block_rows(pylom_ctx ctx, int64_t m, int64_t n);
 
 /* SPOD (Alg. 6; Sec. 2.3, Eq. csdimp with the SVD of the spectral matrix).
  *

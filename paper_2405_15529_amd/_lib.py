@@ -46,7 +46,16 @@ SIGNATURES = {
                                   I64, I64, ctypes.c_int, ctypes.c_int, VP, VP, VP, VP]),
     "pylom_spod_query": (ctypes.c_int, [VP, ctypes.c_int, I64, I64, I64, I64, I64P, I64P,
                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "pylom_pod_batched": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int, I64, VP, ctypes.c_int]),
+    "pylom_tune_block_rows": (I64, [VP, I64, I64]),
 }
+
+
+class Problem(ctypes.Structure):
+    """Mirror of pylom_problem (include/pylom.h)."""
+    _fields_ = [("m", I64), ("n", I64), ("D", VP), ("ldd", I64), ("remove_mean", ctypes.c_int),
+                ("residual", ctypes.c_double), ("mean", VP), ("U", VP), ("ldu", I64),
+                ("S", VP), ("VT", VP), ("ldvt", I64), ("n_r", VP)]
 
 _lib = None
 

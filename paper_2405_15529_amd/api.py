@@ -280,3 +280,67 @@ def spod(D: torch.Tensor, dt: float = 1.0, npwin: int = 256, nolap: int = 128,
                             _ptr(f), _ptr(order))
     ctx.check(rc)
     return SpodResult(modes=modes, L=L, f=f, order=order)
+
+
+def tune_block_rows(m: int, n: int, ctx: Context | None = None) -> int:
+    """The leaf height the library picks for an m x n problem (host-side model)."""
+    ctx = ctx or Context(-1)
+    b = ctx.lib.pylom_tune_block_rows(ctx.h, m, n)
+    if b < 0:
+        raise PylomError(int(b), "tune_block_rows")
+    return int(b)
+
+
+class PodBatch:
+    """A batch of POD instances of uneven shapes run by one pylom_pod_batched
+    call.  Outputs are allocated once, so that with use_graph the captured
+    launch sequence is replayed by every later run()."""
+
+    def __init__(self, Ds, remove_mean=False, r: float = 0.01, precision: str = "fp64",
+                 use_graph: bool = True, ctx: Context | None = None):
+        if not Ds:
+            raise ValueError("empty batch")
+        dt = Ds[0].dtype
+        for D in Ds:
+            _rowmajor(D, "D")
+            if D.dtype != dt or not D.is_cuda:
+                raise ValueError("all instances must be GPU tensors of one dtype")
+        self.ctx = ctx or context(Ds[0].device.index)
+        self.precision = precision
+        self.use_graph = bool(use_graph)
+        self.dtype = _dtype_code(Ds[0])
+        rms = remove_mean if isinstance(remove_mean, (list, tuple)) else [remove_mean] * len(Ds)
+        rs = r if isinstance(r, (list, tuple)) else [r] * len(Ds)
+        self.Ds = list(Ds)
+        self.out = []
+        arr = (_lib.Problem * len(Ds))()
+        for i, D in enumerate(Ds):
+            m, n = D.shape
+            dev = D.device
+            o = dict(U=torch.empty((m, n), dtype=dt, device=dev),
+                     S=torch.empty(n, dtype=torch.float64, device=dev),
+                     VT=torch.empty((n, n), dtype=torch.float64, device=dev),
+                     nr=torch.empty(1, dtype=torch.int64, device=dev),
+                     mean=torch.empty(m, dtype=dt, device=dev) if rms[i] else None)
+            self.out.append(o)
+            arr[i] = _lib.Problem(m, n, D.data_ptr(), D.stride(0), int(bool(rms[i])), float(rs[i]),
+                                  o["mean"].data_ptr() if o["mean"] is not None else 0,
+                                  o["U"].data_ptr(), n, o["S"].data_ptr(), o["VT"].data_ptr(), n,
+                                  o["nr"].data_ptr())
+        self.arr = arr
+
+    def run(self):
+        self.ctx.bind_stream()
+        rc = self.ctx.lib.pylom_pod_batched(self.ctx.h, self.dtype, _PREC[self.precision],
+                                            len(self.Ds), ctypes.cast(self.arr, ctypes.c_void_p),
+                                            int(self.use_graph))
+        self.ctx.check(rc)
+        return self
+
+    def results(self):
+        res = []
+        for o in self.out:
+            k = int(o["nr"].item())
+            res.append(PodResult(U=o["U"][:, :k], S=o["S"], VT=o["VT"][:k], mean=o["mean"], nr=k,
+                                 U_full=o["U"], VT_full=o["VT"]))
+        return res

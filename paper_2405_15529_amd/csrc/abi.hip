@@ -9,9 +9,12 @@
 //   leaf apply U_i = Q_1i W_i               Eq. svdqr3 / Q_i = Q_1i Q_w
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/pylom.h"
@@ -31,10 +34,25 @@ struct pylom_ctx_s {
   int status_valid = 0;
   int status_pairs = 1;        // 2 after a mixed-precision call (SVD of R + Gram eigen)
   int64_t timing = 0;         // number of per-call event slots (0 = off)
-  std::vector<hipEvent_t> ev;  // timing x 6 events
+  std::vector<hipEvent_t> ev;  // timing x kEvPerSlot events
+  std::vector<char> ev_mixed;  // per slot: recorded by a mixed-precision call
   int64_t ev_calls = 0;        // timed calls since the last read
   std::string last_error;
+  // batched execution
+  int ncu = 256;                 // compute units of the device
+  int64_t streams = 4;           // concurrent streams of pylom_pod_batched
+  std::vector<hipStream_t> lanes;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  hipStream_t cap = nullptr;     // origin stream of graph capture and replay
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::unordered_map<uint64_t, hipGraphExec_t> graphs;  // captured batches
 };
+
+static void drop_graphs(pylom_ctx c) {
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
 
 static int fail(pylom_ctx c, int code, const char* msg) {
   if (c) c->last_error = msg;
@@ -56,7 +74,7 @@ static int hip_fail(pylom_ctx c, hipError_t e, const char* where) {
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-constexpr int kEvPerSlot = 7;  // timing events recorded per call
+constexpr int kEvPerSlot = 8;  // timing events recorded per call
 constexpr int kPhases = 6;     // phases reported by pylom_phase_times
 
 // ---------------------------------------------------------------------------
@@ -87,6 +105,7 @@ extern "C" int pylom_create(pylom_ctx* out, int device) {
       return PYLOM_ENOMEM;
     }
     c->device = device;
+    if (prop.multiProcessorCount > 0) c->ncu = prop.multiProcessorCount;
   }
   *out = c;
   return PYLOM_OK;
@@ -97,6 +116,13 @@ extern "C" int pylom_destroy(pylom_ctx c) {
   if (c->device >= 0) {
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    for (hipStream_t q : c->lanes) hipStreamDestroy(q);
+    for (hipEvent_t e : c->ev_join) hipEventDestroy(e);
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->ev_in) hipEventDestroy(c->ev_in);
+    if (c->ev_out) hipEventDestroy(c->ev_out);
+    if (c->cap) hipStreamDestroy(c->cap);
     if (c->ws) hipFree(c->ws);
     if (c->status_dev) hipFree(c->status_dev);
     for (hipEvent_t e : c->ev)
@@ -123,6 +149,9 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
   } else if (!std::strcmp(key, "ws_cap_mb")) {
     if (v < 0) return fail(c, PYLOM_EINVAL, "ws_cap_mb must be >= 0");
     c->ws_cap_mb = v;
+  } else if (!std::strcmp(key, "streams")) {
+    if (v < 1 || v > 16) return fail(c, PYLOM_EINVAL, "streams must be in [1, 16]");
+    c->streams = v;
   } else if (!std::strcmp(key, "timing")) {
     if (v < 0 || v > 4096) return fail(c, PYLOM_EINVAL, "timing must be in [0, 4096]");
     if (c->device >= 0) {
@@ -131,6 +160,7 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
       for (hipEvent_t e : c->ev)
         if (e) hipEventDestroy(e);
       c->ev.assign((size_t)v * kEvPerSlot, nullptr);
+      c->ev_mixed.assign((size_t)v, 0);
       for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) return fail(c, PYLOM_EHIP, "hipEventCreate");
     }
@@ -152,6 +182,8 @@ extern "C" int pylom_get_option(pylom_ctx c, const char* key, int64_t* v) {
     *v = c->ws_cap_mb;
   else if (!std::strcmp(key, "timing"))
     *v = c->timing;
+  else if (!std::strcmp(key, "streams"))
+    *v = c->streams;
   else
     return fail(c, PYLOM_EINVAL, "unknown option");
   return PYLOM_OK;
@@ -183,6 +215,9 @@ static int ensure_ws(pylom_ctx c, size_t bytes) {
   if (bytes <= c->ws_bytes) return PYLOM_OK;
   if (c->ws) {
     hipStreamSynchronize(c->stream);
+    for (hipStream_t q : c->lanes) hipStreamSynchronize(q);
+    if (c->cap) hipStreamSynchronize(c->cap);
+    drop_graphs(c);  // captured graphs point into the old workspace
     hipFree(c->ws);
     c->ws = nullptr;
     c->ws_bytes = 0;
@@ -218,6 +253,47 @@ struct Plan {
   size_t part_bytes;
 };
 
+// Leaf height model.  The stacked QR of a leaf is a chain of ceil(b / s)
+// chunks; each chunk factors n columns one after another (about 1.6k cycles
+// of latency per column on one wave) plus one look-ahead tile per panel
+// (about 5k cycles).  Leaves run one workgroup per CU, in waves over the
+// device; the tree adds ceil(log2 P) dependent levels of about half a chunk
+// chain each for ceil(n / s) chunks, and every launch costs about 20k cycles.
+static double leaf_model(int64_t m, int64_t n, int64_t b, int ncu) {
+  QrGeom g;
+  if (!qr_geom((int)n, 8, &g)) return 1e300;
+  const double c_col = 1600.0, c_tile = 5000.0, c_launch = 20000.0;
+  const double chain = (double)n * c_col + (double)g.npanels * c_tile;
+  int64_t P = m / b;
+  if (P < 1) P = 1;
+  const int64_t last = m - (P - 1) * b;
+  const double waves = std::ceil((double)P / (double)ncu);
+  const double t_leaf = waves * std::ceil((double)last / g.s) * chain + c_launch;
+  int64_t lv = 0;
+  for (int64_t h = 1; h < P; h *= 2) ++lv;
+  const double t_tree = (double)lv * (std::ceil((double)n / g.s) * chain * 0.5 + c_launch);
+  return t_leaf + t_tree;
+}
+
+static int64_t tune_block_rows(int64_t m, int64_t n, int ncu) {
+  int64_t best = 0;
+  double tbest = 0.0;
+  for (int64_t b = 128; b <= 32768; b *= 2) {
+    if (b < n) continue;
+    const double t = leaf_model(m, n, b, ncu);
+    if (best == 0 || t < tbest) {
+      best = b;
+      tbest = t;
+    }
+  }
+  return best > 0 ? best : n;
+}
+
+extern "C" int64_t pylom_tune_block_rows(pylom_ctx c, int64_t m, int64_t n) {
+  if (!c || n < 1 || m < n || n > 1024) return PYLOM_EINVAL;
+  return tune_block_rows(m, n, c->ncu);
+}
+
 static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
                      bool mixed = false) {
   if (n < 1 || m < n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
@@ -226,7 +302,7 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
   if (mixed) store_q = false;
   p->m = m;
   p->n = n;
-  int64_t b = c->block_rows > 0 ? c->block_rows : 4096;
+  int64_t b = c->block_rows > 0 ? c->block_rows : tune_block_rows(m, n, c->ncu);
   if (b < n) b = n;
   int64_t P = m / b;
   if (P < 1) P = 1;
@@ -354,10 +430,181 @@ static int check_common(pylom_ctx c, pylom_dtype dtype, pylom_prec prec) {
   return PYLOM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// launch sequences, parameterised by stream / workspace / status so that the
+// single-problem calls and the batched call share them
+// ---------------------------------------------------------------------------
+struct Exec {
+  hipStream_t st;
+  char* ws;             // this problem's workspace (Plan offsets)
+  int* status;          // Jacobi status pair(s) of this problem (2 or 4 ints)
+  bool coop;            // cooperative launch for the multi-workgroup Jacobi
+  int max_sweeps;
+  hipEvent_t* evs;      // timing events (kEvPerSlot) or nullptr
+  int64_t* nr0;         // mixed precision: where N0 goes (nullptr: the workspace)
+  char* keep;           // mixed precision: S0, VT0 and the mean, kept from phase 1 to
+                        // phase 2 (nullptr: the workspace); layout keep_bytes()
+};
+
+// Phase-1 results of the mixed path that phase 2 reads: S0 (n), VT0 (n x n),
+// mean (m), each 256-byte aligned.
+static size_t keep_bytes(int64_t m, int64_t n) {
+  return align_up(8 * (size_t)n) + align_up(8 * (size_t)n * n) + align_up(8 * (size_t)m);
+}
+static double* keep_S0(const Exec& x, const Plan& p) {
+  return x.keep ? (double*)x.keep : (double*)(x.ws + p.oS0);
+}
+static double* keep_VT0(const Exec& x, const Plan& p) {
+  return x.keep ? (double*)(x.keep + align_up(8 * (size_t)p.n)) : (double*)(x.ws + p.oVT0);
+}
+static double* keep_mean(const Exec& x, const Plan& p) {
+  return x.keep ? (double*)(x.keep + align_up(8 * (size_t)p.n) + align_up(8 * (size_t)p.n * p.n))
+                : (double*)(x.ws + p.oMean);
+}
+
+#define EVREC(j) \
+  if (x.evs) HIPCHK(c, hipEventRecord(x.evs[j], x.st), "hipEventRecord")
+
+// FP64 POD / TSVD: Alg. 2 (mean) -> Alg. 1 (leaf QR, tree) -> Eq. svdqr2 ->
+// propagation -> Eq. svdqr3.
+static int enqueue_fp64(pylom_ctx c, const Exec& x, const Plan& p, pylom_dtype dtype,
+                        const void* D, int64_t ldd, int remove_mean, double residual, void* mean,
+                        void* U, int64_t ldu, double* S, double* VT, int64_t ldvt, int64_t* n_r) {
+  const int64_t m = p.m, n = p.n;
+  double* V = (double*)(x.ws + p.oV);
+  double* Tleaf = (double*)(x.ws + p.oTleaf);
+  double* Rbuf = (double*)(x.ws + p.oR);
+  double* Ttree = (double*)(x.ws + p.oTtree);
+  double* W = (double*)(x.ws + p.oW);
+  double* meanws = (double*)(x.ws + p.oMean);
+  const int in64 = dtype == PYLOM_R64;
+  hipStream_t st = x.st;
+  EVREC(0);
+  EVREC(1);
+  HIPCHK(c, launch_leaf_qr_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws, V, Tleaf,
+                               p.nch_leaf, Rbuf, st), "leaf QR");
+  EVREC(2);
+  for (int64_t h = 1; h < p.P; h *= 2)
+    HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, 1, st), "tree combine");
+  EVREC(3);
+  HIPCHK(c, launch_small_svd(p.jp, Rbuf, x.max_sweeps, x.ws + p.oSvd, S, VT, ldvt, W, residual,
+                             n_r, x.status, st, x.coop), "small SVD");
+  EVREC(4);
+  int64_t top = 1;
+  while (top * 2 < p.P) top *= 2;
+  if (p.P > 1)
+    for (int64_t h = top; h >= 1; h /= 2)
+      HIPCHK(c, launch_apply_tree_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, W, n, n_r, n, st),
+             "tree propagation");
+  EVREC(5);
+  HIPCHK(c, launch_apply_leaf_f64(p.g, m, p.b, p.P, V, Tleaf, p.nch_leaf, W, n, n_r, n, U, in64,
+                                  ldu, st), "leaf apply");
+  if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, in64, m, st), "mean out");
+  EVREC(6);
+  return PYLOM_OK;
+}
+
+// Mixed precision, phase 1: FP32 leaf QR (R only, mean fused), FP64 tree and
+// SVD of R: S0, VT0 and N0 in the workspace.
+static int enqueue_mixed1(pylom_ctx c, const Exec& x, const Plan& p, const void* D, int64_t ldd,
+                          int remove_mean, double residual) {
+  const int64_t m = p.m, n = p.n;
+  hipStream_t st = x.st;
+  EVREC(0);
+  EVREC(1);
+  HIPCHK(c, launch_leaf_qr_f32(p.g, (const float*)D, ldd, m, p.b, p.P, remove_mean,
+                               keep_mean(x, p), (float*)(x.ws + p.oR32), st),
+         "leaf QR (FP32)");
+  HIPCHK(c, launch_cast_f32_f64((const float*)(x.ws + p.oR32), (double*)(x.ws + p.oR), p.P * n * n,
+                                st), "R to FP64");
+  EVREC(2);
+  for (int64_t h = 1; h < p.P; h *= 2)
+    HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, (double*)(x.ws + p.oR), nullptr, p.nch_tree, 0,
+                                      st), "tree combine");
+  EVREC(3);
+  HIPCHK(c, launch_small_svd(p.jp, (double*)(x.ws + p.oR), x.max_sweeps, x.ws + p.oSvd,
+                             keep_S0(x, p), keep_VT0(x, p), n,
+                             (double*)(x.ws + p.oW), residual,
+                             x.nr0 ? x.nr0 : (int64_t*)(x.ws + p.oNr0), x.status, st, x.coop),
+         "small SVD");
+  // end of the first SVD (the host read-back of N0 follows)
+  if (x.evs) HIPCHK(c, hipEventRecord(x.evs[7], st), "hipEventRecord");
+  return PYLOM_OK;
+}
+
+static int64_t refine_width(int64_t nr0, int64_t n) {
+  int64_t over = nr0 / 4;
+  if (over < 8) over = 8;
+  return (nr0 + over < n) ? nr0 + over : n;
+}
+
+// Mixed precision, phase 2 (after the host has read N0): Rayleigh-Ritz
+// refinement on the k = refine_width(N0) leading right singular vectors.
+static int enqueue_mixed2(pylom_ctx c, const Exec& x, const Plan& p, const void* D, int64_t ldd,
+                          int remove_mean, double residual, void* mean, void* U, int64_t ldu,
+                          double* S, double* VT, int64_t ldvt, int64_t* n_r, int64_t nr_first) {
+  const int64_t m = p.m, n = p.n;
+  hipStream_t st = x.st;
+  double* S0 = keep_S0(x, p);
+  double* meanws = keep_mean(x, p);
+  EVREC(4);
+  if (nr_first <= 0) {
+    // all-zero spectrum: nothing to refine, no mode is kept
+    HIPCHK(c, hipMemcpyAsync(S, S0, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st),
+           "S copy");
+    HIPCHK(c, launch_set_i64(n_r, 0, st), "N_r");
+    // no second SVD: its status pair reads (0 sweeps, no timeout)
+    HIPCHK(c, launch_set_i64(reinterpret_cast<int64_t*>(x.status + 2), 0, st), "status");
+    EVREC(5);
+  } else {
+    const int64_t k = refine_width(nr_first, n);
+    JacobiPlan jk;
+    if (!jacobi_plan((int)k, &jk)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
+    const int64_t ns = matmul_tn_splits(m, k, k);
+    if (sizeof(double) * (size_t)ns * k * k > p.part_bytes)
+      return fail(c, PYLOM_ENOTSUP, "Gram partials exceed the planned workspace");
+    double* Z = (double*)(x.ws + p.oZ);
+    double* G = (double*)(x.ws + p.oG);
+    double* lam = (double*)(x.ws + p.oLam);
+    double* WT = (double*)(x.ws + p.oWT);
+    double* M = (double*)(x.ws + p.oM);
+    const double* VT0 = keep_VT0(x, p);
+    HIPCHK(c, launch_rr_project(0, m, (int)n, (int)k, D, ldd, remove_mean ? meanws : nullptr, VT0,
+                                Z, st), "Rayleigh-Ritz projection");
+    HIPCHK(c, launch_matmul_tn(1, m, k, k, Z, k, Z, k, G, k, (double*)(x.ws + p.oPart), ns, st),
+           "Gram");
+    HIPCHK(c, launch_small_svd(jk, G, x.max_sweeps, x.ws + p.oSvd2, lam, WT, k,
+                               (double*)(x.ws + p.oUR2), 0.0, (int64_t*)(x.ws + p.oNr2),
+                               x.status + 2, st, x.coop), "Gram eigen-decomposition");
+    HIPCHK(c, launch_rr_finish((int)n, (int)k, S0, lam, residual, S, n_r, WT, VT0, VT, ldvt, M,
+                               st), "refined spectrum");
+    EVREC(5);
+    HIPCHK(c, launch_rr_form_u(0, m, (int)k, Z, M, n_r, U, ldu, st), "form U");
+  }
+  if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, 0, m, st), "mean out");
+  EVREC(6);
+  return PYLOM_OK;
+}
+#undef EVREC
+
+static Exec ctx_exec(pylom_ctx c) {
+  Exec x;
+  x.st = c->stream;
+  x.ws = (char*)c->ws;
+  x.status = c->status_dev;
+  x.coop = true;
+  x.max_sweeps = (int)c->max_sweeps;
+  const bool tm = c->timing > 0 && !c->ev.empty();
+  x.evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * kEvPerSlot] : nullptr;
+  x.nr0 = nullptr;
+  x.keep = nullptr;
+  return x;
+}
+
 // Mixed precision (FP32 storage): FP32 leaf QR (R only), FP64 tree and SVD of
 // R, then the Rayleigh-Ritz refinement against the input on the k leading
-// right singular vectors, k = N_r0 + max(8, N_r0 / 4) (at most n).  The host
-// reads N_r0 once (one stream synchronisation) to size the refinement.
+// right singular vectors.  The host reads N0 once (one stream
+// synchronisation) to size the refinement.
 static int run_mixed(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, const void* D,
                      int64_t ldd, int remove_mean, double residual, void* mean, void* U,
                      int64_t ldu, double* S, double* VT, int64_t ldvt, int64_t* n_r) {
@@ -369,77 +616,21 @@ static int run_mixed(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, const
   HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
   rc = ensure_ws(c, p.total);
   if (rc) return rc;
-  char* ws = (char*)c->ws;
-  double* Rbuf = (double*)(ws + p.oR);
-  float* R32 = (float*)(ws + p.oR32);
-  double* meanws = (double*)(ws + p.oMean);
-  double* S0 = (double*)(ws + p.oS0);
-  double* VT0 = (double*)(ws + p.oVT0);
-  double* UR0 = (double*)(ws + p.oW);
-  int64_t* nr0 = (int64_t*)(ws + p.oNr0);
-  double* Z = (double*)(ws + p.oZ);
-  double* G = (double*)(ws + p.oG);
-  double* part = (double*)(ws + p.oPart);
-  double* lam = (double*)(ws + p.oLam);
-  double* WT = (double*)(ws + p.oWT);
-  double* UR2 = (double*)(ws + p.oUR2);
-  int64_t* nr2 = (int64_t*)(ws + p.oNr2);
-  double* M = (double*)(ws + p.oM);
-  hipStream_t st = c->stream;
-  const bool tm = c->timing > 0 && !c->ev.empty();
-  hipEvent_t* evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * kEvPerSlot] : nullptr;
-#define EVREC(j) \
-  if (tm) HIPCHK(c, hipEventRecord(evs[j], st), "hipEventRecord")
-
-  EVREC(0);
-  EVREC(1);
-  HIPCHK(c, launch_leaf_qr_f32(p.g, (const float*)D, ldd, m, p.b, p.P, remove_mean, meanws, R32,
-                               st), "leaf QR (FP32)");
-  HIPCHK(c, launch_cast_f32_f64(R32, Rbuf, p.P * n * n, st), "R to FP64");
-  EVREC(2);
-  for (int64_t h = 1; h < p.P; h *= 2)
-    HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, Rbuf, nullptr, p.nch_tree, 0, st),
-           "tree combine");
-  EVREC(3);
-  HIPCHK(c, launch_small_svd(p.jp, Rbuf, (int)c->max_sweeps, ws + p.oSvd, S0, VT0, n, UR0,
-                             residual, nr0, c->status_dev, st), "small SVD");
+  const Exec x = ctx_exec(c);
+  if (x.evs) c->ev_mixed[(size_t)(c->ev_calls % c->timing)] = 1;
+  rc = enqueue_mixed1(c, x, p, D, ldd, remove_mean, residual);
+  if (rc) return rc;
   c->status_valid = 1;
   c->status_pairs = 1;
   int64_t nr_first = 0;
-  HIPCHK(c, hipMemcpyAsync(&nr_first, nr0, sizeof(int64_t), hipMemcpyDeviceToHost, st),
+  HIPCHK(c, hipMemcpyAsync(&nr_first, x.ws + p.oNr0, sizeof(int64_t), hipMemcpyDeviceToHost, x.st),
          "N_r read-back");
-  HIPCHK(c, hipStreamSynchronize(st), "hipStreamSynchronize");
-  EVREC(4);
-  if (nr_first <= 0) {
-    // all-zero spectrum: nothing to refine, no mode is kept
-    HIPCHK(c, hipMemcpyAsync(S, S0, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st),
-           "S copy");
-    HIPCHK(c, launch_set_i64(n_r, 0, st), "N_r");
-  } else {
-    int64_t over = nr_first / 4;
-    if (over < 8) over = 8;
-    const int64_t k = (nr_first + over < n) ? nr_first + over : n;
-    JacobiPlan jk;
-    if (!jacobi_plan((int)k, &jk)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
-    const int64_t ns = matmul_tn_splits(m, k, k);
-    if (sizeof(double) * (size_t)ns * k * k > p.part_bytes)
-      return fail(c, PYLOM_ENOTSUP, "Gram partials exceed the planned workspace");
-    HIPCHK(c, launch_rr_project(0, m, (int)n, (int)k, D, ldd, remove_mean ? meanws : nullptr, VT0,
-                                Z, st), "Rayleigh-Ritz projection");
-    HIPCHK(c, launch_matmul_tn(1, m, k, k, Z, k, Z, k, G, k, part, ns, st), "Gram");
-    HIPCHK(c, launch_small_svd(jk, G, (int)c->max_sweeps, ws + p.oSvd2, lam, WT, k, UR2, 0.0, nr2,
-                               c->status_dev + 2, st), "Gram eigen-decomposition");
-    c->status_pairs = 2;
-    HIPCHK(c, launch_rr_finish((int)n, (int)k, S0, lam, residual, S, n_r, WT, VT0, VT, ldvt, M,
-                               st), "refined spectrum");
-    EVREC(5);
-    HIPCHK(c, launch_rr_form_u(0, m, (int)k, Z, M, n_r, U, ldu, st), "form U");
-  }
-  if (!(nr_first > 0) && tm) HIPCHK(c, hipEventRecord(evs[5], st), "hipEventRecord");
-  if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, 0, m, st), "mean out");
-  EVREC(6);
-#undef EVREC
-  if (tm) ++c->ev_calls;
+  HIPCHK(c, hipStreamSynchronize(x.st), "hipStreamSynchronize");
+  if (nr_first > 0) c->status_pairs = 2;
+  rc = enqueue_mixed2(c, x, p, D, ldd, remove_mean, residual, mean, U, ldu, S, VT, ldvt, n_r,
+                      nr_first);
+  if (rc) return rc;
+  if (x.evs) ++c->ev_calls;
   return PYLOM_OK;
 }
 
@@ -461,48 +652,219 @@ static int run_tsvd(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, 
   HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
   rc = ensure_ws(c, p.total);
   if (rc) return rc;
-  char* ws = (char*)c->ws;
-  double* V = (double*)(ws + p.oV);
-  double* Tleaf = (double*)(ws + p.oTleaf);
-  double* Rbuf = (double*)(ws + p.oR);
-  double* Ttree = (double*)(ws + p.oTtree);
-  double* W = (double*)(ws + p.oW);
-  double* meanws = (double*)(ws + p.oMean);
-  void* svdws = ws + p.oSvd;
-  hipStream_t st = c->stream;
-  const int in64 = dtype == PYLOM_R64;
-  const bool tm = c->timing > 0 && !c->ev.empty();
-  hipEvent_t* evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * kEvPerSlot] : nullptr;
-#define EVREC(j) \
-  if (tm) HIPCHK(c, hipEventRecord(evs[j], st), "hipEventRecord")
-
-  EVREC(0);
-  EVREC(1);
-  HIPCHK(c, launch_leaf_qr_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws, V, Tleaf,
-                               p.nch_leaf, Rbuf, st), "leaf QR");
-  EVREC(2);
-  for (int64_t h = 1; h < p.P; h *= 2)
-    HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, 1, st), "tree combine");
-  EVREC(3);
-  HIPCHK(c, launch_small_svd(p.jp, Rbuf, (int)c->max_sweeps, svdws, S, VT, ldvt, W, residual, n_r,
-                             c->status_dev, st), "small SVD");
+  const Exec x = ctx_exec(c);
+  if (x.evs) c->ev_mixed[(size_t)(c->ev_calls % c->timing)] = 0;
+  rc = enqueue_fp64(c, x, p, dtype, D, ldd, remove_mean, residual, mean, U, ldu, S, VT, ldvt, n_r);
+  if (rc) return rc;
   c->status_valid = 1;
   c->status_pairs = 1;
-  EVREC(4);
-  int64_t top = 1;
-  while (top * 2 < p.P) top *= 2;
-  if (p.P > 1)
-    for (int64_t h = top; h >= 1; h /= 2)
-      HIPCHK(c, launch_apply_tree_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, W, n, n_r, n, st),
-             "tree propagation");
-  EVREC(5);
-  HIPCHK(c, launch_apply_leaf_f64(p.g, m, p.b, p.P, V, Tleaf, p.nch_leaf, W, n, n_r, n, U, in64,
-                                  ldu, st), "leaf apply");
-  if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, in64, m, st), "mean out");
-  EVREC(6);
-#undef EVREC
-  if (tm) ++c->ev_calls;
+  if (x.evs) ++c->ev_calls;
   return PYLOM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched POD of uneven instances
+// ---------------------------------------------------------------------------
+static uint64_t fnv1a(uint64_t h, const void* data, size_t len) {
+  const unsigned char* p = (const unsigned char*)data;
+  for (size_t i = 0; i < len; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+static int ensure_lanes(pylom_ctx c, int64_t k) {
+  while ((int64_t)c->lanes.size() < k) {
+    hipStream_t q = nullptr;
+    HIPCHK(c, hipStreamCreateWithFlags(&q, hipStreamNonBlocking), "hipStreamCreate");
+    c->lanes.push_back(q);
+    hipEvent_t e = nullptr;
+    HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    c->ev_join.push_back(e);
+  }
+  if (!c->ev_fork) HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "hipEventCreate");
+  if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking), "hipStreamCreate");
+  if (!c->ev_in) HIPCHK(c, hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
+  if (!c->ev_out) HIPCHK(c, hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming), "hipEventCreate");
+  return PYLOM_OK;
+}
+
+struct BatchLayout {
+  std::vector<Plan> plans;
+  std::vector<int> lane;          // lane of each problem
+  std::vector<size_t> lane_off;   // workspace offset of each lane
+  size_t oStatus, oNr0, total;
+  std::vector<size_t> keep_off;   // mixed precision: per-instance phase-1 results
+  int64_t K;
+};
+
+// One launch phase of the batch (0: FP64 whole path; 1, 2: mixed phases),
+// forked from the context stream over the lanes and joined back.
+static int batch_phase(pylom_ctx c, const BatchLayout& L, pylom_dtype dtype, int phase,
+                       int64_t count, const pylom_problem* pr, const int64_t* nr_first,
+                       bool capturing, hipStream_t origin) {
+  char* ws = (char*)c->ws;
+  HIPCHK(c, hipEventRecord(c->ev_fork, origin), "hipEventRecord");
+  for (int64_t l = 0; l < L.K; ++l)
+    HIPCHK(c, hipStreamWaitEvent(c->lanes[l], c->ev_fork, 0), "hipStreamWaitEvent");
+  for (int64_t i = 0; i < count; ++i) {
+    const int l = L.lane[i];
+    Exec x;
+    x.st = c->lanes[l];
+    x.ws = ws + L.lane_off[l];
+    x.status = (int*)(ws + L.oStatus) + 4 * i;
+    x.coop = !capturing;
+    x.max_sweeps = (int)c->max_sweeps;
+    x.evs = nullptr;
+    x.nr0 = (int64_t*)(ws + L.oNr0) + i;
+    x.keep = L.keep_off.empty() ? nullptr : ws + L.keep_off[(size_t)i];
+    const pylom_problem& q = pr[i];
+    int rc;
+    if (phase == 0)
+      rc = enqueue_fp64(c, x, L.plans[i], dtype, q.D, q.ldd, q.remove_mean ? 1 : 0, q.residual,
+                        q.mean, q.U, q.ldu, q.S, q.VT, q.ldvt, q.n_r);
+    else if (phase == 1)
+      rc = enqueue_mixed1(c, x, L.plans[i], q.D, q.ldd, q.remove_mean ? 1 : 0, q.residual);
+    else
+      rc = enqueue_mixed2(c, x, L.plans[i], q.D, q.ldd, q.remove_mean ? 1 : 0, q.residual, q.mean,
+                          q.U, q.ldu, q.S, q.VT, q.ldvt, q.n_r, nr_first[i]);
+    if (rc) return rc;
+  }
+  for (int64_t l = 0; l < L.K; ++l) {
+    HIPCHK(c, hipEventRecord(c->ev_join[l], c->lanes[l]), "hipEventRecord");
+    HIPCHK(c, hipStreamWaitEvent(origin, c->ev_join[l], 0), "hipStreamWaitEvent");
+  }
+  if (phase != 1) {
+    // reduced Jacobi status of the whole batch into the context's status
+    HIPCHK(c, launch_status_reduce(count, (const int*)(ws + L.oStatus), 4, phase == 0 ? 1 : 2,
+                                   c->status_dev, origin), "status");
+  }
+  return PYLOM_OK;
+}
+
+// Run one phase eagerly, or capture it once into a graph and replay it.
+static int batch_run(pylom_ctx c, const BatchLayout& L, pylom_dtype dtype, int phase,
+                     int64_t count, const pylom_problem* pr, const int64_t* nr_first,
+                     bool use_graph, uint64_t key) {
+  if (!use_graph) return batch_phase(c, L, dtype, phase, count, pr, nr_first, false, c->stream);
+  // the graph is captured on, and replayed from, the context's own origin
+  // stream, ordered after the caller's stream by events on both sides (the
+  // caller's stream may be the legacy null stream, which cannot be captured)
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+    const int rc = batch_phase(c, L, dtype, phase, count, pr, nr_first, true, c->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e2 != hipSuccess) return hip_fail(c, e2, "hipGraphInstantiate");
+    it = c->graphs.emplace(key, ge).first;
+  }
+  HIPCHK(c, hipEventRecord(c->ev_in, c->stream), "hipEventRecord");
+  HIPCHK(c, hipStreamWaitEvent(c->cap, c->ev_in, 0), "hipStreamWaitEvent");
+  HIPCHK(c, hipGraphLaunch(it->second, c->cap), "hipGraphLaunch");
+  HIPCHK(c, hipEventRecord(c->ev_out, c->cap), "hipEventRecord");
+  HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_out, 0), "hipStreamWaitEvent");
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_pod_batched(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t count,
+                                 const pylom_problem* pr, int use_graph) {
+  int rc = check_common(c, dtype, prec);
+  if (rc) return rc;
+  if (count < 0 || (count > 0 && !pr)) return fail(c, PYLOM_EINVAL, "problems");
+  if (count > (1 << 20)) return fail(c, PYLOM_ENOTSUP, "too many problems");
+  if (prec == PYLOM_MIXED && dtype != PYLOM_R32)
+    return fail(c, PYLOM_EDTYPE, "mixed precision needs R32 storage");
+  const bool mixed = prec == PYLOM_MIXED;
+  BatchLayout L;
+  L.plans.resize((size_t)count);
+  std::vector<double> cost((size_t)count);
+  for (int64_t i = 0; i < count; ++i) {
+    const pylom_problem& q = pr[i];
+    if (!q.D || !q.U || !q.S || !q.VT || !q.n_r) return fail(c, PYLOM_EINVAL, "null array argument");
+    if (!(q.residual >= 0.0 && q.residual < 1.0))
+      return fail(c, PYLOM_EINVAL, "residual must be in [0, 1)");
+    if (q.n < 1 || q.m < q.n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
+    if (q.ldd < q.n || q.ldu < q.n || q.ldvt < q.n)
+      return fail(c, PYLOM_ESHAPE, "leading dimension < n");
+    rc = make_plan(c, q.m, q.n, !mixed, &L.plans[(size_t)i], mixed);
+    if (rc) return rc;
+    cost[(size_t)i] = leaf_model(q.m, q.n, L.plans[(size_t)i].b, c->ncu);
+  }
+  if (count == 0) return PYLOM_OK;
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+  // longest-processing-time assignment of instances to lanes
+  L.K = std::min<int64_t>(c->streams, count);
+  L.lane.assign((size_t)count, 0);
+  std::vector<int64_t> order((size_t)count);
+  for (int64_t i = 0; i < count; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return cost[(size_t)a] > cost[(size_t)b]; });
+  std::vector<double> load((size_t)L.K, 0.0);
+  std::vector<size_t> lane_ws((size_t)L.K, 0);
+  for (int64_t i : order) {
+    int64_t best = 0;
+    for (int64_t l = 1; l < L.K; ++l)
+      if (load[(size_t)l] < load[(size_t)best]) best = l;
+    L.lane[(size_t)i] = (int)best;
+    load[(size_t)best] += cost[(size_t)i];
+    lane_ws[(size_t)best] = std::max(lane_ws[(size_t)best], L.plans[(size_t)i].total);
+  }
+  size_t off = 0;
+  L.lane_off.resize((size_t)L.K);
+  for (int64_t l = 0; l < L.K; ++l) {
+    L.lane_off[(size_t)l] = off;
+    off = align_up(off + lane_ws[(size_t)l]);
+  }
+  L.oStatus = off;
+  off = align_up(off + sizeof(int) * 4 * (size_t)count);
+  L.oNr0 = off;
+  off = align_up(off + sizeof(int64_t) * (size_t)count);
+  if (mixed) {
+    // instances that share a lane also share its scratch, so what phase 2
+    // reads from phase 1 is kept per instance
+    L.keep_off.resize((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+      L.keep_off[(size_t)i] = off;
+      off = align_up(off + keep_bytes(pr[i].m, pr[i].n));
+    }
+  }
+  L.total = off;
+  rc = ensure_ws(c, L.total);
+  if (rc) return rc;
+  rc = ensure_lanes(c, L.K);
+  if (rc) return rc;
+  // graph key: everything the captured launches depend on
+  uint64_t key = 1469598103934665603ull;
+  const int64_t hdr[6] = {(int64_t)dtype, (int64_t)prec, count, L.K, c->max_sweeps, c->block_rows};
+  key = fnv1a(key, hdr, sizeof(hdr));
+  const void* wsp = c->ws;
+  key = fnv1a(key, &wsp, sizeof(wsp));
+  key = fnv1a(key, &c->stream, sizeof(c->stream));
+  key = fnv1a(key, pr, sizeof(pylom_problem) * (size_t)count);
+  c->status_valid = 1;
+  c->status_pairs = 1;
+  if (!mixed)
+    return batch_run(c, L, dtype, 0, count, pr, nullptr, use_graph != 0, fnv1a(key, "p0", 2));
+  rc = batch_run(c, L, dtype, 1, count, pr, nullptr, use_graph != 0, fnv1a(key, "p1", 2));
+  if (rc) return rc;
+  std::vector<int64_t> nr0((size_t)count, 0);
+  HIPCHK(c, hipMemcpyAsync(nr0.data(), (char*)c->ws + L.oNr0, sizeof(int64_t) * (size_t)count,
+                           hipMemcpyDeviceToHost, c->stream), "N_r read-back");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  // phase 2 depends on the refinement widths, part of its key
+  return batch_run(c, L, dtype, 2, count, pr, nr0.data(), use_graph != 0,
+                   fnv1a(fnv1a(key, "p2", 2), nr0.data(), sizeof(int64_t) * (size_t)count));
 }
 
 extern "C" int pylom_pod(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
@@ -706,6 +1068,7 @@ extern "C" int pylom_spod(pylom_ctx c, pylom_dtype spectra, pylom_prec prec, int
   const int64_t n = p.n, nb = p.nb, nf = p.nf, M2 = p.M2, P = p.P, np = p.g.npanels;
   const bool tm = c->timing > 0 && !c->ev.empty();
   hipEvent_t* evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * kEvPerSlot] : nullptr;
+  if (tm) c->ev_mixed[(size_t)(c->ev_calls % c->timing)] = 0;
 #define EVREC(j) \
   if (tm) HIPCHK(c, hipEventRecord(evs[j], st), "hipEventRecord")
 
@@ -759,15 +1122,19 @@ extern "C" int pylom_phase_times(pylom_ctx c, double* out, int cap) {
   if (c->timing <= 0 || c->ev_calls == 0) return fail(c, PYLOM_EINVAL, "no timed call recorded");
   const int64_t nrec = c->ev_calls < c->timing ? c->ev_calls : c->timing;
   // events per slot: e0 call start, e1 after the front end (SPOD FFT; none
-  // for POD), e2..e6 after leaf QR, tree, SVD, propagation, apply
+  // for POD), e2..e6 after leaf QR, tree, SVD, propagation, apply; e7 (mixed
+  // precision) after the first SVD, before the host read-back
   double acc[kPhases] = {0, 0, 0, 0, 0, 0};
   for (int64_t k = 0; k < nrec; ++k) {
     const int64_t slot = (c->ev_calls - 1 - k) % c->timing;
     hipEvent_t* e = &c->ev[(size_t)slot * kEvPerSlot];
-    HIPCHK(c, hipEventSynchronize(e[kEvPerSlot - 1]), "hipEventSynchronize");
+    const bool mixed = c->ev_mixed[(size_t)slot] != 0;
+    HIPCHK(c, hipEventSynchronize(e[6]), "hipEventSynchronize");
     for (int i = 0; i < kPhases; ++i) {
       float ms = 0.f;
-      if (i < 5)
+      if (i == 2 && mixed)  // the first SVD ends at e7, before the host read-back
+        HIPCHK(c, hipEventElapsedTime(&ms, e[3], e[7]), "hipEventElapsedTime");
+      else if (i < 5)
         HIPCHK(c, hipEventElapsedTime(&ms, e[i + 1], e[i + 2]), "hipEventElapsedTime");
       else
         HIPCHK(c, hipEventElapsedTime(&ms, e[0], e[1]), "hipEventElapsedTime");

@@ -74,9 +74,10 @@ size_t jacobi_ws_bytes(const JacobiPlan& p, int max_sweeps);
 // row-major, ldvt), UR (n x n row-major, ld n; the left factor, sign
 // convention applied) and N_r (device) for residual r; status[0] = sweeps
 // (-1 if not converged), status[1] = barrier timeout flag.
+// coop = false uses a plain launch (for stream capture).
 hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps, void* ws,
                             double* S, double* VT, int64_t ldvt, double* UR, double residual,
-                            int64_t* nr, int* status, hipStream_t st);
+                            int64_t* nr, int* status, hipStream_t st, bool coop = true);
 
 // Same for `count` problems of one size n <= 32 (one workgroup each; G == 1):
 // problem k reads R + k*sR, uses the workspace slice ws + k*jacobi_ws_stride,
@@ -88,6 +89,11 @@ hipError_t launch_small_svd_batched(const JacobiPlan& p, int64_t count, const do
                                     double* VT, int64_t ldvt, int64_t sVT, double* UR,
                                     int64_t sUR, double residual, int64_t* nr, int* status_each,
                                     int* status, hipStream_t st);
+
+// status[0..1] <- reduction of `count` records of `stride` ints, each holding
+// `pairs` (sweeps, timeout) pairs.
+hipError_t launch_status_reduce(int64_t count, const int* st_each, int stride, int pairs,
+                                int* status, hipStream_t st);
 
 // ---- misc ------------------------------------------------------------------
 hipError_t launch_cast_out(const double* src, void* dst, int dst_f64, int64_t count, hipStream_t st);

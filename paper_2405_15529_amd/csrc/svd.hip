@@ -474,7 +474,7 @@ __global__ void k_svd_one(const double* R, double* S, double* VT, double* UR, do
 
 hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps, void* ws,
                             double* S, double* VT, int64_t ldvt, double* UR, double residual,
-                            int64_t* nr, int* status, hipStream_t st) {
+                            int64_t* nr, int* status, hipStream_t st, bool coop) {
   if (p.n == 1) {
     hipLaunchKernelGGL(k_svd_one, dim3(1), dim3(1), 0, st, R, S, VT, UR, residual, nr, status);
     return hipGetLastError();
@@ -500,7 +500,15 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
       case 64: fn = (const void*)k_jacobi<64>; break;
       default: return hipErrorInvalidValue;
     }
-    e = hipLaunchCooperativeKernel(fn, grid, block, args, 0, st);
+    if (coop && p.G > 1) {
+      e = hipLaunchCooperativeKernel(fn, grid, block, args, 0, st);
+    } else {
+      // plain launch (one working group, or inside stream capture): the
+      // G <= 32 working groups fit on distinct CUs once earlier work on the
+      // stream has drained, and the bounded-spin barrier turns a failure to
+      // co-reside into an error flag, never a hang
+      e = hipLaunchKernel(fn, grid, block, args, 0, st);
+    }
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_svd_finalize, dim3(1), dim3(FT), 0, st, p.n, w.A, w.V, S, VT, ldvt, UR,
@@ -514,7 +522,8 @@ size_t jacobi_ws_stride(const JacobiPlan& p, int max_sweeps) {
 
 // Status of a batch: sweeps = the largest count, -1 if any problem did not
 // converge; the barrier flag is the OR over problems.
-__global__ void k_status_reduce(int64_t count, const int* __restrict__ st, int* out) {
+__global__ void k_status_reduce(int64_t count, const int* __restrict__ st, int stride, int pairs,
+                                int* out) {
   __shared__ int smax, sneg, stmo;
   if (threadIdx.x == 0) {
     smax = 0;
@@ -523,10 +532,12 @@ __global__ void k_status_reduce(int64_t count, const int* __restrict__ st, int* 
   }
   __syncthreads();
   for (int64_t k = threadIdx.x; k < count; k += blockDim.x) {
-    const int sw = st[2 * k];
-    if (sw < 0) atomicOr(&sneg, 1);
-    else atomicMax(&smax, sw);
-    if (st[2 * k + 1]) atomicOr(&stmo, 1);
+    for (int q = 0; q < pairs; ++q) {
+      const int sw = st[k * stride + 2 * q];
+      if (sw < 0) atomicOr(&sneg, 1);
+      else atomicMax(&smax, sw);
+      if (st[k * stride + 2 * q + 1]) atomicOr(&stmo, 1);
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -572,7 +583,14 @@ hipError_t launch_small_svd_batched(const JacobiPlan& p, int64_t count, const do
                      VT, ldvt, UR, residual, nr, wsb, sS, sVT, sUR);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_status_reduce, dim3(1), dim3(256), 0, st, count, status_each, status);
+  hipLaunchKernelGGL(k_status_reduce, dim3(1), dim3(256), 0, st, count, status_each, 2, 1, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_reduce(int64_t count, const int* st_each, int stride, int pairs,
+                                int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_status_reduce, dim3(1), dim3(256), 0, st, count, st_each, stride, pairs,
+                     status);
   return hipGetLastError();
 }
 

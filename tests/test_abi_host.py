@@ -196,3 +196,38 @@ def test_spod_query_and_validation(hctx):
     assert run(dt=0.0) == -1
     assert run(window=3) == -1
     assert run(ldd=100) == -2
+
+
+def test_block_rows_tuner(hctx):
+    # the latency model keeps the 4096-row leaves of the 1048576 x 256 workload
+    assert api.tune_block_rows(1 << 20, 256, hctx) == 4096
+    for m, n in [(20000, 100), (50000, 32), (2_000_000, 512), (1000, 1000), (300, 200)]:
+        b = api.tune_block_rows(m, n, hctx)
+        assert b >= n and (b & (b - 1)) == 0 or b == n
+    assert hctx.lib.pylom_tune_block_rows(hctx.h, 10, 20) < 0   # m < n
+
+
+def test_batched_validation_before_device(hctx):
+    from paper_2405_15529_amd import _lib
+    lib, h = hctx.lib, hctx.h
+    ok = dict(m=1000, n=20, D=1, ldd=20, remove_mean=0, residual=0.01, mean=0, U=1, ldu=20, S=1,
+              VT=1, ldvt=20, n_r=1)
+
+    def run(probs, dtype=api.R64, prec=api.FP64, graph=0):
+        arr = (_lib.Problem * len(probs))(*[_lib.Problem(**p) for p in probs])
+        return lib.pylom_pod_batched(h, dtype, prec, len(probs), ctypes.cast(arr, ctypes.c_void_p),
+                                     graph)
+    assert run([ok, dict(ok, m=5000, n=64, ldd=64, ldu=64, ldvt=64)]) == -7   # valid: no device
+    assert lib.pylom_pod_batched(h, api.R64, api.FP64, 0, None, 0) == 0       # empty batch
+    assert lib.pylom_pod_batched(h, api.R64, api.FP64, 2, None, 0) == -1
+    assert run([ok, dict(ok, D=0)]) == -1
+    assert run([ok, dict(ok, m=10)]) == -2                                    # m < n
+    assert run([dict(ok, ldu=5)]) == -2
+    assert run([dict(ok, residual=1.5)]) == -1
+    assert run([ok], prec=api.MIXED) == -3                                   # mixed needs R32
+    assert run([ok], dtype=api.R32, prec=api.MIXED) == -7
+    assert run([dict(ok, m=5000, n=2000, ldd=2000, ldu=2000, ldvt=2000)]) == -6
+    hctx.set_option("streams", 8)
+    assert hctx.get_option("streams") == 8
+    with pytest.raises(api.PylomError):
+        hctx.set_option("streams", 0)
