@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--spod-m", type=int, default=262144)
     ap.add_argument("--spod-nt", type=int, default=2048)
     ap.add_argument("--spod-steps", type=int, default=3)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=2)
     return ap.parse_args()
 
 
@@ -163,6 +166,78 @@ def timed_pod(api, ctx, A, m, n, r, precision, steps, warmup):
                 nr=int(nr_d.item()))
 
 
+def timed_batch(api, count, seed, steps, warmup):
+    """Uneven POD batch: `count` instances, m log-uniform in [5e4, 2e6], n
+    uniform in [32, 512], FP32 known spectra s_i = 10^(-6i/n), 99 % energy.
+    The mixed-precision batch (one graph-captured pylom_pod_batched call) is
+    timed against `count` sequential FP64 pylom_pod calls on the promoted
+    instances."""
+    import numpy as np
+    import torch
+    from paper_2405_15529_amd import synth
+
+    shapes = synth.uneven_batch(count=count, seed=seed)
+    A32 = [synth.known_spectrum_device(m, n, synth.uneven_spectrum(n), seed=1000 + i,
+                                       dtype=torch.float32) for i, (m, n) in enumerate(shapes)]
+    torch.cuda.synchronize()
+    flops = sum(2.0 * m * n * n for m, n in shapes)
+    ctx = api.Context(0)
+    batch = api.PodBatch(A32, remove_mean=False, r=0.01, precision="mixed", use_graph=True, ctx=ctx)
+    for _ in range(max(1, warmup)):
+        batch.run()   # the first call captures the graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.run()
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / steps
+    rc_mixed, _ = ctx.status()
+    res = batch.results()
+    # sequential FP64 solves, one pylom_pod per instance on the promoted data
+    ctx64 = api.Context(0)
+    t_seq = 0.0
+    worst_vs64 = 0.0
+    worst_exact = 0.0
+    nr_diff = 0
+    for i, (m, n) in enumerate(shapes):
+        A64 = A32[i].double()
+        api.pod(A64, remove_mean=False, r=0.01, ctx=ctx64, sync=False)  # warm workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g64 = api.pod(A64, remove_mean=False, r=0.01, ctx=ctx64, sync=False)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        S64 = g64.S.cpu().numpy()
+        Sx = res[i].S.cpu().numpy()
+        s = synth.uneven_spectrum(n)
+        k = res[i].nr
+        if k:
+            worst_vs64 = max(worst_vs64, float(np.max(np.abs(Sx[:k] - S64[:k]) / S64[:k])))
+            worst_exact = max(worst_exact, float(np.max(np.abs(Sx[:k] - s[:k]) / s[:k])))
+        del A64, g64
+    rc64, _ = ctx64.status()
+    out = {
+        "workload": f"{count} POD instances, m log-uniform [5e4, 2e6], n uniform [32, 512], "
+                    f"FP32 known spectra 10^(-6i/n), 99% energy",
+        "total_rows": int(sum(m for m, _ in shapes)),
+        "mixed_batched_graph_s": round(t_mixed, 4),
+        "fp64_sequential_s": round(t_seq, 4),
+        "speedup": round(t_seq / t_mixed, 3),
+        "mixed_tflops": round(flops / t_mixed / 1e12, 4),
+        "fp64_seq_tflops": round(flops / t_seq / 1e12, 4),
+        "sigma_rel_err_vs_fp64_max": worst_vs64,
+        "sigma_rel_err_vs_exact_max": worst_exact,
+        "status_mixed": rc_mixed,
+        "status_fp64": rc64,
+        "streams": ctx.get_option("streams"),
+    }
+    ctx.close()
+    ctx64.close()
+    del A32, batch, res
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -264,6 +339,9 @@ def main():
         torch.cuda.empty_cache()
         out["spod"] = timed_spod(api, args.spod_m, args.spod_nt, 256, 128, args.spod_steps,
                                  1 if args.warmup else 0)
+    if not args.no_batch:
+        out["uneven_batch"] = timed_batch(api, args.batch_count, 4, args.batch_steps,
+                                          1 if args.warmup else 0)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_rows, r)
     print(json.dumps(out), flush=True)

@@ -154,3 +154,36 @@ def graded_fp64_device(m: int = 1_048_576, n: int = 256, seed: int = 1, per_deca
         return A, s, Q1, Q2
     del Q1
     return A, s
+
+
+def known_spectrum_device(m: int, n: int, s, seed: int, device: str = "cuda",
+                          dtype=None):
+    """A = Q1 diag(s) Q2^T on the device, Q1 (m x n) and Q2 (n x n) Haar: the
+    Q factors of Gaussian matrices drawn with torch's seeded device generator,
+    formed as G L^{-T} with L L^T = G^T G (positive-diagonal Cholesky, the
+    same factor as the QR with diag R > 0).  Returns A in `dtype` (default
+    float64)."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    s = torch.as_tensor(np.asarray(s, dtype=np.float64), device=device)
+
+    def haar_dev(rows, cols):
+        G = torch.randn((rows, cols), generator=gen, dtype=torch.float64, device=device)
+        L = torch.linalg.cholesky(G.T @ G)
+        eye = torch.eye(cols, dtype=torch.float64, device=device)
+        Linv = torch.linalg.solve_triangular(L, eye, upper=False)  # n x n
+        return (G @ Linv.T.contiguous()).contiguous()               # G L^{-T}
+
+    Q2 = haar_dev(n, n)
+    A = haar_dev(m, n) * s[None, :]
+    A = A @ Q2.T.contiguous()
+    if dtype is not None:
+        A = A.to(dtype)
+    return A.contiguous()
+
+
+def uneven_spectrum(n: int) -> np.ndarray:
+    """s_i = 10^(-6 i / n), i = 0..n-1: six decades over every instance."""
+    return 10.0 ** (-6.0 * np.arange(n) / n)
