@@ -439,22 +439,199 @@ __device__ __forceinline__ void tile_update(T* __restrict__ C, int ldc, const T*
 
 // ---------------------------------------------------------------------------
 // chunk loads
+// Structured panel (the head of column k0+kk is state row k0+kk, the tail is
+// all s chunk rows), written for a short critical path:
+//  - every lane keeps its column's raw values and the scale that turns them
+//    into the reflector, so the register tile is never rewritten per column,
+//    and the update weight is simply zero for columns at or left of kk;
+//  - the head rows come from the prefetched diagonal block in registers (the
+//    lane that holds an entry adds it to its partial sum), so LDS is written
+//    but not read inside the loop;
+//  - 1/sqrt and 1/x use the hardware estimates refined by Newton steps;
+//  - v_kk is broadcast through an LDS vector laid out without bank conflicts;
+//  - the compact-WY T is built one column per step from the Gram values of
+//    the same pass, T(:c, c) = -tau_c T(:c, :c) (V(:, :c)^T v_c), with each
+//    lane holding four entries of its T row in registers.
+__device__ __forceinline__ double hw_rcp(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double hw_rsq(double x) { return __builtin_amdgcn_rsq(x); }
+__device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+template <typename T>
+__device__ __forceinline__ T rcp_nr(T x) {
+  T r = hw_rcp(x);
+  r = r * (T(2) - x * r);
+  r = r * (T(2) - x * r);
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ T rsq_nr(T x) {
+  T y = hw_rsq(x);
+  y = y * (T(1.5) - T(0.5) * x * y * y);
+  y = y * (T(1.5) - T(0.5) * x * y * y);
+  return y;
+}
+
+template <typename T, int RT>
+__device__ __forceinline__ void factor_panel_structured(
+    T* __restrict__ C, int ldc, T* __restrict__ Vp, T* __restrict__ Tm, T* __restrict__ state,
+    int n, int k0, int kw, int lane, const T (&rd4)[4], T* __restrict__ Rd, T* __restrict__ Gm,
+    T* __restrict__ vb, T* __restrict__ taus) {
+  const int j = lane & 15, g = lane >> 4;
+  T p[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) p[t] = (j < kw) ? C[(g + 4 * t) * ldc + k0 + j] : T(0);
+  T mysc = T(1), myscal = T(0);  // v_j = (x_j * mysc) * myscal once column j is factored
+  T treg[4] = {T(0), T(0), T(0), T(0)};  // T[j][4g + u]
+  T tau_prev = T(0);
+  auto t_column = [&](int c, T tauc) {
+    // the four Gram values are loaded unconditionally (one LDS round trip,
+    // overlapping the norm computation) and masked afterwards
+    T gv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) gv[u] = Gm[c * NB + 4 * g + u];
+    T part = T(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) part += (4 * g + u < c) ? treg[u] * gv[u] : T(0);
+    part = perm32_pairsum(perm16_pairsum(part));
+    const T val = (j < c) ? -tauc * part : ((j == c) ? tauc : T(0));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) treg[u] = (4 * g + u == c) ? val : treg[u];
+  };
+#pragma unroll 1
+  for (int kk = 0; kk < kw; ++kk) {
+    if (kk > 0) t_column(kk - 1, tau_prev);
+    // this lane's entry of head row kk (held by the lanes of row group kk/4)
+    const int uk = kk & 3;
+    const T rsel = (uk == 0) ? rd4[0] : (uk == 1) ? rd4[1] : (uk == 2) ? rd4[2] : rd4[3];
+    const bool owner = g == (kk >> 2);
+    const T alpha = readlane(rsel, ((kk >> 2) << 4) + kk);
+    // squared norm of column kk's tail (all s chunk rows)
+    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+#pragma unroll
+    for (int t = 0; t < RT; t += 4) {
+      a0 += p[t] * p[t];
+      if (t + 1 < RT) a1 += p[t + 1] * p[t + 1];
+      if (t + 2 < RT) a2 += p[t + 2] * p[t + 2];
+      if (t + 3 < RT) a3 += p[t + 3] * p[t + 3];
+    }
+    T x2 = (a0 + a1) + (a2 + a3);
+    x2 = perm32_pairsum(perm16_pairsum(x2));
+    T sig = readlane(x2, kk);
+    T sc = T(1);
+    if (__builtin_expect(sig < Tiny<T>::x2 && fabs(alpha) < Tiny<T>::root, 0)) {
+      // tiny head and tail (rank-deficient input): rescale by the power of
+      // two that brings max(|alpha|, |x|) into [0.5, 1) before forming the
+      // norm, so that no square falls into the subnormal range
+      T amax = T(0);
+#pragma unroll
+      for (int t = 0; t < RT; ++t) amax = fmax(amax, fabs(p[t]));
+      amax = perm32_pairmax(perm16_pairmax(amax));
+      amax = fmax(readlane(amax, kk), fabs(alpha));
+      if (amax > T(0)) {
+        int e;
+        frexp(amax, &e);
+        sc = ldexp(T(1), (-e < Tiny<T>::max_exp) ? -e : Tiny<T>::max_exp);
+      }
+      T xs2 = T(0);
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const T xs = p[t] * sc;
+        xs2 += xs * xs;
+      }
+      xs2 = perm32_pairsum(perm16_pairsum(xs2));
+      sig = readlane(xs2, kk);
+    }
+    T tau, beta, scal;
+    if (sig == T(0)) {
+      tau = T(0);
+      beta = alpha;
+      scal = T(0);
+    } else {
+      // a = as^2 + sig is a normal number here (>= 2^-960, or >= 1/4 after
+      // a rescale): y = 1/sqrt(a), |beta_s| = a y, 1/beta_s = -+y,
+      // tau = (bs - as)/bs = 1 - as/bs, scal = 1/(as - bs)
+      const T as = alpha * sc;
+      const T a = as * as + sig;
+      const T y = rsq_nr(a);
+      const T nrm = a * y;
+      const bool pos = as >= T(0);
+      const T bs = pos ? -nrm : nrm;
+      const T ibs = pos ? -y : y;
+      tau = T(1) - as * ibs;
+      scal = rcp_nr(as - bs);
+      beta = bs / sc;
+    }
+    if (j == kk) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) vb[t * 4 + g] = (p[t] * sc) * scal;
+    }
+    mysc = (j == kk) ? sc : mysc;
+    myscal = (j == kk) ? scal : myscal;
+    if (lane == 0) {
+      taus[kk] = tau;
+      Rd[kk * TLD + kk] = beta;
+    }
+    wave_lds_sync();
+    T v[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) v[t] = vb[t * 4 + g];
+    // d_j = [head; x_j]^T v: v^T [head row kk; column j] for j > kk, and
+    // x_j^T v_kk for j < kk (x_j = the raw column, v_j = x_j mysc myscal)
+    T d0 = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
+#pragma unroll
+    for (int t = 0; t < RT; t += 4) {
+      d0 += p[t] * v[t];
+      if (t + 1 < RT) d1 += p[t + 1] * v[t + 1];
+      if (t + 2 < RT) d2 += p[t + 2] * v[t + 2];
+      if (t + 3 < RT) d3 += p[t + 3] * v[t + 3];
+    }
+    T d = (d0 + d1) + (d2 + d3) + ((owner && j > kk) ? rsel : T(0));
+    d = perm32_pairsum(perm16_pairsum(d));
+    if (j < kk && g == 0) Gm[kk * NB + j] = (d * mysc) * myscal;
+    const T tw = (j > kk) ? tau * d : T(0);
+#pragma unroll
+    for (int t = 0; t < RT; ++t) p[t] -= tw * v[t];
+    if (owner && j > kk && j < kw) Rd[kk * TLD + j] = rsel - tw;
+    tau_prev = tau;
+    wave_lds_sync();
+  }
+  t_column(kw - 1, tau_prev);
+  // T, the state diagonal block (R rows of this panel), then C and the exact
+  // reflectors (structured: the chunk rows of column j hold v_j)
+#pragma unroll
+  for (int u = 0; u < 4; ++u) Tm[j * NB + 4 * g + u] = treg[u];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int kk = g * 4 + u;
+    if (kk <= j && j < kw) state[(int64_t)(k0 + kk) * n + k0 + j] = Rd[kk * TLD + j];
+  }
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int r = g + 4 * t;
+    const T vx = (p[t] * mysc) * myscal;
+    if (j < kw) C[r * ldc + k0 + j] = vx;
+    Vp[r * VPLD + j] = (j < kw) ? vx : T(0);
+  }
+  wave_lds_sync();
+}
+
 // ---------------------------------------------------------------------------
-// Rows i = wave, wave + 4, ... of the chunk, LB rows per batch with all their
-// loads issued before any is consumed; optional row-mean removal (Alg. 2).
+// Rows i = wave, wave + nw, ... of the chunk (nw waves), LB rows per batch
+// with all their loads issued before any is consumed; optional row-mean
+// removal (Alg. 2).
 template <typename T, typename TI>
 __device__ __forceinline__ void load_chunk(T* __restrict__ C, int ldc, int s, int sc, int n,
                                            const TI* __restrict__ src, int64_t ld_src,
                                            int remove_mean, double* __restrict__ mean_out,
-                                           int wave, int lane) {
+                                           int wave, int lane, int nw) {
   constexpr int LB = 4;    // rows per batch and wave
   constexpr int NCOL = 4;  // columns per lane and row held in registers (n <= 256)
   if (n <= 64 * NCOL) {
-    for (int i0 = wave; i0 < s; i0 += 4 * LB) {
+    for (int i0 = wave; i0 < s; i0 += nw * LB) {
       TI x[LB][NCOL];
 #pragma unroll
       for (int b = 0; b < LB; ++b) {
-        const int i = i0 + 4 * b;
+        const int i = i0 + nw * b;
 #pragma unroll
         for (int c = 0; c < NCOL; ++c) {
           const int col = lane + 64 * c;
@@ -463,7 +640,7 @@ __device__ __forceinline__ void load_chunk(T* __restrict__ C, int ldc, int s, in
       }
 #pragma unroll
       for (int b = 0; b < LB; ++b) {
-        const int i = i0 + 4 * b;
+        const int i = i0 + nw * b;
         if (i >= s) continue;
         double mu = 0.0;
         if (remove_mean && i < sc) {
@@ -483,7 +660,7 @@ __device__ __forceinline__ void load_chunk(T* __restrict__ C, int ldc, int s, in
     }
     return;
   }
-  for (int i = wave; i < s; i += 4) {
+  for (int i = wave; i < s; i += nw) {
     if (i >= sc) {
       for (int col = lane; col < n; col += 64) C[i * ldc + col] = T(0);
       continue;
@@ -533,6 +710,7 @@ void k_stacked_qr(QrArgs<T, TI> a) {
   T* taus = vb + 64;
   T* Gm = Yb;  // the panel wave's Y tile doubles as its Gram scratch
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = (int)(blockDim.x >> 6);  // 4, or 1 for narrow problems
   const bool leaf = (a.mode == 0);
   T* Yw = Yb + wave * NB * NB;
 
@@ -568,9 +746,9 @@ void k_stacked_qr(QrArgs<T, TI> a) {
     const int sc = (int)((rows - r0) < S ? (rows - r0) : S);
     if (leaf)
       load_chunk<T, TI>(C, ldc, S, sc, n, srcI + r0 * ld_src, ld_src, a.remove_mean,
-                        a.mean_ws ? a.mean_ws + row0 + r0 : nullptr, wave, lane);
+                        a.mean_ws ? a.mean_ws + row0 + r0 : nullptr, wave, lane, nw);
     else
-      load_chunk<T, T>(C, ldc, S, sc, n, srcT + r0 * ld_src, ld_src, 0, nullptr, wave, lane);
+      load_chunk<T, T>(C, ldc, S, sc, n, srcT + r0 * ld_src, ld_src, 0, nullptr, wave, lane, nw);
     int p_lo, p_hi;
     if (leaf) {
       const int lim = (f + sc < n) ? f + sc : n;
@@ -611,8 +789,8 @@ void k_stacked_qr(QrArgs<T, TI> a) {
             factor_panel<T, RT, true>(C, ldc, Vcur, Tcur, state, n, k0, kw, f, lane, rd4, Rd, Gm,
                                       vb, taus);
           else
-            factor_panel<T, RT, false>(C, ldc, Vcur, Tcur, state, n, k0, kw, f, lane, rd4, Rd,
-                                       Gm, vb, taus);
+            factor_panel_structured<T, RT>(C, ldc, Vcur, Tcur, state, n, k0, kw, lane, rd4, Rd,
+                                           Gm, vb, taus);
           if (tout) {
             T* tp = tout + ((int64_t)c * npan + p) * (NB * NB);
 #pragma unroll
@@ -620,6 +798,16 @@ void k_stacked_qr(QrArgs<T, TI> a) {
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) rd4[u] = rd_next[u];
+        }
+        if (nw == 1 && p > p_lo) {
+          // single-wave workgroup (narrow problems, several leaves per CU):
+          // this wave also applies panel p-1 to the remaining tiles
+          for (int t = p + 1; t < npan; ++t) {
+            T hd[4] = {T(0), T(0), T(0), T(0)};
+            if (!int_prev) load_head4<T>(hd, state, n, kp, kwp, t * NB, lane);
+            tile_update<T, RT>(C, ldc, Vprev, Tprev, Yw, state, n, kp, kwp, int_prev, t * NB, hd,
+                               lane);
+          }
         }
       } else if (p > p_lo) {
         for (int t = p + wave; t < npan; t += 3) {
@@ -633,13 +821,13 @@ void k_stacked_qr(QrArgs<T, TI> a) {
     }
     if (leaf && f < n) {
       const int nf = (sc < n - f) ? sc : n - f;
-      for (int idx = tid; idx < nf * n; idx += 256) {
+      for (int idx = tid; idx < nf * n; idx += (int)blockDim.x) {
         const int i = idx / n, col = idx - (idx / n) * n;
         state[(int64_t)(f + i) * n + col] = (col >= f + i) ? C[i * ldc + col] : T(0);
       }
     }
     if (vout) {
-      for (int idx = tid; idx < sc * n; idx += 256) {
+      for (int idx = tid; idx < sc * n; idx += (int)blockDim.x) {
         const int i = idx / n, col = idx - (idx / n) * n;
         vout[(r0 + i) * n + col] = C[i * ldc + col];
       }
@@ -892,13 +1080,17 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// Problems of at most two panels use single-wave workgroups: their trailing
+// work per step is one tile, so three of four waves would idle, while several
+// single-wave leaves share a CU and overlap their panel latencies.
 template <typename T, typename TI, int RT>
 static hipError_t launch_qr_t(const QrArgs<T, TI>& a, int grid, int gy, size_t lds,
                               hipStream_t st) {
   hipError_t e = hipFuncSetAttribute((const void*)k_stacked_qr<T, TI, RT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_stacked_qr<T, TI, RT>), dim3(grid, gy), dim3(256), lds, st, a);
+  const int threads = (a.npanels <= 2) ? 64 : 256;
+  hipLaunchKernelGGL((k_stacked_qr<T, TI, RT>), dim3(grid, gy), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
