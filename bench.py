@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--spod-nt", type=int, default=2048)
     ap.add_argument("--spod-steps", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, copy one 1 GiB FP64 buffer on the device "
+                         "(a plain copy of known size, for calibrating HBM byte counters)")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=2)
     return ap.parse_args()
@@ -116,6 +120,36 @@ def cpu_baseline(n: int, rows: int, r: float):
                 sample=f"{rows} x {n} rows of the same known-spectrum generator, FP64, "
                        f"{dt:.2f} s, one thread",
                 seconds=dt)
+
+
+# HBM bytes per launch of the FP64 leaf QR at 1048576 x 256 (row blocks 4096),
+# from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by the
+# same counters read on a plain 1 GiB device copy; valid only for the kernel
+# sources they were taken on (their SHA-256 below).  The counter summary is
+# in profiles/.
+LEAF_TRAFFIC = {
+    "sources_sha256": "adbb3d7baf4da0f84c3519d08f0dbd32e0faffa5680318f23c69a1bd63e7586c",
+    "m": 1048576, "n": 256, "b": 4096,
+    "bytes": 13614624466,  # FETCH 6.575e9 (x1.99994) + WRITE 7.040e9 (x1.0)
+}
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("tsqr.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2405_15529_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def leaf_traffic(m: int, n: int, b: int):
+    t = LEAF_TRAFFIC
+    if not t or (t["m"], t["n"], t["b"]) != (m, n, b):
+        return None
+    if t["sources_sha256"] != kernel_sources_sha256():
+        return None  # the kernel changed since the counters were taken
+    return t["bytes"]
 
 
 def timed_pod(api, ctx, A, m, n, r, precision, steps, warmup):
@@ -277,33 +311,24 @@ def main():
     leaf_ms = f["phases"]["leaf_qr"]
     leaf_tflops = 2.0 * m * n * n / (leaf_ms * 1e-3) / 1e12
 
+    if args.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # mixed path on the FP32 copy of the same matrix
     A32 = A.float().contiguous()
     del A
-    x = timed_pod(api, ctx, A32, m, n, r, "mixed", args.steps, args.warmup)
-    nrx = x["nr"]
-    Sx = x["S"].cpu().numpy()
-    kx = min(nrx, nr)
-    mixed = {
-        "precision": "mixed (FP32 leaf QR, FP64 tree + SVD, FP64 Rayleigh-Ritz refinement)",
-        "storage": "f32",
-        "ms_per_step": round(x["ms"], 4),
-        "tflops": round(flops / (x["ms"] * 1e-3) / 1e12, 4),
-        "gbps": round((2.0 * 4 * m * n + 4.0 * m * nrx) / (x["ms"] * 1e-3) / 1e9, 2),
-        "speedup_vs_fp64": round(ms / x["ms"], 3),
-        "n_r": nrx,
-        "sigma_rel_err_vs_fp64_run": float(np.max(np.abs(Sx[:kx] - S_h[:kx]) / S_h[:kx])) if kx else 0.0,
-        "sigma_rel_err_vs_exact": float(np.max(np.abs(Sx[:kx] - s[:kx]) / s[:kx])) if kx else 0.0,
-        "orth_err_U": orth_err(x["U"], nrx),
-        "jacobi_sweeps_first": x["sweeps"],
-        "phase_ms": {"leaf_qr_fp32": round(x["phases"]["leaf_qr"], 4),
-                     "tree_combine": round(x["phases"]["tree_combine"], 4),
-                     "small_svd": round(x["phases"]["small_svd"], 4),
-                     "refine_project_gram_eig": round(x["phases"]["tree_propagate"], 4),
-                     "form_u": round(x["phases"]["leaf_apply"], 4)},
-    }
-    del x["U"]
-
+    if args.no_mixed:
+        x = None
+    else:
+        x = timed_pod(api, ctx, A32, m, n, r, "mixed", args.steps, args.warmup)
+    mixed = None
+    if x is not None:
+        mixed = mixed_summary(x, ms, flops, m, n, s, S_h, nr, orth_err)
+        del x["U"]
     out = {
         "metric": "POD TSQR-SVD GB/s & TFLOP/s: mixed-precision vs FP64 at sigma rel err <=1e-6",
         "value": round(tflops, 4),
@@ -331,11 +356,11 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_stacked_qr (leaf QR, FP64)",
                      "achieved": round(leaf_tflops, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(leaf_tflops / FP64_PEAK_TFLOPS, 4),
-                     "traffic": None},
-        "wall_s": round(f["wall"] + x["wall"], 3),
+                     "traffic": leaf_traffic(m, n, args.block_rows)},
+        "wall_s": round(f["wall"], 3),
     }
     if not args.no_spod:
-        del A32, x, f
+        del A32, f
         torch.cuda.empty_cache()
         out["spod"] = timed_spod(api, args.spod_m, args.spod_nt, 256, 128, args.spod_steps,
                                  1 if args.warmup else 0)
@@ -345,6 +370,31 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_rows, r)
     print(json.dumps(out), flush=True)
+
+
+def mixed_summary(x, ms, flops, m, n, s, S_h, nr, orth_err):
+    import numpy as np
+    nrx = x["nr"]
+    Sx = x["S"].cpu().numpy()
+    kx = min(nrx, nr)
+    return {
+        "precision": "mixed (FP32 leaf QR, FP64 tree + SVD, FP64 Rayleigh-Ritz refinement)",
+        "storage": "f32",
+        "ms_per_step": round(x["ms"], 4),
+        "tflops": round(flops / (x["ms"] * 1e-3) / 1e12, 4),
+        "gbps": round((2.0 * 4 * m * n + 4.0 * m * nrx) / (x["ms"] * 1e-3) / 1e9, 2),
+        "speedup_vs_fp64": round(ms / x["ms"], 3),
+        "n_r": nrx,
+        "sigma_rel_err_vs_fp64_run": float(np.max(np.abs(Sx[:kx] - S_h[:kx]) / S_h[:kx])) if kx else 0.0,
+        "sigma_rel_err_vs_exact": float(np.max(np.abs(Sx[:kx] - s[:kx]) / s[:kx])) if kx else 0.0,
+        "orth_err_U": orth_err(x["U"], nrx),
+        "jacobi_sweeps_first": x["sweeps"],
+        "phase_ms": {"leaf_qr_fp32": round(x["phases"]["leaf_qr"], 4),
+                     "tree_combine": round(x["phases"]["tree_combine"], 4),
+                     "small_svd": round(x["phases"]["small_svd"], 4),
+                     "refine_project_gram_eig": round(x["phases"]["tree_propagate"], 4),
+                     "form_u": round(x["phases"]["leaf_apply"], 4)},
+    }
 
 
 if __name__ == "__main__":
