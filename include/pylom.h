@@ -94,6 +94,14 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
  *   "timing"       k > 0: record HIP events around the phases of every
  *                  pod/tsvd call in a ring of k call slots (read back with
  *                  pylom_phase_times); 0 = off (default).
+ *   "blocked_from" n at which pod/tsvd/tsqr switch to the column-blocked
+ *                  TSQR (2..2049, default 1025): every leaf and every tree
+ *                  combine is then a blocked Householder QR over panels of 64
+ *                  columns (the local QR of Alg. 1 as LAPACK blocks it), the
+ *                  leaf height defaults to ceil(m / CUs) rounded up to 64,
+ *                  and the working copy of D, the reflectors of every panel
+ *                  and the tree pairs stay in the workspace.  Smaller values
+ *                  route narrow problems through the same path (tests).
  * Unknown keys return PYLOM_EINVAL. */
 int pylom_set_option(pylom_ctx ctx, const char* key, int64_t value);
 int pylom_get_option(pylom_ctx ctx, const char* key, int64_t* value);
@@ -122,7 +130,9 @@ const char* pylom_last_error(pylom_ctx ctx);
  *   n_r    one int64 in device memory: N_r.
  * Sign convention: each (u_i, v_i) is signed so that the largest-magnitude
  * entry of v_i (lowest index on ties) is positive.  Requires m >= n >= 1 and
- * n <= 1024.
+ * n <= 2048 (n >= "blocked_from": the column-blocked TSQR; there the modes of
+ * an exactly zero singular value of an exactly rank-deficient panel may come
+ * out as zero columns of U).
  * PYLOM_MIXED (D must be R32): FP32 leaf QR without reflector storage, FP64
  * tree and SVD of R, then a Rayleigh-Ritz refinement against D in FP64 on the
  * k = min(n, N0 + max(8, N0/4)) leading right singular vectors V_k of that SVD
@@ -130,7 +140,8 @@ const char* pylom_last_error(pylom_ctx ctx);
  * (lambda, w) of Z^T Z give S[i] = sqrt(lambda_i) (i < k; S[i] for i >= k is
  * the unrefined value), v_i = V_k w_i, u_i = Z w_i / S[i]; N_r <= k.  The call
  * synchronises the stream once, after the first SVD, to read N0.  Modes with
- * S[i] = 0 get a zero U column.
+ * S[i] = 0 get a zero U column.  On the column-blocked path the working copy
+ * of D is FP32 and k may not exceed 1024 (PYLOM_ENOTSUP otherwise).
  * Returns PYLOM_WNOCONV (>0, outputs written) if the Jacobi SVD did not
  * converge within max_sweeps -- this is only known after the stream is
  * synchronised, so the return value of an asynchronous call is 0 and the
@@ -166,7 +177,7 @@ int pylom_matmul(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int trans_a,
 
 /* One instance of a batched POD (the arguments of pylom_pod). */
 typedef struct {
-  int64_t m, n;        /* shape, m >= n >= 1, n <= 1024                      */
+  int64_t m, n;        /* shape, m >= n >= 1, n < "blocked_from"             */
   const void* D;       /* m x n snapshots (storage type of the batch), ldd   */
   int64_t ldd;
   int remove_mean;     /* Alg. 2 mean removal                                 */
@@ -201,7 +212,8 @@ int pylom_pod_batched(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t
  * minimiser, over b in {128, 256, ..., 32768} with b >= n, of a latency model
  * of the stacked QR (leaf critical path of ceil(b / s) chunks, waves of leaves
  * over the device's compute units, ceil(log2 P) dependent tree levels and one
- * launch per level).  Host only. */
+ * launch per level).  For n >= "blocked_from", ceil(m / CUs) rounded up to a
+ * multiple of 64 (at least n).  Host only; n <= 2048. */
 int64_t pylom_tune_block_rows(pylom_ctx ctx, int64_t m, int64_t n);
 
 /* SPOD (Alg. 6; Sec. 2.3, Eq. csdimp with the SVD of the spectral matrix).

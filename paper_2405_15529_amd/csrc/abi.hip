@@ -30,6 +30,7 @@ struct pylom_ctx_s {
   int64_t block_rows = 0;
   int64_t max_sweeps = 60;
   int64_t ws_cap_mb = 0;
+  int64_t blocked_from = 1025;  // n at which the column-blocked TSQR takes over
   int* status_dev = nullptr;  // Jacobi status pairs (sweeps, barrier timeout) of the last call
   int status_valid = 0;
   int status_pairs = 1;        // 2 after a mixed-precision call (SVD of R + Gram eigen)
@@ -75,6 +76,10 @@ static int hip_fail(pylom_ctx c, hipError_t e, const char* where) {
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int kEvPerSlot = 8;  // timing events recorded per call
+constexpr int64_t kMaxN = 2048;  // widest snapshot count the kernels take
+constexpr int64_t kPW = 64;      // panel width of the column-blocked TSQR
+constexpr int64_t kZcap = 1024;  // refinement width planned for the blocked mixed path
+constexpr int64_t kTF = 256;     // elements of one 16 x 16 compact-WY T factor
 constexpr int kPhases = 6;     // phases reported by pylom_phase_times
 
 // ---------------------------------------------------------------------------
@@ -149,6 +154,9 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
   } else if (!std::strcmp(key, "ws_cap_mb")) {
     if (v < 0) return fail(c, PYLOM_EINVAL, "ws_cap_mb must be >= 0");
     c->ws_cap_mb = v;
+  } else if (!std::strcmp(key, "blocked_from")) {
+    if (v < 2 || v > kMaxN + 1) return fail(c, PYLOM_EINVAL, "blocked_from must be in [2, 2049]");
+    c->blocked_from = v;
   } else if (!std::strcmp(key, "streams")) {
     if (v < 1 || v > 16) return fail(c, PYLOM_EINVAL, "streams must be in [1, 16]");
     c->streams = v;
@@ -180,6 +188,8 @@ extern "C" int pylom_get_option(pylom_ctx c, const char* key, int64_t* v) {
     *v = c->max_sweeps;
   else if (!std::strcmp(key, "ws_cap_mb"))
     *v = c->ws_cap_mb;
+  else if (!std::strcmp(key, "blocked_from"))
+    *v = c->blocked_from;
   else if (!std::strcmp(key, "timing"))
     *v = c->timing;
   else if (!std::strcmp(key, "streams"))
@@ -251,7 +261,15 @@ struct Plan {
   bool mixed;
   size_t oR32, oS0, oVT0, oNr0, oZ, oG, oPart, oLam, oWT, oUR2, oNr2, oM, oSvd2;
   size_t part_bytes;
+  int64_t zcap;  // widest refinement subspace the workspace holds
+  // column-blocked TSQR (wide problems): panels of kPW columns
+  bool blocked;
+  int64_t K, nch_l, nch_p, wcap;
+  QrGeom gp, gpl;  // geometry of a full panel and of the last panel
+  size_t oWk, oTl, oPSl, oPb, oTp, oPSp, oXp, oXu;
 };
+
+static int64_t level_pairs(int64_t P, int64_t h) { return (P - h + 2 * h - 1) / (2 * h); }
 
 // Leaf height model.  The stacked QR of a leaf is a chain of ceil(b / s)
 // chunks; each chunk factors n columns one after another (about 1.6k cycles
@@ -289,19 +307,33 @@ static int64_t tune_block_rows(int64_t m, int64_t n, int ncu) {
   return best > 0 ? best : n;
 }
 
+// Leaf height of the column-blocked path: one leaf per CU (the panel
+// factorisations run one workgroup per leaf), rows a multiple of the chunk.
+static int64_t blocked_block_rows(int64_t m, int64_t n, int ncu) {
+  int64_t b = (m + ncu - 1) / (ncu > 0 ? ncu : 1);
+  if (b < n) b = n;
+  return (b + kPW - 1) / kPW * kPW;
+}
+
 extern "C" int64_t pylom_tune_block_rows(pylom_ctx c, int64_t m, int64_t n) {
-  if (!c || n < 1 || m < n || n > 1024) return PYLOM_EINVAL;
+  if (!c || n < 1 || m < n || n > kMaxN) return PYLOM_EINVAL;
+  if (n >= c->blocked_from) return blocked_block_rows(m, n, c->ncu);
   return tune_block_rows(m, n, c->ncu);
 }
+
+static int make_blocked_plan(pylom_ctx c, Plan* p, bool mixed);
 
 static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
                      bool mixed = false) {
   if (n < 1 || m < n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
-  if (n > 1024) return fail(c, PYLOM_ENOTSUP, "n > 1024 is not supported");
+  if (n > kMaxN) return fail(c, PYLOM_ENOTSUP, "n > 2048 is not supported");
   p->mixed = mixed;
+  p->blocked = false;
+  p->zcap = n;
   if (mixed) store_q = false;
   p->m = m;
   p->n = n;
+  if (n >= c->blocked_from) return make_blocked_plan(c, p, mixed);
   int64_t b = c->block_rows > 0 ? c->block_rows : tune_block_rows(m, n, c->ncu);
   if (b < n) b = n;
   int64_t P = m / b;
@@ -372,6 +404,118 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
     off = align_up(off + sizeof(int64_t));
     p->oM = off;
     off = align_up(off + sizeof(double) * (size_t)n * n);
+    p->oSvd2 = off;
+    off = align_up(off + svd2);
+  }
+  p->total = off;
+  return PYLOM_OK;
+}
+
+// Wide problems (n >= blocked_from): the leaves and the tree combines are
+// column-blocked QRs (blocked.hip).  Workspace, in order: the working copy of
+// D (compute type), the leaf T factors and panel states (per panel), the
+// FP64 R of every leaf (tree state in place), the tree pairs with their T
+// factors and panel states, the propagation W, and for FP64 the X buffers of
+// the propagation; the mixed path adds its refinement buffers (Z for at most
+// kZcap columns).
+static int make_blocked_plan(pylom_ctx c, Plan* p, bool mixed) {
+  const int64_t m = p->m, n = p->n;
+  p->blocked = true;
+  int64_t b = c->block_rows > 0 ? c->block_rows : blocked_block_rows(m, n, c->ncu);
+  if (b < n) b = n;
+  int64_t P = m / b;
+  if (P < 1) P = 1;
+  if (P > 65535) return fail(c, PYLOM_ENOTSUP, "too many leaves for the blocked path");
+  p->b = b;
+  p->P = P;
+  p->last_rows = m - (P - 1) * b;
+  p->K = (n + kPW - 1) / kPW;
+  const int es = mixed ? 4 : 8;
+  if (!qr_geom((int)(n < kPW ? n : kPW), es, &p->gp) ||
+      !qr_geom((int)(n - (p->K - 1) * kPW), es, &p->gpl) || p->gp.s != kPW || p->gpl.s != kPW)
+    return fail(c, PYLOM_ENOTSUP, "no panel geometry");
+  QrGeom g8;
+  if (!qr_geom((int)(n - (p->K - 1) * kPW), 8, &g8) || g8.s != kPW)
+    return fail(c, PYLOM_ENOTSUP, "no panel geometry");
+  if (!jacobi_plan((int)n, &p->jp)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
+  p->g = p->gp;
+  p->nch_l = (p->last_rows + kPW - 1) / kPW;
+  p->nch_p = (2 * n + kPW - 1) / kPW;
+  p->nch_leaf = p->nch_l;
+  p->nch_tree = p->nch_p;
+  int64_t lv = 0;
+  for (int64_t h = 1; h < P; h *= 2) ++lv;
+  p->levels = lv;
+  const int64_t np_all = P - 1;
+  const size_t tpp = (size_t)kTF;  // one T factor
+  p->wcap = n < 256 ? n : 256;
+  size_t off = 0;
+  p->oV = p->oTleaf = p->oTtree = 0;
+  p->oWk = off;
+  off = align_up(off + (size_t)es * m * n);
+  p->oTl = off;
+  off = align_up(off + (size_t)es * p->K * P * p->nch_l * 4 * tpp);
+  p->oPSl = off;
+  off = align_up(off + (size_t)es * p->K * P * kPW * kPW);
+  p->oR = off;
+  off = align_up(off + sizeof(double) * (size_t)P * n * n);
+  p->oPb = off;
+  off = align_up(off + sizeof(double) * (size_t)np_all * 2 * n * n);
+  p->oTp = off;
+  off = align_up(off + sizeof(double) * (size_t)p->K * np_all * p->nch_p * 4 * tpp);
+  p->oPSp = off;
+  off = align_up(off + sizeof(double) * (size_t)p->K * np_all * kPW * kPW);
+  p->oW = off;
+  off = align_up(off + sizeof(double) * (size_t)P * n * n);
+  p->oMean = off;
+  off = align_up(off + sizeof(double) * (size_t)m);
+  p->oSig = off;
+  off = align_up(off + sizeof(double) * (size_t)n);
+  p->oSvd = off;
+  off = align_up(off + jacobi_ws_bytes(p->jp, (int)c->max_sweeps));
+  p->oXp = p->oXu = off;
+  if (!mixed) {
+    p->oXp = off;
+    off = align_up(off + sizeof(double) * (size_t)level_pairs(P, 1) * 2 * n * n);
+    p->oXu = off;
+    off = align_up(off + sizeof(double) * (size_t)m * p->wcap);
+  } else {
+    p->zcap = n < kZcap ? n : kZcap;
+    size_t svd2 = 0, part = 0;
+    for (int64_t k = 1; k <= p->zcap; ++k) {
+      JacobiPlan jk;
+      if (!jacobi_plan((int)k, &jk)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
+      const size_t wb = jacobi_ws_bytes(jk, (int)c->max_sweeps);
+      if (wb > svd2) svd2 = wb;
+      const size_t pb = sizeof(double) * (size_t)matmul_tn_splits(m, k, k) * k * k;
+      if (pb > part) part = pb;
+    }
+    const int64_t zc = p->zcap;
+    p->part_bytes = part;
+    p->oR32 = off;
+    off = align_up(off + sizeof(float) * (size_t)P * n * n);
+    p->oS0 = off;
+    off = align_up(off + sizeof(double) * (size_t)n);
+    p->oVT0 = off;
+    off = align_up(off + sizeof(double) * (size_t)n * n);
+    p->oNr0 = off;
+    off = align_up(off + sizeof(int64_t));
+    p->oZ = off;
+    off = align_up(off + sizeof(double) * (size_t)m * zc);
+    p->oG = off;
+    off = align_up(off + sizeof(double) * (size_t)zc * zc);
+    p->oPart = off;
+    off = align_up(off + part);
+    p->oLam = off;
+    off = align_up(off + sizeof(double) * (size_t)zc);
+    p->oWT = off;
+    off = align_up(off + sizeof(double) * (size_t)zc * zc);
+    p->oUR2 = off;
+    off = align_up(off + sizeof(double) * (size_t)zc * zc);
+    p->oNr2 = off;
+    off = align_up(off + sizeof(int64_t));
+    p->oM = off;
+    off = align_up(off + sizeof(double) * (size_t)zc * zc);
     p->oSvd2 = off;
     off = align_up(off + svd2);
   }
@@ -465,11 +609,21 @@ static double* keep_mean(const Exec& x, const Plan& p) {
 #define EVREC(j) \
   if (x.evs) HIPCHK(c, hipEventRecord(x.evs[j], x.st), "hipEventRecord")
 
+static int enqueue_fp64_blocked(pylom_ctx c, const Exec& x, const Plan& p, pylom_dtype dtype,
+                                const void* D, int64_t ldd, int remove_mean, double residual,
+                                void* mean, void* U, int64_t ldu, double* S, double* VT,
+                                int64_t ldvt, int64_t* n_r);
+static int enqueue_mixed1_blocked(pylom_ctx c, const Exec& x, const Plan& p, const void* D,
+                                  int64_t ldd, int remove_mean, double residual);
+
 // FP64 POD / TSVD: Alg. 2 (mean) -> Alg. 1 (leaf QR, tree) -> Eq. svdqr2 ->
 // propagation -> Eq. svdqr3.
 static int enqueue_fp64(pylom_ctx c, const Exec& x, const Plan& p, pylom_dtype dtype,
                         const void* D, int64_t ldd, int remove_mean, double residual, void* mean,
                         void* U, int64_t ldu, double* S, double* VT, int64_t ldvt, int64_t* n_r) {
+  if (p.blocked)
+    return enqueue_fp64_blocked(c, x, p, dtype, D, ldd, remove_mean, residual, mean, U, ldu, S, VT,
+                                ldvt, n_r);
   const int64_t m = p.m, n = p.n;
   double* V = (double*)(x.ws + p.oV);
   double* Tleaf = (double*)(x.ws + p.oTleaf);
@@ -504,10 +658,206 @@ static int enqueue_fp64(pylom_ctx c, const Exec& x, const Plan& p, pylom_dtype d
   return PYLOM_OK;
 }
 
+// ---- column-blocked sequences (n >= blocked_from) ---------------------------
+static size_t t_slot(const Plan& p, bool pairs) {  // T-factor elements per panel
+  return (size_t)(pairs ? p.P - 1 : p.P) * (pairs ? p.nch_p : p.nch_l) * 4 * kTF;
+}
+static size_t ps_slot(const Plan& p, bool pairs) {  // panel-state elements per panel
+  return (size_t)(pairs ? p.P - 1 : p.P) * kPW * kPW;
+}
+
+// Blocked QR of nprob problems stored in a working matrix of row stride n
+// (problem l: rows [l bstride, ...), at most mrows rows in all).  R of
+// problem l goes to Rout + l rstride (row stride n).  Tbase / PSbase point at
+// the group's first problem inside the slot of panel 0.
+template <typename T>
+static int blocked_qr(pylom_ctx c, hipStream_t st, const Plan& p, T* Wk, int64_t nprob,
+                      int64_t bstride, int64_t mrows, bool pairs, T* Tbase, int64_t nch,
+                      T* PSbase, T* Rout, int64_t rstride) {
+  const int64_t n = p.n;
+  const size_t tps = t_slot(p, pairs), pps = ps_slot(p, pairs);
+  for (int64_t k = 0; k < p.K; ++k) {
+    const int64_t c0 = k * kPW;
+    const int kw = (int)((n - c0 < kPW) ? n - c0 : kPW);
+    const QrGeom& g = (k == p.K - 1) ? p.gpl : p.gp;
+    // a pair's panel k touches the first (k + 1) 64 rows of each triangle,
+    // a prefix of the interleaved layout
+    const int64_t rows_lim = pairs ? 2 * ((c0 + kPW < n) ? c0 + kPW : n) : 0;
+    T* Tk = Tbase + k * tps;
+    T* PSk = PSbase + k * pps;
+    HIPCHK(c, launch_panel_qr<T>(g, Wk + c0, n, mrows, bstride, nprob, rows_lim, Tk, nch, PSk, st),
+           "panel QR");
+    if (c0 + kw < n) {
+      PanelApplyArgs<T> a{};
+      a.kw = kw; a.npan = g.npanels; a.nlv = nprob; a.b = bstride; a.m = mrows;
+      a.rows_lim = rows_lim; a.V = Wk + c0; a.ldv = n; a.Tf = Tk; a.nch = nch;
+      a.X = Wk + c0 + kw; a.ldx = n; a.ncols = n - c0 - kw; a.nc_dev = nullptr; a.nc_off = 0;
+      a.x_zero = 0; a.S = Rout + c0 * n + c0 + kw; a.s_leaf = rstride; a.s_ld = n;
+      HIPCHK(c, launch_panel_apply<T>(a, false, st), "trailing update");
+    }
+  }
+  HIPCHK(c, launch_assemble_r<T>((int)n, nprob, PSbase, (int64_t)pps, Rout, rstride, st),
+         "R assembly");
+  return PYLOM_OK;
+}
+
+// Leaf level in the compute type T (FP64, or FP32 for the mixed path).
+template <typename T>
+static int blocked_leaves(pylom_ctx c, hipStream_t st, const Plan& p, char* ws, T* Rout) {
+  return blocked_qr<T>(c, st, p, (T*)(ws + p.oWk), p.P, p.b, p.m, false, (T*)(ws + p.oTl),
+                       p.nch_l, (T*)(ws + p.oPSl), Rout, p.n * p.n);
+}
+
+// The reduction tree of Alg. 1 in FP64 on the leaf R's (ws + oR): each level
+// packs its pairs and runs the blocked QR on them; R_j is overwritten by the
+// combined R.
+static int blocked_tree(pylom_ctx c, hipStream_t st, const Plan& p, char* ws) {
+  const int64_t n = p.n;
+  double* R = (double*)(ws + p.oR);
+  int64_t base = 0;
+  for (int64_t h = 1; h < p.P; h *= 2) {
+    const int64_t np = level_pairs(p.P, h);
+    double* Pb = (double*)(ws + p.oPb) + base * 2 * n * n;
+    HIPCHK(c, launch_pair_pack((int)n, h, np, R, Pb, st), "pair pack");
+    const int rc = blocked_qr<double>(c, st, p, Pb, np, 2 * n, np * 2 * n, true,
+                                      (double*)(ws + p.oTp) + base * p.nch_p * 4 * kTF,
+                                      p.nch_p, (double*)(ws + p.oPSp) + base * kPW * kPW, R,
+                                      2 * h * n * n);
+    if (rc) return rc;
+    base += np;
+  }
+  return PYLOM_OK;
+}
+
+// Down-tree propagation: W_0 (ws + oW, n x ncols, row stride n) through every
+// level's pair Q, leaving W_j for every leaf j.  Columns >= *nc_dev are not
+// touched (nc_dev may be null).
+static int blocked_propagate(pylom_ctx c, hipStream_t st, const Plan& p, char* ws,
+                             const int64_t* nc_dev, int64_t ncols) {
+  const int64_t n = p.n;
+  double* W = (double*)(ws + p.oW);
+  double* Xp = (double*)(ws + p.oXp);
+  std::vector<int64_t> bases;
+  int64_t base = 0;
+  for (int64_t h = 1; h < p.P; h *= 2) {
+    bases.push_back(base);
+    base += level_pairs(p.P, h);
+  }
+  const size_t tps = t_slot(p, true);
+  for (int64_t li = (int64_t)bases.size() - 1; li >= 0; --li) {
+    const int64_t h = (int64_t)1 << li;
+    const int64_t np = level_pairs(p.P, h);
+    const double* Pb = (double*)(ws + p.oPb) + bases[(size_t)li] * 2 * n * n;
+    const double* Tl = (double*)(ws + p.oTp) + bases[(size_t)li] * p.nch_p * 4 * kTF;
+    for (int64_t k = p.K - 1; k >= 0; --k) {
+      const int64_t c0 = k * kPW;
+      const int kw = (int)((n - c0 < kPW) ? n - c0 : kPW);
+      const QrGeom& g = (k == p.K - 1) ? p.gpl : p.gp;
+      PanelApplyArgs<double> a{};
+      a.kw = kw; a.npan = g.npanels; a.nlv = np; a.b = 2 * n; a.m = np * 2 * n;
+      a.rows_lim = 2 * ((c0 + kPW < n) ? c0 + kPW : n);
+      a.V = Pb + c0; a.ldv = n; a.Tf = Tl + k * tps; a.nch = p.nch_p;
+      a.X = Xp; a.ldx = n; a.ncols = ncols; a.nc_dev = nc_dev; a.nc_off = 0;
+      a.x_zero = (k == p.K - 1); a.S = W + c0 * n; a.s_leaf = 2 * h * n * n; a.s_ld = n;
+      HIPCHK(c, launch_panel_apply<double>(a, true, st), "tree propagation");
+    }
+    HIPCHK(c, launch_pair_unpack((int)n, h, np, Xp, n, W, n, ncols, nc_dev, st), "pair unpack");
+  }
+  return PYLOM_OK;
+}
+
+// U (m x ncols) = Q_leaf W_j for every leaf, in column groups of wcap through
+// the FP64 buffer ws + oXu, stored in the output type.
+static int blocked_leaf_apply(pylom_ctx c, hipStream_t st, const Plan& p, char* ws,
+                              const int64_t* nc_dev, int64_t ncols, void* U, int out_f64,
+                              int64_t ldu) {
+  const int64_t n = p.n;
+  double* W = (double*)(ws + p.oW);
+  double* Xu = (double*)(ws + p.oXu);
+  const double* Wk = (const double*)(ws + p.oWk);
+  const double* Tl = (const double*)(ws + p.oTl);
+  const size_t tps = t_slot(p, false);
+  for (int64_t col0 = 0; col0 < ncols; col0 += p.wcap) {
+    const int64_t ncg = (ncols - col0 < p.wcap) ? ncols - col0 : p.wcap;
+    for (int64_t k = p.K - 1; k >= 0; --k) {
+      const int64_t c0 = k * kPW;
+      const int kw = (int)((n - c0 < kPW) ? n - c0 : kPW);
+      const QrGeom& g = (k == p.K - 1) ? p.gpl : p.gp;
+      PanelApplyArgs<double> a{};
+      a.kw = kw; a.npan = g.npanels; a.nlv = p.P; a.b = p.b; a.m = p.m; a.rows_lim = 0;
+      a.V = Wk + c0; a.ldv = n; a.Tf = Tl + k * tps; a.nch = p.nch_l;
+      a.X = Xu; a.ldx = p.wcap; a.ncols = ncg; a.nc_dev = nc_dev; a.nc_off = col0;
+      a.x_zero = (k == p.K - 1); a.S = W + c0 * n + col0; a.s_leaf = n * n; a.s_ld = n;
+      HIPCHK(c, launch_panel_apply<double>(a, true, st), "leaf apply");
+    }
+    HIPCHK(c, launch_copy_cols(out_f64, p.m, col0, ncg, ncols, nc_dev, Xu, p.wcap, U, ldu, st),
+           "U out");
+  }
+  return PYLOM_OK;
+}
+
+static int enqueue_fp64_blocked(pylom_ctx c, const Exec& x, const Plan& p, pylom_dtype dtype,
+                                const void* D, int64_t ldd, int remove_mean, double residual,
+                                void* mean, void* U, int64_t ldu, double* S, double* VT,
+                                int64_t ldvt, int64_t* n_r) {
+  const int64_t m = p.m, n = p.n;
+  double* Rbuf = (double*)(x.ws + p.oR);
+  double* meanws = (double*)(x.ws + p.oMean);
+  const int in64 = dtype == PYLOM_R64;
+  hipStream_t st = x.st;
+  EVREC(0);
+  HIPCHK(c, launch_make_work(in64, 1, m, (int)n, D, ldd, remove_mean, meanws, x.ws + p.oWk, st),
+         "working copy");
+  EVREC(1);
+  int rc = blocked_leaves<double>(c, st, p, x.ws, Rbuf);
+  if (rc) return rc;
+  EVREC(2);
+  rc = blocked_tree(c, st, p, x.ws);
+  if (rc) return rc;
+  EVREC(3);
+  HIPCHK(c, launch_small_svd(p.jp, Rbuf, x.max_sweeps, x.ws + p.oSvd, S, VT, ldvt,
+                             (double*)(x.ws + p.oW), residual, n_r, x.status, st, x.coop),
+         "small SVD");
+  EVREC(4);
+  rc = blocked_propagate(c, st, p, x.ws, n_r, n);
+  if (rc) return rc;
+  EVREC(5);
+  rc = blocked_leaf_apply(c, st, p, x.ws, n_r, n, U, in64, ldu);
+  if (rc) return rc;
+  if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, in64, m, st), "mean out");
+  EVREC(6);
+  return PYLOM_OK;
+}
+
+static int enqueue_mixed1_blocked(pylom_ctx c, const Exec& x, const Plan& p, const void* D,
+                                  int64_t ldd, int remove_mean, double residual) {
+  const int64_t m = p.m, n = p.n;
+  hipStream_t st = x.st;
+  EVREC(0);
+  HIPCHK(c, launch_make_work(0, 0, m, (int)n, D, ldd, remove_mean, keep_mean(x, p),
+                             x.ws + p.oWk, st), "working copy (FP32)");
+  EVREC(1);
+  int rc = blocked_leaves<float>(c, st, p, x.ws, (float*)(x.ws + p.oR32));
+  if (rc) return rc;
+  HIPCHK(c, launch_cast_f32_f64((const float*)(x.ws + p.oR32), (double*)(x.ws + p.oR), p.P * n * n,
+                                st), "R to FP64");
+  EVREC(2);
+  rc = blocked_tree(c, st, p, x.ws);
+  if (rc) return rc;
+  EVREC(3);
+  HIPCHK(c, launch_small_svd(p.jp, (double*)(x.ws + p.oR), x.max_sweeps, x.ws + p.oSvd,
+                             keep_S0(x, p), keep_VT0(x, p), n, (double*)(x.ws + p.oW), residual,
+                             x.nr0 ? x.nr0 : (int64_t*)(x.ws + p.oNr0), x.status, st, x.coop),
+         "small SVD");
+  if (x.evs) HIPCHK(c, hipEventRecord(x.evs[7], st), "hipEventRecord");
+  return PYLOM_OK;
+}
+
 // Mixed precision, phase 1: FP32 leaf QR (R only, mean fused), FP64 tree and
 // SVD of R: S0, VT0 and N0 in the workspace.
 static int enqueue_mixed1(pylom_ctx c, const Exec& x, const Plan& p, const void* D, int64_t ldd,
                           int remove_mean, double residual) {
+  if (p.blocked) return enqueue_mixed1_blocked(c, x, p, D, ldd, remove_mean, residual);
   const int64_t m = p.m, n = p.n;
   hipStream_t st = x.st;
   EVREC(0);
@@ -558,6 +908,7 @@ static int enqueue_mixed2(pylom_ctx c, const Exec& x, const Plan& p, const void*
     EVREC(5);
   } else {
     const int64_t k = refine_width(nr_first, n);
+    if (k > p.zcap) return fail(c, PYLOM_ENOTSUP, "refinement width exceeds the planned workspace");
     JacobiPlan jk;
     if (!jacobi_plan((int)k, &jk)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
     const int64_t ns = matmul_tn_splits(m, k, k);
@@ -798,6 +1149,8 @@ extern "C" int pylom_pod_batched(pylom_ctx c, pylom_dtype dtype, pylom_prec prec
       return fail(c, PYLOM_ESHAPE, "leading dimension < n");
     rc = make_plan(c, q.m, q.n, !mixed, &L.plans[(size_t)i], mixed);
     if (rc) return rc;
+    if (L.plans[(size_t)i].blocked)
+      return fail(c, PYLOM_ENOTSUP, "batched problems need n below the blocked_from option");
     cost[(size_t)i] = leaf_model(q.m, q.n, L.plans[(size_t)i].b, c->ncu);
   }
   if (count == 0) return PYLOM_OK;
@@ -897,6 +1250,28 @@ extern "C" int pylom_tsqr(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64
   if (rc) return rc;
   char* ws = (char*)c->ws;
   const bool wq = Q != nullptr;
+  if (p.blocked) {
+    hipStream_t st = c->stream;
+    const int in64 = dtype == PYLOM_R64;
+    double* Rbuf = (double*)(ws + p.oR);
+    double* signs = (double*)(ws + p.oSig);
+    HIPCHK(c, launch_make_work(in64, 1, m, (int)n, A, lda, 0, nullptr, ws + p.oWk, st),
+           "working copy");
+    rc = blocked_leaves<double>(c, st, p, ws, Rbuf);
+    if (rc) return rc;
+    rc = blocked_tree(c, st, p, ws);
+    if (rc) return rc;
+    HIPCHK(c, launch_r_out(Rbuf, n, R, ldr, signs, st), "R out");
+    if (wq) {
+      HIPCHK(c, launch_eye((double*)(ws + p.oW), n, n, st), "identity");
+      rc = blocked_propagate(c, st, p, ws, nullptr, n);
+      if (rc) return rc;
+      rc = blocked_leaf_apply(c, st, p, ws, nullptr, n, Q, in64, ldq);
+      if (rc) return rc;
+      HIPCHK(c, launch_q_signs(Q, in64, m, n, ldq, signs, st), "Q signs");
+    }
+    return PYLOM_OK;
+  }
   double* V = wq ? (double*)(ws + p.oV) : nullptr;
   double* Tleaf = (double*)(ws + p.oTleaf);
   double* Rbuf = (double*)(ws + p.oR);

@@ -27,6 +27,52 @@ bool qr_geom(int n, int esize, QrGeom* g);
 size_t qr_lds_bytes(const QrGeom& g, int esize);
 size_t apply_lds_bytes(const QrGeom& g, int esize);
 
+// ---- column-blocked TSQR for wide problems (blocked.hip) ----------------------
+// One panel (kw <= 64 columns, starting at Wk) of every leaf of a working
+// matrix with row stride ldw: the stacked QR with a zero initial state;
+// reflector tails overwrite the panel in place, T factors go to
+// Tf[((l nch + c) npan + p) 256], the kw x kw state of leaf l to
+// Rstate + l kw^2.  At most rows_lim rows per leaf take part (0: all).
+template <typename T>
+hipError_t launch_panel_qr(const QrGeom& g, T* Wk, int64_t ldw, int64_t m, int64_t b, int64_t P,
+                           int64_t rows_lim, T* Tf, int64_t nch, T* Rstate, hipStream_t st);
+
+template <typename T>
+struct PanelApplyArgs {
+  int kw, npan;                 // panel width and its 16-column sub-panels
+  int64_t nlv, b, m, rows_lim;  // leaves, leaf row stride, total rows, row cap (0: none)
+  const T* V;                   // reflector tails (row stride ldv), rows as X
+  int64_t ldv;
+  const T* Tf;                  // T factors, nch chunks per leaf
+  int64_t nch;
+  T* X;                         // rows updated in place (row stride ldx)
+  int64_t ldx;
+  int64_t ncols;                // columns of X (and of the state)
+  const int64_t* nc_dev;        // optional device bound: columns < *nc_dev - nc_off
+  int64_t nc_off;
+  int x_zero;                   // the rows of X start at zero and are not read
+  T* S;                         // state of leaf l: S + l s_leaf, row stride s_ld
+  int64_t s_leaf, s_ld;
+};
+size_t panel_apply_lds_bytes(int esize);
+// fwd = false: X <- Q_k^T X for the trailing columns, the final state is
+// written to S; fwd = true: [*; X] <- Q_k [S; X], the state is read from S.
+template <typename T>
+hipError_t launch_panel_apply(const PanelApplyArgs<T>& a, bool fwd, hipStream_t st);
+hipError_t launch_make_work(int in_f64, int out_f64, int64_t m, int n, const void* D, int64_t ldd,
+                            int remove_mean, double* mean_out, void* W, hipStream_t st);
+hipError_t launch_pair_pack(int n, int64_t h, int64_t npairs, const double* R, double* Pb,
+                            hipStream_t st);
+hipError_t launch_pair_unpack(int n, int64_t h, int64_t npairs, const double* Xp, int64_t ldx,
+                              double* W, int64_t ldw, int64_t ncols, const int64_t* nc_dev,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_assemble_r(int n, int64_t nprob, const T* PSt, int64_t pstride, T* R,
+                             int64_t rstride, hipStream_t st);
+hipError_t launch_copy_cols(int out_f64, int64_t m, int64_t col0, int64_t ncg, int64_t ncols,
+                            const int64_t* nc_dev, const double* X, int64_t ldx, void* U,
+                            int64_t ldu, hipStream_t st);
+
 // ---- leaf QR (Alg. 1, local qr of each row block) ----------------------------
 // One workgroup per leaf j: rows [j*b, j*b + b) (the last leaf takes the
 // remainder), optional fused mean removal (Alg. 2) into mean_ws (double, m).

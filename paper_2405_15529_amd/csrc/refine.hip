@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_rr_spectrum(int n, int k, const double*
                                                      const double* __restrict__ lam,
                                                      double residual, double* __restrict__ S,
                                                      int64_t* __restrict__ nr) {
-  __shared__ double tail[1025];
+  __shared__ double tail[2049];
   const int tid = threadIdx.x;
   for (int c = tid; c < n; c += 256) {
     double s = S0[c];
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(256) void k_rr_vectors(int n, int k, const double* 
                                                     const int64_t* __restrict__ nr,
                                                     double* __restrict__ VT, int64_t ldvt,
                                                     double* __restrict__ M) {
-  __shared__ double v[1024];
+  __shared__ double v[2048];
   __shared__ double best_v[256];
   __shared__ int best_i[256];
   const int c = blockIdx.x;

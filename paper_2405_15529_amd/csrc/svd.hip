@@ -31,10 +31,10 @@
 namespace pylom {
 
 constexpr int JT = 256;     // threads per Jacobi workgroup
-constexpr int JRPL = 16;    // max column rows per lane
+constexpr int JRPL = 32;    // max column rows per lane (16 up to n = 1024)
 
 bool jacobi_plan(int n, JacobiPlan* p) {
-  if (n < 1 || n > 1024) return false;
+  if (n < 1 || n > 2048) return false;
   // block width w (even, 4..16): a pair is handled by 256/w lanes of one wave,
   // each holding at most JRPL rows of a column
   int w = 16;
@@ -152,24 +152,24 @@ __device__ __forceinline__ int rr_player(int i, int st, int nplayers) {
   return ((i - 1 + st) % (nplayers - 1)) + 1;
 }
 
-template <int LPP>
-__device__ __forceinline__ double col_norm2(const double (&a)[JRPL], int rpl) {
+template <int LPP, int JR>
+__device__ __forceinline__ double col_norm2(const double (&a)[JR], int rpl) {
   double x = 0.0;
 #pragma unroll
-  for (int k = 0; k < JRPL; ++k)
+  for (int k = 0; k < JR; ++k)
     if (k < rpl) x += a[k] * a[k];
   return gsum<LPP>(x);
 }
 
 // Rotate the pair (a, b) held by an LPP-lane group (RPL rows per lane each)
 // if it is not yet orthogonal; norms na, nb are updated.  Returns 1 if rotated.
-template <int LPP>
-__device__ __forceinline__ int jacobi_pair(double (&a)[JRPL], double (&va)[JRPL], double (&b)[JRPL],
-                                           double (&vb)[JRPL], double& na, double& nb, int rpl_a,
+template <int LPP, int JR>
+__device__ __forceinline__ int jacobi_pair(double (&a)[JR], double (&va)[JR], double (&b)[JR],
+                                           double (&vb)[JR], double& na, double& nb, int rpl_a,
                                            int rpl_v, double tol) {
   double g = 0.0;
 #pragma unroll
-  for (int k = 0; k < JRPL; ++k)
+  for (int k = 0; k < JR; ++k)
     if (k < rpl_a) g += a[k] * b[k];
   g = gsum<LPP>(g);
   if (!(na > 0.0) || !(nb > 0.0)) return 0;
@@ -186,7 +186,7 @@ __device__ __forceinline__ int jacobi_pair(double (&a)[JRPL], double (&va)[JRPL]
   const double c = 1.0 / sqrt(1.0 + t * t);
   const double s = c * t;
 #pragma unroll
-  for (int k = 0; k < JRPL; ++k) {
+  for (int k = 0; k < JR; ++k) {
     if (k < rpl_a) {
       const double x = a[k], y = b[k];
       a[k] = c * x - s * y;
@@ -204,8 +204,8 @@ __device__ __forceinline__ int jacobi_pair(double (&a)[JRPL], double (&va)[JRPL]
     // in rank-deficient R): carried norms would lose all accuracy and stall
     // the convergence test, so recompute both from the rotated columns.
     // The branch is uniform over the group (its inputs are group sums).
-    na = col_norm2<LPP>(a, rpl_a);
-    nb = col_norm2<LPP>(b, rpl_a);
+    na = col_norm2<LPP, JR>(a, rpl_a);
+    nb = col_norm2<LPP, JR>(b, rpl_a);
   } else {
     na = na2;
     nb = nb2;
@@ -213,21 +213,21 @@ __device__ __forceinline__ int jacobi_pair(double (&a)[JRPL], double (&va)[JRPL]
   return 1;
 }
 
-template <int LPP>
-__device__ __forceinline__ void load_col(double (&x)[JRPL], const double* __restrict__ col, int rows,
+template <int LPP, int JR>
+__device__ __forceinline__ void load_col(double (&x)[JR], const double* __restrict__ col, int rows,
                                          int sub) {
 #pragma unroll
-  for (int k = 0; k < JRPL; ++k) {
+  for (int k = 0; k < JR; ++k) {
     const int r = sub + LPP * k;
     x[k] = (r < rows) ? col[r] : 0.0;
   }
 }
 
-template <int LPP>
-__device__ __forceinline__ void store_col(const double (&x)[JRPL], double* __restrict__ col, int rows,
+template <int LPP, int JR>
+__device__ __forceinline__ void store_col(const double (&x)[JR], double* __restrict__ col, int rows,
                                           int sub) {
 #pragma unroll
-  for (int k = 0; k < JRPL; ++k) {
+  for (int k = 0; k < JR; ++k) {
     const int r = sub + LPP * k;
     if (r < rows) col[r] = x[k];
   }
@@ -243,7 +243,7 @@ struct JacobiArgs {
   int64_t sWs;  // batch: workspace slice stride in bytes (problem = blockIdx.y)
 };
 
-template <int LPP>
+template <int LPP, int JR>
 __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
   if (blockIdx.x % a.xcd_stride) return;
   if (blockIdx.y) {
@@ -254,7 +254,10 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
     a.flags = (int*)((char*)a.flags + pb * a.sWs);
     a.status += 2 * pb;
   }
-  __shared__ double xbuf[2][JT * 2 * JRPL];  // circulating b columns (A and V parts), 2 buffers
+  // circulating b columns (A and V parts): two buffers, one for the widest
+  // columns (32 rows per lane), where two do not fit in LDS
+  constexpr int NBUF = (JR <= 16) ? 2 : 1;
+  __shared__ double xbuf[NBUF][JT * 2 * JR];
   __shared__ double xnorm[2][JT / 2];
   __shared__ int rot_count;
   const int g = blockIdx.x / a.xcd_stride;
@@ -265,7 +268,7 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
   const double tol = (double)n * 0x1p-53;
   const int nplayers = 2 * a.G;
   unsigned int epoch = 0;
-  double ca[JRPL], cva[JRPL], cb[JRPL], cvb[JRPL];
+  double ca[JR], cva[JR], cb[JR], cvb[JR];
   int sweep_done = -1;
   // Deflation: columns of R^T (rows of R) whose norm is at most 2^-53 times
   // the largest are rounding noise (rank-deficient input leaves them graded
@@ -282,8 +285,8 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
       const int jc = (hb ? blk1 : blk0) * w + grp;
-      load_col<LPP>(ca, a.A + (int64_t)jc * n, n, sub);
-      nr2[hb] = col_norm2<LPP>(ca, rpl);
+      load_col<LPP, JR>(ca, a.A + (int64_t)jc * n, n, sub);
+      nr2[hb] = col_norm2<LPP, JR>(ca, rpl);
     }
     if (sub == 0)
       atomicMax(cmax, (unsigned long long)__double_as_longlong(nr2[0] > nr2[1] ? nr2[0] : nr2[1]));
@@ -296,8 +299,8 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
       if (nr2[hb] > 0.0 && nr2[hb] <= thr2) {
         const int jc = (hb ? blk1 : blk0) * w + grp;
 #pragma unroll
-        for (int k = 0; k < JRPL; ++k) ca[k] = 0.0;
-        store_col<LPP>(ca, a.A + (int64_t)jc * n, n, sub);
+        for (int k = 0; k < JR; ++k) ca[k] = 0.0;
+        store_col<LPP, JR>(ca, a.A + (int64_t)jc * n, n, sub);
       }
     }
     __syncthreads();
@@ -315,16 +318,16 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
       for (int q = 0; q < w - 1; ++q) {
         const int c1 = rr_player(pi, q, w), c2 = rr_player(w - 1 - pi, q, w);
         const int j1 = which * w + c1, j2 = which * w + c2;
-        load_col<LPP>(ca, a.A + (int64_t)j1 * n, n, sub);
-        load_col<LPP>(cva, a.V + (int64_t)j1 * n, n, sub);
-        load_col<LPP>(cb, a.A + (int64_t)j2 * n, n, sub);
-        load_col<LPP>(cvb, a.V + (int64_t)j2 * n, n, sub);
-        double na = col_norm2<LPP>(ca, rpl), nb = col_norm2<LPP>(cb, rpl);
-        myrot += jacobi_pair<LPP>(ca, cva, cb, cvb, na, nb, rpl, rpl, tol);
-        store_col<LPP>(ca, a.A + (int64_t)j1 * n, n, sub);
-        store_col<LPP>(cva, a.V + (int64_t)j1 * n, n, sub);
-        store_col<LPP>(cb, a.A + (int64_t)j2 * n, n, sub);
-        store_col<LPP>(cvb, a.V + (int64_t)j2 * n, n, sub);
+        load_col<LPP, JR>(ca, a.A + (int64_t)j1 * n, n, sub);
+        load_col<LPP, JR>(cva, a.V + (int64_t)j1 * n, n, sub);
+        load_col<LPP, JR>(cb, a.A + (int64_t)j2 * n, n, sub);
+        load_col<LPP, JR>(cvb, a.V + (int64_t)j2 * n, n, sub);
+        double na = col_norm2<LPP, JR>(ca, rpl), nb = col_norm2<LPP, JR>(cb, rpl);
+        myrot += jacobi_pair<LPP, JR>(ca, cva, cb, cvb, na, nb, rpl, rpl, tol);
+        store_col<LPP, JR>(ca, a.A + (int64_t)j1 * n, n, sub);
+        store_col<LPP, JR>(cva, a.V + (int64_t)j1 * n, n, sub);
+        store_col<LPP, JR>(cb, a.A + (int64_t)j2 * n, n, sub);
+        store_col<LPP, JR>(cvb, a.V + (int64_t)j2 * n, n, sub);
         __syncthreads();
       }
     }
@@ -332,39 +335,41 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
     for (int st = 0; st < nplayers - 1; ++st) {
       const int blk_a = rr_player(g, st, nplayers), blk_b = rr_player(nplayers - 1 - g, st, nplayers);
       const int ja = blk_a * w + grp;
-      load_col<LPP>(ca, a.A + (int64_t)ja * n, n, sub);
-      load_col<LPP>(cva, a.V + (int64_t)ja * n, n, sub);
-      load_col<LPP>(cb, a.A + (int64_t)(blk_b * w + grp) * n, n, sub);
-      load_col<LPP>(cvb, a.V + (int64_t)(blk_b * w + grp) * n, n, sub);
-      double na = col_norm2<LPP>(ca, rpl), nb = col_norm2<LPP>(cb, rpl);
+      load_col<LPP, JR>(ca, a.A + (int64_t)ja * n, n, sub);
+      load_col<LPP, JR>(cva, a.V + (int64_t)ja * n, n, sub);
+      load_col<LPP, JR>(cb, a.A + (int64_t)(blk_b * w + grp) * n, n, sub);
+      load_col<LPP, JR>(cvb, a.V + (int64_t)(blk_b * w + grp) * n, n, sub);
+      double na = col_norm2<LPP, JR>(ca, rpl), nb = col_norm2<LPP, JR>(cb, rpl);
       for (int q = 0; q < w; ++q) {
-        myrot += jacobi_pair<LPP>(ca, cva, cb, cvb, na, nb, rpl, rpl, tol);
+        myrot += jacobi_pair<LPP, JR>(ca, cva, cb, cvb, na, nb, rpl, rpl, tol);
         if (q < w - 1) {
-          // pass my b column to group grp-1, take the one of group grp+1; the
-          // two buffers alternate, so one barrier per round suffices
-          double* xb = xbuf[q & 1];
+          // pass my b column to group grp-1, take the one of group grp+1; with
+          // two alternating buffers one barrier per round suffices, with one
+          // buffer the previous round's reads must end first
+          if (NBUF == 1 && q > 0) __syncthreads();
+          double* xb = xbuf[(NBUF == 2) ? (q & 1) : 0];
           // k-major slots: consecutive lanes touch consecutive doubles
 #pragma unroll
-          for (int k = 0; k < JRPL; ++k) {
+          for (int k = 0; k < JR; ++k) {
             xb[k * JT + tid] = cb[k];
-            xb[(JRPL + k) * JT + tid] = cvb[k];
+            xb[(JR + k) * JT + tid] = cvb[k];
           }
           if (sub == 0) xnorm[q & 1][grp] = nb;
           __syncthreads();
           const int src = (grp + 1) % w;
 #pragma unroll
-          for (int k = 0; k < JRPL; ++k) {
+          for (int k = 0; k < JR; ++k) {
             cb[k] = xb[k * JT + src * LPP + sub];
-            cvb[k] = xb[(JRPL + k) * JT + src * LPP + sub];
+            cvb[k] = xb[(JR + k) * JT + src * LPP + sub];
           }
           nb = xnorm[q & 1][src];
         }
       }
-      store_col<LPP>(ca, a.A + (int64_t)ja * n, n, sub);
-      store_col<LPP>(cva, a.V + (int64_t)ja * n, n, sub);
+      store_col<LPP, JR>(ca, a.A + (int64_t)ja * n, n, sub);
+      store_col<LPP, JR>(cva, a.V + (int64_t)ja * n, n, sub);
       const int jb = blk_b * w + (grp + w - 1) % w;
-      store_col<LPP>(cb, a.A + (int64_t)jb * n, n, sub);
-      store_col<LPP>(cvb, a.V + (int64_t)jb * n, n, sub);
+      store_col<LPP, JR>(cb, a.A + (int64_t)jb * n, n, sub);
+      store_col<LPP, JR>(cvb, a.V + (int64_t)jb * n, n, sub);
       if (st == nplayers - 2) {
         // count rotations of this sweep before the last barrier
         if (sub == 0 && myrot) atomicAdd(&rot_count, myrot);
@@ -401,10 +406,10 @@ __global__ __launch_bounds__(FT) void k_svd_finalize(int n, const double* __rest
     UR += pb * sUR;
     nr += pb;
   }
-  __shared__ double sig[1024];
-  __shared__ double sgn[1024];
-  __shared__ int rank[1024];
-  __shared__ double tail[1025];
+  __shared__ double sig[2048];
+  __shared__ double sgn[2048];
+  __shared__ int rank[2048];
+  __shared__ double tail[2049];
   const int tid = threadIdx.x;
   for (int j = tid; j < n; j += FT) {
     const double* col = A + (int64_t)j * n;
@@ -494,10 +499,11 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
     void* args[] = {&a};
     const dim3 grid(p.G * p.xcd_stride), block(JT);
     const void* fn = nullptr;
+    const bool wide = (p.n + p.lpp - 1) / p.lpp > 16;
     switch (p.lpp) {
-      case 16: fn = (const void*)k_jacobi<16>; break;
-      case 32: fn = (const void*)k_jacobi<32>; break;
-      case 64: fn = (const void*)k_jacobi<64>; break;
+      case 16: fn = (const void*)k_jacobi<16, 16>; break;
+      case 32: fn = (const void*)k_jacobi<32, 16>; break;
+      case 64: fn = wide ? (const void*)k_jacobi<64, 32> : (const void*)k_jacobi<64, 16>; break;
       default: return hipErrorInvalidValue;
     }
     if (coop && p.G > 1) {
@@ -570,10 +576,11 @@ hipError_t launch_small_svd_batched(const JacobiPlan& p, int64_t count, const do
     a.status = status_each;
     a.sWs = wsb;
     const dim3 grid(1, (unsigned)count), block(JT);
+    if ((p.n + p.lpp - 1) / p.lpp > 16) return hipErrorInvalidValue;
     switch (p.lpp) {
-      case 16: hipLaunchKernelGGL(k_jacobi<16>, grid, block, 0, st, a); break;
-      case 32: hipLaunchKernelGGL(k_jacobi<32>, grid, block, 0, st, a); break;
-      case 64: hipLaunchKernelGGL(k_jacobi<64>, grid, block, 0, st, a); break;
+      case 16: hipLaunchKernelGGL((k_jacobi<16, 16>), grid, block, 0, st, a); break;
+      case 32: hipLaunchKernelGGL((k_jacobi<32, 16>), grid, block, 0, st, a); break;
+      case 64: hipLaunchKernelGGL((k_jacobi<64, 16>), grid, block, 0, st, a); break;
       default: return hipErrorInvalidValue;
     }
     e = hipGetLastError();

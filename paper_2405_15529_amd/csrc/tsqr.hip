@@ -110,6 +110,12 @@ struct QrArgs {
   T* Rbuf;
   // batch strides (elements), problem = blockIdx.y
   int64_t bsD, bsMean, bsV, bsTleaf, bsR, bsTtree;
+  // column-blocked use (a panel of a wider matrix): the leaf state starts at
+  // zero, so every chunk is a structured [state; chunk] step (no filling
+  // rows); reflectors are written with row stride ldv (0: n); at most
+  // rows_lim rows of each leaf take part (0: all)
+  int zero_state;
+  int64_t ldv, rows_lim;
 };
 
 // ---------------------------------------------------------------------------
@@ -712,6 +718,7 @@ void k_stacked_qr(QrArgs<T, TI> a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = (int)(blockDim.x >> 6);  // 4, or 1 for narrow problems
   const bool leaf = (a.mode == 0);
+  const int64_t ldv = (leaf && a.ldv > 0) ? a.ldv : n;
   T* Yw = Yb + wave * NB * NB;
 
   const TI* srcI = nullptr;
@@ -724,9 +731,10 @@ void k_stacked_qr(QrArgs<T, TI> a) {
     const int64_t jl = blockIdx.x;
     row0 = jl * a.b;
     rows = (jl == a.P - 1) ? (a.m - row0) : a.b;
+    if (a.rows_lim > 0 && rows > a.rows_lim) rows = a.rows_lim;
     srcI = a.D + row0 * a.ldd;
     ld_src = a.ldd;
-    vout = a.store_q ? a.V + row0 * n : nullptr;
+    vout = a.store_q ? a.V + row0 * ldv : nullptr;
     state = a.Rbuf + jl * (int64_t)n * n;
     tout = a.store_q ? a.Tleaf + jl * a.nch_leaf * npan * (NB * NB) : nullptr;
   } else {
@@ -740,7 +748,11 @@ void k_stacked_qr(QrArgs<T, TI> a) {
     tout = a.store_q ? a.Ttree + jb * a.nch_tree * npan * (NB * NB) : nullptr;
   }
   const int nch = (int)((rows + S - 1) / S);
-  int f = leaf ? 0 : n;
+  int f = (leaf && !a.zero_state) ? 0 : n;
+  if (leaf && a.zero_state) {
+    for (int idx = tid; idx < n * n; idx += (int)blockDim.x) state[idx] = T(0);
+    __syncthreads();
+  }
   for (int c = 0; c < nch; ++c) {
     const int64_t r0 = (int64_t)c * S;
     const int sc = (int)((rows - r0) < S ? (rows - r0) : S);
@@ -829,7 +841,7 @@ void k_stacked_qr(QrArgs<T, TI> a) {
     if (vout) {
       for (int idx = tid; idx < sc * n; idx += (int)blockDim.x) {
         const int i = idx / n, col = idx - (idx / n) * n;
-        vout[(r0 + i) * n + col] = C[i * ldc + col];
+        vout[(r0 + i) * ldv + col] = C[i * ldc + col];
       }
     }
     __syncthreads();
@@ -1167,6 +1179,24 @@ hipError_t launch_tree_combine_f64(const QrGeom& g, int64_t h, int64_t P, double
   set_qr_batch(a, bt);
   return launch_qr_any(a, (int)ncomb, qr_lds_bytes(g, 8), st, bt.count);
 }
+
+template <typename T>
+hipError_t launch_panel_qr(const QrGeom& g, T* Wk, int64_t ldw, int64_t m, int64_t b, int64_t P,
+                           int64_t rows_lim, T* Tf, int64_t nch, T* Rstate, hipStream_t st) {
+  QrArgs<T, T> a{};
+  a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.mode = 0; a.store_q = 1;
+  a.D = Wk; a.ldd = ldw; a.m = m; a.b = b; a.P = P; a.remove_mean = 0; a.mean_ws = nullptr;
+  a.V = Wk; a.Tleaf = Tf; a.nch_leaf = nch; a.Rbuf = Rstate;
+  a.zero_state = 1; a.ldv = ldw; a.rows_lim = rows_lim;
+  if (P > 0x7fffffff) return hipErrorInvalidValue;
+  return launch_qr_any(a, (int)P, qr_lds_bytes(g, (int)sizeof(T)), st);
+}
+template hipError_t launch_panel_qr<double>(const QrGeom&, double*, int64_t, int64_t, int64_t,
+                                            int64_t, int64_t, double*, int64_t, double*,
+                                            hipStream_t);
+template hipError_t launch_panel_qr<float>(const QrGeom&, float*, int64_t, int64_t, int64_t,
+                                           int64_t, int64_t, float*, int64_t, float*,
+                                           hipStream_t);
 
 template <typename TO>
 static hipError_t launch_apply_t(const ApplyArgs<double, TO>& a, int grid, size_t lds,

@@ -66,10 +66,12 @@ def test_argument_validation_before_device(hctx):
     assert _pod(hctx, r=-0.5) == -1
     assert _pod(hctx, dtype=99) == -3
     assert _pod(hctx, prec=7) == -3
-    assert _pod(hctx, m=5000, n=2000) == -6        # wider than the kernels
+    assert _pod(hctx, m=5000, n=3000) == -6        # wider than the kernels
+    assert _pod(hctx, m=5000, n=2000) == -7        # column-blocked path
     assert _pod(hctx, prec=api.MIXED) == -3        # mixed precision needs FP32 storage
     assert _pod(hctx, dtype=api.R32, prec=api.MIXED) == -7
-    assert _pod(hctx, dtype=api.R32, prec=api.MIXED, m=5000, n=2000) == -6
+    assert _pod(hctx, dtype=api.R32, prec=api.MIXED, m=5000, n=2000) == -7
+    assert _pod(hctx, dtype=api.R32, prec=api.MIXED, m=5000, n=2049) == -6
     assert hctx.lib.pylom_pod(None, 2, 0, 10, 2, None, 2, 0, 0.0, None, None, 2, None, None, 2,
                               None) == -1
 
@@ -102,6 +104,37 @@ def test_plan_geometry(hctx):
     p = hctx.plan(1000, 300)
     assert p["block_rows"] == 300 and p["leaves"] == 3
     assert hctx.workspace_bytes(1_048_576, 256) > 1_048_576 * 256 * 8
+
+
+def test_blocked_plan_geometry(hctx):
+    # the wide mixed-precision case: 4,194,304 x 1,808, one leaf per CU
+    assert hctx.get_option("blocked_from") == 1025
+    ncu = 256
+    m, n = 4_194_304, 1808
+    p = hctx.plan(m, n)
+    assert p["chunk_rows"] == 64
+    b = p["block_rows"]
+    assert b % 64 == 0 and b >= n and p["leaves"] == m // b
+    assert api.tune_block_rows(m, n, hctx) == b
+    if hctx.lib.pylom_tune_block_rows(hctx.h, m, n) == 16384:
+        assert p["leaves"] == ncu and p["levels"] == 8
+    # working copy + reflectors and T factors + tree pairs: a few times the
+    # input, well inside 288 GB of HBM
+    w64 = hctx.workspace_bytes(m, n)
+    w32 = hctx.workspace_bytes(m, n, dtype=api.R32, precision="mixed")
+    assert m * n * 8 < w64 < 150e9
+    assert m * n * 4 < w32 < 150e9
+    # forcing narrow problems through the blocked path
+    hctx.set_option("blocked_from", 64)
+    p = hctx.plan(10_000, 200)
+    assert p["chunk_rows"] == 64 and p["block_rows"] % 64 == 0
+    hctx.set_option("block_rows", 1000)
+    p = hctx.plan(10_000, 200)
+    assert p["block_rows"] == 1000 and p["leaves"] == 10
+    with pytest.raises(api.PylomError):
+        hctx.set_option("blocked_from", 1)
+    with pytest.raises(api.PylomError):
+        hctx.set_option("blocked_from", 4096)
 
 
 def emulate_alg1(P):
