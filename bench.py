@@ -45,6 +45,12 @@ def parse():
     ap.add_argument("--spod-steps", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-wide", action="store_true")
+    ap.add_argument("--wide-m", type=int, default=4_194_304)
+    ap.add_argument("--wide-n", type=int, default=1808)
+    ap.add_argument("--wide-steps", type=int, default=2)
+    ap.add_argument("--only-wide", action="store_true",
+                    help="run only the wide mixed-vs-FP64 leg and print its object")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy one 1 GiB FP64 buffer on the device "
                          "(a plain copy of known size, for calibrating HBM byte counters)")
@@ -152,7 +158,7 @@ def leaf_traffic(m: int, n: int, b: int):
     return t["bytes"]
 
 
-def timed_pod(api, ctx, A, m, n, r, precision, steps, warmup):
+def timed_pod(api, ctx, A, m, n, r, precision, steps, warmup, remove_mean=False):
     """Run pylom_pod `warmup` + `steps` times on the resident A; returns the
     mean ms per call (HIP events on the library stream), phase means and the
     outputs of the last call."""
@@ -168,10 +174,12 @@ def timed_pod(api, ctx, A, m, n, r, precision, steps, warmup):
     S = torch.empty(n, dtype=torch.float64, device=dev)
     VT = torch.empty((n, n), dtype=torch.float64, device=dev)
     nr_d = torch.empty(1, dtype=torch.int64, device=dev)
+    mean = torch.empty(m, dtype=A.dtype, device=dev) if remove_mean else None
     vp = ctypes.c_void_p
 
     def step():
-        rc = lib.pylom_pod(ctx.h, dt, prec, m, n, vp(A.data_ptr()), n, 0, r, vp(0),
+        rc = lib.pylom_pod(ctx.h, dt, prec, m, n, vp(A.data_ptr()), n, 1 if remove_mean else 0, r,
+                           vp(mean.data_ptr() if remove_mean else 0),
                            vp(U.data_ptr()), n, vp(S.data_ptr()), vp(VT.data_ptr()), n,
                            vp(nr_d.data_ptr()))
         if rc != 0:
@@ -198,6 +206,73 @@ def timed_pod(api, ctx, A, m, n, r, precision, steps, warmup):
     rc, sweeps = ctx.status()
     return dict(ms=ms, wall=wall, phases=phases, rc=rc, sweeps=sweeps, U=U, S=S, VT=VT,
                 nr=int(nr_d.item()))
+
+
+def timed_wide(api, m, n, steps, warmup):
+    """Wide mixed-precision POD: m x n FP32 sum of 64 travelling waves plus
+    N(0, 1e-8) noise, mean removed, 99 % energy, through the column-blocked
+    TSQR; the mixed path against the FP64 path on the same FP32 buffer
+    (promoted on load)."""
+    import numpy as np
+    import torch
+    from paper_2405_15529_amd import synth
+
+    r = 0.01
+    D = synth.travelling_waves_device(m, n, seed=2, device="cuda")
+    torch.cuda.synchronize()
+    ctx = api.Context(0)
+    ctx.set_option("timing", max(1, steps))
+    ctx.bind_stream()
+    b = api.tune_block_rows(m, n, ctx)
+
+    def orth_err(U, k):
+        Ur = U[:, :k].double()
+        return float(torch.linalg.norm(Ur.T @ Ur - torch.eye(k, dtype=torch.float64,
+                                                               device=U.device)).item())
+
+    x = timed_pod(api, ctx, D, m, n, r, "mixed", steps, warmup, remove_mean=True)
+    Sx = x["S"].cpu().numpy()
+    nrx = x["nr"]
+    orth_x = orth_err(x["U"], nrx)
+    del x["U"]
+    torch.cuda.empty_cache()
+    f = timed_pod(api, ctx, D, m, n, r, "fp64", steps, warmup, remove_mean=True)
+    Sf = f["S"].cpu().numpy()
+    nrf = f["nr"]
+    orth_f = orth_err(f["U"], nrf)
+    del f["U"]
+    ctx.close()
+    del D
+    torch.cuda.empty_cache()
+    k = min(nrx, nrf)
+
+    def rates(ms, nr, s_in, s_out):
+        fl = 2.0 * m * n * n + 2.0 * m * n * nr
+        by = 2.0 * s_in * m * n + s_out * m * nr
+        return round(fl / (ms * 1e-3) / 1e12, 4), round(by / (ms * 1e-3) / 1e9, 2)
+
+    tf_f, gb_f = rates(f["ms"], nrf, 4, 4)
+    tf_x, gb_x = rates(x["ms"], nrx, 4, 4)
+    return {
+        "workload": f"travelling-wave POD FP32 {m}x{n} (64 waves + N(0,1e-8)), mean removed, "
+                    f"99% energy, column-blocked TSQR (64-column panels), row blocks {b}",
+        "m": m, "n": n, "block_rows": b,
+        "fp64": {"ms_per_step": round(f["ms"], 3), "tflops": tf_f, "gbps": gb_f, "n_r": nrf,
+                 "orth_err_U": orth_f, "jacobi_sweeps": f["sweeps"],
+                 "phase_ms": {k2: round(v, 3) for k2, v in f["phases"].items()}},
+        "mixed": {"ms_per_step": round(x["ms"], 3), "tflops": tf_x, "gbps": gb_x, "n_r": nrx,
+                  "speedup_vs_fp64": round(f["ms"] / x["ms"], 3),
+                  "sigma_rel_err_vs_fp64_run":
+                      float(np.max(np.abs(Sx[:k] - Sf[:k]) / Sf[:k])) if k else 0.0,
+                  "orth_err_U": orth_x, "jacobi_sweeps_first": x["sweeps"],
+                  "phase_ms": {"working_copy": round(x["phases"]["front_end"], 3),
+                               "leaf_qr_fp32": round(x["phases"]["leaf_qr"], 3),
+                               "tree_combine": round(x["phases"]["tree_combine"], 3),
+                               "small_svd": round(x["phases"]["small_svd"], 3),
+                               "refine_project_gram_eig": round(x["phases"]["tree_propagate"], 3),
+                               "form_u": round(x["phases"]["leaf_apply"], 3)}},
+        "steps": steps, "warmup": warmup,
+    }
 
 
 def timed_batch(api, count, seed, steps, warmup):
@@ -281,6 +356,10 @@ def main():
     import torch
     from paper_2405_15529_amd import api, synth
 
+    if args.only_wide:
+        print(json.dumps({"wide": timed_wide(api, args.wide_m, args.wide_n, args.wide_steps,
+                                             1 if args.warmup else 0)}), flush=True)
+        return
     m, n, r = args.m, args.n, 0.01
     dev = torch.device("cuda:0")
     A, s = synth.graded_fp64_device(m=m, n=n, seed=1, device="cuda")
@@ -363,6 +442,9 @@ def main():
         del A32, f
         torch.cuda.empty_cache()
         out["spod"] = timed_spod(api, args.spod_m, args.spod_nt, 256, 128, args.spod_steps,
+                                 1 if args.warmup else 0)
+    if not args.no_wide:
+        out["wide"] = timed_wide(api, args.wide_m, args.wide_n, args.wide_steps,
                                  1 if args.warmup else 0)
     if not args.no_batch:
         out["uneven_batch"] = timed_batch(api, args.batch_count, 4, args.batch_steps,

@@ -273,7 +273,8 @@ int pylom_plan_query(pylom_ctx ctx, int64_t m, int64_t n, int64_t* leaves, int64
  *   out[3] tree propagation
  *   out[4] leaf apply U = Q_1i W_i (+ mean output; for SPOD also the modes,
  *          energies and frequency order)
- *   out[5] the SPOD front end (windowed FFT); 0 for pod/tsvd.
+ *   out[5] the front end: the SPOD windowed FFT, or the working copy of D
+ *          on the column-blocked path; 0 for the stacked pod/tsvd.
  * For PYLOM_MIXED calls out[3] is the refinement (projection
  * Z = (D - mean 1^T) V_k, Gram, its eigen-solve, refined spectrum) and out[4]
  * forms U = Z M; the host read-back of N0 between them is in neither.

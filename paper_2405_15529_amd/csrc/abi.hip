@@ -1496,8 +1496,9 @@ extern "C" int pylom_phase_times(pylom_ctx c, double* out, int cap) {
   if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
   if (c->timing <= 0 || c->ev_calls == 0) return fail(c, PYLOM_EINVAL, "no timed call recorded");
   const int64_t nrec = c->ev_calls < c->timing ? c->ev_calls : c->timing;
-  // events per slot: e0 call start, e1 after the front end (SPOD FFT; none
-  // for POD), e2..e6 after leaf QR, tree, SVD, propagation, apply; e7 (mixed
+  // events per slot: e0 call start, e1 after the front end (SPOD FFT, or the
+  // working copy of the column-blocked path; none for the stacked POD),
+  // e2..e6 after leaf QR, tree, SVD, propagation, apply; e7 (mixed
   // precision) after the first SVD, before the host read-back
   double acc[kPhases] = {0, 0, 0, 0, 0, 0};
   for (int64_t k = 0; k < nrec; ++k) {

@@ -94,6 +94,40 @@ def travelling_waves(m: int, n: int, seed: int = 2, nwaves: int = 64, noise: flo
     return np.ascontiguousarray(D.astype(dtype))
 
 
+def travelling_waves_device(m: int, n: int, seed: int = 2, nwaves: int = 64,
+                            noise: float = 1e-4, device: str = "cuda", rows_per_pass: int = 131072):
+    """Device-side twin of ``travelling_waves`` for large m (FP32, m x n):
+    the same wave parameters (numpy draws in the same order), the same
+    cos/sin factorisation as two GEMMs in FP64, rows formed in passes of
+    rows_per_pass; the N(0, noise^2) term comes from torch's seeded device
+    generator, so it is not the CPU generator's noise sample."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    kmax = max(2, min(2048, m // 2 - 1))
+    kap = rng.choice(np.arange(1, kmax + 1), size=nwaves, replace=False).astype(np.float64)
+    w = rng.uniform(0.1, 5.0, nwaves)
+    th = rng.uniform(0.0, 2.0 * np.pi, nwaves)
+    a = 2.0 ** (-np.arange(nwaves) / 8.0)
+    t = np.arange(n, dtype=np.float64)
+    arg = np.outer(w, t) - th[:, None]
+    temporal = np.concatenate([a[:, None] * np.cos(arg), a[:, None] * np.sin(arg)], axis=0)
+    Tt = torch.from_numpy(np.ascontiguousarray(temporal)).to(device)   # 2 nwaves x n
+    kap_d = torch.from_numpy(kap).to(device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    D = torch.empty((m, n), dtype=torch.float32, device=device)
+    for r0 in range(0, m, rows_per_pass):
+        r1 = min(m, r0 + rows_per_pass)
+        x = 2.0 * np.pi * torch.arange(r0, r1, dtype=torch.float64, device=device) / m
+        ph = x[:, None] * kap_d[None, :]
+        S = torch.cat([torch.cos(ph), torch.sin(ph)], dim=1)               # rows x 2 nwaves
+        blk = S @ Tt
+        blk += noise * torch.randn((r1 - r0, n), generator=gen, dtype=torch.float64, device=device)
+        D[r0:r1] = blk.to(torch.float32)
+    return D
+
+
 def spod_field(m: int, nt: int, seed: int = 3, nmodes: int = 32, noise: float = 1e-3,
                on_bins: int = 0, dtype=np.float32) -> np.ndarray:
     """nmodes random unit spatial modes, each oscillating at its own random
