@@ -266,7 +266,7 @@ struct Plan {
   bool blocked;
   int64_t K, nch_l, nch_p, wcap;
   QrGeom gp, gpl;  // geometry of a full panel and of the last panel
-  size_t oWk, oTl, oPSl, oPb, oTp, oPSp, oXp, oXu;
+  size_t oWk, oTl, oPSl, oTp, oPSp, oXu;
 };
 
 static int64_t level_pairs(int64_t P, int64_t h) { return (P - h + 2 * h - 1) / (2 * h); }
@@ -414,10 +414,10 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
 // Wide problems (n >= blocked_from): the leaves and the tree combines are
 // column-blocked QRs (blocked.hip).  Workspace, in order: the working copy of
 // D (compute type), the leaf T factors and panel states (per panel), the
-// FP64 R of every leaf (tree state in place), the tree pairs with their T
-// factors and panel states, the propagation W, and for FP64 the X buffers of
-// the propagation; the mixed path adds its refinement buffers (Z for at most
-// kZcap columns).
+// FP64 R of every leaf (tree state in place; the partner's triangle keeps
+// the combine's reflectors), the tree T factors and panel states, the
+// propagation W, and for FP64 the column-group buffer of the leaf apply; the
+// mixed path adds its refinement buffers (Z for at most kZcap columns).
 static int make_blocked_plan(pylom_ctx c, Plan* p, bool mixed) {
   const int64_t m = p->m, n = p->n;
   p->blocked = true;
@@ -440,7 +440,7 @@ static int make_blocked_plan(pylom_ctx c, Plan* p, bool mixed) {
   if (!jacobi_plan((int)n, &p->jp)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
   p->g = p->gp;
   p->nch_l = (p->last_rows + kPW - 1) / kPW;
-  p->nch_p = (2 * n + kPW - 1) / kPW;
+  p->nch_p = (n + kPW - 1) / kPW;
   p->nch_leaf = p->nch_l;
   p->nch_tree = p->nch_p;
   int64_t lv = 0;
@@ -459,8 +459,6 @@ static int make_blocked_plan(pylom_ctx c, Plan* p, bool mixed) {
   off = align_up(off + (size_t)es * p->K * P * kPW * kPW);
   p->oR = off;
   off = align_up(off + sizeof(double) * (size_t)P * n * n);
-  p->oPb = off;
-  off = align_up(off + sizeof(double) * (size_t)np_all * 2 * n * n);
   p->oTp = off;
   off = align_up(off + sizeof(double) * (size_t)p->K * np_all * p->nch_p * 4 * tpp);
   p->oPSp = off;
@@ -473,10 +471,8 @@ static int make_blocked_plan(pylom_ctx c, Plan* p, bool mixed) {
   off = align_up(off + sizeof(double) * (size_t)n);
   p->oSvd = off;
   off = align_up(off + jacobi_ws_bytes(p->jp, (int)c->max_sweeps));
-  p->oXp = p->oXu = off;
+  p->oXu = off;
   if (!mixed) {
-    p->oXp = off;
-    off = align_up(off + sizeof(double) * (size_t)level_pairs(P, 1) * 2 * n * n);
     p->oXu = off;
     off = align_up(off + sizeof(double) * (size_t)m * p->wcap);
   } else {
@@ -666,77 +662,86 @@ static size_t ps_slot(const Plan& p, bool pairs) {  // panel-state elements per 
   return (size_t)(pairs ? p.P - 1 : p.P) * kPW * kPW;
 }
 
-// Blocked QR of nprob problems stored in a working matrix of row stride n
-// (problem l: rows [l bstride, ...), at most mrows rows in all).  R of
-// problem l goes to Rout + l rstride (row stride n).  Tbase / PSbase point at
-// the group's first problem inside the slot of panel 0.
+// Blocked QR of the P leaves of the working matrix (row stride n, zero
+// initial state per panel); R of leaf l goes to Rout + l n^2 (row stride n).
 template <typename T>
-static int blocked_qr(pylom_ctx c, hipStream_t st, const Plan& p, T* Wk, int64_t nprob,
-                      int64_t bstride, int64_t mrows, bool pairs, T* Tbase, int64_t nch,
-                      T* PSbase, T* Rout, int64_t rstride) {
+static int blocked_leaves(pylom_ctx c, hipStream_t st, const Plan& p, char* ws, T* Rout) {
   const int64_t n = p.n;
-  const size_t tps = t_slot(p, pairs), pps = ps_slot(p, pairs);
+  T* Wk = (T*)(ws + p.oWk);
+  const size_t tps = t_slot(p, false), pps = ps_slot(p, false);
   for (int64_t k = 0; k < p.K; ++k) {
     const int64_t c0 = k * kPW;
     const int kw = (int)((n - c0 < kPW) ? n - c0 : kPW);
     const QrGeom& g = (k == p.K - 1) ? p.gpl : p.gp;
-    // a pair's panel k touches the first (k + 1) 64 rows of each triangle,
-    // a prefix of the interleaved layout
-    const int64_t rows_lim = pairs ? 2 * ((c0 + kPW < n) ? c0 + kPW : n) : 0;
-    T* Tk = Tbase + k * tps;
-    T* PSk = PSbase + k * pps;
-    HIPCHK(c, launch_panel_qr<T>(g, Wk + c0, n, mrows, bstride, nprob, rows_lim, Tk, nch, PSk, st),
+    T* Tk = (T*)(ws + p.oTl) + k * tps;
+    T* PSk = (T*)(ws + p.oPSl) + k * pps;
+    HIPCHK(c, launch_panel_qr<T>(g, Wk + c0, n, p.m, p.b, p.P, 0, Tk, p.nch_l, PSk, 1, st),
            "panel QR");
     if (c0 + kw < n) {
       PanelApplyArgs<T> a{};
-      a.kw = kw; a.npan = g.npanels; a.nlv = nprob; a.b = bstride; a.m = mrows;
-      a.rows_lim = rows_lim; a.V = Wk + c0; a.ldv = n; a.Tf = Tk; a.nch = nch;
+      a.kw = kw; a.npan = g.npanels; a.nlv = p.P; a.b = p.b; a.m = p.m; a.rows_lim = 0;
+      a.V = Wk + c0; a.ldv = n; a.Tf = Tk; a.nch = p.nch_l;
       a.X = Wk + c0 + kw; a.ldx = n; a.ncols = n - c0 - kw; a.nc_dev = nullptr; a.nc_off = 0;
-      a.x_zero = 0; a.S = Rout + c0 * n + c0 + kw; a.s_leaf = rstride; a.s_ld = n;
+      a.x_zero = 0; a.S = Rout + c0 * n + c0 + kw; a.s_leaf = n * n; a.s_ld = n;
+      a.load_state = 0; a.store_state = 1; a.leaf_major = 0;
       HIPCHK(c, launch_panel_apply<T>(a, false, st), "trailing update");
     }
   }
-  HIPCHK(c, launch_assemble_r<T>((int)n, nprob, PSbase, (int64_t)pps, Rout, rstride, st),
+  HIPCHK(c, launch_assemble_r<T>((int)n, p.P, (T*)(ws + p.oPSl), (int64_t)pps, Rout, n * n, st),
          "R assembly");
   return PYLOM_OK;
 }
 
-// Leaf level in the compute type T (FP64, or FP32 for the mixed path).
-template <typename T>
-static int blocked_leaves(pylom_ctx c, hipStream_t st, const Plan& p, char* ws, T* Rout) {
-  return blocked_qr<T>(c, st, p, (T*)(ws + p.oWk), p.P, p.b, p.m, false, (T*)(ws + p.oTl),
-                       p.nch_l, (T*)(ws + p.oPSl), Rout, p.n * p.n);
-}
-
-// The reduction tree of Alg. 1 in FP64 on the leaf R's (ws + oR): each level
-// packs its pairs and runs the blocked QR on them; R_j is overwritten by the
-// combined R.
+// The reduction tree of Alg. 1 in FP64 on the leaf R's (ws + oR), in place:
+// at level h, pair q combines R_j (j = 2hq, the state) with R_{j+h} (the
+// chunks, rows 0..c0+kw at panel k); R_j becomes the combined R, R_{j+h}
+// keeps the reflector tails.
 static int blocked_tree(pylom_ctx c, hipStream_t st, const Plan& p, char* ws) {
   const int64_t n = p.n;
   double* R = (double*)(ws + p.oR);
+  const size_t tps = t_slot(p, true), pps = ps_slot(p, true);
   int64_t base = 0;
   for (int64_t h = 1; h < p.P; h *= 2) {
     const int64_t np = level_pairs(p.P, h);
-    double* Pb = (double*)(ws + p.oPb) + base * 2 * n * n;
-    HIPCHK(c, launch_pair_pack((int)n, h, np, R, Pb, st), "pair pack");
-    const int rc = blocked_qr<double>(c, st, p, Pb, np, 2 * n, np * 2 * n, true,
-                                      (double*)(ws + p.oTp) + base * p.nch_p * 4 * kTF,
-                                      p.nch_p, (double*)(ws + p.oPSp) + base * kPW * kPW, R,
-                                      2 * h * n * n);
-    if (rc) return rc;
+    const int64_t rs = 2 * h * n * n;      // pair stride (elements)
+    double* Rb = R + h * n * n;            // R_{j+h} of pair 0, as rows of stride n
+    double* Tb = (double*)(ws + p.oTp) + base * p.nch_p * 4 * kTF;
+    double* PSb = (double*)(ws + p.oPSp) + base * kPW * kPW;
+    for (int64_t k = 0; k < p.K; ++k) {
+      const int64_t c0 = k * kPW;
+      const int kw = (int)((n - c0 < kPW) ? n - c0 : kPW);
+      const QrGeom& g = (k == p.K - 1) ? p.gpl : p.gp;
+      const int64_t rows_lim = c0 + kw;
+      double* Tk = Tb + k * tps;
+      double* PSk = PSb + k * pps;
+      HIPCHK(c, launch_diag_load((int)n, c0, kw, np, R, rs, PSk, st), "pair state");
+      HIPCHK(c, launch_panel_qr<double>(g, Rb + c0, n, np * 2 * h * n, 2 * h * n, np, rows_lim, Tk,
+                                        p.nch_p, PSk, 2, st), "pair panel QR");
+      if (c0 + kw < n) {
+        PanelApplyArgs<double> a{};
+        a.kw = kw; a.npan = g.npanels; a.nlv = np; a.b = 2 * h * n; a.m = np * 2 * h * n;
+        a.rows_lim = rows_lim; a.V = Rb + c0; a.ldv = n; a.Tf = Tk; a.nch = p.nch_p;
+        a.X = Rb + c0 + kw; a.ldx = n; a.ncols = n - c0 - kw; a.nc_dev = nullptr; a.nc_off = 0;
+        a.x_zero = 0; a.S = R + c0 * n + c0 + kw; a.s_leaf = rs; a.s_ld = n;
+        a.load_state = 1; a.store_state = 1; a.leaf_major = 0;
+        HIPCHK(c, launch_panel_apply<double>(a, false, st), "pair trailing update");
+      }
+    }
+    HIPCHK(c, launch_assemble_r<double>((int)n, np, PSb, (int64_t)pps, R, rs, st), "R assembly");
     base += np;
   }
   return PYLOM_OK;
 }
 
 // Down-tree propagation: W_0 (ws + oW, n x ncols, row stride n) through every
-// level's pair Q, leaving W_j for every leaf j.  Columns >= *nc_dev are not
-// touched (nc_dev may be null).
+// level's pair Q ([W_j; 0] -> [W_j; W_{j+h}], W_j updated in place),
+// leaving W_j for every leaf j.  Columns >= *nc_dev are not touched (nc_dev
+// may be null).
 static int blocked_propagate(pylom_ctx c, hipStream_t st, const Plan& p, char* ws,
                              const int64_t* nc_dev, int64_t ncols) {
   const int64_t n = p.n;
   double* W = (double*)(ws + p.oW);
-  double* Xp = (double*)(ws + p.oXp);
+  const double* R = (const double*)(ws + p.oR);
   std::vector<int64_t> bases;
   int64_t base = 0;
   for (int64_t h = 1; h < p.P; h *= 2) {
@@ -747,21 +752,19 @@ static int blocked_propagate(pylom_ctx c, hipStream_t st, const Plan& p, char* w
   for (int64_t li = (int64_t)bases.size() - 1; li >= 0; --li) {
     const int64_t h = (int64_t)1 << li;
     const int64_t np = level_pairs(p.P, h);
-    const double* Pb = (double*)(ws + p.oPb) + bases[(size_t)li] * 2 * n * n;
-    const double* Tl = (double*)(ws + p.oTp) + bases[(size_t)li] * p.nch_p * 4 * kTF;
+    const double* Tb = (const double*)(ws + p.oTp) + bases[(size_t)li] * p.nch_p * 4 * kTF;
     for (int64_t k = p.K - 1; k >= 0; --k) {
       const int64_t c0 = k * kPW;
       const int kw = (int)((n - c0 < kPW) ? n - c0 : kPW);
       const QrGeom& g = (k == p.K - 1) ? p.gpl : p.gp;
       PanelApplyArgs<double> a{};
-      a.kw = kw; a.npan = g.npanels; a.nlv = np; a.b = 2 * n; a.m = np * 2 * n;
-      a.rows_lim = 2 * ((c0 + kPW < n) ? c0 + kPW : n);
-      a.V = Pb + c0; a.ldv = n; a.Tf = Tl + k * tps; a.nch = p.nch_p;
-      a.X = Xp; a.ldx = n; a.ncols = ncols; a.nc_dev = nc_dev; a.nc_off = 0;
-      a.x_zero = (k == p.K - 1); a.S = W + c0 * n; a.s_leaf = 2 * h * n * n; a.s_ld = n;
+      a.kw = kw; a.npan = g.npanels; a.nlv = np; a.b = 2 * h * n; a.m = np * 2 * h * n;
+      a.rows_lim = c0 + kw; a.V = R + h * n * n + c0; a.ldv = n; a.Tf = Tb + k * tps;
+      a.nch = p.nch_p; a.X = W + h * n * n; a.ldx = n; a.ncols = ncols; a.nc_dev = nc_dev;
+      a.nc_off = 0; a.x_zero = (k == p.K - 1); a.S = W + c0 * n; a.s_leaf = 2 * h * n * n;
+      a.s_ld = n; a.load_state = 1; a.store_state = 1; a.leaf_major = 1;
       HIPCHK(c, launch_panel_apply<double>(a, true, st), "tree propagation");
     }
-    HIPCHK(c, launch_pair_unpack((int)n, h, np, Xp, n, W, n, ncols, nc_dev, st), "pair unpack");
   }
   return PYLOM_OK;
 }
@@ -788,6 +791,7 @@ static int blocked_leaf_apply(pylom_ctx c, hipStream_t st, const Plan& p, char* 
       a.V = Wk + c0; a.ldv = n; a.Tf = Tl + k * tps; a.nch = p.nch_l;
       a.X = Xu; a.ldx = p.wcap; a.ncols = ncg; a.nc_dev = nc_dev; a.nc_off = col0;
       a.x_zero = (k == p.K - 1); a.S = W + c0 * n + col0; a.s_leaf = n * n; a.s_ld = n;
+      a.load_state = 1; a.store_state = 0; a.leaf_major = 1;
       HIPCHK(c, launch_panel_apply<double>(a, true, st), "leaf apply");
     }
     HIPCHK(c, launch_copy_cols(out_f64, p.m, col0, ncg, ncols, nc_dev, Xu, p.wcap, U, ldu, st),

@@ -21,11 +21,16 @@
 //   X <- 0;  for k = K-1 .. 0:  [*; X] <- Q_k [W_k; X]
 //
 // leaves X = Q_thin W (k_panel_apply in Q mode: the state starts at W_k and
-// is dropped at the end).  A combine of the reduction tree runs the same
-// blocked QR on the 2n x n pair [R_a; R_b]; its rows are stored interleaved
-// in blocks of 64 (A_0, B_0, A_1, B_1, ...) so that the rows panel k touches
-// (the first (k+1) 64 rows of each triangle; the rest are still zero in
-// those columns) form a prefix.
+// is dropped at the end).
+//
+// A combine of the reduction tree, [R_a; R_b] = Q [R; 0], is the blocked QR
+// of the two triangles with the rows of R_a as the state: panel k starts from
+// the diagonal block of R_a's rows c0.. (untouched by earlier panels, whose
+// reflectors do not reach those rows) and streams R_b's rows 0..c0+kw (the
+// rest are still zero in those columns), in place: the reflector tails
+// overwrite R_b, R_a's rows become R's.  The Q of the pair then maps
+// [W; 0] to [W_a; W_b] by the Q-mode apply with the state read from and
+// written back to W's rows c0.., panels from the last to the first.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -40,34 +45,42 @@ constexpr int PLD = PW + 1;   // LDS row stride of the reflector block
 }  // namespace
 
 size_t panel_apply_lds_bytes(int esize) {
-  return (size_t)esize * ((size_t)PS * CLD + (size_t)PS * PLD + (size_t)PW * CLD +
-                          4 * (size_t)NB * NB + 4 * (size_t)NB * YLD);
+  return (size_t)esize * ((size_t)PS * CLD + (size_t)PS * PLD + 4 * (size_t)NB * NB +
+                          4 * (size_t)NB * YLD);
 }
 
 // Applies the panel reflectors of every leaf to a 64-column tile of X.
 // Leaf l owns rows [l b, l b + rows_l) of X and V (rows_l = b, the last leaf
 // m - l b, both capped at rows_lim); its reflector tails for chunk c are V
 // rows c*64.., its T factors Tf[((l nch + c) npan + p) 256].  The state tile
-// (kw rows) is S + l s_leaf (row stride s_ld): zero at the start and written
-// at the end (Q^T), or read at the start and dropped (Q, FWD).
-// Grid: (ceil(ncols / 64), leaves); 256 threads, wave w owns 16 columns.
+// (kw rows) is S + l s_leaf (row stride s_ld): read at the start if
+// load_state (else zero), written at the end if store_state.
+// Grid: (ceil(ncols / 64), leaves), or (leaves, ceil(ncols / 64)) when
+// leaf_major (launches where only the first tiles are live, so that the live
+// workgroups spread over all XCDs); 256 threads, wave w owns 16 columns.
+//
+// Each lane keeps its own state entries in registers (rows 16p + drow, its
+// column): the MFMA layouts give every lane the same entries in all three
+// products.  Chunks are staged through registers: the loads of the next
+// chunk are issued before the products of the current one, so their HBM
+// latency overlaps the MFMA work; each thread then writes back and replaces
+// exactly the LDS slots it staged, so one barrier separates the chunks.
 template <typename T, bool FWD>
 __global__ __launch_bounds__(256) void k_panel_apply(PanelApplyArgs<T> a) {
   typedef typename Mfma<T>::v4 v4;
   extern __shared__ __align__(16) unsigned char smem[];
   T* Cs = reinterpret_cast<T*>(smem);
   T* Vs = Cs + PS * CLD;
-  T* St = Vs + PS * PLD;
-  T* Ts = St + PW * CLD;
+  T* Ts = Vs + PS * PLD;
   T* Yb = Ts + 4 * NB * NB;
   int64_t nc = a.ncols;
   if (a.nc_dev) {
     const int64_t d = *a.nc_dev - a.nc_off;
     if (d < nc) nc = d;
   }
-  const int64_t c0 = (int64_t)blockIdx.x * CT;
+  const int64_t c0 = (int64_t)(a.leaf_major ? blockIdx.y : blockIdx.x) * CT;
   if (c0 >= nc) return;
-  const int64_t l = blockIdx.y;
+  const int64_t l = a.leaf_major ? blockIdx.x : blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i16 = lane & 15, g4 = lane >> 4;
   const int kw = a.kw, npan = a.npan;
@@ -76,104 +89,143 @@ __global__ __launch_bounds__(256) void k_panel_apply(PanelApplyArgs<T> a) {
   const int nch = (int)((rows + PS - 1) / PS);
   const int64_t row0 = l * a.b;
   T* Sl = a.S + l * a.s_leaf;
-  for (int idx = tid; idx < PW * CT; idx += 256) {
-    const int i = idx / CT, j = idx - (idx / CT) * CT;
-    T v = T(0);
-    if (FWD && i < kw && c0 + j < nc) v = Sl[(int64_t)i * a.s_ld + c0 + j];
-    St[i * CLD + j] = v;
-  }
-  T* Yw = Yb + wave * NB * YLD;
   const int cw = 16 * wave + i16;  // this lane's column of the tile
-  for (int cc = 0; cc < nch; ++cc) {
-    const int c = FWD ? nch - 1 - cc : cc;
+  const bool cw_ok = c0 + cw < nc;
+  T st[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = NB * p + Mfma<T>::drow(g4, q);
+      T v = T(0);
+      if (a.load_state && i < kw && cw_ok) v = Sl[(int64_t)i * a.s_ld + c0 + cw];
+      st[p][q] = v;
+    }
+  T* Yw = Yb + wave * NB * YLD;
+  // staging: thread (rr, jr) holds rows rr + 4e (e < 16) of column jr of the
+  // chunk tile and of the reflector block, and 4 entries of the T factors
+  constexpr int EPT = PS / 4;
+  const int jr = tid & 63, rr = tid >> 6;
+  const bool jx = c0 + jr < nc;
+  T rc[EPT], rv[EPT], rt[4];
+  auto fetch = [&](int c) {
     const int64_t r0 = (int64_t)c * PS;
     const int sc = (int)((rows - r0) < PS ? (rows - r0) : PS);
-    // stage the chunk rows of the tile, the reflector tails and the T factors
-    for (int idx = tid; idx < PS * CT; idx += 256) {
-      const int r = idx / CT, j = idx - (idx / CT) * CT;
-      T v = T(0);
-      if (!a.x_zero && r < sc && c0 + j < nc) v = a.X[(row0 + r0 + r) * a.ldx + c0 + j];
-      Cs[r * CLD + j] = v;
-    }
-    for (int idx = tid; idx < PS * PW; idx += 256) {
-      const int r = idx / PW, j = idx - (idx / PW) * PW;
-      T v = T(0);
-      if (r < sc && j < kw) v = a.V[(row0 + r0 + r) * a.ldv + j];
-      Vs[r * PLD + j] = v;
+    const T* xs = a.X + (row0 + r0) * a.ldx + c0 + jr;
+    const T* vs = a.V + (row0 + r0) * a.ldv + jr;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int r = rr + 4 * e;
+      rc[e] = (!a.x_zero && r < sc && jx) ? xs[(int64_t)r * a.ldx] : T(0);
+      rv[e] = (r < sc && jr < kw) ? vs[(int64_t)r * a.ldv] : T(0);
     }
     const T* tsrc = a.Tf + ((l * a.nch + c) * npan) * (NB * NB);
-    for (int idx = tid; idx < npan * NB * NB; idx += 256) Ts[idx] = tsrc[idx];
-    __syncthreads();
-    for (int pp = 0; pp < npan; ++pp) {
-      const int p = FWD ? npan - 1 - pp : pp;
-      const int k0 = NB * p;
-      // Y = V_p^T C + (state rows k0..k0+15): the reflector heads are the
-      // unit vectors of those state rows
-      v4 y0 = vzero4<T>(), y1 = vzero4<T>();
 #pragma unroll
-      for (int kb0 = 0; kb0 < PS / 4; kb0 += 4) {
-        T av[4], bv[4];
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + 256 * e;
+      rt[e] = (idx < npan * NB * NB) ? tsrc[idx] : T(0);
+    }
+  };
+  auto commit = [&]() {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int r = 4 * (kb0 + u) + g4;
-          av[u] = Vs[r * PLD + k0 + i16];
-          bv[u] = Cs[r * CLD + cw];
+    for (int e = 0; e < EPT; ++e) {
+      const int r = rr + 4 * e;
+      Cs[r * CLD + jr] = rc[e];
+      Vs[r * PLD + jr] = rv[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Ts[tid + 256 * e] = rt[e];
+  };
+  fetch(FWD ? nch - 1 : 0);
+  commit();
+  __syncthreads();
+  for (int cc = 0; cc < nch; ++cc) {
+    const int c = FWD ? nch - 1 - cc : cc;
+    if (cc + 1 < nch) fetch(FWD ? c - 1 : c + 1);
+#pragma unroll
+    for (int pp = 0; pp < 4; ++pp) {
+      const int p = FWD ? 3 - pp : pp;  // sub-panels >= npan are empty
+      if (p < npan) {
+        const int k0 = NB * p;
+        // Y = V_p^T C + (state rows k0..k0+15): the reflector heads are the
+        // unit vectors of those state rows
+        v4 y0 = vzero4<T>(), y1 = vzero4<T>();
+#pragma unroll
+        for (int kb0 = 0; kb0 < PS / 4; kb0 += 4) {
+          T av[4], bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int r = 4 * (kb0 + u) + g4;
+            av[u] = Vs[r * PLD + k0 + i16];
+            bv[u] = Cs[r * CLD + cw];
+          }
+          y0 = Mfma<T>::op(av[0], bv[0], y0);
+          y1 = Mfma<T>::op(av[1], bv[1], y1);
+          y0 = Mfma<T>::op(av[2], bv[2], y0);
+          y1 = Mfma<T>::op(av[3], bv[3], y1);
         }
-        y0 = Mfma<T>::op(av[0], bv[0], y0);
-        y1 = Mfma<T>::op(av[1], bv[1], y1);
-        y0 = Mfma<T>::op(av[2], bv[2], y0);
-        y1 = Mfma<T>::op(av[3], bv[3], y1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          Yw[Mfma<T>::drow(g4, q) * YLD + i16] = y0[q] + y1[q] + st[p][q];
+        wave_lds_sync();
+        // Z = T^T Y for Q^T, T Y for Q (T row-major, upper triangular)
+        const T* Tp = Ts + p * NB * NB;
+        v4 z = vzero4<T>();
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+          const int k = 4 * kb + g4;
+          const T ta = FWD ? Tp[i16 * NB + k] : Tp[k * NB + i16];
+          z = Mfma<T>::op(ta, Yw[k * YLD + i16], z);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          Yw[Mfma<T>::drow(g4, q) * YLD + i16] = z[q];
+          st[p][q] -= z[q];
+        }
+        wave_lds_sync();
+        // C -= V_p Z, one 16-row tile at a time
+        T zb[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) zb[kb] = Yw[(4 * kb + g4) * YLD + i16];
+#pragma unroll
+        for (int mt = 0; mt < PS / 16; ++mt) {
+          v4 u = vzero4<T>();
+#pragma unroll
+          for (int kb = 0; kb < 4; ++kb)
+            u = Mfma<T>::op(Vs[(16 * mt + i16) * PLD + k0 + 4 * kb + g4], zb[kb], u);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Cs[(16 * mt + Mfma<T>::drow(g4, q)) * CLD + cw] -= u[q];
+        }
+        wave_lds_sync();
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = Mfma<T>::drow(g4, q);
-        Yw[i * YLD + i16] = y0[q] + y1[q] + St[(k0 + i) * CLD + cw];
-      }
-      wave_lds_sync();
-      // Z = T^T Y for Q^T, T Y for Q (T row-major, upper triangular)
-      const T* Tp = Ts + p * NB * NB;
-      v4 z = vzero4<T>();
-#pragma unroll
-      for (int kb = 0; kb < 4; ++kb) {
-        const int k = 4 * kb + g4;
-        const T ta = FWD ? Tp[i16 * NB + k] : Tp[k * NB + i16];
-        z = Mfma<T>::op(ta, Yw[k * YLD + i16], z);
-      }
-      wave_lds_sync();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = Mfma<T>::drow(g4, q);
-        Yw[i * YLD + i16] = z[q];
-        St[(k0 + i) * CLD + cw] -= z[q];
-      }
-      wave_lds_sync();
-      // C -= V_p Z, one 16-row tile at a time
-      T zb[4];
-#pragma unroll
-      for (int kb = 0; kb < 4; ++kb) zb[kb] = Yw[(4 * kb + g4) * YLD + i16];
-#pragma unroll
-      for (int mt = 0; mt < PS / 16; ++mt) {
-        v4 u = vzero4<T>();
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
-          u = Mfma<T>::op(Vs[(16 * mt + i16) * PLD + k0 + 4 * kb + g4], zb[kb], u);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Cs[(16 * mt + Mfma<T>::drow(g4, q)) * CLD + cw] -= u[q];
-      }
-      wave_lds_sync();
     }
     __syncthreads();
-    for (int idx = tid; idx < PS * CT; idx += 256) {
-      const int r = idx / CT, j = idx - (idx / CT) * CT;
-      if (r < sc && c0 + j < nc) a.X[(row0 + r0 + r) * a.ldx + c0 + j] = Cs[r * CLD + j];
+    // write back the rows this thread staged, then stage the next chunk in
+    // the same slots
+    {
+      const int64_t r0 = (int64_t)c * PS;
+      const int sc = (int)((rows - r0) < PS ? (rows - r0) : PS);
+      T* xd = a.X + (row0 + r0) * a.ldx + c0 + jr;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int r = rr + 4 * e;
+        if (r < sc && jx) xd[(int64_t)r * a.ldx] = Cs[r * CLD + jr];
+      }
     }
-    __syncthreads();
+    if (cc + 1 < nch) {
+      commit();
+      __syncthreads();
+    }
   }
-  if (!FWD) {
-    for (int idx = tid; idx < PW * CT; idx += 256) {
-      const int i = idx / CT, j = idx - (idx / CT) * CT;
-      if (i < kw && c0 + j < nc) Sl[(int64_t)i * a.s_ld + c0 + j] = St[i * CLD + j];
-    }
+  if (a.store_state) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = NB * p + Mfma<T>::drow(g4, q);
+        if (i < kw && cw_ok) Sl[(int64_t)i * a.s_ld + c0 + cw] = st[p][q];
+      }
   }
 }
 
@@ -201,49 +253,18 @@ __global__ __launch_bounds__(256) void k_make_work(int64_t m, int n, const TI* _
   for (int col = lane; col < n; col += 64) out[col] = (T)((double)row[col] - mu);
 }
 
-// Row map of the interleaved pair layout: pair row pr -> (triangle, row).
-__device__ __forceinline__ void pair_row(int pr, int n, int& isB, int& srow) {
-  const int nblk = (n + PW - 1) / PW;
-  int i = pr / (2 * PW);
-  if (i > nblk - 1) i = nblk - 1;
-  const int base = 2 * i * PW;
-  const int sz = (n - i * PW < PW) ? n - i * PW : PW;
-  const int within = pr - base;
-  isB = within >= sz;
-  srow = i * PW + (isB ? within - sz : within);
-}
-
-// Pairs of tree level h: pair q packs R_j (j = 2hq) and R_{j+h} (n x n,
-// upper triangular, row stride n) into Pb + q 2n n, interleaved.
-// Grid: (2n, pairs).
-__global__ __launch_bounds__(256) void k_pair_pack(int n, int64_t h, const double* __restrict__ R,
-                                                   double* __restrict__ Pb) {
-  const int pr = blockIdx.x;
-  const int64_t q = blockIdx.y;
-  int isB, srow;
-  pair_row(pr, n, isB, srow);
-  const int64_t j = 2 * h * q + (isB ? h : 0);
-  const double* src = R + j * (int64_t)n * n + (int64_t)srow * n;
-  double* dst = Pb + q * 2 * (int64_t)n * n + (int64_t)pr * n;
-  for (int col = threadIdx.x; col < n; col += 256) dst[col] = src[col];
-}
-
-// The inverse map for the propagation: X rows of pair q go to the W blocks
-// of nodes j and j + h (columns < min(ncols, *nc_dev)).  Grid: (2n, pairs).
-__global__ __launch_bounds__(256) void k_pair_unpack(int n, int64_t h, const double* __restrict__ Xp,
-                                                     int64_t ldx, double* __restrict__ W,
-                                                     int64_t ldw, int64_t ncols,
-                                                     const int64_t* __restrict__ nc_dev) {
-  int64_t nc = ncols;
-  if (nc_dev && *nc_dev < nc) nc = *nc_dev;
-  const int pr = blockIdx.x;
-  const int64_t q = blockIdx.y;
-  int isB, srow;
-  pair_row(pr, n, isB, srow);
-  const int64_t j = 2 * h * q + (isB ? h : 0);
-  const double* src = Xp + (q * 2 * (int64_t)n + pr) * ldx;
-  double* dst = W + j * (int64_t)n * ldw + (int64_t)srow * ldw;
-  for (int64_t col = threadIdx.x; col < nc; col += 256) dst[col] = src[col];
+// Diagonal block (c0, c0) of R_j, j = 2 h q (R_j at R + q rstride), into
+// the panel state slot of pair q (kw x kw, zeros below the diagonal).
+__global__ __launch_bounds__(256) void k_diag_load(int n, int64_t c0, int kw,
+                                                   const double* __restrict__ R, int64_t rstride,
+                                                   double* __restrict__ PS) {
+  const int64_t q = blockIdx.x;
+  const double* src = R + q * rstride + c0 * n + c0;
+  double* dst = PS + q * (int64_t)kw * kw;
+  for (int idx = threadIdx.x; idx < kw * kw; idx += 256) {
+    const int i = idx / kw, j = idx - (idx / kw) * kw;
+    dst[idx] = (j >= i) ? src[(int64_t)i * n + j] : 0.0;
+  }
 }
 
 // Completes the R of each problem from the per-panel states: row r of panel
@@ -295,9 +316,11 @@ template <typename T>
 hipError_t launch_panel_apply(const PanelApplyArgs<T>& a, bool fwd, hipStream_t st) {
   if (a.nlv <= 0 || a.ncols <= 0) return hipSuccess;
   if (a.kw < 1 || a.kw > PW || a.npan != (a.kw + NB - 1) / NB) return hipErrorInvalidValue;
-  if (a.nlv > 65535) return hipErrorInvalidValue;
+  const int64_t tiles = (a.ncols + CT - 1) / CT;
+  if ((a.leaf_major ? tiles : a.nlv) > 65535) return hipErrorInvalidValue;
   const size_t lds = panel_apply_lds_bytes((int)sizeof(T));
-  const dim3 grid((unsigned)((a.ncols + CT - 1) / CT), (unsigned)a.nlv);
+  const dim3 grid = a.leaf_major ? dim3((unsigned)a.nlv, (unsigned)tiles)
+                                 : dim3((unsigned)tiles, (unsigned)a.nlv);
   hipError_t e;
   if (fwd) {
     e = hipFuncSetAttribute((const void*)k_panel_apply<T, true>,
@@ -333,22 +356,11 @@ hipError_t launch_make_work(int in_f64, int out_f64, int64_t m, int n, const voi
   return hipGetLastError();
 }
 
-hipError_t launch_pair_pack(int n, int64_t h, int64_t npairs, const double* R, double* Pb,
-                            hipStream_t st) {
+hipError_t launch_diag_load(int n, int64_t c0, int kw, int64_t npairs, const double* R,
+                            int64_t rstride, double* PS, hipStream_t st) {
   if (npairs <= 0) return hipSuccess;
-  if (npairs > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pair_pack, dim3((unsigned)(2 * n), (unsigned)npairs), dim3(256), 0, st, n,
-                     h, R, Pb);
-  return hipGetLastError();
-}
-
-hipError_t launch_pair_unpack(int n, int64_t h, int64_t npairs, const double* Xp, int64_t ldx,
-                              double* W, int64_t ldw, int64_t ncols, const int64_t* nc_dev,
-                              hipStream_t st) {
-  if (npairs <= 0) return hipSuccess;
-  if (npairs > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pair_unpack, dim3((unsigned)(2 * n), (unsigned)npairs), dim3(256), 0, st,
-                     n, h, Xp, ldx, W, ldw, ncols, nc_dev);
+  hipLaunchKernelGGL(k_diag_load, dim3((unsigned)npairs), dim3(256), 0, st, n, c0, kw, R, rstride,
+                     PS);
   return hipGetLastError();
 }
 

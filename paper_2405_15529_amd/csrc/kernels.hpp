@@ -29,13 +29,15 @@ size_t apply_lds_bytes(const QrGeom& g, int esize);
 
 // ---- column-blocked TSQR for wide problems (blocked.hip) ----------------------
 // One panel (kw <= 64 columns, starting at Wk) of every leaf of a working
-// matrix with row stride ldw: the stacked QR with a zero initial state;
-// reflector tails overwrite the panel in place, T factors go to
-// Tf[((l nch + c) npan + p) 256], the kw x kw state of leaf l to
-// Rstate + l kw^2.  At most rows_lim rows per leaf take part (0: all).
+// matrix with row stride ldw: the stacked QR with every chunk structured,
+// from a zero state (state_mode 1) or from the upper-triangular state given
+// in Rstate (state_mode 2); reflector tails overwrite the panel in place, T
+// factors go to Tf[((l nch + c) npan + p) 256], the kw x kw state of leaf l
+// to Rstate + l kw^2.  At most rows_lim rows per leaf take part (0: all).
 template <typename T>
 hipError_t launch_panel_qr(const QrGeom& g, T* Wk, int64_t ldw, int64_t m, int64_t b, int64_t P,
-                           int64_t rows_lim, T* Tf, int64_t nch, T* Rstate, hipStream_t st);
+                           int64_t rows_lim, T* Tf, int64_t nch, T* Rstate, int state_mode,
+                           hipStream_t st);
 
 template <typename T>
 struct PanelApplyArgs {
@@ -53,19 +55,21 @@ struct PanelApplyArgs {
   int x_zero;                   // the rows of X start at zero and are not read
   T* S;                         // state of leaf l: S + l s_leaf, row stride s_ld
   int64_t s_leaf, s_ld;
+  int load_state;               // the state starts from S (else zero)
+  int store_state;              // the final state is written to S
+  int leaf_major;               // grid x = leaves (for launches with few live tiles)
 };
 size_t panel_apply_lds_bytes(int esize);
-// fwd = false: X <- Q_k^T X for the trailing columns, the final state is
-// written to S; fwd = true: [*; X] <- Q_k [S; X], the state is read from S.
+// fwd = false: [state; X] <- Q_k^T [state; X] (trailing update);
+// fwd = true: [state; X] <- Q_k [state; X] (modes, propagation).
 template <typename T>
 hipError_t launch_panel_apply(const PanelApplyArgs<T>& a, bool fwd, hipStream_t st);
+// Copies the kw x kw diagonal block at (c0, c0) of R_j (j = 2 h q, upper
+// part, zeros below) into PS + q kw^2 for each of npairs tree pairs.
+hipError_t launch_diag_load(int n, int64_t c0, int kw, int64_t npairs, const double* R,
+                            int64_t rstride, double* PS, hipStream_t st);
 hipError_t launch_make_work(int in_f64, int out_f64, int64_t m, int n, const void* D, int64_t ldd,
                             int remove_mean, double* mean_out, void* W, hipStream_t st);
-hipError_t launch_pair_pack(int n, int64_t h, int64_t npairs, const double* R, double* Pb,
-                            hipStream_t st);
-hipError_t launch_pair_unpack(int n, int64_t h, int64_t npairs, const double* Xp, int64_t ldx,
-                              double* W, int64_t ldw, int64_t ncols, const int64_t* nc_dev,
-                              hipStream_t st);
 template <typename T>
 hipError_t launch_assemble_r(int n, int64_t nprob, const T* PSt, int64_t pstride, T* R,
                              int64_t rstride, hipStream_t st);

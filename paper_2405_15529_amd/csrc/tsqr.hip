@@ -110,11 +110,12 @@ struct QrArgs {
   T* Rbuf;
   // batch strides (elements), problem = blockIdx.y
   int64_t bsD, bsMean, bsV, bsTleaf, bsR, bsTtree;
-  // column-blocked use (a panel of a wider matrix): the leaf state starts at
-  // zero, so every chunk is a structured [state; chunk] step (no filling
-  // rows); reflectors are written with row stride ldv (0: n); at most
-  // rows_lim rows of each leaf take part (0: all)
-  int zero_state;
+  // column-blocked use (a panel of a wider matrix): state_mode 1 starts the
+  // leaf state at zero, 2 takes it as given in Rbuf; either way every chunk
+  // is a structured [state; chunk] step (no filling rows).  Reflectors are
+  // written with row stride ldv (0: n); at most rows_lim rows of each leaf
+  // take part (0: all)
+  int state_mode;
   int64_t ldv, rows_lim;
 };
 
@@ -748,8 +749,8 @@ void k_stacked_qr(QrArgs<T, TI> a) {
     tout = a.store_q ? a.Ttree + jb * a.nch_tree * npan * (NB * NB) : nullptr;
   }
   const int nch = (int)((rows + S - 1) / S);
-  int f = (leaf && !a.zero_state) ? 0 : n;
-  if (leaf && a.zero_state) {
+  int f = (leaf && a.state_mode == 0) ? 0 : n;
+  if (leaf && a.state_mode == 1) {
     for (int idx = tid; idx < n * n; idx += (int)blockDim.x) state[idx] = T(0);
     __syncthreads();
   }
@@ -1182,20 +1183,22 @@ hipError_t launch_tree_combine_f64(const QrGeom& g, int64_t h, int64_t P, double
 
 template <typename T>
 hipError_t launch_panel_qr(const QrGeom& g, T* Wk, int64_t ldw, int64_t m, int64_t b, int64_t P,
-                           int64_t rows_lim, T* Tf, int64_t nch, T* Rstate, hipStream_t st) {
+                           int64_t rows_lim, T* Tf, int64_t nch, T* Rstate, int state_mode,
+                           hipStream_t st) {
   QrArgs<T, T> a{};
   a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.mode = 0; a.store_q = 1;
   a.D = Wk; a.ldd = ldw; a.m = m; a.b = b; a.P = P; a.remove_mean = 0; a.mean_ws = nullptr;
   a.V = Wk; a.Tleaf = Tf; a.nch_leaf = nch; a.Rbuf = Rstate;
-  a.zero_state = 1; a.ldv = ldw; a.rows_lim = rows_lim;
+  a.state_mode = state_mode; a.ldv = ldw; a.rows_lim = rows_lim;
+  if (state_mode != 1 && state_mode != 2) return hipErrorInvalidValue;
   if (P > 0x7fffffff) return hipErrorInvalidValue;
   return launch_qr_any(a, (int)P, qr_lds_bytes(g, (int)sizeof(T)), st);
 }
 template hipError_t launch_panel_qr<double>(const QrGeom&, double*, int64_t, int64_t, int64_t,
-                                            int64_t, int64_t, double*, int64_t, double*,
+                                            int64_t, int64_t, double*, int64_t, double*, int,
                                             hipStream_t);
 template hipError_t launch_panel_qr<float>(const QrGeom&, float*, int64_t, int64_t, int64_t,
-                                           int64_t, int64_t, float*, int64_t, float*,
+                                           int64_t, int64_t, float*, int64_t, float*, int,
                                            hipStream_t);
 
 template <typename TO>
