@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--wide-m", type=int, default=4_194_304)
     ap.add_argument("--wide-n", type=int, default=1808)
     ap.add_argument("--wide-steps", type=int, default=2)
+    ap.add_argument("--wide-block-rows", type=int, default=0, help="0: the library's choice")
     ap.add_argument("--only-wide", action="store_true",
                     help="run only the wide mixed-vs-FP64 leg and print its object")
     ap.add_argument("--copy-probe", action="store_true",
@@ -208,7 +209,7 @@ def timed_pod(api, ctx, A, m, n, r, precision, steps, warmup, remove_mean=False)
                 nr=int(nr_d.item()))
 
 
-def timed_wide(api, m, n, steps, warmup):
+def timed_wide(api, m, n, steps, warmup, block_rows=0):
     """Wide mixed-precision POD: m x n FP32 sum of 64 travelling waves plus
     N(0, 1e-8) noise, mean removed, 99 % energy, through the column-blocked
     TSQR; the mixed path against the FP64 path on the same FP32 buffer
@@ -223,7 +224,9 @@ def timed_wide(api, m, n, steps, warmup):
     ctx = api.Context(0)
     ctx.set_option("timing", max(1, steps))
     ctx.bind_stream()
-    b = api.tune_block_rows(m, n, ctx)
+    if block_rows:
+        ctx.set_option("block_rows", block_rows)
+    b = block_rows or api.tune_block_rows(m, n, ctx)
 
     def orth_err(U, k):
         Ur = U[:, :k].double()
@@ -358,7 +361,8 @@ def main():
 
     if args.only_wide:
         print(json.dumps({"wide": timed_wide(api, args.wide_m, args.wide_n, args.wide_steps,
-                                             1 if args.warmup else 0)}), flush=True)
+                                             1 if args.warmup else 0, args.wide_block_rows)}),
+              flush=True)
         return
     m, n, r = args.m, args.n, 0.01
     dev = torch.device("cuda:0")
@@ -445,7 +449,7 @@ def main():
                                  1 if args.warmup else 0)
     if not args.no_wide:
         out["wide"] = timed_wide(api, args.wide_m, args.wide_n, args.wide_steps,
-                                 1 if args.warmup else 0)
+                                 1 if args.warmup else 0, args.wide_block_rows)
     if not args.no_batch:
         out["uneven_batch"] = timed_batch(api, args.batch_count, 4, args.batch_steps,
                                           1 if args.warmup else 0)
