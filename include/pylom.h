@@ -98,7 +98,7 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
  *                  TSQR (2..2049, default 1025): every leaf and every tree
  *                  combine is then a blocked Householder QR over panels of 64
  *                  columns (the local QR of Alg. 1 as LAPACK blocks it), the
- *                  leaf height defaults to ceil(m / CUs) rounded up to 64,
+ *                  leaf height defaults to ceil(m / (2 CUs)) rounded up to 64,
  *                  and the working copy of D, the reflectors of every panel
  *                  and the tree pairs stay in the workspace.  Smaller values
  *                  route narrow problems through the same path (tests).
@@ -212,8 +212,8 @@ int pylom_pod_batched(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t
  * minimiser, over b in {128, 256, ..., 32768} with b >= n, of a latency model
  * of the stacked QR (leaf critical path of ceil(b / s) chunks, waves of leaves
  * over the device's compute units, ceil(log2 P) dependent tree levels and one
- * launch per level).  For n >= "blocked_from", ceil(m / CUs) rounded up to a
- * multiple of 64 (at least n).  Host only; n <= 2048. */
+ * launch per level).  For n >= "blocked_from", ceil(m / (2 CUs)) rounded up
+ * to a multiple of 64 (at least n).  Host only; n <= 2048. */
 int64_t pylom_tune_block_rows(pylom_ctx ctx, int64_t m, int64_t n);
 
 /* SPOD (Alg. 6; Sec. 2.3, Eq. csdimp with the SVD of the spectral matrix).

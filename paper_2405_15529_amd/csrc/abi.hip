@@ -307,10 +307,12 @@ static int64_t tune_block_rows(int64_t m, int64_t n, int ncu) {
   return best > 0 ? best : n;
 }
 
-// Leaf height of the column-blocked path: one leaf per CU (the panel
-// factorisations run one workgroup per leaf), rows a multiple of the chunk.
+// Leaf height of the column-blocked path: two leaves per CU (the panel
+// factorisations run one workgroup per leaf, two per CU, their panel waves
+// on different SIMDs), rows a multiple of the chunk.
 static int64_t blocked_block_rows(int64_t m, int64_t n, int ncu) {
-  int64_t b = (m + ncu - 1) / (ncu > 0 ? ncu : 1);
+  const int64_t slots = 2 * (int64_t)(ncu > 0 ? ncu : 1);
+  int64_t b = (m + slots - 1) / slots;
   if (b < n) b = n;
   return (b + kPW - 1) / kPW * kPW;
 }

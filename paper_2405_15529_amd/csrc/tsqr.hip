@@ -693,9 +693,17 @@ __device__ __forceinline__ void load_chunk(T* __restrict__ C, int ldc, int s, in
 // p-1 to the 16 columns of panel p (look-ahead) and then factors panel p,
 // while waves 1..3 apply panel p-1 to the remaining trailing columns.  The
 // reflectors and T of consecutive panels alternate between two LDS buffers.
-template <typename T, typename TI, int RT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+// Variants: VAR 0 fills the leaf state from the first chunks (stacked
+// leaves); VAR 1 and 2 compile the filling path out (tree combines and
+// column-blocked panels never fill).  VAR 2 is register-limited to two
+// waves per SIMD, so that two workgroups share a CU, and the wave that
+// factors the panels rotates with the workgroup index, so that the panel
+// waves of co-resident workgroups sit on different SIMDs.
+template <typename T, typename TI, int RT, int VAR>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(VAR == 2 ? 2 : 1, VAR == 2 ? 2 : 1)))
 void k_stacked_qr(QrArgs<T, TI> a) {
+  constexpr bool FILL = VAR == 0;
   extern __shared__ __align__(16) unsigned char smem[];
   if (blockIdx.y) {
     const int64_t pb = blockIdx.y;
@@ -715,9 +723,12 @@ void k_stacked_qr(QrArgs<T, TI> a) {
   T* Rd = Yb + 4 * NB * NB;
   T* vb = Rd + NB * TLD;
   T* taus = vb + 64;
-  T* Gm = Yb;  // the panel wave's Y tile doubles as its Gram scratch
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = (int)(blockDim.x >> 6);  // 4, or 1 for narrow problems
+  // panel wave pw; wr = 0 for it, 1..3 for the trailing-tile waves
+  const int pw = (VAR == 2 && nw == 4) ? (int)(((blockIdx.x >> 3) + (blockIdx.x >> 8)) & 3) : 0;
+  const int wr = (wave - pw) & 3;
+  T* Gm = Yb + pw * NB * NB;  // the panel wave's Y tile doubles as its Gram scratch
   const bool leaf = (a.mode == 0);
   const int64_t ldv = (leaf && a.ldv > 0) ? a.ldv : n;
   T* Yw = Yb + wave * NB * NB;
@@ -749,7 +760,7 @@ void k_stacked_qr(QrArgs<T, TI> a) {
     tout = a.store_q ? a.Ttree + jb * a.nch_tree * npan * (NB * NB) : nullptr;
   }
   const int nch = (int)((rows + S - 1) / S);
-  int f = (leaf && a.state_mode == 0) ? 0 : n;
+  int f = (FILL && leaf && a.state_mode == 0) ? 0 : n;
   if (leaf && a.state_mode == 1) {
     for (int idx = tid; idx < n * n; idx += (int)blockDim.x) state[idx] = T(0);
     __syncthreads();
@@ -774,29 +785,29 @@ void k_stacked_qr(QrArgs<T, TI> a) {
     // panel wave prefetches: diagonal block of the first panel
     T rd4[4] = {T(0), T(0), T(0), T(0)};
     T hd4[4] = {T(0), T(0), T(0), T(0)};
-    if (wave == 0 && !(leaf && p_lo * NB >= f)) load_diag4<T>(rd4, state, n, p_lo * NB, lane);
+    if (wr == 0 && !(FILL && leaf && p_lo * NB >= f)) load_diag4<T>(rd4, state, n, p_lo * NB, lane);
     __syncthreads();
     for (int p = p_lo; p <= p_hi; ++p) {
       const int kp = (p - 1) * NB;  // previous panel (its reflectors are applied now)
       const int kwp = (n - kp < NB) ? n - kp : NB;
-      const bool int_prev = leaf && (kp >= f);
+      const bool int_prev = FILL && leaf && (kp >= f);
       T* Vprev = Vp0 + ((p - 1) & 1) * S * VPLD;
       T* Tprev = Tm0 + ((p - 1) & 1) * NB * NB;
-      if (wave == 0) {
+      if (wr == 0) {
         if (p > p_lo && p < npan)
           tile_update<T, RT>(C, ldc, Vprev, Tprev, Yw, state, n, kp, kwp, int_prev, p * NB, hd4,
                              lane);
         if (p < p_hi) {
           const int k0 = p * NB;
           const int kw = (n - k0 < NB) ? n - k0 : NB;
-          const bool internal = leaf && (k0 >= f);
+          const bool internal = FILL && leaf && (k0 >= f);
           T* Vcur = Vp0 + (p & 1) * S * VPLD;
           T* Tcur = Tm0 + (p & 1) * NB * NB;
           // prefetch for the next step: head values of this panel's rows over the
           // next panel's columns, and the next panel's diagonal block
           T rd_next[4] = {T(0), T(0), T(0), T(0)};
           if (!internal && p + 1 < npan) load_head4<T>(hd4, state, n, k0, kw, (p + 1) * NB, lane);
-          if (p + 1 < p_hi && !(leaf && (p + 1) * NB >= f))
+          if (p + 1 < p_hi && !(FILL && leaf && (p + 1) * NB >= f))
             load_diag4<T>(rd_next, state, n, (p + 1) * NB, lane);
           if (internal)
             factor_panel<T, RT, true>(C, ldc, Vcur, Tcur, state, n, k0, kw, f, lane, rd4, Rd, Gm,
@@ -823,7 +834,7 @@ void k_stacked_qr(QrArgs<T, TI> a) {
           }
         }
       } else if (p > p_lo) {
-        for (int t = p + wave; t < npan; t += 3) {
+        for (int t = p + wr; t < npan; t += 3) {
           T hd[4] = {T(0), T(0), T(0), T(0)};
           if (!int_prev) load_head4<T>(hd, state, n, kp, kwp, t * NB, lane);
           tile_update<T, RT>(C, ldc, Vprev, Tprev, Yw, state, n, kp, kwp, int_prev, t * NB, hd,
@@ -832,7 +843,7 @@ void k_stacked_qr(QrArgs<T, TI> a) {
       }
       __syncthreads();
     }
-    if (leaf && f < n) {
+    if (FILL && leaf && f < n) {
       const int nf = (sc < n - f) ? sc : n - f;
       for (int idx = tid; idx < nf * n; idx += (int)blockDim.x) {
         const int i = idx / n, col = idx - (idx / n) * n;
@@ -846,7 +857,7 @@ void k_stacked_qr(QrArgs<T, TI> a) {
       }
     }
     __syncthreads();
-    if (leaf) f = (f + sc < n) ? f + sc : n;
+    if (FILL && leaf) f = (f + sc < n) ? f + sc : n;
   }
 }
 
@@ -1096,29 +1107,40 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
 // Problems of at most two panels use single-wave workgroups: their trailing
 // work per step is one tile, so three of four waves would idle, while several
 // single-wave leaves share a CU and overlap their panel latencies.
-template <typename T, typename TI, int RT>
+template <typename T, typename TI, int RT, int VAR>
 static hipError_t launch_qr_t(const QrArgs<T, TI>& a, int grid, int gy, size_t lds,
                               hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_stacked_qr<T, TI, RT>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_stacked_qr<T, TI, RT, VAR>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int threads = (a.npanels <= 2) ? 64 : 256;
-  hipLaunchKernelGGL((k_stacked_qr<T, TI, RT>), dim3(grid, gy), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL((k_stacked_qr<T, TI, RT, VAR>), dim3(grid, gy), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
+template <typename T, typename TI, int VAR>
+static hipError_t launch_qr_var(const QrArgs<T, TI>& a, int grid, size_t lds, hipStream_t st,
+                                int64_t gy) {
+  switch (a.s) {
+    case 16: return launch_qr_t<T, TI, 4, VAR>(a, grid, (int)gy, lds, st);
+    case 32: return launch_qr_t<T, TI, 8, VAR>(a, grid, (int)gy, lds, st);
+    case 48: return launch_qr_t<T, TI, 12, VAR>(a, grid, (int)gy, lds, st);
+    case 64: return launch_qr_t<T, TI, 16, VAR>(a, grid, (int)gy, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Leaves of the stacked path fill their state from the first chunks (VAR 0);
+// tree combines never do (VAR 1); column-blocked panels (VAR 2) run two
+// workgroups per CU.
 template <typename T, typename TI>
 static hipError_t launch_qr_any(const QrArgs<T, TI>& a, int grid, size_t lds, hipStream_t st,
                                 int64_t gy = 1) {
   if (grid <= 0 || gy <= 0) return hipSuccess;
   if (gy > 65535) return hipErrorInvalidValue;
-  switch (a.s) {
-    case 16: return launch_qr_t<T, TI, 4>(a, grid, (int)gy, lds, st);
-    case 32: return launch_qr_t<T, TI, 8>(a, grid, (int)gy, lds, st);
-    case 48: return launch_qr_t<T, TI, 12>(a, grid, (int)gy, lds, st);
-    case 64: return launch_qr_t<T, TI, 16>(a, grid, (int)gy, lds, st);
-    default: return hipErrorInvalidValue;
-  }
+  if (a.mode == 0 && a.state_mode == 0) return launch_qr_var<T, TI, 0>(a, grid, lds, st, gy);
+  if (a.mode == 1) return launch_qr_var<T, TI, 1>(a, grid, lds, st, gy);
+  return launch_qr_var<T, TI, 2>(a, grid, lds, st, gy);
 }
 
 template <typename QA>
