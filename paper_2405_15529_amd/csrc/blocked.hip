@@ -39,14 +39,27 @@ namespace pylom {
 namespace {
 constexpr int PS = 64;        // chunk rows (the stacked QR's s for panels of <= 64 columns)
 constexpr int PW = 64;        // panel width
-constexpr int CT = 64;        // columns per workgroup: 4 waves x 16
-constexpr int CLD = CT + 1;   // LDS row stride of the chunk tile and of the state tile
 constexpr int PLD = PW + 1;   // LDS row stride of the reflector block
 }  // namespace
 
+// LDS of k_panel_apply: the reflector block, the T factors, one Y tile per
+// wave (the chunk tile itself stays in registers).
 size_t panel_apply_lds_bytes(int esize) {
-  return (size_t)esize * ((size_t)PS * CLD + (size_t)PS * PLD + 4 * (size_t)NB * NB +
-                          4 * (size_t)NB * YLD);
+  return (size_t)esize * ((size_t)PS * PLD + 4 * (size_t)NB * NB + 4 * (size_t)NB * YLD);
+}
+
+// Row of a 16-row MFMA tile that lane slot i16 of the A operand loads so
+// that the product lands, register q of lane (i16, g4), on tile row
+// 4 q + g4: the rows the same lane holds as a B operand.  The FP64 output
+// layout is already 4 q + g4; the FP32 one (4 g4 + q) needs the 4 x 4
+// transpose of the slot index.
+template <typename T>
+__device__ __forceinline__ int a_row_for_b_layout(int i16);
+template <>
+__device__ __forceinline__ int a_row_for_b_layout<double>(int i16) { return i16; }
+template <>
+__device__ __forceinline__ int a_row_for_b_layout<float>(int i16) {
+  return 4 * (i16 & 3) + (i16 >> 2);
 }
 
 // Applies the panel reflectors of every leaf to a 64-column tile of X.
@@ -55,22 +68,25 @@ size_t panel_apply_lds_bytes(int esize) {
 // rows c*64.., its T factors Tf[((l nch + c) npan + p) 256].  The state tile
 // (kw rows) is S + l s_leaf (row stride s_ld): read at the start if
 // load_state (else zero), written at the end if store_state.
-// Grid: (ceil(ncols / 64), leaves), or (leaves, ceil(ncols / 64)) when
-// leaf_major (launches where only the first tiles are live, so that the live
-// workgroups spread over all XCDs); 256 threads, wave w owns 16 columns.
+// Grid: (column tiles, leaves), or (leaves, column tiles) when leaf_major
+// (launches where only the first tiles are live, so that the live
+// workgroups spread over all XCDs); 256 threads, wave w owns columns
+// 16 w .. 16 w + 15 of the tile.
 //
-// Each lane keeps its own state entries in registers (rows 16p + drow, its
-// column): the MFMA layouts give every lane the same entries in all three
-// products.  Chunks are staged through registers: the loads of the next
-// chunk are issued before the products of the current one, so their HBM
-// latency overlaps the MFMA work; each thread then writes back and replaces
-// exactly the LDS slots it staged, so one barrier separates the chunks.
+// Every lane keeps, for its column, the 16 chunk rows 4 k + g4 (k < 16) and
+// the state rows 16 p + 4 q + g4 in registers: the B operand of V^T C, the
+// output of V Z (A rows permuted, see a_row_for_b_layout) and the state
+// slots of Y and Z all use that row set, so the chunk tile never goes
+// through LDS.  Only the reflector block and T factors are staged in LDS,
+// through registers; the next chunk's loads (C, V, T) are issued before the
+// products of the current one, so their HBM latency overlaps the MFMA work.
 template <typename T, bool FWD>
-__global__ __launch_bounds__(256) void k_panel_apply(PanelApplyArgs<T> a) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(FWD || sizeof(T) == 4 ? 2 : 1, FWD || sizeof(T) == 4 ? 2 : 1)))
+void k_panel_apply(PanelApplyArgs<T> a) {
   typedef typename Mfma<T>::v4 v4;
   extern __shared__ __align__(16) unsigned char smem[];
-  T* Cs = reinterpret_cast<T*>(smem);
-  T* Vs = Cs + PS * CLD;
+  T* Vs = reinterpret_cast<T*>(smem);
   T* Ts = Vs + PS * PLD;
   T* Yb = Ts + 4 * NB * NB;
   int64_t nc = a.ncols;
@@ -78,7 +94,7 @@ __global__ __launch_bounds__(256) void k_panel_apply(PanelApplyArgs<T> a) {
     const int64_t d = *a.nc_dev - a.nc_off;
     if (d < nc) nc = d;
   }
-  const int64_t c0 = (int64_t)(a.leaf_major ? blockIdx.y : blockIdx.x) * CT;
+  const int64_t c0 = (int64_t)(a.leaf_major ? blockIdx.y : blockIdx.x) * 64;
   if (c0 >= nc) return;
   const int64_t l = a.leaf_major ? blockIdx.x : blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -102,22 +118,29 @@ __global__ __launch_bounds__(256) void k_panel_apply(PanelApplyArgs<T> a) {
       st[p][q] = v;
     }
   T* Yw = Yb + wave * NB * YLD;
-  // staging: thread (rr, jr) holds rows rr + 4e (e < 16) of column jr of the
-  // chunk tile and of the reflector block, and 4 entries of the T factors
-  constexpr int EPT = PS / 4;
-  const int jr = tid & 63, rr = tid >> 6;
-  const bool jx = c0 + jr < nc;
-  T rc[EPT], rv[EPT], rt[4];
+  const int arow = a_row_for_b_layout<T>(i16);
+  // reflector block staging: thread (rw, jw) holds rows rw + 4 e of column jw
+  constexpr int EPV = PS / 4;
+  const int jw = tid & 63, rw = tid >> 6;
+  T cc_[16], cn[16], rv[EPV], rt[4];
   auto fetch = [&](int c) {
     const int64_t r0 = (int64_t)c * PS;
     const int sc = (int)((rows - r0) < PS ? (rows - r0) : PS);
-    const T* xs = a.X + (row0 + r0) * a.ldx + c0 + jr;
-    const T* vs = a.V + (row0 + r0) * a.ldv + jr;
+    const T* xs = a.X + (row0 + r0 + g4) * a.ldx + c0 + cw;
+    const int64_t xstep = 4 * a.ldx;
+    const bool xon = !a.x_zero && cw_ok;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int r = rr + 4 * e;
-      rc[e] = (!a.x_zero && r < sc && jx) ? xs[(int64_t)r * a.ldx] : T(0);
-      rv[e] = (r < sc && jr < kw) ? vs[(int64_t)r * a.ldv] : T(0);
+    for (int k = 0; k < 16; ++k) {
+      cn[k] = (xon && 4 * k + g4 < sc) ? *xs : T(0);
+      xs += xstep;
+    }
+    const T* vs = a.V + (row0 + r0 + rw) * a.ldv + jw;
+    const int64_t vstep = 4 * a.ldv;
+    const bool von = jw < kw;
+#pragma unroll
+    for (int e = 0; e < EPV; ++e) {
+      rv[e] = (von && rw + 4 * e < sc) ? *vs : T(0);
+      vs += vstep;
     }
     const T* tsrc = a.Tf + ((l * a.nch + c) * npan) * (NB * NB);
 #pragma unroll
@@ -128,20 +151,18 @@ __global__ __launch_bounds__(256) void k_panel_apply(PanelApplyArgs<T> a) {
   };
   auto commit = [&]() {
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int r = rr + 4 * e;
-      Cs[r * CLD + jr] = rc[e];
-      Vs[r * PLD + jr] = rv[e];
-    }
+    for (int e = 0; e < EPV; ++e) Vs[(rw + 4 * e) * PLD + jw] = rv[e];
 #pragma unroll
     for (int e = 0; e < 4; ++e) Ts[tid + 256 * e] = rt[e];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) cc_[k] = cn[k];
   };
   fetch(FWD ? nch - 1 : 0);
   commit();
   __syncthreads();
-  for (int cc = 0; cc < nch; ++cc) {
-    const int c = FWD ? nch - 1 - cc : cc;
-    if (cc + 1 < nch) fetch(FWD ? c - 1 : c + 1);
+  for (int ci = 0; ci < nch; ++ci) {
+    const int c = FWD ? nch - 1 - ci : ci;
+    if (ci + 1 < nch) fetch(FWD ? c - 1 : c + 1);
 #pragma unroll
     for (int pp = 0; pp < 4; ++pp) {
       const int p = FWD ? 3 - pp : pp;  // sub-panels >= npan are empty
@@ -151,18 +172,9 @@ __global__ __launch_bounds__(256) void k_panel_apply(PanelApplyArgs<T> a) {
         // unit vectors of those state rows
         v4 y0 = vzero4<T>(), y1 = vzero4<T>();
 #pragma unroll
-        for (int kb0 = 0; kb0 < PS / 4; kb0 += 4) {
-          T av[4], bv[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int r = 4 * (kb0 + u) + g4;
-            av[u] = Vs[r * PLD + k0 + i16];
-            bv[u] = Cs[r * CLD + cw];
-          }
-          y0 = Mfma<T>::op(av[0], bv[0], y0);
-          y1 = Mfma<T>::op(av[1], bv[1], y1);
-          y0 = Mfma<T>::op(av[2], bv[2], y0);
-          y1 = Mfma<T>::op(av[3], bv[3], y1);
+        for (int k = 0; k < 16; k += 2) {
+          y0 = Mfma<T>::op(Vs[(4 * k + g4) * PLD + k0 + i16], cc_[k], y0);
+          y1 = Mfma<T>::op(Vs[(4 * (k + 1) + g4) * PLD + k0 + i16], cc_[k + 1], y1);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -184,36 +196,36 @@ __global__ __launch_bounds__(256) void k_panel_apply(PanelApplyArgs<T> a) {
           st[p][q] -= z[q];
         }
         wave_lds_sync();
-        // C -= V_p Z, one 16-row tile at a time
+        // C -= V_p Z: 16-row tile mt lands on the lane's rows 16 mt + 4 q + g4
         T zb[4];
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) zb[kb] = Yw[(4 * kb + g4) * YLD + i16];
 #pragma unroll
-        for (int mt = 0; mt < PS / 16; ++mt) {
+        for (int mt = 0; mt < 4; ++mt) {
           v4 u = vzero4<T>();
 #pragma unroll
           for (int kb = 0; kb < 4; ++kb)
-            u = Mfma<T>::op(Vs[(16 * mt + i16) * PLD + k0 + 4 * kb + g4], zb[kb], u);
+            u = Mfma<T>::op(Vs[(16 * mt + arow) * PLD + k0 + 4 * kb + g4], zb[kb], u);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) Cs[(16 * mt + Mfma<T>::drow(g4, q)) * CLD + cw] -= u[q];
+          for (int q = 0; q < 4; ++q) cc_[4 * mt + q] -= u[q];
         }
         wave_lds_sync();
       }
     }
-    __syncthreads();
-    // write back the rows this thread staged, then stage the next chunk in
-    // the same slots
+    // write back the chunk rows of this lane's column
     {
       const int64_t r0 = (int64_t)c * PS;
       const int sc = (int)((rows - r0) < PS ? (rows - r0) : PS);
-      T* xd = a.X + (row0 + r0) * a.ldx + c0 + jr;
+      T* xd = a.X + (row0 + r0 + g4) * a.ldx + c0 + cw;
+      const int64_t xstep = 4 * a.ldx;
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int r = rr + 4 * e;
-        if (r < sc && jx) xd[(int64_t)r * a.ldx] = Cs[r * CLD + jr];
+      for (int k = 0; k < 16; ++k) {
+        if (cw_ok && 4 * k + g4 < sc) *xd = cc_[k];
+        xd += xstep;
       }
     }
-    if (cc + 1 < nch) {
+    if (ci + 1 < nch) {
+      __syncthreads();  // every wave is done with this chunk's V and T
       commit();
       __syncthreads();
     }
@@ -312,28 +324,25 @@ __global__ __launch_bounds__(256) void k_copy_cols(int64_t m, int64_t col0, int6
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T>
-hipError_t launch_panel_apply(const PanelApplyArgs<T>& a, bool fwd, hipStream_t st) {
-  if (a.nlv <= 0 || a.ncols <= 0) return hipSuccess;
-  if (a.kw < 1 || a.kw > PW || a.npan != (a.kw + NB - 1) / NB) return hipErrorInvalidValue;
-  const int64_t tiles = (a.ncols + CT - 1) / CT;
+template <typename T, bool FWD>
+static hipError_t launch_panel_apply_t(const PanelApplyArgs<T>& a, hipStream_t st) {
+  const int64_t tiles = (a.ncols + 63) / 64;
   if ((a.leaf_major ? tiles : a.nlv) > 65535) return hipErrorInvalidValue;
   const size_t lds = panel_apply_lds_bytes((int)sizeof(T));
   const dim3 grid = a.leaf_major ? dim3((unsigned)a.nlv, (unsigned)tiles)
                                  : dim3((unsigned)tiles, (unsigned)a.nlv);
-  hipError_t e;
-  if (fwd) {
-    e = hipFuncSetAttribute((const void*)k_panel_apply<T, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_panel_apply<T, true>), grid, dim3(256), lds, st, a);
-  } else {
-    e = hipFuncSetAttribute((const void*)k_panel_apply<T, false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_panel_apply<T, false>), grid, dim3(256), lds, st, a);
-  }
+  hipError_t e = hipFuncSetAttribute((const void*)k_panel_apply<T, FWD>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_panel_apply<T, FWD>), grid, dim3(256), lds, st, a);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_panel_apply(const PanelApplyArgs<T>& a, bool fwd, hipStream_t st) {
+  if (a.nlv <= 0 || a.ncols <= 0) return hipSuccess;
+  if (a.kw < 1 || a.kw > PW || a.npan != (a.kw + NB - 1) / NB) return hipErrorInvalidValue;
+  return fwd ? launch_panel_apply_t<T, true>(a, st) : launch_panel_apply_t<T, false>(a, st);
 }
 template hipError_t launch_panel_apply<double>(const PanelApplyArgs<double>&, bool, hipStream_t);
 template hipError_t launch_panel_apply<float>(const PanelApplyArgs<float>&, bool, hipStream_t);
