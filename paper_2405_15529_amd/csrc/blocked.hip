@@ -80,9 +80,10 @@ __device__ __forceinline__ int a_row_for_b_layout<float>(int i16) {
 // through LDS.  Only the reflector block and T factors are staged in LDS,
 // through registers; the next chunk's loads (C, V, T) are issued before the
 // products of the current one, so their HBM latency overlaps the MFMA work.
+// Two workgroups share a CU.
 template <typename T, bool FWD>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(FWD || sizeof(T) == 4 ? 2 : 1, FWD || sizeof(T) == 4 ? 2 : 1)))
+__attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_panel_apply(PanelApplyArgs<T> a) {
   typedef typename Mfma<T>::v4 v4;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -94,9 +95,18 @@ void k_panel_apply(PanelApplyArgs<T> a) {
     const int64_t d = *a.nc_dev - a.nc_off;
     if (d < nc) nc = d;
   }
-  const int64_t c0 = (int64_t)(a.leaf_major ? blockIdx.y : blockIdx.x) * 64;
+  int64_t tile = a.leaf_major ? blockIdx.y : blockIdx.x;
+  int64_t l = a.leaf_major ? blockIdx.x : blockIdx.y;
+  if (!a.leaf_major && (a.nlv & 7) == 0) {
+    // workgroup ids go to the eight XCDs round-robin: give each XCD whole
+    // leaves, so that the tiles of a leaf share one L2 for its V and T
+    const int64_t id = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+    const int64_t xcd = id & 7, k = id >> 3;
+    l = xcd + 8 * (k / gridDim.x);
+    tile = k % gridDim.x;
+  }
+  const int64_t c0 = tile * 64;
   if (c0 >= nc) return;
-  const int64_t l = a.leaf_major ? blockIdx.x : blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i16 = lane & 15, g4 = lane >> 4;
   const int kw = a.kw, npan = a.npan;
@@ -122,8 +132,12 @@ void k_panel_apply(PanelApplyArgs<T> a) {
   // reflector block staging: thread (rw, jw) holds rows rw + 4 e of column jw
   constexpr int EPV = PS / 4;
   const int jw = tid & 63, rw = tid >> 6;
-  T cc_[16], cn[16], rv[EPV], rt[4];
-  auto fetch = [&](int c) {
+  // the FP64 trailing update has no registers left for a second chunk tile:
+  // it loads the tile after the barrier and leaves the latency to the
+  // second workgroup on the CU
+  constexpr bool PREF_C = FWD || sizeof(T) == 4;
+  T cc_[16], cn[PREF_C ? 16 : 1], rv[EPV], rt[4];
+  auto load_c = [&](int c, T* dst) {
     const int64_t r0 = (int64_t)c * PS;
     const int sc = (int)((rows - r0) < PS ? (rows - r0) : PS);
     const T* xs = a.X + (row0 + r0 + g4) * a.ldx + c0 + cw;
@@ -131,9 +145,14 @@ void k_panel_apply(PanelApplyArgs<T> a) {
     const bool xon = !a.x_zero && cw_ok;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      cn[k] = (xon && 4 * k + g4 < sc) ? *xs : T(0);
+      dst[k] = (xon && 4 * k + g4 < sc) ? *xs : T(0);
       xs += xstep;
     }
+  };
+  auto fetch = [&](int c) {
+    const int64_t r0 = (int64_t)c * PS;
+    const int sc = (int)((rows - r0) < PS ? (rows - r0) : PS);
+    if (PREF_C) load_c(c, cn);
     const T* vs = a.V + (row0 + r0 + rw) * a.ldv + jw;
     const int64_t vstep = 4 * a.ldv;
     const bool von = jw < kw;
@@ -154,11 +173,14 @@ void k_panel_apply(PanelApplyArgs<T> a) {
     for (int e = 0; e < EPV; ++e) Vs[(rw + 4 * e) * PLD + jw] = rv[e];
 #pragma unroll
     for (int e = 0; e < 4; ++e) Ts[tid + 256 * e] = rt[e];
+    if (PREF_C) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) cc_[k] = cn[k];
+      for (int k = 0; k < 16; ++k) cc_[k] = cn[PREF_C ? k : 0];
+    }
   };
   fetch(FWD ? nch - 1 : 0);
   commit();
+  if (!PREF_C) load_c(FWD ? nch - 1 : 0, cc_);
   __syncthreads();
   for (int ci = 0; ci < nch; ++ci) {
     const int c = FWD ? nch - 1 - ci : ci;
@@ -227,6 +249,7 @@ void k_panel_apply(PanelApplyArgs<T> a) {
     if (ci + 1 < nch) {
       __syncthreads();  // every wave is done with this chunk's V and T
       commit();
+      if (!PREF_C) load_c(FWD ? c - 1 : c + 1, cc_);
       __syncthreads();
     }
   }
