@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--m", type=int, default=1_048_576)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--block-rows", type=int, default=4096)
+    ap.add_argument("--blocked-from", type=int, default=0,
+                    help="set the library's blocked_from option for the main workload (0: default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=131072)
     ap.add_argument("--no-spod", action="store_true")
@@ -369,6 +371,8 @@ def main():
     A, s = synth.graded_fp64_device(m=m, n=n, seed=1, device="cuda")
     ctx = api.Context(0)
     ctx.set_option("block_rows", args.block_rows)
+    if args.blocked_from:
+        ctx.set_option("blocked_from", args.blocked_from)
     ctx.set_option("timing", max(1, args.steps))
     ctx.bind_stream()
 

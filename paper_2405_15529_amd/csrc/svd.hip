@@ -69,14 +69,14 @@ static JacobiWs jacobi_ws(const JacobiPlan& p, int max_sweeps, void* ws) {
   c += sizeof(double) * (size_t)p.npad * p.n;
   w.V = (double*)c;
   c += sizeof(double) * (size_t)p.npad * p.n;
-  w.bar = (unsigned int*)c;
-  c += 256;
+  w.bar = (unsigned int*)c;  // global counter, deflation maximum, eight group counters
+  c += 1024;
   w.flags = (int*)c;
   return w;
 }
 
 size_t jacobi_ws_bytes(const JacobiPlan& p, int max_sweeps) {
-  return sizeof(double) * 2 * (size_t)p.npad * p.n + 256 + sizeof(int) * (size_t)(max_sweeps + 64);
+  return sizeof(double) * 2 * (size_t)p.npad * p.n + 1024 + sizeof(int) * (size_t)(max_sweeps + 64);
 }
 
 // ---- setup: A <- R^T (column j = row j of R), V <- I, counters <- 0 ---------
@@ -103,6 +103,8 @@ __global__ void k_jacobi_setup(int n, int npad, const double* __restrict__ R, do
   }
   if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < nflags; k += blockDim.x) flags[k] = 0;
+    if (threadIdx.x < 8)
+      *reinterpret_cast<unsigned int*>(reinterpret_cast<char*>(bar) + 128 + 64 * threadIdx.x) = 0u;
     if (threadIdx.x == 0) {
       *bar = 0u;
       *reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(bar) + 64) = 0ull;
@@ -112,18 +114,37 @@ __global__ void k_jacobi_setup(int n, int npad, const double* __restrict__ R, do
   }
 }
 
-__device__ __forceinline__ void grid_barrier(unsigned int* bar, unsigned int G, unsigned int& epoch,
-                                             int* status) {
+// Device-wide barrier of the G participating workgroups (participant index
+// gi).  Two levels: participants arrive on eight group counters (gi & 7,
+// separate 64-byte lines after the global counter and the deflation word),
+// and only the last arriver of each group increments the global counter, so
+// a barrier costs eight global atomics instead of G.  The spin is bounded:
+// a timeout, or a timeout already flagged by any workgroup, sets the error
+// flag and stops waiting, so a failed barrier ends the kernel quickly
+// instead of stalling every later one.
+__device__ __forceinline__ void grid_barrier(unsigned int* bar, unsigned int G, unsigned int gi,
+                                             unsigned int& epoch, int* status) {
   __syncthreads();
   if (threadIdx.x == 0) {
     ++epoch;
+    const unsigned int ng = G < 8u ? G : 8u;
+    const unsigned int grp = gi & 7u;
+    const unsigned int gs = (G - grp + 7u) / 8u;  // participants in this group
+    unsigned int* cnt =
+        reinterpret_cast<unsigned int*>(reinterpret_cast<char*>(bar) + 128 + 64 * grp);
     __threadfence();
-    atomicAdd(bar, 1u);
-    const unsigned int target = epoch * G;
+    const unsigned int prev = atomicAdd(cnt, 1u);
+    if (prev == epoch * gs - 1u) {
+      __threadfence();
+      atomicAdd(bar, 1u);
+    }
+    const unsigned int target = epoch * ng;
     unsigned long long spins = 0;
     while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(2);
-      if (++spins > (1ull << 24)) {
+      if ((++spins & 1023ull) == 0 &&
+          (spins > (1ull << 24) ||
+           __hip_atomic_load(status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
         atomicExch(status + 1, 1);
         break;
       }
@@ -290,7 +311,7 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
     }
     if (sub == 0)
       atomicMax(cmax, (unsigned long long)__double_as_longlong(nr2[0] > nr2[1] ? nr2[0] : nr2[1]));
-    grid_barrier(a.bar, (unsigned int)a.G, epoch, a.status);
+    grid_barrier(a.bar, (unsigned int)a.G, (unsigned int)g, epoch, a.status);
     const double mx = __longlong_as_double(
         (long long)__hip_atomic_load(cmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const double thr2 = mx * 0x1p-106;
@@ -376,7 +397,7 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
         __syncthreads();
         if (tid == 0 && rot_count) atomicAdd(a.flags + sw, rot_count);
       }
-      grid_barrier(a.bar, (unsigned int)a.G, epoch, a.status);
+      grid_barrier(a.bar, (unsigned int)a.G, (unsigned int)g, epoch, a.status);
     }
     const int total = __hip_atomic_load(a.flags + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (total == 0) {
