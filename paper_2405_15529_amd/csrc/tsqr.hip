@@ -693,17 +693,65 @@ __device__ __forceinline__ void load_chunk(T* __restrict__ C, int ldc, int s, in
 // p-1 to the 16 columns of panel p (look-ahead) and then factors panel p,
 // while waves 1..3 apply panel p-1 to the remaining trailing columns.  The
 // reflectors and T of consecutive panels alternate between two LDS buffers.
+// Small-chunk prefetch of the stacked QR (variant 3): the loads of the next
+// chunk are in flight while the current one is factored, instead of a chain
+// of dependent load rounds at the start of every chunk (a single-wave
+// workgroup needs 16 of them for 64 rows).  Element e = tid + t nthr of the
+// chunk (row e / n, column e % n) goes to register t; rows past the leaf are
+// zero.
+constexpr int kPfn = 32;
+template <typename TI, int N>
+__device__ __forceinline__ void chunk_prefetch(TI (&pfv)[N], const TI* __restrict__ src,
+                                               int64_t ld_src, int c, int64_t rows, int S, int n,
+                                               int tid, int nthr) {
+  const int64_t r0 = (int64_t)c * S;
+  const int lim = (int)(((rows - r0) < S ? (rows - r0) : S) * n);
+  int j = tid - (tid / n) * n;
+  const int di = nthr / n, dj = nthr - (nthr / n) * n;
+  // one walking pointer: consecutive elements of a thread are nthr apart
+  const TI* ptr = src + (r0 + tid / n) * ld_src + j;
+  const int64_t step = (int64_t)di * ld_src + dj, wrap = ld_src - n;
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    pfv[t] = (tid + t * nthr < lim) ? *ptr : TI(0);
+    ptr += step;
+    j += dj;
+    if (j >= n) {
+      j -= n;
+      ptr += wrap;
+    }
+  }
+}
+template <typename T, typename TI, int N>
+__device__ __forceinline__ void chunk_commit(const TI (&pfv)[N], T* __restrict__ C, int ldc, int S,
+                                             int n, int tid, int nthr) {
+  int i = tid / n, j = tid - (tid / n) * n;
+  const int di = nthr / n, dj = nthr - (nthr / n) * n;
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    if (tid + t * nthr < S * n) C[i * ldc + j] = (T)pfv[t];
+    j += dj;
+    i += di;
+    if (j >= n) {
+      j -= n;
+      ++i;
+    }
+  }
+}
+
 // Variants: VAR 0 fills the leaf state from the first chunks (stacked
-// leaves); VAR 1 and 2 compile the filling path out (tree combines and
-// column-blocked panels never fill).  VAR 2 is register-limited to two
-// waves per SIMD, so that two workgroups share a CU, and the wave that
-// factors the panels rotates with the workgroup index, so that the panel
-// waves of co-resident workgroups sit on different SIMDs.
+// leaves); VAR 3 does the same and prefetches small chunks (see pf below);
+// VAR 1 and 2 compile the filling path out (tree combines and column-blocked
+// panels never fill).  VAR 2 is register-limited to two waves per SIMD, so
+// that two workgroups share a CU, and the wave that factors the panels
+// rotates with the workgroup index, so that the panel waves of co-resident
+// workgroups sit on different SIMDs.
 template <typename T, typename TI, int RT, int VAR>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(VAR == 2 ? 2 : 1, VAR == 2 ? 2 : 1)))
 void k_stacked_qr(QrArgs<T, TI> a) {
-  constexpr bool FILL = VAR == 0;
+  constexpr bool FILL = VAR == 0 || VAR == 3;
+  constexpr bool PF = VAR == 3;
   extern __shared__ __align__(16) unsigned char smem[];
   if (blockIdx.y) {
     const int64_t pb = blockIdx.y;
@@ -765,14 +813,24 @@ void k_stacked_qr(QrArgs<T, TI> a) {
     for (int idx = tid; idx < n * n; idx += (int)blockDim.x) state[idx] = T(0);
     __syncthreads();
   }
+  // VAR 3 (leaves without mean removal whose chunk is at most kPfn values
+  // per thread) prefetches the next chunk into registers (chunk_prefetch).
+  TI pfv[PF ? kPfn : 1];
+  if constexpr (PF) chunk_prefetch<TI, kPfn>(pfv, srcI, ld_src, 0, rows, S, n, tid, (int)blockDim.x);
   for (int c = 0; c < nch; ++c) {
     const int64_t r0 = (int64_t)c * S;
     const int sc = (int)((rows - r0) < S ? (rows - r0) : S);
-    if (leaf)
-      load_chunk<T, TI>(C, ldc, S, sc, n, srcI + r0 * ld_src, ld_src, a.remove_mean,
-                        a.mean_ws ? a.mean_ws + row0 + r0 : nullptr, wave, lane, nw);
-    else
-      load_chunk<T, T>(C, ldc, S, sc, n, srcT + r0 * ld_src, ld_src, 0, nullptr, wave, lane, nw);
+    if constexpr (PF) {
+      chunk_commit<T, TI, kPfn>(pfv, C, ldc, S, n, tid, (int)blockDim.x);
+      if (c + 1 < nch)
+        chunk_prefetch<TI, kPfn>(pfv, srcI, ld_src, c + 1, rows, S, n, tid, (int)blockDim.x);
+    } else {
+      if (leaf)
+        load_chunk<T, TI>(C, ldc, S, sc, n, srcI + r0 * ld_src, ld_src, a.remove_mean,
+                          a.mean_ws ? a.mean_ws + row0 + r0 : nullptr, wave, lane, nw);
+      else
+        load_chunk<T, T>(C, ldc, S, sc, n, srcT + r0 * ld_src, ld_src, 0, nullptr, wave, lane, nw);
+    }
     int p_lo, p_hi;
     if (leaf) {
       const int lim = (f + sc < n) ? f + sc : n;
@@ -1130,15 +1188,20 @@ static hipError_t launch_qr_var(const QrArgs<T, TI>& a, int grid, size_t lds, hi
   }
 }
 
-// Leaves of the stacked path fill their state from the first chunks (VAR 0);
-// tree combines never do (VAR 1); column-blocked panels (VAR 2) run two
-// workgroups per CU.
+// Leaves of the stacked path fill their state from the first chunks (VAR 0,
+// or VAR 3 with the small-chunk prefetch); tree combines never do (VAR 1);
+// column-blocked panels (VAR 2) run two workgroups per CU.
 template <typename T, typename TI>
 static hipError_t launch_qr_any(const QrArgs<T, TI>& a, int grid, size_t lds, hipStream_t st,
                                 int64_t gy = 1) {
   if (grid <= 0 || gy <= 0) return hipSuccess;
   if (gy > 65535) return hipErrorInvalidValue;
-  if (a.mode == 0 && a.state_mode == 0) return launch_qr_var<T, TI, 0>(a, grid, lds, st, gy);
+  if (a.mode == 0 && a.state_mode == 0) {
+    const int nthr = (a.npanels <= 2) ? 64 : 256;
+    if (!a.remove_mean && a.s * a.n <= kPfn * nthr)
+      return launch_qr_var<T, TI, 3>(a, grid, lds, st, gy);
+    return launch_qr_var<T, TI, 0>(a, grid, lds, st, gy);
+  }
   if (a.mode == 1) return launch_qr_var<T, TI, 1>(a, grid, lds, st, gy);
   return launch_qr_var<T, TI, 2>(a, grid, lds, st, gy);
 }
