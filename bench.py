@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--wide-block-rows", type=int, default=0, help="0: the library's choice")
     ap.add_argument("--only-wide", action="store_true",
                     help="run only the wide mixed-vs-FP64 leg and print its object")
+    ap.add_argument("--paper-shapes", action="store_true",
+                    help="run only the shapes of the paper's performance study (the JSM "
+                         "matrix and the weak scaling in N) and print their object")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy one 1 GiB FP64 buffer on the device "
                          "(a plain copy of known size, for calibrating HBM byte counters)")
@@ -280,6 +283,151 @@ def timed_wide(api, m, n, steps, warmup, block_rows=0):
     }
 
 
+def fit_power(xs, ts):
+    """Least-squares exponent x and prefactor c of t = c n^x (log-log fit)."""
+    import numpy as np
+    lx, lt = np.log(np.asarray(xs, dtype=np.float64)), np.log(np.asarray(ts, dtype=np.float64))
+    x, lc = np.polyfit(lx, lt, 1)
+    return float(x), float(np.exp(lc))
+
+
+def timed_paper_shapes(api, steps, warmup, jsm_m=58_300_000, jsm_n=56, weak_m=36_000_000,
+                       weak_ns=(10, 20, 40, 80, 160, 320), top_m=18_000_000, top_n=630):
+    """The shapes of the paper's performance study (Sec. 4) on one GPU.
+
+    * The JSM strong-scaling matrix, 5.83e7 x 56 (FP64, 26 GB; a known
+      spectrum s_i = 10^(-i/8) stands in for the flow data): FP64 and mixed
+      at the tuned leaf height, then a sweep of leaf heights that splits the
+      time into leaf QR and tree levels, the one-GPU counterpart of the
+      paper's QR-versus-communication breakdown.
+    * The weak scaling in N: n = 10 sqrt(k) columns at M = 3.6e7 rows (FP32
+      travelling waves, mean removed), FP64 and mixed, for n up to 320; the
+      exponent x of t ~ n^x is fitted over that range.  n = 630 does not fit
+      one GPU at M = 3.6e7 (input, U and the reflectors alone are 273 GB in
+      mixed precision), so it runs at 1.8e7 rows, mixed, and stays out of
+      the fit."""
+    import numpy as np
+    import torch
+    from paper_2405_15529_amd import synth
+
+    def log(msg):
+        print(f"[paper-shapes] {msg}", file=sys.stderr, flush=True)
+
+    def orth_err(U, k):
+        if k == 0:
+            return 0.0
+        Ur = U[:, :k].double()
+        return float(torch.linalg.norm(Ur.T @ Ur - torch.eye(k, dtype=torch.float64,
+                                                               device=U.device)).item())
+
+    def levels(P):
+        lv, h = 0, 1
+        while h < P:
+            lv, h = lv + 1, 2 * h
+        return lv
+
+    def run(A, m, n, precision, remove_mean, b=0):
+        ctx = api.Context(0)
+        ctx.set_option("timing", max(1, steps))
+        ctx.bind_stream()
+        if b:
+            ctx.set_option("block_rows", b)
+        bb = b or api.tune_block_rows(m, n, ctx)
+        res = timed_pod(api, ctx, A, m, n, 0.01, precision, steps, warmup, remove_mean=remove_mean)
+        ctx.close()
+        res["b"] = bb
+        res["orth"] = orth_err(res["U"], res["nr"])
+        del res["U"]
+        torch.cuda.empty_cache()
+        return res
+
+    def summary(res, m, n, s_in):
+        fl = 2.0 * m * n * n + 2.0 * m * n * res["nr"]
+        P = max(1, m // res["b"])
+        return {"ms": round(res["ms"], 3), "tflops": round(fl / (res["ms"] * 1e-3) / 1e12, 4),
+                "gbps": round((2.0 * s_in * m * n + s_in * m * res["nr"]) / (res["ms"] * 1e-3) / 1e9, 2),
+                "n_r": res["nr"], "orth_err_U": res["orth"], "status": res["rc"],
+                "block_rows": res["b"], "leaves": P, "tree_levels": levels(P),
+                "phase_ms": {k: round(v, 3) for k, v in res["phases"].items()}}
+
+    out = {}
+    # --- JSM strong-scaling matrix ---------------------------------------
+    m, n = jsm_m, jsm_n
+    s = 10.0 ** (-np.arange(n) / 8.0)
+    log(f"JSM {m}x{n} FP64 known spectrum")
+    A = synth.known_spectrum_device(m, n, s, seed=5)
+    torch.cuda.synchronize()
+    f = run(A, m, n, "fp64", False)
+    Sf = f["S"].cpu().numpy()
+    jsm = {"workload": f"JSM strong-scaling shape {m}x{n} FP64, known spectrum "
+                       f"s_i=10^(-i/8), 99% energy", "fp64": summary(f, m, n, 8),
+           "sigma_rel_err_retained": float(np.max(np.abs(Sf[:f["nr"]] - s[:f["nr"]]) / s[:f["nr"]]))}
+    log(f"  fp64 {jsm['fp64']['ms']} ms")
+    sweep = []
+    for b in (2048, 8192, 32768, 131072):
+        g = run(A, m, n, "fp64", False, b=b)
+        row = summary(g, m, n, 8)
+        sweep.append({k: row[k] for k in ("block_rows", "leaves", "tree_levels", "ms")} |
+                     {"leaf_qr_ms": row["phase_ms"]["leaf_qr"],
+                      "tree_ms": row["phase_ms"]["tree_combine"],
+                      "tree_ms_per_level": round(row["phase_ms"]["tree_combine"] /
+                                                 max(1, row["tree_levels"]), 4)})
+        log(f"  b={b}: {row['ms']} ms (leaf {sweep[-1]['leaf_qr_ms']}, tree {sweep[-1]['tree_ms']})")
+    jsm["leaf_height_sweep_fp64"] = sweep
+    A32 = A.float()
+    del A
+    torch.cuda.empty_cache()
+    x = run(A32, m, n, "mixed", False)
+    Sx = x["S"].cpu().numpy()
+    k = min(x["nr"], f["nr"])
+    jsm["mixed"] = summary(x, m, n, 4)
+    jsm["mixed"]["sigma_rel_err_vs_fp64_run"] = float(np.max(np.abs(Sx[:k] - Sf[:k]) / Sf[:k])) if k else 0.0
+    jsm["mixed"]["speedup_vs_fp64"] = round(f["ms"] / x["ms"], 3)
+    log(f"  mixed {jsm['mixed']['ms']} ms")
+    del A32
+    torch.cuda.empty_cache()
+    out["jsm"] = jsm
+
+    # --- weak scaling in N ------------------------------------------------
+    pts = []
+    for n in weak_ns:
+        m = weak_m
+        log(f"weak-N {m}x{n} FP32 travelling waves")
+        D = synth.travelling_waves_device(m, n, seed=2)
+        torch.cuda.synchronize()
+        f = run(D, m, n, "fp64", True)
+        x = run(D, m, n, "mixed", True)
+        Sf, Sx = f["S"].cpu().numpy(), x["S"].cpu().numpy()
+        k = min(f["nr"], x["nr"])
+        pt = {"m": m, "n": n, "fp64": summary(f, m, n, 4), "mixed": summary(x, m, n, 4),
+              "sigma_rel_err_mixed_vs_fp64": float(np.max(np.abs(Sx[:k] - Sf[:k]) / Sf[:k])) if k else 0.0}
+        pts.append(pt)
+        log(f"  fp64 {pt['fp64']['ms']} ms, mixed {pt['mixed']['ms']} ms")
+        del D
+        torch.cuda.empty_cache()
+    ns = [p["n"] for p in pts]
+    fits = {}
+    for prec in ("fp64", "mixed"):
+        xe, c = fit_power(ns, [p[prec]["ms"] for p in pts])
+        xl, _ = fit_power(ns, [p[prec]["phase_ms"]["leaf_qr"] for p in pts])
+        fits[prec] = {"x_total": round(xe, 4), "x_leaf_qr": round(xl, 4)}
+    m, n = top_m, top_n
+    log(f"weak-N top point {m}x{n} FP32, mixed")
+    D = synth.travelling_waves_device(m, n, seed=2)
+    torch.cuda.synchronize()
+    x = run(D, m, n, "mixed", True)
+    top = {"m": m, "n": n, "mixed": summary(x, m, n, 4)}
+    log(f"  mixed {top['mixed']['ms']} ms")
+    del D
+    torch.cuda.empty_cache()
+    out["weak_n"] = {"workload": f"weak scaling in N: FP32 travelling waves {weak_m} x n, "
+                                 f"n = 10 sqrt(k), mean removed, 99% energy",
+                     "points": pts, "fit_t_vs_n": fits, "paper_exponent": 1.387,
+                     "top_point": top}
+    out["steps"], out["warmup"] = steps, warmup
+    return out
+
+
 def timed_batch(api, count, seed, steps, warmup):
     """Uneven POD batch: `count` instances, m log-uniform in [5e4, 2e6], n
     uniform in [32, 512], FP32 known spectra s_i = 10^(-6i/n), 99 % energy.
@@ -364,6 +512,10 @@ def main():
     if args.only_wide:
         print(json.dumps({"wide": timed_wide(api, args.wide_m, args.wide_n, args.wide_steps,
                                              1 if args.warmup else 0, args.wide_block_rows)}),
+              flush=True)
+        return
+    if args.paper_shapes:
+        print(json.dumps({"paper_shapes": timed_paper_shapes(api, 2, 1 if args.warmup else 0)}),
               flush=True)
         return
     m, n, r = args.m, args.n, 0.01

@@ -275,8 +275,10 @@ static int64_t level_pairs(int64_t P, int64_t h) { return (P - h + 2 * h - 1) / 
 // chunks; each chunk factors n columns one after another (about 1.6k cycles
 // of latency per column on one wave) plus one look-ahead tile per panel
 // (about 5k cycles).  Leaves run one workgroup per CU, in waves over the
-// device; the tree adds ceil(log2 P) dependent levels of about half a chunk
-// chain each for ceil(n / s) chunks, and every launch costs about 20k cycles.
+// device.  Tree level h holds level_pairs(P, h) combines, one workgroup each,
+// so it too runs in waves over the device; one combine costs about half a
+// chunk chain for each of its ceil(n / s) chunks, and every launch costs
+// about 20k cycles.
 static double leaf_model(int64_t m, int64_t n, int64_t b, int ncu) {
   QrGeom g;
   if (!qr_geom((int)n, 8, &g)) return 1e300;
@@ -287,9 +289,10 @@ static double leaf_model(int64_t m, int64_t n, int64_t b, int ncu) {
   const int64_t last = m - (P - 1) * b;
   const double waves = std::ceil((double)P / (double)ncu);
   const double t_leaf = waves * std::ceil((double)last / g.s) * chain + c_launch;
-  int64_t lv = 0;
-  for (int64_t h = 1; h < P; h *= 2) ++lv;
-  const double t_tree = (double)lv * (std::ceil((double)n / g.s) * chain * 0.5 + c_launch);
+  const double combine = std::ceil((double)n / g.s) * chain * 0.5;
+  double t_tree = 0.0;
+  for (int64_t h = 1; h < P; h *= 2)
+    t_tree += std::ceil((double)level_pairs(P, h) / (double)ncu) * combine + c_launch;
   return t_leaf + t_tree;
 }
 

@@ -1,0 +1,170 @@
+"""GPU checks at the shapes of the paper's performance study (Sec. 4), in the
+launch configurations bench.py --paper-shapes times.  The oracle cannot
+finish these shapes, so each test checks what holds at any size or what it
+can recompute on sampled rows:
+
+* the JSM strong-scaling matrix, 58,300,000 x 56 FP64 with a known spectrum:
+  sigma against the exact spectrum, orthogonality, sampled rows of U against
+  (A v_j) / sigma_j, and the mixed path on the FP32 copy against the FP64 run;
+* the weak scaling in N at M = 36,000,000 rows, its widest point that fits
+  in both precisions (n = 320, FP32 travelling waves, mean removed): mixed
+  against FP64 on the same buffer, the mean and U on sampled rows;
+* n = 630 at 18,000,000 rows, mixed: sigma against the square roots of the
+  eigenvalues of the FP64 Gram (D - mu 1^T)^T (D - mu 1^T), accumulated by
+  torch over row slices (relative error about u64 (sigma_1 / sigma_i)^2 on
+  the retained modes, far below the bar), N_r against the oracle's
+  truncation rule applied to that spectrum, orthogonality and sampled rows.
+
+Bars: FP64 on FP64 data 1e-12 (sigma, orthogonality, sampled rows); mixed,
+and U stored in FP32, 1e-6 (sigma, orthogonality) and 1e-5 (sampled rows of U, relative to the column's
+largest entry), as for the other full-size tests.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_15529_amd import synth
+from tests import checks
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def orth_err_dev(U):
+    import torch
+    Ud = U.double()
+    return float(torch.linalg.norm(Ud.T @ Ud - torch.eye(Ud.shape[1], dtype=torch.float64,
+                                                           device=U.device)).item())
+
+
+def sampled_u_err(D, rows, out, mu=None):
+    """max over the retained columns of |U[rows] - Y[rows] v / sigma|, each
+    column scaled by its largest reference entry on the sample."""
+    import torch
+    Y = D[rows].double()
+    if mu is not None:
+        Y = Y - mu[:, None]
+    nr = out.nr
+    ref = (Y @ out.VT[:nr].T.contiguous()) / out.S[:nr]
+    err = torch.abs(out.U[rows].double() - ref).max(dim=0).values
+    return float((err / torch.abs(ref).max(dim=0).values).max().item())
+
+
+def test_jsm_58300000x56_fp64_and_mixed():
+    import torch
+    from paper_2405_15529_amd import api
+    m, n = 58_300_000, 56
+    say(f"[gpu] JSM shape {m}x{n} FP64 known spectrum")
+    s = 10.0 ** (-np.arange(n) / 8.0)
+    A = synth.known_spectrum_device(m, n, s, seed=5)
+    ctx = api.Context(0)
+    out = api.pod(A, remove_mean=False, r=0.01, ctx=ctx)
+    rc, sweeps = ctx.status()
+    nr = out.nr
+    S = out.S.cpu().numpy()
+    rel = float(np.max(np.abs(S[:nr] - s[:nr]) / s[:nr]))
+    nw = float(np.max(np.abs(S - s)) / s[0])
+    oe = orth_err_dev(out.U)
+    say(f"    rc {rc} sweeps {sweeps} N_r {nr}; sigma rel {rel:.2e} normwise {nw:.2e} "
+        f"|U^T U - I|_F {oe:.2e}")
+    assert rc == 0 and nr > 0
+    assert rel <= 1e-12 and nw <= 1e-12 and oe <= 1e-12
+    rows = torch.from_numpy(np.random.default_rng(8).choice(m, 256, replace=False)).cuda()
+    ref = (A[rows] @ out.VT[:nr].T.contiguous()) / out.S[:nr]
+    err = float((torch.abs(out.U[rows] - ref) * (out.S[:nr] / out.S[0])).max().item())
+    say(f"    sampled rows: max |u - A v / sigma| sigma / sigma_1 {err:.2e}")
+    assert err <= 1e-12
+    A32 = A.float()
+    del A, out
+    torch.cuda.empty_cache()
+    x = api.pod(A32, remove_mean=False, r=0.01, precision="mixed", ctx=ctx)
+    rcx, _ = ctx.status()
+    Sx = x.S.cpu().numpy()
+    assert rcx == 0
+    assert checks.nr_agrees(x.nr, nr, S, 0.01, tie=1e-5), (x.nr, nr)
+    k = min(x.nr, nr)
+    relx = float(np.max(np.abs(Sx[:k] - S[:k]) / S[:k]))
+    oex = orth_err_dev(x.U)
+    say(f"    mixed: N_r {x.nr} sigma rel vs FP64 {relx:.2e} |U^T U - I|_F {oex:.2e}")
+    assert relx <= 1e-6 and oex <= 1e-6
+    ctx.close()
+
+
+def test_weak_n_36000000x320_mixed_vs_fp64():
+    import torch
+    from paper_2405_15529_amd import api
+    m, n = 36_000_000, 320
+    say(f"[gpu] weak-N shape {m}x{n} FP32 travelling waves: mixed and FP64")
+    D = synth.travelling_waves_device(m, n, seed=2)
+    rows = torch.from_numpy(np.random.default_rng(9).choice(m, 256, replace=False)).cuda()
+    mu_ref = D[rows].double().mean(dim=1)
+    ctx = api.Context(0)
+    x = api.pod(D, remove_mean=True, r=0.01, precision="mixed", ctx=ctx)
+    rcx, swx = ctx.status()
+    Sx, nrx = x.S.cpu().numpy(), x.nr
+    oex = orth_err_dev(x.U)
+    errx = sampled_u_err(D, rows, x, mu_ref)
+    emx = float((torch.abs(x.mean[rows].double() - mu_ref) /
+                 torch.abs(mu_ref).clamp_min(1e-30)).max())
+    del x
+    torch.cuda.empty_cache()
+    f = api.pod(D, remove_mean=True, r=0.01, precision="fp64", ctx=ctx)
+    rcf, swf = ctx.status()
+    Sf, nrf = f.S.cpu().numpy(), f.nr
+    oef = orth_err_dev(f.U)
+    errf = sampled_u_err(D, rows, f, mu_ref)
+    emf = float((torch.abs(f.mean[rows].double() - mu_ref) /
+                 torch.abs(mu_ref).clamp_min(1e-30)).max())
+    say(f"    rc {rcx}/{rcf} sweeps {swx}/{swf} N_r {nrx}/{nrf}")
+    assert rcx == 0 and rcf == 0
+    assert checks.nr_agrees(nrx, nrf, Sf, 0.01, tie=1e-5), (nrx, nrf)
+    k = min(nrx, nrf)
+    assert k > 0
+    rel = float(np.max(np.abs(Sx[:k] - Sf[:k]) / Sf[:k]))
+    say(f"    sigma rel mixed vs FP64 {rel:.2e}; |U^T U - I|_F mixed {oex:.2e} FP64 {oef:.2e}; "
+        f"sampled U rows {errx:.2e} / {errf:.2e}; mean {emx:.2e} / {emf:.2e}")
+    # U is stored in the input's type (FP32) on both paths
+    assert rel <= 1e-6 and oex <= 1e-6 and oef <= 1e-6
+    assert errx <= 1e-5 and errf <= 1e-5
+    assert max(emx, emf) <= 2.0 ** -23
+    ctx.close()
+
+
+def test_weak_n_top_18000000x630_mixed_vs_gram():
+    import torch
+    from paper_2405_15529_amd import api
+    m, n = 18_000_000, 630
+    say(f"[gpu] weak-N top shape {m}x{n} FP32 travelling waves, mixed, against the FP64 Gram")
+    D = synth.travelling_waves_device(m, n, seed=2)
+    G = torch.zeros((n, n), dtype=torch.float64, device=D.device)
+    for r0 in range(0, m, 1_000_000):
+        Y = D[r0:r0 + 1_000_000].double()
+        Y -= Y.mean(dim=1, keepdim=True)
+        G += Y.T @ Y
+        del Y
+    lam = torch.linalg.eigvalsh(G).flip(0).clamp_min(0.0)
+    Sref = torch.sqrt(lam).cpu().numpy()
+    del G
+    torch.cuda.empty_cache()
+    rows = torch.from_numpy(np.random.default_rng(10).choice(m, 256, replace=False)).cuda()
+    mu_ref = D[rows].double().mean(dim=1)
+    ctx = api.Context(0)
+    x = api.pod(D, remove_mean=True, r=0.01, precision="mixed", ctx=ctx)
+    rc, sweeps = ctx.status()
+    Sx, nr = x.S.cpu().numpy(), x.nr
+    assert rc == 0
+    nr_ref = oracle.truncate(Sref, 0.01)
+    assert nr > 0 and checks.nr_agrees(nr, nr_ref, Sref, 0.01, tie=1e-5), (nr, nr_ref)
+    rel = float(np.max(np.abs(Sx[:nr] - Sref[:nr]) / Sref[:nr]))
+    oe = orth_err_dev(x.U)
+    err = sampled_u_err(D, rows, x, mu_ref)
+    say(f"    rc {rc} sweeps {sweeps} N_r {nr}; sigma rel vs Gram {rel:.2e}; "
+        f"|U^T U - I|_F {oe:.2e}; sampled U rows {err:.2e}")
+    assert rel <= 1e-6 and oe <= 1e-6 and err <= 1e-5
+    ctx.close()
