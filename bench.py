@@ -37,8 +37,12 @@ def parse():
     ap.add_argument("--m", type=int, default=1_048_576)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--block-rows", type=int, default=4096)
-    ap.add_argument("--blocked-from", type=int, default=0,
-                    help="set the library's blocked_from option for the main workload (0: default)")
+    ap.add_argument("--blocked-from", type=int, default=1025,
+                    help="the library's blocked_from option for the main workload (default "
+                         "1025: the stacked QR, the faster path at 4096-row leaves; 0: the "
+                         "library's automatic choice)")
+    ap.add_argument("--no-default-path", action="store_true",
+                    help="skip the run of the main matrix on the library's automatic path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=131072)
     ap.add_argument("--no-spod", action="store_true")
@@ -523,8 +527,7 @@ def main():
     A, s = synth.graded_fp64_device(m=m, n=n, seed=1, device="cuda")
     ctx = api.Context(0)
     ctx.set_option("block_rows", args.block_rows)
-    if args.blocked_from:
-        ctx.set_option("blocked_from", args.blocked_from)
+    ctx.set_option("blocked_from", args.blocked_from)
     ctx.set_option("timing", max(1, args.steps))
     ctx.bind_stream()
 
@@ -550,6 +553,30 @@ def main():
     leaf_ms = f["phases"]["leaf_qr"]
     leaf_tflops = 2.0 * m * n * n / (leaf_ms * 1e-3) / 1e12
 
+    # the same matrix on the library's automatic choice of path and leaf height
+    auto = None
+    if not args.no_default_path:
+        ctx_a = api.Context(0)
+        ctx_a.set_option("timing", max(1, args.steps))
+        ctx_a.bind_stream()
+        a = timed_pod(api, ctx_a, A, m, n, r, "fp64", args.steps, args.warmup)
+        Sa = a["S"].cpu().numpy()
+        nra = a["nr"]
+        b_auto = api.tune_block_rows(m, n, ctx_a)
+        ctx_a.set_option("blocked_from", 2)
+        b_blk = api.tune_block_rows(m, n, ctx_a)
+        ctx_a.set_option("blocked_from", 0)
+        auto = {"path": "column-blocked TSQR" if b_auto == b_blk else "stacked TSQR",
+                "block_rows": b_auto,
+                "ms_per_step": round(a["ms"], 4),
+                "tflops": round((2.0 * m * n * n + 2.0 * m * n * nra) / (a["ms"] * 1e-3) / 1e12, 4),
+                "n_r": nra,
+                "sigma_rel_err_retained": float(np.max(np.abs(Sa[:nra] - s[:nra]) / s[:nra])) if nra else 0.0,
+                "orth_err_U": orth_err(a["U"], nra),
+                "phase_ms": {k: round(v, 4) for k, v in a["phases"].items()}}
+        ctx_a.close()
+        del a
+        torch.cuda.empty_cache()
     if args.copy_probe:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -583,7 +610,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"known-spectrum POD FP64 {m}x{n}, s_i=10^(-i/32), "
                                f"row blocks {args.block_rows}, 99% energy",
-                   "m": m, "n": n, "block_rows": args.block_rows, "precision": "fp64"},
+                   "m": m, "n": n, "block_rows": args.block_rows, "precision": "fp64",
+                   "blocked_from": args.blocked_from},
         "gbps": round(gbps, 2),
         "n_r": nr,
         "sigma_rel_err_retained": sig_rel,
@@ -592,6 +620,7 @@ def main():
         "jacobi_sweeps": f["sweeps"],
         "phase_ms": {k: round(v, 4) for k, v in f["phases"].items()},
         "mixed": mixed,
+        "library_default": auto,
         "roofline": {"bound": "mfma", "kernel": "k_stacked_qr (leaf QR, FP64)",
                      "achieved": round(leaf_tflops, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(leaf_tflops / FP64_PEAK_TFLOPS, 4),

@@ -95,13 +95,17 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
  *                  pod/tsvd call in a ring of k call slots (read back with
  *                  pylom_phase_times); 0 = off (default).
  *   "blocked_from" n at which pod/tsvd/tsqr switch to the column-blocked
- *                  TSQR (2..2049, default 1025): every leaf and every tree
- *                  combine is then a blocked Householder QR over panels of 64
- *                  columns (the local QR of Alg. 1 as LAPACK blocks it), the
- *                  leaf height defaults to ceil(m / (2 CUs)) rounded up to 64,
- *                  and the working copy of D, the reflectors of every panel
- *                  and the tree pairs stay in the workspace.  Smaller values
- *                  route narrow problems through the same path (tests).
+ *                  TSQR (2..2049), or 0 (default) for the automatic choice:
+ *                  column-blocked when n >= 512, or when n >= 64 and
+ *                  m <= 8,388,608; the stacked QR otherwise (and for every
+ *                  instance of pylom_pod_batched with n <= 1024).  On the
+ *                  column-blocked path every leaf and every tree combine is a
+ *                  blocked Householder QR over panels of 64 columns (the
+ *                  local QR of Alg. 1 as LAPACK blocks it), the leaf height
+ *                  defaults to ceil(m / (2 CUs)) rounded up to 64, and the
+ *                  working copy of D, the reflectors of every panel and the
+ *                  tree pairs stay in the workspace.  The stacked QR factors
+ *                  at most 1024 columns.
  * Unknown keys return PYLOM_EINVAL. */
 int pylom_set_option(pylom_ctx ctx, const char* key, int64_t value);
 int pylom_get_option(pylom_ctx ctx, const char* key, int64_t* value);
@@ -130,9 +134,9 @@ const char* pylom_last_error(pylom_ctx ctx);
  *   n_r    one int64 in device memory: N_r.
  * Sign convention: each (u_i, v_i) is signed so that the largest-magnitude
  * entry of v_i (lowest index on ties) is positive.  Requires m >= n >= 1 and
- * n <= 2048 (n >= "blocked_from": the column-blocked TSQR; there the modes of
- * an exactly zero singular value of an exactly rank-deficient panel may come
- * out as zero columns of U).
+ * n <= 2048 (on the column-blocked TSQR, see "blocked_from", the modes of an
+ * exactly zero singular value of an exactly rank-deficient panel may come out
+ * as zero columns of U).
  * PYLOM_MIXED (D must be R32): FP32 leaf QR without reflector storage, FP64
  * tree and SVD of R, then a Rayleigh-Ritz refinement against D in FP64 on the
  * k = min(n, N0 + max(8, N0/4)) leading right singular vectors V_k of that SVD
@@ -177,7 +181,8 @@ int pylom_matmul(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int trans_a,
 
 /* One instance of a batched POD (the arguments of pylom_pod). */
 typedef struct {
-  int64_t m, n;        /* shape, m >= n >= 1, n < "blocked_from"             */
+  int64_t m, n;        /* shape, m >= n >= 1, n <= 1024 and, when the
+                          "blocked_from" option is set, n < blocked_from     */
   const void* D;       /* m x n snapshots (storage type of the batch), ldd   */
   int64_t ldd;
   int remove_mean;     /* Alg. 2 mean removal                                 */
@@ -212,8 +217,9 @@ int pylom_pod_batched(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t
  * minimiser, over b in {128, 256, ..., 32768} with b >= n, of a latency model
  * of the stacked QR (leaf critical path of ceil(b / s) chunks, waves of leaves
  * over the device's compute units, ceil(log2 P) dependent tree levels and one
- * launch per level).  For n >= "blocked_from", ceil(m / (2 CUs)) rounded up
- * to a multiple of 64 (at least n).  Host only; n <= 2048. */
+ * launch per level).  Where the column-blocked TSQR serves the shape (see
+ * "blocked_from"), ceil(m / (2 CUs)) rounded up to a multiple of 64 (at
+ * least n).  Host only; n <= 2048. */
 int64_t pylom_tune_block_rows(pylom_ctx ctx, int64_t m, int64_t n);
 
 /* SPOD (Alg. 6; Sec. 2.3, Eq. csdimp with the SVD of the spectral matrix).

@@ -30,7 +30,7 @@ struct pylom_ctx_s {
   int64_t block_rows = 0;
   int64_t max_sweeps = 60;
   int64_t ws_cap_mb = 0;
-  int64_t blocked_from = 1025;  // n at which the column-blocked TSQR takes over
+  int64_t blocked_from = 0;  // n at which the column-blocked TSQR takes over (0: automatic)
   int* status_dev = nullptr;  // Jacobi status pairs (sweeps, barrier timeout) of the last call
   int status_valid = 0;
   int status_pairs = 1;        // 2 after a mixed-precision call (SVD of R + Gram eigen)
@@ -155,7 +155,8 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
     if (v < 0) return fail(c, PYLOM_EINVAL, "ws_cap_mb must be >= 0");
     c->ws_cap_mb = v;
   } else if (!std::strcmp(key, "blocked_from")) {
-    if (v < 2 || v > kMaxN + 1) return fail(c, PYLOM_EINVAL, "blocked_from must be in [2, 2049]");
+    if (v != 0 && (v < 2 || v > kMaxN + 1))
+      return fail(c, PYLOM_EINVAL, "blocked_from must be 0 or in [2, 2049]");
     c->blocked_from = v;
   } else if (!std::strcmp(key, "streams")) {
     if (v < 1 || v > 16) return fail(c, PYLOM_EINVAL, "streams must be in [1, 16]");
@@ -320,16 +321,29 @@ static int64_t blocked_block_rows(int64_t m, int64_t n, int ncu) {
   return (b + kPW - 1) / kPW * kPW;
 }
 
+// Which TSQR serves an m x n problem.  An explicit "blocked_from" threshold
+// decides alone.  The automatic choice (0) follows measurements of both paths
+// on one MI355X: the column-blocked TSQR was 1.1-2x faster for 64 <= n <= 1024
+// at up to 4M rows and 2.4x faster at 1.8e7 x 630, while the stacked QR was
+// faster at 3.6e7 x 160 (many short leaves keep every CU busy and its
+// workspace is smaller).  Batched instances stay on the stacked QR up to
+// n = 1024, the widest it factors.
+static bool use_blocked(const pylom_ctx_s* c, int64_t m, int64_t n, bool batched = false) {
+  if (c->blocked_from > 0) return n >= c->blocked_from;
+  if (batched) return n > 1024;
+  return n >= 512 || (n >= 64 && m <= ((int64_t)8 << 20));
+}
+
 extern "C" int64_t pylom_tune_block_rows(pylom_ctx c, int64_t m, int64_t n) {
   if (!c || n < 1 || m < n || n > kMaxN) return PYLOM_EINVAL;
-  if (n >= c->blocked_from) return blocked_block_rows(m, n, c->ncu);
+  if (use_blocked(c, m, n)) return blocked_block_rows(m, n, c->ncu);
   return tune_block_rows(m, n, c->ncu);
 }
 
 static int make_blocked_plan(pylom_ctx c, Plan* p, bool mixed);
 
 static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
-                     bool mixed = false) {
+                     bool mixed = false, bool batched = false) {
   if (n < 1 || m < n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
   if (n > kMaxN) return fail(c, PYLOM_ENOTSUP, "n > 2048 is not supported");
   p->mixed = mixed;
@@ -338,7 +352,7 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
   if (mixed) store_q = false;
   p->m = m;
   p->n = n;
-  if (n >= c->blocked_from) return make_blocked_plan(c, p, mixed);
+  if (use_blocked(c, m, n, batched)) return make_blocked_plan(c, p, mixed);
   int64_t b = c->block_rows > 0 ? c->block_rows : tune_block_rows(m, n, c->ncu);
   if (b < n) b = n;
   int64_t P = m / b;
@@ -416,7 +430,7 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
   return PYLOM_OK;
 }
 
-// Wide problems (n >= blocked_from): the leaves and the tree combines are
+// Wide problems (use_blocked): the leaves and the tree combines are
 // column-blocked QRs (blocked.hip).  Workspace, in order: the working copy of
 // D (compute type), the leaf T factors and panel states (per panel), the
 // FP64 R of every leaf (tree state in place; the partner's triangle keeps
@@ -659,7 +673,7 @@ static int enqueue_fp64(pylom_ctx c, const Exec& x, const Plan& p, pylom_dtype d
   return PYLOM_OK;
 }
 
-// ---- column-blocked sequences (n >= blocked_from) ---------------------------
+// ---- column-blocked sequences (use_blocked) -------------------------------
 static size_t t_slot(const Plan& p, bool pairs) {  // T-factor elements per panel
   return (size_t)(pairs ? p.P - 1 : p.P) * (pairs ? p.nch_p : p.nch_l) * 4 * kTF;
 }
@@ -1156,7 +1170,7 @@ extern "C" int pylom_pod_batched(pylom_ctx c, pylom_dtype dtype, pylom_prec prec
     if (q.n < 1 || q.m < q.n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
     if (q.ldd < q.n || q.ldu < q.n || q.ldvt < q.n)
       return fail(c, PYLOM_ESHAPE, "leading dimension < n");
-    rc = make_plan(c, q.m, q.n, !mixed, &L.plans[(size_t)i], mixed);
+    rc = make_plan(c, q.m, q.n, !mixed, &L.plans[(size_t)i], mixed, true);
     if (rc) return rc;
     if (L.plans[(size_t)i].blocked)
       return fail(c, PYLOM_ENOTSUP, "batched problems need n below the blocked_from option");

@@ -108,7 +108,7 @@ def test_plan_geometry(hctx):
 
 def test_blocked_plan_geometry(hctx):
     # the wide mixed-precision case: 4,194,304 x 1,808, one leaf per CU
-    assert hctx.get_option("blocked_from") == 1025
+    assert hctx.get_option("blocked_from") == 0  # automatic
     ncu = 256
     m, n = 4_194_304, 1808
     p = hctx.plan(m, n)
@@ -135,6 +135,27 @@ def test_blocked_plan_geometry(hctx):
         hctx.set_option("blocked_from", 1)
     with pytest.raises(api.PylomError):
         hctx.set_option("blocked_from", 4096)
+
+
+def test_automatic_path_choice(hctx):
+    # blocked_from = 0: column-blocked for n >= 512, or n >= 64 with
+    # m <= 8,388,608; the stacked QR otherwise.  Each path has its own leaf
+    # height, read here with the path forced by an explicit threshold.
+    def rows(m, n, bf):
+        hctx.set_option("blocked_from", bf)
+        return api.tune_block_rows(m, n, hctx)
+
+    for m, n, blocked in [(1_048_576, 256, True), (1_048_576, 63, False),
+                          (8_388_608, 64, True), (8_388_609, 64, False),
+                          (36_000_000, 320, False), (18_000_000, 630, True),
+                          (58_300_000, 56, False), (4_194_304, 1808, True)]:
+        want = rows(m, n, 2 if blocked else 2049)
+        other = rows(m, n, 2049 if blocked else 2)
+        assert want != other, (m, n)
+        hctx.set_option("blocked_from", 0)
+        assert api.tune_block_rows(m, n, hctx) == want, (m, n)
+        assert hctx.plan(m, n)["block_rows"] == want, (m, n)
+    assert hctx.get_option("blocked_from") == 0
 
 
 def emulate_alg1(P):
@@ -232,11 +253,15 @@ def test_spod_query_and_validation(hctx):
 
 
 def test_block_rows_tuner(hctx):
-    # the latency model keeps the 4096-row leaves of the 1048576 x 256 workload
+    # the stacked QR's latency model keeps the 4096-row leaves of the
+    # 1048576 x 256 workload (the automatic path choice puts that shape on
+    # the column-blocked TSQR, so the stacked path is named here)
+    hctx.set_option("blocked_from", 1025)
     assert api.tune_block_rows(1 << 20, 256, hctx) == 4096
     for m, n in [(20000, 100), (50000, 32), (2_000_000, 512), (1000, 1000), (300, 200)]:
         b = api.tune_block_rows(m, n, hctx)
         assert b >= n and (b & (b - 1)) == 0 or b == n
+    hctx.set_option("blocked_from", 0)
     assert hctx.lib.pylom_tune_block_rows(hctx.h, 10, 20) < 0   # m < n
 
 

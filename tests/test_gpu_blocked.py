@@ -162,7 +162,7 @@ def test_blocked_wide_known_spectrum():
     A_np, Q1, _ = synth.known_spectrum(m, n, s, seed=41)
     A = torch.from_numpy(A_np).cuda()
     ctx = api.Context(0)
-    assert ctx.get_option("blocked_from") == 1025
+    assert ctx.get_option("blocked_from") == 0  # automatic: n >= 512 is column-blocked
     out = api.pod(A, remove_mean=False, r=0.0, ctx=ctx)
     rc, sweeps = ctx.status()
     say(f"    rc {rc} sweeps {sweeps} nr {out.nr}")
