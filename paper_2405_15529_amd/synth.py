@@ -221,3 +221,41 @@ def known_spectrum_device(m: int, n: int, s, seed: int, device: str = "cuda",
 def uneven_spectrum(n: int) -> np.ndarray:
     """s_i = 10^(-6 i / n), i = 0..n-1: six decades over every instance."""
     return 10.0 ** (-6.0 * np.arange(n) / n)
+
+
+def linear_dynamics(m: int, nt: int, seed: int = 6, pairs=None, real_eigs=(), noise: float = 0.0):
+    """Snapshots of an exactly linear system, d_t = sum_i phi_i b_i lambda_i^t
+    (t = 0..nt-1), real because the complex eigenvalues come in conjugate
+    pairs with conjugate modes and amplitudes.
+
+    pairs: (radius, angle) of each conjugate pair lambda = r e^{+-i angle};
+    real_eigs: real eigenvalues (real modes and amplitudes).  Modes are
+    random complex unit vectors, amplitudes random of modulus in [0.5, 2].
+    Returns (D m x nt float64, lam, phi m x k complex, b) listing every
+    eigenvalue (both members of each pair)."""
+    rng = np.random.default_rng(seed)
+    if pairs is None:
+        pairs = [(0.99, 0.3), (0.97, 0.9), (0.93, 1.7)]
+    lam, phi, amp = [], [], []
+    for rad, ang in pairs:
+        v = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+        v /= np.linalg.norm(v)
+        a = rng.uniform(0.5, 2.0) * np.exp(1j * rng.uniform(0.0, 2.0 * np.pi))
+        z = rad * np.exp(1j * ang)
+        lam += [z, np.conj(z)]
+        phi += [v, np.conj(v)]
+        amp += [a, np.conj(a)]
+    for z in real_eigs:
+        v = rng.standard_normal(m).astype(np.complex128)
+        v /= np.linalg.norm(v)
+        lam.append(complex(z))
+        phi.append(v)
+        amp.append(complex(rng.uniform(0.5, 2.0) * rng.choice([-1.0, 1.0])))
+    lam = np.array(lam)
+    phi = np.array(phi).T
+    amp = np.array(amp)
+    t = np.arange(nt)
+    D = np.real((phi * amp[None, :]) @ (lam[:, None] ** t[None, :]))
+    if noise:
+        D = D + noise * rng.standard_normal(D.shape)
+    return np.ascontiguousarray(D), lam, phi, amp
