@@ -252,6 +252,44 @@ int pylom_spod(pylom_ctx ctx, pylom_dtype spectra, pylom_prec prec, int64_t m, i
                const float* D, int64_t ldd, double dt, int64_t npwin, int64_t nolap, int window,
                int remove_mean, void* modes, double* L, double* freqs, int64_t* order);
 
+/* Exact DMD (Sec. 3.2, the exact DMD of Tu et al.; Alg. 3 with the product
+ * of Alg. 4 and the amplitudes of Alg. 5, Jovanovic et al.).
+ *
+ *   D       m x n snapshots (rows = points, ldd >= n), PYLOM_R64 or PYLOM_R32
+ *           (promoted to FP64), device; n >= 2 and m >= n - 1.
+ *   remove_mean  nonzero: Y = D - mean 1^T with the mean over all n
+ *           snapshots; zero: Y = D.  Y1 = Y[:, :n-1], Y2 = Y[:, 1:].
+ *   residual  truncation of the TS-SVD of Y1 = U S W^T, as for pylom_pod.
+ *   dt      snapshot spacing (> 0), for the frequencies and growth rates.
+ *   phi     m x ldphi complex128 (interleaved re, im), ldphi >= min(n-1, 128);
+ *           columns 0..N_r-1 receive the exact DMD modes
+ *           phi_i = Y2 W S^-1 w_i / mu_i (Eq. dmdmodes).
+ *   mu, b   min(n-1, 128) complex128 each: the eigenvalues of the linear map
+ *           A = U^T Y2 W S^-1 and the amplitudes minimising
+ *           |S W^T - w diag(b) V_and|_F (V_and[i][t] = mu_i^t, t < n-1).
+ *   freq, growth  min(n-1, 128) doubles each, or NULL: arg(mu) / (2 pi dt)
+ *           (Eq. freq) and log|mu| / dt.
+ *   n_r     one int64 in device memory: N_r.
+ * Every modal output is ordered by |b| descending (ties: Im(mu) descending,
+ * then eigenvalue index).  Each eigenvector w_i has unit 2-norm with its
+ * largest-magnitude entry real and positive.  All arithmetic is FP64; every
+ * step runs on the device (TS-SVD, U^T Y2, Householder-Hessenberg reduction,
+ * Francis double-shift QR, complex inverse iteration, the Cholesky solve of
+ * Alg. 5, the mode GEMM).  The call synchronises once, to read N_r.
+ * Errors: PYLOM_ESHAPE (shapes, leading dimensions), PYLOM_EINVAL (null
+ * arrays, residual outside [0, 1), dt <= 0), PYLOM_ENOTSUP when the
+ * truncation keeps more than 128 modes or a zero singular value (raise the
+ * residual).  N_r = 0 (Y1 = 0) writes n_r only.  A QR sweep limit or a
+ * Cholesky pivot <= 0 is reported by pylom_check as PYLOM_WNOCONV.  The
+ * workspace holds an FP64 copy of Y when remove_mean is set or D is R32,
+ * and U (m x (n-1), FP64). */
+int pylom_dmd(pylom_ctx ctx, pylom_dtype dtype, int64_t m, int64_t n, const void* D, int64_t ldd,
+              int remove_mean, double residual, double dt, void* phi, int64_t ldphi, void* mu,
+              void* b, double* freq, double* growth, int64_t* n_r);
+/* Workspace bytes of a pylom_dmd call of this shape (host only). */
+int pylom_dmd_workspace_query(pylom_ctx ctx, pylom_dtype dtype, int64_t m, int64_t n,
+                              int remove_mean, size_t* bytes);
+
 /* Number of Welch blocks and frequencies, and the workspace bytes, of a
  * pylom_spod call of this shape (host only). */
 int pylom_spod_query(pylom_ctx ctx, pylom_dtype spectra, int64_t m, int64_t nt, int64_t npwin,
@@ -290,7 +328,7 @@ int pylom_plan_query(pylom_ctx ctx, int64_t m, int64_t n, int64_t* leaves, int64
 int pylom_phase_times(pylom_ctx ctx, double* out, int cap);
 
 /* After a stream synchronisation: the deferred numerical status of the last
- * pod/tsvd call on this context (0 or PYLOM_WNOCONV) and its sweep count.
+ * pod/tsvd/dmd call on this context (0 or PYLOM_WNOCONV) and its sweep count.
  * Synchronises the context's stream. */
 int pylom_check(pylom_ctx ctx, int64_t* sweeps);
 

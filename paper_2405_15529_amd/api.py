@@ -282,6 +282,54 @@ def spod(D: torch.Tensor, dt: float = 1.0, npwin: int = 256, nolap: int = 128,
     return SpodResult(modes=modes, L=L, f=f, order=order)
 
 
+DMD_MAX_MODES = 128
+
+
+@dataclass
+class DmdResult:
+    phi: torch.Tensor     # m x N_r complex128 exact DMD modes, ordered by |b|
+    mu: torch.Tensor      # N_r complex128 eigenvalues of the linear map
+    b: torch.Tensor       # N_r complex128 amplitudes (Alg. 5)
+    freq: torch.Tensor    # N_r frequencies arg(mu) / (2 pi dt)
+    growth: torch.Tensor  # N_r growth rates log|mu| / dt
+    nr: int
+
+
+def dmd_workspace_bytes(m: int, n: int, dtype=R64, remove_mean: bool = False,
+                        ctx: Context | None = None) -> int:
+    ctx = ctx or Context(-1)
+    b = ctypes.c_size_t()
+    ctx.check(ctx.lib.pylom_dmd_workspace_query(ctx.h, dtype, m, n, int(bool(remove_mean)),
+                                                ctypes.byref(b)))
+    return b.value
+
+
+def dmd(D: torch.Tensor, remove_mean: bool = False, r: float = 0.01, dt: float = 1.0,
+        ctx: Context | None = None) -> DmdResult:
+    """Exact DMD of the snapshot matrix D (m x N, rows = points): Alg. 3 with
+    the TS-SVD of Alg. 1 and the amplitudes of Alg. 5."""
+    _rowmajor(D, "D")
+    if not D.is_cuda:
+        raise ValueError("D must be a GPU tensor")
+    ctx = ctx or context(D.device.index)
+    m, n = D.shape
+    kc = max(1, min(n - 1, DMD_MAX_MODES))
+    dev = D.device
+    phi = torch.empty((m, kc), dtype=torch.complex128, device=dev)
+    mu = torch.empty(kc, dtype=torch.complex128, device=dev)
+    b = torch.empty(kc, dtype=torch.complex128, device=dev)
+    freq = torch.empty(kc, dtype=torch.float64, device=dev)
+    growth = torch.empty(kc, dtype=torch.float64, device=dev)
+    nr = torch.zeros(1, dtype=torch.int64, device=dev)
+    ctx.bind_stream()
+    rc = ctx.lib.pylom_dmd(ctx.h, _dtype_code(D), m, n, _ptr(D), D.stride(0),
+                           int(bool(remove_mean)), float(r), float(dt), _ptr(phi), kc, _ptr(mu),
+                           _ptr(b), _ptr(freq), _ptr(growth), _ptr(nr))
+    ctx.check(rc)
+    k = int(nr.item())
+    return DmdResult(phi=phi[:, :k], mu=mu[:k], b=b[:k], freq=freq[:k], growth=growth[:k], nr=k)
+
+
 def tune_block_rows(m: int, n: int, ctx: Context | None = None) -> int:
     """The leaf height the library picks for an m x n problem (host-side model)."""
     ctx = ctx or Context(-1)

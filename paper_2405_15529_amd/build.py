@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpylom.so")
-SOURCES = ["abi.hip", "tsqr.hip", "svd.hip", "misc.hip", "refine.hip", "spod.hip", "blocked.hip"]
+SOURCES = ["abi.hip", "tsqr.hip", "svd.hip", "misc.hip", "refine.hip", "spod.hip", "blocked.hip", "dmd.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

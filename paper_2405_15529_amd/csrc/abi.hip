@@ -1351,6 +1351,168 @@ extern "C" int pylom_matmul(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int
 }
 
 // ---------------------------------------------------------------------------
+// exact DMD (Sec. 3.2, Alg. 3-5)
+// ---------------------------------------------------------------------------
+struct DmdLayout {
+  bool copy;  // Y = D - mean 1^T (or D promoted) in an FP64 working copy
+  size_t oY, oMean, oU, oS, oVT, oNr, oAux, oPart, oA, oH0, oQv, oQtau, oWr, oWi, oHn, oW, oUb,
+      oP, oQ, oB, oMu, oBo, oPerm, oBr, total;
+};
+
+// The TS-SVD plan of Y1 (m x (n - 1)) first, then the DMD buffers, sized for
+// the widest linear map the eigen-solver takes.
+static int make_dmd_layout(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, int remove_mean,
+                           Plan* p, DmdLayout* L) {
+  const int64_t n1 = n - 1;
+  int rc = make_plan(c, m, n1, true, p);
+  if (rc) return rc;
+  const int64_t kc = std::min<int64_t>(n1, kDmdMax);
+  size_t off = align_up(p->total);
+  auto take = [&off](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L->copy = remove_mean || dtype == PYLOM_R32;
+  L->oY = L->copy ? take(8 * (size_t)m * n) : 0;
+  L->oMean = take(8 * (size_t)m);
+  L->oU = take(8 * (size_t)m * n1);
+  L->oS = take(8 * (size_t)n1);
+  L->oVT = take(8 * (size_t)n1 * n1);
+  L->oNr = take(8);
+  size_t part = 0;
+  for (int64_t k = 1; k <= kc; ++k)
+    part = std::max(part, 8 * (size_t)matmul_tn_splits(m, k, n1) * k * n1);
+  L->oAux = take(8 * (size_t)kc * n1);
+  L->oPart = take(part);
+  L->oA = take(8 * (size_t)kc * kc);
+  L->oH0 = take(8 * (size_t)kc * kc);
+  L->oQv = take(8 * (size_t)kc * kc);
+  L->oQtau = take(8 * (size_t)kc);
+  L->oWr = take(8 * (size_t)kc);
+  L->oWi = take(8 * (size_t)kc);
+  L->oHn = take(8);
+  L->oW = take(16 * (size_t)kc * kc);
+  L->oUb = take(16 * (size_t)kc * kc * kc);
+  L->oP = take(16 * (size_t)kc * kc);
+  L->oQ = take(16 * (size_t)kc);
+  L->oB = take(16 * (size_t)kc);
+  L->oMu = take(16 * (size_t)kc);
+  L->oBo = take(16 * (size_t)kc);
+  L->oPerm = take(4 * (size_t)kc);
+  L->oBr = take(8 * (size_t)n1 * 2 * kc);
+  L->total = off;
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_dmd_workspace_query(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n,
+                                         int remove_mean, size_t* bytes) {
+  if (!c || !bytes) return PYLOM_EINVAL;
+  if (dtype != PYLOM_R64 && dtype != PYLOM_R32) return fail(c, PYLOM_EDTYPE, "dtype");
+  if (n < 2 || m < n - 1) return fail(c, PYLOM_ESHAPE, "need n >= 2 snapshots and m >= n - 1");
+  Plan p;
+  DmdLayout L;
+  const int rc = make_dmd_layout(c, dtype, m, n, remove_mean, &p, &L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_dmd(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, const void* D,
+                         int64_t ldd, int remove_mean, double residual, double dt, void* phi,
+                         int64_t ldphi, void* mu, void* b, double* freq, double* growth,
+                         int64_t* n_r) {
+  int rc = check_common(c, dtype, PYLOM_FP64);
+  if (rc) return rc;
+  if (!D || !phi || !mu || !b || !n_r) return fail(c, PYLOM_EINVAL, "null array argument");
+  if (!(residual >= 0.0 && residual < 1.0)) return fail(c, PYLOM_EINVAL, "residual must be in [0, 1)");
+  if (!(dt > 0.0)) return fail(c, PYLOM_EINVAL, "dt must be positive");
+  if (n < 2 || m < n - 1) return fail(c, PYLOM_ESHAPE, "need n >= 2 snapshots and m >= n - 1");
+  const int64_t n1 = n - 1, kc = std::min<int64_t>(n1, kDmdMax);
+  if (ldd < n || ldphi < kc) return fail(c, PYLOM_ESHAPE, "leading dimension");
+  Plan p;
+  DmdLayout L;
+  rc = make_dmd_layout(c, dtype, m, n, remove_mean, &p, &L);
+  if (rc) return rc;
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+  rc = ensure_ws(c, L.total);
+  if (rc) return rc;
+  Exec x = ctx_exec(c);
+  x.evs = nullptr;  // the phase ring times pod/tsvd calls only
+  char* ws = x.ws;
+  const hipStream_t st = x.st;
+  double* mean = (double*)(ws + L.oMean);
+  const double* Y = (const double*)D;
+  int64_t ldy = ldd;
+  if (L.copy) {
+    HIPCHK(c, launch_make_work(dtype == PYLOM_R64, 1, m, (int)n, D, ldd, remove_mean, mean,
+                               ws + L.oY, st), "working copy");
+    Y = (const double*)(ws + L.oY);
+    ldy = n;
+  }
+  double* U = (double*)(ws + L.oU);
+  double* S = (double*)(ws + L.oS);
+  double* VT = (double*)(ws + L.oVT);
+  int64_t* nr_dev = (int64_t*)(ws + L.oNr);
+  // TS-SVD of Y1 = Y[:, :n-1] (Alg. 1 + truncation), FP64
+  rc = enqueue_fp64(c, x, p, PYLOM_R64, Y, ldy, 0, residual, nullptr, U, n1, S, VT, n1, nr_dev);
+  if (rc) return rc;
+  c->status_valid = 1;
+  c->status_pairs = 1;
+  int64_t k = 0;
+  std::vector<double> Sh((size_t)n1);
+  HIPCHK(c, hipMemcpyAsync(&k, nr_dev, sizeof(int64_t), hipMemcpyDeviceToHost, st), "N_r read-back");
+  HIPCHK(c, hipMemcpyAsync(Sh.data(), S, sizeof(double) * (size_t)n1, hipMemcpyDeviceToHost, st),
+         "S read-back");
+  HIPCHK(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (k == 0) {
+    HIPCHK(c, launch_set_i64(n_r, 0, st), "N_r");
+    return PYLOM_OK;
+  }
+  if (k > kDmdMax) return fail(c, PYLOM_ENOTSUP, "DMD keeps at most 128 modes: raise the residual");
+  if (!(Sh[(size_t)k - 1] > 0.0))
+    return fail(c, PYLOM_ENOTSUP, "a retained singular value is zero: raise the residual");
+  // aux = U^T Y2 (Alg. 4)
+  HIPCHK(c, launch_matmul_tn(1, m, k, n1, U, n1, Y + 1, ldy, ws + L.oAux, n1,
+                             (double*)(ws + L.oPart), matmul_tn_splits(m, k, n1), st), "U^T Y2");
+  DmdSmallArgs a{};
+  a.k = (int)k;
+  a.n1 = (int)n1;
+  a.dt = dt;
+  a.aux = (const double*)(ws + L.oAux);
+  a.VT = VT;
+  a.ldvt = n1;
+  a.S = S;
+  a.A = (double*)(ws + L.oA);
+  a.H0 = (double*)(ws + L.oH0);
+  a.Qv = (double*)(ws + L.oQv);
+  a.Qtau = (double*)(ws + L.oQtau);
+  a.wr = (double*)(ws + L.oWr);
+  a.wi = (double*)(ws + L.oWi);
+  a.hnorm = (double*)(ws + L.oHn);
+  a.status = x.status + 2;
+  a.Ubuf = (double2*)(ws + L.oUb);
+  a.W = (double2*)(ws + L.oW);
+  a.P = (double2*)(ws + L.oP);
+  a.q = (double2*)(ws + L.oQ);
+  a.b = (double2*)(ws + L.oB);
+  a.mu_out = (double2*)mu;
+  a.b_out = (double2*)b;
+  a.freq = freq;
+  a.growth = growth;
+  a.perm = (int*)(ws + L.oPerm);
+  a.B = (double*)(ws + L.oBr);
+  HIPCHK(c, launch_dmd_small(a, st), "DMD eigen-solve and amplitudes");
+  c->status_pairs = 2;
+  // phi = Y2 B (Eq. dmdmodes), interleaved complex
+  HIPCHK(c, launch_tall_gemm_f64(m, (int)n1, (int)(2 * k), Y + 1, ldy, a.B, 2 * k, (double*)phi,
+                                 2 * ldphi, st), "modes");
+  HIPCHK(c, launch_set_i64(n_r, k, st), "N_r");
+  return PYLOM_OK;
+}
+
+// ---------------------------------------------------------------------------
 // SPOD: FFT front end + one batch of realified TSQR-SVD problems
 // ---------------------------------------------------------------------------
 struct SpodPlan {
@@ -1560,7 +1722,10 @@ extern "C" int pylom_check(pylom_ctx c, int64_t* sweeps) {
   if (sweeps) *sweeps = st[0];
   for (int k = 0; k < c->status_pairs; ++k) {
     if (st[2 * k + 1]) return fail(c, PYLOM_EHIP, "Jacobi grid barrier timed out");
-    if (st[2 * k] < 0) return fail(c, PYLOM_WNOCONV, "Jacobi SVD did not converge");
+    if (st[2 * k] < 0)
+      return fail(c, PYLOM_WNOCONV,
+                  k == 0 ? "Jacobi SVD did not converge"
+                         : "second solve did not converge (Gram eigenpairs or DMD eigen/Cholesky)");
   }
   return PYLOM_OK;
 }

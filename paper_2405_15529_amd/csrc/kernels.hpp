@@ -162,6 +162,34 @@ int64_t matmul_tn_splits(int64_t m, int64_t p, int64_t q);
 hipError_t launch_matmul_nn(int f64, int64_t m, int64_t p, int64_t q, const void* A, int64_t lda,
                             const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st);
 
+// ---- exact DMD (Sec. 3.2, Alg. 3-5) ----------------------------------------
+constexpr int kDmdMax = 128;  // widest linear map A (N_r) the eigen-solver takes
+struct DmdSmallArgs {
+  int k, n1;              // N_r, N - 1
+  double dt;
+  const double* aux;      // U^T Y2, k x n1 (ld n1)
+  const double* VT;       // right singular vectors as rows, ld ldvt
+  int64_t ldvt;
+  const double* S;        // singular values
+  double *A, *H0, *Qv, *Qtau, *wr, *wi, *hnorm;  // k x k, k x k, k x k, k, k, k, 1
+  int* status;            // (sweeps or -1, 0)
+  double2* Ubuf;          // k x k x k
+  double2* W;             // eigenvectors, k x k (column i = eigenvalue i)
+  double2 *P, *q, *b;     // k x k, k, k
+  double2 *mu_out, *b_out;  // k each, ordered
+  double *freq, *growth;  // k each (may be null)
+  int* perm;              // k
+  double* B;              // n1 x 2k, interleaved complex
+};
+size_t dmd_eig_lds_bytes(int k);
+// Linear map, eigendecomposition, amplitudes, ordering and the right factor
+// of the modes (every step after U^T Y2 and before phi = Y2 B).
+hipError_t launch_dmd_small(const DmdSmallArgs& a, hipStream_t st);
+// C (m x nc, ld ldc) = A (m x K, ld lda) B (K x nc, ld ldb), FP64.
+hipError_t launch_tall_gemm_f64(int64_t m, int K, int nc, const double* A, int64_t lda,
+                                const double* B, int64_t ldb, double* C, int64_t ldc,
+                                hipStream_t st);
+
 // ---- mixed precision: Rayleigh-Ritz refinement against the input ------------
 hipError_t launch_cast_f32_f64(const float* src, double* dst, int64_t count, hipStream_t st);
 // Z (m x k, ld k) = (A - mu 1^T) V_k with V_k[t][j] = VT0[j * n + t].

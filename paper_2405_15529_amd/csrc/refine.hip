@@ -254,4 +254,14 @@ hipError_t launch_rr_form_u(int out_f64, int64_t m, int k, const double* Z, cons
   return hipGetLastError();
 }
 
+hipError_t launch_tall_gemm_f64(int64_t m, int K, int nc, const double* A, int64_t lda,
+                                const double* B, int64_t ldb, double* C, int64_t ldc,
+                                hipStream_t st) {
+  if (m <= 0 || nc <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((m + GR - 1) / GR), (unsigned)((nc + GC - 1) / GC));
+  hipLaunchKernelGGL((k_tall_gemm<double, double, false>), grid, dim3(256), 0, st, m, K, nc,
+                     (const int64_t*)nullptr, A, lda, (const double*)nullptr, B, ldb, C, ldc);
+  return hipGetLastError();
+}
+
 }  // namespace pylom

@@ -1,0 +1,153 @@
+"""GPU parity of exact DMD (pylom_dmd) against the CPU oracle (oracle/dmd.py).
+
+The modal outputs are compared in forms that do not depend on conventions
+both sides share only up to rounding:
+
+* eigenvalues as sets (each GPU eigenvalue matched to the nearest oracle
+  eigenvalue, a bijection asserted), with the frequency and growth rate of
+  each matched pair;
+* |b| of matched modes, and the product phi_i b_i (independent of how an
+  eigenvector is scaled; the scaling convention itself is checked on the
+  GPU's own output: unit-norm eigenvectors enter phi through w / mu);
+* the order: |b| non-increasing along the output.
+
+Bars.  Exactly linear data: the eigenvalues are well conditioned and both
+sides reach them to ~1e-13; mu 1e-10, |b| and phi b 1e-8 relative.  Noisy
+data: both sides start from SVDs that agree to 1e-12 and the linear map's
+eigenvalues amplify that by their condition numbers (below 1e3 here):
+mu 1e-9, |b| and phi b 1e-7 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import dmd as odmd
+from paper_2405_15529_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(D, remove_mean, r, dt=1.0, dtype=np.float64):
+    import torch
+    from paper_2405_15529_amd import api
+    ctx = api.Context(0)
+    Dg = torch.from_numpy(np.ascontiguousarray(D.astype(dtype))).cuda()
+    out = api.dmd(Dg, remove_mean=remove_mean, r=r, dt=dt, ctx=ctx)
+    rc, sweeps = ctx.status()
+    res = dict(nr=out.nr, mu=out.mu.cpu().numpy(), b=out.b.cpu().numpy(),
+               phi=out.phi.cpu().numpy(), freq=out.freq.cpu().numpy(),
+               growth=out.growth.cpu().numpy(), rc=rc)
+    ctx.close()
+    return res
+
+
+def match(mu, ref):
+    idx = []
+    used = np.zeros(len(ref), bool)
+    for z in mu:
+        d = np.abs(ref - z)
+        d[used] = np.inf
+        j = int(np.argmin(d))
+        used[j] = True
+        idx.append(j)
+    return np.array(idx)
+
+
+def assert_parity(g, o, mu_tol, rel_tol, dt=1.0):
+    assert g["rc"] == 0
+    assert g["nr"] == o["nr"], (g["nr"], o["nr"])
+    k = g["nr"]
+    if k == 0:
+        return
+    idx = match(g["mu"], o["mu"])
+    emu = float(np.max(np.abs(g["mu"] - o["mu"][idx])))
+    ab, ao = np.abs(g["b"]), np.abs(o["b"][idx])
+    eb = float(np.max(np.abs(ab - ao)) / ao.max())
+    pg = g["phi"] * g["b"][None, :]
+    po = o["phi"][:, idx] * o["b"][idx][None, :]
+    ep = float(np.max(np.abs(pg - po)) / np.max(np.abs(po)))
+    ef = float(np.max(np.abs(g["freq"] - o["freq"][idx])))
+    eg = float(np.max(np.abs(g["growth"] - o["growth"][idx])))
+    say(f"    N_r {k}: |mu - mu_ref| {emu:.2e}, |b| {eb:.2e}, phi b {ep:.2e}, "
+        f"freq {ef:.2e}, growth {eg:.2e}")
+    assert emu <= mu_tol and eb <= rel_tol and ep <= rel_tol
+    assert ef <= mu_tol / dt and eg <= 10 * mu_tol / dt
+    # ordered by |b|
+    assert np.all(np.diff(ab) <= rel_tol * ab.max())
+
+
+@pytest.mark.parametrize("m,N,rm", [(5000, 60, False), (3000, 41, True)])
+def test_dmd_linear_dynamics(m, N, rm):
+    say(f"[gpu] dmd linear dynamics {m}x{N} remove_mean={rm}")
+    pairs = [(0.999, 0.11), (0.99, 0.35), (0.97, 0.8), (0.95, 1.3), (0.9, 2.2)]
+    D, lam, phi, amp = synth.linear_dynamics(m, N, seed=m + N, pairs=pairs, real_eigs=(0.85, -0.6))
+    if rm:
+        # a constant field on top: whole periods make the snapshot mean exact
+        # only approximately, so the parity is with the oracle, not with lam
+        D = D + np.linspace(-1.0, 1.0, m)[:, None]
+    o = odmd.dmd(D, remove_mean=rm, r=1e-10, dt=0.5)
+    g = run_gpu(D, rm, 1e-10, dt=0.5)
+    assert_parity(g, o, 1e-10, 1e-8, dt=0.5)
+    if not rm:
+        idx = match(g["mu"], lam)
+        assert np.max(np.abs(g["mu"] - lam[idx])) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_dmd_travelling_waves(dtype):
+    m, N = 20000, 100
+    say(f"[gpu] dmd travelling waves {m}x{N} {np.dtype(dtype).name}")
+    D = synth.travelling_waves(m, N, seed=12, nwaves=12, noise=1e-3)
+    D = D.astype(dtype).astype(np.float64)  # the oracle sees the same values
+    o = odmd.dmd(D, remove_mean=True, r=1e-4, dt=0.1)
+    g = run_gpu(D, True, 1e-4, dt=0.1, dtype=dtype)
+    assert_parity(g, o, 1e-9, 1e-7, dt=0.1)
+
+
+def test_dmd_two_and_three_snapshots():
+    rng = np.random.default_rng(21)
+    for N in (2, 3):
+        say(f"[gpu] dmd {N} snapshots")
+        D = rng.standard_normal((500, N))
+        o = odmd.dmd(D, r=0.0)
+        g = run_gpu(D, False, 0.0)
+        assert_parity(g, o, 1e-10, 1e-8)
+
+
+def test_dmd_empty_basis():
+    say("[gpu] dmd constant field, mean removed")
+    # integers: the mean of 12 equal values is exact, so Y1 = 0 exactly
+    D = np.repeat(np.arange(1.0, 401.0)[:, None], 12, axis=1)
+    g = run_gpu(D, True, 0.01)
+    assert g["rc"] == 0 and g["nr"] == 0
+
+
+def test_dmd_too_many_modes_is_an_error():
+    import torch
+    from paper_2405_15529_amd import api
+    say("[gpu] dmd with more than 128 retained modes")
+    D = np.random.default_rng(22).standard_normal((2000, 200))
+    ctx = api.Context(0)
+    with pytest.raises(api.PylomError) as e:
+        api.dmd(torch.from_numpy(D).cuda(), r=1e-12, ctx=ctx)
+    assert e.value.status == -6  # PYLOM_ENOTSUP
+    ctx.close()
+
+
+def test_dmd_eigvec_convention_and_amplitude_fit():
+    # the GPU's own outputs satisfy the amplitude fit: Y1 ~ phi diag(b) V_and
+    # reproduces exactly linear data
+    say("[gpu] dmd reconstruction of linear data")
+    D, lam, phi, amp = synth.linear_dynamics(4000, 50, seed=23)
+    g = run_gpu(D, False, 1e-10)
+    Vand = g["mu"][:, None] ** np.arange(49)[None, :]
+    rec = (g["phi"] * g["b"][None, :]) @ Vand
+    err = np.max(np.abs(rec - D[:, :-1])) / np.max(np.abs(D))
+    say(f"    reconstruction error {err:.2e}")
+    assert err <= 1e-9
