@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--spod-nt", type=int, default=2048)
     ap.add_argument("--spod-steps", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-dmd", action="store_true")
+    ap.add_argument("--dmd-m", type=int, default=58_300_000)
+    ap.add_argument("--dmd-n", type=int, default=56)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--wide-m", type=int, default=4_194_304)
@@ -432,6 +435,94 @@ def timed_paper_shapes(api, steps, warmup, jsm_m=58_300_000, jsm_n=56, weak_m=36
     return out
 
 
+def timed_dmd(api, m, n, steps, warmup):
+    """Exact DMD (Alg. 3-5) of exactly linear FP64 snapshots, m x n with 50
+    modes (24 conjugate pairs and two real eigenvalues), residual 1e-10: one
+    pylom_dmd call per step, and the TS-SVD of Y1 alone (pylom_tsvd on the
+    first n - 1 columns) to split the time."""
+    import ctypes
+    import numpy as np
+    import torch
+    from paper_2405_15529_amd import synth
+
+    D, lam, phi, amp = synth.linear_dynamics_device(m, n, seed=24)
+    del phi
+    torch.cuda.empty_cache()
+    ctx = api.Context(0)
+    ctx.bind_stream()
+    kc = min(n - 1, api.DMD_MAX_MODES)
+    dev = D.device
+    phi = torch.empty((m, kc), dtype=torch.complex128, device=dev)
+    mu_d = torch.empty(kc, dtype=torch.complex128, device=dev)
+    b_d = torch.empty(kc, dtype=torch.complex128, device=dev)
+    fr = torch.empty(kc, dtype=torch.float64, device=dev)
+    gr = torch.empty(kc, dtype=torch.float64, device=dev)
+    nr_d = torch.empty(1, dtype=torch.int64, device=dev)
+    vp = ctypes.c_void_p
+    ctx.check(ctx.lib.pylom_reserve(ctx.h, api.dmd_workspace_bytes(m, n, api.R64, False, ctx)))
+
+    def step():
+        ctx.check(ctx.lib.pylom_dmd(ctx.h, api.R64, m, n, vp(D.data_ptr()), n, 0, 1e-10, 1.0,
+                                    vp(phi.data_ptr()), kc, vp(mu_d.data_ptr()),
+                                    vp(b_d.data_ptr()), vp(fr.data_ptr()), vp(gr.data_ptr()),
+                                    vp(nr_d.data_ptr())))
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record()
+    for _ in range(steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - wall0) / steps
+    ms = t0.elapsed_time(t1) / steps
+    rc, _ = ctx.status()
+    k = int(nr_d.item())
+    mu = mu_d[:k].cpu().numpy()
+    emu = float(max(np.min(np.abs(lam - z)) for z in mu)) if k else 0.0
+    del phi
+    torch.cuda.empty_cache()
+    # the TS-SVD of Y1 alone, same context and leaf heights
+    n1 = n - 1
+    U = torch.empty((m, n1), dtype=torch.float64, device=D.device)
+    S = torch.empty(n1, dtype=torch.float64, device=D.device)
+    VT = torch.empty((n1, n1), dtype=torch.float64, device=D.device)
+    nr = torch.empty(1, dtype=torch.int64, device=D.device)
+    vp = ctypes.c_void_p
+
+    def tsvd():
+        ctx.check(ctx.lib.pylom_tsvd(ctx.h, api.R64, api.FP64, m, n1, vp(D.data_ptr()), n, 1e-10,
+                                     vp(U.data_ptr()), n1, vp(S.data_ptr()), vp(VT.data_ptr()),
+                                     n1, vp(nr.data_ptr())))
+    tsvd()
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        tsvd()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_svd = t0.elapsed_time(t1) / steps
+    ctx.close()
+    del D, U, VT
+    torch.cuda.empty_cache()
+    flops = (2.0 * m * n1 * n1 + 2.0 * m * n1 * k   # TS-SVD: leaf QR + U
+             + 2.0 * m * k * n1                     # U^T Y2 (Alg. 4)
+             + 2.0 * m * n1 * 2 * k)                # phi = Y2 B, complex B
+    return {
+        "workload": f"exact DMD of the JSM shape {m}x{n} FP64, exactly linear dynamics with "
+                    f"{len(lam)} modes, residual 1e-10",
+        "ms_per_step": round(ms, 3), "wall_ms_per_step": round(wall * 1e3, 3),
+        "tflops": round(flops / (ms * 1e-3) / 1e12, 4),
+        "tsvd_of_y1_ms": round(ms_svd, 3),
+        "linear_map_eig_amplitudes_modes_ms": round(ms - ms_svd, 3),
+        "n_r": k, "status": rc, "max_abs_mu_minus_lambda": emu,
+        "steps": steps, "warmup": warmup,
+    }
+
+
 def timed_batch(api, count, seed, steps, warmup):
     """Uneven POD batch: `count` instances, m log-uniform in [5e4, 2e6], n
     uniform in [32, 512], FP32 known spectra s_i = 10^(-6i/n), 99 % energy.
@@ -635,6 +726,8 @@ def main():
     if not args.no_wide:
         out["wide"] = timed_wide(api, args.wide_m, args.wide_n, args.wide_steps,
                                  1 if args.warmup else 0, args.wide_block_rows)
+    if not args.no_dmd:
+        out["dmd"] = timed_dmd(api, args.dmd_m, args.dmd_n, 2, 1 if args.warmup else 0)
     if not args.no_batch:
         out["uneven_batch"] = timed_batch(api, args.batch_count, 4, args.batch_steps,
                                           1 if args.warmup else 0)

@@ -31,6 +31,7 @@ struct pylom_ctx_s {
   int64_t max_sweeps = 60;
   int64_t ws_cap_mb = 0;
   int64_t blocked_from = 0;  // n at which the column-blocked TSQR takes over (0: automatic)
+  int64_t narrow_leaves = 1;  // single-wave 32-row leaves for 33 <= n <= 64 with many leaves
   int* status_dev = nullptr;  // Jacobi status pairs (sweeps, barrier timeout) of the last call
   int status_valid = 0;
   int status_pairs = 1;        // 2 after a mixed-precision call (SVD of R + Gram eigen)
@@ -154,6 +155,9 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
   } else if (!std::strcmp(key, "ws_cap_mb")) {
     if (v < 0) return fail(c, PYLOM_EINVAL, "ws_cap_mb must be >= 0");
     c->ws_cap_mb = v;
+  } else if (!std::strcmp(key, "narrow_leaves")) {
+    if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "narrow_leaves must be 0 or 1");
+    c->narrow_leaves = v;
   } else if (!std::strcmp(key, "blocked_from")) {
     if (v != 0 && (v < 2 || v > kMaxN + 1))
       return fail(c, PYLOM_EINVAL, "blocked_from must be 0 or in [2, 2049]");
@@ -191,6 +195,8 @@ extern "C" int pylom_get_option(pylom_ctx c, const char* key, int64_t* v) {
     *v = c->ws_cap_mb;
   else if (!std::strcmp(key, "blocked_from"))
     *v = c->blocked_from;
+  else if (!std::strcmp(key, "narrow_leaves"))
+    *v = c->narrow_leaves;
   else if (!std::strcmp(key, "timing"))
     *v = c->timing;
   else if (!std::strcmp(key, "streams"))
@@ -363,6 +369,14 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
   p->last_rows = m - (P - 1) * b;
   if (!qr_geom((int)n, 8, &p->g)) return fail(c, PYLOM_ENOTSUP, "no chunk geometry");
   if (!jacobi_plan((int)n, &p->jp)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
+  // Narrow problems (3 or 4 panels) with at least two leaves per CU: 32-row
+  // chunks and single-wave workgroups, so that four leaves share a CU (38 KB
+  // of LDS each at n = 64), instead of one four-wave workgroup whose three
+  // trailing-tile waves mostly wait on the panel wave.
+  if (c->narrow_leaves && p->g.npanels >= 3 && p->g.npanels <= 4 && P >= 2 * (int64_t)c->ncu) {
+    p->g.s = 32;
+    p->g.nthr = 64;
+  }
   const int64_t s = p->g.s, np = p->g.npanels;
   p->nch_leaf = (p->last_rows + s - 1) / s;
   p->nch_tree = (n + s - 1) / s;

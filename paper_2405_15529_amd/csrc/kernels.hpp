@@ -12,6 +12,7 @@ struct QrGeom {
   int s;        // chunk rows staged in LDS (multiple of 16)
   int ldc;      // LDS row stride of the chunk (odd)
   int npanels;  // ceil(n / 16)
+  int nthr;     // threads of a QR workgroup (0: 64 for at most two panels, else 256)
 };
 
 // A batch of same-shape problems (blockIdx.y = problem): element strides

@@ -90,39 +90,70 @@ hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Alg. 4: C = sum over row blocks of A_i^T B_i.  Each wave owns one 16x16 tile
-// of C and one slice of rows (split-K); its MFMA partial goes to an FP64
-// buffer, and a second kernel sums the slices in a fixed order (the device
-// stand-in for the all_reduce, deterministic).
+// Alg. 4: C = sum over row blocks of A_i^T B_i.  Each workgroup owns one
+// 64x64 tile of C and one slice of rows (split-K): it stages 32-row slabs of
+// A (transposed) and B in LDS, promotes them to FP64 and accumulates with the
+// FP64 MFMA (wave w owns rows 16w..16w+15 of the tile); its partial goes to
+// an FP64 buffer, and a second kernel sums the slices in a fixed order (the
+// device stand-in for the all_reduce, deterministic).
 // ---------------------------------------------------------------------------
+namespace {
+constexpr int MT = 64;       // tile edge
+constexpr int MK = 32;       // rows per slab
+constexpr int MALD = MK + 1;
+constexpr int MBLD = MT + 1;
+}  // namespace
+
 template <typename T>
-__global__ __launch_bounds__(64) void k_matmul_tn_partial(int64_t m, int64_t p, int64_t q,
-                                                          const T* __restrict__ A, int64_t lda,
-                                                          const T* __restrict__ B, int64_t ldb,
-                                                          double* __restrict__ part,
-                                                          int64_t nsplit) {
-  typedef typename Mfma<T>::v4 v4;
-  const int64_t tp = (p + 15) / 16, tq = (q + 15) / 16;
+__global__ __launch_bounds__(256) void k_matmul_tn_partial(int64_t m, int64_t p, int64_t q,
+                                                           const T* __restrict__ A, int64_t lda,
+                                                           const T* __restrict__ B, int64_t ldb,
+                                                           double* __restrict__ part,
+                                                           int64_t nsplit) {
+  __shared__ double As[MT * MALD];  // As[i * MALD + r] = A[r][i0 + i]
+  __shared__ double Bs[MK * MBLD];  // Bs[r * MBLD + j] = B[r][j0 + j]
+  typedef Mfma<double>::v4 v4;
+  const int64_t tp = (p + MT - 1) / MT, tq = (q + MT - 1) / MT;
   const int64_t tile = blockIdx.x % (tp * tq);
   const int64_t split = blockIdx.x / (tp * tq);
-  const int64_t i0 = (tile / tq) * 16, j0 = (tile % tq) * 16;
+  const int64_t i0 = (tile / tq) * MT, j0 = (tile % tq) * MT;
   const int64_t rows_per = (m + nsplit - 1) / nsplit;
   const int64_t k0 = split * rows_per;
   const int64_t k1 = (k0 + rows_per < m) ? k0 + rows_per : m;
-  const int lane = threadIdx.x, i16 = lane & 15, g4 = lane >> 4;
-  const bool iok = i0 + i16 < p, jok = j0 + i16 < q;
-  v4 acc = vzero4<T>();
-  for (int64_t k = k0; k < k1; k += 4) {
-    const int64_t r = k + g4;
-    const T av = (r < k1 && iok) ? A[r * lda + i0 + i16] : T(0);
-    const T bv = (r < k1 && jok) ? B[r * ldb + j0 + i16] : T(0);
-    acc = Mfma<T>::op(av, bv, acc);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  v4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = vzero4<double>();
+  for (int64_t kk = k0; kk < k1; kk += MK) {
+#pragma unroll
+    for (int e = 0; e < (MK * MT) / 256; ++e) {
+      const int idx = tid + 256 * e;
+      const int r = idx / MT, c = idx % MT;
+      const int64_t gr = kk + r;
+      const bool rok = gr < k1;
+      As[c * MALD + r] = (rok && i0 + c < p) ? (double)A[gr * lda + i0 + c] : 0.0;
+      Bs[r * MBLD + c] = (rok && j0 + c < q) ? (double)B[gr * ldb + j0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kb = 0; kb < MK; kb += 4) {
+      const double av = As[(wave * 16 + i16) * MALD + kb + g4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        acc[c] = Mfma<double>::op(av, Bs[(kb + g4) * MBLD + c * 16 + i16], acc[c]);
+    }
+    __syncthreads();
   }
   double* out = part + split * p * q;
 #pragma unroll
-  for (int qq = 0; qq < 4; ++qq) {
-    const int64_t i = i0 + Mfma<T>::drow(g4, qq), j = j0 + i16;
-    if (i < p && j < q) out[i * q + j] = (double)acc[qq];
+  for (int c = 0; c < 4; ++c) {
+    const int64_t j = j0 + c * 16 + i16;
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int64_t i = i0 + wave * 16 + Mfma<double>::drow(g4, qq);
+      if (i < p && j < q) out[i * q + j] = acc[c][qq];
+    }
   }
 }
 
@@ -138,9 +169,9 @@ __global__ void k_matmul_reduce(int64_t p, int64_t q, const double* __restrict__
 }
 
 int64_t matmul_tn_splits(int64_t m, int64_t p, int64_t q) {
-  const int64_t tiles = ((p + 15) / 16) * ((q + 15) / 16);
-  // aim for ~4096 waves, each slice at least 256 rows
-  int64_t s = (4096 + tiles - 1) / tiles;
+  const int64_t tiles = ((p + 63) / 64) * ((q + 63) / 64);
+  // aim for ~1024 workgroups (four per CU), each slice at least 256 rows
+  int64_t s = (1024 + tiles - 1) / tiles;
   const int64_t maxs = (m + 255) / 256;
   if (s > maxs) s = maxs;
   if (s < 1) s = 1;
@@ -150,13 +181,13 @@ int64_t matmul_tn_splits(int64_t m, int64_t p, int64_t q) {
 hipError_t launch_matmul_tn(int f64, int64_t m, int64_t p, int64_t q, const void* A, int64_t lda,
                             const void* B, int64_t ldb, void* C, int64_t ldc, double* partial,
                             int64_t nsplit, hipStream_t st) {
-  const int64_t tiles = ((p + 15) / 16) * ((q + 15) / 16);
+  const int64_t tiles = ((p + 63) / 64) * ((q + 63) / 64);
   const dim3 grid((unsigned)(tiles * nsplit));
   if (f64)
-    hipLaunchKernelGGL(k_matmul_tn_partial<double>, grid, dim3(64), 0, st, m, p, q,
+    hipLaunchKernelGGL(k_matmul_tn_partial<double>, grid, dim3(256), 0, st, m, p, q,
                        (const double*)A, lda, (const double*)B, ldb, partial, nsplit);
   else
-    hipLaunchKernelGGL(k_matmul_tn_partial<float>, grid, dim3(64), 0, st, m, p, q,
+    hipLaunchKernelGGL(k_matmul_tn_partial<float>, grid, dim3(256), 0, st, m, p, q,
                        (const float*)A, lda, (const float*)B, ldb, partial, nsplit);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

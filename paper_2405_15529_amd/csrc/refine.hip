@@ -23,10 +23,8 @@ namespace pylom {
 
 namespace {
 constexpr int GR = 64;   // rows per workgroup
-constexpr int GC = 64;   // columns per workgroup
 constexpr int GK = 32;   // K slab staged in LDS
 constexpr int ALD = GK + 1;
-constexpr int BLD = GC + 1;
 }  // namespace
 
 __global__ void k_cast_f32_f64(const float* __restrict__ src, double* __restrict__ dst,
@@ -39,15 +37,18 @@ __global__ void k_cast_f32_f64(const float* __restrict__ src, double* __restrict
 // C (m x nc) = (A - mu 1^T) (m x K) * B (K x nc), FP64 MFMA on promoted tiles.
 // B(t, j) = Bs[j * ldb + t] when BT (B given by rows of its transpose), else
 // Bs[t * ldb + j].  nc = min(nc_host, *nc_dev) when nc_dev is given.
-// Grid: (ceil(m / 64), ceil(nc_host / 64)); 256 threads, wave w owns rows
-// 16w..16w+15 of the tile and all four 16-column MFMA tiles.
-template <typename TI, typename TO, bool BT>
+// Grid: (ceil(m / 64), ceil(nc_host / GC)); 256 threads, wave w owns rows
+// 16w..16w+15 of the tile and all GC / 16 column tiles.  GC = 128 lets up to
+// 128 output columns read A once.
+template <typename TI, typename TO, bool BT, int GC = 64>
 __global__ __launch_bounds__(256) void k_tall_gemm(int64_t m, int K, int nc_host,
                                                    const int64_t* __restrict__ nc_dev,
                                                    const TI* __restrict__ A, int64_t lda,
                                                    const double* __restrict__ mu,
                                                    const double* __restrict__ Bs, int64_t ldb,
                                                    TO* __restrict__ C, int64_t ldc) {
+  constexpr int BLD = GC + 1;
+  constexpr int NT = GC / 16;
   __shared__ double As[GR * ALD];
   __shared__ double Bsh[GK * BLD];
   int nc = nc_host;
@@ -61,9 +62,9 @@ __global__ __launch_bounds__(256) void k_tall_gemm(int64_t m, int K, int nc_host
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i16 = lane & 15, g4 = lane >> 4;
   typedef Mfma<double>::v4 v4;
-  v4 acc[4];
+  v4 acc[NT];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) acc[c] = vzero4<double>();
+  for (int c = 0; c < NT; ++c) acc[c] = vzero4<double>();
   for (int k0 = 0; k0 < K; k0 += GK) {
     // stage A slab (64 x 32): consecutive threads walk a row
 #pragma unroll
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(256) void k_tall_gemm(int64_t m, int K, int nc_host
     for (int kb = 0; kb < GK; kb += 4) {
       const double av = As[(wave * 16 + i16) * ALD + kb + g4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < NT; ++c) {
         const double bv = Bsh[(kb + g4) * BLD + c * 16 + i16];
         acc[c] = Mfma<double>::op(av, bv, acc[c]);
       }
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(256) void k_tall_gemm(int64_t m, int K, int nc_host
     __syncthreads();
   }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < NT; ++c) {
     const int col = j0 + c * 16 + i16;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -215,19 +216,32 @@ hipError_t launch_cast_f32_f64(const float* src, double* dst, int64_t count, hip
   return hipGetLastError();
 }
 
+// One launch of the tall GEMM: 128-column workgroups when more than 64
+// output columns are asked for (A is then read once per 128 columns).
+template <typename TI, typename TO, bool BT>
+static hipError_t launch_tg(int64_t m, int K, int nc, const int64_t* nc_dev, const TI* A,
+                            int64_t lda, const double* mu, const double* B, int64_t ldb, TO* C,
+                            int64_t ldc, hipStream_t st) {
+  if (m <= 0 || nc <= 0) return hipSuccess;
+  if (nc > 64) {
+    const dim3 grid((unsigned)((m + GR - 1) / GR), (unsigned)((nc + 127) / 128));
+    hipLaunchKernelGGL((k_tall_gemm<TI, TO, BT, 128>), grid, dim3(256), 0, st, m, K, nc, nc_dev,
+                       A, lda, mu, B, ldb, C, ldc);
+  } else {
+    const dim3 grid((unsigned)((m + GR - 1) / GR), 1u);
+    hipLaunchKernelGGL((k_tall_gemm<TI, TO, BT, 64>), grid, dim3(256), 0, st, m, K, nc, nc_dev,
+                       A, lda, mu, B, ldb, C, ldc);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_rr_project(int in_f64, int64_t m, int n, int k, const void* A, int64_t lda,
                              const double* mu, const double* VT0, double* Z, hipStream_t st) {
-  if (m <= 0 || k <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((m + GR - 1) / GR), (unsigned)((k + GC - 1) / GC));
   if (in_f64)
-    hipLaunchKernelGGL((k_tall_gemm<double, double, true>), grid, dim3(256), 0, st, m, n, k,
-                       (const int64_t*)nullptr, (const double*)A, lda, mu, VT0, (int64_t)n, Z,
-                       (int64_t)k);
-  else
-    hipLaunchKernelGGL((k_tall_gemm<float, double, true>), grid, dim3(256), 0, st, m, n, k,
-                       (const int64_t*)nullptr, (const float*)A, lda, mu, VT0, (int64_t)n, Z,
-                       (int64_t)k);
-  return hipGetLastError();
+    return launch_tg<double, double, true>(m, n, k, nullptr, (const double*)A, lda, mu, VT0,
+                                           (int64_t)n, Z, (int64_t)k, st);
+  return launch_tg<float, double, true>(m, n, k, nullptr, (const float*)A, lda, mu, VT0,
+                                        (int64_t)n, Z, (int64_t)k, st);
 }
 
 hipError_t launch_rr_finish(int n, int k, const double* S0, const double* lam, double residual,
@@ -243,25 +257,17 @@ hipError_t launch_rr_finish(int n, int k, const double* S0, const double* lam, d
 
 hipError_t launch_rr_form_u(int out_f64, int64_t m, int k, const double* Z, const double* M,
                             const int64_t* nr, void* U, int64_t ldu, hipStream_t st) {
-  if (m <= 0 || k <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((m + GR - 1) / GR), (unsigned)((k + GC - 1) / GC));
   if (out_f64)
-    hipLaunchKernelGGL((k_tall_gemm<double, double, false>), grid, dim3(256), 0, st, m, k, k, nr,
-                       Z, (int64_t)k, (const double*)nullptr, M, (int64_t)k, (double*)U, ldu);
-  else
-    hipLaunchKernelGGL((k_tall_gemm<double, float, false>), grid, dim3(256), 0, st, m, k, k, nr, Z,
-                       (int64_t)k, (const double*)nullptr, M, (int64_t)k, (float*)U, ldu);
-  return hipGetLastError();
+    return launch_tg<double, double, false>(m, k, k, nr, Z, (int64_t)k, nullptr, M, (int64_t)k,
+                                            (double*)U, ldu, st);
+  return launch_tg<double, float, false>(m, k, k, nr, Z, (int64_t)k, nullptr, M, (int64_t)k,
+                                         (float*)U, ldu, st);
 }
 
 hipError_t launch_tall_gemm_f64(int64_t m, int K, int nc, const double* A, int64_t lda,
                                 const double* B, int64_t ldb, double* C, int64_t ldc,
                                 hipStream_t st) {
-  if (m <= 0 || nc <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((m + GR - 1) / GR), (unsigned)((nc + GC - 1) / GC));
-  hipLaunchKernelGGL((k_tall_gemm<double, double, false>), grid, dim3(256), 0, st, m, K, nc,
-                     (const int64_t*)nullptr, A, lda, (const double*)nullptr, B, ldb, C, ldc);
-  return hipGetLastError();
+  return launch_tg<double, double, false>(m, K, nc, nullptr, A, lda, nullptr, B, ldb, C, ldc, st);
 }
 
 }  // namespace pylom

@@ -53,6 +53,7 @@ bool qr_geom(int n, int esize, QrGeom* g) {
   g->n = n;
   g->ldc = n;  // column-per-lane panel access and MFMA operand walks are row-contiguous
   g->npanels = (n + NB - 1) / NB;
+  g->nthr = 0;
   int best = 0;
   for (int s = 16; s <= 64; s += 16) {
     QrGeom t = *g;
@@ -92,6 +93,7 @@ struct Tiny<float> {
 template <typename T, typename TI>
 struct QrArgs {
   int n, s, ldc, npanels;
+  int nthr;     // workgroup threads (0: 64 for at most two panels, else 256)
   int mode;     // 0 = leaf, 1 = combine
   int store_q;  // write reflectors and T factors
   // leaf
@@ -1164,14 +1166,15 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
 // ---------------------------------------------------------------------------
 // Problems of at most two panels use single-wave workgroups: their trailing
 // work per step is one tile, so three of four waves would idle, while several
-// single-wave leaves share a CU and overlap their panel latencies.
+// single-wave leaves share a CU and overlap their panel latencies.  A plan
+// may ask for single-wave workgroups on wider problems too (QrGeom::nthr).
 template <typename T, typename TI, int RT, int VAR>
 static hipError_t launch_qr_t(const QrArgs<T, TI>& a, int grid, int gy, size_t lds,
                               hipStream_t st) {
   hipError_t e = hipFuncSetAttribute((const void*)k_stacked_qr<T, TI, RT, VAR>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int threads = (a.npanels <= 2) ? 64 : 256;
+  const int threads = a.nthr ? a.nthr : ((a.npanels <= 2) ? 64 : 256);
   hipLaunchKernelGGL((k_stacked_qr<T, TI, RT, VAR>), dim3(grid, gy), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
@@ -1197,7 +1200,7 @@ static hipError_t launch_qr_any(const QrArgs<T, TI>& a, int grid, size_t lds, hi
   if (grid <= 0 || gy <= 0) return hipSuccess;
   if (gy > 65535) return hipErrorInvalidValue;
   if (a.mode == 0 && a.state_mode == 0) {
-    const int nthr = (a.npanels <= 2) ? 64 : 256;
+    const int nthr = a.nthr ? a.nthr : ((a.npanels <= 2) ? 64 : 256);
     if (!a.remove_mean && a.s * a.n <= kPfn * nthr)
       return launch_qr_var<T, TI, 3>(a, grid, lds, st, gy);
     return launch_qr_var<T, TI, 0>(a, grid, lds, st, gy);
@@ -1225,7 +1228,7 @@ hipError_t launch_leaf_qr_f64(const QrGeom& g, const void* D, int in_f64, int64_
   const size_t lds = qr_lds_bytes(g, 8);
   if (in_f64) {
     QrArgs<double, double> a{};
-    a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.mode = 0;
+    a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.nthr = g.nthr; a.mode = 0;
     a.store_q = V != nullptr;
     a.D = (const double*)D; a.ldd = ldd; a.m = m; a.b = b; a.P = P;
     a.remove_mean = remove_mean; a.mean_ws = mean_ws; a.V = V; a.Tleaf = Tleaf;
@@ -1234,7 +1237,7 @@ hipError_t launch_leaf_qr_f64(const QrGeom& g, const void* D, int in_f64, int64_
     return launch_qr_any(a, (int)P, lds, st, bt.count);
   }
   QrArgs<double, float> a{};
-  a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.mode = 0;
+  a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.nthr = g.nthr; a.mode = 0;
   a.store_q = V != nullptr;
   a.D = (const float*)D; a.ldd = ldd; a.m = m; a.b = b; a.P = P;
   a.remove_mean = remove_mean; a.mean_ws = mean_ws; a.V = V; a.Tleaf = Tleaf;
@@ -1247,7 +1250,7 @@ hipError_t launch_leaf_qr_f32(const QrGeom& g, const float* D, int64_t ldd, int6
                               int64_t P, int remove_mean, double* mean_ws, float* Rbuf32,
                               hipStream_t st, const Batch& bt) {
   QrArgs<float, float> a{};
-  a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.mode = 0; a.store_q = 0;
+  a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.nthr = g.nthr; a.mode = 0; a.store_q = 0;
   a.D = D; a.ldd = ldd; a.m = m; a.b = b; a.P = P;
   a.remove_mean = remove_mean; a.mean_ws = mean_ws; a.Rbuf = Rbuf32;
   set_qr_batch(a, bt);
@@ -1258,7 +1261,7 @@ hipError_t launch_tree_combine_f64(const QrGeom& g, int64_t h, int64_t P, double
                                    double* Ttree, int64_t nch_tree, int store_q, hipStream_t st,
                                    const Batch& bt) {
   QrArgs<double, double> a{};
-  a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.mode = 1;
+  a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.nthr = g.nthr; a.mode = 1;
   a.store_q = store_q; a.h = h; a.Ttree = Ttree; a.nch_tree = nch_tree; a.Rbuf = Rbuf;
   // combines at this level: j = 0, 2h, 4h, ... with j + h < P
   const int64_t ncomb = (P - h + 2 * h - 1) / (2 * h);
@@ -1271,7 +1274,7 @@ hipError_t launch_panel_qr(const QrGeom& g, T* Wk, int64_t ldw, int64_t m, int64
                            int64_t rows_lim, T* Tf, int64_t nch, T* Rstate, int state_mode,
                            hipStream_t st) {
   QrArgs<T, T> a{};
-  a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.mode = 0; a.store_q = 1;
+  a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.nthr = g.nthr; a.mode = 0; a.store_q = 1;
   a.D = Wk; a.ldd = ldw; a.m = m; a.b = b; a.P = P; a.remove_mean = 0; a.mean_ws = nullptr;
   a.V = Wk; a.Tleaf = Tf; a.nch_leaf = nch; a.Rbuf = Rstate;
   a.state_mode = state_mode; a.ldv = ldw; a.rows_lim = rows_lim;

@@ -259,3 +259,47 @@ def linear_dynamics(m: int, nt: int, seed: int = 6, pairs=None, real_eigs=(), no
     if noise:
         D = D + noise * rng.standard_normal(D.shape)
     return np.ascontiguousarray(D), lam, phi, amp
+
+
+def linear_dynamics_device(m: int, nt: int, seed: int = 6, npairs: int = 24,
+                           real_eigs=(0.95, -0.9), device: str = "cuda",
+                           rows_per_pass: int = 1 << 20):
+    """Device-side exactly linear snapshots for large m (FP64, m x nt):
+    d_t = sum_i phi_i b_i lambda_i^t with npairs conjugate pairs
+    lambda = r e^{+-i theta} (r drawn in [0.97, 1], theta evenly spaced over
+    [0.1, 3.0], so that the snapshot matrix is well conditioned) and the
+    given real eigenvalues; the radii and amplitudes are numpy draws, the
+    complex unit-norm modes come from torch's seeded device generator.
+    Returns (D, lam, phi m x k complex128 on the device, amp)."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    rad = rng.uniform(0.97, 1.0, npairs)
+    ang = np.linspace(0.1, 3.0, npairs)
+    a = rng.uniform(0.5, 2.0, npairs) * np.exp(1j * rng.uniform(0.0, 2.0 * np.pi, npairs))
+    z = rad * np.exp(1j * ang)
+    lam = np.concatenate([np.ravel(np.column_stack([z, np.conj(z)])),
+                          np.asarray(real_eigs, dtype=np.complex128)])
+    amp = np.concatenate([np.ravel(np.column_stack([a, np.conj(a)])),
+                          rng.uniform(0.5, 2.0, len(real_eigs)).astype(np.complex128)])
+    k = len(lam)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    re = torch.randn((m, npairs), generator=gen, dtype=torch.float64, device=device)
+    im = torch.randn((m, npairs), generator=gen, dtype=torch.float64, device=device)
+    rl = torch.randn((m, len(real_eigs)), generator=gen, dtype=torch.float64, device=device)
+    phi = torch.empty((m, k), dtype=torch.complex128, device=device)
+    pc = torch.complex(re, im)
+    pc /= torch.linalg.norm(pc, dim=0, keepdim=True)
+    rl /= torch.linalg.norm(rl, dim=0, keepdim=True)
+    phi[:, 0:2 * npairs:2] = pc
+    phi[:, 1:2 * npairs:2] = pc.conj()
+    phi[:, 2 * npairs:] = rl.to(torch.complex128)
+    del re, im, rl, pc
+    t = np.arange(nt)
+    Vt = torch.from_numpy((amp[:, None] * lam[:, None] ** t[None, :]).astype(np.complex128)).to(device)
+    D = torch.empty((m, nt), dtype=torch.float64, device=device)
+    for r0 in range(0, m, rows_per_pass):
+        r1 = min(m, r0 + rows_per_pass)
+        D[r0:r1] = torch.real(phi[r0:r1] @ Vt)
+    return D, lam, phi, amp

@@ -151,3 +151,32 @@ def test_dmd_eigvec_convention_and_amplitude_fit():
     err = np.max(np.abs(rec - D[:, :-1])) / np.max(np.abs(D))
     say(f"    reconstruction error {err:.2e}")
     assert err <= 1e-9
+
+
+def test_dmd_jsm_58300000x56_linear_dynamics():
+    # the shape of the paper's DMD profiling (the JSM matrix), exactly linear
+    # data with 50 known modes: the eigenvalues against the true ones, and
+    # phi_i b_i against the true mode times amplitude on sampled rows
+    import torch
+    from paper_2405_15529_amd import api
+    m, N = 58_300_000, 56
+    say(f"[gpu] dmd JSM shape {m}x{N}, 50 known modes")
+    D, lam, phi, amp = synth.linear_dynamics_device(m, N, seed=24)
+    rows = torch.from_numpy(np.random.default_rng(25).choice(m, 256, replace=False)).cuda()
+    ref = (phi[rows] * torch.from_numpy(amp).cuda()[None, :]).cpu().numpy()
+    del phi
+    torch.cuda.empty_cache()
+    ctx = api.Context(0)
+    out = api.dmd(D, r=1e-10, dt=1.0, ctx=ctx)
+    rc, _ = ctx.status()
+    assert rc == 0 and out.nr == len(lam), out.nr
+    mu = out.mu.cpu().numpy()
+    idx = match(mu, lam)
+    emu = float(np.max(np.abs(mu - lam[idx])))
+    pb = (out.phi[rows] * out.b[None, :]).cpu().numpy()
+    ep = float(np.max(np.abs(pb - ref[:, idx])) / np.max(np.abs(ref)))
+    ab = np.abs(out.b.cpu().numpy())
+    say(f"    N_r {out.nr}: |mu - lambda| {emu:.2e}, sampled phi b {ep:.2e}")
+    assert emu <= 1e-10 and ep <= 1e-8
+    assert np.all(np.diff(ab) <= 1e-8 * ab.max())
+    ctx.close()
