@@ -94,10 +94,12 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
  *   "timing"       k > 0: record HIP events around the phases of every
  *                  pod/tsvd call in a ring of k call slots (read back with
  *                  pylom_phase_times); 0 = off (default).
- *   "narrow_leaves" 1 (default): stacked-QR plans with 33 <= n <= 64 and at
- *                  least two leaves per CU factor their leaves in 32-row
- *                  chunks with single-wave workgroups, four leaves per CU;
- *                  0: 64-row chunks with four-wave workgroups, one per CU.
+ *   "narrow_leaves" 1 (default): stacked-QR plans of 3 to 6 panels of 16
+ *                  columns (33 <= n <= 96; up to 8 panels, n <= 128, for the
+ *                  FP32 leaves of PYLOM_MIXED) with at least two leaves per
+ *                  CU factor their leaves in 32-row chunks with single-wave
+ *                  workgroups, several leaves per CU; 0: the default chunk
+ *                  height with four-wave workgroups, one per CU.
  *   "blocked_from" n at which pod/tsvd/tsqr switch to the column-blocked
  *                  TSQR (2..2049), or 0 (default) for the automatic choice:
  *                  column-blocked when n >= 512, or when n >= 64 and

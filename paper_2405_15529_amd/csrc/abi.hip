@@ -31,7 +31,7 @@ struct pylom_ctx_s {
   int64_t max_sweeps = 60;
   int64_t ws_cap_mb = 0;
   int64_t blocked_from = 0;  // n at which the column-blocked TSQR takes over (0: automatic)
-  int64_t narrow_leaves = 1;  // single-wave 32-row leaves for 33 <= n <= 64 with many leaves
+  int64_t narrow_leaves = 1;  // single-wave 32-row leaves for narrow problems with many leaves
   int* status_dev = nullptr;  // Jacobi status pairs (sweeps, barrier timeout) of the last call
   int status_valid = 0;
   int status_pairs = 1;        // 2 after a mixed-precision call (SVD of R + Gram eigen)
@@ -369,11 +369,16 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
   p->last_rows = m - (P - 1) * b;
   if (!qr_geom((int)n, 8, &p->g)) return fail(c, PYLOM_ENOTSUP, "no chunk geometry");
   if (!jacobi_plan((int)n, &p->jp)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
-  // Narrow problems (3 or 4 panels) with at least two leaves per CU: 32-row
-  // chunks and single-wave workgroups, so that four leaves share a CU (38 KB
-  // of LDS each at n = 64), instead of one four-wave workgroup whose three
-  // trailing-tile waves mostly wait on the panel wave.
-  if (c->narrow_leaves && p->g.npanels >= 3 && p->g.npanels <= 4 && P >= 2 * (int64_t)c->ncu) {
+  // Narrow problems with at least two leaves per CU: 32-row chunks and
+  // single-wave workgroups, so that several leaves share a CU (38 KB of LDS
+  // each at n = 64), instead of one four-wave workgroup whose three
+  // trailing-tile waves mostly wait on the panel wave.  Measured on 3.6e7-row
+  // problems: 1.6x faster leaves at 3-4 panels; at 6 panels 1.3x (FP64) and
+  // 1.8x (FP32); at 8 panels 1.7x for FP32 but 16 % slower for FP64, where the
+  // single wave's serial trailing-tile MFMA work dominates; no gain at 1-2
+  // panels (already single-wave).
+  const int np_ = p->g.npanels;
+  if (c->narrow_leaves && np_ >= 3 && np_ <= (mixed ? 8 : 6) && P >= 2 * (int64_t)c->ncu) {
     p->g.s = 32;
     p->g.nthr = 64;
   }

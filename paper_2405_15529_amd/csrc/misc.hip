@@ -157,6 +157,42 @@ __global__ __launch_bounds__(256) void k_matmul_tn_partial(int64_t m, int64_t p,
   }
 }
 
+// Small products (p, q <= 32): one wave per 16x16 tile of C and slice of
+// rows, operands read straight from memory (a 64x64 tile would idle most of
+// its MFMA work and staging on such shapes).
+template <typename T>
+__global__ __launch_bounds__(64) void k_matmul_tn_small(int64_t m, int64_t p, int64_t q,
+                                                        const T* __restrict__ A, int64_t lda,
+                                                        const T* __restrict__ B, int64_t ldb,
+                                                        double* __restrict__ part,
+                                                        int64_t nsplit) {
+  typedef Mfma<double>::v4 v4;
+  const int64_t tp = (p + 15) / 16, tq = (q + 15) / 16;
+  const int64_t tile = blockIdx.x % (tp * tq);
+  const int64_t split = blockIdx.x / (tp * tq);
+  const int64_t i0 = (tile / tq) * 16, j0 = (tile % tq) * 16;
+  const int64_t rows_per = (m + nsplit - 1) / nsplit;
+  const int64_t k0 = split * rows_per;
+  const int64_t k1 = (k0 + rows_per < m) ? k0 + rows_per : m;
+  const int lane = threadIdx.x, i16 = lane & 15, g4 = lane >> 4;
+  const bool iok = i0 + i16 < p, jok = j0 + i16 < q;
+  v4 acc = vzero4<double>();
+  for (int64_t k = k0; k < k1; k += 4) {
+    const int64_t r = k + g4;
+    const double av = (r < k1 && iok) ? (double)A[r * lda + i0 + i16] : 0.0;
+    const double bv = (r < k1 && jok) ? (double)B[r * ldb + j0 + i16] : 0.0;
+    acc = Mfma<double>::op(av, bv, acc);
+  }
+  double* out = part + split * p * q;
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) {
+    const int64_t i = i0 + Mfma<double>::drow(g4, qq), j = j0 + i16;
+    if (i < p && j < q) out[i * q + j] = acc[qq];
+  }
+}
+
+static bool matmul_small(int64_t p, int64_t q) { return p <= 32 && q <= 32; }
+
 template <typename TO>
 __global__ void k_matmul_reduce(int64_t p, int64_t q, const double* __restrict__ part,
                                 int64_t nsplit, TO* C, int64_t ldc) {
@@ -169,9 +205,13 @@ __global__ void k_matmul_reduce(int64_t p, int64_t q, const double* __restrict__
 }
 
 int64_t matmul_tn_splits(int64_t m, int64_t p, int64_t q) {
-  const int64_t tiles = ((p + 63) / 64) * ((q + 63) / 64);
-  // aim for ~1024 workgroups (four per CU), each slice at least 256 rows
-  int64_t s = (1024 + tiles - 1) / tiles;
+  // small shapes: ~4096 one-wave tiles; otherwise ~1024 workgroups of 64x64
+  // (four per CU); each slice at least 256 rows
+  const bool sm = matmul_small(p, q);
+  const int64_t e = sm ? 16 : 64;
+  const int64_t tiles = ((p + e - 1) / e) * ((q + e - 1) / e);
+  const int64_t target = sm ? 4096 : 1024;
+  int64_t s = (target + tiles - 1) / tiles;
   const int64_t maxs = (m + 255) / 256;
   if (s > maxs) s = maxs;
   if (s < 1) s = 1;
@@ -181,14 +221,25 @@ int64_t matmul_tn_splits(int64_t m, int64_t p, int64_t q) {
 hipError_t launch_matmul_tn(int f64, int64_t m, int64_t p, int64_t q, const void* A, int64_t lda,
                             const void* B, int64_t ldb, void* C, int64_t ldc, double* partial,
                             int64_t nsplit, hipStream_t st) {
-  const int64_t tiles = ((p + 63) / 64) * ((q + 63) / 64);
-  const dim3 grid((unsigned)(tiles * nsplit));
-  if (f64)
-    hipLaunchKernelGGL(k_matmul_tn_partial<double>, grid, dim3(256), 0, st, m, p, q,
-                       (const double*)A, lda, (const double*)B, ldb, partial, nsplit);
-  else
-    hipLaunchKernelGGL(k_matmul_tn_partial<float>, grid, dim3(256), 0, st, m, p, q,
-                       (const float*)A, lda, (const float*)B, ldb, partial, nsplit);
+  if (matmul_small(p, q)) {
+    const int64_t tiles = ((p + 15) / 16) * ((q + 15) / 16);
+    const dim3 grid((unsigned)(tiles * nsplit));
+    if (f64)
+      hipLaunchKernelGGL(k_matmul_tn_small<double>, grid, dim3(64), 0, st, m, p, q,
+                         (const double*)A, lda, (const double*)B, ldb, partial, nsplit);
+    else
+      hipLaunchKernelGGL(k_matmul_tn_small<float>, grid, dim3(64), 0, st, m, p, q,
+                         (const float*)A, lda, (const float*)B, ldb, partial, nsplit);
+  } else {
+    const int64_t tiles = ((p + 63) / 64) * ((q + 63) / 64);
+    const dim3 grid((unsigned)(tiles * nsplit));
+    if (f64)
+      hipLaunchKernelGGL(k_matmul_tn_partial<double>, grid, dim3(256), 0, st, m, p, q,
+                         (const double*)A, lda, (const double*)B, ldb, partial, nsplit);
+    else
+      hipLaunchKernelGGL(k_matmul_tn_partial<float>, grid, dim3(256), 0, st, m, p, q,
+                         (const float*)A, lda, (const float*)B, ldb, partial, nsplit);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (f64)

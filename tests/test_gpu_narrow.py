@@ -1,6 +1,7 @@
-"""GPU parity of the narrow-leaf variant of the stacked TSQR (3 or 4 panels,
-33 <= n <= 64, at least two leaves per CU: 32-row chunks and single-wave
-workgroups) against the CPU oracle, with the variant on and off.
+"""GPU parity of the narrow-leaf variant of the stacked TSQR (3 to 6 panels,
+33 <= n <= 96, up to 8 panels for the FP32 leaves of the mixed path; at
+least two leaves per CU: 32-row chunks and single-wave workgroups) against
+the CPU oracle, with the variant on and off.
 
 Leaf heights are set small so that P >= 512 leaves at sizes the oracle
 finishes in seconds; the stacked path is named explicitly (blocked_from =
@@ -62,6 +63,7 @@ def assert_parity(g, ref, r, srel=1e-12, orth=1e-12, vec=1e-9, tie=1e-10):
     (64 * 600, 40, 64, False),         # no mean removal (register prefetch)
     (64 * 512 + 100, 64, 64, True),    # four full panels
     (40 * 515, 33, 40, False),         # three panels, the last one column wide
+    (96 * 520, 90, 96, True),          # six panels, the last one ten columns wide
 ])
 def test_narrow_leaves_pod(m, n, b, rm):
     rng = np.random.default_rng(m + n)
@@ -77,8 +79,10 @@ def test_narrow_leaves_pod(m, n, b, rm):
             np.testing.assert_allclose(g["mean"], ref["mean"], rtol=0, atol=1e-14)
 
 
-def test_narrow_leaves_mixed():
-    m, n, b = 64 * 530, 56, 64
+@pytest.mark.parametrize("n", [56, 120])
+def test_narrow_leaves_mixed(n):
+    b = 128 if n > 64 else 64
+    m = b * 530
     rng = np.random.default_rng(77)
     D32 = (rng.standard_normal((m, n)) * np.exp(-np.arange(n) / 8.0)[None, :] + 0.3).astype(np.float32)
     ref = oracle.pod(D32.astype(np.float64), remove_mean=True, r=0.02)
