@@ -286,29 +286,53 @@ static int64_t level_pairs(int64_t P, int64_t h) { return (P - h + 2 * h - 1) / 
 // so it too runs in waves over the device; one combine costs about half a
 // chunk chain for each of its ceil(n / s) chunks, and every launch costs
 // about 20k cycles.
-static double leaf_model(int64_t m, int64_t n, int64_t b, int ncu) {
+// Whether a stacked plan of P leaves uses the narrow-leaf geometry: 32-row
+// chunks in single-wave workgroups (3-6 panels, up to 8 for the FP32 leaves
+// of the mixed path, at least two leaves per CU).  Measured on 3.6e7-row
+// problems: 1.6x faster leaves at 3-4 panels; at 6 panels 1.3x (FP64) and
+// 1.8x (FP32); at 8 panels 1.7x for FP32 but 16 % slower for FP64, where the
+// single wave's serial trailing-tile MFMA work dominates; no gain at 1-2
+// panels (already single-wave).
+static bool narrow_plan(const pylom_ctx_s* c, int npanels, int64_t P, bool mixed) {
+  return c->narrow_leaves && npanels >= 3 && npanels <= (mixed ? 8 : 6) &&
+         P >= 2 * (int64_t)c->ncu;
+}
+
+static double leaf_model(const pylom_ctx_s* c, int64_t m, int64_t n, int64_t b, bool mixed) {
   QrGeom g;
   if (!qr_geom((int)n, 8, &g)) return 1e300;
+  const int ncu = c->ncu;
   const double c_col = 1600.0, c_tile = 5000.0, c_launch = 20000.0;
   const double chain = (double)n * c_col + (double)g.npanels * c_tile;
   int64_t P = m / b;
   if (P < 1) P = 1;
   const int64_t last = m - (P - 1) * b;
-  const double waves = std::ceil((double)P / (double)ncu);
-  const double t_leaf = waves * std::ceil((double)last / g.s) * chain + c_launch;
+  // leaves run in waves over the CUs: one four-wave workgroup per CU, or as
+  // many single-wave narrow leaves as LDS holds (at most one per SIMD)
+  double slots = (double)ncu;
+  if (narrow_plan(c, g.npanels, P, mixed)) {
+    g.s = 32;
+    const double per_cu = std::floor(160.0 * 1024.0 / (double)qr_lds_bytes(g, 8));
+    slots = (double)ncu * std::max(1.0, std::min(4.0, per_cu));
+  }
+  // every wave but the last holds b-row leaves; the last one holds the
+  // remainder leaf too
+  const double waves = std::ceil((double)P / slots);
+  const double cb = std::ceil((double)b / g.s), cl = std::ceil((double)last / g.s);
+  const double t_leaf = ((waves - 1.0) * cb + std::max(cb, cl)) * chain + c_launch;
   const double combine = std::ceil((double)n / g.s) * chain * 0.5;
   double t_tree = 0.0;
   for (int64_t h = 1; h < P; h *= 2)
-    t_tree += std::ceil((double)level_pairs(P, h) / (double)ncu) * combine + c_launch;
+    t_tree += std::ceil((double)level_pairs(P, h) / slots) * combine + c_launch;
   return t_leaf + t_tree;
 }
 
-static int64_t tune_block_rows(int64_t m, int64_t n, int ncu) {
+static int64_t tune_block_rows(const pylom_ctx_s* c, int64_t m, int64_t n, bool mixed = false) {
   int64_t best = 0;
   double tbest = 0.0;
   for (int64_t b = 128; b <= 32768; b *= 2) {
     if (b < n) continue;
-    const double t = leaf_model(m, n, b, ncu);
+    const double t = leaf_model(c, m, n, b, mixed);
     if (best == 0 || t < tbest) {
       best = b;
       tbest = t;
@@ -343,7 +367,7 @@ static bool use_blocked(const pylom_ctx_s* c, int64_t m, int64_t n, bool batched
 extern "C" int64_t pylom_tune_block_rows(pylom_ctx c, int64_t m, int64_t n) {
   if (!c || n < 1 || m < n || n > kMaxN) return PYLOM_EINVAL;
   if (use_blocked(c, m, n)) return blocked_block_rows(m, n, c->ncu);
-  return tune_block_rows(m, n, c->ncu);
+  return tune_block_rows(c, m, n);
 }
 
 static int make_blocked_plan(pylom_ctx c, Plan* p, bool mixed);
@@ -359,7 +383,7 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
   p->m = m;
   p->n = n;
   if (use_blocked(c, m, n, batched)) return make_blocked_plan(c, p, mixed);
-  int64_t b = c->block_rows > 0 ? c->block_rows : tune_block_rows(m, n, c->ncu);
+  int64_t b = c->block_rows > 0 ? c->block_rows : tune_block_rows(c, m, n, mixed);
   if (b < n) b = n;
   int64_t P = m / b;
   if (P < 1) P = 1;
@@ -369,16 +393,11 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
   p->last_rows = m - (P - 1) * b;
   if (!qr_geom((int)n, 8, &p->g)) return fail(c, PYLOM_ENOTSUP, "no chunk geometry");
   if (!jacobi_plan((int)n, &p->jp)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
-  // Narrow problems with at least two leaves per CU: 32-row chunks and
-  // single-wave workgroups, so that several leaves share a CU (38 KB of LDS
-  // each at n = 64), instead of one four-wave workgroup whose three
-  // trailing-tile waves mostly wait on the panel wave.  Measured on 3.6e7-row
-  // problems: 1.6x faster leaves at 3-4 panels; at 6 panels 1.3x (FP64) and
-  // 1.8x (FP32); at 8 panels 1.7x for FP32 but 16 % slower for FP64, where the
-  // single wave's serial trailing-tile MFMA work dominates; no gain at 1-2
-  // panels (already single-wave).
-  const int np_ = p->g.npanels;
-  if (c->narrow_leaves && np_ >= 3 && np_ <= (mixed ? 8 : 6) && P >= 2 * (int64_t)c->ncu) {
+  // Narrow problems with many leaves: 32-row chunks and single-wave
+  // workgroups, so that several leaves share a CU (38 KB of LDS each at
+  // n = 64), instead of one four-wave workgroup whose three trailing-tile
+  // waves mostly wait on the panel wave (narrow_plan).
+  if (narrow_plan(c, p->g.npanels, P, mixed)) {
     p->g.s = 32;
     p->g.nthr = 64;
   }
@@ -1193,7 +1212,7 @@ extern "C" int pylom_pod_batched(pylom_ctx c, pylom_dtype dtype, pylom_prec prec
     if (rc) return rc;
     if (L.plans[(size_t)i].blocked)
       return fail(c, PYLOM_ENOTSUP, "batched problems need n below the blocked_from option");
-    cost[(size_t)i] = leaf_model(q.m, q.n, L.plans[(size_t)i].b, c->ncu);
+    cost[(size_t)i] = leaf_model(c, q.m, q.n, L.plans[(size_t)i].b, mixed);
   }
   if (count == 0) return PYLOM_OK;
   if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
