@@ -262,7 +262,7 @@ int pylom_spod(pylom_ctx ctx, pylom_dtype spectra, pylom_prec prec, int64_t m, i
  * of Alg. 4 and the amplitudes of Alg. 5, Jovanovic et al.).
  *
  *   D       m x n snapshots (rows = points, ldd >= n), PYLOM_R64 or PYLOM_R32
- *           (promoted to FP64), device; n >= 2 and m >= n - 1.
+ *           (promoted to FP64), device; n >= 2 and m >= n.
  *   remove_mean  nonzero: Y = D - mean 1^T with the mean over all n
  *           snapshots; zero: Y = D.  Y1 = Y[:, :n-1], Y2 = Y[:, 1:].
  *   residual  truncation of the TS-SVD of Y1 = U S W^T, as for pylom_pod.
@@ -279,16 +279,18 @@ int pylom_spod(pylom_ctx ctx, pylom_dtype spectra, pylom_prec prec, int64_t m, i
  * Every modal output is ordered by |b| descending (ties: Im(mu) descending,
  * then eigenvalue index).  Each eigenvector w_i has unit 2-norm with its
  * largest-magnitude entry real and positive.  All arithmetic is FP64; every
- * step runs on the device (TS-SVD, U^T Y2, Householder-Hessenberg reduction,
- * Francis double-shift QR, complex inverse iteration, the Cholesky solve of
- * Alg. 5, the mode GEMM).  The call synchronises once, to read N_r.
+ * step runs on the device: one R-only TSQR of Y = Q_f R_f gives both the
+ * TS-SVD of Y1 (the SVD of R1 = R_f[:n-1, :n-1], since Y1 = Q_f[:, :n-1] R1)
+ * and U^T Y2 = U_R^T R_f[:n-1, 1:]; then the Householder-Hessenberg
+ * reduction, Francis double-shift QR, complex inverse iteration, the
+ * Cholesky solve of Alg. 5 and the mode GEMM.  The call synchronises once,
+ * to read N_r.
  * Errors: PYLOM_ESHAPE (shapes, leading dimensions), PYLOM_EINVAL (null
  * arrays, residual outside [0, 1), dt <= 0), PYLOM_ENOTSUP when the
  * truncation keeps more than 128 modes or a zero singular value (raise the
  * residual).  N_r = 0 (Y1 = 0) writes n_r only.  A QR sweep limit or a
  * Cholesky pivot <= 0 is reported by pylom_check as PYLOM_WNOCONV.  The
- * workspace holds an FP64 copy of Y when remove_mean is set or D is R32,
- * and U (m x (n-1), FP64). */
+ * workspace is that of an R-only TSQR of an m x n matrix plus O(n^2). */
 int pylom_dmd(pylom_ctx ctx, pylom_dtype dtype, int64_t m, int64_t n, const void* D, int64_t ldd,
               int remove_mean, double residual, double dt, void* phi, int64_t ldphi, void* mu,
               void* b, double* freq, double* growth, int64_t* n_r);

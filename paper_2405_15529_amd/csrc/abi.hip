@@ -1392,18 +1392,18 @@ extern "C" int pylom_matmul(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int
 // exact DMD (Sec. 3.2, Alg. 3-5)
 // ---------------------------------------------------------------------------
 struct DmdLayout {
-  bool copy;  // Y = D - mean 1^T (or D promoted) in an FP64 working copy
-  size_t oY, oMean, oU, oS, oVT, oNr, oAux, oPart, oA, oH0, oQv, oQtau, oWr, oWi, oHn, oW, oUb,
-      oP, oQ, oB, oMu, oBo, oPerm, oBr, total;
+  size_t oRf, oR1, oS, oVT, oUR, oSvd, oNr, oAux, oPart, oA, oH0, oQv, oQtau, oWr, oWi, oHn, oW,
+      oUb, oP, oQ, oB, oMu, oBo, oPerm, oBr, total;
 };
 
-// The TS-SVD plan of Y1 (m x (n - 1)) first, then the DMD buffers, sized for
-// the widest linear map the eigen-solver takes.
-static int make_dmd_layout(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, int remove_mean,
-                           Plan* p, DmdLayout* L) {
+// The R-only TSQR plan of all n snapshots first, then the DMD buffers, sized
+// for the widest linear map the eigen-solver takes.
+static int make_dmd_layout(pylom_ctx c, int64_t m, int64_t n, Plan* p, JacobiPlan* jp1,
+                           DmdLayout* L) {
   const int64_t n1 = n - 1;
-  int rc = make_plan(c, m, n1, true, p);
+  int rc = make_plan(c, m, n, false, p);
   if (rc) return rc;
+  if (!jacobi_plan((int)n1, jp1)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
   const int64_t kc = std::min<int64_t>(n1, kDmdMax);
   size_t off = align_up(p->total);
   auto take = [&off](size_t bytes) {
@@ -1411,16 +1411,16 @@ static int make_dmd_layout(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n,
     off = align_up(off + bytes);
     return o;
   };
-  L->copy = remove_mean || dtype == PYLOM_R32;
-  L->oY = L->copy ? take(8 * (size_t)m * n) : 0;
-  L->oMean = take(8 * (size_t)m);
-  L->oU = take(8 * (size_t)m * n1);
+  L->oRf = take(8 * (size_t)n * n);
+  L->oR1 = take(8 * (size_t)n1 * n1);
   L->oS = take(8 * (size_t)n1);
   L->oVT = take(8 * (size_t)n1 * n1);
+  L->oUR = take(8 * (size_t)n1 * n1);
+  L->oSvd = take(jacobi_ws_bytes(*jp1, (int)c->max_sweeps));
   L->oNr = take(8);
   size_t part = 0;
   for (int64_t k = 1; k <= kc; ++k)
-    part = std::max(part, 8 * (size_t)matmul_tn_splits(m, k, n1) * k * n1);
+    part = std::max(part, 8 * (size_t)matmul_tn_splits(n1, k, n1) * k * n1);
   L->oAux = take(8 * (size_t)kc * n1);
   L->oPart = take(part);
   L->oA = take(8 * (size_t)kc * kc);
@@ -1445,17 +1445,25 @@ static int make_dmd_layout(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n,
 
 extern "C" int pylom_dmd_workspace_query(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n,
                                          int remove_mean, size_t* bytes) {
+  (void)remove_mean;
   if (!c || !bytes) return PYLOM_EINVAL;
   if (dtype != PYLOM_R64 && dtype != PYLOM_R32) return fail(c, PYLOM_EDTYPE, "dtype");
-  if (n < 2 || m < n - 1) return fail(c, PYLOM_ESHAPE, "need n >= 2 snapshots and m >= n - 1");
+  if (n < 2 || m < n) return fail(c, PYLOM_ESHAPE, "need n >= 2 snapshots and m >= n");
   Plan p;
+  JacobiPlan jp1;
   DmdLayout L;
-  const int rc = make_dmd_layout(c, dtype, m, n, remove_mean, &p, &L);
+  const int rc = make_dmd_layout(c, m, n, &p, &jp1, &L);
   if (rc) return rc;
   *bytes = L.total;
   return PYLOM_OK;
 }
 
+// Exact DMD.  The TS-SVD of Y1 and the product U^T Y2 of Alg. 3-4 come from
+// one R-only TSQR of all n snapshots: with Y = Q_f R_f, the first n - 1
+// columns of R_f are [R1; 0], so Y1 = Q_f[:, :n-1] R1, the SVD
+// R1 = U_R S W^T gives U = Q_f[:, :n-1] U_R, and U^T Y2 = U_R^T R_f[:n-1, 1:]
+// (exact; no reflector storage, no U, no pass over the data for U^T Y2).
+// The QR's mean removal runs over all n snapshots, as the DMD mean does.
 extern "C" int pylom_dmd(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, const void* D,
                          int64_t ldd, int remove_mean, double residual, double dt, void* phi,
                          int64_t ldphi, void* mu, void* b, double* freq, double* growth,
@@ -1465,12 +1473,13 @@ extern "C" int pylom_dmd(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, c
   if (!D || !phi || !mu || !b || !n_r) return fail(c, PYLOM_EINVAL, "null array argument");
   if (!(residual >= 0.0 && residual < 1.0)) return fail(c, PYLOM_EINVAL, "residual must be in [0, 1)");
   if (!(dt > 0.0)) return fail(c, PYLOM_EINVAL, "dt must be positive");
-  if (n < 2 || m < n - 1) return fail(c, PYLOM_ESHAPE, "need n >= 2 snapshots and m >= n - 1");
+  if (n < 2 || m < n) return fail(c, PYLOM_ESHAPE, "need n >= 2 snapshots and m >= n");
   const int64_t n1 = n - 1, kc = std::min<int64_t>(n1, kDmdMax);
   if (ldd < n || ldphi < kc) return fail(c, PYLOM_ESHAPE, "leading dimension");
   Plan p;
+  JacobiPlan jp1;
   DmdLayout L;
-  rc = make_dmd_layout(c, dtype, m, n, remove_mean, &p, &L);
+  rc = make_dmd_layout(c, m, n, &p, &jp1, &L);
   if (rc) return rc;
   if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
   HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
@@ -1480,22 +1489,35 @@ extern "C" int pylom_dmd(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, c
   x.evs = nullptr;  // the phase ring times pod/tsvd calls only
   char* ws = x.ws;
   const hipStream_t st = x.st;
-  double* mean = (double*)(ws + L.oMean);
-  const double* Y = (const double*)D;
-  int64_t ldy = ldd;
-  if (L.copy) {
-    HIPCHK(c, launch_make_work(dtype == PYLOM_R64, 1, m, (int)n, D, ldd, remove_mean, mean,
-                               ws + L.oY, st), "working copy");
-    Y = (const double*)(ws + L.oY);
-    ldy = n;
+  const int in64 = dtype == PYLOM_R64;
+  double* meanws = (double*)(ws + p.oMean);
+  double* Rbuf = (double*)(ws + p.oR);
+  // R-only TSQR of Y = D - mean 1^T (Alg. 2 + Alg. 1 reduce)
+  if (p.blocked) {
+    HIPCHK(c, launch_make_work(in64, 1, m, (int)n, D, ldd, remove_mean, meanws, ws + p.oWk, st),
+           "working copy");
+    rc = blocked_leaves<double>(c, st, p, ws, Rbuf);
+    if (rc) return rc;
+    rc = blocked_tree(c, st, p, ws);
+    if (rc) return rc;
+  } else {
+    HIPCHK(c, launch_leaf_qr_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws, nullptr,
+                                 (double*)(ws + p.oTleaf), p.nch_leaf, Rbuf, st), "leaf QR");
+    for (int64_t h = 1; h < p.P; h *= 2)
+      HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, Rbuf, (double*)(ws + p.oTtree), p.nch_tree,
+                                        0, st), "tree combine");
   }
-  double* U = (double*)(ws + L.oU);
+  double* Rf = (double*)(ws + L.oRf);
+  double* R1 = (double*)(ws + L.oR1);
   double* S = (double*)(ws + L.oS);
   double* VT = (double*)(ws + L.oVT);
+  double* UR = (double*)(ws + L.oUR);
   int64_t* nr_dev = (int64_t*)(ws + L.oNr);
-  // TS-SVD of Y1 = Y[:, :n-1] (Alg. 1 + truncation), FP64
-  rc = enqueue_fp64(c, x, p, PYLOM_R64, Y, ldy, 0, residual, nullptr, U, n1, S, VT, n1, nr_dev);
-  if (rc) return rc;
+  HIPCHK(c, launch_r_out(Rbuf, n, Rf, n, nullptr, st), "R out");
+  HIPCHK(c, launch_dmd_r1(n1, n, Rf, R1, st), "R1");
+  // SVD of R1 = the SVD of Y1 (Eq. svdqr2) and truncation
+  HIPCHK(c, launch_small_svd(jp1, R1, x.max_sweeps, ws + L.oSvd, S, VT, n1, UR, residual, nr_dev,
+                             x.status, st, x.coop), "small SVD");
   c->status_valid = 1;
   c->status_pairs = 1;
   int64_t k = 0;
@@ -1511,9 +1533,10 @@ extern "C" int pylom_dmd(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, c
   if (k > kDmdMax) return fail(c, PYLOM_ENOTSUP, "DMD keeps at most 128 modes: raise the residual");
   if (!(Sh[(size_t)k - 1] > 0.0))
     return fail(c, PYLOM_ENOTSUP, "a retained singular value is zero: raise the residual");
-  // aux = U^T Y2 (Alg. 4)
-  HIPCHK(c, launch_matmul_tn(1, m, k, n1, U, n1, Y + 1, ldy, ws + L.oAux, n1,
-                             (double*)(ws + L.oPart), matmul_tn_splits(m, k, n1), st), "U^T Y2");
+  // U^T Y2 = U_R[:, :k]^T R_f[:n-1, 1:] (the product of Alg. 4 on the n - 1
+  // rows that span Y1)
+  HIPCHK(c, launch_matmul_tn(1, n1, k, n1, UR, n1, Rf + 1, n, ws + L.oAux, n1,
+                             (double*)(ws + L.oPart), matmul_tn_splits(n1, k, n1), st), "U^T Y2");
   DmdSmallArgs a{};
   a.k = (int)k;
   a.n1 = (int)n1;
@@ -1543,9 +1566,11 @@ extern "C" int pylom_dmd(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, c
   a.B = (double*)(ws + L.oBr);
   HIPCHK(c, launch_dmd_small(a, st), "DMD eigen-solve and amplitudes");
   c->status_pairs = 2;
-  // phi = Y2 B (Eq. dmdmodes), interleaved complex
-  HIPCHK(c, launch_tall_gemm_f64(m, (int)n1, (int)(2 * k), Y + 1, ldy, a.B, 2 * k, (double*)phi,
-                                 2 * ldphi, st), "modes");
+  // phi = (D[:, 1:] - mean 1^T) B (Eq. dmdmodes), interleaved complex
+  const void* D2 = in64 ? (const void*)((const double*)D + 1) : (const void*)((const float*)D + 1);
+  HIPCHK(c, launch_tall_gemm_mu(in64, m, (int)n1, (int)(2 * k), D2, ldd,
+                                remove_mean ? meanws : nullptr, a.B, 2 * k, (double*)phi,
+                                2 * ldphi, st), "modes");
   HIPCHK(c, launch_set_i64(n_r, k, st), "N_r");
   return PYLOM_OK;
 }

@@ -5,6 +5,8 @@
 // taken as columns), every step below runs on the device:
 //
 //   A   = (U^T Y2) W S^-1                     k_dmd_linear_map   (N_r x N_r)
+//         (U^T Y2 arrives as U_R^T R_f[:N-1, 1:], from the R-only TSQR of all
+//         N snapshots; k_dmd_r1 extracts the R1 whose SVD is that of Y1)
 //   A   = Q H Q^T, H upper Hessenberg           k_dmd_hess         (Householder)
 //   mu  = eig(H)                                k_dmd_hqr          (Francis double-shift QR)
 //   w_i = Q x_i, (H - mu_i I) x_i = 0           k_dmd_invit        (complex inverse iteration)
@@ -12,7 +14,7 @@
 //   b   = P^-1 q by Cholesky                    k_dmd_cholsolve
 //   order by |b|, frequencies, growth rates     k_dmd_order
 //   B   = W S^-1 w / mu (interleaved complex)   k_dmd_mode_rhs
-//   phi = Y2 B                                  the tall FP64 MFMA GEMM of refine.hip
+//   phi = (D2 - mean 1^T) B                     the tall FP64 MFMA GEMM of refine.hip
 //
 // The eigen-solver is LAPACK's dgeev recast for one workgroup: the linear map
 // is at most kDmdMax = 128 wide, so H (ld = N_r | 1) sits in LDS, the QR
@@ -616,6 +618,23 @@ __global__ __launch_bounds__(128) void k_dmd_mode_rhs(int k, int n1, const doubl
     B[(int64_t)t * 2 * k + 2 * c] = v.x;
     B[(int64_t)t * 2 * k + 2 * c + 1] = v.y;
   }
+}
+
+__global__ void k_dmd_r1(int64_t n1, int64_t n, const double* __restrict__ R,
+                         double* __restrict__ R1) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n1 * n1;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / n1, j = idx % n1;
+    R1[idx] = R[i * n + j];
+  }
+}
+
+hipError_t launch_dmd_r1(int64_t n1, int64_t n, const double* R, double* R1, hipStream_t st) {
+  int64_t g = (n1 * n1 + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_dmd_r1, dim3((unsigned)g), dim3(256), 0, st, n1, n, R, R1);
+  return hipGetLastError();
 }
 
 size_t dmd_eig_lds_bytes(int k) {

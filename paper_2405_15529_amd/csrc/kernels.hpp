@@ -186,10 +186,13 @@ size_t dmd_eig_lds_bytes(int k);
 // Linear map, eigendecomposition, amplitudes, ordering and the right factor
 // of the modes (every step after U^T Y2 and before phi = Y2 B).
 hipError_t launch_dmd_small(const DmdSmallArgs& a, hipStream_t st);
-// C (m x nc, ld ldc) = A (m x K, ld lda) B (K x nc, ld ldb), FP64.
-hipError_t launch_tall_gemm_f64(int64_t m, int K, int nc, const double* A, int64_t lda,
-                                const double* B, int64_t ldb, double* C, int64_t ldc,
-                                hipStream_t st);
+// C (m x nc, ld ldc, FP64) = (A - mu 1^T) (m x K, ld lda; FP64 or FP32, mu
+// may be null) B (K x nc, ld ldb), FP64 MFMA.
+hipError_t launch_tall_gemm_mu(int in_f64, int64_t m, int K, int nc, const void* A, int64_t lda,
+                               const double* mu, const double* B, int64_t ldb, double* C,
+                               int64_t ldc, hipStream_t st);
+// R1 (n1 x n1, row stride n1) = the leading n1 x n1 block of R (row stride n).
+hipError_t launch_dmd_r1(int64_t n1, int64_t n, const double* R, double* R1, hipStream_t st);
 
 // ---- mixed precision: Rayleigh-Ritz refinement against the input ------------
 hipError_t launch_cast_f32_f64(const float* src, double* dst, int64_t count, hipStream_t st);

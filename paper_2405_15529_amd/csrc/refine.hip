@@ -264,10 +264,14 @@ hipError_t launch_rr_form_u(int out_f64, int64_t m, int k, const double* Z, cons
                                          (float*)U, ldu, st);
 }
 
-hipError_t launch_tall_gemm_f64(int64_t m, int K, int nc, const double* A, int64_t lda,
-                                const double* B, int64_t ldb, double* C, int64_t ldc,
-                                hipStream_t st) {
-  return launch_tg<double, double, false>(m, K, nc, nullptr, A, lda, nullptr, B, ldb, C, ldc, st);
+hipError_t launch_tall_gemm_mu(int in_f64, int64_t m, int K, int nc, const void* A, int64_t lda,
+                               const double* mu, const double* B, int64_t ldb, double* C,
+                               int64_t ldc, hipStream_t st) {
+  if (in_f64)
+    return launch_tg<double, double, false>(m, K, nc, nullptr, (const double*)A, lda, mu, B, ldb,
+                                            C, ldc, st);
+  return launch_tg<float, double, false>(m, K, nc, nullptr, (const float*)A, lda, mu, B, ldb, C,
+                                         ldc, st);
 }
 
 }  // namespace pylom

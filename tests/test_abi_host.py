@@ -289,3 +289,28 @@ def test_batched_validation_before_device(hctx):
     assert hctx.get_option("streams") == 8
     with pytest.raises(api.PylomError):
         hctx.set_option("streams", 0)
+
+
+def test_dmd_validation_before_device(hctx):
+    lib, h = hctx.lib, hctx.h
+    vp = ctypes.c_void_p
+
+    def call(m=1000, n=20, D=1, ldd=None, r=0.01, dt=1.0, phi=1, ldphi=None, mu=1, b=1, nr=1,
+             dtype=api.R64):
+        ldd = n if ldd is None else ldd
+        ldphi = max(1, min(n - 1, 128)) if ldphi is None else ldphi
+        return lib.pylom_dmd(h, dtype, m, n, vp(D), ldd, 0, r, dt, vp(phi), ldphi, vp(mu), vp(b),
+                             None, None, vp(nr))
+    assert call() == -7                       # valid: no device
+    assert call(dtype=api.R32) == -7
+    assert call(n=1) == -2                    # one snapshot
+    assert call(m=10, n=20) == -2             # m < n
+    assert call(ldd=10) == -2
+    assert call(ldphi=5) == -2                # ldphi < min(n - 1, 128)
+    assert call(D=0) == -1 and call(phi=0) == -1 and call(nr=0) == -1
+    assert call(r=1.0) == -1 and call(dt=0.0) == -1
+    assert call(dtype=api.C64) == -3
+    b = ctypes.c_size_t()
+    assert lib.pylom_dmd_workspace_query(h, api.R64, 58_300_000, 56, 0, ctypes.byref(b)) == 0
+    # an R-only TSQR of the snapshots plus O(n^2): far below the 26 GB input
+    assert 0 < b.value < 8 * 58_300_000 * 56
