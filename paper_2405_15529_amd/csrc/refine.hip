@@ -23,7 +23,7 @@ namespace pylom {
 
 namespace {
 constexpr int GR = 64;   // rows per workgroup
-constexpr int GK = 32;   // K slab staged in LDS
+constexpr int GK = 8;    // K slab staged in LDS (9-13 KB per workgroup: registers bound the occupancy)
 constexpr int ALD = GK + 1;
 }  // namespace
 
