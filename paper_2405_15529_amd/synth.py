@@ -94,6 +94,20 @@ def travelling_waves(m: int, n: int, seed: int = 2, nwaves: int = 64, noise: flo
     return np.ascontiguousarray(D.astype(dtype))
 
 
+def travelling_wave_params(m: int, seed: int = 2, nwaves: int = 64):
+    """The draws of ``travelling_waves_device`` in their order: distinct integer
+    wavenumbers kappa, angular frequencies w ~ U[0.1, 5] (per snapshot),
+    phases and amplitudes a_k = 2^(-k/8).  Each wave is two exponentials in
+    time, e^{+-i w t}: the eigenvalues exact DMD recovers."""
+    rng = np.random.default_rng(seed)
+    kmax = max(2, min(2048, m // 2 - 1))
+    kap = rng.choice(np.arange(1, kmax + 1), size=nwaves, replace=False).astype(np.float64)
+    w = rng.uniform(0.1, 5.0, nwaves)
+    th = rng.uniform(0.0, 2.0 * np.pi, nwaves)
+    a = 2.0 ** (-np.arange(nwaves) / 8.0)
+    return kap, w, th, a
+
+
 def travelling_waves_device(m: int, n: int, seed: int = 2, nwaves: int = 64,
                             noise: float = 1e-4, device: str = "cuda", rows_per_pass: int = 131072):
     """Device-side twin of ``travelling_waves`` for large m (FP32, m x n):
@@ -103,12 +117,7 @@ def travelling_waves_device(m: int, n: int, seed: int = 2, nwaves: int = 64,
     generator, so it is not the CPU generator's noise sample."""
     import torch
 
-    rng = np.random.default_rng(seed)
-    kmax = max(2, min(2048, m // 2 - 1))
-    kap = rng.choice(np.arange(1, kmax + 1), size=nwaves, replace=False).astype(np.float64)
-    w = rng.uniform(0.1, 5.0, nwaves)
-    th = rng.uniform(0.0, 2.0 * np.pi, nwaves)
-    a = 2.0 ** (-np.arange(nwaves) / 8.0)
+    kap, w, th, a = travelling_wave_params(m, seed, nwaves)
     t = np.arange(n, dtype=np.float64)
     arg = np.outer(w, t) - th[:, None]
     temporal = np.concatenate([a[:, None] * np.cos(arg), a[:, None] * np.sin(arg)], axis=0)
