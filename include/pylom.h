@@ -221,9 +221,11 @@ int pylom_pod_batched(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t
 
 /* The leaf height b chosen for an m x n problem when "block_rows" is 0: the
  * minimiser, over b in {128, 256, ..., 32768} with b >= n, of a latency model
- * of the stacked QR (leaf critical path of ceil(b / s) chunks, waves of leaves
- * over the device's compute units, ceil(log2 P) dependent tree levels and one
- * launch per level).  Where the column-blocked TSQR serves the shape (see
+ * of the stacked QR (leaf critical path of ceil(b / s) chunks; leaves in
+ * waves over the compute units, one per CU, or several single-wave narrow
+ * leaves per CU, see "narrow_leaves"; the remainder leaf in the last wave;
+ * ceil(log2 P) tree levels, each in waves of its combines, and one launch
+ * per level).  FP64 plans.  Where the column-blocked TSQR serves the shape (see
  * "blocked_from"), ceil(m / (2 CUs)) rounded up to a multiple of 64 (at
  * least n).  Host only; n <= 2048. */
 int64_t pylom_tune_block_rows(pylom_ctx ctx, int64_t m, int64_t n);
