@@ -216,6 +216,71 @@ hipError_t launch_cast_f32_f64(const float* src, double* dst, int64_t count, hip
   return hipGetLastError();
 }
 
+// The same product for a small K (<= 64) and at most 128 output columns, as
+// in the DMD modes: every workgroup stages all of B in LDS once and then walks
+// row tiles of 64 (grid-stride), staging only K slabs of A.
+constexpr int PK = 64;    // largest K kept whole in LDS
+constexpr int PGC = 128;  // output columns
+template <typename TI>
+__global__ __launch_bounds__(256) void k_tall_gemm_pb(int64_t m, int K, int nc,
+                                                      const TI* __restrict__ A, int64_t lda,
+                                                      const double* __restrict__ mu,
+                                                      const double* __restrict__ Bs, int64_t ldb,
+                                                      double* __restrict__ C, int64_t ldc) {
+  constexpr int BLD = PGC + 1;
+  constexpr int NT = PGC / 16;
+  __shared__ double Bsh[PK * BLD];
+  __shared__ double As[GR * ALD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  for (int idx = tid; idx < PK * PGC; idx += 256) {
+    const int t = idx / PGC, j = idx % PGC;
+    Bsh[t * BLD + j] = (t < K && j < nc) ? Bs[(int64_t)t * ldb + j] : 0.0;
+  }
+  __syncthreads();
+  const int64_t ntiles = (m + GR - 1) / GR;
+  typedef Mfma<double>::v4 v4;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t r0 = tile * GR;
+    v4 acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[c] = vzero4<double>();
+    for (int k0 = 0; k0 < K; k0 += GK) {
+#pragma unroll
+      for (int e = 0; e < (GR * GK) / 256; ++e) {
+        const int idx = tid + 256 * e;
+        const int r = idx / GK, c = idx % GK;
+        const int64_t gr = r0 + r;
+        const int gc = k0 + c;
+        double v = 0.0;
+        if (gr < m && gc < K) {
+          v = (double)A[gr * lda + gc];
+          if (mu) v -= mu[gr];
+        }
+        As[r * ALD + c] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kb = 0; kb < GK; kb += 4) {
+        const double av = As[(wave * 16 + i16) * ALD + kb + g4];
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+          acc[c] = Mfma<double>::op(av, Bsh[(k0 + kb + g4) * BLD + c * 16 + i16], acc[c]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      const int col = c * 16 + i16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t row = r0 + wave * 16 + Mfma<double>::drow(g4, q);
+        if (row < m && col < nc) C[row * ldc + col] = acc[c][q];
+      }
+    }
+  }
+}
+
 // One launch of the tall GEMM: 128-column workgroups when more than 64
 // output columns are asked for (A is then read once per 128 columns).
 template <typename TI, typename TO, bool BT>
@@ -267,6 +332,17 @@ hipError_t launch_rr_form_u(int out_f64, int64_t m, int k, const double* Z, cons
 hipError_t launch_tall_gemm_mu(int in_f64, int64_t m, int K, int nc, const void* A, int64_t lda,
                                const double* mu, const double* B, int64_t ldb, double* C,
                                int64_t ldc, hipStream_t st) {
+  if (m > 0 && K <= PK && nc > 0 && nc <= PGC) {
+    const int64_t ntiles = (m + GR - 1) / GR;
+    const unsigned g = (unsigned)(ntiles < 1024 ? ntiles : 1024);
+    if (in_f64)
+      hipLaunchKernelGGL(k_tall_gemm_pb<double>, dim3(g), dim3(256), 0, st, m, K, nc,
+                         (const double*)A, lda, mu, B, ldb, C, ldc);
+    else
+      hipLaunchKernelGGL(k_tall_gemm_pb<float>, dim3(g), dim3(256), 0, st, m, K, nc,
+                         (const float*)A, lda, mu, B, ldb, C, ldc);
+    return hipGetLastError();
+  }
   if (in_f64)
     return launch_tg<double, double, false>(m, K, nc, nullptr, (const double*)A, lda, mu, B, ldb,
                                             C, ldc, st);
