@@ -217,68 +217,114 @@ hipError_t launch_cast_f32_f64(const float* src, double* dst, int64_t count, hip
 }
 
 // The same product for a small K (<= 64) and at most 128 output columns, as
-// in the DMD modes: every workgroup stages all of B in LDS once and then walks
-// row tiles of 64 (grid-stride), staging only K slabs of A.
+// in the DMD modes.  Every workgroup stages B once in LDS, sized to the call
+// (4 ceil(K/4) rows of 16 ceil(nc/16) + 1 doubles); after that one barrier
+// each wave walks 16-row strips on its own (grid-stride over strips, no
+// further barriers).  The contraction index is split in four contiguous
+// quarters of kq = ceil(K/4): lane (i, g) holds row i of its strip at
+// columns g kq .. g kq + kq - 1, so MFMA step t takes column g kq + t of A
+// and the matching row of B from LDS (the sum over k is the same, its order
+// differs).  The next strip's A (and its mean) is loaded into registers
+// before the current strip is multiplied, and the mean is subtracted when a
+// value is used, so nothing waits on the prefetch until the strip is done.
 constexpr int PK = 64;    // largest K kept whole in LDS
 constexpr int PGC = 128;  // output columns
+constexpr int PKQ = PK / 4;
+constexpr int PNT = PGC / 16;
+
+template <typename TI>
+__device__ __forceinline__ void pb_load(int64_t strip, int64_t m, int K, int kq, int i16, int g4,
+                                        const TI* __restrict__ A, int64_t lda,
+                                        const double* __restrict__ mu, TI (&x)[PKQ],
+                                        double& mr) {
+  const int64_t row = strip * 16 + i16;
+  const bool in = row < m;
+  const TI* ar = A + (in ? row : 0) * lda + g4 * kq;
+#pragma unroll
+  for (int t = 0; t < PKQ; ++t) x[t] = (in && t < kq && g4 * kq + t < K) ? ar[t] : TI(0);
+  mr = (in && mu) ? mu[row] : 0.0;
+}
+
 template <typename TI>
 __global__ __launch_bounds__(256) void k_tall_gemm_pb(int64_t m, int K, int nc,
                                                       const TI* __restrict__ A, int64_t lda,
                                                       const double* __restrict__ mu,
                                                       const double* __restrict__ Bs, int64_t ldb,
                                                       double* __restrict__ C, int64_t ldc) {
-  constexpr int BLD = PGC + 1;
-  constexpr int NT = PGC / 16;
-  __shared__ double Bsh[PK * BLD];
-  __shared__ double As[GR * ALD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int i16 = lane & 15, g4 = lane >> 4;
-  for (int idx = tid; idx < PK * PGC; idx += 256) {
-    const int t = idx / PGC, j = idx % PGC;
-    Bsh[t * BLD + j] = (t < K && j < nc) ? Bs[(int64_t)t * ldb + j] : 0.0;
+  extern __shared__ double Bsh[];
+  const int kq = (K + 3) >> 2, nct = (nc + 15) >> 4;
+  const int bw = 16 * nct, bld = bw + 1;
+  for (int idx = threadIdx.x; idx < 4 * kq * bw; idx += 256) {
+    const int t = idx / bw, j = idx % bw;
+    Bsh[t * bld + j] = (t < K && j < nc) ? Bs[(int64_t)t * ldb + j] : 0.0;
   }
   __syncthreads();
-  const int64_t ntiles = (m + GR - 1) / GR;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  const int64_t nstrips = (m + 15) >> 4;
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  int64_t s = (int64_t)blockIdx.x * 4 + wave;
+  if (s >= nstrips) return;
   typedef Mfma<double>::v4 v4;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t r0 = tile * GR;
-    v4 acc[NT];
+  TI a[PKQ], an[PKQ];
+  double mr, mrn;
+  pb_load(s, m, K, kq, i16, g4, A, lda, mu, a, mr);
+  const double* brow = Bsh + (g4 * kq) * bld + i16;
+  for (; s < nstrips; s += stride) {
+    const int64_t sn = s + stride;
+    if (sn < nstrips) pb_load(sn, m, K, kq, i16, g4, A, lda, mu, an, mrn);
+    v4 acc[PNT];
 #pragma unroll
-    for (int c = 0; c < NT; ++c) acc[c] = vzero4<double>();
-    for (int k0 = 0; k0 < K; k0 += GK) {
+    for (int c = 0; c < PNT; ++c) acc[c] = vzero4<double>();
 #pragma unroll
-      for (int e = 0; e < (GR * GK) / 256; ++e) {
-        const int idx = tid + 256 * e;
-        const int r = idx / GK, c = idx % GK;
-        const int64_t gr = r0 + r;
-        const int gc = k0 + c;
-        double v = 0.0;
-        if (gr < m && gc < K) {
-          v = (double)A[gr * lda + gc];
-          if (mu) v -= mu[gr];
-        }
-        As[r * ALD + c] = v;
+    for (int t = 0; t < PKQ; ++t) {
+      if (t < kq) {
+        const double av = (double)a[t] - mr;
+#pragma unroll
+        for (int c = 0; c < PNT; ++c)
+          if (c < nct) acc[c] = Mfma<double>::op(av, brow[t * bld + c * 16], acc[c]);
       }
-      __syncthreads();
-#pragma unroll
-      for (int kb = 0; kb < GK; kb += 4) {
-        const double av = As[(wave * 16 + i16) * ALD + kb + g4];
-#pragma unroll
-        for (int c = 0; c < NT; ++c)
-          acc[c] = Mfma<double>::op(av, Bsh[(k0 + kb + g4) * BLD + c * 16 + i16], acc[c]);
-      }
-      __syncthreads();
     }
 #pragma unroll
-    for (int c = 0; c < NT; ++c) {
+    for (int c = 0; c < PNT; ++c) {
       const int col = c * 16 + i16;
+      if (c < nct && col < nc) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t row = r0 + wave * 16 + Mfma<double>::drow(g4, q);
-        if (row < m && col < nc) C[row * ldc + col] = acc[c][q];
+        for (int q = 0; q < 4; ++q) {
+          const int64_t row = s * 16 + Mfma<double>::drow(g4, q);
+          if (row < m) C[row * ldc + col] = acc[c][q];
+        }
       }
     }
+#pragma unroll
+    for (int t = 0; t < PKQ; ++t) a[t] = an[t];
+    mr = mrn;
   }
+}
+
+template <typename TI>
+static hipError_t launch_pb(int64_t m, int K, int nc, const TI* A, int64_t lda, const double* mu,
+                            const double* B, int64_t ldb, double* C, int64_t ldc, hipStream_t st) {
+  const int kq = (K + 3) / 4, nct = (nc + 15) / 16;
+  const size_t lds = (size_t)4 * kq * (16 * nct + 1) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_tall_gemm_pb<TI>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, ncu = 0, per = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_tall_gemm_pb<TI>,
+                                                        256, lds)) != hipSuccess)
+    return e;
+  // one workgroup per resident slot (each wave walks its strips), no more
+  // than there are groups of four strips
+  const int64_t groups = ((m + 15) / 16 + 3) / 4;
+  int64_t g = (int64_t)(ncu > 0 ? ncu : 1) * (per > 0 ? per : 1);
+  if (g > groups) g = groups;
+  hipLaunchKernelGGL(k_tall_gemm_pb<TI>, dim3((unsigned)g), dim3(256), lds, st, m, K, nc, A, lda,
+                     mu, B, ldb, C, ldc);
+  return hipGetLastError();
 }
 
 // One launch of the tall GEMM: 128-column workgroups when more than 64
@@ -332,16 +378,9 @@ hipError_t launch_rr_form_u(int out_f64, int64_t m, int k, const double* Z, cons
 hipError_t launch_tall_gemm_mu(int in_f64, int64_t m, int K, int nc, const void* A, int64_t lda,
                                const double* mu, const double* B, int64_t ldb, double* C,
                                int64_t ldc, hipStream_t st) {
-  if (m > 0 && K <= PK && nc > 0 && nc <= PGC) {
-    const int64_t ntiles = (m + GR - 1) / GR;
-    const unsigned g = (unsigned)(ntiles < 1024 ? ntiles : 1024);
-    if (in_f64)
-      hipLaunchKernelGGL(k_tall_gemm_pb<double>, dim3(g), dim3(256), 0, st, m, K, nc,
-                         (const double*)A, lda, mu, B, ldb, C, ldc);
-    else
-      hipLaunchKernelGGL(k_tall_gemm_pb<float>, dim3(g), dim3(256), 0, st, m, K, nc,
-                         (const float*)A, lda, mu, B, ldb, C, ldc);
-    return hipGetLastError();
+  if (m > 0 && K > 0 && K <= PK && nc > 0 && nc <= PGC) {
+    if (in_f64) return launch_pb<double>(m, K, nc, (const double*)A, lda, mu, B, ldb, C, ldc, st);
+    return launch_pb<float>(m, K, nc, (const float*)A, lda, mu, B, ldb, C, ldc, st);
   }
   if (in_f64)
     return launch_tg<double, double, false>(m, K, nc, nullptr, (const double*)A, lda, mu, B, ldb,
