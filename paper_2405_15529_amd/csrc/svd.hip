@@ -36,9 +36,11 @@ constexpr int JRPL = 32;    // max column rows per lane (16 up to n = 1024)
 bool jacobi_plan(int n, JacobiPlan* p) {
   if (n < 1 || n > 2048) return false;
   // block width w (even, 4..16): a pair is handled by 256/w lanes of one wave,
-  // each holding at most JRPL rows of a column
-  int w = 16;
-  while (w > 4 && n * w > 4096) w >>= 1;
+  // each holding at most JRPL rows of a column.  16 up to n = 256, else 4:
+  // measured on one MI355X (the SVD phase of FP64 POD), n = 256 takes 6.3 ms
+  // at w = 16, 8.9 at w = 8 and 17.3 at w = 4; n = 320 takes 12.9 ms at
+  // w = 8 and 11.2 at w = 4; n = 512 34.2 ms at w = 8 and 22.2 at w = 4.
+  int w = (n * 16 <= 4096) ? 16 : 4;
   if (n <= 2 * w) {
     int half = (n + 1) / 2;
     int ww = 4;
