@@ -77,6 +77,10 @@ SHAPES = [
     (2000, 300, 2000, False),
     (4100, 97, 512, True),
     (2600, 129, 300, False),
+    # the Jacobi of R with 4-column blocks: n = 257 is the narrowest such
+    # problem (33 workgroups), n = 500 has a 52-column last panel
+    (2600, 257, 1300, True),
+    (3000, 500, 1500, False),
 ]
 
 
