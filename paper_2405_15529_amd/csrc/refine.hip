@@ -227,6 +227,8 @@ hipError_t launch_cast_f32_f64(const float* src, double* dst, int64_t count, hip
 // differs).  The next strip's A (and its mean) is loaded into registers
 // before the current strip is multiplied, and the mean is subtracted when a
 // value is used, so nothing waits on the prefetch until the strip is done.
+// B(t, j) = Bs[j * ldb + t] when BT (the mixed refinement's projection onto
+// the rows of V^T), else Bs[t * ldb + j] (the DMD modes).
 constexpr int PK = 64;    // largest K kept whole in LDS
 constexpr int PGC = 128;  // output columns
 constexpr int PKQ = PK / 4;
@@ -245,7 +247,7 @@ __device__ __forceinline__ void pb_load(int64_t strip, int64_t m, int K, int kq,
   mr = (in && mu) ? mu[row] : 0.0;
 }
 
-template <typename TI>
+template <typename TI, bool BT>
 __global__ __launch_bounds__(256) void k_tall_gemm_pb(int64_t m, int K, int nc,
                                                       const TI* __restrict__ A, int64_t lda,
                                                       const double* __restrict__ mu,
@@ -256,7 +258,9 @@ __global__ __launch_bounds__(256) void k_tall_gemm_pb(int64_t m, int K, int nc,
   const int bw = 16 * nct, bld = bw + 1;
   for (int idx = threadIdx.x; idx < 4 * kq * bw; idx += 256) {
     const int t = idx / bw, j = idx % bw;
-    Bsh[t * bld + j] = (t < K && j < nc) ? Bs[(int64_t)t * ldb + j] : 0.0;
+    double v = 0.0;
+    if (t < K && j < nc) v = BT ? Bs[(int64_t)j * ldb + t] : Bs[(int64_t)t * ldb + j];
+    Bsh[t * bld + j] = v;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -302,19 +306,21 @@ __global__ __launch_bounds__(256) void k_tall_gemm_pb(int64_t m, int K, int nc,
   }
 }
 
-template <typename TI>
+// K in 1..PK, nc in 1..PGC.
+template <typename TI, bool BT>
 static hipError_t launch_pb(int64_t m, int K, int nc, const TI* A, int64_t lda, const double* mu,
                             const double* B, int64_t ldb, double* C, int64_t ldc, hipStream_t st) {
+  if (K < 1 || K > PK || nc < 1 || nc > PGC) return hipErrorInvalidValue;
   const int kq = (K + 3) / 4, nct = (nc + 15) / 16;
   const size_t lds = (size_t)4 * kq * (16 * nct + 1) * sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void*)k_tall_gemm_pb<TI>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_tall_gemm_pb<TI, BT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int dev = 0, ncu = 0, per = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return e;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_tall_gemm_pb<TI>,
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_tall_gemm_pb<TI, BT>,
                                                         256, lds)) != hipSuccess)
     return e;
   // one workgroup per resident slot (each wave walks its strips), no more
@@ -322,8 +328,8 @@ static hipError_t launch_pb(int64_t m, int K, int nc, const TI* A, int64_t lda, 
   const int64_t groups = ((m + 15) / 16 + 3) / 4;
   int64_t g = (int64_t)(ncu > 0 ? ncu : 1) * (per > 0 ? per : 1);
   if (g > groups) g = groups;
-  hipLaunchKernelGGL(k_tall_gemm_pb<TI>, dim3((unsigned)g), dim3(256), lds, st, m, K, nc, A, lda,
-                     mu, B, ldb, C, ldc);
+  hipLaunchKernelGGL((k_tall_gemm_pb<TI, BT>), dim3((unsigned)g), dim3(256), lds, st, m, K, nc, A,
+                     lda, mu, B, ldb, C, ldc);
   return hipGetLastError();
 }
 
@@ -348,6 +354,11 @@ static hipError_t launch_tg(int64_t m, int K, int nc, const int64_t* nc_dev, con
 
 hipError_t launch_rr_project(int in_f64, int64_t m, int n, int k, const void* A, int64_t lda,
                              const double* mu, const double* VT0, double* Z, hipStream_t st) {
+  // narrow inputs (n <= 64): B = V_k^T stays in LDS, A is read once in
+  // register strips
+  if (!in_f64 && m > 0 && n > 0 && n <= PK && k > 0 && k <= PGC)
+    return launch_pb<float, true>(m, n, k, (const float*)A, lda, mu, VT0, (int64_t)n, Z,
+                                  (int64_t)k, st);
   if (in_f64)
     return launch_tg<double, double, true>(m, n, k, nullptr, (const double*)A, lda, mu, VT0,
                                            (int64_t)n, Z, (int64_t)k, st);
@@ -379,8 +390,9 @@ hipError_t launch_tall_gemm_mu(int in_f64, int64_t m, int K, int nc, const void*
                                const double* mu, const double* B, int64_t ldb, double* C,
                                int64_t ldc, hipStream_t st) {
   if (m > 0 && K > 0 && K <= PK && nc > 0 && nc <= PGC) {
-    if (in_f64) return launch_pb<double>(m, K, nc, (const double*)A, lda, mu, B, ldb, C, ldc, st);
-    return launch_pb<float>(m, K, nc, (const float*)A, lda, mu, B, ldb, C, ldc, st);
+    if (in_f64)
+      return launch_pb<double, false>(m, K, nc, (const double*)A, lda, mu, B, ldb, C, ldc, st);
+    return launch_pb<float, false>(m, K, nc, (const float*)A, lda, mu, B, ldb, C, ldc, st);
   }
   if (in_f64)
     return launch_tg<double, double, false>(m, K, nc, nullptr, (const double*)A, lda, mu, B, ldb,
