@@ -247,13 +247,16 @@ __device__ __forceinline__ void pb_load(int64_t strip, int64_t m, int K, int kq,
   mr = (in && mu) ? mu[row] : 0.0;
 }
 
-template <typename TI, bool BT>
+template <typename TI, typename TO, bool BT>
 __global__ __launch_bounds__(256) void k_tall_gemm_pb(int64_t m, int K, int nc,
+                                                      const int64_t* __restrict__ nc_dev,
                                                       const TI* __restrict__ A, int64_t lda,
                                                       const double* __restrict__ mu,
                                                       const double* __restrict__ Bs, int64_t ldb,
-                                                      double* __restrict__ C, int64_t ldc) {
+                                                      TO* __restrict__ C, int64_t ldc) {
   extern __shared__ double Bsh[];
+  if (nc_dev && *nc_dev < nc) nc = (int)*nc_dev;  // the same value in every thread
+  if (nc <= 0) return;
   const int kq = (K + 3) >> 2, nct = (nc + 15) >> 4;
   const int bw = 16 * nct, bld = bw + 1;
   for (int idx = threadIdx.x; idx < 4 * kq * bw; idx += 256) {
@@ -296,7 +299,7 @@ __global__ __launch_bounds__(256) void k_tall_gemm_pb(int64_t m, int K, int nc,
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t row = s * 16 + Mfma<double>::drow(g4, q);
-          if (row < m) C[row * ldc + col] = acc[c][q];
+          if (row < m) C[row * ldc + col] = (TO)acc[c][q];
         }
       }
     }
@@ -306,30 +309,32 @@ __global__ __launch_bounds__(256) void k_tall_gemm_pb(int64_t m, int K, int nc,
   }
 }
 
-// K in 1..PK, nc in 1..PGC.
-template <typename TI, bool BT>
-static hipError_t launch_pb(int64_t m, int K, int nc, const TI* A, int64_t lda, const double* mu,
-                            const double* B, int64_t ldb, double* C, int64_t ldc, hipStream_t st) {
+// K in 1..PK, nc in 1..PGC (with nc_dev: nc = min(nc, *nc_dev), LDS sized
+// for nc).
+template <typename TI, typename TO, bool BT>
+static hipError_t launch_pb(int64_t m, int K, int nc, const int64_t* nc_dev, const TI* A,
+                            int64_t lda, const double* mu, const double* B, int64_t ldb, TO* C,
+                            int64_t ldc, hipStream_t st) {
   if (K < 1 || K > PK || nc < 1 || nc > PGC) return hipErrorInvalidValue;
   const int kq = (K + 3) / 4, nct = (nc + 15) / 16;
   const size_t lds = (size_t)4 * kq * (16 * nct + 1) * sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void*)k_tall_gemm_pb<TI, BT>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_tall_gemm_pb<TI, TO, BT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int dev = 0, ncu = 0, per = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return e;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_tall_gemm_pb<TI, BT>,
-                                                        256, lds)) != hipSuccess)
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+           &per, (const void*)k_tall_gemm_pb<TI, TO, BT>, 256, lds)) != hipSuccess)
     return e;
   // one workgroup per resident slot (each wave walks its strips), no more
   // than there are groups of four strips
   const int64_t groups = ((m + 15) / 16 + 3) / 4;
   int64_t g = (int64_t)(ncu > 0 ? ncu : 1) * (per > 0 ? per : 1);
   if (g > groups) g = groups;
-  hipLaunchKernelGGL((k_tall_gemm_pb<TI, BT>), dim3((unsigned)g), dim3(256), lds, st, m, K, nc, A,
-                     lda, mu, B, ldb, C, ldc);
+  hipLaunchKernelGGL((k_tall_gemm_pb<TI, TO, BT>), dim3((unsigned)g), dim3(256), lds, st, m, K,
+                     nc, nc_dev, A, lda, mu, B, ldb, C, ldc);
   return hipGetLastError();
 }
 
@@ -357,8 +362,8 @@ hipError_t launch_rr_project(int in_f64, int64_t m, int n, int k, const void* A,
   // narrow inputs (n <= 64): B = V_k^T stays in LDS, A is read once in
   // register strips
   if (!in_f64 && m > 0 && n > 0 && n <= PK && k > 0 && k <= PGC)
-    return launch_pb<float, true>(m, n, k, (const float*)A, lda, mu, VT0, (int64_t)n, Z,
-                                  (int64_t)k, st);
+    return launch_pb<float, double, true>(m, n, k, nullptr, (const float*)A, lda, mu, VT0,
+                                          (int64_t)n, Z, (int64_t)k, st);
   if (in_f64)
     return launch_tg<double, double, true>(m, n, k, nullptr, (const double*)A, lda, mu, VT0,
                                            (int64_t)n, Z, (int64_t)k, st);
@@ -379,6 +384,14 @@ hipError_t launch_rr_finish(int n, int k, const double* S0, const double* lam, d
 
 hipError_t launch_rr_form_u(int out_f64, int64_t m, int k, const double* Z, const double* M,
                             const int64_t* nr, void* U, int64_t ldu, hipStream_t st) {
+  // a narrow subspace (k <= 64): M in LDS, Z in register strips
+  if (m > 0 && k > 0 && k <= PK) {
+    if (out_f64)
+      return launch_pb<double, double, false>(m, k, k, nr, Z, (int64_t)k, nullptr, M, (int64_t)k,
+                                              (double*)U, ldu, st);
+    return launch_pb<double, float, false>(m, k, k, nr, Z, (int64_t)k, nullptr, M, (int64_t)k,
+                                           (float*)U, ldu, st);
+  }
   if (out_f64)
     return launch_tg<double, double, false>(m, k, k, nr, Z, (int64_t)k, nullptr, M, (int64_t)k,
                                             (double*)U, ldu, st);
@@ -391,8 +404,10 @@ hipError_t launch_tall_gemm_mu(int in_f64, int64_t m, int K, int nc, const void*
                                int64_t ldc, hipStream_t st) {
   if (m > 0 && K > 0 && K <= PK && nc > 0 && nc <= PGC) {
     if (in_f64)
-      return launch_pb<double, false>(m, K, nc, (const double*)A, lda, mu, B, ldb, C, ldc, st);
-    return launch_pb<float, false>(m, K, nc, (const float*)A, lda, mu, B, ldb, C, ldc, st);
+      return launch_pb<double, double, false>(m, K, nc, nullptr, (const double*)A, lda, mu, B, ldb,
+                                              C, ldc, st);
+    return launch_pb<float, double, false>(m, K, nc, nullptr, (const float*)A, lda, mu, B, ldb, C,
+                                           ldc, st);
   }
   if (in_f64)
     return launch_tg<double, double, false>(m, K, nc, nullptr, (const double*)A, lda, mu, B, ldb,
