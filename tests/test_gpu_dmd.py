@@ -122,6 +122,16 @@ def test_dmd_two_and_three_snapshots():
         assert_parity(g, o, 1e-10, 1e-8)
 
 
+def test_dmd_fewer_rows_than_a_strip():
+    # m = 12 < 16: the modes' product has one partial 16-row strip
+    rng = np.random.default_rng(26)
+    D = rng.standard_normal((12, 6))
+    say("[gpu] dmd 12 x 6")
+    o = odmd.dmd(D, r=0.0)
+    g = run_gpu(D, False, 0.0)
+    assert_parity(g, o, 1e-10, 1e-8)
+
+
 def test_dmd_empty_basis():
     say("[gpu] dmd constant field, mean removed")
     # integers: the mean of 12 equal values is exact, so Y1 = 0 exactly

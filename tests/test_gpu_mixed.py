@@ -77,6 +77,9 @@ SHAPES = [
     (200, 200, 200, False),
     (300, 1, 64, False),
     (2500, 5, 100, True),
+    # fewer rows than one 16-row strip of the refinement's register-strip
+    # products (three of the four waves have no strip)
+    (13, 5, 64, True),
 ]
 
 
