@@ -66,8 +66,9 @@ bool qr_geom(int n, int esize, QrGeom* g) {
 }
 
 size_t apply_lds_bytes(const QrGeom& g, int esize) {
-  // X (n x 17), Z (s x 17), Vp (s x 17), Tm (16 x 17), 4 partial Y + 4 own Y.
-  size_t e = (size_t)g.n * 17 + 2 * (size_t)g.s * 17 + (size_t)NB * TLD + 8 * (size_t)NB * YLD;
+  // X (n x 17), Z (s x 17), Vp (s x 17), Tm (16 x 17), 4 partial Y (each
+  // wave keeps the full Y and T Y in registers).
+  size_t e = (size_t)g.n * 17 + 2 * (size_t)g.s * 17 + (size_t)NB * TLD + 4 * (size_t)NB * YLD;
   return e * esize;
 }
 
@@ -977,10 +978,8 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
   T* Vp = Z + (size_t)s * 17;         // s x 17
   T* Tm = Vp + (size_t)s * 17;        // 16 x 17
   T* Yp = Tm + NB * TLD;              // 4 x 16 x 17 partials
-  T* Yo = Yp + 4 * NB * YLD;          // 4 x 16 x 17 per-wave Y
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i16 = lane & 15, g4 = lane >> 4;
-  T* Yw = Yo + wave * NB * YLD;
 
   int64_t rows, row0 = 0;
   const T* Vsrc;
@@ -1104,25 +1103,23 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
         if (!internal && i < kw) acc += X[(k0 + i) * 17 + i16];
         yf[q] = acc;
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * YLD + i16] = yf[q];
-      wave_lds_sync();
+      // In the FP64 16x16x4 layout, accumulator q of lane (i16, g4) holds row
+      // 4q + g4, column i16, which is exactly the B operand that lane
+      // supplies at step kb = q: Y and T Y feed the next products from
+      // registers.
+      static_assert(sizeof(T) == 8, "register operands assume the FP64 MFMA layout");
       v4 ty = vzero4<T>();
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb) {
         const int k = 4 * kb + g4;
-        ty = Mfma<T>::op(Tm[i16 * TLD + k], Yw[k * YLD + i16], ty);  // (T Y)
+        ty = Mfma<T>::op(Tm[i16 * TLD + k], yf[kb], ty);  // (T Y)
       }
-      wave_lds_sync();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * YLD + i16] = ty[q];
-      wave_lds_sync();
       for (int mt = wave; mt < ntr; mt += 4) {
         v4 u = vzero4<T>();
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
           const int k = 4 * kb + g4;
-          u = Mfma<T>::op(Vp[(16 * mt + i16) * 17 + k], Yw[k * YLD + i16], u);
+          u = Mfma<T>::op(Vp[(16 * mt + i16) * 17 + k], ty[kb], u);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) Z[(16 * mt + Mfma<T>::drow(g4, q)) * 17 + i16] -= u[q];
