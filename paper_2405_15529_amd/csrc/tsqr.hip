@@ -402,14 +402,21 @@ __device__ __forceinline__ void tile_update(T* __restrict__ C, int ldc, const T*
   T y[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) y[q] = y0[q] + y1[q] + (internal ? T(0) : head[q]);
+  // In the FP64 16x16x4 layout, accumulator q of lane (i16, g4) holds row
+  // 4q + g4, column i16: exactly the B operand that lane supplies at step
+  // kb = q, so Y and T^T Y feed the next products from registers.  The FP32
+  // layout (rows 4 g4 + q) goes through the wave's LDS tile instead.
+  constexpr bool REG = sizeof(T) == 8;
+  if (!REG) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * NB + i16] = y[q];
-  wave_lds_sync();
+    for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * NB + i16] = y[q];
+    wave_lds_sync();
+  }
   v4 z = vzero4<T>();
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb) {
     const int k = 4 * kb + g4;
-    z = Mfma<T>::op(Tm[k * NB + i16], Yw[k * NB + i16], z);  // (T^T Y)
+    z = Mfma<T>::op(Tm[k * NB + i16], REG ? y[kb] : Yw[k * NB + i16], z);  // (T^T Y)
   }
   if (!internal) {
 #pragma unroll
@@ -418,14 +425,19 @@ __device__ __forceinline__ void tile_update(T* __restrict__ C, int ldc, const T*
       if (colok && i < kw) state[(int64_t)(k0 + i) * n + col] = head[q] - z[q];
     }
   }
-  wave_lds_sync();
-#pragma unroll
-  for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * NB + i16] = z[q];
-  wave_lds_sync();
   // C(:, tile) -= V Z: the S/16 row tiles are independent accumulations
   T zb[4];
+  if (REG) {
 #pragma unroll
-  for (int kb = 0; kb < 4; ++kb) zb[kb] = Yw[(4 * kb + g4) * NB + i16];
+    for (int kb = 0; kb < 4; ++kb) zb[kb] = z[kb];
+  } else {
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Yw[(Mfma<T>::drow(g4, q)) * NB + i16] = z[q];
+    wave_lds_sync();
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) zb[kb] = Yw[(4 * kb + g4) * NB + i16];
+  }
   v4 u[S / 16];
   T a[S / 16][4];
 #pragma unroll
