@@ -56,6 +56,9 @@ extern "C" {
 #define PYLOM_ENOTSUP (-6)  /* shape outside what the kernels support        */
 #define PYLOM_ENODEV (-7)   /* no usable gfx950 device                       */
 #define PYLOM_WNOCONV 1     /* Jacobi SVD hit max_sweeps before converging   */
+#define PYLOM_WNONFINITE 2  /* a singular value is NaN or Inf: the input held
+                               a non-finite value (outputs are written, and
+                               hold NaN or Inf)                             */
 
 /* ---- storage types ---- */
 typedef enum {
@@ -112,6 +115,12 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
  *                  working copy of D, the reflectors of every panel and the
  *                  tree pairs stay in the workspace.  The stacked QR factors
  *                  at most 1024 columns.
+ * Read-only (pylom_get_option):
+ *   "batch_jacobi_chained"  1 if the last pylom_pod_batched call ordered its
+ *                  multi-workgroup Jacobi launches one after another across
+ *                  streams (their grid barriers need every workgroup resident;
+ *                  the batch chains them when the largest Jacobi grid of each
+ *                  stream would not fit on the device together), else 0.
  * Unknown keys return PYLOM_EINVAL. */
 int pylom_set_option(pylom_ctx ctx, const char* key, int64_t value);
 int pylom_get_option(pylom_ctx ctx, const char* key, int64_t* value);
@@ -338,8 +347,10 @@ int pylom_plan_query(pylom_ctx ctx, int64_t m, int64_t n, int64_t* leaves, int64
 int pylom_phase_times(pylom_ctx ctx, double* out, int cap);
 
 /* After a stream synchronisation: the deferred numerical status of the last
- * pod/tsvd/dmd call on this context (0 or PYLOM_WNOCONV) and its sweep count.
- * Synchronises the context's stream. */
+ * pod/tsvd/spod/dmd/batched call on this context (0, PYLOM_WNOCONV, or
+ * PYLOM_WNONFINITE, which takes precedence) and its sweep count.  A grid
+ * barrier that timed out returns PYLOM_EHIP.  Synchronises the context's
+ * stream. */
 int pylom_check(pylom_ctx ctx, int64_t* sweeps);
 
 #ifdef __cplusplus

@@ -10,7 +10,10 @@ Alg. 4 (matmul), Eqs. svdqr1-svdqr3.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import sys
+import weakref
 from dataclasses import dataclass
 
 import torch
@@ -21,7 +24,7 @@ R32, R64, C64, C128 = 1, 2, 3, 4
 FP64, MIXED = 0, 1
 _PREC = {"fp64": FP64, "mixed": MIXED}
 
-OK, WNOCONV = 0, 1
+OK, WNOCONV, WNONFINITE = 0, 1, 2
 
 
 class PylomError(RuntimeError):
@@ -47,6 +50,28 @@ def _rowmajor(t: torch.Tensor, name: str):
         raise ValueError(f"{name} must be a 2-D row-major tensor (stride(1) == 1)")
 
 
+def _on_gpu(t: torch.Tensor, name: str):
+    # a host pointer handed to the kernels would be a GPU page fault
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+
+
+# Every open context, so that all are closed by an exit hook while the HIP
+# runtime (and any profiler attached to it) is still alive: a context left to
+# the garbage collector at interpreter shutdown would destroy its graphs,
+# streams and workspace after the runtime has been torn down.
+_live = weakref.WeakSet()
+
+
+def close_all():
+    """Close every open context (registered as an exit hook)."""
+    for c in list(_live):
+        c.close()
+
+
+atexit.register(close_all)
+
+
 class Context:
     """A library context (device workspace + options).  device=-1 creates a
     host-only context: it validates arguments and plans, but runs nothing."""
@@ -59,13 +84,22 @@ class Context:
             raise PylomError(rc, self.lib.pylom_strerror(rc).decode())
         self.h = h
         self.device = device
+        _live.add(self)
 
     def close(self):
         if getattr(self, "h", None):
             self.lib.pylom_destroy(self.h)
             self.h = None
+        dev = getattr(self, "device", None)
+        if _contexts.get(dev) is self:
+            del _contexts[dev]
 
-    def __del__(self):  # pragma: no cover - interpreter shutdown order
+    def __del__(self, _finalizing=sys.is_finalizing):  # pragma: no cover - shutdown order
+        # at shutdown the exit hook has already closed every context; never
+        # call into the runtime from a finalising interpreter (whose module
+        # globals may already be gone, hence the bound default)
+        if _finalizing() or not getattr(self, "h", None):
+            return
         try:
             self.close()
         except Exception:
@@ -145,8 +179,7 @@ def pod(D: torch.Tensor, remove_mean: bool = True, r: float = 0.01, precision: s
         ctx: Context | None = None, sync: bool = True) -> PodResult:
     """POD of the snapshot matrix D (m x n, rows = points): Alg. 2 + Alg. 1."""
     _rowmajor(D, "D")
-    if not D.is_cuda:
-        raise ValueError("D must be a GPU tensor")
+    _on_gpu(D, "D")
     ctx = ctx or context(D.device.index)
     m, n = D.shape
     dev = D.device
@@ -168,6 +201,7 @@ def tsvd(A: torch.Tensor, r: float = 0.01, precision: str = "fp64", ctx: Context
          sync: bool = True) -> PodResult:
     """Tall-skinny SVD without mean removal."""
     _rowmajor(A, "A")
+    _on_gpu(A, "A")
     ctx = ctx or context(A.device.index)
     m, n = A.shape
     dev = A.device
@@ -186,6 +220,7 @@ def tsvd(A: torch.Tensor, r: float = 0.01, precision: str = "fp64", ctx: Context
 def tsqr(A: torch.Tensor, want_q: bool = True, ctx: Context | None = None):
     """TSQR (Alg. 1): returns (Q or None, R) with diag(R) >= 0."""
     _rowmajor(A, "A")
+    _on_gpu(A, "A")
     ctx = ctx or context(A.device.index)
     m, n = A.shape
     Q = torch.empty((m, n), dtype=A.dtype, device=A.device) if want_q else None
@@ -201,6 +236,8 @@ def matmul(A: torch.Tensor, B: torch.Tensor, trans_a: bool, ctx: Context | None 
     """Alg. 4 on one GPU: A^T B (trans_a) or A B."""
     _rowmajor(A, "A")
     _rowmajor(B, "B")
+    _on_gpu(A, "A")
+    _on_gpu(B, "B")
     if A.dtype != B.dtype:
         raise TypeError("A and B must have the same dtype")
     ctx = ctx or context(A.device.index)

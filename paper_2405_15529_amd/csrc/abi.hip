@@ -48,12 +48,31 @@ struct pylom_ctx_s {
   std::vector<hipEvent_t> ev_join;
   hipStream_t cap = nullptr;     // origin stream of graph capture and replay
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  std::unordered_map<uint64_t, hipGraphExec_t> graphs;  // captured batches
+  // captured batches: key -> (graph, last use); at most kMaxGraphs are kept,
+  // the least recently used is destroyed first
+  std::unordered_map<uint64_t, std::pair<hipGraphExec_t, uint64_t>> graphs;
+  uint64_t graph_clock = 0;
+  // ordering of the multi-workgroup Jacobi launches of a batch across lanes
+  // when their workgroups could not all be resident together
+  std::vector<hipEvent_t> jac_ev;
+  int64_t last_jac_chain = 0;  // whether the last batched call chained them
 };
 
 static void drop_graphs(pylom_ctx c) {
-  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second.first);
   c->graphs.clear();
+}
+
+constexpr size_t kMaxGraphs = 16;  // captured batch graphs kept per context
+
+static void evict_graphs(pylom_ctx c) {
+  while (c->graphs.size() >= kMaxGraphs) {
+    auto old = c->graphs.begin();
+    for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it)
+      if (it->second.second < old->second.second) old = it;
+    hipGraphExecDestroy(old->second.first);
+    c->graphs.erase(old);
+  }
 }
 
 static int fail(pylom_ctx c, int code, const char* msg) {
@@ -125,6 +144,7 @@ extern "C" int pylom_destroy(pylom_ctx c) {
     drop_graphs(c);
     for (hipStream_t q : c->lanes) hipStreamDestroy(q);
     for (hipEvent_t e : c->ev_join) hipEventDestroy(e);
+    for (hipEvent_t e : c->jac_ev) hipEventDestroy(e);
     if (c->ev_fork) hipEventDestroy(c->ev_fork);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
@@ -157,11 +177,11 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
     c->ws_cap_mb = v;
   } else if (!std::strcmp(key, "narrow_leaves")) {
     if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "narrow_leaves must be 0 or 1");
-    c->narrow_leaves = v;
+    c->narrow_leaves = v;  // part of every batch graph key
   } else if (!std::strcmp(key, "blocked_from")) {
     if (v != 0 && (v < 2 || v > kMaxN + 1))
       return fail(c, PYLOM_EINVAL, "blocked_from must be 0 or in [2, 2049]");
-    c->blocked_from = v;
+    c->blocked_from = v;  // part of every batch graph key
   } else if (!std::strcmp(key, "streams")) {
     if (v < 1 || v > 16) return fail(c, PYLOM_EINVAL, "streams must be in [1, 16]");
     c->streams = v;
@@ -201,6 +221,8 @@ extern "C" int pylom_get_option(pylom_ctx c, const char* key, int64_t* v) {
     *v = c->timing;
   else if (!std::strcmp(key, "streams"))
     *v = c->streams;
+  else if (!std::strcmp(key, "batch_jacobi_chained"))
+    *v = c->last_jac_chain;
   else
     return fail(c, PYLOM_EINVAL, "unknown option");
   return PYLOM_OK;
@@ -217,6 +239,7 @@ extern "C" const char* pylom_strerror(int s) {
     case PYLOM_ENOTSUP: return "shape not supported by the kernels";
     case PYLOM_ENODEV: return "no usable gfx950 device";
     case PYLOM_WNOCONV: return "Jacobi SVD did not converge within max_sweeps";
+    case PYLOM_WNONFINITE: return "a singular value is not finite (non-finite input)";
     default: return "unknown status";
   }
 }
@@ -245,6 +268,14 @@ static int ensure_ws(pylom_ctx c, size_t bytes) {
     return fail(c, PYLOM_ENOMEM, "hipMalloc of the workspace failed");
   }
   c->ws_bytes = bytes;
+  return PYLOM_OK;
+}
+
+// The workspace cap is checked with the plan, before anything else needs a
+// device, so that an over-cap call fails the same way on every context.
+static int cap_check(pylom_ctx c, size_t bytes) {
+  if (c->ws_cap_mb > 0 && bytes > (size_t)c->ws_cap_mb * (1u << 20))
+    return fail(c, PYLOM_ENOMEM, "workspace over ws_cap_mb");
   return PYLOM_OK;
 }
 
@@ -641,7 +672,35 @@ struct Exec {
   int64_t* nr0;         // mixed precision: where N0 goes (nullptr: the workspace)
   char* keep;           // mixed precision: S0, VT0 and the mean, kept from phase 1 to
                         // phase 2 (nullptr: the workspace); layout keep_bytes()
+  hipEvent_t* jac_ev;   // batch: events that chain the multi-workgroup Jacobi
+  int64_t* jac_next;    //   launches across lanes (nullptr: no chaining)
 };
+
+// A batch whose lanes could run more Jacobi workgroups at once than the
+// device holds chains every multi-workgroup Jacobi launch after the previous
+// one (in instance order, so the chain never points backwards in any lane):
+// the grid barrier of each then waits only for workgroups that can be placed.
+static int jac_before(pylom_ctx c, const Exec& x, const JacobiPlan& jp) {
+  if (!x.jac_ev || jp.G <= 1 || *x.jac_next == 0) return PYLOM_OK;
+  HIPCHK(c, hipStreamWaitEvent(x.st, x.jac_ev[*x.jac_next - 1], 0), "hipStreamWaitEvent");
+  return PYLOM_OK;
+}
+static int jac_after(pylom_ctx c, const Exec& x, const JacobiPlan& jp) {
+  if (!x.jac_ev || jp.G <= 1) return PYLOM_OK;
+  HIPCHK(c, hipEventRecord(x.jac_ev[*x.jac_next], x.st), "hipEventRecord");
+  ++*x.jac_next;
+  return PYLOM_OK;
+}
+#define JAC_BEFORE(jp)                         \
+  do {                                         \
+    const int _r = jac_before(c, x, (jp));     \
+    if (_r) return _r;                         \
+  } while (0)
+#define JAC_AFTER(jp)                          \
+  do {                                         \
+    const int _r = jac_after(c, x, (jp));      \
+    if (_r) return _r;                         \
+  } while (0)
 
 // Phase-1 results of the mixed path that phase 2 reads: S0 (n), VT0 (n x n),
 // mean (m), each 256-byte aligned.
@@ -694,8 +753,10 @@ static int enqueue_fp64(pylom_ctx c, const Exec& x, const Plan& p, pylom_dtype d
   for (int64_t h = 1; h < p.P; h *= 2)
     HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, 1, st), "tree combine");
   EVREC(3);
+  JAC_BEFORE(p.jp);
   HIPCHK(c, launch_small_svd(p.jp, Rbuf, x.max_sweeps, x.ws + p.oSvd, S, VT, ldvt, W, residual,
                              n_r, x.status, st, x.coop), "small SVD");
+  JAC_AFTER(p.jp);
   EVREC(4);
   int64_t top = 1;
   while (top * 2 < p.P) top *= 2;
@@ -876,9 +937,11 @@ static int enqueue_fp64_blocked(pylom_ctx c, const Exec& x, const Plan& p, pylom
   rc = blocked_tree(c, st, p, x.ws);
   if (rc) return rc;
   EVREC(3);
+  JAC_BEFORE(p.jp);
   HIPCHK(c, launch_small_svd(p.jp, Rbuf, x.max_sweeps, x.ws + p.oSvd, S, VT, ldvt,
                              (double*)(x.ws + p.oW), residual, n_r, x.status, st, x.coop),
          "small SVD");
+  JAC_AFTER(p.jp);
   EVREC(4);
   rc = blocked_propagate(c, st, p, x.ws, n_r, n);
   if (rc) return rc;
@@ -906,10 +969,12 @@ static int enqueue_mixed1_blocked(pylom_ctx c, const Exec& x, const Plan& p, con
   rc = blocked_tree(c, st, p, x.ws);
   if (rc) return rc;
   EVREC(3);
+  JAC_BEFORE(p.jp);
   HIPCHK(c, launch_small_svd(p.jp, (double*)(x.ws + p.oR), x.max_sweeps, x.ws + p.oSvd,
                              keep_S0(x, p), keep_VT0(x, p), n, (double*)(x.ws + p.oW), residual,
                              x.nr0 ? x.nr0 : (int64_t*)(x.ws + p.oNr0), x.status, st, x.coop),
          "small SVD");
+  JAC_AFTER(p.jp);
   if (x.evs) HIPCHK(c, hipEventRecord(x.evs[7], st), "hipEventRecord");
   return PYLOM_OK;
 }
@@ -933,11 +998,13 @@ static int enqueue_mixed1(pylom_ctx c, const Exec& x, const Plan& p, const void*
     HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, (double*)(x.ws + p.oR), nullptr, p.nch_tree, 0,
                                       st), "tree combine");
   EVREC(3);
+  JAC_BEFORE(p.jp);
   HIPCHK(c, launch_small_svd(p.jp, (double*)(x.ws + p.oR), x.max_sweeps, x.ws + p.oSvd,
                              keep_S0(x, p), keep_VT0(x, p), n,
                              (double*)(x.ws + p.oW), residual,
                              x.nr0 ? x.nr0 : (int64_t*)(x.ws + p.oNr0), x.status, st, x.coop),
          "small SVD");
+  JAC_AFTER(p.jp);
   // end of the first SVD (the host read-back of N0 follows)
   if (x.evs) HIPCHK(c, hipEventRecord(x.evs[7], st), "hipEventRecord");
   return PYLOM_OK;
@@ -985,9 +1052,11 @@ static int enqueue_mixed2(pylom_ctx c, const Exec& x, const Plan& p, const void*
                                 Z, st), "Rayleigh-Ritz projection");
     HIPCHK(c, launch_matmul_tn(1, m, k, k, Z, k, Z, k, G, k, (double*)(x.ws + p.oPart), ns, st),
            "Gram");
+    JAC_BEFORE(jk);
     HIPCHK(c, launch_small_svd(jk, G, x.max_sweeps, x.ws + p.oSvd2, lam, WT, k,
                                (double*)(x.ws + p.oUR2), 0.0, (int64_t*)(x.ws + p.oNr2),
                                x.status + 2, st, x.coop), "Gram eigen-decomposition");
+    JAC_AFTER(jk);
     HIPCHK(c, launch_rr_finish((int)n, (int)k, S0, lam, residual, S, n_r, WT, VT0, VT, ldvt, M,
                                st), "refined spectrum");
     EVREC(5);
@@ -1010,6 +1079,8 @@ static Exec ctx_exec(pylom_ctx c) {
   x.evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * kEvPerSlot] : nullptr;
   x.nr0 = nullptr;
   x.keep = nullptr;
+  x.jac_ev = nullptr;
+  x.jac_next = nullptr;
   return x;
 }
 
@@ -1024,6 +1095,7 @@ static int run_mixed(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, const
   Plan p;
   int rc = make_plan(c, m, n, false, &p, true);
   if (rc) return rc;
+  if ((rc = cap_check(c, p.total))) return rc;
   if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
   HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
   rc = ensure_ws(c, p.total);
@@ -1060,6 +1132,7 @@ static int run_tsvd(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, 
   Plan p;
   rc = make_plan(c, m, n, true, &p);
   if (rc) return rc;
+  if ((rc = cap_check(c, p.total))) return rc;
   if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
   HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
   rc = ensure_ws(c, p.total);
@@ -1103,6 +1176,7 @@ static int ensure_lanes(pylom_ctx c, int64_t k) {
 }
 
 struct BatchLayout {
+  bool jac_chain = false;         // chain the multi-workgroup Jacobi launches (jac_before)
   std::vector<Plan> plans;
   std::vector<int> lane;          // lane of each problem
   std::vector<size_t> lane_off;   // workspace offset of each lane
@@ -1117,6 +1191,7 @@ static int batch_phase(pylom_ctx c, const BatchLayout& L, pylom_dtype dtype, int
                        int64_t count, const pylom_problem* pr, const int64_t* nr_first,
                        bool capturing, hipStream_t origin) {
   char* ws = (char*)c->ws;
+  int64_t jac_next = 0;
   HIPCHK(c, hipEventRecord(c->ev_fork, origin), "hipEventRecord");
   for (int64_t l = 0; l < L.K; ++l)
     HIPCHK(c, hipStreamWaitEvent(c->lanes[l], c->ev_fork, 0), "hipStreamWaitEvent");
@@ -1131,6 +1206,8 @@ static int batch_phase(pylom_ctx c, const BatchLayout& L, pylom_dtype dtype, int
     x.evs = nullptr;
     x.nr0 = (int64_t*)(ws + L.oNr0) + i;
     x.keep = L.keep_off.empty() ? nullptr : ws + L.keep_off[(size_t)i];
+    x.jac_ev = L.jac_chain ? c->jac_ev.data() : nullptr;
+    x.jac_next = L.jac_chain ? &jac_next : nullptr;
     const pylom_problem& q = pr[i];
     int rc;
     if (phase == 0)
@@ -1165,6 +1242,7 @@ static int batch_run(pylom_ctx c, const BatchLayout& L, pylom_dtype dtype, int p
   // caller's stream may be the legacy null stream, which cannot be captured)
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
+    evict_graphs(c);
     HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
     const int rc = batch_phase(c, L, dtype, phase, count, pr, nr_first, true, c->cap);
     hipGraph_t g = nullptr;
@@ -1178,11 +1256,12 @@ static int batch_run(pylom_ctx c, const BatchLayout& L, pylom_dtype dtype, int p
     const hipError_t e2 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
     if (e2 != hipSuccess) return hip_fail(c, e2, "hipGraphInstantiate");
-    it = c->graphs.emplace(key, ge).first;
+    it = c->graphs.emplace(key, std::make_pair(ge, (uint64_t)0)).first;
   }
+  it->second.second = ++c->graph_clock;
   HIPCHK(c, hipEventRecord(c->ev_in, c->stream), "hipEventRecord");
   HIPCHK(c, hipStreamWaitEvent(c->cap, c->ev_in, 0), "hipStreamWaitEvent");
-  HIPCHK(c, hipGraphLaunch(it->second, c->cap), "hipGraphLaunch");
+  HIPCHK(c, hipGraphLaunch(it->second.first, c->cap), "hipGraphLaunch");
   HIPCHK(c, hipEventRecord(c->ev_out, c->cap), "hipEventRecord");
   HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_out, 0), "hipStreamWaitEvent");
   return PYLOM_OK;
@@ -1215,8 +1294,6 @@ extern "C" int pylom_pod_batched(pylom_ctx c, pylom_dtype dtype, pylom_prec prec
     cost[(size_t)i] = leaf_model(c, q.m, q.n, L.plans[(size_t)i].b, mixed);
   }
   if (count == 0) return PYLOM_OK;
-  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
-  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
   // longest-processing-time assignment of instances to lanes
   L.K = std::min<int64_t>(c->streams, count);
   L.lane.assign((size_t)count, 0);
@@ -1254,18 +1331,60 @@ extern "C" int pylom_pod_batched(pylom_ctx c, pylom_dtype dtype, pylom_prec prec
     }
   }
   L.total = off;
+  if ((rc = cap_check(c, L.total))) return rc;
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+  // Co-residency of the grid-barrier Jacobi: lanes run concurrently, so the
+  // largest Jacobi grid of each lane may be live at once; when their sum
+  // exceeds what the device holds, the Jacobi launches are chained instead.
+  {
+    std::vector<int64_t> lane_g((size_t)L.K, 0);
+    int64_t per_cu = 1 << 20;
+    for (int64_t i = 0; i < count; ++i) {
+      const JacobiPlan& jp = L.plans[(size_t)i].jp;
+      lane_g[(size_t)L.lane[(size_t)i]] = std::max<int64_t>(lane_g[(size_t)L.lane[(size_t)i]], jp.G);
+      if (jp.G > 1) per_cu = std::min<int64_t>(per_cu, jacobi_resident_per_cu(jp));
+    }
+    int64_t gsum = 0;
+    for (int64_t g : lane_g) gsum += (g > 1) ? g : 0;
+    if (per_cu == (1 << 20)) per_cu = 1;
+    L.jac_chain = L.K > 1 && gsum > (int64_t)c->ncu * std::max<int64_t>(per_cu, 1);
+    c->last_jac_chain = L.jac_chain ? 1 : 0;
+  }
   rc = ensure_ws(c, L.total);
   if (rc) return rc;
   rc = ensure_lanes(c, L.K);
   if (rc) return rc;
-  // graph key: everything the captured launches depend on
+  if (L.jac_chain) {
+    const size_t need = 2 * (size_t)count;
+    while (c->jac_ev.size() < need) {
+      hipEvent_t e = nullptr;
+      HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+      c->jac_ev.push_back(e);
+    }
+  }
+  // graph key: everything the captured launches depend on, field by field
+  // (never the raw descriptor bytes, whose padding a C caller may leave
+  // uninitialised)
   uint64_t key = 1469598103934665603ull;
-  const int64_t hdr[6] = {(int64_t)dtype, (int64_t)prec, count, L.K, c->max_sweeps, c->block_rows};
+  const int64_t hdr[9] = {(int64_t)dtype, (int64_t)prec, count,           L.K,
+                          c->max_sweeps,  c->block_rows, c->narrow_leaves, c->blocked_from,
+                          L.jac_chain ? 1 : 0};
   key = fnv1a(key, hdr, sizeof(hdr));
   const void* wsp = c->ws;
   key = fnv1a(key, &wsp, sizeof(wsp));
   key = fnv1a(key, &c->stream, sizeof(c->stream));
-  key = fnv1a(key, pr, sizeof(pylom_problem) * (size_t)count);
+  for (int64_t i = 0; i < count; ++i) {
+    const pylom_problem& q = pr[i];
+    int64_t rbits;
+    std::memcpy(&rbits, &q.residual, sizeof(rbits));
+    const int64_t f[14] = {q.m,         q.n,           (int64_t)(uintptr_t)q.D,    q.ldd,
+                           q.remove_mean ? 1 : 0,      rbits,
+                           (int64_t)(uintptr_t)q.mean, (int64_t)(uintptr_t)q.U,    q.ldu,
+                           (int64_t)(uintptr_t)q.S,    (int64_t)(uintptr_t)q.VT,   q.ldvt,
+                           (int64_t)(uintptr_t)q.n_r,  0};
+    key = fnv1a(key, f, sizeof(f));
+  }
   c->status_valid = 1;
   c->status_pairs = 1;
   if (!mixed)
@@ -1305,6 +1424,7 @@ extern "C" int pylom_tsqr(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64
   Plan p;
   rc = make_plan(c, m, n, Q != nullptr, &p);
   if (rc) return rc;
+  if ((rc = cap_check(c, p.total))) return rc;
   if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
   HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
   rc = ensure_ws(c, p.total);
@@ -1481,6 +1601,7 @@ extern "C" int pylom_dmd(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, c
   DmdLayout L;
   rc = make_dmd_layout(c, m, n, &p, &jp1, &L);
   if (rc) return rc;
+  if ((rc = cap_check(c, L.total))) return rc;
   if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
   HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
   rc = ensure_ws(c, L.total);
@@ -1670,6 +1791,7 @@ extern "C" int pylom_spod(pylom_ctx c, pylom_dtype spectra, pylom_prec prec, int
   SpodPlan p;
   int rc = make_spod_plan(c, spectra, m, nt, npwin, nolap, &p);
   if (rc) return rc;
+  if ((rc = cap_check(c, p.total))) return rc;
   if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
   HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
   rc = ensure_ws(c, p.total);
@@ -1785,6 +1907,10 @@ extern "C" int pylom_check(pylom_ctx c, int64_t* sweeps) {
   if (sweeps) *sweeps = st[0];
   for (int k = 0; k < c->status_pairs; ++k) {
     if (st[2 * k + 1]) return fail(c, PYLOM_EHIP, "Jacobi grid barrier timed out");
+    if (st[2 * k] == -2)
+      return fail(c, PYLOM_WNONFINITE, "a singular value is not finite (non-finite input)");
+  }
+  for (int k = 0; k < c->status_pairs; ++k) {
     if (st[2 * k] < 0)
       return fail(c, PYLOM_WNOCONV,
                   k == 0 ? "Jacobi SVD did not converge"

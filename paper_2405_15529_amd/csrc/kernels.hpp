@@ -121,10 +121,14 @@ struct JacobiPlan {
 };
 bool jacobi_plan(int n, JacobiPlan* p);
 size_t jacobi_ws_bytes(const JacobiPlan& p, int max_sweeps);
+// Workgroups of this plan's Jacobi kernel that one CU holds at once (the
+// occupancy query; 1 if it fails).
+int jacobi_resident_per_cu(const JacobiPlan& p);
 // Full SVD of R (n x n row-major, FP64) into S (n, descending), VT (n x n
 // row-major, ldvt), UR (n x n row-major, ld n; the left factor, sign
 // convention applied) and N_r (device) for residual r; status[0] = sweeps
-// (-1 if not converged), status[1] = barrier timeout flag.
+// (-1 if not converged, -2 if a singular value is not finite: a non-finite
+// input), status[1] = barrier timeout flag.
 // coop = false uses a plain launch (for stream capture).
 hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps, void* ws,
                             double* S, double* VT, int64_t ldvt, double* UR, double residual,
@@ -133,7 +137,8 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
 // Same for `count` problems of one size n <= 32 (one workgroup each; G == 1):
 // problem k reads R + k*sR, uses the workspace slice ws + k*jacobi_ws_stride,
 // writes S + k*sS, VT + k*sVT, UR + k*sUR, nr[k] and status_each[2k..2k+1];
-// status[0..1] receives the reduced status (max sweeps or -1, timeout flag).
+// status[0..1] receives the reduced status (max sweeps, or the lowest
+// negative code, -2 before -1; timeout flag).
 size_t jacobi_ws_stride(const JacobiPlan& p, int max_sweeps);
 hipError_t launch_small_svd_batched(const JacobiPlan& p, int64_t count, const double* R,
                                     int64_t sR, int max_sweeps, void* ws, double* S, int64_t sS,

@@ -414,12 +414,16 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
 // A holds W (columns w_j, sigma_j = |w_j|, v_j = w_j / sigma_j); V holds J
 // (u_j = column j).  Each pair is signed so that the largest-magnitude entry
 // of v_j (lowest index on ties) is positive.  A zero sigma leaves v_j = 0.
+// A singular value that is not finite (NaN or Inf in the input propagates
+// into R, and the Jacobi rotates no pair whose norms are not positive) sets
+// status[0] = -2.
 constexpr int FT = 1024;
 __global__ __launch_bounds__(FT) void k_svd_finalize(int n, const double* __restrict__ A,
                                                      const double* __restrict__ V, double* S,
                                                      double* VT, int64_t ldvt, double* UR,
                                                      double residual, int64_t* nr, int64_t sWs,
-                                                     int64_t sS, int64_t sVT, int64_t sUR) {
+                                                     int64_t sS, int64_t sVT, int64_t sUR,
+                                                     int* status) {
   if (blockIdx.y) {
     const int64_t pb = blockIdx.y;
     A = (const double*)((const char*)A + pb * sWs);
@@ -428,7 +432,10 @@ __global__ __launch_bounds__(FT) void k_svd_finalize(int n, const double* __rest
     VT += pb * sVT;
     UR += pb * sUR;
     nr += pb;
+    status += 2 * pb;
   }
+  __shared__ int nonfinite;
+  if (threadIdx.x == 0) nonfinite = 0;
   __shared__ double sig[2048];
   __shared__ double sgn[2048];
   __shared__ int rank[2048];
@@ -449,8 +456,10 @@ __global__ __launch_bounds__(FT) void k_svd_finalize(int n, const double* __rest
     }
     sig[j] = sqrt(x);
     sgn[j] = (col[arg] < 0.0) ? -1.0 : 1.0;
+    if (!isfinite(sig[j])) nonfinite = 1;
   }
   __syncthreads();
+  if (threadIdx.x == 0 && nonfinite) status[0] = -2;
   for (int j = tid; j < n; j += FT) {
     const double sj = sig[j];
     int r = 0;
@@ -496,7 +505,7 @@ __global__ void k_svd_one(const double* R, double* S, double* VT, double* UR, do
   VT[0] = 1.0;
   UR[0] = (r < 0.0) ? -1.0 : 1.0;
   *nr = (residual > 0.0 && r == 0.0) ? 0 : 1;
-  status[0] = 1;
+  status[0] = isfinite(r) ? 1 : -2;
   status[1] = 0;
 }
 
@@ -532,17 +541,38 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
     if (coop && p.G > 1) {
       e = hipLaunchCooperativeKernel(fn, grid, block, args, 0, st);
     } else {
-      // plain launch (one working group, or inside stream capture): the
-      // G <= 32 working groups fit on distinct CUs once earlier work on the
-      // stream has drained, and the bounded-spin barrier turns a failure to
-      // co-reside into an error flag, never a hang
+      // plain launch (one workgroup, or inside stream capture, where a
+      // cooperative launch cannot be recorded).  The G workgroups (up to
+      // 226 at n = 2048, one per CU: the kernel holds 128 KB of LDS) become
+      // resident as earlier work drains, since nothing else they wait for
+      // holds a CU; the batched call chains its Jacobi launches across lanes
+      // whenever their grids could not all be resident together.  Should
+      // co-residency fail anyway, the bounded-spin barrier sets the error
+      // flag (PYLOM_EHIP from pylom_check) instead of hanging.
       e = hipLaunchKernel(fn, grid, block, args, 0, st);
     }
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_svd_finalize, dim3(1), dim3(FT), 0, st, p.n, w.A, w.V, S, VT, ldvt, UR,
-                     residual, nr, (int64_t)0, (int64_t)0, (int64_t)0, (int64_t)0);
+                     residual, nr, (int64_t)0, (int64_t)0, (int64_t)0, (int64_t)0, status);
   return hipGetLastError();
+}
+
+int jacobi_resident_per_cu(const JacobiPlan& p) {
+  const void* fn = nullptr;
+  const bool wide = (p.n + p.lpp - 1) / p.lpp > 16;
+  switch (p.lpp) {
+    case 16: fn = (const void*)k_jacobi<16, 16>; break;
+    case 32: fn = (const void*)k_jacobi<32, 16>; break;
+    case 64: fn = wide ? (const void*)k_jacobi<64, 32> : (const void*)k_jacobi<64, 16>; break;
+    default: return 1;
+  }
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, JT, 0) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return nb;
 }
 
 size_t jacobi_ws_stride(const JacobiPlan& p, int max_sweeps) {
@@ -563,14 +593,14 @@ __global__ void k_status_reduce(int64_t count, const int* __restrict__ st, int s
   for (int64_t k = threadIdx.x; k < count; k += blockDim.x) {
     for (int q = 0; q < pairs; ++q) {
       const int sw = st[k * stride + 2 * q];
-      if (sw < 0) atomicOr(&sneg, 1);
+      if (sw < 0) atomicMin(&sneg, sw);
       else atomicMax(&smax, sw);
       if (st[k * stride + 2 * q + 1]) atomicOr(&stmo, 1);
     }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    out[0] = sneg ? -1 : smax;
+    out[0] = sneg ? sneg : smax;
     out[1] = stmo;
   }
 }
@@ -610,7 +640,7 @@ hipError_t launch_small_svd_batched(const JacobiPlan& p, int64_t count, const do
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_svd_finalize, dim3(1, (unsigned)count), dim3(FT), 0, st, p.n, w.A, w.V, S,
-                     VT, ldvt, UR, residual, nr, wsb, sS, sVT, sUR);
+                     VT, ldvt, UR, residual, nr, wsb, sS, sVT, sUR, status_each);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_status_reduce, dim3(1), dim3(256), 0, st, count, status_each, 2, 1, status);

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror_names_every_code():
     lib = _lib.load()
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, 1):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, 1, 2):
         assert lib.pylom_strerror(code).decode() not in ("", "unknown status")
     assert lib.pylom_strerror(12345).decode() == "unknown status"
 
@@ -314,3 +314,46 @@ def test_dmd_validation_before_device(hctx):
     assert lib.pylom_dmd_workspace_query(h, api.R64, 58_300_000, 56, 0, ctypes.byref(b)) == 0
     # an R-only TSQR of the snapshots plus O(n^2): far below the 26 GB input
     assert 0 < b.value < 8 * 58_300_000 * 56
+
+
+def test_workspace_cap_returns_enomem(hctx):
+    # the cap is checked with the plan, before the device: a host-only
+    # context reports PYLOM_ENOMEM for a call whose workspace exceeds it
+    need = hctx.workspace_bytes(100000, 64)
+    hctx.set_option("ws_cap_mb", max(1, need // (1 << 20) // 2))
+    assert _pod(hctx, m=100000, n=64) == -4
+    assert "ws_cap_mb" in hctx.lib.pylom_last_error(hctx.h).decode()
+    assert _pod(hctx, dtype=api.R32, prec=api.MIXED, m=100000, n=64) == -4
+    vp = ctypes.c_void_p
+    R = ctypes.c_void_p(1)
+    assert hctx.lib.pylom_tsqr(hctx.h, api.R64, api.FP64, 100000, 64, vp(1), 64, vp(1), 64, R,
+                               64) == -4
+    hctx.set_option("ws_cap_mb", 1 << 30)   # large enough: only the device is missing
+    assert _pod(hctx, m=100000, n=64) == -7
+    hctx.set_option("ws_cap_mb", 0)         # 0 = unlimited
+    assert _pod(hctx, m=100000, n=64) == -7
+
+
+def test_batched_workspace_cap(hctx):
+    arr = (_lib.Problem * 2)()
+    for i in range(2):
+        arr[i] = _lib.Problem(50000, 40, 1, 40, 0, 0.01, 0, 1, 40, 1, 1, 40, 1)
+    hctx.set_option("ws_cap_mb", 1)
+    assert hctx.lib.pylom_pod_batched(hctx.h, api.R64, api.FP64, 2,
+                                      ctypes.cast(arr, ctypes.c_void_p), 0) == -4
+    hctx.set_option("ws_cap_mb", 0)
+    assert hctx.lib.pylom_pod_batched(hctx.h, api.R64, api.FP64, 2,
+                                      ctypes.cast(arr, ctypes.c_void_p), 0) == -7
+
+
+def test_binding_rejects_host_tensors():
+    # a host pointer handed to the kernels would be a GPU page fault: every
+    # entry of the binding refuses CPU tensors before calling the library
+    import torch
+    A = torch.zeros((64, 8), dtype=torch.float64)
+    B = torch.zeros((64, 4), dtype=torch.float64)
+    for call in (lambda: api.pod(A), lambda: api.tsvd(A), lambda: api.tsqr(A),
+                 lambda: api.matmul(A, B, trans_a=True), lambda: api.dmd(A),
+                 lambda: api.spod(A.float())):
+        with pytest.raises(ValueError):
+            call()

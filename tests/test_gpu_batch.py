@@ -47,7 +47,7 @@ def check_instance(g, ref, r, mixed):
     S = g.S.cpu().numpy()
     rel, nw = checks.sigma_errors(S, ref["S"], k)
     assert rel <= (1e-6 if mixed else 1e-12), rel
-    U = g.U_full.cpu().numpy().astype(np.float64)
+    U = g.U_full[:, :g.nr].cpu().numpy().astype(np.float64)
     VT = g.VT_full.cpu().numpy()
     live = [i for i in range(k) if ref["S"][i] > 1e3 * len(ref["S"]) * checks.EPS64 * ref["S"][0]]
     if live:
@@ -104,4 +104,45 @@ def test_batched_reports_nonconvergence():
     api.PodBatch(Ds, r=0.05, use_graph=False, ctx=ctx).run()
     rc, sweeps = ctx.status()
     assert rc == api.WNOCONV and sweeps == -1
+    ctx.close()
+
+
+def test_batched_wide_jacobi_grids_are_chained():
+    # three instances with n = 600, 1000, 700 on three streams: their Jacobi
+    # grids (G = n / 8 workgroups of one CU each) sum to 288 > 256 CUs, so the
+    # batch must order them one after another (never a barrier timeout);
+    # checked against the exact spectra, eagerly and through the graph
+    import torch
+    from paper_2405_15529_amd import api, synth
+    shapes = [(2400, 600), (3000, 1000), (2100, 700)]
+    say(f"[gpu] batched wide Jacobi chaining {shapes}")
+    Ds, specs = [], []
+    for i, (m, n) in enumerate(shapes):
+        s = 10.0 ** (-np.arange(n) / (n / 4.0))
+        A, _, _ = synth.known_spectrum(m, n, s, seed=300 + i)
+        Ds.append(torch.from_numpy(A).cuda())
+        specs.append(s)
+    ctx = api.Context(0)
+    ctx.set_option("streams", 3)
+    for use_graph in (False, True):
+        batch = api.PodBatch(Ds, r=0.0, precision="fp64", use_graph=use_graph, ctx=ctx)
+        for rep in range(2 if use_graph else 1):
+            batch.run()
+            rc, _ = ctx.status()
+            assert rc == 0, rc
+            assert ctx.get_option("batch_jacobi_chained") == 1
+            for res, s, (m, n) in zip(batch.results(), specs, shapes):
+                assert res.nr == n
+                err = np.max(np.abs(res.S.cpu().numpy() - s)) / s[0]
+                U = res.U_full.double()
+                oe = torch.linalg.norm(U.T @ U - torch.eye(n, dtype=torch.float64,
+                                                           device=U.device)).item()
+                say(f"  n={n} graph={use_graph} sigma err {err:.2e} |U^T U - I|_F {oe:.2e}")
+                assert err <= 1e-12
+                assert oe <= 10.0 * n ** 1.5 * 2.0 ** -53
+    # a batch of narrow instances needs no chaining
+    small = [torch.from_numpy(D).cuda() for D in make_inputs(5, np.float64)[:3]]
+    api.PodBatch(small, r=0.05, use_graph=False, ctx=ctx).run()
+    assert ctx.status()[0] == 0
+    assert ctx.get_option("batch_jacobi_chained") == 0
     ctx.close()

@@ -39,7 +39,7 @@ def run_mixed(D32, remove_mean, r, block_rows):
     Dg = torch.from_numpy(np.ascontiguousarray(D32)).cuda()
     out = api.pod(Dg, remove_mean=remove_mean, r=r, precision="mixed", ctx=ctx)
     rc, sweeps = ctx.status()
-    res = dict(U=out.U_full.cpu().numpy().astype(np.float64), S=out.S.cpu().numpy(),
+    res = dict(U=out.U_full[:, :out.nr].cpu().numpy().astype(np.float64), S=out.S.cpu().numpy(),
                VT=out.VT_full.cpu().numpy(), nr=out.nr, rc=rc, sweeps=sweeps,
                mean=None if out.mean is None else out.mean.cpu().numpy().astype(np.float64))
     ctx.close()

@@ -37,7 +37,7 @@ def run(D, remove_mean, r, b, narrow, precision="fp64"):
     Dg = torch.from_numpy(np.ascontiguousarray(D)).cuda()
     out = api.pod(Dg, remove_mean=remove_mean, r=r, precision=precision, ctx=ctx)
     rc, sweeps = ctx.status()
-    res = dict(U=out.U_full.cpu().numpy().astype(np.float64), S=out.S.cpu().numpy(),
+    res = dict(U=out.U_full[:, :out.nr].cpu().numpy().astype(np.float64), S=out.S.cpu().numpy(),
                VT=out.VT_full.cpu().numpy(), nr=out.nr, rc=rc,
                mean=None if out.mean is None else out.mean.cpu().numpy().astype(np.float64),
                leaves=ctx.plan(D.shape[0], D.shape[1])["leaves"])

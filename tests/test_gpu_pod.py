@@ -37,7 +37,7 @@ def run_pod(D, remove_mean, r, block_rows):
     Dg = torch.from_numpy(np.ascontiguousarray(D)).cuda()
     out = api.pod(Dg, remove_mean=remove_mean, r=r, ctx=ctx)
     rc, sweeps = ctx.status()
-    res = dict(U=out.U_full.cpu().numpy().astype(np.float64), S=out.S.cpu().numpy(),
+    res = dict(U=out.U_full[:, :out.nr].cpu().numpy().astype(np.float64), S=out.S.cpu().numpy(),
                VT=out.VT_full.cpu().numpy(), nr=out.nr, rc=rc, sweeps=sweeps,
                mean=None if out.mean is None else out.mean.cpu().numpy())
     ctx.close()
@@ -214,3 +214,30 @@ def test_pod_exactly_repeated_columns_converges():
     np.testing.assert_allclose(S[:2], ref, rtol=1e-13)
     assert np.all(S[2:] <= 1e-13 * S[0])
     assert checks.orth_error(g["U"]) <= 1e-12
+
+
+@pytest.mark.parametrize("precision,blocked_from,bad", [("fp64", 0, np.nan), ("fp64", 2, np.inf),
+                                                        ("mixed", 0, np.nan), ("mixed", 2, -np.inf)])
+def test_pod_nonfinite_input_reported(precision, blocked_from, bad):
+    # a NaN or Inf in the snapshots propagates into R; the call completes
+    # (every loop in the kernels is bounded) and pylom_check reports
+    # PYLOM_WNONFINITE
+    torch = _torch()
+    from paper_2405_15529_amd import api
+    say(f"[gpu] pod non-finite input {precision} blocked_from={blocked_from} {bad}")
+    D = synth.plain_pod_fp64(m=3000, n=40, seed=12)
+    D[1234, 7] = bad
+    if precision == "mixed":
+        D = D.astype(np.float32)
+    ctx = api.Context(0)
+    ctx.set_option("blocked_from", blocked_from)
+    ctx.set_option("block_rows", 512)
+    api.pod(torch.from_numpy(D).cuda(), remove_mean=True, r=0.01, precision=precision, ctx=ctx)
+    rc, _ = ctx.status()
+    assert rc == api.WNONFINITE, rc
+    # the context stays usable: a finite input afterwards is clean
+    out = api.pod(torch.from_numpy(np.nan_to_num(D, nan=0.0, posinf=0.0, neginf=0.0)).cuda(),
+                  remove_mean=True, r=0.01, precision=precision, ctx=ctx)
+    rc, _ = ctx.status()
+    assert rc == 0 and out.nr > 0
+    ctx.close()

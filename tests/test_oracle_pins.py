@@ -250,6 +250,26 @@ def test_zsvd_known_spectrum():
     np.testing.assert_allclose(S, np.linalg.svd(A, compute_uv=False), rtol=1e-11)
 
 
+def test_zsvd_rank_deficient_completes_unitary_basis():
+    # two exactly zero columns give two exactly zero singular values; their
+    # left vectors come from the complex basis completion, which must make
+    # the whole U unitary (U^H U = I): a completion that projects with the
+    # plain transpose instead of the conjugate transpose, or skips the second
+    # Gram-Schmidt pass, leaves U^H U - I of order one in the affected block
+    rng = np.random.default_rng(57)
+    m, n = 30, 6
+    A = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    A[:, 2] = 0.0
+    A[:, 4] = 0.0
+    U, S, VH, _ = oracle.zsvd_tall(A)
+    assert S[4] == 0.0 and S[5] == 0.0 and S[3] > 0.1
+    np.testing.assert_allclose(U.conj().T @ U, np.eye(n), atol=1e-13)
+    np.testing.assert_allclose(U @ np.diag(S) @ VH, A, atol=1e-12)
+    # the completed columns are orthogonal to the range of A as well
+    assert np.max(np.abs(A.conj().T @ U[:, 4:])) < 1e-12
+    np.testing.assert_allclose(S[:4], np.linalg.svd(A, compute_uv=False)[:4], rtol=1e-12)
+
+
 # ------------------------------------------------ SPOD front end (Alg. 6)
 
 def test_spod_block_count_closed_form():
@@ -281,6 +301,33 @@ def test_spod_spectra_against_library_fft():
         F = np.fft.rfft(seg, axis=1) / w.sum()
         F[:, 1:-1] *= 2.0
         np.testing.assert_allclose(Q[:, :, b].T, F / np.sqrt(nblk), atol=1e-13)
+
+
+@pytest.mark.parametrize("npwin,nolap,kind", [(32, 16, "hann"), (16, 4, "hamming")])
+def test_spod_one_sided_doubling_parseval(npwin, nolap, kind):
+    # Parseval per block, written without any FFT: for a real block y = w x
+    # with DFT Y, sum_f |Y_f|^2 = npwin sum_j y_j^2 and Y_{npwin-f} = conj(Y_f),
+    # so with q_f = c_f Y_f / sum(w) / sqrt(nBlks) (c_f = 2 for the interior
+    # bins, 1 at f = 0 and npwin/2):
+    #   |q_0|^2 + |q_{N/2}|^2 + (1/2) sum_{0<f<N/2} |q_f|^2
+    #       = npwin sum_j y_j^2 / (sum w)^2 / nBlks.
+    # Holds with amplitude doubling; fails without it (factor 1/2 on the
+    # interior) and with power doubling (sqrt 2).
+    rng = np.random.default_rng(npwin + nolap)
+    nt = 3 * npwin
+    D = rng.standard_normal((5, nt))
+    Q = oracle.spod_spectra(D, npwin, nolap, kind, remove_mean=True)
+    nblk = oracle.spod_nblocks(nt, npwin, nolap)
+    j = np.arange(npwin)
+    a0, a1 = (0.5, 0.5) if kind == "hann" else (0.54, 0.46)
+    w = a0 - a1 * np.cos(2 * np.pi * j / (npwin - 1))
+    Y = D - D.mean(axis=1, keepdims=True)
+    for b in range(nblk):
+        y = Y[:, b * (npwin - nolap): b * (npwin - nolap) + npwin] * w
+        rhs = npwin * np.sum(y * y, axis=1) / w.sum() ** 2 / nblk
+        q2 = np.abs(Q[:, :, b]) ** 2           # nfreq x points
+        lhs = q2[0] + q2[npwin // 2] + 0.5 * q2[1:npwin // 2].sum(axis=0)
+        np.testing.assert_allclose(lhs, rhs, rtol=1e-12)
 
 
 def test_spod_dc_closed_form():
