@@ -194,6 +194,21 @@ int pylom_matmul(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int trans_a,
                  int64_t p, int64_t q, const void* A, int64_t lda, const void* B, int64_t ldb,
                  void* C, int64_t ldc);
 
+/* pylom_matmul for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments and results as pylom_matmul; it calls no hipMalloc, hipFree
+ * or allocating library routine.  For trans_a = 1 the split-K partial sums
+ * go to a fixed 32 MiB device array of the library (one per device, held
+ * until the process ends; every call on a device shares it and it keeps the
+ * last call's contents, none of which a call reads), with fewer row splits
+ * when the usual count would not fit, so results may differ from
+ * pylom_matmul in the rounding of the cross-split sum.  p * q * 8 bytes over
+ * 32 MiB returns PYLOM_ENOMEM before any launch.  Calls that overlap on one
+ * device (several streams or host threads) race on that array. */
+int pylom_matmul_noalloc(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int trans_a, int64_t m,
+                         int64_t p, int64_t q, const void* A, int64_t lda, const void* B,
+                         int64_t ldb, void* C, int64_t ldc);
+
 /* One instance of a batched POD (the arguments of pylom_pod). */
 typedef struct {
   int64_t m, n;        /* shape, m >= n >= 1, n <= 1024 and, when the

@@ -38,6 +38,8 @@ SIGNATURES = {
                                   I64]),
     "pylom_matmul": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, I64, I64, I64,
                                     VP, I64, VP, I64, VP, I64]),
+    "pylom_matmul_noalloc": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, I64, I64,
+                                            I64, VP, I64, VP, I64, VP, I64]),
     "pylom_tree_plan": (I64, [I64, I64P, I64]),
     "pylom_plan_query": (ctypes.c_int, [VP, I64, I64, I64P, I64P, I64P, I64P]),
     "pylom_check": (ctypes.c_int, [VP, I64P]),

@@ -260,6 +260,29 @@ def matmul(A: torch.Tensor, B: torch.Tensor, trans_a: bool, ctx: Context | None 
     return C
 
 
+def matmul_noalloc(A: torch.Tensor, B: torch.Tensor, trans_a: bool, C: torch.Tensor,
+                   ctx: Context | None = None):
+    """Alg. 4 into the caller's C without any device allocation by the library
+    (pylom_matmul_noalloc); C is (p x q) for trans_a, else (m x q)."""
+    for t, nm in ((A, "A"), (B, "B"), (C, "C")):
+        _rowmajor(t, nm)
+        _on_gpu(t, nm)
+    if A.dtype != B.dtype or C.dtype != A.dtype:
+        raise TypeError("A, B and C must have the same dtype")
+    ctx = ctx or context(A.device.index)
+    m, p = A.shape
+    q = B.shape[1]
+    want = (p, q) if trans_a else (m, q)
+    if (B.shape[0] != (m if trans_a else p)) or tuple(C.shape) != want:
+        raise ValueError("shapes do not match")
+    ctx.bind_stream()
+    rc = ctx.lib.pylom_matmul_noalloc(ctx.h, _dtype_code(A), FP64, int(bool(trans_a)), m, p, q,
+                                      _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C),
+                                      C.stride(0))
+    ctx.check(rc)
+    return C
+
+
 def tree_plan(P: int):
     """The in-device reduction tree for P leaves: list of (level, receiver, sender)."""
     lib = _lib.load()

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -103,6 +104,33 @@ constexpr int64_t kTF = 256;     // elements of one 16 x 16 compact-WY T factor
 constexpr int kPhases = 6;     // phases reported by pylom_phase_times
 
 // ---------------------------------------------------------------------------
+// fixed device scratch of the allocation-free entry point
+// ---------------------------------------------------------------------------
+// The split-K partial sums of pylom_matmul_noalloc live in this array, one
+// copy per device, held until the process ends.  In host code its name is
+// only a stand-in for the symbol: its device address is taken once per
+// device, with that device current, at context creation (scratch_ptr[]),
+// and only that address is ever handed to kernels.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+static void* scratch_ptr[kMaxDevices] = {};
+static std::mutex scratch_mu;
+
+// With `device` current: the device address of its scratch copy.
+static hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 extern "C" int pylom_create(pylom_ctx* out, int device) {
@@ -128,6 +156,12 @@ extern "C" int pylom_create(pylom_ctx* out, int device) {
     if (hipMalloc((void**)&c->status_dev, 256) != hipSuccess) {
       delete c;
       return PYLOM_ENOMEM;
+    }
+    if (scratch_setup(device) != hipSuccess) {
+      (void)hipGetLastError();
+      hipFree(c->status_dev);
+      delete c;
+      return PYLOM_ENODEV;
     }
     c->device = device;
     if (prop.multiProcessorCount > 0) c->ncu = prop.multiProcessorCount;
@@ -1503,6 +1537,39 @@ extern "C" int pylom_matmul(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int
     if (lda < p || ldb < q || ldc < q) return fail(c, PYLOM_ESHAPE, "leading dimension");
     if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
     HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    HIPCHK(c, launch_matmul_nn(f64, m, p, q, A, lda, B, ldb, C, ldc, c->stream), "matmul nn");
+  }
+  return PYLOM_OK;
+}
+
+// Alg. 4 as pylom_matmul, for callers that cannot allocate: the split-K
+// partials of trans_a = 1 go to the device's fixed scratch (kScratchBytes),
+// with fewer row splits when the usual count would not fit.  Every split
+// writes its whole p x q partial, so nothing in the scratch needs clearing.
+// Calls that overlap on one device race on the scratch.
+extern "C" int pylom_matmul_noalloc(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int trans_a,
+                                    int64_t m, int64_t p, int64_t q, const void* A, int64_t lda,
+                                    const void* B, int64_t ldb, void* C, int64_t ldc) {
+  int rc = check_common(c, dtype, prec);
+  if (rc) return rc;
+  if (!A || !B || !C) return fail(c, PYLOM_EINVAL, "null array argument");
+  if (m < 1 || p < 1 || q < 1) return fail(c, PYLOM_ESHAPE, "empty matrix");
+  if (lda < p || ldb < q || ldc < q) return fail(c, PYLOM_ESHAPE, "leading dimension");
+  const int f64 = dtype == PYLOM_R64;
+  const size_t one = sizeof(double) * (size_t)p * (size_t)q;
+  if (trans_a && one > kScratchBytes)
+    return fail(c, PYLOM_ENOMEM, "p x q partial sums exceed the 32 MiB static scratch");
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+  if (trans_a) {
+    void* part = scratch_ptr[c->device];
+    if (!part) return fail(c, PYLOM_ENODEV, "device scratch not set up");
+    int64_t ns = matmul_tn_splits(m, p, q);
+    const int64_t fit = (int64_t)(kScratchBytes / one);
+    if (ns > fit) ns = fit;
+    HIPCHK(c, launch_matmul_tn(f64, m, p, q, A, lda, B, ldb, C, ldc, (double*)part, ns, c->stream),
+           "matmul tn");
+  } else {
     HIPCHK(c, launch_matmul_nn(f64, m, p, q, A, lda, B, ldb, C, ldc, c->stream), "matmul nn");
   }
   return PYLOM_OK;
