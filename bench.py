@@ -1,18 +1,20 @@
 """Benchmark of the POD TSQR-SVD hot path on one MI355X.
 
-One step = one pylom_pod call (leaf QR -> tree combines -> Jacobi SVD of R ->
-truncation -> tree propagation -> U = Q U_R) on a resident synthetic input.
-Default workload: the known-spectrum FP64 POD, A = Q1 diag(s) Q2^T,
-m = 1,048,576, n = 256, s_i = 10^(-i/32), row blocks of 4,096 (256 leaves,
-8 tree levels), 99 % energy truncation.
+Headline (the metric's own comparison, mixed precision against FP64 on one
+input): the travelling-wave POD of m = 4,194,304 grid points by n = 1,808
+FP32 snapshots (64 travelling waves plus N(0, 1e-8) noise), mean removed,
+99 % energy, on the column-blocked TSQR.  One step = one mixed-precision
+pylom_pod call (FP32 leaf QR, FP64 tree and SVD of R, Rayleigh-Ritz
+refinement against the input); the FP64 call on the same buffer is timed
+beside it for the speed-up and the sigma agreement.
 
-Prints one JSON line.  value = algorithmic TFLOP/s of the whole FP64 step,
-F = 2 m n^2 + 2 m n N_r (TSQR leaf term + U = Q U_R); "mixed" times the
-mixed-precision path on the FP32 copy of the same matrix with the same F
-(speed-up and sigma error against the FP64 run); the roofline object rates
-the dominant kernel (the FP64 leaf QR, 2 m n^2 flops per launch) against the
-FP64 MFMA peak; cpu_baseline times the CPU oracle on a bounded row sample of
-the same workload.
+value = algorithmic TFLOP/s of the mixed step, F = 2 m n^2 + 2 m n N_r (the
+TSQR leaf term of Eq. flops + U = Q U_R); gbps counts B = 2 s_in m n +
+s_out m N_r.  The roofline object rates the dominant kernel of the mixed
+step, timed live with an event pair around each launch inside the timed
+region.  cpu_baseline times the CPU oracle on a bounded row slice of the
+same field.  The known-spectrum FP64 workload (1,048,576 x 256, row blocks
+4,096) runs as the "c2" sub-object, SPOD, the uneven batch and DMD after it.
 """
 from __future__ import annotations
 
@@ -32,8 +34,14 @@ HBM_PEAK_GBPS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5,
+                    help="timed mixed-precision calls of the headline workload")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=5,
+                    help="timed FP64 calls beside the headline (at most --steps)")
+    ap.add_argument("--c2-steps", type=int, default=10)
+    ap.add_argument("--c2-warmup", type=int, default=3)
+    ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--m", type=int, default=1_048_576)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--block-rows", type=int, default=4096)
@@ -44,23 +52,21 @@ def parse():
     ap.add_argument("--no-default-path", action="store_true",
                     help="skip the run of the main matrix on the library's automatic path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=131072)
+    ap.add_argument("--cpu-rows", type=int, default=8192)
     ap.add_argument("--no-spod", action="store_true")
     ap.add_argument("--spod-m", type=int, default=262144)
     ap.add_argument("--spod-nt", type=int, default=2048)
     ap.add_argument("--spod-steps", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-dmd", action="store_true")
+    ap.add_argument("--dmd-wide", action="store_true",
+                    help="also time exact DMD of the headline field (N = 1808 snapshots)")
     ap.add_argument("--dmd-m", type=int, default=58_300_000)
     ap.add_argument("--dmd-n", type=int, default=56)
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--wide-m", type=int, default=4_194_304)
     ap.add_argument("--wide-n", type=int, default=1808)
-    ap.add_argument("--wide-steps", type=int, default=2)
     ap.add_argument("--wide-block-rows", type=int, default=0, help="0: the library's choice")
-    ap.add_argument("--only-wide", action="store_true",
-                    help="run only the wide mixed-vs-FP64 leg and print its object")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="run only the shapes of the paper's performance study (the JSM "
                          "matrix and the weak scaling in N) and print their object")
@@ -122,9 +128,49 @@ def timed_spod(api, m, nt, npwin, nolap, steps, warmup):
     return res
 
 
-def cpu_baseline(n: int, rows: int, r: float):
-    """The oracle (single-threaded C, FP64) on a row sample of the workload."""
+def host_info():
+    """nproc and the CPU model of this host (for the CPU baseline)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 0, model
+
+
+def cpu_baseline_c3(m: int, n: int, rows: int):
+    """The oracle (plain single-threaded C, FP64) on the first `rows` rows of
+    the headline field: its temporal mean (Alg. 2) and its Householder QR
+    with R only (the 2 rows n^2 leaf term of Eq. flops, which dominates F).
+    The Jacobi SVD of the 1808 x 1808 R is left out: its cost does not
+    shrink with the row sample (several minutes of one core).  Rate in
+    TFLOP/s of the same accounting, 2 rows n^2 over the timed seconds."""
     import numpy as np
+    import oracle
+    from paper_2405_15529_amd import synth
+
+    D = synth.travelling_waves_rows(m, n, 0, rows, seed=2).astype(np.float64)
+    oracle.build()
+    t0 = time.perf_counter()
+    mu = oracle.mean(D)
+    Y = D - mu[:, None]
+    oracle.qr(Y, want_q=False)
+    dt = time.perf_counter() - t0
+    nproc, model = host_info()
+    return dict(value=2.0 * rows * n * n / dt / 1e12, unit="TFLOP/s", cores=1, kind="oracle",
+                sample=f"rows 0..{rows - 1} of the {m} x {n} travelling-wave field (FP64): the "
+                       f"oracle's temporal mean and Householder QR (R only, the 2 m n^2 term); "
+                       f"{dt:.2f} s on one thread",
+                seconds=dt, host_nproc=nproc, host_cpu=model, threads=1)
+
+
+def cpu_baseline_c2(n: int, rows: int, r: float):
+    """The oracle's whole POD (single-threaded C, FP64) on a row sample of
+    the known-spectrum workload."""
     import oracle
     from paper_2405_15529_amd import synth
 
@@ -137,44 +183,51 @@ def cpu_baseline(n: int, rows: int, r: float):
     flops = 2.0 * rows * n * n + 2.0 * rows * n * nr
     return dict(value=flops / dt / 1e12, unit="TFLOP/s", cores=1, kind="oracle",
                 sample=f"{rows} x {n} rows of the same known-spectrum generator, FP64, "
-                       f"{dt:.2f} s, one thread",
-                seconds=dt)
+                       f"{dt:.2f} s, one thread", seconds=dt)
 
 
-# HBM bytes per launch of the FP64 leaf QR at 1048576 x 256 (row blocks 4096),
-# from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by the
-# same counters read on a plain 1 GiB device copy; valid only for the kernel
-# sources they were taken on (their SHA-256 below).  The counter summary is
-# in profiles/.
-LEAF_TRAFFIC = {
-    "sources_sha256": "0623733ccd8603f060147c06517f02aa27e381df97a66cca21b98b788aab9a20",
-    "m": 1048576, "n": 256, "b": 4096,
-    "bytes": 13614639179,  # FETCH 6.575e+09 (x1.99994) + WRITE 7.04e+09 (x1.0)
+# HBM bytes per launch, from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE) scaled by the same counters read on a plain 1 GiB device copy;
+# each entry is valid only for the kernel sources it was taken on (their
+# SHA-256) and for its shape.  The counter summaries are in profiles/.
+TRAFFIC = {
+    # FP64 stacked leaf QR, 1048576 x 256, row blocks 4096 (one launch)
+    "stacked_leaf_fp64": {
+        "sources": ("tsqr.hip", "common.hpp"),
+        "sources_sha256": "0623733ccd8603f060147c06517f02aa27e381df97a66cca21b98b788aab9a20",
+        "shape": (1048576, 256, 4096),
+        "bytes": 13614639179,  # FETCH 6.575e+09 (x1.99994) + WRITE 7.04e+09 (x1.0)
+    },
 }
 
 
-def kernel_sources_sha256() -> str:
+def sources_sha256(names) -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in ("tsqr.hip", "common.hpp"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_2405_15529_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def leaf_traffic(m: int, n: int, b: int):
-    t = LEAF_TRAFFIC
-    if not t or (t["m"], t["n"], t["b"]) != (m, n, b):
+def measured_traffic(key: str, shape):
+    """Bytes per launch of a kernel, or None if none were taken for these
+    sources and this shape."""
+    t = TRAFFIC.get(key)
+    if not t or tuple(t["shape"]) != tuple(shape):
         return None
-    if t["sources_sha256"] != kernel_sources_sha256():
+    if t["sources_sha256"] != sources_sha256(t["sources"]):
         return None  # the kernel changed since the counters were taken
     return t["bytes"]
 
 
-def timed_pod(api, ctx, A, m, n, r, precision, steps, warmup, remove_mean=False):
+def timed_pod(api, ctx, A, m, n, r, precision, steps, warmup, remove_mean=False,
+              kernel_timing=False):
     """Run pylom_pod `warmup` + `steps` times on the resident A; returns the
-    mean ms per call (HIP events on the library stream), phase means and the
-    outputs of the last call."""
+    mean ms per call (HIP events on the library stream), phase means, the
+    outputs of the last call and, with kernel_timing, the summed duration and
+    launch count of every kernel role over the timed calls (an event pair
+    around each launch, on the library stream)."""
     import ctypes
     import torch
 
@@ -206,6 +259,8 @@ def timed_pod(api, ctx, A, m, n, r, precision, steps, warmup, remove_mean=False)
         ctx.phase_times()  # drop warm-up samples
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
+    if kernel_timing:
+        ctx.set_option("kernel_timing", 1)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t0.record()
@@ -215,17 +270,40 @@ def timed_pod(api, ctx, A, m, n, r, precision, steps, warmup, remove_mean=False)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = t0.elapsed_time(t1) / steps
+    kt = None
+    if kernel_timing:
+        kt = ctx.kernel_times()
+        ctx.set_option("kernel_timing", 0)
     phases = ctx.phase_times()
     rc, sweeps = ctx.status()
     return dict(ms=ms, wall=wall, phases=phases, rc=rc, sweeps=sweeps, U=U, S=S, VT=VT,
-                nr=int(nr_d.item()))
+                nr=int(nr_d.item()), kernels=kt)
 
 
-def timed_wide(api, m, n, steps, warmup, block_rows=0):
-    """Wide mixed-precision POD: m x n FP32 sum of 64 travelling waves plus
-    N(0, 1e-8) noise, mean removed, 99 % energy, through the column-blocked
-    TSQR; the mixed path against the FP64 path on the same FP32 buffer
-    (promoted on load)."""
+FP32_PEAK_TFLOPS = 157.3
+
+
+def blocked_trailing_flops(m: int, n: int, pw: int = 64) -> float:
+    """Algorithmic flops of all leaf trailing updates of the column-blocked
+    TSQR: panel k (pw columns) applies its block reflector to the
+    n - (k+1) pw columns right of it over all m rows, W = V^T C then
+    C -= V (T^T W): 4 m pw (n - (k+1) pw) flops per launch (the small T^T W
+    product is not counted)."""
+    K = (n + pw - 1) // pw
+    return sum(4.0 * m * pw * (n - (k + 1) * pw) for k in range(K - 1))
+
+
+def kernel_summary(kt, steps):
+    """Per-call milliseconds and launches of every kernel role."""
+    return {k: {"ms_per_call": round(v[0] / steps, 3), "launches_per_call": v[1] // steps}
+            for k, v in kt.items() if v[1]}
+
+
+def timed_c3(api, m, n, steps, warmup, block_rows=0, fp64_steps=None):
+    """The headline: mixed precision against FP64 on one FP32 buffer, m x n
+    travelling waves (64 waves + N(0, 1e-8)), mean removed, 99 % energy,
+    through the column-blocked TSQR.  Kernel roles are timed live during the
+    timed mixed and FP64 calls."""
     import numpy as np
     import torch
     from paper_2405_15529_amd import synth
@@ -239,19 +317,22 @@ def timed_wide(api, m, n, steps, warmup, block_rows=0):
     if block_rows:
         ctx.set_option("block_rows", block_rows)
     b = block_rows or api.tune_block_rows(m, n, ctx)
+    fp64_steps = steps if fp64_steps is None else fp64_steps
 
     def orth_err(U, k):
         Ur = U[:, :k].double()
         return float(torch.linalg.norm(Ur.T @ Ur - torch.eye(k, dtype=torch.float64,
                                                                device=U.device)).item())
 
-    x = timed_pod(api, ctx, D, m, n, r, "mixed", steps, warmup, remove_mean=True)
+    x = timed_pod(api, ctx, D, m, n, r, "mixed", steps, warmup, remove_mean=True,
+                  kernel_timing=True)
     Sx = x["S"].cpu().numpy()
     nrx = x["nr"]
     orth_x = orth_err(x["U"], nrx)
     del x["U"]
     torch.cuda.empty_cache()
-    f = timed_pod(api, ctx, D, m, n, r, "fp64", steps, warmup, remove_mean=True)
+    f = timed_pod(api, ctx, D, m, n, r, "fp64", fp64_steps, min(warmup, 1), remove_mean=True,
+                  kernel_timing=True)
     Sf = f["S"].cpu().numpy()
     nrf = f["nr"]
     orth_f = orth_err(f["U"], nrf)
@@ -264,28 +345,48 @@ def timed_wide(api, m, n, steps, warmup, block_rows=0):
     def rates(ms, nr, s_in, s_out):
         fl = 2.0 * m * n * n + 2.0 * m * n * nr
         by = 2.0 * s_in * m * n + s_out * m * nr
-        return round(fl / (ms * 1e-3) / 1e12, 4), round(by / (ms * 1e-3) / 1e9, 2)
+        return fl / (ms * 1e-3) / 1e12, by / (ms * 1e-3) / 1e9
 
     tf_f, gb_f = rates(f["ms"], nrf, 4, 4)
     tf_x, gb_x = rates(x["ms"], nrx, 4, 4)
+    # roofline of the leaf trailing updates (the 2 m n^2 term on MFMA):
+    # algorithmic flops of all launches over their summed live durations
+    trail_fl = blocked_trailing_flops(m, n)
+    kx, kf = x["kernels"], f["kernels"]
+    t32_ms, t32_n = kx["leaf_trailing_update"]
+    t64_ms, t64_n = kf["leaf_trailing_update"]
+    ach32 = trail_fl * steps / (t32_ms * 1e-3) / 1e12
+    ach64 = trail_fl * fp64_steps / (t64_ms * 1e-3) / 1e12
     return {
         "workload": f"travelling-wave POD FP32 {m}x{n} (64 waves + N(0,1e-8)), mean removed, "
                     f"99% energy, column-blocked TSQR (64-column panels), row blocks {b}",
         "m": m, "n": n, "block_rows": b,
-        "fp64": {"ms_per_step": round(f["ms"], 3), "tflops": tf_f, "gbps": gb_f, "n_r": nrf,
-                 "orth_err_U": orth_f, "jacobi_sweeps": f["sweeps"],
-                 "phase_ms": {k2: round(v, 3) for k2, v in f["phases"].items()}},
-        "mixed": {"ms_per_step": round(x["ms"], 3), "tflops": tf_x, "gbps": gb_x, "n_r": nrx,
-                  "speedup_vs_fp64": round(f["ms"] / x["ms"], 3),
-                  "sigma_rel_err_vs_fp64_run":
-                      float(np.max(np.abs(Sx[:k] - Sf[:k]) / Sf[:k])) if k else 0.0,
-                  "orth_err_U": orth_x, "jacobi_sweeps_first": x["sweeps"],
+        "mixed": {"ms_per_step": round(x["ms"], 3), "tflops": round(tf_x, 4),
+                  "gbps": round(gb_x, 2), "n_r": nrx, "orth_err_U": orth_x,
+                  "jacobi_sweeps_first": x["sweeps"], "status": x["rc"],
+                  "wall_s": round(x["wall"], 3),
                   "phase_ms": {"working_copy": round(x["phases"]["front_end"], 3),
                                "leaf_qr_fp32": round(x["phases"]["leaf_qr"], 3),
                                "tree_combine": round(x["phases"]["tree_combine"], 3),
                                "small_svd": round(x["phases"]["small_svd"], 3),
                                "refine_project_gram_eig": round(x["phases"]["tree_propagate"], 3),
-                               "form_u": round(x["phases"]["leaf_apply"], 3)}},
+                               "form_u": round(x["phases"]["leaf_apply"], 3)},
+                  "kernels": kernel_summary(kx, steps)},
+        "fp64": {"ms_per_step": round(f["ms"], 3), "tflops": round(tf_f, 4),
+                 "gbps": round(gb_f, 2), "n_r": nrf, "orth_err_U": orth_f,
+                 "jacobi_sweeps": f["sweeps"], "status": f["rc"], "steps": fp64_steps,
+                 "phase_ms": {k2: round(v, 3) for k2, v in f["phases"].items()},
+                 "kernels": kernel_summary(kf, fp64_steps)},
+        "speedup_mixed_vs_fp64": round(f["ms"] / x["ms"], 3),
+        "sigma_rel_err_mixed_vs_fp64_run":
+            float(np.max(np.abs(Sx[:k] - Sf[:k]) / Sf[:k])) if k else 0.0,
+        "trailing_update": {
+            "algorithmic_flops_per_call": trail_fl,
+            "fp32_launches_per_call": t32_n // steps,
+            "fp32_mean_launch_ms": round(t32_ms / t32_n, 4),
+            "fp32_tflops": round(ach32, 3), "fp32_frac": round(ach32 / FP32_PEAK_TFLOPS, 4),
+            "fp64_mean_launch_ms": round(t64_ms / t64_n, 4),
+            "fp64_tflops": round(ach64, 3), "fp64_frac": round(ach64 / FP64_PEAK_TFLOPS, 4)},
         "steps": steps, "warmup": warmup,
     }
 
@@ -300,7 +401,7 @@ def fit_power(xs, ts):
 
 def timed_paper_shapes(api, steps, warmup, jsm_m=58_300_000, jsm_n=56, weak_m=36_000_000,
                        weak_ns=(10, 20, 40, 80, 160, 320), top_m=18_000_000, top_n=630):
-    """The shapes of the paper's performance study (Sec. 4) on one GPU.
+    """The shapes of the paper's performance study (Sec. 5) on one GPU.
 
     * The JSM strong-scaling matrix, 5.83e7 x 56 (FP64, 26 GB; a known
       spectrum s_i = 10^(-i/8) stands in for the flow data): FP64 and mixed
@@ -652,31 +753,22 @@ def timed_batch(api, count, seed, steps, warmup):
     return out
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
+def timed_c2(api, args):
+    """The known-spectrum FP64 workload, A = Q1 diag(s) Q2^T, m x n with
+    s_i = 10^(-i/32), fixed row blocks, 99 % energy (no mean removal): FP64
+    on the stacked QR, the library's automatic path beside it, and the mixed
+    path on the FP32 copy of the same matrix."""
     import numpy as np
     import torch
-    from paper_2405_15529_amd import api, synth
+    from paper_2405_15529_amd import synth
 
-    if args.only_wide:
-        print(json.dumps({"wide": timed_wide(api, args.wide_m, args.wide_n, args.wide_steps,
-                                             1 if args.warmup else 0, args.wide_block_rows)}),
-              flush=True)
-        return
-    if args.paper_shapes:
-        print(json.dumps({"paper_shapes": timed_paper_shapes(api, 2, 1 if args.warmup else 0)}),
-              flush=True)
-        return
     m, n, r = args.m, args.n, 0.01
     dev = torch.device("cuda:0")
     A, s = synth.graded_fp64_device(m=m, n=n, seed=1, device="cuda")
     ctx = api.Context(0)
     ctx.set_option("block_rows", args.block_rows)
     ctx.set_option("blocked_from", args.blocked_from)
-    ctx.set_option("timing", max(1, args.steps))
+    ctx.set_option("timing", max(1, args.c2_steps))
     ctx.bind_stream()
 
     def orth_err(U, k):
@@ -684,30 +776,25 @@ def main():
         return float(torch.linalg.norm(Ur.T @ Ur - torch.eye(k, dtype=torch.float64,
                                                                device=dev)).item())
 
-    # FP64 path on the FP64 matrix (the named workload)
-    f = timed_pod(api, ctx, A, m, n, r, "fp64", args.steps, args.warmup)
+    f = timed_pod(api, ctx, A, m, n, r, "fp64", args.c2_steps, args.c2_warmup,
+                  kernel_timing=True)
     nr = f["nr"]
     S_h = f["S"].cpu().numpy()
     sig_rel = float(np.max(np.abs(S_h[:nr] - s[:nr]) / s[:nr])) if nr else 0.0
     sig_norm = float(np.max(np.abs(S_h - s)) / s[0])
     orth = orth_err(f["U"], nr)
     del f["U"]
-
     flops = 2.0 * m * n * n + 2.0 * m * n * nr
     bytes64 = 2.0 * 8 * m * n + 8.0 * m * nr
     ms = f["ms"]
-    tflops = flops / (ms * 1e-3) / 1e12
-    gbps = bytes64 / (ms * 1e-3) / 1e9
-    leaf_ms = f["phases"]["leaf_qr"]
-    leaf_tflops = 2.0 * m * n * n / (leaf_ms * 1e-3) / 1e12
-
-    # the same matrix on the library's automatic choice of path and leaf height
+    leaf_ms, leaf_n = f["kernels"]["stacked_leaf_qr"]
+    leaf_tflops = 2.0 * m * n * n * leaf_n / (leaf_ms * 1e-3) / 1e12
     auto = None
     if not args.no_default_path:
         ctx_a = api.Context(0)
-        ctx_a.set_option("timing", max(1, args.steps))
+        ctx_a.set_option("timing", max(1, args.c2_steps))
         ctx_a.bind_stream()
-        a = timed_pod(api, ctx_a, A, m, n, r, "fp64", args.steps, args.warmup)
+        a = timed_pod(api, ctx_a, A, m, n, r, "fp64", args.c2_steps, args.c2_warmup)
         Sa = a["S"].cpu().numpy()
         nra = a["nr"]
         b_auto = api.tune_block_rows(m, n, ctx_a)
@@ -725,74 +812,127 @@ def main():
         ctx_a.close()
         del a
         torch.cuda.empty_cache()
-    if args.copy_probe:
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    # mixed path on the FP32 copy of the same matrix
     A32 = A.float().contiguous()
     del A
-    if args.no_mixed:
-        x = None
-    else:
-        x = timed_pod(api, ctx, A32, m, n, r, "mixed", args.steps, args.warmup)
     mixed = None
-    if x is not None:
+    if not args.no_mixed:
+        x = timed_pod(api, ctx, A32, m, n, r, "mixed", args.c2_steps, args.c2_warmup)
         mixed = mixed_summary(x, ms, flops, m, n, s, S_h, nr, orth_err)
         del x["U"]
+    ctx.close()
+    del A32
+    torch.cuda.empty_cache()
+    out = {
+        "workload": f"known-spectrum POD FP64 {m}x{n}, s_i=10^(-i/32), row blocks "
+                    f"{args.block_rows}, 99% energy, stacked TSQR",
+        "m": m, "n": n, "block_rows": args.block_rows, "blocked_from": args.blocked_from,
+        "ms_per_step": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 4),
+        "gbps": round(bytes64 / (ms * 1e-3) / 1e9, 2), "n_r": nr,
+        "sigma_rel_err_retained": sig_rel, "sigma_err_normwise": sig_norm, "orth_err_U": orth,
+        "jacobi_sweeps": f["sweeps"],
+        "phase_ms": {k: round(v, 4) for k, v in f["phases"].items()},
+        "kernels": kernel_summary(f["kernels"], args.c2_steps),
+        "roofline_leaf_qr": {"bound": "mfma", "kernel": "k_stacked_qr (leaf QR, FP64)",
+                             "achieved": round(leaf_tflops, 3), "peak": FP64_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(leaf_tflops / FP64_PEAK_TFLOPS, 4),
+                             "traffic": measured_traffic("stacked_leaf_fp64",
+                                                         (m, n, args.block_rows))},
+        "mixed": mixed, "library_default": auto,
+        "steps": args.c2_steps, "warmup": args.c2_warmup,
+    }
+    return out
+
+
+def copy_probe():
+    """One plain 1 GiB FP64 device copy, a kernel of known traffic for
+    calibrating the HBM byte counters of rocprofv3 --pmc."""
+    import torch
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2405_15529_amd import api
+
+    if args.paper_shapes:
+        print(json.dumps({"paper_shapes": timed_paper_shapes(api, 2, 1 if args.warmup else 0)}),
+              flush=True)
+        return
+    m, n = args.wide_m, args.wide_n
+    print(f"[bench] headline {m}x{n} mixed vs fp64: {args.steps} steps, {args.warmup} warm-up",
+          file=sys.stderr, flush=True)
+    c3 = timed_c3(api, m, n, args.steps, args.warmup, args.wide_block_rows,
+                  fp64_steps=min(args.steps, args.fp64_steps))
+    x, f = c3["mixed"], c3["fp64"]
+    tu = c3["trailing_update"]
     out = {
         "metric": "POD TSQR-SVD GB/s & TFLOP/s: mixed-precision vs FP64 at sigma rel err <=1e-6",
-        "value": round(tflops, 4),
+        "value": x["tflops"],
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": x["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"known-spectrum POD FP64 {m}x{n}, s_i=10^(-i/32), "
-                               f"row blocks {args.block_rows}, 99% energy",
-                   "m": m, "n": n, "block_rows": args.block_rows, "precision": "fp64",
-                   "blocked_from": args.blocked_from},
-        "gbps": round(gbps, 2),
-        "n_r": nr,
-        "sigma_rel_err_retained": sig_rel,
-        "sigma_err_normwise": sig_norm,
-        "orth_err_U": orth,
-        "jacobi_sweeps": f["sweeps"],
-        "phase_ms": {k: round(v, 4) for k, v in f["phases"].items()},
-        "mixed": mixed,
-        "library_default": auto,
-        "roofline": {"bound": "mfma", "kernel": "k_stacked_qr (leaf QR, FP64)",
-                     "achieved": round(leaf_tflops, 3), "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(leaf_tflops / FP64_PEAK_TFLOPS, 4),
-                     "traffic": leaf_traffic(m, n, args.block_rows)},
-        "wall_s": round(f["wall"], 3),
+        "config": {"workload": f"travelling-wave POD {m}x{n} FP32 snapshots (64 waves + noise), "
+                               f"mean removed, 99% energy: mixed precision (FP32 leaf QR, FP64 "
+                               f"tree and SVD, Rayleigh-Ritz refinement) vs FP64 on the same "
+                               f"buffer", "m": m, "n": n, "block_rows": c3["block_rows"],
+                   "path": "column-blocked TSQR", "precision": "mixed vs fp64"},
+        "gbps": x["gbps"],
+        "fp64": {"ms_per_step": f["ms_per_step"], "tflops": f["tflops"], "gbps": f["gbps"],
+                 "steps": f["steps"]},
+        "speedup_mixed_vs_fp64": c3["speedup_mixed_vs_fp64"],
+        "sigma_rel_err_mixed_vs_fp64_run": c3["sigma_rel_err_mixed_vs_fp64_run"],
+        "n_r": {"mixed": x["n_r"], "fp64": f["n_r"]},
+        "orth_err_U": {"mixed": x["orth_err_U"], "fp64": f["orth_err_U"]},
+        "roofline": {"bound": "mfma",
+                     "kernel": "k_panel_apply<float> (leaf trailing updates of the FP32 "
+                               "column-blocked QR, the 2 m n^2 term)",
+                     "achieved": tu["fp32_tflops"], "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tu["fp32_frac"],
+                     "traffic": measured_traffic("blocked_trailing_fp32", (m, n, c3["block_rows"])),
+                     "share_of_step": round(x["kernels"]["leaf_trailing_update"]["ms_per_call"] /
+                                            x["ms_per_step"], 4)},
+        "c3": c3,
     }
+    print(f"[bench] headline: mixed {x['ms_per_step']} ms, fp64 {f['ms_per_step']} ms",
+          file=sys.stderr, flush=True)
+    if args.copy_probe:
+        copy_probe()
+    if args.dmd_wide:
+        out["dmd_wide"] = timed_dmd_wide(api, m, n, 1, 1 if args.warmup else 0)
+    if not args.no_c2:
+        out["c2"] = timed_c2(api, args)
+        print(f"[bench] c2: {out['c2']['ms_per_step']} ms", file=sys.stderr, flush=True)
     if not args.no_spod:
-        del A32, f
-        torch.cuda.empty_cache()
         out["spod"] = timed_spod(api, args.spod_m, args.spod_nt, 256, 128, args.spod_steps,
                                  1 if args.warmup else 0)
-    if not args.no_wide:
-        out["wide"] = timed_wide(api, args.wide_m, args.wide_n, args.wide_steps,
-                                 1 if args.warmup else 0, args.wide_block_rows)
+        print(f"[bench] spod: {out['spod']['ms_per_step']} ms", file=sys.stderr, flush=True)
     if not args.no_dmd:
         out["dmd"] = timed_dmd(api, args.dmd_m, args.dmd_n, 2, 1 if args.warmup else 0)
-        if not args.no_wide:
-            out["dmd"]["wide"] = timed_dmd_wide(api, args.wide_m, args.wide_n, 1,
-                                                1 if args.warmup else 0)
+        print(f"[bench] dmd: {out['dmd']['ms_per_step']} ms", file=sys.stderr, flush=True)
     if not args.no_batch:
         out["uneven_batch"] = timed_batch(api, args.batch_count, 4, args.batch_steps,
                                           1 if args.warmup else 0)
+        print(f"[bench] batch: {out['uneven_batch']['mixed_batched_graph_s']} s", file=sys.stderr,
+              flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, args.cpu_rows, r)
+        out["cpu_baseline"] = cpu_baseline_c3(m, n, args.cpu_rows)
     print(json.dumps(out), flush=True)
 
 

@@ -97,6 +97,11 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
  *   "timing"       k > 0: record HIP events around the phases of every
  *                  pod/tsvd call in a ring of k call slots (read back with
  *                  pylom_phase_times); 0 = off (default).
+ *   "ooc_window_rows" rows per window of pylom_pod_host (0 = automatic,
+ *                  2^20; at least 4 n; rounded down to whole leaves).
+ *   "kernel_timing" 1: record an event pair around every kernel launch of
+ *                  the single-problem calls, read with pylom_kernel_times;
+ *                  0 = off (default).
  *   "narrow_leaves" 1 (default): stacked-QR plans of 3 to 6 panels of 16
  *                  columns (33 <= n <= 96; up to 8 panels, n <= 128, for the
  *                  FP32 leaves of PYLOM_MIXED) with at least two leaves per
@@ -168,6 +173,35 @@ const char* pylom_last_error(pylom_ctx ctx);
 int pylom_pod(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
               const void* D, int64_t ldd, int remove_mean, double residual, void* mean, void* U,
               int64_t ldu, double* S, double* VT, int64_t ldvt, int64_t* n_r);
+
+/* Out-of-core POD (Alg. 2 -> Alg. 1 -> Eqs. svdqr1-3) of a snapshot matrix
+ * held in HOST memory, for matrices larger than the device: the arguments of
+ * pylom_pod with D, mean, U, S, VT and n_r all HOST pointers (D need not be
+ * pinned).  FP64 compute (PYLOM_FP64; R64 or R32 storage, promoted on load).
+ * The rows stream through the device in windows of whole leaves (option
+ * "ooc_window_rows", default 2^20 rows, at least 4 n; the leaf height is the
+ * "block_rows" option, else two leaves per CU per window), each window
+ * twice: pass 1 removes the mean and factors the window's leaves into their
+ * R (Alg. 1 local QR); the binary tree of Alg. 1, the SVD of R, the
+ * truncation and the down-tree propagation then run once on the device;
+ * pass 2 factors each window's leaves again (the same arithmetic, so the
+ * same reflectors) and forms its rows of U = Q [W; 0], which stream back.
+ * Only O(P n^2 + m) bytes (P = leaves) stay resident, plus the windows.
+ * The leaves, the tree and every reflector are those of the column-blocked
+ * path (see "blocked_from") at the same leaf height, so the results equal
+ * those of pylom_pod there.  Transfers run on two copy streams through
+ * pinned staging buffers that the context allocates (two windows each way);
+ * host-side copies between the caller's rows and that staging use up to 8
+ * host threads.  Synchronous: returns when U, S, VT, mean and n_r are
+ * written.  Workspace: pylom_ooc_workspace_query. */
+int pylom_pod_host(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
+                   const void* D, int64_t ldd, int remove_mean, double residual, void* mean,
+                   void* U, int64_t ldu, double* S, double* VT, int64_t ldvt, int64_t* n_r);
+/* Device workspace bytes of a pylom_pod_host call of this shape, the rows of
+ * a full window and the number of windows (host only; the last two may be
+ * NULL). */
+int pylom_ooc_workspace_query(pylom_ctx ctx, pylom_dtype dtype, int64_t m, int64_t n,
+                              size_t* bytes, int64_t* window_rows, int64_t* windows);
 
 /* Tall-skinny SVD without mean removal (pylom_pod with remove_mean = 0, as
  * DMD's Alg. 3 applies it to Y[:, :-1]).  Arguments as pylom_pod. */
@@ -360,6 +394,26 @@ int pylom_plan_query(pylom_ctx ctx, int64_t m, int64_t n, int64_t* leaves, int64
  * or a negative status.  Waits for the recorded events, then starts a new
  * averaging window. */
 int pylom_phase_times(pylom_ctx ctx, double* out, int cap);
+
+/* Per-kernel durations (option "kernel_timing" = 1: an event pair around
+ * every launch of the pod/tsvd/tsqr calls on this context; batched calls are
+ * not timed).  Sums, over the launches made since the previous read, of the
+ * milliseconds of each kernel role, and the launch counts:
+ *   0 working copy of D (mean removal, type conversion)
+ *   1 leaf panel QRs (column-blocked TSQR; with the R assembly and cast)
+ *   2 leaf trailing updates (column-blocked TSQR)
+ *   3 tree panel QRs (column-blocked TSQR; pair states and R assembly)
+ *   4 tree trailing updates (column-blocked TSQR)
+ *   5 SVD of R (Jacobi set-up, sweeps, finalize and truncation)
+ *   6 down-tree propagation
+ *   7 leaf apply U = Q [W; 0] and U out
+ *   8 mixed refinement (projection, Gram, its eigenpairs, refined spectrum)
+ *   9 mixed refinement U = Z M
+ *  10 stacked leaf QR (and the FP32 to FP64 cast of its R)
+ *  11 stacked tree combines
+ * `ms` and `launches` are host arrays of `cap` entries; returns the number of
+ * roles (12) or a negative status.  Waits for the recorded events. */
+int pylom_kernel_times(pylom_ctx ctx, double* ms, int64_t* launches, int cap);
 
 /* After a stream synchronisation: the deferred numerical status of the last
  * pod/tsvd/spod/dmd/batched call on this context (0, PYLOM_WNOCONV, or

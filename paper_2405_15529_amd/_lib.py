@@ -32,6 +32,11 @@ SIGNATURES = {
     "pylom_last_error": (ctypes.c_char_p, [VP]),
     "pylom_pod": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int, I64, I64, VP, I64, ctypes.c_int,
                                  ctypes.c_double, VP, VP, I64, VP, VP, I64, VP]),
+    "pylom_pod_host": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int, I64, I64, VP, I64,
+                                      ctypes.c_int, ctypes.c_double, VP, VP, I64, VP, VP, I64,
+                                      VP]),
+    "pylom_ooc_workspace_query": (ctypes.c_int, [VP, ctypes.c_int, I64, I64,
+                                                 ctypes.POINTER(ctypes.c_size_t), I64P, I64P]),
     "pylom_tsvd": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int, I64, I64, VP, I64,
                                   ctypes.c_double, VP, I64, VP, VP, I64, VP]),
     "pylom_tsqr": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int, I64, I64, VP, I64, VP, I64, VP,
@@ -44,6 +49,7 @@ SIGNATURES = {
     "pylom_plan_query": (ctypes.c_int, [VP, I64, I64, I64P, I64P, I64P, I64P]),
     "pylom_check": (ctypes.c_int, [VP, I64P]),
     "pylom_phase_times": (ctypes.c_int, [VP, DP, ctypes.c_int]),
+    "pylom_kernel_times": (ctypes.c_int, [VP, DP, I64P, ctypes.c_int]),
     "pylom_spod": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int, I64, I64, VP, I64, ctypes.c_double,
                                   I64, I64, ctypes.c_int, ctypes.c_int, VP, VP, VP, VP]),
     "pylom_spod_query": (ctypes.c_int, [VP, ctypes.c_int, I64, I64, I64, I64, I64P, I64P,

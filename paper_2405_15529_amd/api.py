@@ -144,6 +144,21 @@ class Context:
             raise PylomError(rc, self.lib.pylom_last_error(self.h).decode())
         return {k: buf[i] for i, k in enumerate(self.PHASES)}
 
+    KERNEL_ROLES = ("working_copy", "leaf_panel_qr", "leaf_trailing_update", "tree_panel_qr",
+                    "tree_trailing_update", "small_svd", "tree_propagate", "leaf_apply",
+                    "refine", "refine_form_u", "stacked_leaf_qr", "stacked_tree")
+
+    def kernel_times(self) -> dict:
+        """Summed milliseconds and launch counts per kernel role since the
+        last read (needs the kernel_timing option)."""
+        n = len(self.KERNEL_ROLES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        rc = self.lib.pylom_kernel_times(self.h, ms, cnt, n)
+        if rc < 0:
+            raise PylomError(rc, self.lib.pylom_last_error(self.h).decode())
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNEL_ROLES)}
+
     def status(self):
         """Synchronise the stream; return (status, sweeps) of the last SVD."""
         sw = ctypes.c_int64()
@@ -195,6 +210,56 @@ def pod(D: torch.Tensor, remove_mean: bool = True, r: float = 0.01, precision: s
     ctx.check(rc)
     k = int(nr.item()) if sync else n
     return PodResult(U=U[:, :k], S=S, VT=VT[:k], mean=mean, nr=k, U_full=U, VT_full=VT)
+
+
+def ooc_query(m: int, n: int, dtype=R64, ctx: Context | None = None):
+    """(device workspace bytes, rows per window, windows) of a pod_host call."""
+    ctx = ctx or Context(-1)
+    b, wr, nw = ctypes.c_size_t(), ctypes.c_int64(), ctypes.c_int64()
+    ctx.check(ctx.lib.pylom_ooc_workspace_query(ctx.h, dtype, m, n, ctypes.byref(b),
+                                                ctypes.byref(wr), ctypes.byref(nw)))
+    return b.value, wr.value, nw.value
+
+
+@dataclass
+class HostPodResult:
+    U: "object"          # m x N_r spatial modes (numpy, storage type)
+    S: "object"          # n singular values (numpy FP64)
+    VT: "object"         # N_r x n temporal coefficients (numpy FP64)
+    mean: "object"       # m row means (numpy, storage type) or None
+    nr: int
+
+
+def pod_host(D, remove_mean: bool = True, r: float = 0.01, ctx: Context | None = None,
+             U=None) -> HostPodResult:
+    """Out-of-core POD of a snapshot matrix in host memory (a C-contiguous
+    numpy array, float64 or float32, m x n): pylom_pod_host streams its rows
+    through the device.  U (m x n capacity, same dtype) may be given."""
+    import numpy as np
+    if not isinstance(D, np.ndarray) or D.ndim != 2 or not D.flags["C_CONTIGUOUS"]:
+        raise ValueError("D must be a C-contiguous 2-D numpy array")
+    if D.dtype not in (np.float64, np.float32):
+        raise TypeError("D must be float64 or float32")
+    m, n = D.shape
+    ctx = ctx or context(0)
+    code = R64 if D.dtype == np.float64 else R32
+    if U is None:
+        U = np.empty((m, n), dtype=D.dtype)
+    if U.shape != (m, n) or U.dtype != D.dtype or not U.flags["C_CONTIGUOUS"]:
+        raise ValueError("U must be a C-contiguous m x n array of D's dtype")
+    S = np.empty(n)
+    VT = np.empty((n, n))
+    mean = np.empty(m, dtype=D.dtype) if remove_mean else None
+    nr = ctypes.c_int64(0)
+    vp = ctypes.c_void_p
+    rc = ctx.lib.pylom_pod_host(ctx.h, code, FP64, m, n, vp(D.ctypes.data), n,
+                                int(bool(remove_mean)), float(r),
+                                vp(mean.ctypes.data if mean is not None else 0),
+                                vp(U.ctypes.data), n, vp(S.ctypes.data), vp(VT.ctypes.data), n,
+                                ctypes.byref(nr))
+    ctx.check(rc)
+    k = nr.value
+    return HostPodResult(U=U[:, :k], S=S, VT=VT[:k], mean=mean, nr=k)
 
 
 def tsvd(A: torch.Tensor, r: float = 0.01, precision: str = "fp64", ctx: Context | None = None,

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -57,7 +58,74 @@ struct pylom_ctx_s {
   // when their workgroups could not all be resident together
   std::vector<hipEvent_t> jac_ev;
   int64_t last_jac_chain = 0;  // whether the last batched call chained them
+  // per-kernel timing (option "kernel_timing"): an event pair around every
+  // launch of the single-problem calls, summed by role in pylom_kernel_times
+  // out-of-core calls: copy streams and pinned host staging (two buffers each
+  // way), grown on demand, freed with the context
+  hipStream_t cs_in = nullptr, cs_out = nullptr;
+  hipEvent_t ooc_ev[8] = {};
+  void* pin_in[2] = {};
+  void* pin_out[2] = {};
+  size_t pin_bytes = 0;
+  int64_t ooc_window_rows = 0;     // option "ooc_window_rows" (0: automatic)
+  int64_t ktiming = 0;
+  bool kt_off = false;             // set while a batch is enqueued or captured
+  std::vector<hipEvent_t> kev;     // event pool; pairs (start, end)
+  size_t kev_next = 0;             // events used since the last read
+  std::vector<std::pair<int, size_t>> kmarks;  // (role, start event index)
 };
+
+// Kernel roles of pylom_kernel_times (include/pylom.h lists them).
+enum KernelRole {
+  KR_WORK = 0,       // working copy of D (mean removal, type conversion)
+  KR_LEAF_PANEL,     // leaf panel QRs (column-blocked)
+  KR_LEAF_TRAIL,     // leaf trailing updates (column-blocked)
+  KR_TREE_PANEL,     // tree panel QRs (column-blocked)
+  KR_TREE_TRAIL,     // tree trailing updates (column-blocked)
+  KR_SVD,            // SVD of R: Jacobi set-up, sweeps, finalize, truncation
+  KR_PROPAGATE,      // down-tree propagation
+  KR_LEAF_APPLY,     // U = Q [W; 0] per leaf, and U out
+  KR_REFINE,         // mixed refinement: projection, Gram, eigenpairs, spectrum
+  KR_FORM_U,         // mixed refinement: U = Z M
+  KR_STACKED_LEAF,   // stacked leaf QR (with fused mean removal)
+  KR_STACKED_TREE,   // stacked tree combines
+  KR_COUNT
+};
+constexpr size_t kMaxKernelEvents = (size_t)1 << 16;
+
+static int64_t kt_begin(pylom_ctx c, hipStream_t st) {
+  if (!c->ktiming || c->kt_off || c->kev_next + 2 > kMaxKernelEvents) return -1;
+  while (c->kev.size() < c->kev_next + 2) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return -1;
+    }
+    c->kev.push_back(e);
+  }
+  const size_t t = c->kev_next;
+  if (hipEventRecord(c->kev[t], st) != hipSuccess) {
+    (void)hipGetLastError();
+    return -1;
+  }
+  c->kev_next += 2;
+  return (int64_t)t;
+}
+static void kt_end(pylom_ctx c, hipStream_t st, int64_t t, int role) {
+  if (t < 0) return;
+  if (hipEventRecord(c->kev[(size_t)t + 1], st) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  c->kmarks.emplace_back(role, (size_t)t);
+}
+// One launch under the kernel timer (stream `st` in scope).
+#define KT(role, launch, where)                     \
+  do {                                              \
+    const int64_t _kt = kt_begin(c, st);            \
+    HIPCHK(c, (launch), where);                     \
+    kt_end(c, st, _kt, (role));                     \
+  } while (0)
 
 static void drop_graphs(pylom_ctx c) {
   for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second.first);
@@ -179,6 +247,15 @@ extern "C" int pylom_destroy(pylom_ctx c) {
     for (hipStream_t q : c->lanes) hipStreamDestroy(q);
     for (hipEvent_t e : c->ev_join) hipEventDestroy(e);
     for (hipEvent_t e : c->jac_ev) hipEventDestroy(e);
+    for (hipEvent_t e : c->kev) hipEventDestroy(e);
+    for (hipEvent_t e : c->ooc_ev)
+      if (e) hipEventDestroy(e);
+    if (c->cs_in) hipStreamDestroy(c->cs_in);
+    if (c->cs_out) hipStreamDestroy(c->cs_out);
+    for (int k = 0; k < 2; ++k) {
+      if (c->pin_in[k]) hipHostFree(c->pin_in[k]);
+      if (c->pin_out[k]) hipHostFree(c->pin_out[k]);
+    }
     if (c->ev_fork) hipEventDestroy(c->ev_fork);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
@@ -219,6 +296,14 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
   } else if (!std::strcmp(key, "streams")) {
     if (v < 1 || v > 16) return fail(c, PYLOM_EINVAL, "streams must be in [1, 16]");
     c->streams = v;
+  } else if (!std::strcmp(key, "ooc_window_rows")) {
+    if (v < 0) return fail(c, PYLOM_EINVAL, "ooc_window_rows must be >= 0");
+    c->ooc_window_rows = v;
+  } else if (!std::strcmp(key, "kernel_timing")) {
+    if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "kernel_timing must be 0 or 1");
+    c->ktiming = v;
+    c->kev_next = 0;
+    c->kmarks.clear();
   } else if (!std::strcmp(key, "timing")) {
     if (v < 0 || v > 4096) return fail(c, PYLOM_EINVAL, "timing must be in [0, 4096]");
     if (c->device >= 0) {
@@ -255,6 +340,10 @@ extern "C" int pylom_get_option(pylom_ctx c, const char* key, int64_t* v) {
     *v = c->timing;
   else if (!std::strcmp(key, "streams"))
     *v = c->streams;
+  else if (!std::strcmp(key, "kernel_timing"))
+    *v = c->ktiming;
+  else if (!std::strcmp(key, "ooc_window_rows"))
+    *v = c->ooc_window_rows;
   else if (!std::strcmp(key, "batch_jacobi_chained"))
     *v = c->last_jac_chain;
   else
@@ -781,26 +870,27 @@ static int enqueue_fp64(pylom_ctx c, const Exec& x, const Plan& p, pylom_dtype d
   hipStream_t st = x.st;
   EVREC(0);
   EVREC(1);
-  HIPCHK(c, launch_leaf_qr_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws, V, Tleaf,
-                               p.nch_leaf, Rbuf, st), "leaf QR");
+  KT(KR_STACKED_LEAF, launch_leaf_qr_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws, V,
+                                         Tleaf, p.nch_leaf, Rbuf, st), "leaf QR");
   EVREC(2);
   for (int64_t h = 1; h < p.P; h *= 2)
-    HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, 1, st), "tree combine");
+    KT(KR_STACKED_TREE, launch_tree_combine_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, 1, st),
+       "tree combine");
   EVREC(3);
   JAC_BEFORE(p.jp);
-  HIPCHK(c, launch_small_svd(p.jp, Rbuf, x.max_sweeps, x.ws + p.oSvd, S, VT, ldvt, W, residual,
-                             n_r, x.status, st, x.coop), "small SVD");
+  KT(KR_SVD, launch_small_svd(p.jp, Rbuf, x.max_sweeps, x.ws + p.oSvd, S, VT, ldvt, W, residual,
+                              n_r, x.status, st, x.coop), "small SVD");
   JAC_AFTER(p.jp);
   EVREC(4);
   int64_t top = 1;
   while (top * 2 < p.P) top *= 2;
   if (p.P > 1)
     for (int64_t h = top; h >= 1; h /= 2)
-      HIPCHK(c, launch_apply_tree_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, W, n, n_r, n, st),
-             "tree propagation");
+      KT(KR_PROPAGATE, launch_apply_tree_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, W, n, n_r, n,
+                                             st), "tree propagation");
   EVREC(5);
-  HIPCHK(c, launch_apply_leaf_f64(p.g, m, p.b, p.P, V, Tleaf, p.nch_leaf, W, n, n_r, n, U, in64,
-                                  ldu, st), "leaf apply");
+  KT(KR_LEAF_APPLY, launch_apply_leaf_f64(p.g, m, p.b, p.P, V, Tleaf, p.nch_leaf, W, n, n_r, n, U,
+                                          in64, ldu, st), "leaf apply");
   if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, in64, m, st), "mean out");
   EVREC(6);
   return PYLOM_OK;
@@ -827,8 +917,8 @@ static int blocked_leaves(pylom_ctx c, hipStream_t st, const Plan& p, char* ws, 
     const QrGeom& g = (k == p.K - 1) ? p.gpl : p.gp;
     T* Tk = (T*)(ws + p.oTl) + k * tps;
     T* PSk = (T*)(ws + p.oPSl) + k * pps;
-    HIPCHK(c, launch_panel_qr<T>(g, Wk + c0, n, p.m, p.b, p.P, 0, Tk, p.nch_l, PSk, 1, st),
-           "panel QR");
+    KT(KR_LEAF_PANEL, launch_panel_qr<T>(g, Wk + c0, n, p.m, p.b, p.P, 0, Tk, p.nch_l, PSk, 1, st),
+       "panel QR");
     if (c0 + kw < n) {
       PanelApplyArgs<T> a{};
       a.kw = kw; a.npan = g.npanels; a.nlv = p.P; a.b = p.b; a.m = p.m; a.rows_lim = 0;
@@ -836,11 +926,11 @@ static int blocked_leaves(pylom_ctx c, hipStream_t st, const Plan& p, char* ws, 
       a.X = Wk + c0 + kw; a.ldx = n; a.ncols = n - c0 - kw; a.nc_dev = nullptr; a.nc_off = 0;
       a.x_zero = 0; a.S = Rout + c0 * n + c0 + kw; a.s_leaf = n * n; a.s_ld = n;
       a.load_state = 0; a.store_state = 1; a.leaf_major = 0;
-      HIPCHK(c, launch_panel_apply<T>(a, false, st), "trailing update");
+      KT(KR_LEAF_TRAIL, launch_panel_apply<T>(a, false, st), "trailing update");
     }
   }
-  HIPCHK(c, launch_assemble_r<T>((int)n, p.P, (T*)(ws + p.oPSl), (int64_t)pps, Rout, n * n, st),
-         "R assembly");
+  KT(KR_LEAF_PANEL, launch_assemble_r<T>((int)n, p.P, (T*)(ws + p.oPSl), (int64_t)pps, Rout,
+                                         n * n, st), "R assembly");
   return PYLOM_OK;
 }
 
@@ -866,9 +956,10 @@ static int blocked_tree(pylom_ctx c, hipStream_t st, const Plan& p, char* ws) {
       const int64_t rows_lim = c0 + kw;
       double* Tk = Tb + k * tps;
       double* PSk = PSb + k * pps;
-      HIPCHK(c, launch_diag_load((int)n, c0, kw, np, R, rs, PSk, st), "pair state");
-      HIPCHK(c, launch_panel_qr<double>(g, Rb + c0, n, np * 2 * h * n, 2 * h * n, np, rows_lim, Tk,
-                                        p.nch_p, PSk, 2, st), "pair panel QR");
+      KT(KR_TREE_PANEL, launch_diag_load((int)n, c0, kw, np, R, rs, PSk, st), "pair state");
+      KT(KR_TREE_PANEL, launch_panel_qr<double>(g, Rb + c0, n, np * 2 * h * n, 2 * h * n, np,
+                                                rows_lim, Tk, p.nch_p, PSk, 2, st),
+         "pair panel QR");
       if (c0 + kw < n) {
         PanelApplyArgs<double> a{};
         a.kw = kw; a.npan = g.npanels; a.nlv = np; a.b = 2 * h * n; a.m = np * 2 * h * n;
@@ -876,10 +967,11 @@ static int blocked_tree(pylom_ctx c, hipStream_t st, const Plan& p, char* ws) {
         a.X = Rb + c0 + kw; a.ldx = n; a.ncols = n - c0 - kw; a.nc_dev = nullptr; a.nc_off = 0;
         a.x_zero = 0; a.S = R + c0 * n + c0 + kw; a.s_leaf = rs; a.s_ld = n;
         a.load_state = 1; a.store_state = 1; a.leaf_major = 0;
-        HIPCHK(c, launch_panel_apply<double>(a, false, st), "pair trailing update");
+        KT(KR_TREE_TRAIL, launch_panel_apply<double>(a, false, st), "pair trailing update");
       }
     }
-    HIPCHK(c, launch_assemble_r<double>((int)n, np, PSb, (int64_t)pps, R, rs, st), "R assembly");
+    KT(KR_TREE_PANEL, launch_assemble_r<double>((int)n, np, PSb, (int64_t)pps, R, rs, st),
+       "R assembly");
     base += np;
   }
   return PYLOM_OK;
@@ -915,7 +1007,7 @@ static int blocked_propagate(pylom_ctx c, hipStream_t st, const Plan& p, char* w
       a.nch = p.nch_p; a.X = W + h * n * n; a.ldx = n; a.ncols = ncols; a.nc_dev = nc_dev;
       a.nc_off = 0; a.x_zero = (k == p.K - 1); a.S = W + c0 * n; a.s_leaf = 2 * h * n * n;
       a.s_ld = n; a.load_state = 1; a.store_state = 1; a.leaf_major = 1;
-      HIPCHK(c, launch_panel_apply<double>(a, true, st), "tree propagation");
+      KT(KR_PROPAGATE, launch_panel_apply<double>(a, true, st), "tree propagation");
     }
   }
   return PYLOM_OK;
@@ -944,10 +1036,10 @@ static int blocked_leaf_apply(pylom_ctx c, hipStream_t st, const Plan& p, char* 
       a.X = Xu; a.ldx = p.wcap; a.ncols = ncg; a.nc_dev = nc_dev; a.nc_off = col0;
       a.x_zero = (k == p.K - 1); a.S = W + c0 * n + col0; a.s_leaf = n * n; a.s_ld = n;
       a.load_state = 1; a.store_state = 0; a.leaf_major = 1;
-      HIPCHK(c, launch_panel_apply<double>(a, true, st), "leaf apply");
+      KT(KR_LEAF_APPLY, launch_panel_apply<double>(a, true, st), "leaf apply");
     }
-    HIPCHK(c, launch_copy_cols(out_f64, p.m, col0, ncg, ncols, nc_dev, Xu, p.wcap, U, ldu, st),
-           "U out");
+    KT(KR_LEAF_APPLY, launch_copy_cols(out_f64, p.m, col0, ncg, ncols, nc_dev, Xu, p.wcap, U, ldu,
+                                       st), "U out");
   }
   return PYLOM_OK;
 }
@@ -962,8 +1054,8 @@ static int enqueue_fp64_blocked(pylom_ctx c, const Exec& x, const Plan& p, pylom
   const int in64 = dtype == PYLOM_R64;
   hipStream_t st = x.st;
   EVREC(0);
-  HIPCHK(c, launch_make_work(in64, 1, m, (int)n, D, ldd, remove_mean, meanws, x.ws + p.oWk, st),
-         "working copy");
+  KT(KR_WORK, launch_make_work(in64, 1, m, (int)n, D, ldd, remove_mean, meanws, x.ws + p.oWk, st),
+     "working copy");
   EVREC(1);
   int rc = blocked_leaves<double>(c, st, p, x.ws, Rbuf);
   if (rc) return rc;
@@ -972,9 +1064,9 @@ static int enqueue_fp64_blocked(pylom_ctx c, const Exec& x, const Plan& p, pylom
   if (rc) return rc;
   EVREC(3);
   JAC_BEFORE(p.jp);
-  HIPCHK(c, launch_small_svd(p.jp, Rbuf, x.max_sweeps, x.ws + p.oSvd, S, VT, ldvt,
-                             (double*)(x.ws + p.oW), residual, n_r, x.status, st, x.coop),
-         "small SVD");
+  KT(KR_SVD, launch_small_svd(p.jp, Rbuf, x.max_sweeps, x.ws + p.oSvd, S, VT, ldvt,
+                              (double*)(x.ws + p.oW), residual, n_r, x.status, st, x.coop),
+     "small SVD");
   JAC_AFTER(p.jp);
   EVREC(4);
   rc = blocked_propagate(c, st, p, x.ws, n_r, n);
@@ -992,22 +1084,22 @@ static int enqueue_mixed1_blocked(pylom_ctx c, const Exec& x, const Plan& p, con
   const int64_t m = p.m, n = p.n;
   hipStream_t st = x.st;
   EVREC(0);
-  HIPCHK(c, launch_make_work(0, 0, m, (int)n, D, ldd, remove_mean, keep_mean(x, p),
-                             x.ws + p.oWk, st), "working copy (FP32)");
+  KT(KR_WORK, launch_make_work(0, 0, m, (int)n, D, ldd, remove_mean, keep_mean(x, p),
+                               x.ws + p.oWk, st), "working copy (FP32)");
   EVREC(1);
   int rc = blocked_leaves<float>(c, st, p, x.ws, (float*)(x.ws + p.oR32));
   if (rc) return rc;
-  HIPCHK(c, launch_cast_f32_f64((const float*)(x.ws + p.oR32), (double*)(x.ws + p.oR), p.P * n * n,
-                                st), "R to FP64");
+  KT(KR_LEAF_PANEL, launch_cast_f32_f64((const float*)(x.ws + p.oR32), (double*)(x.ws + p.oR),
+                                        p.P * n * n, st), "R to FP64");
   EVREC(2);
   rc = blocked_tree(c, st, p, x.ws);
   if (rc) return rc;
   EVREC(3);
   JAC_BEFORE(p.jp);
-  HIPCHK(c, launch_small_svd(p.jp, (double*)(x.ws + p.oR), x.max_sweeps, x.ws + p.oSvd,
-                             keep_S0(x, p), keep_VT0(x, p), n, (double*)(x.ws + p.oW), residual,
-                             x.nr0 ? x.nr0 : (int64_t*)(x.ws + p.oNr0), x.status, st, x.coop),
-         "small SVD");
+  KT(KR_SVD, launch_small_svd(p.jp, (double*)(x.ws + p.oR), x.max_sweeps, x.ws + p.oSvd,
+                              keep_S0(x, p), keep_VT0(x, p), n, (double*)(x.ws + p.oW), residual,
+                              x.nr0 ? x.nr0 : (int64_t*)(x.ws + p.oNr0), x.status, st, x.coop),
+     "small SVD");
   JAC_AFTER(p.jp);
   if (x.evs) HIPCHK(c, hipEventRecord(x.evs[7], st), "hipEventRecord");
   return PYLOM_OK;
@@ -1022,22 +1114,21 @@ static int enqueue_mixed1(pylom_ctx c, const Exec& x, const Plan& p, const void*
   hipStream_t st = x.st;
   EVREC(0);
   EVREC(1);
-  HIPCHK(c, launch_leaf_qr_f32(p.g, (const float*)D, ldd, m, p.b, p.P, remove_mean,
-                               keep_mean(x, p), (float*)(x.ws + p.oR32), st),
-         "leaf QR (FP32)");
-  HIPCHK(c, launch_cast_f32_f64((const float*)(x.ws + p.oR32), (double*)(x.ws + p.oR), p.P * n * n,
-                                st), "R to FP64");
+  KT(KR_STACKED_LEAF, launch_leaf_qr_f32(p.g, (const float*)D, ldd, m, p.b, p.P, remove_mean,
+                                         keep_mean(x, p), (float*)(x.ws + p.oR32), st),
+     "leaf QR (FP32)");
+  KT(KR_STACKED_LEAF, launch_cast_f32_f64((const float*)(x.ws + p.oR32), (double*)(x.ws + p.oR),
+                                          p.P * n * n, st), "R to FP64");
   EVREC(2);
   for (int64_t h = 1; h < p.P; h *= 2)
-    HIPCHK(c, launch_tree_combine_f64(p.g, h, p.P, (double*)(x.ws + p.oR), nullptr, p.nch_tree, 0,
-                                      st), "tree combine");
+    KT(KR_STACKED_TREE, launch_tree_combine_f64(p.g, h, p.P, (double*)(x.ws + p.oR), nullptr,
+                                                p.nch_tree, 0, st), "tree combine");
   EVREC(3);
   JAC_BEFORE(p.jp);
-  HIPCHK(c, launch_small_svd(p.jp, (double*)(x.ws + p.oR), x.max_sweeps, x.ws + p.oSvd,
-                             keep_S0(x, p), keep_VT0(x, p), n,
-                             (double*)(x.ws + p.oW), residual,
-                             x.nr0 ? x.nr0 : (int64_t*)(x.ws + p.oNr0), x.status, st, x.coop),
-         "small SVD");
+  KT(KR_SVD, launch_small_svd(p.jp, (double*)(x.ws + p.oR), x.max_sweeps, x.ws + p.oSvd,
+                              keep_S0(x, p), keep_VT0(x, p), n, (double*)(x.ws + p.oW), residual,
+                              x.nr0 ? x.nr0 : (int64_t*)(x.ws + p.oNr0), x.status, st, x.coop),
+     "small SVD");
   JAC_AFTER(p.jp);
   // end of the first SVD (the host read-back of N0 follows)
   if (x.evs) HIPCHK(c, hipEventRecord(x.evs[7], st), "hipEventRecord");
@@ -1082,19 +1173,19 @@ static int enqueue_mixed2(pylom_ctx c, const Exec& x, const Plan& p, const void*
     double* WT = (double*)(x.ws + p.oWT);
     double* M = (double*)(x.ws + p.oM);
     const double* VT0 = keep_VT0(x, p);
-    HIPCHK(c, launch_rr_project(0, m, (int)n, (int)k, D, ldd, remove_mean ? meanws : nullptr, VT0,
-                                Z, st), "Rayleigh-Ritz projection");
-    HIPCHK(c, launch_matmul_tn(1, m, k, k, Z, k, Z, k, G, k, (double*)(x.ws + p.oPart), ns, st),
-           "Gram");
+    KT(KR_REFINE, launch_rr_project(0, m, (int)n, (int)k, D, ldd, remove_mean ? meanws : nullptr,
+                                    VT0, Z, st), "Rayleigh-Ritz projection");
+    KT(KR_REFINE, launch_matmul_tn(1, m, k, k, Z, k, Z, k, G, k, (double*)(x.ws + p.oPart), ns, st),
+       "Gram");
     JAC_BEFORE(jk);
-    HIPCHK(c, launch_small_svd(jk, G, x.max_sweeps, x.ws + p.oSvd2, lam, WT, k,
-                               (double*)(x.ws + p.oUR2), 0.0, (int64_t*)(x.ws + p.oNr2),
-                               x.status + 2, st, x.coop), "Gram eigen-decomposition");
+    KT(KR_REFINE, launch_small_svd(jk, G, x.max_sweeps, x.ws + p.oSvd2, lam, WT, k,
+                                   (double*)(x.ws + p.oUR2), 0.0, (int64_t*)(x.ws + p.oNr2),
+                                   x.status + 2, st, x.coop), "Gram eigen-decomposition");
     JAC_AFTER(jk);
-    HIPCHK(c, launch_rr_finish((int)n, (int)k, S0, lam, residual, S, n_r, WT, VT0, VT, ldvt, M,
-                               st), "refined spectrum");
+    KT(KR_REFINE, launch_rr_finish((int)n, (int)k, S0, lam, residual, S, n_r, WT, VT0, VT, ldvt,
+                                   M, st), "refined spectrum");
     EVREC(5);
-    HIPCHK(c, launch_rr_form_u(0, m, (int)k, Z, M, n_r, U, ldu, st), "form U");
+    KT(KR_FORM_U, launch_rr_form_u(0, m, (int)k, Z, M, n_r, U, ldu, st), "form U");
   }
   if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, 0, m, st), "mean out");
   EVREC(6);
@@ -1270,6 +1361,12 @@ static int batch_phase(pylom_ctx c, const BatchLayout& L, pylom_dtype dtype, int
 static int batch_run(pylom_ctx c, const BatchLayout& L, pylom_dtype dtype, int phase,
                      int64_t count, const pylom_problem* pr, const int64_t* nr_first,
                      bool use_graph, uint64_t key) {
+  // per-kernel events are recorded for single-problem calls only
+  struct KtOff {
+    pylom_ctx c;
+    explicit KtOff(pylom_ctx cc) : c(cc) { c->kt_off = true; }
+    ~KtOff() { c->kt_off = false; }
+  } kt_off(c);
   if (!use_graph) return batch_phase(c, L, dtype, phase, count, pr, nr_first, false, c->stream);
   // the graph is captured on, and replayed from, the context's own origin
   // stream, ordered after the caller's stream by events on both sides (the
@@ -1764,6 +1861,339 @@ extern "C" int pylom_dmd(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, c
 }
 
 // ---------------------------------------------------------------------------
+// out-of-core POD: row windows streamed from host memory (matrices larger
+// than the device)
+// ---------------------------------------------------------------------------
+// The column-blocked TSQR of the whole matrix with the rows held in host
+// memory.  Only the tree part (every leaf's R, the tree reflectors, the
+// propagation W, the mean and the SVD workspace: O(P n^2 + m) bytes) lives in
+// the device for the whole call; the rows pass through a window of wl leaves
+// twice.  Pass 1 streams each window in, removes the mean, factors its leaves
+// and keeps their R.  Then the tree, the SVD of R and the down-tree
+// propagation run once.  Pass 2 streams each window in again, factors its
+// leaves again (the same arithmetic on the same rows gives the same
+// reflectors, so no reflector ever leaves the device) and forms its rows of
+// U = Q [W; 0], which stream out.  The leaves, their R and every reflector
+// are those of the in-device column-blocked path at the same leaf height:
+// the results are identical.
+struct OocLayout {
+  Plan full;          // leaf geometry of the whole matrix and the tree part
+  int64_t wl = 0;     // leaves per window
+  int64_t nwin = 0;   // windows
+  int64_t wrows = 0;  // rows of the largest window
+  size_t oS = 0, oVT = 0, oNr = 0, oMeanOut = 0;
+  size_t oDin[2] = {}, oUo[2] = {};
+  size_t total = 0;
+};
+
+// Rows [r0, r1) and leaves [l0, l1) of window w.
+static void ooc_window(const OocLayout& L, int64_t w, int64_t* r0, int64_t* r1, int64_t* l0,
+                       int64_t* l1) {
+  const Plan& p = L.full;
+  *l0 = w * L.wl;
+  *l1 = std::min(p.P, *l0 + L.wl);
+  *r0 = *l0 * p.b;
+  *r1 = (*l1 == p.P) ? p.m : *l1 * p.b;
+}
+
+static int make_ooc_layout(pylom_ctx c, int64_t m, int64_t n, int in64, OocLayout* L) {
+  if (n < 1 || m < n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
+  if (n > kMaxN) return fail(c, PYLOM_ENOTSUP, "n > 2048 is not supported");
+  Plan& p = L->full;
+  p.m = m;
+  p.n = n;
+  p.mixed = false;
+  p.blocked = true;
+  p.zcap = n;
+  // default window: 2^20 rows (at least 4 n), at most the whole matrix
+  int64_t wr = c->ooc_window_rows > 0 ? c->ooc_window_rows : ((int64_t)1 << 20);
+  if (wr < 4 * n) wr = 4 * n;
+  if (wr > m) wr = m;
+  int64_t b = c->block_rows > 0 ? c->block_rows : blocked_block_rows(wr, n, c->ncu);
+  if (b < n) b = n;
+  if (b > wr) b = wr;
+  int64_t P = m / b;
+  if (P < 1) P = 1;
+  if (P > 65535) return fail(c, PYLOM_ENOTSUP, "too many leaves: raise block_rows");
+  p.b = b;
+  p.P = P;
+  p.last_rows = m - (P - 1) * b;
+  p.K = (n + kPW - 1) / kPW;
+  if (!qr_geom((int)(n < kPW ? n : kPW), 8, &p.gp) ||
+      !qr_geom((int)(n - (p.K - 1) * kPW), 8, &p.gpl) || p.gp.s != kPW || p.gpl.s != kPW)
+    return fail(c, PYLOM_ENOTSUP, "no panel geometry");
+  if (!jacobi_plan((int)n, &p.jp)) return fail(c, PYLOM_ENOTSUP, "no Jacobi plan");
+  p.g = p.gp;
+  p.nch_l = (p.last_rows + kPW - 1) / kPW;  // the largest leaf sets the T-factor slots
+  p.nch_p = (n + kPW - 1) / kPW;
+  p.nch_leaf = p.nch_l;
+  p.nch_tree = p.nch_p;
+  int64_t lv = 0;
+  for (int64_t h = 1; h < P; h *= 2) ++lv;
+  p.levels = lv;
+  p.wcap = n < 256 ? n : 256;
+  L->wl = std::max<int64_t>(1, wr / b);
+  L->nwin = (P + L->wl - 1) / L->wl;
+  {
+    int64_t r0, r1, l0, l1;
+    ooc_window(*L, L->nwin - 1, &r0, &r1, &l0, &l1);
+    L->wrows = std::max(L->wl * b, r1 - r0);
+  }
+  const int es = in64 ? 8 : 4;
+  const size_t tps = (size_t)kTF;
+  const int64_t np_all = P - 1;
+  size_t off = 0;
+  auto take = [&off](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  // tree part
+  p.oR = take(8 * (size_t)P * n * n);
+  p.oTp = take(8 * (size_t)p.K * np_all * p.nch_p * 4 * tps);
+  p.oPSp = take(8 * (size_t)p.K * np_all * kPW * kPW);
+  p.oW = take(8 * (size_t)P * n * n);
+  p.oMean = take(8 * (size_t)m);
+  p.oSig = take(8 * (size_t)n);
+  p.oSvd = take(jacobi_ws_bytes(p.jp, (int)c->max_sweeps));
+  L->oS = take(8 * (size_t)n);
+  L->oVT = take(8 * (size_t)n * n);
+  L->oNr = take(8);
+  L->oMeanOut = take((size_t)es * m);
+  // window part: working copy, leaf T factors and panel states, the FP64
+  // column-group buffer of the apply, two input and two output windows
+  p.oWk = take(8 * (size_t)L->wrows * n);
+  p.oTl = take(8 * (size_t)p.K * L->wl * p.nch_l * 4 * tps);
+  p.oPSl = take(8 * (size_t)p.K * L->wl * kPW * kPW);
+  p.oXu = take(8 * (size_t)L->wrows * p.wcap);
+  for (int k = 0; k < 2; ++k) L->oDin[k] = take((size_t)es * L->wrows * n);
+  for (int k = 0; k < 2; ++k) L->oUo[k] = take((size_t)es * L->wrows * n);
+  p.total = off;
+  L->total = off;
+  return PYLOM_OK;
+}
+
+// The plan of window w: its leaves and rows; R and W are those leaves' slots
+// of the whole-matrix buffers.
+static Plan ooc_window_plan(const OocLayout& L, int64_t w) {
+  int64_t r0, r1, l0, l1;
+  ooc_window(L, w, &r0, &r1, &l0, &l1);
+  Plan pw = L.full;
+  const int64_t n = pw.n;
+  pw.m = r1 - r0;
+  pw.P = l1 - l0;
+  pw.last_rows = pw.m - (pw.P - 1) * pw.b;
+  pw.oR = L.full.oR + 8 * (size_t)l0 * n * n;
+  pw.oW = L.full.oW + 8 * (size_t)l0 * n * n;
+  return pw;
+}
+
+// Host rows [r0, r1) of a row-major matrix with leading dimension ld
+// (elements of es bytes) to or from a packed buffer of `cols` columns, on
+// several host threads.
+static void host_rows_copy(char* dst, int64_t ldd_dst, const char* src, int64_t ld_src,
+                           int64_t rows, int64_t cols, int es) {
+  const size_t row_bytes = (size_t)cols * es;
+  const size_t total = row_bytes * (size_t)rows;
+  unsigned nt = std::thread::hardware_concurrency();
+  if (nt < 1) nt = 1;
+  if (nt > 8) nt = 8;
+  if (total < ((size_t)8 << 20)) nt = 1;
+  auto work = [&](int64_t a, int64_t b) {
+    if (ldd_dst == cols && ld_src == cols) {
+      std::memcpy(dst + (size_t)a * row_bytes, src + (size_t)a * row_bytes,
+                  (size_t)(b - a) * row_bytes);
+      return;
+    }
+    for (int64_t r = a; r < b; ++r)
+      std::memcpy(dst + (size_t)r * ldd_dst * es, src + (size_t)r * ld_src * es, row_bytes);
+  };
+  if (nt == 1) {
+    work(0, rows);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t per = (rows + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    const int64_t a = t * per, b = std::min(rows, a + per);
+    if (a < b) th.emplace_back(work, a, b);
+  }
+  for (auto& t : th) t.join();
+}
+
+static int ooc_resources(pylom_ctx c, size_t pin_bytes) {
+  if (!c->cs_in)
+    HIPCHK(c, hipStreamCreateWithFlags(&c->cs_in, hipStreamNonBlocking), "hipStreamCreate");
+  if (!c->cs_out)
+    HIPCHK(c, hipStreamCreateWithFlags(&c->cs_out, hipStreamNonBlocking), "hipStreamCreate");
+  for (hipEvent_t& e : c->ooc_ev)
+    if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+  if (c->pin_bytes < pin_bytes) {
+    for (int k = 0; k < 2; ++k) {
+      if (c->pin_in[k]) hipHostFree(c->pin_in[k]);
+      if (c->pin_out[k]) hipHostFree(c->pin_out[k]);
+      c->pin_in[k] = c->pin_out[k] = nullptr;
+    }
+    c->pin_bytes = 0;
+    for (int k = 0; k < 2; ++k) {
+      if (hipHostMalloc(&c->pin_in[k], pin_bytes, hipHostMallocDefault) != hipSuccess ||
+          hipHostMalloc(&c->pin_out[k], pin_bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, PYLOM_ENOMEM, "pinned host staging allocation failed");
+      }
+    }
+    c->pin_bytes = pin_bytes;
+  }
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_ooc_workspace_query(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n,
+                                         size_t* bytes, int64_t* window_rows, int64_t* windows) {
+  if (!c || !bytes) return PYLOM_EINVAL;
+  if (dtype != PYLOM_R64 && dtype != PYLOM_R32) return fail(c, PYLOM_EDTYPE, "dtype");
+  OocLayout L;
+  const int rc = make_ooc_layout(c, m, n, dtype == PYLOM_R64, &L);
+  if (rc) return rc;
+  *bytes = L.total;
+  if (window_rows) *window_rows = L.wl * L.full.b;
+  if (windows) *windows = L.nwin;
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_pod_host(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m,
+                              int64_t n, const void* D, int64_t ldd, int remove_mean,
+                              double residual, void* mean, void* U, int64_t ldu, double* S,
+                              double* VT, int64_t ldvt, int64_t* n_r) {
+  int rc = check_common(c, dtype, prec);
+  if (rc) return rc;
+  if (prec != PYLOM_FP64) return fail(c, PYLOM_ENOTSUP, "the out-of-core path computes in FP64");
+  if (!D || !U || !S || !VT || !n_r) return fail(c, PYLOM_EINVAL, "null array argument");
+  if (!(residual >= 0.0 && residual < 1.0)) return fail(c, PYLOM_EINVAL, "residual must be in [0, 1)");
+  if (n < 1 || m < n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
+  if (ldd < n || ldu < n || ldvt < n) return fail(c, PYLOM_ESHAPE, "leading dimension < n");
+  const int in64 = dtype == PYLOM_R64;
+  const int es = in64 ? 8 : 4;
+  OocLayout L;
+  rc = make_ooc_layout(c, m, n, in64, &L);
+  if (rc) return rc;
+  if ((rc = cap_check(c, L.total))) return rc;
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+  rc = ensure_ws(c, L.total);
+  if (rc) return rc;
+  const size_t win_bytes = (size_t)es * L.wrows * n;
+  rc = ooc_resources(c, win_bytes);
+  if (rc) return rc;
+  const Plan& p = L.full;
+  char* ws = (char*)c->ws;
+  hipStream_t st = c->stream;
+  hipEvent_t* ev_h2d = c->ooc_ev;      // [2] window copied in
+  hipEvent_t* ev_free = c->ooc_ev + 2; // [2] the device input window is free again
+  hipEvent_t* ev_u = c->ooc_ev + 4;    // [2] U window formed
+  hipEvent_t* ev_d2h = c->ooc_ev + 6;  // [2] U window copied out
+  double* meanws = (double*)(ws + p.oMean);
+  // the compute stream's earlier work precedes the copies
+  HIPCHK(c, hipEventRecord(ev_free[0], st), "hipEventRecord");
+  HIPCHK(c, hipEventRecord(ev_free[1], st), "hipEventRecord");
+  HIPCHK(c, hipEventRecord(ev_h2d[0], st), "hipEventRecord");
+  HIPCHK(c, hipEventRecord(ev_h2d[1], st), "hipEventRecord");
+  HIPCHK(c, hipEventRecord(ev_d2h[0], st), "hipEventRecord");
+  HIPCHK(c, hipEventRecord(ev_d2h[1], st), "hipEventRecord");
+
+  // stage window w into device buffer k: the host copy into the pinned
+  // buffer waits for that buffer's previous transfer; the transfer waits for
+  // the compute that last read the device buffer
+  auto stage_in = [&](int64_t w, int k) -> int {
+    int64_t r0, r1, l0, l1;
+    ooc_window(L, w, &r0, &r1, &l0, &l1);
+    HIPCHK(c, hipEventSynchronize(ev_h2d[k]), "hipEventSynchronize");
+    host_rows_copy((char*)c->pin_in[k], n, (const char*)D + (size_t)r0 * ldd * es, ldd, r1 - r0,
+                   n, es);
+    HIPCHK(c, hipStreamWaitEvent(c->cs_in, ev_free[k], 0), "hipStreamWaitEvent");
+    HIPCHK(c, hipMemcpyAsync(ws + L.oDin[k], c->pin_in[k], (size_t)es * (r1 - r0) * n,
+                             hipMemcpyHostToDevice, c->cs_in), "window in");
+    HIPCHK(c, hipEventRecord(ev_h2d[k], c->cs_in), "hipEventRecord");
+    HIPCHK(c, hipStreamWaitEvent(st, ev_h2d[k], 0), "hipStreamWaitEvent");
+    return PYLOM_OK;
+  };
+  // leaf QR of window w from device buffer k (mean removal fused)
+  auto factor = [&](int64_t w, int k) -> int {
+    int64_t r0, r1, l0, l1;
+    ooc_window(L, w, &r0, &r1, &l0, &l1);
+    const Plan pw = ooc_window_plan(L, w);
+    KT(KR_WORK, launch_make_work(in64, 1, r1 - r0, (int)n, ws + L.oDin[k], n, remove_mean,
+                                 meanws + r0, ws + p.oWk, st), "working copy");
+    HIPCHK(c, hipEventRecord(ev_free[k], st), "hipEventRecord");
+    return blocked_leaves<double>(c, st, pw, ws, (double*)(ws + pw.oR));
+  };
+
+  // pass 1: every leaf's R
+  for (int64_t w = 0; w < L.nwin; ++w) {
+    const int k = (int)(w & 1);
+    if ((rc = stage_in(w, k))) return rc;
+    if ((rc = factor(w, k))) return rc;
+  }
+  // the tree, the SVD of the root R with truncation, the down-tree propagation
+  rc = blocked_tree(c, st, p, ws);
+  if (rc) return rc;
+  double* Sd = (double*)(ws + L.oS);
+  double* VTd = (double*)(ws + L.oVT);
+  int64_t* nrd = (int64_t*)(ws + L.oNr);
+  KT(KR_SVD, launch_small_svd(p.jp, (double*)(ws + p.oR), (int)c->max_sweeps, ws + p.oSvd, Sd,
+                              VTd, n, (double*)(ws + p.oW), residual, nrd, c->status_dev, st,
+                              true), "small SVD");
+  c->status_valid = 1;
+  c->status_pairs = 1;
+  rc = blocked_propagate(c, st, p, ws, nrd, n);
+  if (rc) return rc;
+  int64_t nr = 0;
+  HIPCHK(c, hipMemcpyAsync(&nr, nrd, sizeof(int64_t), hipMemcpyDeviceToHost, st), "N_r read-back");
+  HIPCHK(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+  HIPCHK(c, hipMemcpy(S, Sd, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost), "S out");
+  for (int64_t i = 0; i < nr; ++i)
+    HIPCHK(c, hipMemcpy(VT + (size_t)i * ldvt, VTd + (size_t)i * n, sizeof(double) * (size_t)n,
+                        hipMemcpyDeviceToHost), "VT out");
+  *n_r = nr;
+  if (remove_mean && mean) {
+    HIPCHK(c, launch_cast_out(meanws, ws + L.oMeanOut, in64, m, st), "mean out");
+    HIPCHK(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    HIPCHK(c, hipMemcpy(mean, ws + L.oMeanOut, (size_t)es * m, hipMemcpyDeviceToHost), "mean out");
+  }
+  if (nr == 0) return PYLOM_OK;
+  // pass 2: the leaves again, U = Q [W; 0] window by window
+  auto drain = [&](int64_t w, int k) -> int {  // U rows of window w to the caller
+    int64_t r0, r1, l0, l1;
+    ooc_window(L, w, &r0, &r1, &l0, &l1);
+    HIPCHK(c, hipEventSynchronize(ev_d2h[k]), "hipEventSynchronize");
+    host_rows_copy((char*)U + (size_t)r0 * ldu * es, ldu, (const char*)c->pin_out[k], nr,
+                   r1 - r0, nr, es);
+    return PYLOM_OK;
+  };
+  for (int64_t w = 0; w < L.nwin; ++w) {
+    const int k = (int)(w & 1);
+    if ((rc = stage_in(w, k))) return rc;
+    if ((rc = factor(w, k))) return rc;
+    int64_t r0, r1, l0, l1;
+    ooc_window(L, w, &r0, &r1, &l0, &l1);
+    const Plan pw = ooc_window_plan(L, w);
+    HIPCHK(c, hipStreamWaitEvent(st, ev_d2h[k], 0), "hipStreamWaitEvent");
+    rc = blocked_leaf_apply(c, st, pw, ws, nullptr, nr, ws + L.oUo[k], in64, nr);
+    if (rc) return rc;
+    HIPCHK(c, hipEventRecord(ev_u[k], st), "hipEventRecord");
+    if (w >= 2 && (rc = drain(w - 2, k))) return rc;  // frees pin_out[k]
+    HIPCHK(c, hipStreamWaitEvent(c->cs_out, ev_u[k], 0), "hipStreamWaitEvent");
+    HIPCHK(c, hipMemcpyAsync(c->pin_out[k], ws + L.oUo[k], (size_t)es * (r1 - r0) * nr,
+                             hipMemcpyDeviceToHost, c->cs_out), "window out");
+    HIPCHK(c, hipEventRecord(ev_d2h[k], c->cs_out), "hipEventRecord");
+  }
+  for (int64_t w = std::max<int64_t>(0, L.nwin - 2); w < L.nwin; ++w)
+    if ((rc = drain(w, (int)(w & 1)))) return rc;
+  // the context stream follows the copies
+  HIPCHK(c, hipStreamSynchronize(c->cs_out), "hipStreamSynchronize");
+  return PYLOM_OK;
+}
+
+// ---------------------------------------------------------------------------
 // SPOD: FFT front end + one batch of realified TSQR-SVD problems
 // ---------------------------------------------------------------------------
 struct SpodPlan {
@@ -1957,6 +2387,30 @@ extern "C" int pylom_phase_times(pylom_ctx c, double* out, int cap) {
   for (int i = 0; i < kPhases && i < cap; ++i) out[i] = acc[i] / (double)nrec;
   c->ev_calls = 0;
   return kPhases;
+}
+
+extern "C" int pylom_kernel_times(pylom_ctx c, double* ms, int64_t* launches, int cap) {
+  if (!c || cap < 0 || (cap > 0 && (!ms || !launches))) return PYLOM_EINVAL;
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  if (!c->ktiming) return fail(c, PYLOM_EINVAL, "kernel_timing is off");
+  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+  double acc[KR_COUNT] = {};
+  int64_t cnt[KR_COUNT] = {};
+  for (const auto& mk : c->kmarks) {
+    HIPCHK(c, hipEventSynchronize(c->kev[mk.second + 1]), "hipEventSynchronize");
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, c->kev[mk.second], c->kev[mk.second + 1]),
+           "hipEventElapsedTime");
+    acc[mk.first] += t;
+    cnt[mk.first] += 1;
+  }
+  for (int i = 0; i < KR_COUNT && i < cap; ++i) {
+    ms[i] = acc[i];
+    launches[i] = cnt[i];
+  }
+  c->kmarks.clear();
+  c->kev_next = 0;
+  return KR_COUNT;
 }
 
 extern "C" int pylom_check(pylom_ctx c, int64_t* sweeps) {

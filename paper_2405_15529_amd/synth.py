@@ -108,6 +108,22 @@ def travelling_wave_params(m: int, seed: int = 2, nwaves: int = 64):
     return kap, w, th, a
 
 
+def travelling_waves_rows(m: int, n: int, r0: int, r1: int, seed: int = 2, nwaves: int = 64,
+                          noise: float = 1e-4, dtype=np.float32) -> np.ndarray:
+    """Rows r0..r1-1 of the m-row travelling-wave field of
+    ``travelling_waves_device`` (same wave parameters and grid), formed on
+    the host; the noise term is drawn by numpy (seeded by seed and r0), not
+    by the device generator."""
+    kap, w, th, a = travelling_wave_params(m, seed, nwaves)
+    x = 2.0 * np.pi * np.arange(r0, r1, dtype=np.float64) / m
+    t = np.arange(n, dtype=np.float64)
+    arg = np.outer(w, t) - th[:, None]
+    D = (np.cos(np.outer(x, kap)) @ (a[:, None] * np.cos(arg))
+         + np.sin(np.outer(x, kap)) @ (a[:, None] * np.sin(arg)))
+    D += noise * np.random.default_rng([seed, r0]).standard_normal(D.shape)
+    return np.ascontiguousarray(D.astype(dtype))
+
+
 def travelling_waves_device(m: int, n: int, seed: int = 2, nwaves: int = 64,
                             noise: float = 1e-4, device: str = "cuda", rows_per_pass: int = 131072):
     """Device-side twin of ``travelling_waves`` for large m (FP32, m x n):

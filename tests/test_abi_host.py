@@ -357,3 +357,26 @@ def test_binding_rejects_host_tensors():
                  lambda: api.spod(A.float())):
         with pytest.raises(ValueError):
             call()
+
+
+def test_ooc_plan_and_failure_paths(hctx):
+    # windows of whole leaves; the device holds the tree part and two windows
+    hctx.set_option("block_rows", 1024)
+    hctx.set_option("ooc_window_rows", 4096)
+    ws, rows, nwin = api.ooc_query(20000, 100, api.R64, hctx)
+    assert rows == 4096 and nwin == 5            # 19 leaves, 4 per window
+    hctx.set_option("ooc_window_rows", 100)      # raised to 4 n = 400: leaves of 400 rows,
+    ws2, rows2, nwin2 = api.ooc_query(20000, 100, api.R64, hctx)   # one per window
+    assert rows2 == 400 and nwin2 == 50 and ws2 < ws
+    vp = ctypes.c_void_p
+    one = ctypes.c_int64(0)
+
+    def call(prec=api.FP64, cap=0, m=20000, n=100):
+        hctx.set_option("ws_cap_mb", cap)
+        return hctx.lib.pylom_pod_host(hctx.h, api.R64, prec, m, n, vp(1), n, 1, 0.01, vp(0),
+                                       vp(1), n, vp(1), vp(1), n, ctypes.byref(one))
+    assert call() == -7                          # valid: only the device is missing
+    assert call(cap=1) == -4                     # over the workspace cap: PYLOM_ENOMEM
+    assert call(prec=api.MIXED) == -6            # FP64 compute only
+    assert call(m=50, n=100) == -2
+    hctx.set_option("ws_cap_mb", 0)

@@ -1,4 +1,4 @@
-"""GPU checks at the shapes of the paper's performance study (Sec. 4), in the
+"""GPU checks at the shapes of the paper's performance study (Sec. 5), in the
 launch configurations bench.py --paper-shapes times.  The oracle cannot
 finish these shapes, so each test checks what holds at any size or what it
 can recompute on sampled rows:
