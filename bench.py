@@ -58,6 +58,12 @@ def parse():
     ap.add_argument("--spod-nt", type=int, default=2048)
     ap.add_argument("--spod-steps", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-ooc", action="store_true")
+    ap.add_argument("--only-ooc", action="store_true",
+                    help="run only the out-of-core leg and print its object")
+    ap.add_argument("--ooc-m", type=int, default=8_388_608)
+    ap.add_argument("--ooc-n", type=int, default=256)
+    ap.add_argument("--ooc-window", type=int, default=1_048_576)
     ap.add_argument("--no-dmd", action="store_true")
     ap.add_argument("--dmd-wide", action="store_true",
                     help="also time exact DMD of the headline field (N = 1808 snapshots)")
@@ -197,6 +203,14 @@ TRAFFIC = {
         "sources_sha256": "0623733ccd8603f060147c06517f02aa27e381df97a66cca21b98b788aab9a20",
         "shape": (1048576, 256, 4096),
         "bytes": 13614639179,  # FETCH 6.575e+09 (x1.99994) + WRITE 7.04e+09 (x1.0)
+    },
+    # FP32 leaf trailing updates of the column-blocked QR, 4194304 x 1808, row
+    # blocks 8192: mean over the 28 launches of one mixed call
+    "blocked_trailing_fp32": {
+        "sources": ("blocked.hip", "common.hpp"),
+        "sources_sha256": "57cbe4593008bf0f483dc2c578c21dc6f6cce99a35dcd6906c75a9aabfd8c1f2",
+        "shape": (4194304, 1808, 8192),
+        "bytes": 33350109656,  # FETCH 5.068e+11 (x1.99991) + WRITE 4.270e+11 (x1.0), / 28
     },
 }
 
@@ -681,6 +695,66 @@ def timed_dmd_wide(api, m, n, steps, warmup):
     }
 
 
+def timed_ooc(api, m, n, window_rows, steps):
+    """Out-of-core POD (pylom_pod_host) of an m x n FP32 travelling-wave field
+    held in host memory, streamed through the device in windows of
+    window_rows rows (two passes), against the in-device POD of the same
+    matrix on the same path and leaf height.  Rates count the host traffic
+    of the two passes (2 x 4 m n read, 4 m N_r written) over the wall time
+    of the call, which includes every PCIe transfer and host-side copy."""
+    import numpy as np
+    import torch
+    from paper_2405_15529_amd import synth
+
+    Dd = synth.travelling_waves_device(m, n, seed=2, device="cuda")
+    D = Dd.cpu().numpy()
+    torch.cuda.synchronize()
+    # leaves of window_rows / 512 rows: two per CU within a window
+    b = max(n, window_rows // 512)
+    ctx = api.Context(0)
+    ctx.set_option("ooc_window_rows", window_rows)
+    ctx.set_option("block_rows", b)
+    ws, rows, nwin = api.ooc_query(m, n, api.R32, ctx)
+    U = np.empty((m, n), dtype=np.float32)
+    api.pod_host(D, remove_mean=True, r=0.01, ctx=ctx, U=U)   # warm-up: workspace, staging
+    times = []
+    h = None
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        h = api.pod_host(D, remove_mean=True, r=0.01, ctx=ctx, U=U)
+        times.append(time.perf_counter() - t0)
+    rc, _ = ctx.status()
+    ctx.close()
+    # the same matrix resident on the device, column-blocked at the same leaf height
+    ctx2 = api.Context(0)
+    ctx2.set_option("blocked_from", 2)
+    ctx2.set_option("block_rows", b)
+    ctx2.bind_stream()
+    g = api.pod(Dd, remove_mean=True, r=0.01, ctx=ctx2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = api.pod(Dd, remove_mean=True, r=0.01, ctx=ctx2)
+    torch.cuda.synchronize()
+    t_dev = time.perf_counter() - t0
+    Sg = g.S.cpu().numpy()
+    same = bool(np.array_equal(Sg, h.S))
+    ctx2.close()
+    del Dd, g
+    torch.cuda.empty_cache()
+    t = min(times)
+    host_bytes = 2.0 * 4 * m * n + 4.0 * m * h.nr
+    return {
+        "workload": f"out-of-core POD of a {m}x{n} FP32 travelling-wave field in host memory, "
+                    f"mean removed, 99% energy, windows of {rows} rows ({nwin} windows, two "
+                    f"passes), leaves of {b} rows",
+        "s_per_call": round(t, 4), "host_gbps": round(host_bytes / t / 1e9, 2),
+        "tflops": round((2.0 * m * n * n + 2.0 * m * n * h.nr) / t / 1e12, 4),
+        "in_device_s_per_call": round(t_dev, 4), "n_r": h.nr, "status": rc,
+        "sigma_equal_to_in_device": same, "device_workspace_gb": round(ws / 1e9, 2),
+        "steps": steps,
+    }
+
+
 def timed_batch(api, count, seed, steps, warmup):
     """Uneven POD batch: `count` instances, m log-uniform in [5e4, 2e6], n
     uniform in [32, 512], FP32 known spectra s_i = 10^(-6i/n), 99 % energy.
@@ -864,6 +938,10 @@ def main():
     import torch
     from paper_2405_15529_amd import api
 
+    if args.only_ooc:
+        print(json.dumps({"out_of_core": timed_ooc(api, args.ooc_m, args.ooc_n, args.ooc_window,
+                                                   2)}), flush=True)
+        return
     if args.paper_shapes:
         print(json.dumps({"paper_shapes": timed_paper_shapes(api, 2, 1 if args.warmup else 0)}),
               flush=True)
@@ -926,6 +1004,10 @@ def main():
     if not args.no_dmd:
         out["dmd"] = timed_dmd(api, args.dmd_m, args.dmd_n, 2, 1 if args.warmup else 0)
         print(f"[bench] dmd: {out['dmd']['ms_per_step']} ms", file=sys.stderr, flush=True)
+    if not args.no_ooc:
+        out["out_of_core"] = timed_ooc(api, args.ooc_m, args.ooc_n, args.ooc_window, 2)
+        print(f"[bench] out-of-core: {out['out_of_core']['s_per_call']} s", file=sys.stderr,
+              flush=True)
     if not args.no_batch:
         out["uneven_batch"] = timed_batch(api, args.batch_count, 4, args.batch_steps,
                                           1 if args.warmup else 0)
