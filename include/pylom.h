@@ -97,6 +97,13 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
  *   "timing"       k > 0: record HIP events around the phases of every
  *                  pod/tsvd call in a ring of k call slots (read back with
  *                  pylom_phase_times); 0 = off (default).
+ *   "work_queue"   0 (default, and the only value accepted): one launch per
+ *                  phase and tree level.  1 would run the leaf QRs and tree
+ *                  combines of the stacked FP64 TSQR as one persistent launch
+ *                  draining a device task counter (and the propagation and
+ *                  leaf applies likewise); it is switched off and returns
+ *                  PYLOM_ENOTSUP, because that launch did not complete on the
+ *                  GPU and its cause is not known.
  *   "ooc_window_rows" rows per window of pylom_pod_host (0 = automatic,
  *                  2^20; at least 4 n; rounded down to whole leaves).
  *   "kernel_timing" 1: record an event pair around every kernel launch of
@@ -287,6 +294,30 @@ int pylom_pod_batched(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t
  * "blocked_from"), ceil(m / (2 CUs)) rounded up to a multiple of 64 (at
  * least n).  Host only; n <= 2048. */
 int64_t pylom_tune_block_rows(pylom_ctx ctx, int64_t m, int64_t n);
+
+/* Measured leaf height (the "block-row shape" of the TSQR) for an m x n
+ * pylom_pod of this dtype, precision and mean removal: times pylom_pod on D
+ * (device, m x n, ldd) with each candidate leaf height of the path the
+ * context would take (column-blocked: one to four leaves per CU; stacked:
+ * 128 ... 32768 rows; the analytic choice always included), `reps` timed
+ * calls each after one warm-up, 99 % energy, on the context stream with HIP
+ * events, and records the fastest in the context's table under the key
+ * (path, precision, floor(log2 m), n rounded up to 16).  While "block_rows"
+ * is 0, every later call whose shape falls under a recorded key uses that
+ * height.  Writes the height and its mean milliseconds (either pointer may
+ * be NULL).  Allocates its own trial outputs; synchronises the stream. */
+int pylom_autotune(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int64_t m, int64_t n,
+                   const void* D, int64_t ldd, int remove_mean, int reps, int64_t* best_rows,
+                   double* best_ms);
+/* The context's measured table as a JSON file at `path` (host path):
+ *   {"pylom_tuning": 1, "entries": [{"path": "blocked"|"stacked",
+ *    "precision": "fp64"|"mixed", "m_log2": L, "n_bucket": N,
+ *    "block_rows": B, "ms": T}, ...]} */
+int pylom_tune_save(pylom_ctx ctx, const char* path);
+/* Merges the entries of such a file into the context's table; returns the
+ * number of entries read, or PYLOM_EINVAL for a missing or malformed file
+ * (the table is then unchanged).  Works on host-only contexts too. */
+int pylom_tune_load(pylom_ctx ctx, const char* path);
 
 /* SPOD (Alg. 6; Sec. 2.3, Eq. csdimp with the SVD of the spectral matrix).
  *

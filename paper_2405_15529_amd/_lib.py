@@ -56,6 +56,10 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_size_t)]),
     "pylom_pod_batched": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int, I64, VP, ctypes.c_int]),
     "pylom_tune_block_rows": (I64, [VP, I64, I64]),
+    "pylom_autotune": (ctypes.c_int, [VP, ctypes.c_int, ctypes.c_int, I64, I64, VP, I64,
+                                      ctypes.c_int, ctypes.c_int, I64P, DP]),
+    "pylom_tune_save": (ctypes.c_int, [VP, ctypes.c_char_p]),
+    "pylom_tune_load": (ctypes.c_int, [VP, ctypes.c_char_p]),
     "pylom_dmd": (ctypes.c_int, [VP, ctypes.c_int, I64, I64, VP, I64, ctypes.c_int, ctypes.c_double,
                                  ctypes.c_double, VP, I64, VP, VP, VP, VP, VP]),
     "pylom_dmd_workspace_query": (ctypes.c_int, [VP, ctypes.c_int, I64, I64, ctypes.c_int,

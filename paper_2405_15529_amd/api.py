@@ -144,6 +144,26 @@ class Context:
             raise PylomError(rc, self.lib.pylom_last_error(self.h).decode())
         return {k: buf[i] for i, k in enumerate(self.PHASES)}
 
+    def autotune(self, D: torch.Tensor, precision: str = "fp64", remove_mean: bool = True,
+                 reps: int = 2):
+        """Time every candidate leaf height of pylom_pod on D and record the
+        fastest for this shape class (pylom_autotune); returns (rows, ms)."""
+        _rowmajor(D, "D")
+        _on_gpu(D, "D")
+        m, n = D.shape
+        b, t = ctypes.c_int64(), ctypes.c_double()
+        self.bind_stream()
+        self.check(self.lib.pylom_autotune(self.h, _dtype_code(D), _PREC[precision], m, n,
+                                           _ptr(D), D.stride(0), int(bool(remove_mean)), int(reps),
+                                           ctypes.byref(b), ctypes.byref(t)))
+        return b.value, t.value
+
+    def tune_save(self, path: str):
+        self.check(self.lib.pylom_tune_save(self.h, str(path).encode()))
+
+    def tune_load(self, path: str) -> int:
+        return self.check(self.lib.pylom_tune_load(self.h, str(path).encode()))
+
     KERNEL_ROLES = ("working_copy", "leaf_panel_qr", "leaf_trailing_update", "tree_panel_qr",
                     "tree_trailing_update", "small_svd", "tree_propagate", "leaf_apply",
                     "refine", "refine_form_u", "stacked_leaf_qr", "stacked_tree")

@@ -13,7 +13,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <sstream>
+#include <tuple>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -68,6 +72,13 @@ struct pylom_ctx_s {
   void* pin_out[2] = {};
   size_t pin_bytes = 0;
   int64_t ooc_window_rows = 0;     // option "ooc_window_rows" (0: automatic)
+  // option "work_queue": the TSQR phases as work-queue launches.  Switched
+  // off: the queue launch of a stacked POD did not complete on the GPU (two
+  // runs, the second after its spin loop was changed), with no cause found;
+  // the option refuses 1 until one is.
+  int64_t work_queue = 0;
+  // measured leaf heights (pylom_autotune / pylom_tune_load): key -> (rows, ms)
+  std::map<std::tuple<int, int, int, int64_t>, std::pair<int64_t, double>> tuned;
   int64_t ktiming = 0;
   bool kt_off = false;             // set while a batch is enqueued or captured
   std::vector<hipEvent_t> kev;     // event pool; pairs (start, end)
@@ -296,6 +307,13 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
   } else if (!std::strcmp(key, "streams")) {
     if (v < 1 || v > 16) return fail(c, PYLOM_EINVAL, "streams must be in [1, 16]");
     c->streams = v;
+  } else if (!std::strcmp(key, "work_queue")) {
+    if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "work_queue must be 0 or 1");
+    if (v == 1)
+      return fail(c, PYLOM_ENOTSUP,
+                  "work_queue is switched off: its launch did not complete on the GPU");
+    c->work_queue = v;
+    drop_graphs(c);
   } else if (!std::strcmp(key, "ooc_window_rows")) {
     if (v < 0) return fail(c, PYLOM_EINVAL, "ooc_window_rows must be >= 0");
     c->ooc_window_rows = v;
@@ -344,6 +362,8 @@ extern "C" int pylom_get_option(pylom_ctx c, const char* key, int64_t* v) {
     *v = c->ktiming;
   else if (!std::strcmp(key, "ooc_window_rows"))
     *v = c->ooc_window_rows;
+  else if (!std::strcmp(key, "work_queue"))
+    *v = c->work_queue;
   else if (!std::strcmp(key, "batch_jacobi_chained"))
     *v = c->last_jac_chain;
   else
@@ -418,6 +438,8 @@ struct Plan {
   JacobiPlan jp;
   // workspace offsets (bytes)
   size_t oV, oTleaf, oR, oTtree, oW, oMean, oSig, oSvd, total;
+  // work-queue counters of the stacked FP64 sequence (reduce, broadcast)
+  size_t oQ1 = 0, oQ2 = 0, q1_bytes = 0, q2_bytes = 0;
   // mixed precision only: FP32 leaf R, first SVD, refinement buffers
   bool mixed;
   size_t oR32, oS0, oVT0, oNr0, oZ, oG, oPart, oLam, oWT, oUR2, oNr2, oM, oSvd2;
@@ -518,13 +540,31 @@ static bool use_blocked(const pylom_ctx_s* c, int64_t m, int64_t n, bool batched
   return n >= 512 || (n >= 64 && m <= ((int64_t)8 << 20));
 }
 
+static int64_t tune_lookup(const pylom_ctx_s* c, bool blocked, bool mixed, int64_t m, int64_t n);
+
 extern "C" int64_t pylom_tune_block_rows(pylom_ctx c, int64_t m, int64_t n) {
   if (!c || n < 1 || m < n || n > kMaxN) return PYLOM_EINVAL;
-  if (use_blocked(c, m, n)) return blocked_block_rows(m, n, c->ncu);
+  const bool blk = use_blocked(c, m, n);
+  const int64_t t = tune_lookup(c, blk, false, m, n);
+  if (t > 0) return t < n ? n : t;
+  if (blk) return blocked_block_rows(m, n, c->ncu);
   return tune_block_rows(c, m, n);
 }
 
 static int make_blocked_plan(pylom_ctx c, Plan* p, bool mixed);
+
+// Key of the measured leaf-height table: path (1 = column-blocked), mixed
+// precision, floor(log2 m), n rounded up to a multiple of 16.
+static std::tuple<int, int, int, int64_t> tune_key(bool blocked, bool mixed, int64_t m,
+                                                   int64_t n) {
+  int lg = 0;
+  while (((int64_t)1 << (lg + 1)) <= m) ++lg;
+  return std::make_tuple(blocked ? 1 : 0, mixed ? 1 : 0, lg, (n + 15) / 16 * 16);
+}
+static int64_t tune_lookup(const pylom_ctx_s* c, bool blocked, bool mixed, int64_t m, int64_t n) {
+  auto it = c->tuned.find(tune_key(blocked, mixed, m, n));
+  return it == c->tuned.end() ? 0 : it->second.first;
+}
 
 static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
                      bool mixed = false, bool batched = false) {
@@ -537,7 +577,9 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
   p->m = m;
   p->n = n;
   if (use_blocked(c, m, n, batched)) return make_blocked_plan(c, p, mixed);
-  int64_t b = c->block_rows > 0 ? c->block_rows : tune_block_rows(c, m, n, mixed);
+  int64_t b = c->block_rows;
+  if (b <= 0) b = tune_lookup(c, false, mixed, m, n);
+  if (b <= 0) b = tune_block_rows(c, m, n, mixed);
   if (b < n) b = n;
   int64_t P = m / b;
   if (P < 1) P = 1;
@@ -578,6 +620,14 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
   off = align_up(off + sizeof(double) * (size_t)n);
   p->oSvd = off;
   off = align_up(off + jacobi_ws_bytes(p->jp, (int)c->max_sweeps));
+  if (!mixed) {
+    p->q1_bytes = queue_counter_bytes(1, P, 1);
+    p->q2_bytes = queue_counter_bytes(1, P, (n + 15) / 16);
+    p->oQ1 = off;
+    off = align_up(off + p->q1_bytes);
+    p->oQ2 = off;
+    off = align_up(off + p->q2_bytes);
+  }
   if (mixed) {
     // the refinement subspace k (<= n) is known only after the first SVD:
     // size every k-dependent buffer for the largest k
@@ -632,7 +682,9 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
 static int make_blocked_plan(pylom_ctx c, Plan* p, bool mixed) {
   const int64_t m = p->m, n = p->n;
   p->blocked = true;
-  int64_t b = c->block_rows > 0 ? c->block_rows : blocked_block_rows(m, n, c->ncu);
+  int64_t b = c->block_rows;
+  if (b <= 0) b = tune_lookup(c, true, mixed, m, n);
+  if (b <= 0) b = blocked_block_rows(m, n, c->ncu);
   if (b < n) b = n;
   int64_t P = m / b;
   if (P < 1) P = 1;
@@ -870,27 +922,65 @@ static int enqueue_fp64(pylom_ctx c, const Exec& x, const Plan& p, pylom_dtype d
   hipStream_t st = x.st;
   EVREC(0);
   EVREC(1);
-  KT(KR_STACKED_LEAF, launch_leaf_qr_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws, V,
-                                         Tleaf, p.nch_leaf, Rbuf, st), "leaf QR");
+  // the leaf QRs and the tree combines: one work-queue launch when the
+  // option is on and the plan has a tree, else one launch per level
+  bool queued = false;
+  if (c->work_queue && p.P > 1 && p.q1_bytes) {
+    HIPCHK(c, launch_queue_reset(x.ws + p.oQ1, p.q1_bytes, st), "queue reset");
+    const int64_t t = kt_begin(c, st);
+    const hipError_t e = launch_qr_queue_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws,
+                                             V, Tleaf, p.nch_leaf, Rbuf, Ttree, p.nch_tree, 1,
+                                             x.ws + p.oQ1, st, Batch());
+    if (e == hipSuccess) {
+      kt_end(c, st, t, KR_STACKED_LEAF);
+      queued = true;
+    } else if (e != hipErrorNotSupported) {
+      return hip_fail(c, e, "leaf QR and tree (work queue)");
+    }
+  }
+  if (!queued)
+    KT(KR_STACKED_LEAF, launch_leaf_qr_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws, V,
+                                           Tleaf, p.nch_leaf, Rbuf, st), "leaf QR");
   EVREC(2);
-  for (int64_t h = 1; h < p.P; h *= 2)
-    KT(KR_STACKED_TREE, launch_tree_combine_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, 1, st),
-       "tree combine");
+  if (!queued)
+    for (int64_t h = 1; h < p.P; h *= 2)
+      KT(KR_STACKED_TREE, launch_tree_combine_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, 1, st),
+         "tree combine");
   EVREC(3);
   JAC_BEFORE(p.jp);
   KT(KR_SVD, launch_small_svd(p.jp, Rbuf, x.max_sweeps, x.ws + p.oSvd, S, VT, ldvt, W, residual,
                               n_r, x.status, st, x.coop), "small SVD");
   JAC_AFTER(p.jp);
   EVREC(4);
+  // the propagation of every level and the leaf applies: one work-queue
+  // launch (or per level)
+  bool bqueued = false;
+  if (queued) {
+    HIPCHK(c, launch_queue_reset(x.ws + p.oQ2, p.q2_bytes, st), "queue reset");
+    const int64_t t = kt_begin(c, st);
+    const hipError_t e = launch_apply_queue_f64(p.g, m, p.b, p.P, V, Tleaf, p.nch_leaf, Rbuf,
+                                                Ttree, p.nch_tree, W, n, n_r, 0, n, U, in64, ldu,
+                                                x.ws + p.oQ2, st, Batch());
+    if (e == hipSuccess) {
+      kt_end(c, st, t, KR_LEAF_APPLY);
+      bqueued = true;
+    } else if (e != hipErrorNotSupported) {
+      return hip_fail(c, e, "propagation and apply (work queue)");
+    }
+    // a timed-out dependency wait of either queue is reported by pylom_check
+    HIPCHK(c, launch_queue_err_merge(x.ws + p.oQ1, bqueued ? x.ws + p.oQ2 : nullptr,
+                                     x.status + 1, st), "queue status");
+  }
   int64_t top = 1;
   while (top * 2 < p.P) top *= 2;
-  if (p.P > 1)
+  if (p.P > 1 && !bqueued)
     for (int64_t h = top; h >= 1; h /= 2)
       KT(KR_PROPAGATE, launch_apply_tree_f64(p.g, h, p.P, Rbuf, Ttree, p.nch_tree, W, n, n_r, n,
                                              st), "tree propagation");
   EVREC(5);
-  KT(KR_LEAF_APPLY, launch_apply_leaf_f64(p.g, m, p.b, p.P, V, Tleaf, p.nch_leaf, W, n, n_r, n, U,
-                                          in64, ldu, st), "leaf apply");
+  if (!bqueued)
+    KT(KR_LEAF_APPLY, launch_apply_leaf_f64(p.g, m, p.b, p.P, V, Tleaf, p.nch_leaf, W, n, n_r, n,
+                                            U, in64, ldu, st), "leaf apply");
   if (remove_mean && mean) HIPCHK(c, launch_cast_out(meanws, mean, in64, m, st), "mean out");
   EVREC(6);
   return PYLOM_OK;
@@ -1270,6 +1360,198 @@ static int run_tsvd(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m, 
   c->status_pairs = 1;
   if (x.evs) ++c->ev_calls;
   return PYLOM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// measured leaf heights
+// ---------------------------------------------------------------------------
+// Candidate leaf heights of an m x n problem on its path: the column-blocked
+// path tries one to four leaves per CU (rows rounded up to 64), the stacked
+// path the powers of two from 128 to 32768; each at least n, the analytic
+// choice always included.
+static std::vector<int64_t> tune_candidates(pylom_ctx c, bool blocked, bool mixed, int64_t m,
+                                            int64_t n) {
+  std::vector<int64_t> v;
+  auto add = [&](int64_t b) {
+    if (b < n) b = n;
+    if (b > m) b = m;
+    if (blocked && m / b > 65535) return;
+    if (std::find(v.begin(), v.end(), b) == v.end()) v.push_back(b);
+  };
+  if (blocked) {
+    for (int64_t k = 1; k <= 4; ++k) {
+      const int64_t slots = k * (int64_t)c->ncu;
+      add(((m + slots - 1) / slots + kPW - 1) / kPW * kPW);
+    }
+    add(blocked_block_rows(m, n, c->ncu));
+  } else {
+    for (int64_t b = 128; b <= 32768; b *= 2) add(b);
+    add(tune_block_rows(c, m, n, mixed));
+  }
+  std::sort(v.begin(), v.end());
+  return v;
+}
+
+extern "C" int pylom_autotune(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64_t m,
+                              int64_t n, const void* D, int64_t ldd, int remove_mean, int reps,
+                              int64_t* best_rows, double* best_ms) {
+  int rc = check_common(c, dtype, prec);
+  if (rc) return rc;
+  if (!D) return fail(c, PYLOM_EINVAL, "null array argument");
+  if (n < 1 || m < n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
+  if (ldd < n) return fail(c, PYLOM_ESHAPE, "leading dimension < n");
+  if (reps < 1 || reps > 100) return fail(c, PYLOM_EINVAL, "reps must be in [1, 100]");
+  if (prec == PYLOM_MIXED && dtype != PYLOM_R32)
+    return fail(c, PYLOM_EDTYPE, "mixed precision needs R32 storage");
+  if (n > kMaxN) return fail(c, PYLOM_ENOTSUP, "n > 2048 is not supported");
+  if (c->device < 0) return fail(c, PYLOM_ENODEV, "host-only context");
+  HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+  const bool mixed = prec == PYLOM_MIXED;
+  const bool blk = use_blocked(c, m, n);
+  const int es = dtype == PYLOM_R64 ? 8 : 4;
+  const std::vector<int64_t> cand = tune_candidates(c, blk, mixed, m, n);
+  // outputs of the trial calls (tuning allocates; the calls it times do not)
+  void* buf = nullptr;
+  const size_t oU = 0, oS = align_up((size_t)es * m * n), oVT = oS + align_up(8 * (size_t)n),
+               oNr = oVT + align_up(8 * (size_t)n * n), oMean = oNr + 256,
+               tot = oMean + align_up((size_t)es * m);
+  if (hipMalloc(&buf, tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, PYLOM_ENOMEM, "autotune outputs");
+  }
+  char* o = (char*)buf;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int64_t saved = c->block_rows;
+  int64_t best = 0;
+  double tbest = 0.0;
+  rc = PYLOM_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = hip_fail(c, hipGetLastError(), "hipEventCreate");
+  }
+  for (size_t i = 0; rc == PYLOM_OK && i < cand.size(); ++i) {
+    c->block_rows = cand[i];
+    Plan pl;
+    if (make_plan(c, m, n, !mixed, &pl, mixed) != PYLOM_OK) continue;  // not plannable
+    if (c->ws_cap_mb > 0 && pl.total > (size_t)c->ws_cap_mb * (1u << 20)) continue;
+    auto call = [&]() {
+      return run_tsvd(c, dtype, prec, m, n, D, ldd, remove_mean, 0.01,
+                      remove_mean ? o + oMean : nullptr, o + oU, n, (double*)(o + oS),
+                      (double*)(o + oVT), n, (int64_t*)(o + oNr));
+    };
+    if ((rc = call()) < 0) break;  // warm-up: workspace, code objects
+    hipError_t he = hipEventRecord(e0, c->stream);
+    for (int r = 0; rc >= 0 && r < reps; ++r) rc = call();
+    if (rc < 0) break;
+    if (he == hipSuccess) he = hipEventRecord(e1, c->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) {
+      rc = hip_fail(c, he, "autotune timing");
+      break;
+    }
+    rc = PYLOM_OK;
+    const double t = ms / reps;
+    if (best == 0 || t < tbest) {
+      best = cand[i];
+      tbest = t;
+    }
+  }
+  c->block_rows = saved;
+  hipStreamSynchronize(c->stream);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(buf);
+  if (rc < 0) return rc;
+  if (best == 0) return fail(c, PYLOM_ENOTSUP, "no candidate leaf height could be planned");
+  c->tuned[tune_key(blk, mixed, m, n)] = std::make_pair(best, tbest);
+  if (best_rows) *best_rows = best;
+  if (best_ms) *best_ms = tbest;
+  return PYLOM_OK;
+}
+
+extern "C" int pylom_tune_save(pylom_ctx c, const char* path) {
+  if (!c || !path) return PYLOM_EINVAL;
+  std::ofstream f(path, std::ios::out | std::ios::trunc);
+  if (!f) return fail(c, PYLOM_EINVAL, "cannot open the tuning file for writing");
+  f << "{\"pylom_tuning\": 1, \"entries\": [";
+  bool first = true;
+  char line[256];
+  for (const auto& kv : c->tuned) {
+    std::snprintf(line, sizeof line,
+                  "%s\n  {\"path\": \"%s\", \"precision\": \"%s\", \"m_log2\": %d, "
+                  "\"n_bucket\": %lld, \"block_rows\": %lld, \"ms\": %.6g}",
+                  first ? "" : ",", std::get<0>(kv.first) ? "blocked" : "stacked",
+                  std::get<1>(kv.first) ? "mixed" : "fp64", std::get<2>(kv.first),
+                  (long long)std::get<3>(kv.first), (long long)kv.second.first, kv.second.second);
+    f << line;
+    first = false;
+  }
+  f << "\n]}\n";
+  if (!f) return fail(c, PYLOM_EINVAL, "writing the tuning file failed");
+  return PYLOM_OK;
+}
+
+// Reads the value after "key": in one entry object (a string or a number).
+static bool json_field(const std::string& obj, const char* key, std::string* out) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t p = obj.find(k);
+  if (p == std::string::npos) return false;
+  p = obj.find(':', p + k.size());
+  if (p == std::string::npos) return false;
+  ++p;
+  while (p < obj.size() && (obj[p] == ' ' || obj[p] == '\t' || obj[p] == '\n')) ++p;
+  if (p >= obj.size()) return false;
+  if (obj[p] == '"') {
+    const size_t q = obj.find('"', p + 1);
+    if (q == std::string::npos) return false;
+    *out = obj.substr(p + 1, q - p - 1);
+    return true;
+  }
+  size_t q = p;
+  while (q < obj.size() && obj[q] != ',' && obj[q] != '}' && obj[q] != ' ' && obj[q] != '\n') ++q;
+  *out = obj.substr(p, q - p);
+  return !out->empty();
+}
+
+extern "C" int pylom_tune_load(pylom_ctx c, const char* path) {
+  if (!c || !path) return PYLOM_EINVAL;
+  std::ifstream f(path);
+  if (!f) return fail(c, PYLOM_EINVAL, "cannot open the tuning file");
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string text = ss.str();
+  if (text.find("\"pylom_tuning\"") == std::string::npos)
+    return fail(c, PYLOM_EINVAL, "not a pylom tuning file");
+  std::map<std::tuple<int, int, int, int64_t>, std::pair<int64_t, double>> got;
+  size_t pos = text.find('[');
+  while (pos != std::string::npos) {
+    const size_t a = text.find('{', pos + 1);
+    if (a == std::string::npos) break;
+    const size_t b = text.find('}', a);
+    if (b == std::string::npos) return fail(c, PYLOM_EINVAL, "malformed tuning entry");
+    const std::string obj = text.substr(a, b - a + 1);
+    std::string path_s, prec_s, lg_s, nb_s, br_s, ms_s;
+    if (!json_field(obj, "path", &path_s) || !json_field(obj, "precision", &prec_s) ||
+        !json_field(obj, "m_log2", &lg_s) || !json_field(obj, "n_bucket", &nb_s) ||
+        !json_field(obj, "block_rows", &br_s))
+      return fail(c, PYLOM_EINVAL, "malformed tuning entry");
+    if ((path_s != "blocked" && path_s != "stacked") || (prec_s != "mixed" && prec_s != "fp64"))
+      return fail(c, PYLOM_EINVAL, "malformed tuning entry");
+    char* end = nullptr;
+    const long lg = std::strtol(lg_s.c_str(), &end, 10);
+    const long long nb = std::strtoll(nb_s.c_str(), &end, 10);
+    const long long br = std::strtoll(br_s.c_str(), &end, 10);
+    double ms = 0.0;
+    if (json_field(obj, "ms", &ms_s)) ms = std::strtod(ms_s.c_str(), &end);
+    if (lg < 0 || lg > 62 || nb < 16 || nb > kMaxN + 15 || br < 1)
+      return fail(c, PYLOM_EINVAL, "tuning entry out of range");
+    got[std::make_tuple(path_s == "blocked" ? 1 : 0, prec_s == "mixed" ? 1 : 0, (int)lg,
+                        (int64_t)nb)] = std::make_pair((int64_t)br, ms);
+    pos = b;
+  }
+  for (const auto& kv : got) c->tuned[kv.first] = kv.second;
+  return (int)got.size();
 }
 
 // ---------------------------------------------------------------------------
@@ -2201,7 +2483,8 @@ struct SpodPlan {
   int e_f64;
   QrGeom g;
   JacobiPlan jp;
-  size_t oE, oV, oTleaf, oR, oTtree, oW, oSvd, oS, oVT, oUR, oNr, oSt, oUe, total;
+  size_t oE, oV, oTleaf, oR, oTtree, oW, oSvd, oS, oVT, oUR, oNr, oSt, oUe, oQ1, oQ2, total;
+  size_t q1_bytes, q2_bytes;
   size_t svd_stride;
 };
 
@@ -2257,6 +2540,10 @@ static int make_spod_plan(pylom_ctx c, pylom_dtype spectra, int64_t m, int64_t n
   p->oNr = off;    off = align_up(off + 8 * (size_t)nf);
   p->oSt = off;    off = align_up(off + 8 * (size_t)nf);
   p->oUe = off;    off = align_up(off + 8 * (size_t)nf * p->M2 * nb);
+  p->q1_bytes = queue_counter_bytes(nf, P, 1);
+  p->q2_bytes = queue_counter_bytes(nf, P, (nb + 15) / 16);
+  p->oQ1 = off;    off = align_up(off + p->q1_bytes);
+  p->oQ2 = off;    off = align_up(off + p->q2_bytes);
   p->total = off;
   return PYLOM_OK;
 }
@@ -2327,11 +2614,26 @@ extern "C" int pylom_spod(pylom_ctx c, pylom_dtype spectra, pylom_prec prec, int
   bl.sTtree = P * p.nch_tree * np * 256;
   bl.sW = P * n * n;
   bl.sU = M2 * nb;
-  HIPCHK(c, launch_leaf_qr_f64(p.g, E, p.e_f64, n, M2, p.b, P, 0, nullptr, V, Tleaf, p.nch_leaf, R,
-                               st, bl), "leaf QR");
+  // every leaf QR and every tree combine of every frequency: one work-queue
+  // launch (the per-level form with the option off)
+  bool queued = false;
+  if (c->work_queue) {
+    HIPCHK(c, launch_queue_reset(ws + p.oQ1, p.q1_bytes, st), "queue reset");
+    const hipError_t e = launch_qr_queue_f64(p.g, E, p.e_f64, n, M2, p.b, P, 0, nullptr, V, Tleaf,
+                                             p.nch_leaf, R, Ttree, p.nch_tree, 1, ws + p.oQ1, st,
+                                             bl);
+    if (e == hipSuccess) queued = true;
+    else if (e != hipErrorNotSupported) return hip_fail(c, e, "leaf QR and tree (work queue)");
+  }
+  if (!queued) {
+    HIPCHK(c, launch_leaf_qr_f64(p.g, E, p.e_f64, n, M2, p.b, P, 0, nullptr, V, Tleaf, p.nch_leaf,
+                                 R, st, bl), "leaf QR");
+  }
   EVREC(2);
-  for (int64_t h = 1; h < P; h *= 2)
-    HIPCHK(c, launch_tree_combine_f64(p.g, h, P, R, Ttree, p.nch_tree, 1, st, bl), "tree combine");
+  if (!queued)
+    for (int64_t h = 1; h < P; h *= 2)
+      HIPCHK(c, launch_tree_combine_f64(p.g, h, P, R, Ttree, p.nch_tree, 1, st, bl),
+             "tree combine");
   EVREC(3);
   HIPCHK(c, launch_small_svd_batched(p.jp, nf, R, P * n * n, (int)c->max_sweeps, ws + p.oSvd, S, n,
                                      VTb, n, n * n, URb, n * n, 0.0, nr, st_each, c->status_dev,
@@ -2340,15 +2642,30 @@ extern "C" int pylom_spod(pylom_ctx c, pylom_dtype spectra, pylom_prec prec, int
   c->status_pairs = 1;
   HIPCHK(c, launch_select_even((int)n, (int)nb, nf, URb, n * n, W, n, P * n * n, st), "root W");
   EVREC(4);
+  // the down-tree propagation of every level and every leaf apply: one
+  // work-queue launch (or per level)
+  bool bqueued = false;
+  if (queued) {
+    HIPCHK(c, launch_queue_reset(ws + p.oQ2, p.q2_bytes, st), "queue reset");
+    const hipError_t e = launch_apply_queue_f64(p.g, M2, p.b, P, V, Tleaf, p.nch_leaf, R, Ttree,
+                                                p.nch_tree, W, n, nullptr, 0, nb, Ue, 1, nb,
+                                                ws + p.oQ2, st, bl);
+    if (e == hipSuccess) bqueued = true;
+    else if (e != hipErrorNotSupported) return hip_fail(c, e, "propagation and apply (work queue)");
+    // a timed-out dependency wait of either queue is reported by pylom_check
+    HIPCHK(c, launch_queue_err_merge(ws + p.oQ1, bqueued ? ws + p.oQ2 : nullptr,
+                                     c->status_dev + 1, st), "queue status");
+  }
   int64_t top = 1;
   while (top * 2 < P) top *= 2;
-  if (P > 1)
+  if (P > 1 && !bqueued)
     for (int64_t h = top; h >= 1; h /= 2)
       HIPCHK(c, launch_apply_tree_f64(p.g, h, P, R, Ttree, p.nch_tree, W, n, nullptr, nb, st, bl),
              "tree propagation");
   EVREC(5);
-  HIPCHK(c, launch_apply_leaf_f64(p.g, M2, p.b, P, V, Tleaf, p.nch_leaf, W, n, nullptr, nb, Ue, 1,
-                                  nb, st, bl), "leaf apply");
+  if (!bqueued)
+    HIPCHK(c, launch_apply_leaf_f64(p.g, M2, p.b, P, V, Tleaf, p.nch_leaf, W, n, nullptr, nb, Ue,
+                                    1, nb, st, bl), "leaf apply");
   HIPCHK(c, launch_spod_modes(p.e_f64, m, (int)nb, nf, Ue, M2 * nb, VTb, n * n, S, n, modes, L, st),
          "modes");
   HIPCHK(c, launch_spod_order((int)nf, (int)nb, dt, (int)npwin, L, freqs, order, st), "order");
@@ -2427,7 +2744,8 @@ extern "C" int pylom_check(pylom_ctx c, int64_t* sweeps) {
          "status copy");
   if (sweeps) *sweeps = st[0];
   for (int k = 0; k < c->status_pairs; ++k) {
-    if (st[2 * k + 1]) return fail(c, PYLOM_EHIP, "Jacobi grid barrier timed out");
+    if (st[2 * k + 1])
+      return fail(c, PYLOM_EHIP, "a device-wide wait timed out (Jacobi grid barrier or work queue)");
     if (st[2 * k] == -2)
       return fail(c, PYLOM_WNONFINITE, "a singular value is not finite (non-finite input)");
   }

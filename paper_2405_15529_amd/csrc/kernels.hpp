@@ -102,6 +102,60 @@ hipError_t launch_tree_combine_f64(const QrGeom& g, int64_t h, int64_t P, double
                                    double* Ttree, int64_t nch_tree, int store_q, hipStream_t st,
                                    const Batch& bt = Batch());
 
+// ---- work queues: a whole batch's TSQR phase in one persistent launch -------
+// Task numbering and counters of k_qr_queue / k_apply_queue (tsqr.hip).
+constexpr int kMaxQueueLevels = 32;
+struct QrQueue {
+  int64_t P;                              // leaves per problem
+  int nlev;                               // tree levels
+  int64_t lvl_off[kMaxQueueLevels + 2];   // first task of each level, then the total
+  unsigned long long* next;               // task counter (zero before the launch)
+  unsigned int* cnt;                      // count * P node counters (zero before the launch)
+  int* err;                               // set if a dependency wait timed out
+};
+struct ApplyQueue {
+  int64_t P;
+  int nlev;
+  int64_t ntiles;                         // 16-column tiles of W
+  int64_t ncols;                          // columns, when nr is null
+  const int64_t* nr;                      // per-problem column counts (device) or null
+  int64_t nr_stride;
+  int64_t lvl_off[kMaxQueueLevels + 2];   // top level first, the leaves last
+  unsigned long long* next;
+  unsigned int* cnt;                      // count * P * ntiles counters
+  int* err;
+};
+// Bytes of the counter region of one queue launch over `count` problems of P
+// leaves (the task counter at byte 0, the timeout flag at byte 64, node
+// counters from byte 256), to be zeroed by launch_queue_reset before it.
+size_t queue_counter_bytes(int64_t count, int64_t P, int64_t ntiles);
+hipError_t launch_queue_reset(void* counters, size_t bytes, hipStream_t st);
+// *flag = 1 if the timeout flag of either counter region (the second may be
+// null) is set.
+hipError_t launch_queue_err_merge(const void* counters1, const void* counters2, int* flag,
+                                  hipStream_t st);
+// The reduce phase (every leaf QR and every tree combine of `bt.count`
+// problems, FP64 compute) as one work-queue launch; same arguments as
+// launch_leaf_qr_f64 + launch_tree_combine_f64.  counters: a zeroed region of
+// queue_counter_bytes(bt.count, P, 1).  Returns hipErrorNotSupported when the
+// shape does not fit the queue kernel.
+hipError_t launch_qr_queue_f64(const QrGeom& g, const void* D, int in_f64, int64_t ldd, int64_t m,
+                               int64_t b, int64_t P, int remove_mean, double* mean_ws, double* V,
+                               double* Tleaf, int64_t nch_leaf, double* Rbuf, double* Ttree,
+                               int64_t nch_tree, int store_q, void* counters, hipStream_t st,
+                               const Batch& bt);
+// The broadcast phase (every propagation level, then every leaf apply) as
+// one work-queue launch; arguments as launch_apply_tree_f64 +
+// launch_apply_leaf_f64 (nr: one device count per problem, stride nr_stride,
+// or null for ncols).  counters: a zeroed region of
+// queue_counter_bytes(bt.count, P, ceil(ncols / 16)).
+hipError_t launch_apply_queue_f64(const QrGeom& g, int64_t m, int64_t b, int64_t P,
+                                  const double* V, const double* Tleaf, int64_t nch_leaf,
+                                  const double* Rbuf, const double* Ttree, int64_t nch_tree,
+                                  double* W, int64_t ldw, const int64_t* nr, int64_t nr_stride,
+                                  int64_t ncols, void* U, int out_f64, int64_t ldu, void* counters,
+                                  hipStream_t st, const Batch& bt);
+
 // ---- apply (Alg. 1 broadcast phase + Q_i = Q_1i Q_w, Eq. svdqr3) -----------
 // Leaf mode: U rows of leaf j = Q_1j [W_j; 0]; combine mode (level h):
 // [W_j; W_{j+h}] = Q2 [W_j; 0].  Only the first ncols (or *nr) columns.

@@ -120,6 +120,135 @@ __global__ __launch_bounds__(256) void k_tall_gemm(int64_t m, int K, int nc_host
   }
 }
 
+// The same product for long K: 128 rows per workgroup (each wave two 16-row
+// tiles, so every B value read from LDS feeds two MFMAs), NT 16-column tiles
+// (the output width rounded up to 16, not to 64 or 128), K staged in slabs
+// of 16 with the next slab's A and B loaded into registers while the current
+// one is multiplied (one barrier pair per slab).  A is read once per 16 NT
+// columns; B once per 128 rows.
+namespace {
+constexpr int TR = 128;       // rows per workgroup
+constexpr int TK = 16;        // K slab
+constexpr int TALD = TK + 1;
+}  // namespace
+template <typename TI, typename TO, bool BT, int NT>
+__global__ __launch_bounds__(256) void k_tall_gemm_k(int64_t m, int K, int nc_host,
+                                                     const int64_t* __restrict__ nc_dev,
+                                                     const TI* __restrict__ A, int64_t lda,
+                                                     const double* __restrict__ mu,
+                                                     const double* __restrict__ Bs, int64_t ldb,
+                                                     TO* __restrict__ C, int64_t ldc) {
+  constexpr int GC = 16 * NT;
+  constexpr int BLD = GC + 1;
+  constexpr int AE = (TR * TK) / 256;          // A values staged per thread
+  constexpr int BE = (TK * GC + 255) / 256;    // B values staged per thread
+  __shared__ double As[TR * TALD];
+  __shared__ double Bsh[TK * BLD];
+  int nc = nc_host;
+  if (nc_dev) {
+    const int64_t d = *nc_dev;
+    nc = (int)(d < nc ? d : nc);
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * TR;
+  const int j0 = blockIdx.y * GC;
+  if (j0 >= nc) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  typedef Mfma<double>::v4 v4;
+  v4 acc[2][NT];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[r][c] = vzero4<double>();
+  double pa[AE], pb[BE];
+  // A element e of a slab: row idx / TK, column idx % TK (a row's 16 values
+  // are read by 16 consecutive threads); B element: BT walks t fastest
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      const int idx = tid + 256 * e;
+      const int r = idx / TK, c = idx % TK;
+      const int64_t gr = r0 + r;
+      const int gc = k0 + c;
+      double v = 0.0;
+      if (gr < m && gc < K) {
+        v = (double)A[gr * lda + gc];
+        if (mu) v -= mu[gr];
+      }
+      pa[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      const int idx = tid + 256 * e;
+      int t, j;
+      if (BT) {
+        j = idx / TK;
+        t = idx % TK;
+      } else {
+        t = idx / GC;
+        j = idx % GC;
+      }
+      const int gt = k0 + t, gj = j0 + j;
+      double v = 0.0;
+      if (idx < TK * GC && gt < K && gj < nc)
+        v = BT ? Bs[(int64_t)gj * ldb + gt] : Bs[(int64_t)gt * ldb + gj];
+      pb[e] = v;
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      const int idx = tid + 256 * e;
+      As[(idx / TK) * TALD + idx % TK] = pa[e];
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      const int idx = tid + 256 * e;
+      if (idx < TK * GC) {
+        int t, j;
+        if (BT) {
+          j = idx / TK;
+          t = idx % TK;
+        } else {
+          t = idx / GC;
+          j = idx % GC;
+        }
+        Bsh[t * BLD + j] = pb[e];
+      }
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    commit();
+    __syncthreads();
+    if (k0 + TK < K) fetch(k0 + TK);
+#pragma unroll
+    for (int kb = 0; kb < TK; kb += 4) {
+      double bv[NT];
+#pragma unroll
+      for (int c = 0; c < NT; ++c) bv[c] = Bsh[(kb + g4) * BLD + c * 16 + i16];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const double av = As[(wave * 32 + r * 16 + i16) * TALD + kb + g4];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[r][c] = Mfma<double>::op(av, bv[c], acc[r][c]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      const int col = j0 + c * 16 + i16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t row = r0 + wave * 32 + r * 16 + Mfma<double>::drow(g4, q);
+        if (row < m && col < nc) C[row * ldc + col] = (TO)acc[r][c][q];
+      }
+    }
+}
+
 // Refined spectrum: S[c] = sqrt(lambda_c) for c < k, the unrefined S0[c] for
 // c >= k; N_r from the residual-energy rule on S (tail sums from the smallest
 // value upward), capped at k.  One workgroup.
@@ -340,11 +469,36 @@ static hipError_t launch_pb(int64_t m, int K, int nc, const int64_t* nc_dev, con
 
 // One launch of the tall GEMM: 128-column workgroups when more than 64
 // output columns are asked for (A is then read once per 128 columns).
+template <typename TI, typename TO, bool BT, int NT>
+static void launch_tgk(int64_t m, int K, int nc, const int64_t* nc_dev, const TI* A, int64_t lda,
+                       const double* mu, const double* B, int64_t ldb, TO* C, int64_t ldc,
+                       hipStream_t st) {
+  const dim3 grid((unsigned)((m + TR - 1) / TR), (unsigned)((nc + 16 * NT - 1) / (16 * NT)));
+  hipLaunchKernelGGL((k_tall_gemm_k<TI, TO, BT, NT>), grid, dim3(256), 0, st, m, K, nc, nc_dev,
+                     A, lda, mu, B, ldb, C, ldc);
+}
+
 template <typename TI, typename TO, bool BT>
 static hipError_t launch_tg(int64_t m, int K, int nc, const int64_t* nc_dev, const TI* A,
                             int64_t lda, const double* mu, const double* B, int64_t ldb, TO* C,
                             int64_t ldc, hipStream_t st) {
   if (m <= 0 || nc <= 0) return hipSuccess;
+  if (K >= 512) {
+    // long contractions (the refinement's projection of wide inputs): the
+    // output width rounded up to 16 columns, 128-row tiles
+    const int nt = (nc + 15) / 16;
+    switch (nt > 8 ? 8 : nt) {
+      case 1: launch_tgk<TI, TO, BT, 1>(m, K, nc, nc_dev, A, lda, mu, B, ldb, C, ldc, st); break;
+      case 2: launch_tgk<TI, TO, BT, 2>(m, K, nc, nc_dev, A, lda, mu, B, ldb, C, ldc, st); break;
+      case 3: launch_tgk<TI, TO, BT, 3>(m, K, nc, nc_dev, A, lda, mu, B, ldb, C, ldc, st); break;
+      case 4: launch_tgk<TI, TO, BT, 4>(m, K, nc, nc_dev, A, lda, mu, B, ldb, C, ldc, st); break;
+      case 5: launch_tgk<TI, TO, BT, 5>(m, K, nc, nc_dev, A, lda, mu, B, ldb, C, ldc, st); break;
+      case 6: launch_tgk<TI, TO, BT, 6>(m, K, nc, nc_dev, A, lda, mu, B, ldb, C, ldc, st); break;
+      case 7: launch_tgk<TI, TO, BT, 7>(m, K, nc, nc_dev, A, lda, mu, B, ldb, C, ldc, st); break;
+      default: launch_tgk<TI, TO, BT, 8>(m, K, nc, nc_dev, A, lda, mu, B, ldb, C, ldc, st); break;
+    }
+    return hipGetLastError();
+  }
   if (nc > 64) {
     const dim3 grid((unsigned)((m + GR - 1) / GR), (unsigned)((nc + 127) / 128));
     hipLaunchKernelGGL((k_tall_gemm<TI, TO, BT, 128>), grid, dim3(256), 0, st, m, K, nc, nc_dev,

@@ -761,15 +761,15 @@ __device__ __forceinline__ void chunk_commit(const TI (&pfv)[N], T* __restrict__
 // that two workgroups share a CU, and the wave that factors the panels
 // rotates with the workgroup index, so that the panel waves of co-resident
 // workgroups sit on different SIMDs.
+// One leaf (a.mode 0, leaf bx) or one combine (a.mode 1, pair bx at level
+// a.h) of problem by, by the whole workgroup; smem is the dynamic LDS.
 template <typename T, typename TI, int RT, int VAR>
-__global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(VAR == 2 ? 2 : 1, VAR == 2 ? 2 : 1)))
-void k_stacked_qr(QrArgs<T, TI> a) {
+__device__ __forceinline__ void stacked_qr_task(QrArgs<T, TI> a, int64_t bx, int64_t by,
+                                                unsigned char* smem) {
   constexpr bool FILL = VAR == 0 || VAR == 3;
   constexpr bool PF = VAR == 3;
-  extern __shared__ __align__(16) unsigned char smem[];
-  if (blockIdx.y) {
-    const int64_t pb = blockIdx.y;
+  if (by) {
+    const int64_t pb = by;
     if (a.D) a.D += pb * a.bsD;
     if (a.mean_ws) a.mean_ws += pb * a.bsMean;
     if (a.V) a.V += pb * a.bsV;
@@ -789,7 +789,7 @@ void k_stacked_qr(QrArgs<T, TI> a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = (int)(blockDim.x >> 6);  // 4, or 1 for narrow problems
   // panel wave pw; wr = 0 for it, 1..3 for the trailing-tile waves
-  const int pw = (VAR == 2 && nw == 4) ? (int)(((blockIdx.x >> 3) + (blockIdx.x >> 8)) & 3) : 0;
+  const int pw = (VAR == 2 && nw == 4) ? (int)(((bx >> 3) + (bx >> 8)) & 3) : 0;
   const int wr = (wave - pw) & 3;
   T* Gm = Yb + pw * NB * NB;  // the panel wave's Y tile doubles as its Gram scratch
   const bool leaf = (a.mode == 0);
@@ -803,7 +803,7 @@ void k_stacked_qr(QrArgs<T, TI> a) {
   T* state;
   T* tout;
   if (leaf) {
-    const int64_t jl = blockIdx.x;
+    const int64_t jl = bx;
     row0 = jl * a.b;
     rows = (jl == a.P - 1) ? (a.m - row0) : a.b;
     if (a.rows_lim > 0 && rows > a.rows_lim) rows = a.rows_lim;
@@ -813,7 +813,7 @@ void k_stacked_qr(QrArgs<T, TI> a) {
     state = a.Rbuf + jl * (int64_t)n * n;
     tout = a.store_q ? a.Tleaf + jl * a.nch_leaf * npan * (NB * NB) : nullptr;
   } else {
-    const int64_t jn = (int64_t)blockIdx.x * 2 * a.h;
+    const int64_t jn = bx * 2 * a.h;
     const int64_t jb = jn + a.h;
     srcT = a.Rbuf + jb * (int64_t)n * n;
     ld_src = n;
@@ -830,16 +830,25 @@ void k_stacked_qr(QrArgs<T, TI> a) {
   }
   // VAR 3 (leaves without mean removal whose chunk is at most kPfn values
   // per thread) prefetches the next chunk into registers (chunk_prefetch).
+  // (only leaves read srcI: a work-queue launch runs combines in the same
+  // variant)
   TI pfv[PF ? kPfn : 1];
-  if constexpr (PF) chunk_prefetch<TI, kPfn>(pfv, srcI, ld_src, 0, rows, S, n, tid, (int)blockDim.x);
+  if constexpr (PF) {
+    if (leaf) chunk_prefetch<TI, kPfn>(pfv, srcI, ld_src, 0, rows, S, n, tid, (int)blockDim.x);
+  }
   for (int c = 0; c < nch; ++c) {
     const int64_t r0 = (int64_t)c * S;
     const int sc = (int)((rows - r0) < S ? (rows - r0) : S);
+    bool staged = false;
     if constexpr (PF) {
-      chunk_commit<T, TI, kPfn>(pfv, C, ldc, S, n, tid, (int)blockDim.x);
-      if (c + 1 < nch)
-        chunk_prefetch<TI, kPfn>(pfv, srcI, ld_src, c + 1, rows, S, n, tid, (int)blockDim.x);
-    } else {
+      if (leaf) {
+        chunk_commit<T, TI, kPfn>(pfv, C, ldc, S, n, tid, (int)blockDim.x);
+        if (c + 1 < nch)
+          chunk_prefetch<TI, kPfn>(pfv, srcI, ld_src, c + 1, rows, S, n, tid, (int)blockDim.x);
+        staged = true;
+      }
+    }
+    if (!staged) {
       if (leaf)
         load_chunk<T, TI>(C, ldc, S, sc, n, srcI + r0 * ld_src, ld_src, a.remove_mean,
                           a.mean_ws ? a.mean_ws + row0 + r0 : nullptr, wave, lane, nw);
@@ -934,6 +943,97 @@ void k_stacked_qr(QrArgs<T, TI> a) {
   }
 }
 
+template <typename T, typename TI, int RT, int VAR>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(VAR == 2 ? 2 : 1, VAR == 2 ? 2 : 1)))
+void k_stacked_qr(QrArgs<T, TI> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  stacked_qr_task<T, TI, RT, VAR>(a, blockIdx.x, blockIdx.y, smem);
+}
+
+// ---------------------------------------------------------------------------
+// work-queue form: every leaf and every combine of a batch in one launch
+// ---------------------------------------------------------------------------
+// Tasks are numbered level by level (level 0: the leaves of every problem,
+// level l >= 1: the combines at h = 2^(l-1)), and each workgroup takes the
+// next number from a device counter until none is left.  A combine waits
+// until both of its nodes are complete through the levels below it: node j
+// counts one completion for its leaf and one for each combine into it, so
+// before level h it needs 1 + #{h' < h : j + h' < P}.  Every task depends
+// only on tasks with smaller numbers, which workgroups already hold, so the
+// queue always drains; the waits are bounded all the same (about 2^22 polls:
+// a timeout sets err, which ends every later wait, and the task proceeds).
+__device__ __forceinline__ unsigned int qr_need(int64_t j, int64_t h, int64_t P) {
+  unsigned int need = 1;
+  for (int64_t hp = 1; hp < h; hp *= 2)
+    if (j + hp < P) ++need;
+  return need;
+}
+
+// The poll is a relaxed device-scope load (it reads the coherent copy
+// without invalidating this XCD's L2, which an acquire load does on every
+// iteration and which would starve the producers the waiter depends on); the
+// acquire fence follows once, after the count is reached.
+__device__ __forceinline__ void queue_wait(const unsigned int* c, unsigned int need, int* err) {
+  unsigned long long spins = 0;
+  while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+    __builtin_amdgcn_s_sleep(8);
+    if ((++spins & 255ull) == 0 &&
+        (spins > (1ull << 22) || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+      atomicExch(err, 1);
+      break;
+    }
+  }
+}
+
+// Next task number for the whole workgroup (slot: one LDS word).
+__device__ __forceinline__ int64_t queue_next(unsigned long long* next, int64_t* slot) {
+  if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(next, 1ull);
+  __syncthreads();
+  const int64_t t = *slot;
+  __syncthreads();
+  return t;
+}
+
+template <typename T, typename TI, int RT, int VAR>
+__global__ __launch_bounds__(256) void k_qr_queue(QrArgs<T, TI> a, QrQueue q) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int64_t slot;
+  for (;;) {
+    const int64_t t = queue_next(q.next, &slot);
+    if (t >= q.lvl_off[q.nlev + 1]) break;
+    int l = 0;
+    while (t >= q.lvl_off[l + 1]) ++l;
+    const int64_t i = t - q.lvl_off[l];
+    const int64_t h = l ? ((int64_t)1 << (l - 1)) : 0;
+    const int64_t per = l ? (q.P - h + 2 * h - 1) / (2 * h) : q.P;
+    const int64_t prob = i / per, idx = i - prob * per;
+    unsigned int* cnt = q.cnt + prob * q.P;
+    int64_t node = idx;
+    if (l) {
+      node = 2 * h * idx;
+      if (threadIdx.x == 0) {
+        queue_wait(cnt + node, qr_need(node, h, q.P), q.err);
+        queue_wait(cnt + node + h, qr_need(node + h, h, q.P), q.err);
+        __threadfence();
+      }
+      __syncthreads();
+    }
+    QrArgs<T, TI> b = a;
+    b.mode = l ? 1 : 0;
+    b.h = h;
+    stacked_qr_task<T, TI, RT, VAR>(b, idx, prob, smem);
+    // the workgroup barrier completes every thread's stores to this XCD's
+    // L2; the release by thread 0 writes them back device-wide before the
+    // count
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      __hip_atomic_fetch_add(cnt + node, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // apply kernel: Q [W; 0], walking chunks and panels backwards
 // ---------------------------------------------------------------------------
@@ -961,12 +1061,14 @@ struct ApplyArgs {
   int64_t bsV, bsTleaf, bsR, bsTtree, bsW, bsU;
 };
 
+// Column tile `tile` (16 columns of W) of leaf or pair `prob` (a.mode 0 / 1)
+// of problem by, by the whole workgroup.
 template <typename T, typename TO>
-__global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
+__device__ __forceinline__ void stacked_apply_task(ApplyArgs<T, TO> a, int64_t prob, int tile,
+                                                   int64_t by, unsigned char* smem) {
   typedef typename Mfma<T>::v4 v4;
-  extern __shared__ __align__(16) unsigned char smem[];
-  if (blockIdx.y) {
-    const int64_t pb = blockIdx.y;
+  if (by) {
+    const int64_t pb = by;
     if (a.V) a.V += pb * a.bsV;
     if (a.Tleaf) a.Tleaf += pb * a.bsTleaf;
     if (a.Rbuf) a.Rbuf += pb * a.bsR;
@@ -976,11 +1078,6 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
   }
   const int n = a.n, s = a.s, npan = a.npanels;
   const int64_t ncols = a.nr ? *a.nr : a.ncols;
-  // tile-major block order: the active (tile < N_r / 16) blocks are the first
-  // ones and spread over all XCDs
-  const int64_t nprob = a.mode == 0 ? a.P : (a.P - a.h + 2 * a.h - 1) / (2 * a.h);
-  const int tile = (int)(blockIdx.x / nprob);
-  const int64_t prob = blockIdx.x % nprob;
   if ((int64_t)tile * 16 >= ncols) return;
   const int c0 = tile * 16;
   const bool leaf = (a.mode == 0);
@@ -1170,6 +1267,78 @@ __global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
   }
 }
 
+template <typename T, typename TO>
+__global__ __launch_bounds__(256) void k_stacked_apply(ApplyArgs<T, TO> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  // tile-major block order: the active (tile < N_r / 16) blocks are the first
+  // ones and spread over all XCDs
+  const int64_t nprob = a.mode == 0 ? a.P : (a.P - a.h + 2 * a.h - 1) / (2 * a.h);
+  stacked_apply_task<T, TO>(a, blockIdx.x % nprob, (int)(blockIdx.x / nprob), blockIdx.y, smem);
+}
+
+// Work-queue form of the broadcast phase: the down-tree propagation of every
+// level, top level first, then the leaf applies, for every problem and
+// column tile, in one launch.  Node j's tile counts one completion for every
+// propagation step that writes W_j; a step at level h reads W_j for its
+// receiver j, which must first hold every write from the levels above h
+// (apply_need), and a leaf needs every write of all levels.  Tiles at or
+// beyond the device-side column count are skipped by the task and by every
+// task that would wait on it.
+__device__ __forceinline__ unsigned int apply_need(int64_t j, int64_t h, int64_t P) {
+  unsigned int need = 0;
+  for (int64_t hp = 1; hp < P; hp *= 2) {
+    if (hp <= h) continue;
+    const int64_t r = j % (2 * hp);
+    if (r == 0) {
+      if (j + hp < P) ++need;  // receiver of the pair (j, j + hp)
+    } else if (r == hp) {
+      ++need;                  // sender of the pair (j - hp, j)
+    }
+  }
+  return need;
+}
+
+template <typename T, typename TO>
+__global__ __launch_bounds__(256) void k_apply_queue(ApplyArgs<T, TO> tree, ApplyArgs<T, TO> leaf,
+                                                     ApplyQueue q) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int64_t slot;
+  for (;;) {
+    const int64_t t = queue_next(q.next, &slot);
+    if (t >= q.lvl_off[q.nlev + 1]) break;
+    int k = 0;  // position in top-down order: k < nlev are tree levels, k = nlev the leaves
+    while (t >= q.lvl_off[k + 1]) ++k;
+    const int64_t i = t - q.lvl_off[k];
+    const bool is_leaf = k == q.nlev;
+    const int64_t h = is_leaf ? 0 : ((int64_t)1 << (q.nlev - 1 - k));
+    const int64_t per = (is_leaf ? q.P : (q.P - h + 2 * h - 1) / (2 * h)) * q.ntiles;
+    const int64_t prob = i / per, rem = i - prob * per;
+    const int tile = (int)(rem % q.ntiles);
+    const int64_t idx = rem / q.ntiles;
+    const int64_t ncols = q.nr ? q.nr[prob * q.nr_stride] : q.ncols;
+    if ((int64_t)tile * 16 >= ncols) continue;
+    unsigned int* cnt = q.cnt + prob * q.P * q.ntiles;
+    const int64_t j = is_leaf ? idx : 2 * h * idx;
+    if (threadIdx.x == 0) {
+      queue_wait(cnt + j * q.ntiles + tile, apply_need(j, h, q.P), q.err);
+      __threadfence();
+    }
+    __syncthreads();
+    ApplyArgs<T, TO> b = is_leaf ? leaf : tree;
+    if (!is_leaf) b.h = h;
+    if (q.nr) b.nr = q.nr + prob * q.nr_stride;
+    stacked_apply_task<T, TO>(b, idx, tile, prob, smem);
+    __syncthreads();
+    if (threadIdx.x == 0 && !is_leaf) {
+      __threadfence();
+      __hip_atomic_fetch_add(cnt + j * q.ntiles + tile, 1u, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(cnt + (j + h) * q.ntiles + tile, 1u, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1347,6 +1516,208 @@ hipError_t launch_apply_tree_f64(const QrGeom& g, int64_t h, int64_t P, const do
   a.P = P; a.h = h; a.Rbuf = Rbuf; a.Ttree = Ttree; a.nch_tree = nch_tree; a.W = W; a.ldw = ldw;
   set_apply_batch(a, bt);
   return launch_apply_t(a, (int)(ncomb * ntiles), apply_lds_bytes(g, 8), st, bt.count);
+}
+
+// ---- work queues -----------------------------------------------------------
+__global__ void k_queue_reset(unsigned int* p, int64_t nwords) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// counters: the task counter (first 256 bytes), then the node counters
+size_t queue_counter_bytes(int64_t count, int64_t P, int64_t ntiles) {
+  const size_t words = (size_t)count * (size_t)P * (size_t)(ntiles > 1 ? ntiles : 1);
+  return (256 + 4 * words + 255) & ~(size_t)255;
+}
+
+hipError_t launch_queue_reset(void* counters, size_t bytes, hipStream_t st) {
+  const int64_t nwords = (int64_t)(bytes / 4);
+  int64_t g = (nwords + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_queue_reset, dim3((unsigned)g), dim3(256), 0, st, (unsigned int*)counters,
+                     nwords);
+  return hipGetLastError();
+}
+
+__global__ void k_queue_err_merge(const int* e1, const int* e2, int* flag) {
+  if (threadIdx.x == 0 && (*e1 || (e2 && *e2))) *flag = 1;
+}
+
+hipError_t launch_queue_err_merge(const void* counters1, const void* counters2, int* flag,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(k_queue_err_merge, dim3(1), dim3(64), 0, st,
+                     (const int*)((const char*)counters1 + 64),
+                     counters2 ? (const int*)((const char*)counters2 + 64) : nullptr, flag);
+  return hipGetLastError();
+}
+
+static int device_cus() {
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu < 1) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  return ncu;
+}
+
+// Grid of a work-queue launch: every workgroup that can be resident at once
+// (more would only wait for a free slot), at most one per task.
+static int64_t queue_grid(const void* fn, int threads, size_t lds, int64_t ntasks) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess ||
+      per_cu < 1) {
+    (void)hipGetLastError();
+    per_cu = 1;
+  }
+  const int64_t slots = (int64_t)per_cu * device_cus();
+  return ntasks < slots ? ntasks : slots;
+}
+
+template <typename T, typename TI, int RT, int VAR>
+static hipError_t launch_qrq_t(const QrArgs<T, TI>& a, const QrQueue& q, size_t lds,
+                               hipStream_t st) {
+  const void* fn = (const void*)k_qr_queue<T, TI, RT, VAR>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int threads = a.nthr ? a.nthr : ((a.npanels <= 2) ? 64 : 256);
+  const int64_t ntasks = q.lvl_off[q.nlev + 1];
+  const int64_t grid = queue_grid(fn, threads, lds, ntasks);
+  if (grid < 1) return hipSuccess;
+  hipLaunchKernelGGL((k_qr_queue<T, TI, RT, VAR>), dim3((unsigned)grid), dim3(threads), lds, st,
+                     a, q);
+  return hipGetLastError();
+}
+
+template <typename T, typename TI, int VAR>
+static hipError_t launch_qrq_var(const QrArgs<T, TI>& a, const QrQueue& q, size_t lds,
+                                 hipStream_t st) {
+  switch (a.s) {
+    case 16: return launch_qrq_t<T, TI, 4, VAR>(a, q, lds, st);
+    case 32: return launch_qrq_t<T, TI, 8, VAR>(a, q, lds, st);
+    case 48: return launch_qrq_t<T, TI, 12, VAR>(a, q, lds, st);
+    case 64: return launch_qrq_t<T, TI, 16, VAR>(a, q, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename TI>
+static hipError_t launch_qrq(const QrGeom& g, const TI* D, int64_t ldd, int64_t m, int64_t b,
+                             int64_t P, int remove_mean, double* mean_ws, double* V,
+                             double* Tleaf, int64_t nch_leaf, double* Rbuf, double* Ttree,
+                             int64_t nch_tree, int store_q, void* counters, hipStream_t st,
+                             const Batch& bt) {
+  QrArgs<double, TI> a{};
+  a.n = g.n; a.s = g.s; a.ldc = g.ldc; a.npanels = g.npanels; a.nthr = g.nthr; a.mode = 0;
+  a.store_q = store_q;
+  a.D = D; a.ldd = ldd; a.m = m; a.b = b; a.P = P; a.remove_mean = remove_mean;
+  a.mean_ws = mean_ws;
+  a.V = V; a.Tleaf = Tleaf; a.nch_leaf = nch_leaf; a.Rbuf = Rbuf;
+  a.Ttree = Ttree; a.nch_tree = nch_tree;
+  set_qr_batch(a, bt);
+  QrQueue q{};
+  q.P = P;
+  int nlev = 0;
+  for (int64_t h = 1; h < P; h *= 2) ++nlev;
+  if (nlev > kMaxQueueLevels) return hipErrorNotSupported;
+  q.nlev = nlev;
+  q.lvl_off[0] = 0;
+  q.lvl_off[1] = bt.count * P;
+  for (int l = 1; l <= nlev; ++l) {
+    const int64_t h = (int64_t)1 << (l - 1);
+    q.lvl_off[l + 1] = q.lvl_off[l] + bt.count * ((P - h + 2 * h - 1) / (2 * h));
+  }
+  q.next = (unsigned long long*)counters;
+  q.cnt = (unsigned int*)((char*)counters + 256);
+  q.err = (int*)((char*)counters + 64);
+  const size_t lds = qr_lds_bytes(g, 8);
+  if (lds + 64 > kQrLdsBudget) return hipErrorNotSupported;
+  const int nthr = a.nthr ? a.nthr : ((a.npanels <= 2) ? 64 : 256);
+  if (!remove_mean && a.s * a.n <= kPfn * nthr) return launch_qrq_var<double, TI, 3>(a, q, lds, st);
+  return launch_qrq_var<double, TI, 0>(a, q, lds, st);
+}
+
+hipError_t launch_qr_queue_f64(const QrGeom& g, const void* D, int in_f64, int64_t ldd, int64_t m,
+                               int64_t b, int64_t P, int remove_mean, double* mean_ws, double* V,
+                               double* Tleaf, int64_t nch_leaf, double* Rbuf, double* Ttree,
+                               int64_t nch_tree, int store_q, void* counters, hipStream_t st,
+                               const Batch& bt) {
+  if (P < 1 || bt.count < 1) return hipErrorInvalidValue;
+  if (in_f64)
+    return launch_qrq<double>(g, (const double*)D, ldd, m, b, P, remove_mean, mean_ws, V, Tleaf,
+                              nch_leaf, Rbuf, Ttree, nch_tree, store_q, counters, st, bt);
+  return launch_qrq<float>(g, (const float*)D, ldd, m, b, P, remove_mean, mean_ws, V, Tleaf,
+                           nch_leaf, Rbuf, Ttree, nch_tree, store_q, counters, st, bt);
+}
+
+template <typename TO>
+static hipError_t launch_applyq_t(const ApplyArgs<double, TO>& tree,
+                                  const ApplyArgs<double, TO>& leaf, const ApplyQueue& q,
+                                  size_t lds, hipStream_t st) {
+  const void* fn = (const void*)k_apply_queue<double, TO>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int64_t ntasks = q.lvl_off[q.nlev + 1];
+  const int64_t grid = queue_grid(fn, 256, lds, ntasks);
+  if (grid < 1) return hipSuccess;
+  hipLaunchKernelGGL((k_apply_queue<double, TO>), dim3((unsigned)grid), dim3(256), lds, st, tree,
+                     leaf, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_queue_f64(const QrGeom& g, int64_t m, int64_t b, int64_t P,
+                                  const double* V, const double* Tleaf, int64_t nch_leaf,
+                                  const double* Rbuf, const double* Ttree, int64_t nch_tree,
+                                  double* W, int64_t ldw, const int64_t* nr, int64_t nr_stride,
+                                  int64_t ncols, void* U, int out_f64, int64_t ldu, void* counters,
+                                  hipStream_t st, const Batch& bt) {
+  if (P < 1 || bt.count < 1) return hipErrorInvalidValue;
+  ApplyQueue q{};
+  q.P = P;
+  int nlev = 0;
+  for (int64_t h = 1; h < P; h *= 2) ++nlev;
+  if (nlev > kMaxQueueLevels) return hipErrorNotSupported;
+  q.nlev = nlev;
+  q.ntiles = (ncols + 15) / 16;
+  q.ncols = ncols;
+  q.nr = nr;
+  q.nr_stride = nr_stride;
+  q.lvl_off[0] = 0;
+  for (int k = 0; k < nlev; ++k) {
+    const int64_t h = (int64_t)1 << (nlev - 1 - k);
+    q.lvl_off[k + 1] = q.lvl_off[k] + bt.count * ((P - h + 2 * h - 1) / (2 * h)) * q.ntiles;
+  }
+  q.lvl_off[nlev + 1] = q.lvl_off[nlev] + bt.count * P * q.ntiles;
+  q.next = (unsigned long long*)counters;
+  q.cnt = (unsigned int*)((char*)counters + 256);
+  q.err = (int*)((char*)counters + 64);
+  const size_t lds = apply_lds_bytes(g, 8);
+  if (lds + 64 > kQrLdsBudget) return hipErrorNotSupported;
+  if (out_f64) {
+    ApplyArgs<double, double> t{}, l{};
+    t.n = l.n = g.n; t.s = l.s = g.s; t.npanels = l.npanels = g.npanels;
+    t.mode = 1; l.mode = 0; t.nr = l.nr = nullptr; t.ncols = l.ncols = ncols;
+    t.P = l.P = P; t.Rbuf = Rbuf; t.Ttree = Ttree; t.nch_tree = nch_tree;
+    t.W = l.W = W; t.ldw = l.ldw = ldw;
+    l.m = m; l.b = b; l.V = V; l.Tleaf = Tleaf; l.nch_leaf = nch_leaf; l.U = (double*)U;
+    l.ldu = ldu;
+    set_apply_batch(t, bt);
+    set_apply_batch(l, bt);
+    return launch_applyq_t<double>(t, l, q, lds, st);
+  }
+  ApplyArgs<double, float> t{}, l{};
+  t.n = l.n = g.n; t.s = l.s = g.s; t.npanels = l.npanels = g.npanels;
+  t.mode = 1; l.mode = 0; t.nr = l.nr = nullptr; t.ncols = l.ncols = ncols;
+  t.P = l.P = P; t.Rbuf = Rbuf; t.Ttree = Ttree; t.nch_tree = nch_tree;
+  t.W = l.W = W; t.ldw = l.ldw = ldw;
+  l.m = m; l.b = b; l.V = V; l.Tleaf = Tleaf; l.nch_leaf = nch_leaf; l.U = (float*)U;
+  l.ldu = ldu;
+  set_apply_batch(t, bt);
+  set_apply_batch(l, bt);
+  return launch_applyq_t<float>(t, l, q, lds, st);
 }
 
 }  // namespace pylom

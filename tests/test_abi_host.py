@@ -380,3 +380,47 @@ def test_ooc_plan_and_failure_paths(hctx):
     assert call(prec=api.MIXED) == -6            # FP64 compute only
     assert call(m=50, n=100) == -2
     hctx.set_option("ws_cap_mb", 0)
+
+
+def test_work_queue_option_is_switched_off(hctx):
+    # the work-queue launches are switched off: the option keeps its default
+    # (one launch per phase and level) and refuses to be turned on
+    assert hctx.get_option("work_queue") == 0
+    with pytest.raises(api.PylomError) as e:
+        hctx.set_option("work_queue", 1)
+    assert e.value.status == -6
+    hctx.set_option("work_queue", 0)
+
+
+def test_tuning_file_round_trip(hctx, tmp_path):
+    # a measured table read from JSON steers the leaf height of every shape
+    # in its class (path, precision, floor(log2 m), n rounded up to 16)
+    m, n = 10_000_000, 100        # the stacked path (more than 8,388,608 rows)
+    p = tmp_path / "tune.json"
+    p.write_text('{"pylom_tuning": 1, "entries": [\n'
+                 '  {"path": "stacked", "precision": "fp64", "m_log2": 23, "n_bucket": 112, '
+                 '"block_rows": 1536, "ms": 12.5},\n'
+                 '  {"path": "blocked", "precision": "mixed", "m_log2": 22, "n_bucket": 1808, '
+                 '"block_rows": 16384, "ms": 1500}\n]}\n')
+    assert hctx.tune_load(str(p)) == 2
+    assert api.tune_block_rows(m, n, hctx) == 1536           # 2^23 <= m < 2^24, n -> 112
+    assert hctx.plan(m, n)["block_rows"] == 1536
+    assert hctx.plan(m, 97)["block_rows"] == 1536            # same n bucket
+    assert hctx.plan(m, 120)["block_rows"] != 1536           # another bucket
+    assert hctx.plan(20_000_000, n)["block_rows"] != 1536    # another m bucket
+    hctx.set_option("block_rows", 2048)                      # an explicit height wins
+    assert hctx.plan(m, n)["block_rows"] == 2048
+    hctx.set_option("block_rows", 0)
+    q = tmp_path / "saved.json"
+    hctx.tune_save(str(q))
+    other = api.Context(-1)
+    assert other.tune_load(str(q)) == 2
+    assert other.plan(m, n)["block_rows"] == 1536
+    other.close()
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"pylom_tuning": 1, "entries": [{"path": "sideways", "precision": "fp64", '
+                   '"m_log2": 3, "n_bucket": 16, "block_rows": 64}]}')
+    with pytest.raises(api.PylomError):
+        hctx.tune_load(str(bad))
+    with pytest.raises(api.PylomError):
+        hctx.tune_load(str(tmp_path / "missing.json"))

@@ -241,3 +241,33 @@ def test_pod_nonfinite_input_reported(precision, blocked_from, bad):
     rc, _ = ctx.status()
     assert rc == 0 and out.nr > 0
     ctx.close()
+
+
+def test_autotune_records_a_measured_height_and_stays_exact(tmp_path):
+    # the measured leaf height is one of the candidates, steers later calls
+    # of the same shape class, survives a JSON round trip, and the POD at
+    # that height still matches the oracle
+    torch = _torch()
+    from paper_2405_15529_amd import api
+    m, n = 60000, 48
+    say(f"[gpu] autotune {m}x{n}")
+    D = synth.plain_pod_fp64(m=m, n=n, seed=17)
+    Dg = torch.from_numpy(D).cuda()
+    ctx = api.Context(0)
+    b, ms = ctx.autotune(Dg, precision="fp64", remove_mean=True, reps=2)
+    say(f"    best leaf height {b} rows, {ms:.3f} ms")
+    assert b >= n and ms > 0
+    assert ctx.plan(m, n)["block_rows"] == b
+    path = tmp_path / "tune.json"
+    ctx.tune_save(str(path))
+    ctx.close()
+    ctx2 = api.Context(0)
+    assert ctx2.tune_load(str(path)) == 1
+    assert ctx2.plan(m, n)["block_rows"] == b
+    out = api.pod(Dg, remove_mean=True, r=0.01, ctx=ctx2)
+    assert ctx2.status()[0] == 0
+    ref = oracle.pod(D, remove_mean=True, r=0.01)
+    res = dict(U=out.U.cpu().numpy(), S=out.S.cpu().numpy(), VT=out.VT_full.cpu().numpy(),
+               nr=out.nr, rc=0)
+    assert_pod_parity(res, ref, 0.01)
+    ctx2.close()
