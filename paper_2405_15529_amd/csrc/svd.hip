@@ -142,7 +142,10 @@ __device__ __forceinline__ void grid_barrier(unsigned int* bar, unsigned int G, 
     }
     const unsigned int target = epoch * ng;
     unsigned long long spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    // relaxed polls: an acquire load invalidates this XCD's L2 on every
+    // iteration, under workgroups still loading and storing their columns
+    // for this step; the fence after the loop is the acquire
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(2);
       if ((++spins & 1023ull) == 0 &&
           (spins > (1ull << 24) ||
