@@ -288,6 +288,90 @@ __global__ __launch_bounds__(256) void k_make_work(int64_t m, int n, const TI* _
   for (int col = lane; col < n; col += 64) out[col] = (T)((double)row[col] - mu);
 }
 
+// The same pass with 16-byte accesses, for rows of n % VL == 0 elements
+// starting on 16-byte boundaries: each lane loads its NV vectors of the row
+// once, keeps them in registers across the mean, and stores the shifted
+// values (one HBM read and one write per element).
+template <typename TI>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float4 type;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  typedef double2 type;
+  static constexpr int n = 2;
+};
+
+template <typename TI, typename T>
+__device__ __forceinline__ void store_shifted(T* __restrict__ out, int64_t e0, float4 x, double mu) {
+  if constexpr (sizeof(T) == 4) {
+    float4 y;
+    y.x = (float)((double)x.x - mu);
+    y.y = (float)((double)x.y - mu);
+    y.z = (float)((double)x.z - mu);
+    y.w = (float)((double)x.w - mu);
+    *reinterpret_cast<float4*>(out + e0) = y;
+  } else {
+    double2 y0, y1;
+    y0.x = (double)x.x - mu;
+    y0.y = (double)x.y - mu;
+    y1.x = (double)x.z - mu;
+    y1.y = (double)x.w - mu;
+    *reinterpret_cast<double2*>(out + e0) = y0;
+    *reinterpret_cast<double2*>(out + e0 + 2) = y1;
+  }
+}
+template <typename TI, typename T>
+__device__ __forceinline__ void store_shifted(T* __restrict__ out, int64_t e0, double2 x,
+                                              double mu) {
+  double2 y;
+  y.x = x.x - mu;
+  y.y = x.y - mu;
+  *reinterpret_cast<double2*>(out + e0) = y;
+}
+__device__ __forceinline__ double vsum(float4 x) {
+  return ((double)x.x + (double)x.y) + ((double)x.z + (double)x.w);
+}
+__device__ __forceinline__ double vsum(double2 x) { return x.x + x.y; }
+
+template <typename TI, typename T, int NV>
+__global__ __launch_bounds__(256) void k_make_work_v(int64_t m, int n, const TI* __restrict__ D,
+                                                     int64_t ldd, int remove_mean,
+                                                     double* __restrict__ mean_out,
+                                                     T* __restrict__ W) {
+  typedef typename Vec16<TI>::type V;
+  constexpr int VL = Vec16<TI>::n;
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= m) return;
+  const V* row = reinterpret_cast<const V*>(D + r * ldd);
+  const int nv = n / VL;
+  V x[NV];
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < NV; ++t) {
+    const int idx = lane + 64 * t;
+    if (idx < nv) {
+      x[t] = row[idx];
+      acc += vsum(x[t]);
+    }
+  }
+  double mu = 0.0;
+  if (remove_mean) {
+    mu = wave_sum(acc) / (double)n;
+    if (lane == 0 && mean_out) mean_out[r] = mu;
+  }
+  T* out = W + r * (int64_t)n;
+#pragma unroll
+  for (int t = 0; t < NV; ++t) {
+    const int idx = lane + 64 * t;
+    if (idx < nv) store_shifted<TI, T>(out, (int64_t)idx * VL, x[t], mu);
+  }
+}
+
 // Diagonal block (c0, c0) of R_j, j = 2 h q (R_j at R + q rstride), into
 // the panel state slot of pair q (kw x kw, zeros below the diagonal).
 __global__ __launch_bounds__(256) void k_diag_load(int n, int64_t c0, int kw,
@@ -374,6 +458,24 @@ hipError_t launch_make_work(int in_f64, int out_f64, int64_t m, int n, const voi
                             int remove_mean, double* mean_out, void* W, hipStream_t st) {
   if (m <= 0) return hipSuccess;
   const dim3 grid((unsigned)((m + 3) / 4));
+  const int vl = in_f64 ? 2 : 4;
+  const bool vec = n % vl == 0 && ldd % vl == 0 && ((uintptr_t)D & 15) == 0 &&
+                   ((uintptr_t)W & 15) == 0 && n <= 2048;
+  if (vec) {
+    // 16-byte accesses, the row held in registers (up to 2048 elements)
+    if (in_f64 && out_f64)
+      hipLaunchKernelGGL((k_make_work_v<double, double, 16>), grid, dim3(256), 0, st, m, n,
+                         (const double*)D, ldd, remove_mean, mean_out, (double*)W);
+    else if (!in_f64 && out_f64)
+      hipLaunchKernelGGL((k_make_work_v<float, double, 8>), grid, dim3(256), 0, st, m, n,
+                         (const float*)D, ldd, remove_mean, mean_out, (double*)W);
+    else if (!in_f64 && !out_f64)
+      hipLaunchKernelGGL((k_make_work_v<float, float, 8>), grid, dim3(256), 0, st, m, n,
+                         (const float*)D, ldd, remove_mean, mean_out, (float*)W);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (in_f64 && out_f64)
     hipLaunchKernelGGL((k_make_work<double, double>), grid, dim3(256), 0, st, m, n,
                        (const double*)D, ldd, remove_mean, mean_out, (double*)W);
