@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--spod-m", type=int, default=262144)
     ap.add_argument("--spod-nt", type=int, default=2048)
     ap.add_argument("--spod-steps", type=int, default=3)
+    ap.add_argument("--only-spod", action="store_true",
+                    help="run only the SPOD leg (once per --spod-block-rows value)")
+    ap.add_argument("--spod-block-rows", type=int, nargs="*", default=None,
+                    help="leaf heights of the SPOD realification to time (0: the library's)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-ooc", action="store_true")
     ap.add_argument("--only-ooc", action="store_true",
@@ -84,7 +88,7 @@ def parse():
     return ap.parse_args()
 
 
-def timed_spod(api, m, nt, npwin, nolap, steps, warmup):
+def timed_spod(api, m, nt, npwin, nolap, steps, warmup, block_rows=0):
     """Batched SPOD (C4 shape): one pylom_spod call per step on a resident
     FP32 snapshot matrix; complex64 spectra and modes."""
     import torch
@@ -93,6 +97,8 @@ def timed_spod(api, m, nt, npwin, nolap, steps, warmup):
     D = torch.from_numpy(synth.spod_field(m, nt, seed=3, nmodes=32)).cuda()
     ctx = api.Context(0)
     ctx.set_option("timing", max(1, steps))
+    if block_rows:
+        ctx.set_option("block_rows", block_rows)
     nb, nf, ws = api.spod_query(m, nt, npwin, nolap, "c64", ctx)
     ctx.check(ctx.lib.pylom_reserve(ctx.h, ws))
     out = None
@@ -938,6 +944,17 @@ def main():
     import torch
     from paper_2405_15529_amd import api
 
+    if args.only_spod:
+        res = []
+        for b in (args.spod_block_rows or [0]):
+            r = timed_spod(api, args.spod_m, args.spod_nt, 256, 128, args.spod_steps,
+                           1 if args.warmup else 0, b)
+            r["block_rows"] = b
+            res.append(r)
+            print(f"[bench] spod b={b}: {r['ms_per_step']} ms {r['phase_ms']}", file=sys.stderr,
+                  flush=True)
+        print(json.dumps({"spod": res}), flush=True)
+        return
     if args.only_ooc:
         print(json.dumps({"out_of_core": timed_ooc(api, args.ooc_m, args.ooc_n, args.ooc_window,
                                                    2)}), flush=True)

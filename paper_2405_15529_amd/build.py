@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpylom.so")
-SOURCES = ["abi.hip", "tsqr.hip", "svd.hip", "misc.hip", "refine.hip", "spod.hip", "blocked.hip",
-           "dmd.hip"]
+SOURCES = ["abi.hip", "tsqr.hip", "svd.hip", "misc.hip", "refine.hip", "spod.hip", "ctsqr.hip",
+           "blocked.hip", "dmd.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -2479,12 +2479,10 @@ extern "C" int pylom_pod_host(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, i
 // SPOD: FFT front end + one batch of realified TSQR-SVD problems
 // ---------------------------------------------------------------------------
 struct SpodPlan {
-  int64_t m, nt, npwin, nolap, nb, nf, n, M2, b, P, nch_leaf, nch_tree, levels;
+  int64_t m, nt, npwin, nolap, nb, nf, n, P, ldm;
   int e_f64;
-  QrGeom g;
   JacobiPlan jp;
-  size_t oE, oV, oTleaf, oR, oTtree, oW, oSvd, oS, oVT, oUR, oNr, oSt, oUe, oQ1, oQ2, total;
-  size_t q1_bytes, q2_bytes;
+  size_t oE, oTab, oScl, oRn, oVn, oRr, oSvd, oS, oVT, oUR, oNr, oSt, total;
   size_t svd_stride;
 };
 
@@ -2503,47 +2501,28 @@ static int make_spod_plan(pylom_ctx c, pylom_dtype spectra, int64_t m, int64_t n
   p->m = m; p->nt = nt; p->npwin = npwin; p->nolap = nolap; p->nb = nb;
   p->nf = npwin / 2 + 1;
   p->n = 2 * nb;
-  p->M2 = 2 * m;
   p->e_f64 = spectra == PYLOM_C128;
-  if (spod_fft_lds_bytes((int)npwin, (int)nb, p->e_f64 ? 8 : 4) > (size_t)160 * 1024)
-    return fail(c, PYLOM_ENOTSUP, "npwin x blocks too large for the FFT staging");
-  const int64_t n = p->n;
-  int64_t b = c->block_rows > 0 ? c->block_rows : 4096;
-  if (b < n) b = n;
-  int64_t P = p->M2 / b;
-  if (P < 1) P = 1;
-  p->b = b;
-  p->P = P;
-  if (!qr_geom((int)n, 8, &p->g)) return fail(c, PYLOM_ENOTSUP, "no chunk geometry");
-  if (!jacobi_plan((int)n, &p->jp) || p->jp.G != 1)
+  p->P = ctsqr_leaves(m);
+  p->ldm = (m + 63) / 64 * 64;
+  if (p->P > 0x7fffffff) return fail(c, PYLOM_ESHAPE, "too many rows");
+  if (!jacobi_plan((int)p->n, &p->jp) || p->jp.G != 1)
     return fail(c, PYLOM_ENOTSUP, "no single-workgroup Jacobi plan");
-  const int64_t last = p->M2 - (P - 1) * b;
-  const int64_t s = p->g.s, np = p->g.npanels, nf = p->nf;
-  p->nch_leaf = (last + s - 1) / s;
-  p->nch_tree = (n + s - 1) / s;
-  int64_t lv = 0;
-  for (int64_t h = 1; h < P; h *= 2) ++lv;
-  p->levels = lv;
   p->svd_stride = jacobi_ws_stride(p->jp, (int)c->max_sweeps);
   const size_t es = p->e_f64 ? 8 : 4;
+  const int64_t nf = p->nf, n = p->n;
   size_t off = 0;
-  p->oE = off;     off = align_up(off + es * (size_t)nf * p->M2 * n);
-  p->oV = off;     off = align_up(off + 8 * (size_t)nf * p->M2 * n);
-  p->oTleaf = off; off = align_up(off + 8 * (size_t)nf * P * p->nch_leaf * np * 256);
-  p->oR = off;     off = align_up(off + 8 * (size_t)nf * P * n * n);
-  p->oTtree = off; off = align_up(off + 8 * (size_t)nf * P * p->nch_tree * np * 256);
-  p->oW = off;     off = align_up(off + 8 * (size_t)nf * P * n * n);
+  p->oE = off;     off = align_up(off + 2 * es * (size_t)nf * nb * p->ldm);
+  p->oTab = off;   off = align_up(off + spod_table_bytes((int)npwin, p->e_f64));
+  p->oScl = off;   off = align_up(off + 8);
+  p->oRn = off;    off = align_up(off + ctsqr_node_bytes() * (size_t)nf * p->P);
+  p->oVn = off;    off = align_up(off + ctsqr_vnode_bytes() * (size_t)nf * p->P);
+  p->oRr = off;    off = align_up(off + 8 * (size_t)nf * n * n);
   p->oSvd = off;   off = align_up(off + p->svd_stride * (size_t)nf);
   p->oS = off;     off = align_up(off + 8 * (size_t)nf * n);
   p->oVT = off;    off = align_up(off + 8 * (size_t)nf * n * n);
   p->oUR = off;    off = align_up(off + 8 * (size_t)nf * n * n);
   p->oNr = off;    off = align_up(off + 8 * (size_t)nf);
   p->oSt = off;    off = align_up(off + 8 * (size_t)nf);
-  p->oUe = off;    off = align_up(off + 8 * (size_t)nf * p->M2 * nb);
-  p->q1_bytes = queue_counter_bytes(nf, P, 1);
-  p->q2_bytes = queue_counter_bytes(nf, P, (nb + 15) / 16);
-  p->oQ1 = off;    off = align_up(off + p->q1_bytes);
-  p->oQ2 = off;    off = align_up(off + p->q2_bytes);
   p->total = off;
   return PYLOM_OK;
 }
@@ -2582,19 +2561,16 @@ extern "C" int pylom_spod(pylom_ctx c, pylom_dtype spectra, pylom_prec prec, int
   if (rc) return rc;
   char* ws = (char*)c->ws;
   void* E = ws + p.oE;
-  double* V = (double*)(ws + p.oV);
-  double* Tleaf = (double*)(ws + p.oTleaf);
-  double* R = (double*)(ws + p.oR);
-  double* Ttree = (double*)(ws + p.oTtree);
-  double* W = (double*)(ws + p.oW);
+  double* Rn = (double*)(ws + p.oRn);
+  double* Vn = (double*)(ws + p.oVn);
+  double* Rr = (double*)(ws + p.oRr);
   double* S = (double*)(ws + p.oS);
   double* VTb = (double*)(ws + p.oVT);
   double* URb = (double*)(ws + p.oUR);
   int64_t* nr = (int64_t*)(ws + p.oNr);
   int* st_each = (int*)(ws + p.oSt);
-  double* Ue = (double*)(ws + p.oUe);
   hipStream_t st = c->stream;
-  const int64_t n = p.n, nb = p.nb, nf = p.nf, M2 = p.M2, P = p.P, np = p.g.npanels;
+  const int64_t n = p.n, nb = p.nb, nf = p.nf, P = p.P;
   const bool tm = c->timing > 0 && !c->ev.empty();
   hipEvent_t* evs = tm ? &c->ev[(size_t)(c->ev_calls % c->timing) * kEvPerSlot] : nullptr;
   if (tm) c->ev_mixed[(size_t)(c->ev_calls % c->timing)] = 0;
@@ -2602,72 +2578,33 @@ extern "C" int pylom_spod(pylom_ctx c, pylom_dtype spectra, pylom_prec prec, int
   if (tm) HIPCHK(c, hipEventRecord(evs[j], st), "hipEventRecord")
 
   EVREC(0);
-  HIPCHK(c, launch_spod_fft(p.e_f64, m, nt, D, ldd, (int)npwin, (int)nolap, (int)nb, window,
-                            remove_mean, E, n, M2 * n, st), "SPOD front end");
+  HIPCHK(c, launch_spod_front(p.e_f64, m, nt, D, ldd, (int)npwin, (int)nolap, (int)nb, window,
+                              remove_mean, ws + p.oTab, (double*)(ws + p.oScl), E, p.ldm, st),
+         "SPOD front end");
   EVREC(1);
-  Batch bl;
-  bl.count = nf;
-  bl.sD = M2 * n;
-  bl.sV = M2 * n;
-  bl.sTleaf = P * p.nch_leaf * np * 256;
-  bl.sR = P * n * n;
-  bl.sTtree = P * p.nch_tree * np * 256;
-  bl.sW = P * n * n;
-  bl.sU = M2 * nb;
-  // every leaf QR and every tree combine of every frequency: one work-queue
-  // launch (the per-level form with the option off)
-  bool queued = false;
-  if (c->work_queue) {
-    HIPCHK(c, launch_queue_reset(ws + p.oQ1, p.q1_bytes, st), "queue reset");
-    const hipError_t e = launch_qr_queue_f64(p.g, E, p.e_f64, n, M2, p.b, P, 0, nullptr, V, Tleaf,
-                                             p.nch_leaf, R, Ttree, p.nch_tree, 1, ws + p.oQ1, st,
-                                             bl);
-    if (e == hipSuccess) queued = true;
-    else if (e != hipErrorNotSupported) return hip_fail(c, e, "leaf QR and tree (work queue)");
-  }
-  if (!queued) {
-    HIPCHK(c, launch_leaf_qr_f64(p.g, E, p.e_f64, n, M2, p.b, P, 0, nullptr, V, Tleaf, p.nch_leaf,
-                                 R, st, bl), "leaf QR");
-  }
+  HIPCHK(c, launch_cleaf(p.e_f64, 0, (int)nb, m, p.ldm, P, nf, E, Rn, nullptr, nullptr, st),
+         "leaf QR");
   EVREC(2);
-  if (!queued)
-    for (int64_t h = 1; h < P; h *= 2)
-      HIPCHK(c, launch_tree_combine_f64(p.g, h, P, R, Ttree, p.nch_tree, 1, st, bl),
-             "tree combine");
+  for (int64_t h = 1; h < P; h *= 2)
+    HIPCHK(c, launch_ctree_combine((int)nb, P, h, nf, Rn, Vn, st), "tree combine");
   EVREC(3);
-  HIPCHK(c, launch_small_svd_batched(p.jp, nf, R, P * n * n, (int)c->max_sweeps, ws + p.oSvd, S, n,
+  HIPCHK(c, launch_spod_root_realify((int)nb, P, nf, Rn, Rr, st), "root embedding");
+  HIPCHK(c, launch_small_svd_batched(p.jp, nf, Rr, n * n, (int)c->max_sweeps, ws + p.oSvd, S, n,
                                      VTb, n, n * n, URb, n * n, 0.0, nr, st_each, c->status_dev,
                                      st), "batched SVD");
   c->status_valid = 1;
   c->status_pairs = 1;
-  HIPCHK(c, launch_select_even((int)n, (int)nb, nf, URb, n * n, W, n, P * n * n, st), "root W");
+  // the root blocks of Rn become the down-tree factors C
+  HIPCHK(c, launch_spod_root_modes((int)nb, P, nf, S, VTb, URb, Rn, L, st), "root modes");
   EVREC(4);
-  // the down-tree propagation of every level and every leaf apply: one
-  // work-queue launch (or per level)
-  bool bqueued = false;
-  if (queued) {
-    HIPCHK(c, launch_queue_reset(ws + p.oQ2, p.q2_bytes, st), "queue reset");
-    const hipError_t e = launch_apply_queue_f64(p.g, M2, p.b, P, V, Tleaf, p.nch_leaf, R, Ttree,
-                                                p.nch_tree, W, n, nullptr, 0, nb, Ue, 1, nb,
-                                                ws + p.oQ2, st, bl);
-    if (e == hipSuccess) bqueued = true;
-    else if (e != hipErrorNotSupported) return hip_fail(c, e, "propagation and apply (work queue)");
-    // a timed-out dependency wait of either queue is reported by pylom_check
-    HIPCHK(c, launch_queue_err_merge(ws + p.oQ1, bqueued ? ws + p.oQ2 : nullptr,
-                                     c->status_dev + 1, st), "queue status");
-  }
   int64_t top = 1;
   while (top * 2 < P) top *= 2;
-  if (P > 1 && !bqueued)
+  if (P > 1)
     for (int64_t h = top; h >= 1; h /= 2)
-      HIPCHK(c, launch_apply_tree_f64(p.g, h, P, R, Ttree, p.nch_tree, W, n, nullptr, nb, st, bl),
-             "tree propagation");
+      HIPCHK(c, launch_ctree_apply((int)nb, P, h, nf, Rn, Vn, st), "tree propagation");
   EVREC(5);
-  if (!bqueued)
-    HIPCHK(c, launch_apply_leaf_f64(p.g, M2, p.b, P, V, Tleaf, p.nch_leaf, W, n, nullptr, nb, Ue,
-                                    1, nb, st, bl), "leaf apply");
-  HIPCHK(c, launch_spod_modes(p.e_f64, m, (int)nb, nf, Ue, M2 * nb, VTb, n * n, S, n, modes, L, st),
-         "modes");
+  HIPCHK(c, launch_cleaf(p.e_f64, 1, (int)nb, m, p.ldm, P, nf, E, nullptr, Rn, modes, st),
+         "leaf apply");
   HIPCHK(c, launch_spod_order((int)nf, (int)nb, dt, (int)npwin, L, freqs, order, st), "order");
   EVREC(6);
 #undef EVREC

@@ -266,20 +266,41 @@ hipError_t launch_rr_finish(int n, int k, const double* S0, const double* lam, d
 hipError_t launch_rr_form_u(int out_f64, int64_t m, int k, const double* Z, const double* M,
                             const int64_t* nr, void* U, int64_t ldu, hipStream_t st);
 
-// ---- SPOD (Alg. 6): front end, realified batch back end ----------------------
-size_t spod_fft_lds_bytes(int npwin, int nb, int esize);
-// Windowed one-sided FFT of every Welch block of every point of D (m x nt,
-// FP32), written as the realification of each frequency's m x nb spectral
-// matrix: E + f*sE is 2m x 2nb (ld ldE) in FP64 (e_f64) or FP32.
-hipError_t launch_spod_fft(int e_f64, int64_t m, int64_t nt, const float* D, int64_t ldd,
-                           int npwin, int nolap, int nb, int window, int remove_mean, void* E,
-                           int64_t ldE, int64_t sE, hipStream_t st);
-hipError_t launch_select_even(int n, int nb, int64_t count, const double* UR, int64_t sUR,
-                              double* W, int64_t ldw, int64_t sW, hipStream_t st);
-hipError_t launch_spod_modes(int out_f64, int64_t m, int nb, int64_t nf, const double* Ue,
-                             int64_t sUe, const double* VT, int64_t sVT, const double* S,
-                             int64_t sS, void* modes, double* L, hipStream_t st);
+// ---- SPOD (Alg. 6): front end, complex TSQR back end ------------------------
+size_t spod_table_bytes(int npwin, int t_f64);
+// Twiddle/window tables (tab, spod_table_bytes) and scl[0], then the windowed
+// one-sided FFT of every Welch block of every point of D (m x nt, FP32): the
+// spectral matrix of frequency f is column-major, column blk at complex
+// element (f * nb + blk) * ldm of E (complex128 if t_f64, else complex64).
+hipError_t launch_spod_front(int t_f64, int64_t m, int64_t nt, const float* D, int64_t ldd,
+                             int npwin, int nolap, int nb, int window, int remove_mean, void* tab,
+                             double* scl, void* E, int64_t ldm, hipStream_t st);
+hipError_t launch_spod_root_realify(int nb, int64_t P, int64_t nf, const double* Rn, double* Rr,
+                                    hipStream_t st);
+hipError_t launch_spod_root_modes(int nb, int64_t P, int64_t nf, const double* S, const double* VT,
+                                  const double* UR, double* Cn, double* L, hipStream_t st);
 hipError_t launch_spod_order(int nf, int nb, double dt, int npwin, const double* L, double* freqs,
                              int64_t* order, hipStream_t st);
+
+// ---- complex TSQR of the spectral matrices (ctsqr.hip) -------------------------
+// 128-row leaves (one wave each): P = ctsqr_leaves(m) per frequency.  Tree
+// node blocks are ctsqr_node_bytes (16 x 16 complex FP64), reflector blocks
+// ctsqr_vnode_bytes; both arrays are [nf][P].
+int64_t ctsqr_leaves(int64_t m);
+size_t ctsqr_node_bytes();
+size_t ctsqr_vnode_bytes();
+// apply = 0: R of every leaf into Rn.  apply = 1: the same factorisation,
+// then modes[f][p][c] = (Q_leaf [C_leaf; 0])[p][c] (complex, T = t_f64 ?
+// double : float) with C_leaf the node block of Cn.
+hipError_t launch_cleaf(int t_f64, int apply, int nb, int64_t m, int64_t ldm, int64_t P,
+                        int64_t nf, const void* E, double* Rn, const double* Cn, void* modes,
+                        hipStream_t st);
+// Level h of the binary reduction tree (every frequency): node j = 2hc absorbs
+// node j + h; the combine's reflectors go to Vn[j + h].
+hipError_t launch_ctree_combine(int nb, int64_t P, int64_t h, int64_t nf, double* Rn,
+                                double* Vn, hipStream_t st);
+// Level h down the tree: [C_j; C_{j+h}] = Q_(j, j+h) [C_j; 0].
+hipError_t launch_ctree_apply(int nb, int64_t P, int64_t h, int64_t nf, double* Cn,
+                              const double* Vn, hipStream_t st);
 
 }  // namespace pylom

@@ -1,203 +1,302 @@
-// spod.hip -- SPOD front end and back end (Alg. 6 with the SVD of the
+// spod.hip -- SPOD front end and root stage (Alg. 6 with the SVD of the
 // spectral matrices, Sec. 2.3 and Eq. csdimp).
 //
 // Front end (k_spod_fft): for every point p the temporal mean is removed
 // (optional), the series is cut into nBlks Welch blocks of npwin samples
-// starting every npwin - nolap samples, each block is windowed and
-// transformed with a radix-2 Stockham FFT in LDS (one wave per point), and
-// the one-sided spectrum q_f = c_f DFT_f(w x) / sum(w) / sqrt(nBlks)
+// starting every npwin - nolap samples, each block is windowed, and the
+// one-sided spectrum q_f = c_f DFT_f(w x) / sum(w) / sqrt(nBlks)
 // (c_f = 2 for 0 < f < npwin/2, else 1) is kept for f = 0..npwin/2.
 //
-// The complex tall-skinny SVD of each frequency's m x nBlks matrix
-// Q_f = X + iY is computed as the real SVD of its realification: the
-// 2m x 2nBlks matrix whose rows 2p and 2p+1 are [X_p, -Y_p] and [Y_p, X_p].
-// It maps [Re z; Im z] to the interleaved (Re, Im) parts of Q_f z, so every
-// singular value of Q_f appears twice, and a left/right singular pair of the
-// realification at index 2c de-embeds to a complex pair (e^{i theta} u_c,
-// e^{i theta} v_c) of Q_f.  The front end writes each frequency's
-// realification row-contiguously (the per-point staging in LDS turns the
-// frequency-major scatter into 4 nBlks contiguous values per frequency).
+// The real block of N = npwin samples is transformed as one complex sequence
+// of N2 = N/2 values z_n = y_{2n} + i y_{2n+1} (y = w x), Z = DFT_N2(z), and
+// split: Y_k = (Z_k + conj Z_{N2-k})/2 + W_N^k (Z_k - conj Z_{N2-k})/(2i).
+// The N2-point DFT runs in registers on a group of G lanes per point (C = N2/G
+// values per lane, n = C q + n2 for lane q of the group): a radix-2
+// decimation-in-frequency exchange across the G lanes, the twiddles
+// W_N2^(n2 k1), then a C-point radix-2 DFT inside each lane, so lane q ends
+// with Z_(k1 + G k2), k1 the bit reversal of q.  A wave holds 64/G points;
+// for one frequency and block its 64/G consecutive points are written as one
+// contiguous run of the column-major spectral matrix (column (f, blk) of ld
+// ldm complex values).
 //
-// Back end: k_spod_modes de-embeds mode c from column c of the realified U
-// (built from the even columns of U_R) and column 2c of V, fixes the phase so
-// that the largest-|.| entry of v_c (lowest index on ties) is real positive,
-// and writes L[f][c] = S_f[2c]^2; k_spod_order fills the frequency axis and
-// the frequency order by leading energy L[f][0] (descending, ties by
-// ascending frequency).
+// Root stage: the nb x nb complex root factor R of a frequency's TSQR is
+// embedded as the real 2nb x 2nb matrix [[Re R, -Im R], [Im R, Re R]] (it maps
+// [Re z; Im z] to [Re Rz; Im Rz]), whose singular values are those of R, each
+// twice; a singular pair at index 2c de-embeds to a complex pair
+// (e^{i theta} u_c, e^{i theta} v_c) of R.  k_spod_root_modes fixes the phase
+// so that the largest-|.| entry of v_c (lowest index on ties) is real
+// positive, writes the phase-fixed U_R as the root factor of the down-tree
+// apply, and L[f][c] = S[2c]^2.  k_spod_order fills the frequency axis and the
+// frequency order by leading energy L[f][0] (descending, ties by ascending
+// frequency).
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace pylom {
 
 namespace {
-constexpr int SW = 4;  // waves (points) per front-end workgroup
-}
 
 template <typename T>
-struct Cplx {
+struct Cx {
   T re, im;
 };
 
-// LDS carve per workgroup: twiddles (npwin/2), window (npwin), then per wave
-// two FFT buffers (2 * npwin) and the spectra staging (nf * nb).
-size_t spod_fft_lds_bytes(int npwin, int nb, int esize) {
-  const int nf = npwin / 2 + 1;
-  const size_t c = (size_t)2 * esize;  // one complex value
-  return c * (npwin / 2) + (size_t)esize * npwin + SW * c * ((size_t)2 * npwin + (size_t)nf * nb);
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return Cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+constexpr int bitrev_c(int i, int n) {
+  int r = 0;
+  for (int b = 1, rb = n >> 1; b < n; b <<= 1, rb >>= 1)
+    if (i & b) r |= rb;
+  return r;
 }
 
 template <typename T>
-__global__ __launch_bounds__(64 * SW) void k_spod_fft(int64_t m, int64_t nt, const float* __restrict__ D,
-                                                      int64_t ldd, int npwin, int logn, int step,
-                                                      int nb, int window, int remove_mean,
-                                                      T* __restrict__ E, int64_t ldE,
-                                                      int64_t sE) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int nf = npwin / 2 + 1;
-  Cplx<T>* tw = reinterpret_cast<Cplx<T>*>(smem);
-  T* win = reinterpret_cast<T*>(tw + npwin / 2);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  Cplx<T>* buf0 = reinterpret_cast<Cplx<T>*>(win + npwin) + (size_t)wave * (2 * npwin + nf * nb);
-  Cplx<T>* buf1 = buf0 + npwin;
-  Cplx<T>* stage = buf1 + npwin;  // [f][blk]
+struct T2v;
+template <>
+struct T2v<float> {
+  typedef float2 type;
+};
+template <>
+struct T2v<double> {
+  typedef double2 type;
+};
 
-  // twiddles exp(-2 pi i k / npwin) and the window (FP64 evaluation)
-  for (int k = tid; k < npwin / 2; k += 64 * SW) {
-    double sv, cv;
-    sincospi(-2.0 * (double)k / (double)npwin, &sv, &cv);
-    tw[k].re = (T)cv;
-    tw[k].im = (T)sv;
+// C-point radix-2 DFT of z inside one lane (decimation in time, natural-order
+// output); W_L^e = tw[e N / L], a uniform table read.
+template <typename T, int C, int N>
+__device__ __forceinline__ void fft_inlane(Cx<T> (&z)[C], const T* __restrict__ tw) {
+  Cx<T> y[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) y[bitrev_c(i, C)] = z[i];
+#pragma unroll
+  for (int L = 2; L <= C; L <<= 1) {
+#pragma unroll
+    for (int s0 = 0; s0 < C; s0 += L) {
+#pragma unroll
+      for (int e = 0; e < L / 2; ++e) {
+        Cx<T> bb = y[s0 + e + L / 2];
+        if (e != 0) {
+          const int t = e * (N / L);
+          bb = cmul(bb, Cx<T>{tw[2 * t], tw[2 * t + 1]});
+        }
+        const Cx<T> aa = y[s0 + e];
+        y[s0 + e] = Cx<T>{aa.re + bb.re, aa.im + bb.im};
+        y[s0 + e + L / 2] = Cx<T>{aa.re - bb.re, aa.im - bb.im};
+      }
+    }
   }
-  const double a0 = window == 1 ? 0.54 : 0.5, a1 = window == 1 ? 0.46 : 0.5;
-  for (int j = tid; j < npwin; j += 64 * SW)
-    win[j] = (T)(a0 - a1 * cospi(2.0 * (double)j / (double)(npwin - 1)));
-  __syncthreads();
-  // sum of the window (every wave computes it; FP64)
-  double wsum = 0.0;
-  for (int j = lane; j < npwin; j += 64) wsum += (double)win[j];
-  wsum = wave_sum(wsum);
-  const double base_scale = 1.0 / (wsum * sqrt((double)nb));
+#pragma unroll
+  for (int i = 0; i < C; ++i) z[i] = y[i];
+}
 
-  const int64_t p = (int64_t)blockIdx.x * SW + wave;
-  if (p >= m) return;  // no block-wide barrier below this point
-  const float* row = D + p * ldd;
+// tab: W_N^t (re, im) for t < N, then the window w_j, j < N.
+template <typename T, int G, int C>
+__global__ __launch_bounds__(256) void k_spod_fft(int64_t m, int64_t nt, const float* __restrict__ D,
+                                                  int64_t ldd, int step, int nb, int remove_mean,
+                                                  const T* __restrict__ tab,
+                                                  const double* __restrict__ scl,
+                                                  T* __restrict__ E, int64_t ldm) {
+  constexpr int N2 = G * C, N = 2 * N2, PW = 64 / G;
+  typedef typename T2v<T>::type TT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane % G;
+  const int64_t p = ((int64_t)blockIdx.x * 4 + wave) * PW + lane / G;
+  const bool valid = p < m;
+  const float* row = D + (valid ? p : 0) * ldd;
+  const T* tw = tab;
+  const T* win = tab + 2 * N;
+  const double base_scale = scl[0];
   double mu = 0.0;
   if (remove_mean) {
     double acc = 0.0;
-    for (int64_t t = lane; t < nt; t += 64) acc += (double)row[t];
-    mu = wave_sum(acc) / (double)nt;
+    for (int64_t t = q; t < nt; t += G) acc += (double)row[t];
+    mu = group_sum<G>(acc) / (double)nt;
   }
+  const int k1 = bitrev_c(q, G);
+  // partner group lane holding Z_(N2 - k) for k = k1 + G k2 (k1 != 0)
+  const int src = lane - q + bitrev_c((G - k1) & (G - 1), G);
   for (int b = 0; b < nb; ++b) {
-    const int64_t i0 = (int64_t)b * step;
-    for (int j = lane; j < npwin; j += 64) {
-      buf0[j].re = (T)(((double)row[i0 + j] - mu) * (double)win[j]);
-      buf0[j].im = T(0);
+    const float* x = row + (int64_t)b * step;
+    Cx<T> z[C];
+#pragma unroll
+    for (int n2 = 0; n2 < C; ++n2) {
+      const int j = 2 * (C * q + n2);
+      z[n2].re = (T)(((double)x[j] - mu) * (double)win[j]);
+      z[n2].im = (T)(((double)x[j + 1] - mu) * (double)win[j + 1]);
     }
-    wave_lds_sync();
-    Cplx<T>* src = buf0;
-    Cplx<T>* dst = buf1;
-    for (int ls = 0; ls < logn; ++ls) {
-      const int Ns = 1 << ls;
-      for (int jj = lane; jj < npwin / 2; jj += 64) {
-        const Cplx<T> x0 = src[jj];
-        const Cplx<T> x1 = src[jj + npwin / 2];
-        const int k = jj & (Ns - 1);
-        const Cplx<T> w = tw[k << (logn - 1 - ls)];
-        const T yr = x1.re * w.re - x1.im * w.im;
-        const T yi = x1.re * w.im + x1.im * w.re;
-        const int d = ((jj - k) << 1) + k;
-        dst[d].re = x0.re + yr;
-        dst[d].im = x0.im + yi;
-        dst[d + Ns].re = x0.re - yr;
-        dst[d + Ns].im = x0.im - yi;
+    // decimation in frequency across the G lanes of the group
+#pragma unroll
+    for (int half = G / 2; half >= 1; half >>= 1) {
+      const bool up = (q & half) != 0;
+      const int ti = (q & (half - 1)) * (N / (2 * half));
+      const Cx<T> w = up ? Cx<T>{tw[2 * ti], tw[2 * ti + 1]} : Cx<T>{T(1), T(0)};
+#pragma unroll
+      for (int n2 = 0; n2 < C; ++n2) {
+        const T ore = __shfl_xor(z[n2].re, half, 64);
+        const T oim = __shfl_xor(z[n2].im, half, 64);
+        const Cx<T> d = up ? Cx<T>{ore - z[n2].re, oim - z[n2].im}
+                           : Cx<T>{z[n2].re + ore, z[n2].im + oim};
+        z[n2] = up ? cmul(d, w) : d;
       }
-      wave_lds_sync();
-      Cplx<T>* t = src;
-      src = dst;
-      dst = t;
     }
-    for (int f = lane; f < nf; f += 64) {
-      const T sc = (T)(((f > 0 && f < npwin / 2) ? 2.0 : 1.0) * base_scale);
-      stage[f * nb + b].re = src[f].re * sc;
-      stage[f * nb + b].im = src[f].im * sc;
+    if constexpr (G > 1) {
+#pragma unroll
+      for (int n2 = 1; n2 < C; ++n2) {
+        const int e = (n2 * k1) & (N2 - 1);
+        z[n2] = cmul(z[n2], Cx<T>{tw[4 * e], tw[4 * e + 1]});
+      }
     }
-    wave_lds_sync();
-  }
-  // rows 2p and 2p+1 of every frequency's realification: 4 nb contiguous values
-  const int ncol = 2 * nb;
-  for (int f = 0; f < nf; ++f) {
-    T* dstE = E + (int64_t)f * sE + 2 * p * ldE;
-    for (int t = lane; t < 2 * ncol; t += 64) {
-      const int r = t / ncol, c = t % ncol;
-      const int blk = c < nb ? c : c - nb;
-      const Cplx<T> q = stage[f * nb + blk];
-      T v;
-      if (r == 0) v = c < nb ? q.re : -q.im;
-      else v = c < nb ? q.im : q.re;
-      dstE[(int64_t)r * ldE + c] = v;
+    fft_inlane<T, C, N>(z, tw);
+    // real-input split and store
+#pragma unroll
+    for (int k2 = 0; k2 < C; ++k2) {
+      Cx<T> pz = z[(C - k2) & (C - 1)];
+      if constexpr (G > 1) {
+        const T rre = __shfl(z[C - 1 - k2].re, src, 64);
+        const T rim = __shfl(z[C - 1 - k2].im, src, 64);
+        if (q != 0) pz = Cx<T>{rre, rim};
+      }
+      const Cx<T> A = z[k2];
+      const Cx<T> Ev = {(A.re + pz.re) * T(0.5), (A.im - pz.im) * T(0.5)};
+      const Cx<T> O = {(A.im + pz.im) * T(0.5), (pz.re - A.re) * T(0.5)};
+      const int k = k1 + G * k2;
+      const Cx<T> wo = cmul(Cx<T>{tw[2 * k], tw[2 * k + 1]}, O);
+      const double sc = k == 0 ? base_scale : 2.0 * base_scale;
+      if (valid) {
+        TT v;
+        v.x = (T)((double)(Ev.re + wo.re) * sc);
+        v.y = (T)((double)(Ev.im + wo.im) * sc);
+        reinterpret_cast<TT*>(E)[((int64_t)k * nb + b) * ldm + p] = v;
+      }
+    }
+    if (valid && q == 0) {
+      TT v;
+      v.x = (T)(((double)z[0].re - (double)z[0].im) * base_scale);
+      v.y = T(0);
+      reinterpret_cast<TT*>(E)[((int64_t)N2 * nb + b) * ldm + p] = v;
     }
   }
 }
 
-hipError_t launch_spod_fft(int e_f64, int64_t m, int64_t nt, const float* D, int64_t ldd,
-                           int npwin, int nolap, int nb, int window, int remove_mean, void* E,
-                           int64_t ldE, int64_t sE, hipStream_t st) {
-  int logn = 0;
-  while ((1 << logn) < npwin) ++logn;
-  if ((1 << logn) != npwin || npwin < 4) return hipErrorInvalidValue;
-  const size_t lds = spod_fft_lds_bytes(npwin, nb, e_f64 ? 8 : 4);
-  const dim3 grid((unsigned)((m + SW - 1) / SW)), block(64 * SW);
+// Twiddles W_N^t and the window in FP64, rounded to T; scl[0] =
+// 1 / (sum of the rounded window * sqrt(nb)).
+template <typename T>
+__global__ __launch_bounds__(256) void k_spod_tables(int N, int window, int nb, T* __restrict__ tab,
+                                                     double* __restrict__ scl) {
+  __shared__ double part[4];
+  const double a0 = window == 1 ? 0.54 : 0.5, a1 = window == 1 ? 0.46 : 0.5;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) {
+    double sv, cv;
+    sincospi(-2.0 * (double)t / (double)N, &sv, &cv);
+    tab[2 * t] = (T)cv;
+    tab[2 * t + 1] = (T)sv;
+    const T w = (T)(a0 - a1 * cospi(2.0 * (double)t / (double)(N - 1)));
+    tab[2 * N + t] = w;
+    acc += (double)w;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double wsum = part[0] + part[1] + part[2] + part[3];
+    scl[0] = 1.0 / (wsum * sqrt((double)nb));
+  }
+}
+
+constexpr int fft_c(bool f64, int N2) { return N2 <= 32 ? N2 : (!f64 || N2 >= 2048 ? 32 : 16); }
+
+template <typename T, int N2>
+hipError_t fft_launch(int64_t m, int64_t nt, const float* D, int64_t ldd, int step, int nb,
+                      int remove_mean, const T* tab, const double* scl, T* E, int64_t ldm,
+                      hipStream_t st) {
+  constexpr int C = fft_c(sizeof(T) == 8, N2), G = N2 / C, PW = 64 / G;
+  const int64_t blocks = (m + 4 * PW - 1) / (4 * PW);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_spod_fft<T, G, C>), dim3((unsigned)blocks), dim3(256), 0, st, m, nt, D,
+                     ldd, step, nb, remove_mean, tab, scl, E, ldm);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fft_dispatch(int npwin, int64_t m, int64_t nt, const float* D, int64_t ldd, int step,
+                        int nb, int remove_mean, const T* tab, const double* scl, T* E,
+                        int64_t ldm, hipStream_t st) {
+  switch (npwin / 2) {
+#define PYLOM_FFT(K) \
+  case K:            \
+    return fft_launch<T, K>(m, nt, D, ldd, step, nb, remove_mean, tab, scl, E, ldm, st);
+    PYLOM_FFT(2) PYLOM_FFT(4) PYLOM_FFT(8) PYLOM_FFT(16) PYLOM_FFT(32) PYLOM_FFT(64)
+    PYLOM_FFT(128) PYLOM_FFT(256) PYLOM_FFT(512) PYLOM_FFT(1024) PYLOM_FFT(2048)
+#undef PYLOM_FFT
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+size_t spod_table_bytes(int npwin, int t_f64) { return (size_t)3 * npwin * (t_f64 ? 8 : 4); }
+
+hipError_t launch_spod_front(int t_f64, int64_t m, int64_t nt, const float* D, int64_t ldd,
+                             int npwin, int nolap, int nb, int window, int remove_mean, void* tab,
+                             double* scl, void* E, int64_t ldm, hipStream_t st) {
+  if (npwin < 4 || npwin > 4096 || (npwin & (npwin - 1)) || nolap < 0 || nolap >= npwin ||
+      nb < 1 || ldm < m || (int64_t)(nb - 1) * (npwin - nolap) + npwin > nt)
+    return hipErrorInvalidValue;
   const int step = npwin - nolap;
-  if (e_f64) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_spod_fft<double>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (t_f64) {
+    hipLaunchKernelGGL(k_spod_tables<double>, dim3(1), dim3(256), 0, st, npwin, window, nb,
+                       (double*)tab, scl);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_spod_fft<double>, grid, block, lds, st, m, nt, D, ldd, npwin, logn, step,
-                       nb, window, remove_mean, (double*)E, ldE, sE);
-  } else {
-    hipError_t e = hipFuncSetAttribute((const void*)k_spod_fft<float>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_spod_fft<float>, grid, block, lds, st, m, nt, D, ldd, npwin, logn, step,
-                       nb, window, remove_mean, (float*)E, ldE, sE);
+    return fft_dispatch<double>(npwin, m, nt, D, ldd, step, nb, remove_mean, (const double*)tab,
+                                scl, (double*)E, ldm, st);
   }
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_spod_tables<float>, dim3(1), dim3(256), 0, st, npwin, window, nb,
+                     (float*)tab, scl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return fft_dispatch<float>(npwin, m, nt, D, ldd, step, nb, remove_mean, (const float*)tab, scl,
+                             (float*)E, ldm, st);
 }
 
-// W of every problem's tree root: the even columns of U_R (one per complex
-// mode): W[i][c] = UR[i][2c], i < n, c < nb.
-__global__ void k_select_even(int n, int nb, const double* __restrict__ UR, int64_t sUR,
-                              double* __restrict__ W, int64_t ldw, int64_t sW) {
-  const int64_t f = blockIdx.y;
-  const double* u = UR + f * sUR;
-  double* w = W + f * sW;
-  for (int idx = threadIdx.x; idx < n * nb; idx += blockDim.x) {
-    const int i = idx / nb, c = idx % nb;
-    w[(int64_t)i * ldw + c] = u[(int64_t)i * n + 2 * c];
-  }
-}
-
-hipError_t launch_select_even(int n, int nb, int64_t count, const double* UR, int64_t sUR,
-                              double* W, int64_t ldw, int64_t sW, hipStream_t st) {
-  hipLaunchKernelGGL(k_select_even, dim3(1, (unsigned)count), dim3(256), 0, st, n, nb, UR, sUR, W,
-                     ldw, sW);
-  return hipGetLastError();
-}
-
-// Modes and energies of frequency f = blockIdx.y, points blockIdx.x*256 + ..
-// Ue: 2m x nb realified U (row 2p: Re, row 2p+1: Im), VT: n x n (row 2c holds
-// [Re v_c, Im v_c]), S: n.  modes[f][p][c] complex (TO re, im interleaved).
-template <typename TO>
-__global__ __launch_bounds__(256) void k_spod_modes(int64_t m, int nb, const double* __restrict__ Ue,
-                                                    int64_t sUe, const double* __restrict__ VT,
-                                                    int64_t sVT, const double* __restrict__ S,
-                                                    int64_t sS, TO* __restrict__ modes,
-                                                    double* __restrict__ L) {
-  __shared__ double ph_re[64], ph_im[64];
-  const int64_t f = blockIdx.y;
+// Rr[f] (2nb x 2nb, row-major) = [[X, -Y], [Y, X]] for R = X + iY, the root
+// block Rn[f * P] (16 x 16 complex, row-major).
+__global__ void k_spod_root_realify(int nb, int64_t P, const double* __restrict__ Rn,
+                                    double* __restrict__ Rr) {
+  const int64_t f = blockIdx.x;
   const int n = 2 * nb;
-  const double* vt = VT + f * sVT;
-  const double* s = S + f * sS;
+  const double* R = Rn + f * P * 512;
+  double* A = Rr + f * n * n;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, t = idx % n;
+    const int ii = i % nb, tt = t % nb;
+    const double re = R[2 * (ii * 16 + tt)], im = R[2 * (ii * 16 + tt) + 1];
+    const bool top = i < nb, left = t < nb;
+    A[idx] = top == left ? re : (top ? -im : im);
+  }
+}
+
+hipError_t launch_spod_root_realify(int nb, int64_t P, int64_t nf, const double* Rn, double* Rr,
+                                    hipStream_t st) {
+  hipLaunchKernelGGL(k_spod_root_realify, dim3((unsigned)nf), dim3(256), 0, st, nb, P, Rn, Rr);
+  return hipGetLastError();
+}
+
+// From the SVD of frequency f's embedded root (S, VT, UR; n = 2 nb): the
+// phase-fixed complex U_R into the root block of Cn (16 x 16 complex), and L.
+__global__ void k_spod_root_modes(int nb, int64_t P, const double* __restrict__ S,
+                                  const double* __restrict__ VT, const double* __restrict__ UR,
+                                  double* __restrict__ Cn, double* __restrict__ L) {
+  __shared__ double ph_re[16], ph_im[16];
+  const int64_t f = blockIdx.x;
+  const int n = 2 * nb;
+  const double* vt = VT + f * n * n;
+  const double* ur = UR + f * n * n;
   if (threadIdx.x < nb) {
     const int c = threadIdx.x;
     const double* v = vt + (int64_t)(2 * c) * n;
@@ -217,37 +316,25 @@ __global__ __launch_bounds__(256) void k_spod_modes(int64_t m, int nb, const dou
     }
     ph_re[c] = cr;
     ph_im[c] = ci;
-    if (blockIdx.x == 0) {
-      const double sc = s[2 * c];
-      L[f * nb + c] = sc * sc;
-    }
+    const double sc = S[f * n + 2 * c];
+    L[f * nb + c] = sc * sc;
   }
   __syncthreads();
-  const double* ue = Ue + f * sUe;
-  TO* out = modes + 2 * f * m * nb;
-  const int64_t base = (int64_t)blockIdx.x * 256;
-  for (int idx = threadIdx.x; idx < 256 * nb; idx += 256) {
-    const int64_t p = base + idx / nb;
-    const int c = idx % nb;
-    if (p >= m) break;
-    const double ur = ue[(2 * p) * nb + c], ui = ue[(2 * p + 1) * nb + c];
+  double* C = Cn + f * P * 512;
+  for (int idx = threadIdx.x; idx < nb * nb; idx += blockDim.x) {
+    const int i = idx / nb, c = idx % nb;
+    const double ure = ur[(int64_t)i * n + 2 * c], uim = ur[(int64_t)(nb + i) * n + 2 * c];
     const double cr = ph_re[c], ci = ph_im[c];
-    out[2 * (p * nb + c)] = (TO)(ur * cr - ui * ci);
-    out[2 * (p * nb + c) + 1] = (TO)(ur * ci + ui * cr);
+    C[2 * (i * 16 + c)] = ure * cr - uim * ci;
+    C[2 * (i * 16 + c) + 1] = ure * ci + uim * cr;
   }
 }
 
-hipError_t launch_spod_modes(int out_f64, int64_t m, int nb, int64_t nf, const double* Ue,
-                             int64_t sUe, const double* VT, int64_t sVT, const double* S,
-                             int64_t sS, void* modes, double* L, hipStream_t st) {
-  if (nb > 64) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((m + 255) / 256), (unsigned)nf);
-  if (out_f64)
-    hipLaunchKernelGGL(k_spod_modes<double>, grid, dim3(256), 0, st, m, nb, Ue, sUe, VT, sVT, S,
-                       sS, (double*)modes, L);
-  else
-    hipLaunchKernelGGL(k_spod_modes<float>, grid, dim3(256), 0, st, m, nb, Ue, sUe, VT, sVT, S, sS,
-                       (float*)modes, L);
+hipError_t launch_spod_root_modes(int nb, int64_t P, int64_t nf, const double* S, const double* VT,
+                                  const double* UR, double* Cn, double* L, hipStream_t st) {
+  if (nb < 1 || nb > 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_spod_root_modes, dim3((unsigned)nf), dim3(64), 0, st, nb, P, S, VT, UR, Cn,
+                     L);
   return hipGetLastError();
 }
 
