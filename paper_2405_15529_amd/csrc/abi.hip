@@ -2482,7 +2482,7 @@ struct SpodPlan {
   int64_t m, nt, npwin, nolap, nb, nf, n, P, ldm;
   int e_f64;
   JacobiPlan jp;
-  size_t oE, oTab, oScl, oRn, oVn, oRr, oSvd, oS, oVT, oUR, oNr, oSt, total;
+  size_t oE, oTab, oScl, oRn, oVn, oVl, oWl, oRr, oSvd, oS, oVT, oUR, oNr, oSt, total;
   size_t svd_stride;
 };
 
@@ -2516,6 +2516,8 @@ static int make_spod_plan(pylom_ctx c, pylom_dtype spectra, int64_t m, int64_t n
   p->oScl = off;   off = align_up(off + 8);
   p->oRn = off;    off = align_up(off + ctsqr_node_bytes() * (size_t)nf * p->P);
   p->oVn = off;    off = align_up(off + ctsqr_vnode_bytes() * (size_t)nf * p->P);
+  p->oVl = off;    off = align_up(off + ctsqr_leaf_v_bytes((int)nb, p->e_f64) * (size_t)nf * p->P);
+  p->oWl = off;    off = align_up(off + ctsqr_node_bytes() * (size_t)nf * p->P);
   p->oRr = off;    off = align_up(off + 8 * (size_t)nf * n * n);
   p->oSvd = off;   off = align_up(off + p->svd_stride * (size_t)nf);
   p->oS = off;     off = align_up(off + 8 * (size_t)nf * n);
@@ -2582,8 +2584,10 @@ extern "C" int pylom_spod(pylom_ctx c, pylom_dtype spectra, pylom_prec prec, int
                               remove_mean, ws + p.oTab, (double*)(ws + p.oScl), E, p.ldm, st),
          "SPOD front end");
   EVREC(1);
-  HIPCHK(c, launch_cleaf(p.e_f64, 0, (int)nb, m, p.ldm, P, nf, E, Rn, nullptr, nullptr, st),
-         "leaf QR");
+  void* Vl = ws + p.oVl;
+  double* Wl = (double*)(ws + p.oWl);
+  HIPCHK(c, launch_cleaf(p.e_f64, 0, (int)nb, m, p.ldm, P, nf, E, Rn, Vl, Wl, nullptr, nullptr,
+                         st), "leaf QR");
   EVREC(2);
   for (int64_t h = 1; h < P; h *= 2)
     HIPCHK(c, launch_ctree_combine((int)nb, P, h, nf, Rn, Vn, st), "tree combine");
@@ -2603,8 +2607,8 @@ extern "C" int pylom_spod(pylom_ctx c, pylom_dtype spectra, pylom_prec prec, int
     for (int64_t h = top; h >= 1; h /= 2)
       HIPCHK(c, launch_ctree_apply((int)nb, P, h, nf, Rn, Vn, st), "tree propagation");
   EVREC(5);
-  HIPCHK(c, launch_cleaf(p.e_f64, 1, (int)nb, m, p.ldm, P, nf, E, nullptr, Rn, modes, st),
-         "leaf apply");
+  HIPCHK(c, launch_cleaf(p.e_f64, 1, (int)nb, m, p.ldm, P, nf, nullptr, nullptr, Vl, Wl, Rn,
+                         modes, st), "leaf apply");
   HIPCHK(c, launch_spod_order((int)nf, (int)nb, dt, (int)npwin, L, freqs, order, st), "order");
   EVREC(6);
 #undef EVREC

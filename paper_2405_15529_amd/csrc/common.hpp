@@ -116,16 +116,18 @@ __device__ __forceinline__ void wave_reduce16(const T (&in)[16], T (&out)[16], i
 // ---- DPP / permlane reductions (gfx950) ------------------------------------
 // DPP controls: row_ror:N = 0x120 + N, row_mirror = 0x140, row_half_mirror =
 // 0x141, quad_perm [3,2,1,0] = 0x1B, quad_perm [1,0,3,2] = 0xB1.
+// Every control used here reads a valid lane of the same row for every lane
+// and all rows and banks are enabled, so no `old` value is needed.
 template <int CTRL>
 __device__ __forceinline__ double dpp(double x) {
   const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(v & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
 // x + (x of the paired row): permlane16_swap pairs rows 0<->1 and 2<->3,

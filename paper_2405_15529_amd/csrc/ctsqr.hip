@@ -22,17 +22,15 @@
 // the lower parts, row 16 the tau values).  After the root SVD the Rn blocks
 // are reused for the down-tree factors C: [C_j; C_{j+h}] = Q_node [C_j; 0].
 //
-// The leaf apply recomputes the leaf factorisation with the same code (the
-// same reduction trees, so bit-identical reflectors), accumulates the compact
-// WY factor T (LAPACK zlarft, forward columnwise) and writes
-//   U_leaf = Q_leaf [C; 0] = [C; 0] - V (T (V_top^H C))
-// straight into the modes array, so the reflectors are never stored.
+// The factor pass also accumulates the compact WY factor T of each leaf
+// (LAPACK zlarft, forward columnwise, Q_leaf = I - V T V^H), stores the
+// reflectors V in the spectra precision and W = T V_top^H (V_top the leaf's
+// first nb rows of V); the apply pass then writes
+//   U_leaf = Q_leaf [C; 0] = [C; 0] - V (W C)
+// straight into the modes array.
 #include "common.hpp"
 #include "kernels.hpp"
 
-// every product and sum below is rounded as written, so that the factor pass
-// and the recomputing apply pass produce the same bits
-#pragma clang fp contract(off)
 
 namespace pylom {
 
@@ -75,6 +73,15 @@ constexpr int pow2ceil(int v) {
 // and add the partner's copy of the kept half.
 template <int CTRL, int H>
 __device__ __forceinline__ void halve(double (&x)[32], bool up) {
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const double keep = up ? x[i + H] : x[i];
+    const double send = up ? x[i] : x[i + H];
+    x[i] = keep + dpp<CTRL>(send);
+  }
+}
+template <int CTRL, int H>
+__device__ __forceinline__ void halve16(double (&x)[16], bool up) {
 #pragma unroll
   for (int i = 0; i < H; ++i) {
     const double keep = up ? x[i + H] : x[i];
@@ -129,19 +136,79 @@ __device__ __forceinline__ int row_rs(F&& part, double (&x)[32], int i) {
   return base;
 }
 
-// Totals over all 64 lanes of the V/2 complex values part(kk), gathered in
-// red[0..V) (re, im interleaved).
+// Halving across row pairs with one swap per 32-bit half: the swap of (lo, hi)
+// leaves {own lo, partner lo} in the rows that keep the lower half and
+// {partner hi, own hi} in the others, so the sum of the two outputs is the
+// pair total of the kept half.  keep_hi (which half this lane's row keeps) is
+// read once from a swap of constants.
+template <int W>
+__device__ __forceinline__ double swap_sum(double lo, double hi) {
+  const long long a = __double_as_longlong(lo), b = __double_as_longlong(hi);
+  const int alo = (int)(a & 0xffffffffll), ahi = (int)(a >> 32);
+  const int blo = (int)(b & 0xffffffffll), bhi = (int)(b >> 32);
+  if constexpr (W == 16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    return __longlong_as_double(((long long)h[0] << 32) | (unsigned int)l[0]) +
+           __longlong_as_double(((long long)h[1] << 32) | (unsigned int)l[1]);
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    return __longlong_as_double(((long long)h[0] << 32) | (unsigned int)l[0]) +
+           __longlong_as_double(((long long)h[1] << 32) | (unsigned int)l[1]);
+  }
+}
+template <int W>
+__device__ __forceinline__ bool swap_keeps_hi() {
+  if constexpr (W == 16) return __builtin_amdgcn_permlane16_swap(0, 1, false, false)[0] != 0;
+  else return __builtin_amdgcn_permlane32_swap(0, 1, false, false)[0] != 0;
+}
+
+// Totals over all 64 lanes of the V/2 complex values part(kk) (V a power of
+// two, 2..32), gathered in red[0..V) (re, im interleaved): halvings across
+// the 32-lane halves and across row pairs (swaps), then inside each row
+// (mirror, half mirror, quad 3210), pair sums for what is left.
 template <int V, typename F>
 __device__ __forceinline__ void wave_allreduce(F&& part, int lane, double* red) {
-  double x[32];
-  const int base = row_rs<V>(part, x, lane & 15);
-  constexpr int U = V >= 16 ? V / 16 : 1;
+  const int i = lane & 15;
+  const bool h32 = swap_keeps_hi<32>(), h16 = swap_keeps_hi<16>();
+  double x[16];
+  int idx = h32 ? V / 2 : 0;
+  if constexpr (V >= 4) {
 #pragma unroll
-  for (int u = 0; u < U; ++u) x[u] = perm32_pairsum(perm16_pairsum(x[u]));
-  if (lane < 16) {
+    for (int kk = 0; kk < V / 4; ++kk) {
+      const zd lo = part(kk), hi = part(kk + V / 4);
+      x[2 * kk] = swap_sum<32>(lo.re, hi.re);
+      x[2 * kk + 1] = swap_sum<32>(lo.im, hi.im);
+    }
+    // V/2 values left: halve across row pairs
 #pragma unroll
-    for (int u = 0; u < U; ++u) red[base + u] = x[u];
+    for (int u = 0; u < V / 4; ++u) x[u] = swap_sum<16>(x[u], x[u + V / 4]);
+    idx += h16 ? V / 4 : 0;
+  } else {
+    const zd lo = part(0);
+    x[0] = perm16_pairsum(swap_sum<32>(lo.re, lo.im));
   }
+  if constexpr (V >= 8) {
+    halve16<0x140, V / 8>(x, i >= 8);
+    idx += i >= 8 ? V / 8 : 0;
+  } else {
+    x[0] = pairsum<0x140>(x[0]);
+  }
+  if constexpr (V >= 16) {
+    halve16<0x141, V / 16>(x, (i & 7) >= 4);
+    idx += (i & 7) >= 4 ? V / 16 : 0;
+  } else {
+    x[0] = pairsum<0x141>(x[0]);
+  }
+  if constexpr (V >= 32) {
+    halve16<0x1B, V / 32>(x, (i & 3) >= 2);
+    idx += (i & 3) >= 2 ? V / 32 : 0;
+  } else {
+    x[0] = pairsum<0x1B>(x[0]);
+  }
+  x[0] = pairsum<0xB1>(x[0]);
+  red[idx] = x[0];
   wave_lds_sync();
 }
 
@@ -166,10 +233,11 @@ __device__ __forceinline__ void zlarfg(zd alpha, double xn2, double& beta, zd& t
   } else {
     const double nrm = sqrt(fma(alpha.re, alpha.re, fma(alpha.im, alpha.im, xn2)));
     beta = alpha.re >= 0.0 ? -nrm : nrm;
-    tau = zd{(beta - alpha.re) / beta, -alpha.im / beta};
+    const double rb = 1.0 / beta;
+    tau = zd{(beta - alpha.re) * rb, -alpha.im * rb};
     const double dr = alpha.re - beta, di = alpha.im;
-    const double den = fma(dr, dr, di * di);
-    gam = zd{dr / den, -di / den};
+    const double rden = 1.0 / fma(dr, dr, di * di);
+    gam = zd{dr * rden, -di * rden};
   }
 }
 
@@ -185,84 +253,91 @@ struct T2<double> {
 };
 
 // ---- leaf sweep -------------------------------------------------------------
-// Column J of the leaf factorisation; APPLY also builds column J of T from
-// y = V^H v_J over the stored reflectors (zlarft), after the update, so the
-// factorisation itself is the same instruction stream in both passes.
-template <int NB, bool APPLY, int J>
-__device__ __forceinline__ void leaf_cols(zd (&a)[2][NB], int lane, double* red, double* red2,
-                                          zd* drow, zd* Tm) {
+// Column J of the leaf factorisation with column J of the compact WY factor T
+// (LAPACK zlarft, forward columnwise).  One wave-wide sum per column gives
+//   g_k = sum_{r > J} conj(x_r) a_rk   (k >= J; x = column J, g_J = |x|^2)
+//   s_i = sum_{r > J} conj(v_ri) x_r   (i < J; the stored reflectors)
+// and then y_i = (V^H v_J)_i = conj(v_Ji) + gam s_i,
+//   T[i][J] = -tau sum_{l >= i} T[i][l] y_l,  T[J][J] = tau.
+template <int NB, int J>
+__device__ __forceinline__ void leaf_cols(zd (&a)[2][NB], int lane, double* red, zd* drow,
+                                          zd* tbuf, zd* ybuf, zd* Tm) {
   if constexpr (J < NB) {
     constexpr int CG = NB - J;
-    constexpr int VG = pow2ceil(2 * CG);
+    constexpr int V = pow2ceil(2 * NB);
     const bool below = lane > J;
     const zd c0 = below ? a[0][J] : zd{0.0, 0.0};
     const zd c1 = a[1][J];
     if (lane == J) {
 #pragma unroll
-      for (int k = J; k < NB; ++k) drow[k] = a[0][k];
+      for (int k = 0; k < NB; ++k) drow[k] = a[0][k];
     }
-    wave_allreduce<VG>(
+    wave_allreduce<V>(
         [&](int kk) -> zd {
-          if (kk >= CG) return zd{0.0, 0.0};
-          zd p = zcjmac(c0, a[0][J + kk], zd{0.0, 0.0});
-          return zcjmac(c1, a[1][J + kk], p);
+          if (kk < CG) {
+            const zd p = zcjmac(c0, a[0][J + kk], zd{0.0, 0.0});
+            return zcjmac(c1, a[1][J + kk], p);
+          }
+          if (kk < NB) {
+            const int i = kk - CG;
+            const zd p = zcjmac(a[0][i], c0, zd{0.0, 0.0});
+            return zcjmac(a[1][i], c1, p);
+          }
+          return zd{0.0, 0.0};
         },
         lane, red);
     double beta;
     zd tau, gam;
     zlarfg(drow[J], red[0], beta, tau, gam);
-    const zd ctau = zconj(tau), cgam = zconj(gam);
+    // lane k > J: t_k = conj(tau) (d_k + conj(gam) g_k);  lane i < J: y_i
+    if (lane < NB && lane != J) {
+      const zd dk = drow[lane];
+      if (lane > J) {
+        const int o = 2 * (lane - J);
+        const zd q = zmul(zconj(gam), zd{red[o], red[o + 1]});
+        tbuf[lane] = zmul(zconj(tau), zd{dk.re + q.re, dk.im + q.im});
+      } else {
+        const int o = 2 * (CG + lane);
+        const zd q = zmul(gam, zd{red[o], red[o + 1]});
+        ybuf[lane] = zd{dk.re + q.re, -dk.im + q.im};
+      }
+    }
+    wave_lds_sync();
     const zd v0 = below ? zmul(gam, a[0][J]) : zd{lane == J ? 1.0 : 0.0, 0.0};
     const zd v1 = zmul(gam, a[1][J]);
 #pragma unroll
     for (int k = J + 1; k < NB; ++k) {
-      // t_k = conj(tau) (d_k + conj(gam) g_k)
-      const zd dk = drow[k];
-      const zd q = zmul(cgam, zd{red[2 * (k - J)], red[2 * (k - J) + 1]});
-      const zd tk = zmul(ctau, zd{dk.re + q.re, dk.im + q.im});
+      const zd tk = tbuf[k];
       a[0][k] = zsubmul(a[0][k], tk, v0);
       a[1][k] = zsubmul(a[1][k], tk, v1);
     }
     a[0][J] = below ? v0 : (lane == J ? zd{beta, 0.0} : a[0][J]);
     a[1][J] = v1;
-    if constexpr (APPLY) {
-      if constexpr (J > 0) {
-        constexpr int VS = pow2ceil(2 * J);
-        // y_i = sum_r conj(v_ri) v_rJ (v_JJ = 1: v0 of lane J)
-        wave_allreduce<VS>(
-            [&](int i) -> zd {
-              if (i >= J) return zd{0.0, 0.0};
-              zd p = zcjmac(a[0][i], v0, zd{0.0, 0.0});
-              return zcjmac(a[1][i], v1, p);
-            },
-            lane, red2);
-        // T[i][J] = -tau sum_{l >= i} T[i][l] y_l, lane i < J
-        if (lane < J) {
-          zd acc{0.0, 0.0};
+    if (lane < J) {
+      zd acc{0.0, 0.0};
 #pragma unroll
-          for (int l = 0; l < J; ++l)
-            if (l >= lane) acc = zmac(Tm[lane * kLd + l], zd{red2[2 * l], red2[2 * l + 1]}, acc);
-          const zd r = zmul(tau, acc);
-          Tm[lane * kLd + J] = zd{-r.re, -r.im};
-        }
-      }
-      if (lane == J) Tm[J * kLd + J] = tau;
+      for (int l = 0; l < J; ++l)
+        if (l >= lane) acc = zmac(Tm[lane * kLd + l], ybuf[l], acc);
+      const zd r = zmul(tau, acc);
+      Tm[lane * kLd + J] = zd{-r.re, -r.im};
     }
-    leaf_cols<NB, APPLY, J + 1>(a, lane, red, red2, drow, Tm);
+    if (lane == J) Tm[J * kLd + J] = tau;
+    leaf_cols<NB, J + 1>(a, lane, red, drow, tbuf, ybuf, Tm);
   }
 }
 
-// One wave per 128-row leaf of every frequency (blockIdx.y).  Factor pass
-// (APPLY false): R of the leaf into Rn.  Apply pass: the same factorisation,
-// then U rows = Q_leaf [C; 0] into modes (complex T, [f][p][c]).
-template <typename T, int NB, bool APPLY>
-__global__ __launch_bounds__(64, 2) void k_cleaf(int64_t m, int64_t ldm, int64_t P,
-                                              const T* __restrict__ E, zd* __restrict__ Rn,
-                                              const zd* __restrict__ Cn, T* __restrict__ modes) {
+// Factor pass, one wave per 128-row leaf of every frequency (blockIdx.y):
+// R of the leaf into Rn; the leaf's rows after the sweep (R above, the
+// reflectors below the diagonal) into Vl (column-major per leaf, complex T);
+// W = T V_top^H (V_top = rows 0..nb-1 of V, unit lower triangular) into Wl.
+template <typename T, int NB>
+__global__ __launch_bounds__(64, 2) void k_cleaf_factor(int64_t m, int64_t ldm, int64_t P,
+                                                        const T* __restrict__ E,
+                                                        zd* __restrict__ Rn, T* __restrict__ Vl,
+                                                        zd* __restrict__ Wl) {
   __shared__ double red[32];
-  __shared__ double red2[32];
-  __shared__ zd drow[16];
-  __shared__ zd big[APPLY ? 3 * 16 * kLd : 1];
+  __shared__ zd drow[16], tbuf[16], ybuf[16];
+  __shared__ zd Tm[16 * kLd], Vt[16 * kLd];
   typedef typename T2<T>::type TT;
   const int lane = threadIdx.x;
   const int64_t leaf = blockIdx.x, f = blockIdx.y;
@@ -282,95 +357,122 @@ __global__ __launch_bounds__(64, 2) void k_cleaf(int64_t m, int64_t ldm, int64_t
       }
     }
   }
-  zd* Tm = big;
-  leaf_cols<NB, APPLY, 0>(a, lane, red, red2, drow, Tm);
+  leaf_cols<NB, 0>(a, lane, red, drow, tbuf, ybuf, Tm);
   const int64_t node = f * P + leaf;
-  if constexpr (!APPLY) {
-    if (lane < NB) {
-      zd* R = Rn + node * kNodeZ + lane * 16;
+  if (lane < NB) {
+    zd* R = Rn + node * kNodeZ + lane * 16;
 #pragma unroll
-      for (int k = 0; k < NB; ++k) R[k] = k < lane ? zd{0.0, 0.0} : a[0][k];
+    for (int k = 0; k < NB; ++k) R[k] = k < lane ? zd{0.0, 0.0} : a[0][k];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      Vt[lane * kLd + k] = k < lane ? a[0][k] : zd{k == lane ? 1.0 : 0.0, 0.0};
+  }
+  TT* V = reinterpret_cast<TT*>(Vl) + node * NB * kLeafRows;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      TT v;
+      v.x = (T)a[s][k].re;
+      v.y = (T)a[s][k].im;
+      V[k * kLeafRows + 64 * s + lane] = v;
     }
-  } else {
-    zd* B1 = big + 16 * kLd;
-    zd* Cl = big + 2 * 16 * kLd;
-    if (lane < NB) {
+  }
+  wave_lds_sync();
+  // W[i][r] = sum_{i <= l <= r} T[i][l] conj(V_top[r][l]), lane (ii, q) for r = q + 4 kk
+  const int ii = lane & 15, q = lane >> 4;
+  zd w[4];
 #pragma unroll
-      for (int k = 0; k < NB; ++k)
-        B1[lane * kLd + k] = k < lane ? a[0][k] : zd{k == lane ? 1.0 : 0.0, 0.0};
-    }
-    const zd* C = Cn + node * kNodeZ;
-    for (int e = lane; e < NB * NB; e += 64) Cl[(e / NB) * kLd + e % NB] = C[(e / NB) * 16 + e % NB];
-    wave_lds_sync();
-    // X = V_top^H C, lane (ii, q) computes X[ii][q + 4 kk]
-    const int ii = lane & 15, q = lane >> 4;
-    zd X[4];
+  for (int kk = 0; kk < 4; ++kk) w[kk] = zd{0.0, 0.0};
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) X[kk] = zd{0.0, 0.0};
-#pragma unroll
-    for (int r = 0; r < NB; ++r) {
-      if (r >= ii) {
-        const zd vt = B1[r * kLd + ii];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-          if (q + 4 * kk < NB) X[kk] = zcjmac(vt, Cl[r * kLd + q + 4 * kk], X[kk]);
-      }
-    }
-    wave_lds_sync();
-    if (ii < NB) {
+  for (int l = 0; l < NB; ++l) {
+    if (l >= ii) {
+      const zd tl = Tm[ii * kLd + l];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk)
-        if (q + 4 * kk < NB) B1[ii * kLd + q + 4 * kk] = X[kk];
+        if (q + 4 * kk < NB) w[kk] = zmac(tl, zconj(Vt[(q + 4 * kk) * kLd + l]), w[kk]);
     }
+  }
+  if (ii < NB) {
+    zd* W = Wl + node * kNodeZ + ii * 16;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      if (q + 4 * kk < NB) W[q + 4 * kk] = w[kk];
+  }
+}
+
+// Apply pass: U rows of the leaf = [C; 0] - V (W C) into modes (complex T,
+// [f][p][c]), C the leaf's block of Cn.
+template <typename T, int NB>
+__global__ __launch_bounds__(64, 2) void k_cleaf_apply(int64_t m, int64_t P,
+                                                       const T* __restrict__ Vl,
+                                                       const zd* __restrict__ Wl,
+                                                       const zd* __restrict__ Cn,
+                                                       T* __restrict__ modes) {
+  __shared__ zd Cl[16 * kLd], Zl[16 * kLd], Wm[16 * kLd];
+  typedef typename T2<T>::type TT;
+  const int lane = threadIdx.x;
+  const int64_t leaf = blockIdx.x, f = blockIdx.y;
+  const int64_t r0 = leaf * kLeafRows;
+  const int64_t node = f * P + leaf;
+  const zd* C = Cn + node * kNodeZ;
+  const zd* W = Wl + node * kNodeZ;
+  for (int e = lane; e < NB * NB; e += 64) {
+    Cl[(e / NB) * kLd + e % NB] = C[(e / NB) * 16 + e % NB];
+    Wm[(e / NB) * kLd + e % NB] = W[(e / NB) * 16 + e % NB];
+  }
+  const TT* V = reinterpret_cast<const TT*>(Vl) + node * NB * kLeafRows;
+  TT a[2][NB];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int k = 0; k < NB; ++k) a[s][k] = V[k * kLeafRows + 64 * s + lane];
+  wave_lds_sync();
+  // Z = W C, lane (ii, q) computes Z[ii][q + 4 kk]
+  const int ii = lane & 15, q = lane >> 4;
+  zd z[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) z[kk] = zd{0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < NB; ++r) {
+    const zd wr = Wm[ii * kLd + r];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      if (q + 4 * kk < NB) z[kk] = zmac(wr, Cl[r * kLd + q + 4 * kk], z[kk]);
+  }
+  if (ii < NB) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      if (q + 4 * kk < NB) Zl[ii * kLd + q + 4 * kk] = z[kk];
+  }
+  wave_lds_sync();
+  const int lc = lane < NB ? lane : 0;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    // re-read Z for each slot rather than keeping all of it in registers
     wave_lds_sync();
-    // Z = T X
+    zd acc[NB];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) X[kk] = zd{0.0, 0.0};
-#pragma unroll
-    for (int l = 0; l < NB; ++l) {
-      if (l >= ii) {
-        const zd tl = Tm[ii * kLd + l];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-          if (q + 4 * kk < NB) X[kk] = zmac(tl, B1[l * kLd + q + 4 * kk], X[kk]);
-      }
+    for (int c = 0; c < NB; ++c) {
+      const zd cv = Cl[lc * kLd + c];
+      acc[c] = (s == 0 && lane < NB) ? cv : zd{0.0, 0.0};
     }
-    wave_lds_sync();
-    if (ii < NB) {
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-        if (q + 4 * kk < NB) B1[ii * kLd + q + 4 * kk] = X[kk];
+    for (int k = 0; k < NB; ++k) {
+      const zd ak = zd{(double)a[s][k].x, (double)a[s][k].y};
+      const zd vk = s == 1 ? ak : (k < lane ? ak : zd{k == lane ? 1.0 : 0.0, 0.0});
+#pragma unroll
+      for (int c = 0; c < NB; ++c) acc[c] = zsubmul(acc[c], vk, Zl[k * kLd + c]);
     }
-    wave_lds_sync();
-    // rows: U_r = [C; 0]_r - sum_k V[r][k] Z[k][:]
-    const int lc = lane < NB ? lane : 0;
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      // re-read Z for each slot rather than keeping all of it in registers
-      wave_lds_sync();
-      zd acc[NB];
+    const int64_t row = r0 + 64 * s + lane;
+    if (row < m) {
+      TT* out = reinterpret_cast<TT*>(modes) + (f * m + row) * NB;
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
-        const zd cv = Cl[lc * kLd + c];
-        acc[c] = (s == 0 && lane < NB) ? cv : zd{0.0, 0.0};
-      }
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        const zd vk = s == 1 ? a[1][k]
-                             : (k < lane ? a[0][k] : zd{k == lane ? 1.0 : 0.0, 0.0});
-#pragma unroll
-        for (int c = 0; c < NB; ++c) acc[c] = zsubmul(acc[c], vk, B1[k * kLd + c]);
-      }
-      const int64_t row = r0 + 64 * s + lane;
-      if (row < m) {
-        TT* out = reinterpret_cast<TT*>(modes) + (f * m + row) * NB;
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          TT v;
-          v.x = (T)acc[c].re;
-          v.y = (T)acc[c].im;
-          out[c] = v;
-        }
+        TT v;
+        v.x = (T)acc[c].re;
+        v.y = (T)acc[c].im;
+        out[c] = v;
       }
     }
   }
@@ -380,7 +482,8 @@ __global__ __launch_bounds__(64, 2) void k_cleaf(int64_t m, int64_t ldm, int64_t
 // Column J of a combine: the lane's row of the lower block in b, the upper
 // block in LDS (ra, row J is the diagonal row of the step).
 template <int NB, int J>
-__device__ __forceinline__ void comb_cols(zd (&b)[NB], zd* ra, int lt, double* red, zd* taus) {
+__device__ __forceinline__ void comb_cols(zd (&b)[NB], zd* ra, int lt, double* red, zd* taus,
+                                          zd* tbuf) {
   if constexpr (J < NB) {
     constexpr int CG = NB - J;
     constexpr int VG = pow2ceil(2 * CG);
@@ -394,22 +497,27 @@ __device__ __forceinline__ void comb_cols(zd (&b)[NB], zd* ra, int lt, double* r
     double beta;
     zd tau, gam;
     zlarfg(ra[J * kLd + J], red[0], beta, tau, gam);
-    const zd ctau = zconj(tau), cgam = zconj(gam);
+    // t_k = conj(tau) (d_k + conj(gam) g_k), lane k - J of the row computes it
+    // and also updates the diagonal row's entry k
+    if constexpr (CG > 1) {
+      if (lt >= 1 && lt < CG) {
+        const zd dk = ra[J * kLd + J + lt];
+        const zd q = zmul(zconj(gam), zd{red[2 * lt], red[2 * lt + 1]});
+        const zd tk = zmul(zconj(tau), zd{dk.re + q.re, dk.im + q.im});
+        tbuf[J + lt] = tk;
+        ra[J * kLd + J + lt] = zd{dk.re - tk.re, dk.im - tk.im};
+      }
+      wave_lds_sync();
+    }
     const zd v = zmul(gam, cj);
 #pragma unroll
-    for (int k = J + 1; k < NB; ++k) {
-      const zd dk = ra[J * kLd + k];
-      const zd q = zmul(cgam, zd{red[2 * (k - J)], red[2 * (k - J) + 1]});
-      const zd tk = zmul(ctau, zd{dk.re + q.re, dk.im + q.im});
-      b[k] = zsubmul(b[k], tk, v);
-      if (lt == J) ra[J * kLd + k] = zd{dk.re - tk.re, dk.im - tk.im};
-    }
+    for (int k = J + 1; k < NB; ++k) b[k] = zsubmul(b[k], tbuf[k], v);
     b[J] = v;
     if (lt == J) {
       ra[J * kLd + J] = zd{beta, 0.0};
       taus[J] = tau;
     }
-    comb_cols<NB, J + 1>(b, ra, lt, red, taus);
+    comb_cols<NB, J + 1>(b, ra, lt, red, taus, tbuf);
   }
 }
 
@@ -422,6 +530,7 @@ __global__ __launch_bounds__(64, 3) void k_ctree_combine(int64_t P, int64_t h, i
   __shared__ double red[4][32];
   __shared__ zd ra[4][16 * kLd];
   __shared__ zd taus[4][16];
+  __shared__ zd tbuf[4][16];
   const int lane = threadIdx.x, g = lane >> 4, lt = lane & 15;
   const int64_t c = (int64_t)blockIdx.x * 4 + g, f = blockIdx.y;
   const bool active = c < ncomb;
@@ -444,7 +553,7 @@ __global__ __launch_bounds__(64, 3) void k_ctree_combine(int64_t P, int64_t h, i
     }
   }
   wave_lds_sync();
-  comb_cols<NB, 0>(b, ra[g], lt, red[g], taus[g]);
+  comb_cols<NB, 0>(b, ra[g], lt, red[g], taus[g], tbuf[g]);
   wave_lds_sync();
   if (io) {
 #pragma unroll
@@ -530,14 +639,18 @@ __global__ __launch_bounds__(64, 2) void k_ctree_apply(int64_t P, int64_t h, int
 
 int64_t combines_at(int64_t P, int64_t h) { return P > h ? (P - h - 1) / (2 * h) + 1 : 0; }
 
-template <typename T, bool APPLY>
-hipError_t leaf_dispatch(int nb, dim3 grid, hipStream_t st, int64_t m, int64_t ldm, int64_t P,
-                         const T* E, zd* Rn, const zd* Cn, T* modes) {
+template <typename T>
+hipError_t leaf_dispatch(int apply, int nb, dim3 grid, hipStream_t st, int64_t m, int64_t ldm,
+                         int64_t P, const T* E, zd* Rn, T* Vl, zd* Wl, const zd* Cn, T* modes) {
   switch (nb) {
-#define PYLOM_CLEAF(K)                                                                        \
-  case K:                                                                                     \
-    hipLaunchKernelGGL((k_cleaf<T, K, APPLY>), grid, dim3(64), 0, st, m, ldm, P, E, Rn, Cn, \
-                       modes);                                                                \
+#define PYLOM_CLEAF(K)                                                                         \
+  case K:                                                                                      \
+    if (apply)                                                                                 \
+      hipLaunchKernelGGL((k_cleaf_apply<T, K>), grid, dim3(64), 0, st, m, P, Vl, Wl, Cn,       \
+                         modes);                                                               \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_cleaf_factor<T, K>), grid, dim3(64), 0, st, m, ldm, P, E, Rn, Vl, \
+                         Wl);                                                                  \
     break;
     PYLOM_CLEAF(1) PYLOM_CLEAF(2) PYLOM_CLEAF(3) PYLOM_CLEAF(4) PYLOM_CLEAF(5) PYLOM_CLEAF(6)
     PYLOM_CLEAF(7) PYLOM_CLEAF(8) PYLOM_CLEAF(9) PYLOM_CLEAF(10) PYLOM_CLEAF(11)
@@ -555,26 +668,26 @@ int64_t ctsqr_leaves(int64_t m) { return (m + kLeafRows - 1) / kLeafRows; }
 size_t ctsqr_node_bytes() { return sizeof(zd) * kNodeZ; }
 size_t ctsqr_vnode_bytes() { return sizeof(zd) * kVnZ; }
 
+size_t ctsqr_leaf_v_bytes(int nb, int t_f64) {
+  return (size_t)nb * kLeafRows * 2 * (t_f64 ? 8 : 4);
+}
+
 hipError_t launch_cleaf(int t_f64, int apply, int nb, int64_t m, int64_t ldm, int64_t P,
-                        int64_t nf, const void* E, double* Rn, const double* Cn, void* modes,
-                        hipStream_t st) {
+                        int64_t nf, const void* E, double* Rn, void* Vl, double* Wl,
+                        const double* Cn, void* modes, hipStream_t st) {
   if (nb < 1 || nb > 16 || P != ctsqr_leaves(m) || ldm < m || nf < 1 || nf > 65535 ||
-      P > 0x7fffffff)
+      P > 0x7fffffff || !Vl || !Wl)
     return hipErrorInvalidValue;
-  if (apply ? (!Cn || !modes) : !Rn) return hipErrorInvalidValue;
+  if (apply ? (!Cn || !modes) : (!Rn || !E)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)P, (unsigned)nf);
   zd* R = reinterpret_cast<zd*>(Rn);
+  zd* W = reinterpret_cast<zd*>(Wl);
   const zd* C = reinterpret_cast<const zd*>(Cn);
-  if (t_f64) {
-    return apply ? leaf_dispatch<double, true>(nb, grid, st, m, ldm, P, (const double*)E, R, C,
-                                               (double*)modes)
-                 : leaf_dispatch<double, false>(nb, grid, st, m, ldm, P, (const double*)E, R, C,
-                                                (double*)modes);
-  }
-  return apply ? leaf_dispatch<float, true>(nb, grid, st, m, ldm, P, (const float*)E, R, C,
-                                            (float*)modes)
-               : leaf_dispatch<float, false>(nb, grid, st, m, ldm, P, (const float*)E, R, C,
-                                             (float*)modes);
+  if (t_f64)
+    return leaf_dispatch<double>(apply, nb, grid, st, m, ldm, P, (const double*)E, R,
+                                 (double*)Vl, W, C, (double*)modes);
+  return leaf_dispatch<float>(apply, nb, grid, st, m, ldm, P, (const float*)E, R, (float*)Vl, W,
+                              C, (float*)modes);
 }
 
 hipError_t launch_ctree_combine(int nb, int64_t P, int64_t h, int64_t nf, double* Rn,

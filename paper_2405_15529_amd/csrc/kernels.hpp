@@ -289,12 +289,15 @@ hipError_t launch_spod_order(int nf, int nb, double dt, int npwin, const double*
 int64_t ctsqr_leaves(int64_t m);
 size_t ctsqr_node_bytes();
 size_t ctsqr_vnode_bytes();
-// apply = 0: R of every leaf into Rn.  apply = 1: the same factorisation,
-// then modes[f][p][c] = (Q_leaf [C_leaf; 0])[p][c] (complex, T = t_f64 ?
-// double : float) with C_leaf the node block of Cn.
+// Per-leaf storage of the factor pass: Vl holds ctsqr_leaf_v_bytes per leaf
+// (the reflectors, complex T = t_f64 ? double : float), Wl one node block.
+size_t ctsqr_leaf_v_bytes(int nb, int t_f64);
+// apply = 0: R of every leaf into Rn, its reflectors into Vl and
+// W = T V_top^H into Wl.  apply = 1: modes[f][p][c] = (Q_leaf [C_leaf; 0])[p][c]
+// (complex T) with C_leaf the node block of Cn.
 hipError_t launch_cleaf(int t_f64, int apply, int nb, int64_t m, int64_t ldm, int64_t P,
-                        int64_t nf, const void* E, double* Rn, const double* Cn, void* modes,
-                        hipStream_t st);
+                        int64_t nf, const void* E, double* Rn, void* Vl, double* Wl,
+                        const double* Cn, void* modes, hipStream_t st);
 // Level h of the binary reduction tree (every frequency): node j = 2hc absorbs
 // node j + h; the combine's reflectors go to Vn[j + h].
 hipError_t launch_ctree_combine(int nb, int64_t P, int64_t h, int64_t nf, double* Rn,

@@ -64,10 +64,65 @@ struct T2v<double> {
   typedef double2 type;
 };
 
+// cos and sin of 2 pi e / L at compile time: reduction to a quadrant and to
+// an angle in [0, pi/4] (complement otherwise), then the Taylor series (the
+// 15th term is below 1e-20 there).
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double taylor_sin(double x) {
+  double t = x, s = x;
+  for (int k = 1; k < 15; ++k) {
+    t *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    s += t;
+  }
+  return s;
+}
+constexpr double taylor_cos(double x) {
+  double t = 1.0, s = 1.0;
+  for (int k = 1; k < 15; ++k) {
+    t *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    s += t;
+  }
+  return s;
+}
+constexpr void cossin_2pi(int e, int L, double& c, double& s) {
+  e %= L;
+  const int qd = (4 * e) / L, r = 4 * e - qd * L;  // angle = (pi/2)(qd + r/L)
+  double c0, s0;
+  if (2 * r <= L) {
+    const double th = 0.5 * kPi * (double)r / (double)L;
+    c0 = taylor_cos(th);
+    s0 = taylor_sin(th);
+  } else {
+    const double ph = 0.5 * kPi * (double)(L - r) / (double)L;
+    c0 = taylor_sin(ph);
+    s0 = taylor_cos(ph);
+  }
+  switch (qd) {
+    case 0: c = c0; s = s0; break;
+    case 1: c = -s0; s = c0; break;
+    case 2: c = -c0; s = -s0; break;
+    default: c = s0; s = -c0; break;
+  }
+}
+// W_C^e = exp(-2 pi i e / C), e < C/2
+template <int C>
+struct InlaneTwiddles {
+  double re[C / 2 + 1], im[C / 2 + 1];
+  constexpr InlaneTwiddles() : re(), im() {
+    for (int e = 0; e < C / 2; ++e) {
+      double c = 0.0, sn = 0.0;
+      cossin_2pi(e, C, c, sn);
+      re[e] = c;
+      im[e] = -sn;
+    }
+  }
+};
+
 // C-point radix-2 DFT of z inside one lane (decimation in time, natural-order
-// output); W_L^e = tw[e N / L], a uniform table read.
-template <typename T, int C, int N>
-__device__ __forceinline__ void fft_inlane(Cx<T> (&z)[C], const T* __restrict__ tw) {
+// output) with compile-time twiddles.
+template <typename T, int C>
+__device__ __forceinline__ void fft_inlane(Cx<T> (&z)[C]) {
+  constexpr InlaneTwiddles<C> tw{};
   Cx<T> y[C];
 #pragma unroll
   for (int i = 0; i < C; ++i) y[bitrev_c(i, C)] = z[i];
@@ -78,10 +133,7 @@ __device__ __forceinline__ void fft_inlane(Cx<T> (&z)[C], const T* __restrict__ 
 #pragma unroll
       for (int e = 0; e < L / 2; ++e) {
         Cx<T> bb = y[s0 + e + L / 2];
-        if (e != 0) {
-          const int t = e * (N / L);
-          bb = cmul(bb, Cx<T>{tw[2 * t], tw[2 * t + 1]});
-        }
+        if (e != 0) bb = cmul(bb, Cx<T>{(T)tw.re[e * (C / L)], (T)tw.im[e * (C / L)]});
         const Cx<T> aa = y[s0 + e];
         y[s0 + e] = Cx<T>{aa.re + bb.re, aa.im + bb.im};
         y[s0 + e + L / 2] = Cx<T>{aa.re - bb.re, aa.im - bb.im};
@@ -92,87 +144,151 @@ __device__ __forceinline__ void fft_inlane(Cx<T> (&z)[C], const T* __restrict__ 
   for (int i = 0; i < C; ++i) z[i] = y[i];
 }
 
-// tab: W_N^t (re, im) for t < N, then the window w_j, j < N.
-template <typename T, int G, int C>
-__global__ __launch_bounds__(256) void k_spod_fft(int64_t m, int64_t nt, const float* __restrict__ D,
+// Value of lane ^ H inside the group (DPP quad permutations for H = 1, 2).
+template <int H, typename T>
+__device__ __forceinline__ T lane_xor(T v) {
+  if constexpr (H == 1) return dpp<0xB1>(v);
+  else if constexpr (H == 2) return dpp<0x4E>(v);
+  else return __shfl_xor(v, H, 64);
+}
+
+// Radix-2 decimation-in-frequency stages across the G lanes of a group,
+// exchange distance HALF down to 1: the lower lane keeps a + b, the upper
+// (b - a) W_(2 HALF)^(q mod HALF).
+template <typename T, int C, int N, int HALF>
+__device__ __forceinline__ void dif_lanes(Cx<T> (&z)[C], int q, const Cx<T>* tws) {
+  if constexpr (HALF >= 1) {
+    const bool up = (q & HALF) != 0;
+    const Cx<T> w = up ? tws[(q & (HALF - 1)) * (N / (2 * HALF))] : Cx<T>{T(1), T(0)};
+#pragma unroll
+    for (int n2 = 0; n2 < C; ++n2) {
+      const T ore = lane_xor<HALF>(z[n2].re);
+      const T oim = lane_xor<HALF>(z[n2].im);
+      const Cx<T> d = up ? Cx<T>{ore - z[n2].re, oim - z[n2].im}
+                         : Cx<T>{z[n2].re + ore, z[n2].im + oim};
+      z[n2] = up ? cmul(d, w) : d;
+    }
+    dif_lanes<T, C, N, HALF / 2>(z, q, tws);
+  }
+}
+
+// tab: W_N^t (re, im) for t < N, then the window w_j, j < N; copied to LDS.
+// VEC: D rows and block starts are 16-byte aligned (float4 loads).
+template <typename T, int G, int C, bool VEC>
+__global__ __launch_bounds__(256, 3) void k_spod_fft(int64_t m, int64_t nt, const float* __restrict__ D,
                                                   int64_t ldd, int step, int nb, int remove_mean,
                                                   const T* __restrict__ tab,
                                                   const double* __restrict__ scl,
                                                   T* __restrict__ E, int64_t ldm) {
   constexpr int N2 = G * C, N = 2 * N2, PW = 64 / G;
   typedef typename T2v<T>::type TT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* tws = reinterpret_cast<Cx<T>*>(smem);
+  T* win = reinterpret_cast<T*>(tws + N);
+  for (int t = threadIdx.x; t < 3 * N; t += 256) reinterpret_cast<T*>(smem)[t] = tab[t];
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane % G;
   const int64_t p = ((int64_t)blockIdx.x * 4 + wave) * PW + lane / G;
   const bool valid = p < m;
   const float* row = D + (valid ? p : 0) * ldd;
-  const T* tw = tab;
-  const T* win = tab + 2 * N;
   const double base_scale = scl[0];
   double mu = 0.0;
   if (remove_mean) {
     double acc = 0.0;
-    for (int64_t t = q; t < nt; t += G) acc += (double)row[t];
+    int64_t t0 = 0;
+    if constexpr (VEC) {
+      const float4* r4 = reinterpret_cast<const float4*>(row);
+      const int64_t nt4 = nt / 4;
+      for (int64_t t = q; t < nt4; t += G) {
+        const float4 v = r4[t];
+        acc += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+      }
+      t0 = 4 * nt4;
+    }
+    for (int64_t t = t0 + q; t < nt; t += G) acc += (double)row[t];
     mu = group_sum<G>(acc) / (double)nt;
   }
-  const int k1 = bitrev_c(q, G);
-  // partner group lane holding Z_(N2 - k) for k = k1 + G k2 (k1 != 0)
-  const int src = lane - q + bitrev_c((G - k1) & (G - 1), G);
+  // x - mu: in FP64 for T = double; for T = float as (x - mu_hi) - mu_lo with
+  // mu = mu_hi + mu_lo split into floats (error below one float rounding of
+  // the exact difference)
+  const float mu_hi = (float)mu, mu_lo = (float)(mu - (double)mu_hi);
+  auto centred = [&](float v) -> T {
+    if constexpr (sizeof(T) == 8) return (double)v - mu;
+    else return (v - mu_hi) - mu_lo;
+  };
+  const int64_t fstride = (int64_t)G * nb * ldm;  // elements between k and k + G
   for (int b = 0; b < nb; ++b) {
-    const float* x = row + (int64_t)b * step;
+    // lane-dependent addresses and the window and twiddle values are rebuilt
+    // every block (an opaque copy of the lane index) instead of being held in
+    // registers across the loop
+    asm volatile("" ::: "memory");
+    int qv = q;
+    asm volatile("" : "+v"(qv));
+    const int k1 = bitrev_c(qv, G);
+    const float* x = row + (int64_t)b * step + 2 * C * qv;
+    const T* wq = win + 2 * C * qv;
+    TT* out = reinterpret_cast<TT*>(E) + ((int64_t)k1 * nb + b) * ldm + p;
     Cx<T> z[C];
+    if constexpr (VEC) {
 #pragma unroll
-    for (int n2 = 0; n2 < C; ++n2) {
-      const int j = 2 * (C * q + n2);
-      z[n2].re = (T)(((double)x[j] - mu) * (double)win[j]);
-      z[n2].im = (T)(((double)x[j + 1] - mu) * (double)win[j + 1]);
-    }
-    // decimation in frequency across the G lanes of the group
-#pragma unroll
-    for (int half = G / 2; half >= 1; half >>= 1) {
-      const bool up = (q & half) != 0;
-      const int ti = (q & (half - 1)) * (N / (2 * half));
-      const Cx<T> w = up ? Cx<T>{tw[2 * ti], tw[2 * ti + 1]} : Cx<T>{T(1), T(0)};
+      for (int i = 0; i < C / 2; ++i) {
+        const float4 v = reinterpret_cast<const float4*>(x)[i];
+        z[2 * i].re = centred(v.x) * wq[4 * i];
+        z[2 * i].im = centred(v.y) * wq[4 * i + 1];
+        z[2 * i + 1].re = centred(v.z) * wq[4 * i + 2];
+        z[2 * i + 1].im = centred(v.w) * wq[4 * i + 3];
+      }
+    } else {
 #pragma unroll
       for (int n2 = 0; n2 < C; ++n2) {
-        const T ore = __shfl_xor(z[n2].re, half, 64);
-        const T oim = __shfl_xor(z[n2].im, half, 64);
-        const Cx<T> d = up ? Cx<T>{ore - z[n2].re, oim - z[n2].im}
-                           : Cx<T>{z[n2].re + ore, z[n2].im + oim};
-        z[n2] = up ? cmul(d, w) : d;
+        z[n2].re = centred(x[2 * n2]) * wq[2 * n2];
+        z[n2].im = centred(x[2 * n2 + 1]) * wq[2 * n2 + 1];
       }
     }
     if constexpr (G > 1) {
+      dif_lanes<T, C, N, G / 2>(z, qv, tws);
 #pragma unroll
       for (int n2 = 1; n2 < C; ++n2) {
-        const int e = (n2 * k1) & (N2 - 1);
-        z[n2] = cmul(z[n2], Cx<T>{tw[4 * e], tw[4 * e + 1]});
+        asm volatile("" ::: "memory");  // load each twiddle next to its use
+        z[n2] = cmul(z[n2], tws[2 * ((n2 * k1) & (N2 - 1))]);
       }
     }
-    fft_inlane<T, C, N>(z, tw);
-    // real-input split and store
+    fft_inlane<T, C>(z);
+    // real-input split: Z_(N2-k) is z[(C - k2) mod C] of this lane when
+    // k1 = 0, else z[C - 1 - k2] of the lane holding k1' = G - k1
 #pragma unroll
     for (int k2 = 0; k2 < C; ++k2) {
+      asm volatile("" ::: "memory");
       Cx<T> pz = z[(C - k2) & (C - 1)];
-      if constexpr (G > 1) {
+      if constexpr (G == 4) {
+        // lanes (0, 1, 2, 3) hold k1 = (0, 2, 1, 3); partners (0, 1, 3, 2)
+        const T rre = dpp<0xB4>(z[C - 1 - k2].re);
+        const T rim = dpp<0xB4>(z[C - 1 - k2].im);
+        if (qv != 0) pz = Cx<T>{rre, rim};
+      } else if constexpr (G == 2) {
+        if (qv != 0) pz = z[C - 1 - k2];
+      } else if constexpr (G > 4) {
+        const int src = lane - qv + bitrev_c((G - k1) & (G - 1), G);
         const T rre = __shfl(z[C - 1 - k2].re, src, 64);
         const T rim = __shfl(z[C - 1 - k2].im, src, 64);
-        if (q != 0) pz = Cx<T>{rre, rim};
+        if (qv != 0) pz = Cx<T>{rre, rim};
       }
       const Cx<T> A = z[k2];
       const Cx<T> Ev = {(A.re + pz.re) * T(0.5), (A.im - pz.im) * T(0.5)};
       const Cx<T> O = {(A.im + pz.im) * T(0.5), (pz.re - A.re) * T(0.5)};
       const int k = k1 + G * k2;
-      const Cx<T> wo = cmul(Cx<T>{tw[2 * k], tw[2 * k + 1]}, O);
+      const Cx<T> wo = cmul(tws[k], O);
       const double sc = k == 0 ? base_scale : 2.0 * base_scale;
       if (valid) {
         TT v;
         v.x = (T)((double)(Ev.re + wo.re) * sc);
         v.y = (T)((double)(Ev.im + wo.im) * sc);
-        reinterpret_cast<TT*>(E)[((int64_t)k * nb + b) * ldm + p] = v;
+        *out = v;
       }
+      out += fstride;
     }
-    if (valid && q == 0) {
+    if (valid && qv == 0) {
       TT v;
       v.x = (T)(((double)z[0].re - (double)z[0].im) * base_scale);
       v.y = T(0);
@@ -207,7 +323,13 @@ __global__ __launch_bounds__(256) void k_spod_tables(int N, int window, int nb, 
   }
 }
 
-constexpr int fft_c(bool f64, int N2) { return N2 <= 32 ? N2 : (!f64 || N2 >= 2048 ? 32 : 16); }
+// values per lane: at most 32 (FP32) or 16 (FP64; 32 at N2 = 2048, where 64
+// lanes per point is the limit), at least two lanes per point from N2 = 32
+// (FP32) or 16 (FP64) on, which keeps the register count of a lane down
+constexpr int fft_c(bool f64, int N2) {
+  return f64 ? (N2 <= 8 ? N2 : (N2 == 16 ? 8 : (N2 >= 2048 ? 32 : 16)))
+             : (N2 <= 16 ? N2 : (N2 == 32 ? 16 : 32));
+}
 
 template <typename T, int N2>
 hipError_t fft_launch(int64_t m, int64_t nt, const float* D, int64_t ldd, int step, int nb,
@@ -216,8 +338,20 @@ hipError_t fft_launch(int64_t m, int64_t nt, const float* D, int64_t ldd, int st
   constexpr int C = fft_c(sizeof(T) == 8, N2), G = N2 / C, PW = 64 / G;
   const int64_t blocks = (m + 4 * PW - 1) / (4 * PW);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_spod_fft<T, G, C>), dim3((unsigned)blocks), dim3(256), 0, st, m, nt, D,
-                     ldd, step, nb, remove_mean, tab, scl, E, ldm);
+  const size_t lds = (size_t)3 * 2 * N2 * sizeof(T);
+  const bool vec = ((uintptr_t)D % 16 == 0) && ldd % 4 == 0 && step % 4 == 0;
+  const void* fn = vec ? (const void*)k_spod_fft<T, G, C, true> : (const void*)k_spod_fft<T, G, C, false>;
+  if (lds > 64 * 1024) {
+    const hipError_t e =
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (vec)
+    hipLaunchKernelGGL((k_spod_fft<T, G, C, true>), dim3((unsigned)blocks), dim3(256), lds, st, m,
+                       nt, D, ldd, step, nb, remove_mean, tab, scl, E, ldm);
+  else
+    hipLaunchKernelGGL((k_spod_fft<T, G, C, false>), dim3((unsigned)blocks), dim3(256), lds, st, m,
+                       nt, D, ldd, step, nb, remove_mean, tab, scl, E, ldm);
   return hipGetLastError();
 }
 
