@@ -172,6 +172,7 @@ hipError_t launch_apply_tree_f64(const QrGeom& g, int64_t h, int64_t P, const do
 // ---- small SVD (Eq. svdqr2) ------------------------------------------------
 struct JacobiPlan {
   int n, npad, w, G, lpp, xcd_stride;
+  int block;  // 1: block Jacobi of 16-column blocks (n > 256)
 };
 bool jacobi_plan(int n, JacobiPlan* p);
 size_t jacobi_ws_bytes(const JacobiPlan& p, int max_sweeps);

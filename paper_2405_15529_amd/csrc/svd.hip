@@ -32,9 +32,25 @@ namespace pylom {
 
 constexpr int JT = 256;     // threads per Jacobi workgroup
 constexpr int JRPL = 32;    // max column rows per lane (16 up to n = 1024)
+constexpr int BJB = 16;     // column block of the block Jacobi
+// Widths above this use the block Jacobi (k_bjacobi): at n = 1808 the
+// pairwise tournament needs 451 barrier steps per sweep over 4-column blocks.
+constexpr int kBlockJacobiFrom = 256;
 
 bool jacobi_plan(int n, JacobiPlan* p) {
   if (n < 1 || n > 2048) return false;
+  p->block = 0;
+  if (n > kBlockJacobiFrom) {
+    // block tournament: 2G blocks of 16 columns, G workgroups
+    p->n = n;
+    p->w = BJB;
+    p->npad = (n + 2 * BJB - 1) / (2 * BJB) * (2 * BJB);
+    p->G = p->npad / (2 * BJB);
+    p->lpp = 64;
+    p->xcd_stride = 1;
+    p->block = 1;
+    return true;
+  }
   // block width w (even, 4..16): a pair is handled by 256/w lanes of one wave,
   // each holding at most JRPL rows of a column.  16 up to n = 256, else 4:
   // measured on one MI355X (the SVD phase of FP64 POD), n = 256 takes 6.3 ms
@@ -413,6 +429,238 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
   if (g == 0 && tid == 0) a.status[0] = sweep_done;
 }
 
+// ---- block one-sided Jacobi (n > 256) ----------------------------------------
+// The columns of X = R^T are cut into 2G blocks of 16.  The G workgroups play
+// the round-robin tournament of the pairwise kernel over blocks, one
+// device-wide barrier per step; at a step workgroup g owns the 32 columns
+// X_p = [X_I X_J] and rotates all their pairs at once: it forms the Gram
+// matrix M = X_p^T X_p (FP64 MFMA), runs one cyclic sweep of two-sided
+// rotations on M in LDS (16 disjoint pairs per round, 31 rounds; each is the
+// pair rotation of jacobi_pair, decided by the same relative test
+// |m_pq| > tol sqrt(m_pp m_qq), with m_pp - t m_pq and m_qq + t m_pq as the
+// new diagonal and an exact zero at (p, q)), and applies the accumulated
+// orthogonal W (32 x 32) as X_p <- X_p W and V_p <- V_p W (FP64 MFMA).  Every
+// step starts from a fresh Gram matrix of the current columns, so each
+// rotation decision rests on dot products as accurate as the pairwise ones;
+// a step whose Gram matrix passes the test for every pair leaves its columns
+// untouched.  A sweep in which no step rotated ends the iteration.
+struct BJArgs {
+  int n, npad, G, max_sweeps;
+  double* A;
+  double* V;
+  unsigned int* bar;
+  int* flags;
+  int* status;
+};
+
+__global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
+  typedef Mfma<double>::v4 v4;
+  constexpr int LD = 33;
+  __shared__ double Ms[32 * LD];
+  __shared__ double Ws[32 * LD];
+  __shared__ double part[4][3][256];
+  __shared__ double rcs[16][6];  // c, s, t, m_pq, m_pp, m_qq of pair k in this round
+  __shared__ int step_rot, rot_count;
+  const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  const int n = a.n;
+  const double tol = (double)n * 0x1p-53;
+  const int nplayers = 2 * a.G;
+  const int ntiles = (n + 15) / 16;
+  unsigned int epoch = 0;
+  int sweep_done = -1;
+  // deflation of rounding-noise columns, as in the pairwise kernel: 8 threads
+  // per column of the two starting blocks
+  {
+    unsigned long long* cmax =
+        reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(a.bar) + 64);
+    const int b0 = rr_player(g, 0, nplayers), b1 = rr_player(nplayers - 1 - g, 0, nplayers);
+    const int c = tid >> 3, sub = tid & 7;
+    const int jc = (c < 16 ? b0 : b1) * BJB + (c & 15);
+    const double* col = a.A + (int64_t)jc * n;
+    double x = 0.0;
+    for (int r = sub; r < n; r += 8) x += col[r] * col[r];
+    x = group_sum<8>(x);
+    if (sub == 0) atomicMax(cmax, (unsigned long long)__double_as_longlong(x));
+    grid_barrier(a.bar, (unsigned int)a.G, (unsigned int)g, epoch, a.status);
+    const double mx = __longlong_as_double(
+        (long long)__hip_atomic_load(cmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (x > 0.0 && x <= mx * 0x1p-106) {
+      double* cw = a.A + (int64_t)jc * n;
+      for (int r = sub; r < n; r += 8) cw[r] = 0.0;
+    }
+    grid_barrier(a.bar, (unsigned int)a.G, (unsigned int)g, epoch, a.status);
+  }
+  for (int sw = 0; sw < a.max_sweeps; ++sw) {
+    if (tid == 0) rot_count = 0;
+    for (int st = 0; st < nplayers - 1; ++st) {
+      const int bI = rr_player(g, st, nplayers), bJ = rr_player(nplayers - 1 - g, st, nplayers);
+      // ---- Gram matrix: wave w takes the 4-row steps w, w + 4, ... (rows
+      // 16 s + 4 w + g4); three 16 x 16 tiles M_II, M_IJ, M_JJ
+      {
+        const double* xa = a.A + (int64_t)(bI * BJB + i16) * n;
+        const double* xb = a.A + (int64_t)(bJ * BJB + i16) * n;
+        v4 t00 = vzero4<double>(), t01 = vzero4<double>(), t11 = vzero4<double>();
+        for (int r0 = 4 * wave; r0 < n; r0 += 16) {
+          const int r = r0 + g4;
+          const double u = r < n ? xa[r] : 0.0;
+          const double v = r < n ? xb[r] : 0.0;
+          t00 = Mfma<double>::op(u, u, t00);
+          t01 = Mfma<double>::op(u, v, t01);
+          t11 = Mfma<double>::op(v, v, t11);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = Mfma<double>::drow(g4, q) * 16 + i16;
+          part[wave][0][e] = t00[q];
+          part[wave][1][e] = t01[q];
+          part[wave][2][e] = t11[q];
+        }
+      }
+      if (tid == 0) step_rot = 0;
+      __syncthreads();
+      {
+        const int i = tid >> 4, j = tid & 15;
+        const double m00 = (part[0][0][tid] + part[1][0][tid]) + (part[2][0][tid] + part[3][0][tid]);
+        const double m01 = (part[0][1][tid] + part[1][1][tid]) + (part[2][1][tid] + part[3][1][tid]);
+        const double m11 = (part[0][2][tid] + part[1][2][tid]) + (part[2][2][tid] + part[3][2][tid]);
+        Ms[i * LD + j] = m00;
+        Ms[i * LD + 16 + j] = m01;
+        Ms[(16 + j) * LD + i] = m01;
+        Ms[(16 + i) * LD + 16 + j] = m11;
+#pragma unroll
+        for (int e = tid; e < 32 * 32; e += 256) Ws[(e >> 5) * LD + (e & 31)] = (e >> 5) == (e & 31) ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      // does any pair need a rotation?
+      {
+        int need = 0;
+        for (int e = tid; e < 32 * 32; e += 256) {
+          const int i = e >> 5, j = e & 31;
+          if (i < j) {
+            const double mii = Ms[i * LD + i], mjj = Ms[j * LD + j], mij = Ms[i * LD + j];
+            if (mii > 0.0 && mjj > 0.0 && fabs(mij) > tol * sqrt(mii) * sqrt(mjj)) need = 1;
+          }
+        }
+        if (need) step_rot = 1;
+      }
+      __syncthreads();
+      if (step_rot) {
+        int myrot = 0;
+        // ---- one cyclic sweep of two-sided rotations on M, accumulated in W
+        for (int rd = 0; rd < 31; ++rd) {
+          if (tid < 16) {
+            const int p = rr_player(tid, rd, 32), q = rr_player(31 - tid, rd, 32);
+            const double mpp = Ms[p * LD + p], mqq = Ms[q * LD + q], mpq = Ms[p * LD + q];
+            double c = 1.0, sn = 0.0, t = 0.0;
+            if (mpp > 0.0 && mqq > 0.0 && fabs(mpq) > tol * sqrt(mpp) * sqrt(mqq)) {
+              const double zeta = (mqq - mpp) / (2.0 * mpq);
+              const double az = fabs(zeta);
+              double tt = (az > 1e150) ? 0.5 / az : 1.0 / (az + sqrt(1.0 + zeta * zeta));
+              if (tt > 0.0) {
+                if (zeta < 0.0) tt = -tt;
+                c = 1.0 / sqrt(1.0 + tt * tt);
+                sn = c * tt;
+                t = tt;
+                ++myrot;
+              }
+            }
+            rcs[tid][0] = c;
+            rcs[tid][1] = sn;
+            rcs[tid][2] = t;
+            rcs[tid][3] = mpq;
+            rcs[tid][4] = mpp;
+            rcs[tid][5] = mqq;
+          }
+          __syncthreads();
+          // rows p, q of M
+#pragma unroll
+          for (int e = tid; e < 16 * 32; e += 256) {
+            const int k = e >> 5, j = e & 31;
+            const double t = rcs[k][2];
+            if (t != 0.0) {
+              const int p = rr_player(k, rd, 32), q = rr_player(31 - k, rd, 32);
+              const double c = rcs[k][0], sn = rcs[k][1];
+              const double x = Ms[p * LD + j], y = Ms[q * LD + j];
+              Ms[p * LD + j] = c * x - sn * y;
+              Ms[q * LD + j] = sn * x + c * y;
+            }
+          }
+          __syncthreads();
+          // columns p, q of M (exact values at the pair) and of W
+#pragma unroll
+          for (int e = tid; e < 16 * 32; e += 256) {
+            const int k = e >> 5, i = e & 31;
+            const double t = rcs[k][2];
+            if (t != 0.0) {
+              const int p = rr_player(k, rd, 32), q = rr_player(31 - k, rd, 32);
+              const double c = rcs[k][0], sn = rcs[k][1], mpq = rcs[k][3];
+              const double x = Ms[i * LD + p], y = Ms[i * LD + q];
+              if (i == p) {
+                Ms[p * LD + p] = rcs[k][4] - t * mpq;
+                Ms[p * LD + q] = 0.0;
+              } else if (i == q) {
+                Ms[q * LD + p] = 0.0;
+                Ms[q * LD + q] = rcs[k][5] + t * mpq;
+              } else {
+                Ms[i * LD + p] = c * x - sn * y;
+                Ms[i * LD + q] = sn * x + c * y;
+              }
+              const double wx = Ws[i * LD + p], wy = Ws[i * LD + q];
+              Ws[i * LD + p] = c * wx - sn * wy;
+              Ws[i * LD + q] = sn * wx + c * wy;
+            }
+          }
+          __syncthreads();
+        }
+        if (myrot) atomicAdd(&rot_count, myrot);
+        // ---- X_p <- X_p W and V_p <- V_p W: wave w takes the 16-row tiles
+        // w, w + 4, ...; B operand W[4 s + g4][16 h + i16] in registers
+        double wb[2][8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int s4 = 0; s4 < 8; ++s4) wb[h][s4] = Ws[(4 * s4 + g4) * LD + 16 * h + i16];
+#pragma unroll
+        for (int buf = 0; buf < 2; ++buf) {
+          double* X = buf ? a.V : a.A;
+          for (int tl = wave; tl < ntiles; tl += 4) {
+            const int rr = 16 * tl + i16;
+            v4 o0 = vzero4<double>(), o1 = vzero4<double>();
+#pragma unroll
+            for (int s4 = 0; s4 < 8; ++s4) {
+              const int cl = 4 * s4 + g4;
+              const int gc = (cl < 16 ? bI : bJ) * BJB + (cl & 15);
+              const double xv = rr < n ? X[(int64_t)gc * n + rr] : 0.0;
+              o0 = Mfma<double>::op(xv, wb[0][s4], o0);
+              o1 = Mfma<double>::op(xv, wb[1][s4], o1);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = 16 * tl + Mfma<double>::drow(g4, q);
+              if (row < n) {
+                X[(int64_t)(bI * BJB + i16) * n + row] = o0[q];
+                X[(int64_t)(bJ * BJB + i16) * n + row] = o1[q];
+              }
+            }
+          }
+        }
+      }
+      if (st == nplayers - 2) {
+        __syncthreads();
+        if (tid == 0 && rot_count) atomicAdd(a.flags + sw, rot_count);
+      }
+      grid_barrier(a.bar, (unsigned int)a.G, (unsigned int)g, epoch, a.status);
+    }
+    const int total = __hip_atomic_load(a.flags + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (total == 0) {
+      sweep_done = sw + 1;
+      break;
+    }
+  }
+  if (g == 0 && tid == 0) a.status[0] = sweep_done;
+}
+
 // ---- finalize: sigma, sort, sign convention, outputs, truncation ------------
 // A holds W (columns w_j, sigma_j = |w_j|, v_j = w_j / sigma_j); V holds J
 // (u_j = column j).  Each pair is signed so that the largest-magnitude entry
@@ -525,7 +773,16 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
                      w.flags, nflags, status, max_sweeps > 0 ? 0 : -1, (int64_t)0, (int64_t)0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (max_sweeps > 0) {
+  if (max_sweeps > 0 && p.block) {
+    BJArgs b;
+    b.n = p.n; b.npad = p.npad; b.G = p.G; b.max_sweeps = max_sweeps; b.A = w.A; b.V = w.V;
+    b.bar = w.bar; b.flags = w.flags; b.status = status;
+    void* args[] = {&b};
+    const void* fn = (const void*)k_bjacobi;
+    e = (coop && p.G > 1) ? hipLaunchCooperativeKernel(fn, dim3(p.G), dim3(256), args, 0, st)
+                          : hipLaunchKernel(fn, dim3(p.G), dim3(256), args, 0, st);
+    if (e != hipSuccess) return e;
+  } else if (max_sweeps > 0) {
     JacobiArgs a;
     a.n = p.n; a.npad = p.npad; a.w = p.w; a.G = p.G; a.xcd_stride = p.xcd_stride;
     a.max_sweeps = max_sweeps; a.A = w.A; a.V = w.V; a.bar = w.bar; a.flags = w.flags;
@@ -563,6 +820,16 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
 
 int jacobi_resident_per_cu(const JacobiPlan& p) {
   const void* fn = nullptr;
+  if (p.block) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_bjacobi, 256, 0) !=
+            hipSuccess ||
+        nb < 1) {
+      (void)hipGetLastError();
+      return 1;
+    }
+    return nb;
+  }
   const bool wide = (p.n + p.lpp - 1) / p.lpp > 16;
   switch (p.lpp) {
     case 16: fn = (const void*)k_jacobi<16, 16>; break;

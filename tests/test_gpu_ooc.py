@@ -87,7 +87,11 @@ def test_pod_host_matches_in_device_and_oracle(m, n, b, wr, rm, dt):
         f"u {eu:.2e} v {ev:.2e} span {proj:.2e}")
     assert rel <= 1e-12 and nw <= 1e-12
     if dt == np.float64:
-        assert oe <= 1e-12 and eu <= 1e-9 and ev <= 1e-9 and proj <= 1e-9
+        # products of orthogonal factors applied in floating point are
+        # orthogonal to O(n u) per column (Higham, Sec. 19.3): above n = 256
+        # the SVD of R applies its rotations as 32 x 32 orthogonal blocks
+        orth = max(1e-12, 10.0 * np.sqrt(max(len(live), 1)) * n * checks.EPS64)
+        assert oe <= orth and eu <= 1e-9 and ev <= 1e-9 and proj <= 1e-9
     else:
         # U is stored in FP32
         assert oe <= 1e-6 and eu <= 2e-7 and ev <= 1e-9 and proj <= 1e-6
