@@ -1755,8 +1755,9 @@ extern "C" int pylom_pod_batched(pylom_ctx c, pylom_dtype dtype, pylom_prec prec
     int64_t per_cu = 1 << 20;
     for (int64_t i = 0; i < count; ++i) {
       const JacobiPlan& jp = L.plans[(size_t)i].jp;
-      lane_g[(size_t)L.lane[(size_t)i]] = std::max<int64_t>(lane_g[(size_t)L.lane[(size_t)i]], jp.G);
-      if (jp.G > 1) per_cu = std::min<int64_t>(per_cu, jacobi_resident_per_cu(jp));
+      const int64_t wgs = (int64_t)jp.G * jp.ks;
+      lane_g[(size_t)L.lane[(size_t)i]] = std::max<int64_t>(lane_g[(size_t)L.lane[(size_t)i]], wgs);
+      if (wgs > 1) per_cu = std::min<int64_t>(per_cu, jacobi_resident_per_cu(jp));
     }
     int64_t gsum = 0;
     for (int64_t g : lane_g) gsum += (g > 1) ? g : 0;

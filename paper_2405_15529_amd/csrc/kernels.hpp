@@ -173,6 +173,7 @@ hipError_t launch_apply_tree_f64(const QrGeom& g, int64_t h, int64_t P, const do
 struct JacobiPlan {
   int n, npad, w, G, lpp, xcd_stride;
   int block;  // 1: block Jacobi of 16-column blocks (n > 256)
+  int ks;     // workgroups per block pair (block Jacobi; grid = G * ks)
 };
 bool jacobi_plan(int n, JacobiPlan* p);
 size_t jacobi_ws_bytes(const JacobiPlan& p, int max_sweeps);

@@ -40,6 +40,7 @@ constexpr int kBlockJacobiFrom = 256;
 bool jacobi_plan(int n, JacobiPlan* p) {
   if (n < 1 || n > 2048) return false;
   p->block = 0;
+  p->ks = 1;
   if (n > kBlockJacobiFrom) {
     // block tournament: 2G blocks of 16 columns, G workgroups
     p->n = n;
@@ -49,6 +50,9 @@ bool jacobi_plan(int n, JacobiPlan* p) {
     p->lpp = 64;
     p->xcd_stride = 1;
     p->block = 1;
+    // workgroups per block pair (rows split in ks parts): at most 240
+    // workgroups in all, one per CU
+    p->ks = 240 / p->G < 4 ? (240 / p->G < 1 ? 1 : 240 / p->G) : 4;
     return true;
   }
   // block width w (even, 4..16): a pair is handled by 256/w lanes of one wave,
@@ -77,8 +81,17 @@ struct JacobiWs {
   double* A;          // npad columns x n rows (column-major)
   double* V;          // npad columns x n rows
   unsigned int* bar;  // barrier counter
-  int* flags;         // rotations per sweep
+  int* flags;         // rotations per sweep; then (block Jacobi) the pair counters
+  int* pairc;
+  double* gp;         // block Jacobi: posted partial Gram matrices
 };
+
+// Ints of the flags area: rotation counts of max_sweeps + 1 sweeps, then one
+// counter per block pair 16 ints apart (all zeroed by the setup kernel).
+static int jacobi_pair_off(int max_sweeps) { return (max_sweeps + 1 + 15) / 16 * 16; }
+static int jacobi_nflags(const JacobiPlan& p, int max_sweeps) {
+  return p.block ? jacobi_pair_off(max_sweeps) + 16 * p.G : max_sweeps + 1;
+}
 
 static JacobiWs jacobi_ws(const JacobiPlan& p, int max_sweeps, void* ws) {
   JacobiWs w;
@@ -90,11 +103,17 @@ static JacobiWs jacobi_ws(const JacobiPlan& p, int max_sweeps, void* ws) {
   w.bar = (unsigned int*)c;  // global counter, deflation maximum, eight group counters
   c += 1024;
   w.flags = (int*)c;
+  w.pairc = w.flags + jacobi_pair_off(max_sweeps);
+  c += (sizeof(int) * (size_t)(jacobi_nflags(p, max_sweeps) + 64) + 255) & ~(size_t)255;
+  w.gp = (double*)c;
   return w;
 }
 
 size_t jacobi_ws_bytes(const JacobiPlan& p, int max_sweeps) {
-  return sizeof(double) * 2 * (size_t)p.npad * p.n + 1024 + sizeof(int) * (size_t)(max_sweeps + 64);
+  size_t b = sizeof(double) * 2 * (size_t)p.npad * p.n + 1024 +
+             ((sizeof(int) * (size_t)(jacobi_nflags(p, max_sweeps) + 64) + 255) & ~(size_t)255);
+  if (p.block) b += sizeof(double) * 3 * 256 * (size_t)p.G * p.ks;
+  return b;
 }
 
 // ---- setup: A <- R^T (column j = row j of R), V <- I, counters <- 0 ---------
@@ -430,28 +449,86 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
 }
 
 // ---- block one-sided Jacobi (n > 256) ----------------------------------------
-// The columns of X = R^T are cut into 2G blocks of 16.  The G workgroups play
+// The columns of X = R^T are cut into 2G blocks of 16.  G block pairs play
 // the round-robin tournament of the pairwise kernel over blocks, one
-// device-wide barrier per step; at a step workgroup g owns the 32 columns
-// X_p = [X_I X_J] and rotates all their pairs at once: it forms the Gram
-// matrix M = X_p^T X_p (FP64 MFMA), runs one cyclic sweep of two-sided
-// rotations on M in LDS (16 disjoint pairs per round, 31 rounds; each is the
-// pair rotation of jacobi_pair, decided by the same relative test
-// |m_pq| > tol sqrt(m_pp m_qq), with m_pp - t m_pq and m_qq + t m_pq as the
-// new diagonal and an exact zero at (p, q)), and applies the accumulated
-// orthogonal W (32 x 32) as X_p <- X_p W and V_p <- V_p W (FP64 MFMA).  Every
-// step starts from a fresh Gram matrix of the current columns, so each
+// device-wide barrier per step; each pair is served by ks workgroups, one
+// per quarter of the rows.  At a step the workgroups of pair g own the 32
+// columns X_p = [X_I X_J]:
+//   1. each forms the Gram matrix of its rows, M_k = X_p,k^T X_p,k (FP64
+//      MFMA), and posts it; after a barrier of the ks workgroups each sums
+//      them in the same order, M = sum_k M_k;
+//   2. each runs the same rounds of two-sided rotations on M in LDS
+//      (16 disjoint pairs per round: the 256 pairs across the two blocks in
+//      16 rounds, and at the first step of a sweep also the pairs inside
+//      each block in 15 rounds before them; each is the pair rotation of
+//      jacobi_pair, decided by the same relative test m_pq^2 > tol^2 m_pp
+//      m_qq, with m_pp - t m_pq and m_qq + t m_pq as the new diagonal and an
+//      exact zero at (p, q)), accumulating the orthogonal W (32 x 32);
+//      identical inputs give identical W in every workgroup;
+//   3. each applies W to its rows: X_p <- X_p W, V_p <- V_p W (FP64 MFMA).
+// Every step starts from a fresh Gram matrix of the current columns, so each
 // rotation decision rests on dot products as accurate as the pairwise ones;
 // a step whose Gram matrix passes the test for every pair leaves its columns
 // untouched.  A sweep in which no step rotated ends the iteration.
 struct BJArgs {
-  int n, npad, G, max_sweeps;
+  int n, npad, G, ks, max_sweeps;
   double* A;
   double* V;
   unsigned int* bar;
   int* flags;
+  int* pairc;   // one counter per block pair, 16 ints apart
+  double* gp;   // posted partial Gram matrices: [G][ks][3 * 256]
   int* status;
 };
+
+// Barrier of the ks workgroups of one block pair (bounded spin, as the grid
+// barrier).
+__device__ __forceinline__ void pair_barrier(int* cnt, int ks, int& pep, int* status) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ++pep;
+    __threadfence();
+    atomicAdd(cnt, 1);
+    const int target = pep * ks;
+    unsigned long long spins = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 1023ull) == 0 &&
+          (spins > (1ull << 24) ||
+           __hip_atomic_load(status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        atomicExch(status + 1, 1);
+        break;
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// Pair k (< 16) of round rd of a step: the within-block rounds (15, first
+// step of a sweep) pair the columns of each block among themselves (8 pairs
+// in block I, 8 in block J); the cross rounds (16) pair column k of block I
+// with column (k + rd) mod 16 of block J.
+__device__ __forceinline__ void bj_pair(int k, int rd, bool within, int& p, int& q) {
+  if (within) {
+    const int kk = k & 7, off = k < 8 ? 0 : 16;
+    p = off + rr_player(kk, rd, 16);
+    q = off + rr_player(15 - kk, rd, 16);
+  } else {
+    p = k;
+    q = 16 + ((k + rd) & 15);
+  }
+}
+
+// c = (1 + t^2)^(-1/2): hardware reciprocal square root refined by two
+// Newton steps.
+__device__ __forceinline__ double rot_cos(double t) {
+  const double x = fma(t, t, 1.0);
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  return y;
+}
 
 __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
   typedef Mfma<double>::v4 v4;
@@ -461,53 +538,73 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
   __shared__ double part[4][3][256];
   __shared__ double rcs[16][6];  // c, s, t, m_pq, m_pp, m_qq of pair k in this round
   __shared__ int step_rot, rot_count;
-  const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = blockIdx.x / a.ks, kq = blockIdx.x % a.ks;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i16 = lane & 15, g4 = lane >> 4;
-  const int n = a.n;
-  const double tol = (double)n * 0x1p-53;
+  const int n = a.n, ks = a.ks;
+  const double tol = (double)n * 0x1p-53, tol2 = tol * tol;
   const int nplayers = 2 * a.G;
-  const int ntiles = (n + 15) / 16;
+  const unsigned int nwg = (unsigned int)(a.G * ks);
+  // this workgroup's rows: 16-row tiles [t0, t1)
+  const int ntiles = (n + 15) / 16, tq = (ntiles + ks - 1) / ks;
+  const int t0 = kq * tq < ntiles ? kq * tq : ntiles;
+  const int t1 = t0 + tq < ntiles ? t0 + tq : ntiles;
+  const int rlo = 16 * t0, rhi = 16 * t1 < n ? 16 * t1 : n;
+  int* pcnt = a.pairc + 16 * g;
+  double* mypart = a.gp + ((int64_t)g * ks + kq) * (3 * 256);
   unsigned int epoch = 0;
+  int pep = 0;
   int sweep_done = -1;
-  // deflation of rounding-noise columns, as in the pairwise kernel: 8 threads
-  // per column of the two starting blocks
+  // deflation of rounding-noise columns, as in the pairwise kernel (the first
+  // workgroup of each pair, 8 threads per column of its starting blocks)
   {
     unsigned long long* cmax =
         reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(a.bar) + 64);
     const int b0 = rr_player(g, 0, nplayers), b1 = rr_player(nplayers - 1 - g, 0, nplayers);
     const int c = tid >> 3, sub = tid & 7;
     const int jc = (c < 16 ? b0 : b1) * BJB + (c & 15);
-    const double* col = a.A + (int64_t)jc * n;
     double x = 0.0;
-    for (int r = sub; r < n; r += 8) x += col[r] * col[r];
+    if (kq == 0) {
+      const double* col = a.A + (int64_t)jc * n;
+      for (int r = sub; r < n; r += 8) x += col[r] * col[r];
+    }
     x = group_sum<8>(x);
-    if (sub == 0) atomicMax(cmax, (unsigned long long)__double_as_longlong(x));
-    grid_barrier(a.bar, (unsigned int)a.G, (unsigned int)g, epoch, a.status);
+    if (kq == 0 && sub == 0) atomicMax(cmax, (unsigned long long)__double_as_longlong(x));
+    grid_barrier(a.bar, nwg, (unsigned int)blockIdx.x, epoch, a.status);
     const double mx = __longlong_as_double(
         (long long)__hip_atomic_load(cmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    if (x > 0.0 && x <= mx * 0x1p-106) {
+    if (kq == 0 && x > 0.0 && x <= mx * 0x1p-106) {
       double* cw = a.A + (int64_t)jc * n;
       for (int r = sub; r < n; r += 8) cw[r] = 0.0;
     }
-    grid_barrier(a.bar, (unsigned int)a.G, (unsigned int)g, epoch, a.status);
+    grid_barrier(a.bar, nwg, (unsigned int)blockIdx.x, epoch, a.status);
   }
   for (int sw = 0; sw < a.max_sweeps; ++sw) {
     if (tid == 0) rot_count = 0;
     for (int st = 0; st < nplayers - 1; ++st) {
       const int bI = rr_player(g, st, nplayers), bJ = rr_player(nplayers - 1 - g, st, nplayers);
-      // ---- Gram matrix: wave w takes the 4-row steps w, w + 4, ... (rows
-      // 16 s + 4 w + g4); three 16 x 16 tiles M_II, M_IJ, M_JJ
+      // ---- partial Gram matrix of rows [rlo, rhi): wave w takes the 4-row
+      // steps w, w + 4, ...; three 16 x 16 tiles M_II, M_IJ, M_JJ
       {
         const double* xa = a.A + (int64_t)(bI * BJB + i16) * n;
         const double* xb = a.A + (int64_t)(bJ * BJB + i16) * n;
         v4 t00 = vzero4<double>(), t01 = vzero4<double>(), t11 = vzero4<double>();
-        for (int r0 = 4 * wave; r0 < n; r0 += 16) {
-          const int r = r0 + g4;
-          const double u = r < n ? xa[r] : 0.0;
-          const double v = r < n ? xb[r] : 0.0;
-          t00 = Mfma<double>::op(u, u, t00);
-          t01 = Mfma<double>::op(u, v, t01);
-          t11 = Mfma<double>::op(v, v, t11);
+        const int nst = rhi - rlo - 4 * wave > 0 ? (rhi - rlo - 4 * wave + 15) / 16 : 0;
+        for (int s0 = 0; s0 < nst; s0 += 16) {
+          double u[16], v[16];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const int r = rlo + 16 * (s0 + k) + 4 * wave + g4;
+            const bool ok = s0 + k < nst && r < rhi;
+            u[k] = ok ? xa[r] : 0.0;
+            v[k] = ok ? xb[r] : 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            t00 = Mfma<double>::op(u[k], u[k], t00);
+            t01 = Mfma<double>::op(u[k], v[k], t01);
+            t11 = Mfma<double>::op(v[k], v[k], t11);
+          }
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -517,29 +614,37 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
           part[wave][2][e] = t11[q];
         }
       }
-      if (tid == 0) step_rot = 0;
       __syncthreads();
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        mypart[t * 256 + tid] = (part[0][t][tid] + part[1][t][tid]) + (part[2][t][tid] + part[3][t][tid]);
+      pair_barrier(pcnt, ks, pep, a.status);
+      if (tid == 0) step_rot = 0;
       {
+        const double* gp0 = a.gp + (int64_t)g * ks * (3 * 256);
+        double m[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < ks; ++k)
+#pragma unroll
+          for (int t = 0; t < 3; ++t) m[t] += gp0[k * (3 * 256) + t * 256 + tid];
         const int i = tid >> 4, j = tid & 15;
-        const double m00 = (part[0][0][tid] + part[1][0][tid]) + (part[2][0][tid] + part[3][0][tid]);
-        const double m01 = (part[0][1][tid] + part[1][1][tid]) + (part[2][1][tid] + part[3][1][tid]);
-        const double m11 = (part[0][2][tid] + part[1][2][tid]) + (part[2][2][tid] + part[3][2][tid]);
-        Ms[i * LD + j] = m00;
-        Ms[i * LD + 16 + j] = m01;
-        Ms[(16 + j) * LD + i] = m01;
-        Ms[(16 + i) * LD + 16 + j] = m11;
+        Ms[i * LD + j] = m[0];
+        Ms[i * LD + 16 + j] = m[1];
+        Ms[(16 + j) * LD + i] = m[1];
+        Ms[(16 + i) * LD + 16 + j] = m[2];
 #pragma unroll
         for (int e = tid; e < 32 * 32; e += 256) Ws[(e >> 5) * LD + (e & 31)] = (e >> 5) == (e & 31) ? 1.0 : 0.0;
       }
       __syncthreads();
-      // does any pair need a rotation?
+      // does any pair of this step need a rotation?  (the cross pairs; at
+      // the first step of a sweep also the pairs inside each block)
+      const bool first = st == 0;
       {
         int need = 0;
         for (int e = tid; e < 32 * 32; e += 256) {
           const int i = e >> 5, j = e & 31;
-          if (i < j) {
+          if (i < j && (first || (i < 16 && j >= 16))) {
             const double mii = Ms[i * LD + i], mjj = Ms[j * LD + j], mij = Ms[i * LD + j];
-            if (mii > 0.0 && mjj > 0.0 && fabs(mij) > tol * sqrt(mii) * sqrt(mjj)) need = 1;
+            if (mii > 0.0 && mjj > 0.0 && mij * mij > tol2 * mii * mjj) need = 1;
           }
         }
         if (need) step_rot = 1;
@@ -548,18 +653,26 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
       if (step_rot) {
         int myrot = 0;
         // ---- one cyclic sweep of two-sided rotations on M, accumulated in W
-        for (int rd = 0; rd < 31; ++rd) {
+        const int ra = tid >> 4, cb = tid & 15;  // 2 x 2 block (row pair ra, column pair cb)
+        const int nrounds = first ? 31 : 16;
+        for (int rdi = 0; rdi < nrounds; ++rdi) {
+          const bool within = first && rdi < 15;
+          const int rd = within ? rdi : (first ? rdi - 15 : rdi);
           if (tid < 16) {
-            const int p = rr_player(tid, rd, 32), q = rr_player(31 - tid, rd, 32);
+            int p, q;
+            bj_pair(tid, rd, within, p, q);
             const double mpp = Ms[p * LD + p], mqq = Ms[q * LD + q], mpq = Ms[p * LD + q];
             double c = 1.0, sn = 0.0, t = 0.0;
-            if (mpp > 0.0 && mqq > 0.0 && fabs(mpq) > tol * sqrt(mpp) * sqrt(mqq)) {
-              const double zeta = (mqq - mpp) / (2.0 * mpq);
-              const double az = fabs(zeta);
-              double tt = (az > 1e150) ? 0.5 / az : 1.0 / (az + sqrt(1.0 + zeta * zeta));
-              if (tt > 0.0) {
-                if (zeta < 0.0) tt = -tt;
-                c = 1.0 / sqrt(1.0 + tt * tt);
+            if (mpp > 0.0 && mqq > 0.0 && mpq * mpq > tol2 * mpp * mqq) {
+              // the pair rotation: t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2))
+              // with zeta = (m_qq - m_pp) / (2 m_pq), written as
+              // 2 m_pq sign(d) / (|d| + sqrt(d^2 + 4 m_pq^2)), d = m_qq - m_pp
+              const double d = mqq - mpp;
+              const double rr = sqrt(fma(d, d, 4.0 * mpq * mpq));
+              double tt = 2.0 * mpq / (fabs(d) + rr);
+              if (d < 0.0) tt = -tt;
+              if (tt != 0.0 && isfinite(tt)) {
+                c = rot_cos(tt);
                 sn = c * tt;
                 t = tt;
                 ++myrot;
@@ -573,74 +686,90 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
             rcs[tid][5] = mqq;
           }
           __syncthreads();
-          // rows p, q of M
-#pragma unroll
-          for (int e = tid; e < 16 * 32; e += 256) {
-            const int k = e >> 5, j = e & 31;
-            const double t = rcs[k][2];
-            if (t != 0.0) {
-              const int p = rr_player(k, rd, 32), q = rr_player(31 - k, rd, 32);
-              const double c = rcs[k][0], sn = rcs[k][1];
-              const double x = Ms[p * LD + j], y = Ms[q * LD + j];
-              Ms[p * LD + j] = c * x - sn * y;
-              Ms[q * LD + j] = sn * x + c * y;
-            }
-          }
-          __syncthreads();
-          // columns p, q of M (exact values at the pair) and of W
-#pragma unroll
-          for (int e = tid; e < 16 * 32; e += 256) {
-            const int k = e >> 5, i = e & 31;
-            const double t = rcs[k][2];
-            if (t != 0.0) {
-              const int p = rr_player(k, rd, 32), q = rr_player(31 - k, rd, 32);
-              const double c = rcs[k][0], sn = rcs[k][1], mpq = rcs[k][3];
-              const double x = Ms[i * LD + p], y = Ms[i * LD + q];
-              if (i == p) {
-                Ms[p * LD + p] = rcs[k][4] - t * mpq;
-                Ms[p * LD + q] = 0.0;
-              } else if (i == q) {
-                Ms[q * LD + p] = 0.0;
-                Ms[q * LD + q] = rcs[k][5] + t * mpq;
-              } else {
-                Ms[i * LD + p] = c * x - sn * y;
-                Ms[i * LD + q] = sn * x + c * y;
+          {
+            // rows (p_a, q_a) and columns (p_b, q_b) of M: both sides at once
+            int pa, qa, pb, qb;
+            bj_pair(ra, rd, within, pa, qa);
+            bj_pair(cb, rd, within, pb, qb);
+            const double ca = rcs[ra][0], sa = rcs[ra][1];
+            const double cc = rcs[cb][0], sc = rcs[cb][1];
+            if (ra == cb) {
+              if (rcs[ra][2] != 0.0) {
+                const double t = rcs[ra][2], mpq = rcs[ra][3];
+                Ms[pa * LD + pa] = rcs[ra][4] - t * mpq;
+                Ms[qa * LD + qa] = rcs[ra][5] + t * mpq;
+                Ms[pa * LD + qa] = 0.0;
+                Ms[qa * LD + pa] = 0.0;
               }
-              const double wx = Ws[i * LD + p], wy = Ws[i * LD + q];
-              Ws[i * LD + p] = c * wx - sn * wy;
-              Ws[i * LD + q] = sn * wx + c * wy;
+            } else if (rcs[ra][2] != 0.0 || rcs[cb][2] != 0.0) {
+              const double xpp = Ms[pa * LD + pb], xpq = Ms[pa * LD + qb];
+              const double xqp = Ms[qa * LD + pb], xqq = Ms[qa * LD + qb];
+              const double ypp = ca * xpp - sa * xqp, ypq = ca * xpq - sa * xqq;
+              const double yqp = sa * xpp + ca * xqp, yqq = sa * xpq + ca * xqq;
+              Ms[pa * LD + pb] = cc * ypp - sc * ypq;
+              Ms[pa * LD + qb] = sc * ypp + cc * ypq;
+              Ms[qa * LD + pb] = cc * yqp - sc * yqq;
+              Ms[qa * LD + qb] = sc * yqp + cc * yqq;
+            }
+            // W <- W J: rows (p_a, q_a), columns (p_b, q_b)
+            if (rcs[cb][2] != 0.0) {
+              const double wpp = Ws[pa * LD + pb], wpq = Ws[pa * LD + qb];
+              const double wqp = Ws[qa * LD + pb], wqq = Ws[qa * LD + qb];
+              Ws[pa * LD + pb] = cc * wpp - sc * wpq;
+              Ws[pa * LD + qb] = sc * wpp + cc * wpq;
+              Ws[qa * LD + pb] = cc * wqp - sc * wqq;
+              Ws[qa * LD + qb] = sc * wqp + cc * wqq;
             }
           }
           __syncthreads();
         }
-        if (myrot) atomicAdd(&rot_count, myrot);
-        // ---- X_p <- X_p W and V_p <- V_p W: wave w takes the 16-row tiles
-        // w, w + 4, ...; B operand W[4 s + g4][16 h + i16] in registers
+        if (kq == 0 && myrot) atomicAdd(&rot_count, myrot);
+        // ---- X_p <- X_p W and V_p <- V_p W on this workgroup's tiles; wave w
+        // takes the tiles t0 + w, t0 + w + 4, ...; B operand W[4 s + g4][16 h + i16]
         double wb[2][8];
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
           for (int s4 = 0; s4 < 8; ++s4) wb[h][s4] = Ws[(4 * s4 + g4) * LD + 16 * h + i16];
+        int64_t coff[8];
+#pragma unroll
+        for (int s4 = 0; s4 < 8; ++s4) {
+          const int cl = 4 * s4 + g4;
+          coff[s4] = (int64_t)((cl < 16 ? bI : bJ) * BJB + (cl & 15)) * n;
+        }
+        // up to TMX tiles of the wave are loaded before any product (one
+        // memory round trip per buffer instead of one per tile)
+        constexpr int TMX = 8;
 #pragma unroll
         for (int buf = 0; buf < 2; ++buf) {
           double* X = buf ? a.V : a.A;
-          for (int tl = wave; tl < ntiles; tl += 4) {
-            const int rr = 16 * tl + i16;
-            v4 o0 = vzero4<double>(), o1 = vzero4<double>();
+          for (int base = t0 + wave; base < t1; base += 4 * TMX) {
+            double xv[TMX][8];
 #pragma unroll
-            for (int s4 = 0; s4 < 8; ++s4) {
-              const int cl = 4 * s4 + g4;
-              const int gc = (cl < 16 ? bI : bJ) * BJB + (cl & 15);
-              const double xv = rr < n ? X[(int64_t)gc * n + rr] : 0.0;
-              o0 = Mfma<double>::op(xv, wb[0][s4], o0);
-              o1 = Mfma<double>::op(xv, wb[1][s4], o1);
+            for (int jt = 0; jt < TMX; ++jt) {
+              const int tl = base + 4 * jt, rr = 16 * tl + i16;
+              const bool ok = tl < t1 && rr < n;
+#pragma unroll
+              for (int s4 = 0; s4 < 8; ++s4) xv[jt][s4] = ok ? X[coff[s4] + rr] : 0.0;
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int row = 16 * tl + Mfma<double>::drow(g4, q);
-              if (row < n) {
-                X[(int64_t)(bI * BJB + i16) * n + row] = o0[q];
-                X[(int64_t)(bJ * BJB + i16) * n + row] = o1[q];
+            for (int jt = 0; jt < TMX; ++jt) {
+              const int tl = base + 4 * jt;
+              if (tl < t1) {
+                v4 o0 = vzero4<double>(), o1 = vzero4<double>();
+#pragma unroll
+                for (int s4 = 0; s4 < 8; ++s4) {
+                  o0 = Mfma<double>::op(xv[jt][s4], wb[0][s4], o0);
+                  o1 = Mfma<double>::op(xv[jt][s4], wb[1][s4], o1);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const int row = 16 * tl + Mfma<double>::drow(g4, q);
+                  if (row < n) {
+                    X[(int64_t)(bI * BJB + i16) * n + row] = o0[q];
+                    X[(int64_t)(bJ * BJB + i16) * n + row] = o1[q];
+                  }
+                }
               }
             }
           }
@@ -650,7 +779,7 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
         __syncthreads();
         if (tid == 0 && rot_count) atomicAdd(a.flags + sw, rot_count);
       }
-      grid_barrier(a.bar, (unsigned int)a.G, (unsigned int)g, epoch, a.status);
+      grid_barrier(a.bar, nwg, (unsigned int)blockIdx.x, epoch, a.status);
     }
     const int total = __hip_atomic_load(a.flags + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (total == 0) {
@@ -658,7 +787,7 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
       break;
     }
   }
-  if (g == 0 && tid == 0) a.status[0] = sweep_done;
+  if (blockIdx.x == 0 && tid == 0) a.status[0] = sweep_done;
 }
 
 // ---- finalize: sigma, sort, sign convention, outputs, truncation ------------
@@ -768,19 +897,21 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
     return hipGetLastError();
   }
   JacobiWs w = jacobi_ws(p, max_sweeps, ws);
-  const int nflags = max_sweeps + 1;
+  const int nflags = jacobi_nflags(p, max_sweeps);
   hipLaunchKernelGGL(k_jacobi_setup, dim3(64), dim3(256), 0, st, p.n, p.npad, R, w.A, w.V, w.bar,
                      w.flags, nflags, status, max_sweeps > 0 ? 0 : -1, (int64_t)0, (int64_t)0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (max_sweeps > 0 && p.block) {
     BJArgs b;
-    b.n = p.n; b.npad = p.npad; b.G = p.G; b.max_sweeps = max_sweeps; b.A = w.A; b.V = w.V;
-    b.bar = w.bar; b.flags = w.flags; b.status = status;
+    b.n = p.n; b.npad = p.npad; b.G = p.G; b.ks = p.ks; b.max_sweeps = max_sweeps; b.A = w.A;
+    b.V = w.V; b.bar = w.bar; b.flags = w.flags; b.pairc = w.pairc; b.gp = w.gp;
+    b.status = status;
     void* args[] = {&b};
     const void* fn = (const void*)k_bjacobi;
-    e = (coop && p.G > 1) ? hipLaunchCooperativeKernel(fn, dim3(p.G), dim3(256), args, 0, st)
-                          : hipLaunchKernel(fn, dim3(p.G), dim3(256), args, 0, st);
+    const dim3 grid((unsigned)(p.G * p.ks));
+    e = coop ? hipLaunchCooperativeKernel(fn, grid, dim3(256), args, 0, st)
+             : hipLaunchKernel(fn, grid, dim3(256), args, 0, st);
     if (e != hipSuccess) return e;
   } else if (max_sweeps > 0) {
     JacobiArgs a;

@@ -107,12 +107,12 @@ def test_batched_reports_nonconvergence():
     ctx.close()
 
 
-def test_batched_wide_block_jacobi_grids_run_together():
+def test_batched_wide_jacobi_grids_are_chained():
     # three instances with n = 600, 1000, 700 on three streams: widths above
-    # 256 use the block Jacobi, whose grids (n / 32 workgroups: 19 + 32 + 22)
-    # fit on the device together, so the batch runs them concurrently
-    # without chaining (and never hits a barrier timeout); checked against
-    # the exact spectra, eagerly and through the graph
+    # 256 use the block Jacobi, whose grids (n / 32 block pairs of 4
+    # workgroups, one CU each: 76 + 128 + 88) sum to 292 > 256 CUs, so the
+    # batch must order them one after another (never a barrier timeout);
+    # checked against the exact spectra, eagerly and through the graph
     import torch
     from paper_2405_15529_amd import api, synth
     shapes = [(2400, 600), (3000, 1000), (2100, 700)]
@@ -131,7 +131,7 @@ def test_batched_wide_block_jacobi_grids_run_together():
             batch.run()
             rc, _ = ctx.status()
             assert rc == 0, rc
-            assert ctx.get_option("batch_jacobi_chained") == 0
+            assert ctx.get_option("batch_jacobi_chained") == 1
             for res, s, (m, n) in zip(batch.results(), specs, shapes):
                 assert res.nr == n
                 err = np.max(np.abs(res.S.cpu().numpy() - s)) / s[0]
