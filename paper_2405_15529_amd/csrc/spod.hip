@@ -8,8 +8,9 @@
 // (c_f = 2 for 0 < f < npwin/2, else 1) is kept for f = 0..npwin/2.
 //
 // The real block of N = npwin samples is transformed as one complex sequence
-// of N2 = N/2 values z_n = y_{2n} + i y_{2n+1} (y = w x), Z = DFT_N2(z), and
-// split: Y_k = (Z_k + conj Z_{N2-k})/2 + W_N^k (Z_k - conj Z_{N2-k})/(2i).
+// of N2 = N/2 values z_n = y_{2n} + i y_{2n+1} (y = w x, the window carrying
+// the scale 1/(sum(w) sqrt(nBlks))), Z = DFT_N2(z), and split:
+// Y_k = (Z_k + conj Z_{N2-k})/2 + W_N^k (Z_k - conj Z_{N2-k})/(2i).
 // The N2-point DFT runs in registers on a group of G lanes per point (C = N2/G
 // values per lane, n = C q + n2 for lane q of the group): a radix-2
 // decimation-in-frequency exchange across the G lanes, the twiddles
@@ -158,15 +159,18 @@ __device__ __forceinline__ T lane_xor(T v) {
 template <typename T, int C, int N, int HALF>
 __device__ __forceinline__ void dif_lanes(Cx<T> (&z)[C], int q, const Cx<T>* tws) {
   if constexpr (HALF >= 1) {
+    // d = s z + o with s = -1 on the upper lanes; their twiddle is 1 on the
+    // lower lanes and at the last stage (W_2^0), where no product is taken
     const bool up = (q & HALF) != 0;
+    const T sg = up ? T(-1) : T(1);
     const Cx<T> w = up ? tws[(q & (HALF - 1)) * (N / (2 * HALF))] : Cx<T>{T(1), T(0)};
 #pragma unroll
     for (int n2 = 0; n2 < C; ++n2) {
       const T ore = lane_xor<HALF>(z[n2].re);
       const T oim = lane_xor<HALF>(z[n2].im);
-      const Cx<T> d = up ? Cx<T>{ore - z[n2].re, oim - z[n2].im}
-                         : Cx<T>{z[n2].re + ore, z[n2].im + oim};
-      z[n2] = up ? cmul(d, w) : d;
+      const Cx<T> d = {fma(sg, z[n2].re, ore), fma(sg, z[n2].im, oim)};
+      if constexpr (HALF == 1) z[n2] = d;
+      else z[n2] = cmul(d, w);
     }
     dif_lanes<T, C, N, HALF / 2>(z, q, tws);
   }
@@ -192,7 +196,6 @@ __global__ __launch_bounds__(256, 3) void k_spod_fft(int64_t m, int64_t nt, cons
   const int64_t p = ((int64_t)blockIdx.x * 4 + wave) * PW + lane / G;
   const bool valid = p < m;
   const float* row = D + (valid ? p : 0) * ldd;
-  const double base_scale = scl[0];
   double mu = 0.0;
   if (remove_mean) {
     double acc = 0.0;
@@ -274,31 +277,35 @@ __global__ __launch_bounds__(256, 3) void k_spod_fft(int64_t m, int64_t nt, cons
         const T rim = __shfl(z[C - 1 - k2].im, src, 64);
         if (qv != 0) pz = Cx<T>{rre, rim};
       }
+      // 2 Ev = Z_k + conj Z_(N2-k), 2 O = (Z_k - conj Z_(N2-k)) / i; the
+      // one-sided factor c_k = 2 (1 at k = 0) cancels the halves, and the
+      // scale 1 / (sum(w) sqrt(nBlks)) is in the window
       const Cx<T> A = z[k2];
-      const Cx<T> Ev = {(A.re + pz.re) * T(0.5), (A.im - pz.im) * T(0.5)};
-      const Cx<T> O = {(A.im + pz.im) * T(0.5), (pz.re - A.re) * T(0.5)};
+      const Cx<T> E2 = {A.re + pz.re, A.im - pz.im};
+      const Cx<T> O2 = {A.im + pz.im, pz.re - A.re};
       const int k = k1 + G * k2;
-      const Cx<T> wo = cmul(tws[k], O);
-      const double sc = k == 0 ? base_scale : 2.0 * base_scale;
+      const Cx<T> wo = cmul(tws[k], O2);
+      const T h = k == 0 ? T(0.5) : T(1);
       if (valid) {
         TT v;
-        v.x = (T)((double)(Ev.re + wo.re) * sc);
-        v.y = (T)((double)(Ev.im + wo.im) * sc);
+        v.x = (E2.re + wo.re) * h;
+        v.y = (E2.im + wo.im) * h;
         *out = v;
       }
       out += fstride;
     }
     if (valid && qv == 0) {
       TT v;
-      v.x = (T)(((double)z[0].re - (double)z[0].im) * base_scale);
+      v.x = z[0].re - z[0].im;
       v.y = T(0);
       reinterpret_cast<TT*>(E)[((int64_t)N2 * nb + b) * ldm + p] = v;
     }
   }
 }
 
-// Twiddles W_N^t and the window in FP64, rounded to T; scl[0] =
-// 1 / (sum of the rounded window * sqrt(nb)).
+// Twiddles W_N^t in FP64, rounded to T, and the window w_j / (sum(w)
+// sqrt(nb)) (the spectral scale folded in; sums and products in FP64, then
+// rounded to T); scl[0] = 1 / (sum(w) sqrt(nb)).
 template <typename T>
 __global__ __launch_bounds__(256) void k_spod_tables(int N, int window, int nb, T* __restrict__ tab,
                                                      double* __restrict__ scl) {
@@ -310,17 +317,15 @@ __global__ __launch_bounds__(256) void k_spod_tables(int N, int window, int nb, 
     sincospi(-2.0 * (double)t / (double)N, &sv, &cv);
     tab[2 * t] = (T)cv;
     tab[2 * t + 1] = (T)sv;
-    const T w = (T)(a0 - a1 * cospi(2.0 * (double)t / (double)(N - 1)));
-    tab[2 * N + t] = w;
-    acc += (double)w;
+    acc += a0 - a1 * cospi(2.0 * (double)t / (double)(N - 1));
   }
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const double wsum = part[0] + part[1] + part[2] + part[3];
-    scl[0] = 1.0 / (wsum * sqrt((double)nb));
-  }
+  const double scale = 1.0 / ((part[0] + part[1] + part[2] + part[3]) * sqrt((double)nb));
+  for (int t = threadIdx.x; t < N; t += blockDim.x)
+    tab[2 * N + t] = (T)((a0 - a1 * cospi(2.0 * (double)t / (double)(N - 1))) * scale);
+  if (threadIdx.x == 0) scl[0] = scale;
 }
 
 // values per lane: at most 32 (FP32) or 16 (FP64; 32 at N2 = 2048, where 64

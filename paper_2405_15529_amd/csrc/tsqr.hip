@@ -171,12 +171,17 @@ __device__ __forceinline__ void factor_panel(T* __restrict__ C, int ldc, T* __re
         if (t == (h >> 2)) x = p[t];
       alpha = readlane(x, ((h & 3) << 4) + kk);
     }
-    // squared norm of the tail of column kk
-    T x2 = T(0);
+    // squared norm of the tail of column kk (four independent partial sums:
+    // the in-lane part of the column chain)
+    T x2;
+    {
+      T xq[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int r = g + 4 * t;
-      if (!INTERNAL || r > h) x2 += p[t] * p[t];
+      for (int t = 0; t < RT; ++t) {
+        const int r = g + 4 * t;
+        if (!INTERNAL || r > h) xq[t & 3] += p[t] * p[t];
+      }
+      x2 = (xq[0] + xq[1]) + (xq[2] + xq[3]);
     }
     x2 = perm32_pairsum(perm16_pairsum(x2));
     T sig = readlane(x2, kk);
@@ -251,13 +256,17 @@ __device__ __forceinline__ void factor_panel(T* __restrict__ C, int ldc, T* __re
     for (int t = 0; t < RT; ++t) v[t] = vb[g * RT + t];
     // fused pass: j > kk -> v^T [head; column j];  j < kk -> v_j^T v
     const int hj = INTERNAL ? (k0 + j - f) : -1;
-    T d = T(0);
+    T d;
+    {
+      T dq[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int r = g + 4 * t;
-      T cj = p[t];
-      if (INTERNAL && j < kk) cj = (r < hj) ? T(0) : ((r == hj) ? T(1) : p[t]);
-      d += cj * v[t];
+      for (int t = 0; t < RT; ++t) {
+        const int r = g + 4 * t;
+        T cj = p[t];
+        if (INTERNAL && j < kk) cj = (r < hj) ? T(0) : ((r == hj) ? T(1) : p[t]);
+        dq[t & 3] += cj * v[t];
+      }
+      d = (dq[0] + dq[1]) + (dq[2] + dq[3]);
     }
     if (!INTERNAL && j > kk && g == 0) d += Rd[kk * TLD + j];
     d = perm32_pairsum(perm16_pairsum(d));
