@@ -214,9 +214,9 @@ TRAFFIC = {
     # blocks 8192: mean over the 28 launches of one mixed call
     "blocked_trailing_fp32": {
         "sources": ("blocked.hip", "common.hpp"),
-        "sources_sha256": "57cbe4593008bf0f483dc2c578c21dc6f6cce99a35dcd6906c75a9aabfd8c1f2",
+        "sources_sha256": "2d80b6ae7bcaa2f0ab39684947fe5d7e98d29347433f69d67eb497bc80e97520",
         "shape": (4194304, 1808, 8192),
-        "bytes": 33350109656,  # FETCH 5.068e+11 (x1.99991) + WRITE 4.270e+11 (x1.0), / 28
+        "bytes": 33319203623,  # FETCH 5.057e+11 (x1.99992) + WRITE 4.273e+11 (x1.0), / 28
     },
 }
 
