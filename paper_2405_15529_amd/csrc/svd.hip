@@ -31,7 +31,7 @@
 namespace pylom {
 
 constexpr int JT = 256;     // threads per Jacobi workgroup
-constexpr int JRPL = 32;    // max column rows per lane (16 up to n = 1024)
+constexpr int JRPL = 16;    // max column rows per lane
 constexpr int BJB = 16;     // column block of the block Jacobi
 // Widths above this use the block Jacobi (k_bjacobi): at n = 1808 the
 // pairwise tournament needs 451 barrier steps per sweep over 4-column blocks.
@@ -56,11 +56,11 @@ bool jacobi_plan(int n, JacobiPlan* p) {
     return true;
   }
   // block width w (even, 4..16): a pair is handled by 256/w lanes of one wave,
-  // each holding at most JRPL rows of a column.  16 up to n = 256, else 4:
-  // measured on one MI355X (the SVD phase of FP64 POD), n = 256 takes 6.3 ms
-  // at w = 16, 8.9 at w = 8 and 17.3 at w = 4; n = 320 takes 12.9 ms at
-  // w = 8 and 11.2 at w = 4; n = 512 34.2 ms at w = 8 and 22.2 at w = 4.
-  int w = (n * 16 <= 4096) ? 16 : 4;
+  // each holding at most JRPL rows of a column.  16 up to n = 256: measured
+  // on one MI355X (the SVD phase of FP64 POD), n = 256 takes 6.3 ms at
+  // w = 16, 8.9 at w = 8 and 17.3 at w = 4; fewer, wider blocks win because
+  // every tournament step ends in a grid barrier.
+  int w = 16;
   if (n <= 2 * w) {
     int half = (n + 1) / 2;
     int ww = 4;
@@ -315,9 +315,8 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
     a.flags = (int*)((char*)a.flags + pb * a.sWs);
     a.status += 2 * pb;
   }
-  // circulating b columns (A and V parts): two buffers, one for the widest
-  // columns (32 rows per lane), where two do not fit in LDS
-  constexpr int NBUF = (JR <= 16) ? 2 : 1;
+  // circulating b columns (A and V parts), double-buffered
+  constexpr int NBUF = 2;
   __shared__ double xbuf[NBUF][JT * 2 * JR];
   __shared__ double xnorm[2][JT / 2];
   __shared__ int rot_count;
@@ -405,10 +404,8 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
         myrot += jacobi_pair<LPP, JR>(ca, cva, cb, cvb, na, nb, rpl, rpl, tol);
         if (q < w - 1) {
           // pass my b column to group grp-1, take the one of group grp+1; with
-          // two alternating buffers one barrier per round suffices, with one
-          // buffer the previous round's reads must end first
-          if (NBUF == 1 && q > 0) __syncthreads();
-          double* xb = xbuf[(NBUF == 2) ? (q & 1) : 0];
+          // two alternating buffers one barrier per round suffices
+          double* xb = xbuf[q & 1];
           // k-major slots: consecutive lanes touch consecutive doubles
 #pragma unroll
           for (int k = 0; k < JR; ++k) {
@@ -922,19 +919,18 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
     void* args[] = {&a};
     const dim3 grid(p.G * p.xcd_stride), block(JT);
     const void* fn = nullptr;
-    const bool wide = (p.n + p.lpp - 1) / p.lpp > 16;
     switch (p.lpp) {
       case 16: fn = (const void*)k_jacobi<16, 16>; break;
       case 32: fn = (const void*)k_jacobi<32, 16>; break;
-      case 64: fn = wide ? (const void*)k_jacobi<64, 32> : (const void*)k_jacobi<64, 16>; break;
+      case 64: fn = (const void*)k_jacobi<64, 16>; break;
       default: return hipErrorInvalidValue;
     }
     if (coop && p.G > 1) {
       e = hipLaunchCooperativeKernel(fn, grid, block, args, 0, st);
     } else {
       // plain launch (one workgroup, or inside stream capture, where a
-      // cooperative launch cannot be recorded).  The G workgroups (up to
-      // 226 at n = 2048, one per CU: the kernel holds 128 KB of LDS) become
+      // cooperative launch cannot be recorded).  The G workgroups (8 at
+      // n = 256, each holding 128 KB of LDS) become
       // resident as earlier work drains, since nothing else they wait for
       // holds a CU; the batched call chains its Jacobi launches across lanes
       // whenever their grids could not all be resident together.  Should
@@ -961,11 +957,10 @@ int jacobi_resident_per_cu(const JacobiPlan& p) {
     }
     return nb;
   }
-  const bool wide = (p.n + p.lpp - 1) / p.lpp > 16;
   switch (p.lpp) {
     case 16: fn = (const void*)k_jacobi<16, 16>; break;
     case 32: fn = (const void*)k_jacobi<32, 16>; break;
-    case 64: fn = wide ? (const void*)k_jacobi<64, 32> : (const void*)k_jacobi<64, 16>; break;
+    case 64: fn = (const void*)k_jacobi<64, 16>; break;
     default: return 1;
   }
   int nb = 0;

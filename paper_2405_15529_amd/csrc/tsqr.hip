@@ -469,36 +469,43 @@ __device__ __forceinline__ void tile_update(T* __restrict__ C, int ldc, const T*
 }
 
 // ---------------------------------------------------------------------------
-// chunk loads
 // Structured panel (the head of column k0+kk is state row k0+kk, the tail is
-// all s chunk rows), written for a short critical path:
+// all s chunk rows), written for a short per-column critical path:
 //  - every lane keeps its column's raw values and the scale that turns them
 //    into the reflector, so the register tile is never rewritten per column,
 //    and the update weight is simply zero for columns at or left of kk;
 //  - the head rows come from the prefetched diagonal block in registers (the
 //    lane that holds an entry adds it to its partial sum), so LDS is written
 //    but not read inside the loop;
-//  - 1/sqrt and 1/x use the hardware estimates refined by Newton steps;
-//  - v_kk is broadcast through an LDS vector laid out without bank conflicts;
-//  - the compact-WY T is built one column per step from the Gram values of
-//    the same pass, T(:c, c) = -tau_c T(:c, :c) (V(:, :c)^T v_c), with each
-//    lane holding four entries of its T row in registers.
+//  - 1/sqrt and 1/x use the hardware estimates refined by Newton steps (one
+//    in FP32, two in FP64), and the power-of-two rescale is undone by a
+//    multiplication with its exact inverse;
+//  - column kk is broadcast raw through an LDS vector laid out without bank
+//    conflicts; its reflector scale 1/(alpha - beta) is wave-uniform and is
+//    applied once to each dot product and once to each update weight;
+//  - the Gram values v_i^T v_k (i < k) of the same pass are kept in LDS, and
+//    the compact-WY factor is formed once after the loop as
+//    T = (diag(1/tau) + striu(V^T V))^{-1}, the triangular inverse that the
+//    column recurrence T(:c, c) = -tau_c T(:c, :c) V(:, :c)^T v_c also
+//    computes: lane c back-substitutes column c.
 __device__ __forceinline__ double hw_rcp(double x) { return __builtin_amdgcn_rcp(x); }
 __device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double hw_rsq(double x) { return __builtin_amdgcn_rsq(x); }
 __device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// Newton steps: the FP32 estimates are within about one ulp (one step
+// reaches rounding level); the FP64 ones carry about 23 bits (two steps).
 template <typename T>
 __device__ __forceinline__ T rcp_nr(T x) {
   T r = hw_rcp(x);
   r = r * (T(2) - x * r);
-  r = r * (T(2) - x * r);
+  if constexpr (sizeof(T) == 8) r = r * (T(2) - x * r);
   return r;
 }
 template <typename T>
 __device__ __forceinline__ T rsq_nr(T x) {
   T y = hw_rsq(x);
   y = y * (T(1.5) - T(0.5) * x * y * y);
-  y = y * (T(1.5) - T(0.5) * x * y * y);
+  if constexpr (sizeof(T) == 8) y = y * (T(1.5) - T(0.5) * x * y * y);
   return y;
 }
 
@@ -512,125 +519,140 @@ __device__ __forceinline__ void factor_panel_structured(
 #pragma unroll
   for (int t = 0; t < RT; ++t) p[t] = (j < kw) ? C[(g + 4 * t) * ldc + k0 + j] : T(0);
   T mysc = T(1), myscal = T(0);  // v_j = (x_j * mysc) * myscal once column j is factored
-  T treg[4] = {T(0), T(0), T(0), T(0)};  // T[j][4g + u]
-  T tau_prev = T(0);
-  auto t_column = [&](int c, T tauc) {
-    // the four Gram values are loaded unconditionally (one LDS round trip,
-    // overlapping the norm computation) and masked afterwards
-    T gv[4];
+  // Gram scratch S(i, k) = v_i^T v_k at Gm[i NB + k] for i < k < kw; every
+  // other entry stays zero
 #pragma unroll
-    for (int u = 0; u < 4; ++u) gv[u] = Gm[c * NB + 4 * g + u];
-    T part = T(0);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) part += (4 * g + u < c) ? treg[u] * gv[u] : T(0);
-    part = perm32_pairsum(perm16_pairsum(part));
-    const T val = (j < c) ? -tauc * part : ((j == c) ? tauc : T(0));
-#pragma unroll
-    for (int u = 0; u < 4; ++u) treg[u] = (4 * g + u == c) ? val : treg[u];
-  };
+  for (int u = 0; u < 4; ++u) Gm[lane * 4 + u] = T(0);
 #pragma unroll 1
-  for (int kk = 0; kk < kw; ++kk) {
-    if (kk > 0) t_column(kk - 1, tau_prev);
-    // this lane's entry of head row kk (held by the lanes of row group kk/4)
-    const int uk = kk & 3;
-    const T rsel = (uk == 0) ? rd4[0] : (uk == 1) ? rd4[1] : (uk == 2) ? rd4[2] : rd4[3];
-    const bool owner = g == (kk >> 2);
-    const T alpha = readlane(rsel, ((kk >> 2) << 4) + kk);
-    // squared norm of column kk's tail (all s chunk rows)
-    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+  for (int kb = 0; kb < kw; kb += 4) {
+    const bool owner = g == (kb >> 2);  // this lane holds head row kk (kb <= kk < kb + 4)
 #pragma unroll
-    for (int t = 0; t < RT; t += 4) {
-      a0 += p[t] * p[t];
-      if (t + 1 < RT) a1 += p[t + 1] * p[t + 1];
-      if (t + 2 < RT) a2 += p[t + 2] * p[t + 2];
-      if (t + 3 < RT) a3 += p[t + 3] * p[t + 3];
-    }
-    T x2 = (a0 + a1) + (a2 + a3);
-    x2 = perm32_pairsum(perm16_pairsum(x2));
-    T sig = readlane(x2, kk);
-    T sc = T(1);
-    if (__builtin_expect(sig < Tiny<T>::x2 && fabs(alpha) < Tiny<T>::root, 0)) {
-      // tiny head and tail (rank-deficient input): rescale by the power of
-      // two that brings max(|alpha|, |x|) into [0.5, 1) before forming the
-      // norm, so that no square falls into the subnormal range
-      T amax = T(0);
+    for (int u = 0; u < 4; ++u) {
+      const int kk = kb + u;
+      if (kk >= kw) break;
+      const T rsel = rd4[u];  // head row kk, column j, on the owner lanes
+      const T alpha = readlane(rsel, 4 * kb + kk);
+      // squared norm of column kk's tail (all s chunk rows)
+      T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
-      for (int t = 0; t < RT; ++t) amax = fmax(amax, fabs(p[t]));
-      amax = perm32_pairmax(perm16_pairmax(amax));
-      amax = fmax(readlane(amax, kk), fabs(alpha));
-      if (amax > T(0)) {
-        int e;
-        frexp(amax, &e);
-        sc = ldexp(T(1), (-e < Tiny<T>::max_exp) ? -e : Tiny<T>::max_exp);
+      for (int t = 0; t < RT; t += 4) {
+        a0 += p[t] * p[t];
+        if (t + 1 < RT) a1 += p[t + 1] * p[t + 1];
+        if (t + 2 < RT) a2 += p[t + 2] * p[t + 2];
+        if (t + 3 < RT) a3 += p[t + 3] * p[t + 3];
       }
-      T xs2 = T(0);
+      T x2 = (a0 + a1) + (a2 + a3);
+      x2 = perm32_pairsum(perm16_pairsum(x2));
+      T sig = readlane(x2, kk);
+      T sc = T(1), isc = T(1);
+      if (__builtin_expect(sig < Tiny<T>::x2 && fabs(alpha) < Tiny<T>::root, 0)) {
+        // tiny head and tail (rank-deficient input): rescale by the power of
+        // two that brings max(|alpha|, |x|) into [0.5, 1) before forming the
+        // norm, so that no square falls into the subnormal range
+        T amax = T(0);
 #pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const T xs = p[t] * sc;
-        xs2 += xs * xs;
+        for (int t = 0; t < RT; ++t) amax = fmax(amax, fabs(p[t]));
+        amax = perm32_pairmax(perm16_pairmax(amax));
+        amax = fmax(readlane(amax, kk), fabs(alpha));
+        if (amax > T(0)) {
+          int e;
+          frexp(amax, &e);
+          const int k = (-e < Tiny<T>::max_exp) ? -e : Tiny<T>::max_exp;
+          sc = ldexp(T(1), k);
+          isc = ldexp(T(1), -k);
+        }
+        T xs2 = T(0);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const T xs = p[t] * sc;
+          xs2 += xs * xs;
+        }
+        xs2 = perm32_pairsum(perm16_pairsum(xs2));
+        sig = readlane(xs2, kk);
       }
-      xs2 = perm32_pairsum(perm16_pairsum(xs2));
-      sig = readlane(xs2, kk);
-    }
-    T tau, beta, scal;
-    if (sig == T(0)) {
-      tau = T(0);
-      beta = alpha;
-      scal = T(0);
-    } else {
-      // a = as^2 + sig is a normal number here (>= 2^-960, or >= 1/4 after
-      // a rescale): y = 1/sqrt(a), |beta_s| = a y, 1/beta_s = -+y,
-      // tau = (bs - as)/bs = 1 - as/bs, scal = 1/(as - bs)
-      const T as = alpha * sc;
-      const T a = as * as + sig;
-      const T y = rsq_nr(a);
-      const T nrm = a * y;
-      const bool pos = as >= T(0);
-      const T bs = pos ? -nrm : nrm;
-      const T ibs = pos ? -y : y;
-      tau = T(1) - as * ibs;
-      scal = rcp_nr(as - bs);
-      beta = bs / sc;
-    }
-    if (j == kk) {
+      T tau, beta, scal;
+      if (sig == T(0)) {
+        tau = T(0);
+        beta = alpha;
+        scal = T(0);
+      } else {
+        // a = as^2 + sig is a normal number here (>= 2^-960, or >= 1/4 after
+        // a rescale): y = 1/sqrt(a), |beta_s| = a y, 1/beta_s = -+y,
+        // tau = (bs - as)/bs = 1 - as/bs, scal = 1/(as - bs)
+        const T as = alpha * sc;
+        const T a = as * as + sig;
+        const T y = rsq_nr(a);
+        const T nrm = a * y;
+        const bool pos = as >= T(0);
+        const T bs = pos ? -nrm : nrm;
+        const T ibs = pos ? -y : y;
+        tau = T(1) - as * ibs;
+        scal = rcp_nr(as - bs);
+        beta = bs * isc;
+      }
+      if (j == kk) {
 #pragma unroll
-      for (int t = 0; t < RT; ++t) vb[t * 4 + g] = (p[t] * sc) * scal;
-    }
-    mysc = (j == kk) ? sc : mysc;
-    myscal = (j == kk) ? scal : myscal;
-    if (lane == 0) {
-      taus[kk] = tau;
-      Rd[kk * TLD + kk] = beta;
-    }
-    wave_lds_sync();
-    T v[RT];
+        for (int t = 0; t < RT; ++t) vb[t * 4 + g] = p[t];
+      }
+      mysc = (j == kk) ? sc : mysc;
+      myscal = (j == kk) ? scal : myscal;
+      if (lane == 0) {
+        taus[kk] = tau;
+        Rd[kk * TLD + kk] = beta;
+      }
+      wave_lds_sync();
+      // w = x_kk sc: the reflector's tail is w scal
+      T w[RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) v[t] = vb[t * 4 + g];
-    // d_j = [head; x_j]^T v: v^T [head row kk; column j] for j > kk, and
-    // x_j^T v_kk for j < kk (x_j = the raw column, v_j = x_j mysc myscal)
-    T d0 = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
+      for (int t = 0; t < RT; ++t) w[t] = vb[t * 4 + g];
+      if (sc != T(1)) {
 #pragma unroll
-    for (int t = 0; t < RT; t += 4) {
-      d0 += p[t] * v[t];
-      if (t + 1 < RT) d1 += p[t + 1] * v[t + 1];
-      if (t + 2 < RT) d2 += p[t + 2] * v[t + 2];
-      if (t + 3 < RT) d3 += p[t + 3] * v[t + 3];
+        for (int t = 0; t < RT; ++t) w[t] *= sc;
+      }
+      // d_j = v_kk^T [head; x_j]: v^T [head row kk; column j] for j > kk, and
+      // x_j^T v_kk for j < kk (x_j = the raw column, v_j = x_j mysc myscal)
+      T d0 = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
+#pragma unroll
+      for (int t = 0; t < RT; t += 4) {
+        d0 += p[t] * w[t];
+        if (t + 1 < RT) d1 += p[t + 1] * w[t + 1];
+        if (t + 2 < RT) d2 += p[t + 2] * w[t + 2];
+        if (t + 3 < RT) d3 += p[t + 3] * w[t + 3];
+      }
+      T d = scal * ((d0 + d1) + (d2 + d3)) + ((owner && j > kk) ? rsel : T(0));
+      d = perm32_pairsum(perm16_pairsum(d));
+      if (j < kk && g == 0) Gm[j * NB + kk] = (d * mysc) * myscal;
+      const T tw = (j > kk) ? tau * d : T(0);
+      const T tws = tw * scal;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) p[t] -= tws * w[t];
+      if (owner && j > kk && j < kw) Rd[kk * TLD + j] = rsel - tw;
+      wave_lds_sync();
     }
-    T d = (d0 + d1) + (d2 + d3) + ((owner && j > kk) ? rsel : T(0));
-    d = perm32_pairsum(perm16_pairsum(d));
-    if (j < kk && g == 0) Gm[kk * NB + j] = (d * mysc) * myscal;
-    const T tw = (j > kk) ? tau * d : T(0);
-#pragma unroll
-    for (int t = 0; t < RT; ++t) p[t] -= tw * v[t];
-    if (owner && j > kk && j < kw) Rd[kk * TLD + j] = rsel - tw;
-    tau_prev = tau;
-    wave_lds_sync();
   }
-  t_column(kw - 1, tau_prev);
-  // T, the state diagonal block (R rows of this panel), then C and the exact
-  // reflectors (structured: the chunk rows of column j hold v_j)
+  // T = (diag(1/tau) + striu(V^T V))^{-1}, column c = j by back substitution
+  // from the bottom row: T(c, c) = tau_c, T(i, c) = -tau_i sum_{k > i}
+  // S(i, k) T(k, c); rows and columns at or beyond kw are zero (S is zero
+  // there, so no stale value enters a sum)
+  {
+    T tv[NB];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) Tm[j * NB + 4 * g + u] = treg[u];
+    for (int i = NB - 1; i >= 0; --i) {
+      T sacc = T(0);
+#pragma unroll
+      for (int k = NB - 1; k > i; --k) sacc += Gm[i * NB + k] * tv[k];
+      const T ti = taus[i];
+      tv[i] = (i >= kw) ? T(0) : ((i == j) ? ti : ((i < j) ? -ti * sacc : T(0)));
+    }
+    // lane 16 g + j writes rows 4g .. 4g+3 of column j
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T val = (g == 0) ? tv[u] : (g == 1) ? tv[4 + u] : (g == 2) ? tv[8 + u] : tv[12 + u];
+      Tm[(4 * g + u) * NB + j] = val;
+    }
+  }
+  // the state diagonal block (R rows of this panel), then C and the exact
+  // reflectors (structured: the chunk rows of column j hold v_j)
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int kk = g * 4 + u;
