@@ -28,6 +28,7 @@
 // Q [W; 0] (Eq. svdqr3 for a leaf, the broadcast step of Alg. 1 for a tree
 // node): the state tile X (n x 16) stays in LDS, the chunk rows Z accumulate
 // the output.
+#include <type_traits>
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -475,14 +476,17 @@ __device__ __forceinline__ void tile_update(T* __restrict__ C, int ldc, const T*
 //    into the reflector, so the register tile is never rewritten per column,
 //    and the update weight is simply zero for columns at or left of kk;
 //  - the head rows come from the prefetched diagonal block in registers (the
-//    lane that holds an entry adds it to its partial sum), so LDS is written
-//    but not read inside the loop;
+//    lane that holds an entry adds it to its partial sum) and the new R rows
+//    and tau stay there until the state is written back;
 //  - 1/sqrt and 1/x use the hardware estimates refined by Newton steps (one
 //    in FP32, two in FP64), and the power-of-two rescale is undone by a
 //    multiplication with its exact inverse;
-//  - column kk is broadcast raw through an LDS vector laid out without bank
-//    conflicts; its reflector scale 1/(alpha - beta) is wave-uniform and is
-//    applied once to each dot product and once to each update weight;
+//  - column kk is final when its step starts, so it is broadcast raw through
+//    an LDS vector (laid out without bank conflicts) before anything else,
+//    and the raw products x_kk^T x_j are formed beside its norm; the
+//    reflector scale 1/(alpha - beta) is wave-uniform and is applied once to
+//    each product and once to each update weight, so only the Householder
+//    scalars lie between the two reductions and the update;
 //  - the Gram values v_i^T v_k (i < k) of the same pass are kept in LDS, and
 //    the compact-WY factor is formed once after the loop as
 //    T = (diag(1/tau) + striu(V^T V))^{-1}, the triangular inverse that the
@@ -512,13 +516,16 @@ __device__ __forceinline__ T rsq_nr(T x) {
 template <typename T, int RT>
 __device__ __forceinline__ void factor_panel_structured(
     T* __restrict__ C, int ldc, T* __restrict__ Vp, T* __restrict__ Tm, T* __restrict__ state,
-    int n, int k0, int kw, int lane, const T (&rd4)[4], T* __restrict__ Rd, T* __restrict__ Gm,
-    T* __restrict__ vb, T* __restrict__ taus) {
+    int n, int k0, int kw, int lane, const T (&rd4)[4], T* __restrict__ Gm,
+    T* __restrict__ vb) {
   const int j = lane & 15, g = lane >> 4;
   T p[RT];
 #pragma unroll
   for (int t = 0; t < RT; ++t) p[t] = (j < kw) ? C[(g + 4 * t) * ldc + k0 + j] : T(0);
   T mysc = T(1), myscal = T(0);  // v_j = (x_j * mysc) * myscal once column j is factored
+  T mytau = T(0);                 // tau_j, on the lanes of column j
+  // rows 4g .. 4g+3 of column j of the R block, updated in registers
+  T rfin[4] = {rd4[0], rd4[1], rd4[2], rd4[3]};
   // Gram scratch S(i, k) = v_i^T v_k at Gm[i NB + k] for i < k < kw; every
   // other entry stays zero
 #pragma unroll
@@ -531,8 +538,19 @@ __device__ __forceinline__ void factor_panel_structured(
       const int kk = kb + u;
       if (kk >= kw) break;
       const T rsel = rd4[u];  // head row kk, column j, on the owner lanes
+      // column kk is final: broadcast it first, so that the LDS round trip
+      // overlaps the norm
+      if (j == kk) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) vb[t * 4 + g] = p[t];
+      }
+      wave_lds_sync();
+      T w[RT];  // x_kk, and x_kk sc after a rescale: the reflector's tail is w scal
+#pragma unroll
+      for (int t = 0; t < RT; ++t) w[t] = vb[t * 4 + g];
       const T alpha = readlane(rsel, 4 * kb + kk);
-      // squared norm of column kk's tail (all s chunk rows)
+      // squared norm of column kk's tail (all s chunk rows) and, independent
+      // of it, the raw products x_kk^T x_j and head row kk of column j
       T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
       for (int t = 0; t < RT; t += 4) {
@@ -541,14 +559,24 @@ __device__ __forceinline__ void factor_panel_structured(
         if (t + 2 < RT) a2 += p[t + 2] * p[t + 2];
         if (t + 3 < RT) a3 += p[t + 3] * p[t + 3];
       }
-      T x2 = (a0 + a1) + (a2 + a3);
-      x2 = perm32_pairsum(perm16_pairsum(x2));
+      T d0 = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
+#pragma unroll
+      for (int t = 0; t < RT; t += 4) {
+        d0 += p[t] * w[t];
+        if (t + 1 < RT) d1 += p[t + 1] * w[t + 1];
+        if (t + 2 < RT) d2 += p[t + 2] * w[t + 2];
+        if (t + 3 < RT) d3 += p[t + 3] * w[t + 3];
+      }
+      T x2 = perm32_pairsum(perm16_pairsum((a0 + a1) + (a2 + a3)));
+      T dw = perm32_pairsum(perm16_pairsum((d0 + d1) + (d2 + d3)));
+      const T hd = perm32_pairsum(perm16_pairsum((owner && j > kk) ? rsel : T(0)));
       T sig = readlane(x2, kk);
       T sc = T(1), isc = T(1);
       if (__builtin_expect(sig < Tiny<T>::x2 && fabs(alpha) < Tiny<T>::root, 0)) {
         // tiny head and tail (rank-deficient input): rescale by the power of
         // two that brings max(|alpha|, |x|) into [0.5, 1) before forming the
-        // norm, so that no square falls into the subnormal range
+        // norm, so that no square falls into the subnormal range, and form
+        // the products again from the rescaled column
         T amax = T(0);
 #pragma unroll
         for (int t = 0; t < RT; ++t) amax = fmax(amax, fabs(p[t]));
@@ -561,72 +589,46 @@ __device__ __forceinline__ void factor_panel_structured(
           sc = ldexp(T(1), k);
           isc = ldexp(T(1), -k);
         }
-        T xs2 = T(0);
+        T xs2 = T(0), dd = T(0);
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
           const T xs = p[t] * sc;
           xs2 += xs * xs;
+          w[t] *= sc;
+          dd += p[t] * w[t];
         }
         xs2 = perm32_pairsum(perm16_pairsum(xs2));
+        dw = perm32_pairsum(perm16_pairsum(dd));
         sig = readlane(xs2, kk);
       }
-      T tau, beta, scal;
-      if (sig == T(0)) {
-        tau = T(0);
-        beta = alpha;
-        scal = T(0);
-      } else {
-        // a = as^2 + sig is a normal number here (>= 2^-960, or >= 1/4 after
-        // a rescale): y = 1/sqrt(a), |beta_s| = a y, 1/beta_s = -+y,
-        // tau = (bs - as)/bs = 1 - as/bs, scal = 1/(as - bs)
-        const T as = alpha * sc;
-        const T a = as * as + sig;
-        const T y = rsq_nr(a);
-        const T nrm = a * y;
-        const bool pos = as >= T(0);
-        const T bs = pos ? -nrm : nrm;
-        const T ibs = pos ? -y : y;
-        tau = T(1) - as * ibs;
-        scal = rcp_nr(as - bs);
-        beta = bs * isc;
-      }
-      if (j == kk) {
-#pragma unroll
-        for (int t = 0; t < RT; ++t) vb[t * 4 + g] = p[t];
-      }
+      // a = as^2 + sig is a normal number unless sig = 0 (>= 2^-960, or
+      // >= 1/4 after a rescale): y = 1/sqrt(a), |beta_s| = a y, 1/beta_s =
+      // -+y, tau = (bs - as)/bs = 1 - as/bs, scal = 1/(as - bs); sig = 0
+      // gives the identity (tau = 0, beta = alpha)
+      const bool ident = sig == T(0);
+      const T as = alpha * sc;
+      const T a = ident ? T(1) : as * as + sig;
+      const T y = rsq_nr(a);
+      const T nrm = a * y;
+      const bool pos = as >= T(0);
+      const T bs = pos ? -nrm : nrm;
+      const T ibs = pos ? -y : y;
+      const T tau = ident ? T(0) : T(1) - as * ibs;
+      const T scal = ident ? T(0) : rcp_nr(as - bs);
+      const T beta = ident ? alpha : bs * isc;
       mysc = (j == kk) ? sc : mysc;
       myscal = (j == kk) ? scal : myscal;
-      if (lane == 0) {
-        taus[kk] = tau;
-        Rd[kk * TLD + kk] = beta;
-      }
-      wave_lds_sync();
-      // w = x_kk sc: the reflector's tail is w scal
-      T w[RT];
-#pragma unroll
-      for (int t = 0; t < RT; ++t) w[t] = vb[t * 4 + g];
-      if (sc != T(1)) {
-#pragma unroll
-        for (int t = 0; t < RT; ++t) w[t] *= sc;
-      }
+      mytau = (j == kk) ? tau : mytau;
       // d_j = v_kk^T [head; x_j]: v^T [head row kk; column j] for j > kk, and
       // x_j^T v_kk for j < kk (x_j = the raw column, v_j = x_j mysc myscal)
-      T d0 = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
-#pragma unroll
-      for (int t = 0; t < RT; t += 4) {
-        d0 += p[t] * w[t];
-        if (t + 1 < RT) d1 += p[t + 1] * w[t + 1];
-        if (t + 2 < RT) d2 += p[t + 2] * w[t + 2];
-        if (t + 3 < RT) d3 += p[t + 3] * w[t + 3];
-      }
-      T d = scal * ((d0 + d1) + (d2 + d3)) + ((owner && j > kk) ? rsel : T(0));
-      d = perm32_pairsum(perm16_pairsum(d));
+      const T d = scal * dw + hd;
       if (j < kk && g == 0) Gm[j * NB + kk] = (d * mysc) * myscal;
       const T tw = (j > kk) ? tau * d : T(0);
       const T tws = tw * scal;
 #pragma unroll
       for (int t = 0; t < RT; ++t) p[t] -= tws * w[t];
-      if (owner && j > kk && j < kw) Rd[kk * TLD + j] = rsel - tw;
+      // R row kk: beta on the diagonal, the updated head entries right of it
+      rfin[u] = owner ? ((j == kk) ? beta : ((j > kk) ? rsel - tw : rfin[u])) : rfin[u];
       wave_lds_sync();
     }
   }
@@ -641,7 +643,7 @@ __device__ __forceinline__ void factor_panel_structured(
       T sacc = T(0);
 #pragma unroll
       for (int k = NB - 1; k > i; --k) sacc += Gm[i * NB + k] * tv[k];
-      const T ti = taus[i];
+      const T ti = readlane(mytau, i);
       tv[i] = (i >= kw) ? T(0) : ((i == j) ? ti : ((i < j) ? -ti * sacc : T(0)));
     }
     // lane 16 g + j writes rows 4g .. 4g+3 of column j
@@ -656,7 +658,7 @@ __device__ __forceinline__ void factor_panel_structured(
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int kk = g * 4 + u;
-    if (kk <= j && j < kw) state[(int64_t)(k0 + kk) * n + k0 + j] = Rd[kk * TLD + j];
+    if (kk <= j && j < kw) state[(int64_t)(k0 + kk) * n + k0 + j] = rfin[u];
   }
 #pragma unroll
   for (int t = 0; t < RT; ++t) {
@@ -669,48 +671,60 @@ __device__ __forceinline__ void factor_panel_structured(
 }
 
 // ---------------------------------------------------------------------------
-// Rows i = wave, wave + nw, ... of the chunk (nw waves), LB rows per batch
-// with all their loads issued before any is consumed; optional row-mean
-// removal (Alg. 2).
+// chunk loads, with optional row-mean removal (Alg. 2)
+template <int LB, int NCOL, typename T, typename TI>
+__device__ __forceinline__ void load_rows(T* __restrict__ C, int ldc, int s, int sc, int n,
+                                          const TI* __restrict__ src, int64_t ld_src,
+                                          int remove_mean, double* __restrict__ mean_out,
+                                          int wave, int lane, int nw) {
+  for (int i0 = wave; i0 < s; i0 += nw * LB) {
+    TI x[LB][NCOL];
+#pragma unroll
+    for (int b = 0; b < LB; ++b) {
+      const int i = i0 + nw * b;
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) {
+        const int col = lane + 64 * c;
+        x[b][c] = (i < sc && col < n) ? src[(int64_t)i * ld_src + col] : TI(0);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < LB; ++b) {
+      const int i = i0 + nw * b;
+      if (i >= s) continue;
+      double mu = 0.0;
+      if (remove_mean && i < sc) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) acc += (double)x[b][c];
+        acc = wave_sum_fast(acc);
+        mu = acc / (double)n;
+        if (lane == 0 && mean_out) mean_out[i] = mu;
+      }
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) {
+        const int col = lane + 64 * c;
+        if (col < n) C[i * ldc + col] = (i < sc) ? (T)((double)x[b][c] - mu) : T(0);
+      }
+    }
+  }
+}
+
+// Rows i = wave, wave + nw, ... of the chunk (nw waves); each batch issues
+// all its loads before any is consumed: 16 rows per wave for rows of at most
+// 64 values (a 64-row chunk of four waves in one round trip), 4 rows of up
+// to 256 values otherwise.
 template <typename T, typename TI>
 __device__ __forceinline__ void load_chunk(T* __restrict__ C, int ldc, int s, int sc, int n,
                                            const TI* __restrict__ src, int64_t ld_src,
                                            int remove_mean, double* __restrict__ mean_out,
                                            int wave, int lane, int nw) {
-  constexpr int LB = 4;    // rows per batch and wave
-  constexpr int NCOL = 4;  // columns per lane and row held in registers (n <= 256)
-  if (n <= 64 * NCOL) {
-    for (int i0 = wave; i0 < s; i0 += nw * LB) {
-      TI x[LB][NCOL];
-#pragma unroll
-      for (int b = 0; b < LB; ++b) {
-        const int i = i0 + nw * b;
-#pragma unroll
-        for (int c = 0; c < NCOL; ++c) {
-          const int col = lane + 64 * c;
-          x[b][c] = (i < sc && col < n) ? src[(int64_t)i * ld_src + col] : TI(0);
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < LB; ++b) {
-        const int i = i0 + nw * b;
-        if (i >= s) continue;
-        double mu = 0.0;
-        if (remove_mean && i < sc) {
-          double acc = 0.0;
-#pragma unroll
-          for (int c = 0; c < NCOL; ++c) acc += (double)x[b][c];
-          acc = wave_sum_fast(acc);
-          mu = acc / (double)n;
-          if (lane == 0 && mean_out) mean_out[i] = mu;
-        }
-#pragma unroll
-        for (int c = 0; c < NCOL; ++c) {
-          const int col = lane + 64 * c;
-          if (col < n) C[i * ldc + col] = (i < sc) ? (T)((double)x[b][c] - mu) : T(0);
-        }
-      }
-    }
+  if (n <= 64) {
+    load_rows<16, 1, T, TI>(C, ldc, s, sc, n, src, ld_src, remove_mean, mean_out, wave, lane, nw);
+    return;
+  }
+  if (n <= 256) {
+    load_rows<4, 4, T, TI>(C, ldc, s, sc, n, src, ld_src, remove_mean, mean_out, wave, lane, nw);
     return;
   }
   for (int i = wave; i < s; i += nw) {
@@ -787,11 +801,13 @@ __device__ __forceinline__ void chunk_commit(const TI (&pfv)[N], T* __restrict__
 
 // Variants: VAR 0 fills the leaf state from the first chunks (stacked
 // leaves); VAR 3 does the same and prefetches small chunks (see pf below);
-// VAR 1 and 2 compile the filling path out (tree combines and column-blocked
-// panels never fill).  VAR 2 is register-limited to two waves per SIMD, so
-// that two workgroups share a CU, and the wave that factors the panels
-// rotates with the workgroup index, so that the panel waves of co-resident
-// workgroups sit on different SIMDs.
+// VAR 1, 2 and 4 compile the filling path out (tree combines and
+// column-blocked panels never fill).  VAR 2 is register-limited to two waves
+// per SIMD, so that two workgroups share a CU, and the wave that factors the
+// panels rotates with the workgroup index, so that the panel waves of
+// co-resident workgroups sit on different SIMDs.  VAR 4 is VAR 2 for grids
+// of at most one workgroup per CU: with one wave per SIMD it keeps its
+// overflow registers in AGPRs instead of scratch memory.
 // One leaf (a.mode 0, leaf bx) or one combine (a.mode 1, pair bx at level
 // a.h) of problem by, by the whole workgroup; smem is the dynamic LDS.
 template <typename T, typename TI, int RT, int VAR>
@@ -820,7 +836,7 @@ __device__ __forceinline__ void stacked_qr_task(QrArgs<T, TI> a, int64_t bx, int
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = (int)(blockDim.x >> 6);  // 4, or 1 for narrow problems
   // panel wave pw; wr = 0 for it, 1..3 for the trailing-tile waves
-  const int pw = (VAR == 2 && nw == 4) ? (int)(((bx >> 3) + (bx >> 8)) & 3) : 0;
+  const int pw = ((VAR == 2 || VAR == 4) && nw == 4) ? (int)(((bx >> 3) + (bx >> 8)) & 3) : 0;
   const int wr = (wave - pw) & 3;
   T* Gm = Yb + pw * NB * NB;  // the panel wave's Y tile doubles as its Gram scratch
   const bool leaf = (a.mode == 0);
@@ -926,8 +942,8 @@ __device__ __forceinline__ void stacked_qr_task(QrArgs<T, TI> a, int64_t bx, int
             factor_panel<T, RT, true>(C, ldc, Vcur, Tcur, state, n, k0, kw, f, lane, rd4, Rd, Gm,
                                       vb, taus);
           else
-            factor_panel_structured<T, RT>(C, ldc, Vcur, Tcur, state, n, k0, kw, lane, rd4, Rd,
-                                           Gm, vb, taus);
+            factor_panel_structured<T, RT>(C, ldc, Vcur, Tcur, state, n, k0, kw, lane, rd4, Gm,
+                                           vb);
           if (tout) {
             T* tp = tout + ((int64_t)c * npan + p) * (NB * NB);
 #pragma unroll
@@ -1400,9 +1416,30 @@ static hipError_t launch_qr_var(const QrArgs<T, TI>& a, int grid, size_t lds, hi
   }
 }
 
+// Compute units of the current device (cached per device).
+static int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  if (cus[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        v < 1) {
+      (void)hipGetLastError();
+      v = 256;
+    }
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
+
 // Leaves of the stacked path fill their state from the first chunks (VAR 0,
 // or VAR 3 with the small-chunk prefetch); tree combines never do (VAR 1);
-// column-blocked panels (VAR 2) run two workgroups per CU.
+// column-blocked panels run two workgroups per CU (VAR 2) unless the grid
+// has at most one per CU (VAR 4).
 template <typename T, typename TI>
 static hipError_t launch_qr_any(const QrArgs<T, TI>& a, int grid, size_t lds, hipStream_t st,
                                 int64_t gy = 1) {
@@ -1415,6 +1452,9 @@ static hipError_t launch_qr_any(const QrArgs<T, TI>& a, int grid, size_t lds, hi
     return launch_qr_var<T, TI, 0>(a, grid, lds, st, gy);
   }
   if (a.mode == 1) return launch_qr_var<T, TI, 1>(a, grid, lds, st, gy);
+  if constexpr (std::is_same<T, TI>::value) {
+    if ((int64_t)grid * gy <= device_cus()) return launch_qr_var<T, TI, 4>(a, grid, lds, st, gy);
+  }
   return launch_qr_var<T, TI, 2>(a, grid, lds, st, gy);
 }
 
@@ -1582,17 +1622,6 @@ hipError_t launch_queue_err_merge(const void* counters1, const void* counters2, 
                      (const int*)((const char*)counters1 + 64),
                      counters2 ? (const int*)((const char*)counters2 + 64) : nullptr, flag);
   return hipGetLastError();
-}
-
-static int device_cus() {
-  int dev = 0, ncu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      ncu < 1) {
-    (void)hipGetLastError();
-    return 256;
-  }
-  return ncu;
 }
 
 // Grid of a work-queue launch: every workgroup that can be resident at once
