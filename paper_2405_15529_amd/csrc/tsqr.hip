@@ -382,12 +382,13 @@ __device__ __forceinline__ void load_head4(T (&hd)[4], const T* __restrict__ sta
 // ---------------------------------------------------------------------------
 // one trailing tile: [head; C(:, col0:col0+16)] <- Q_p^T [head; C(...)]
 // ---------------------------------------------------------------------------
-template <typename T, int RT>
+// HEADREG: the head rows stay in registers (head is updated in place and
+// the state is not touched).
+template <typename T, int RT, bool HEADREG = false>
 __device__ __forceinline__ void tile_update(T* __restrict__ C, int ldc, const T* __restrict__ Vp,
                                             const T* __restrict__ Tm, T* __restrict__ Yw,
                                             T* __restrict__ state, int n, int k0, int kw,
-                                            bool internal, int col0, const T (&head)[4],
-                                            int lane) {
+                                            bool internal, int col0, T (&head)[4], int lane) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int S = 4 * RT;  // chunk rows
   const int i16 = lane & 15, g4 = lane >> 4;
@@ -428,7 +429,13 @@ __device__ __forceinline__ void tile_update(T* __restrict__ C, int ldc, const T*
     const int k = 4 * kb + g4;
     z = Mfma<T>::op(Tm[k * NB + i16], REG ? y[kb] : Yw[k * NB + i16], z);  // (T^T Y)
   }
-  if (!internal) {
+  if (HEADREG) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = Mfma<T>::drow(g4, q);
+      head[q] = (colok && i < kw) ? head[q] - z[q] : head[q];
+    }
+  } else if (!internal) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = Mfma<T>::drow(g4, q);
@@ -513,19 +520,19 @@ __device__ __forceinline__ T rsq_nr(T x) {
   return y;
 }
 
+// Core of the structured panel factorisation: p holds the tail rows g + 4t
+// of column j (lane 16 g + j) and rfin the head rows 4g .. 4g+3 (the
+// diagonal block of the state); on exit p, mysc and myscal give the
+// reflector tails v_j = (p mysc) myscal, rfin the R rows and Tm the T factor.
 template <typename T, int RT>
-__device__ __forceinline__ void factor_panel_structured(
-    T* __restrict__ C, int ldc, T* __restrict__ Vp, T* __restrict__ Tm, T* __restrict__ state,
-    int n, int k0, int kw, int lane, const T (&rd4)[4], T* __restrict__ Gm,
-    T* __restrict__ vb) {
+__device__ __forceinline__ void factor_core(T (&p)[RT], T& mysc, T& myscal, T (&rfin)[4],
+                                            T* __restrict__ Tm, int kw, int lane,
+                                            T* __restrict__ Gm, T* __restrict__ vb) {
   const int j = lane & 15, g = lane >> 4;
-  T p[RT];
-#pragma unroll
-  for (int t = 0; t < RT; ++t) p[t] = (j < kw) ? C[(g + 4 * t) * ldc + k0 + j] : T(0);
-  T mysc = T(1), myscal = T(0);  // v_j = (x_j * mysc) * myscal once column j is factored
-  T mytau = T(0);                 // tau_j, on the lanes of column j
-  // rows 4g .. 4g+3 of column j of the R block, updated in registers
-  T rfin[4] = {rd4[0], rd4[1], rd4[2], rd4[3]};
+  mysc = T(1);
+  myscal = T(0);
+  T mytau = T(0);  // tau_j, on the lanes of column j
+  const T rd0[4] = {rfin[0], rfin[1], rfin[2], rfin[3]};  // head rows at entry
   // Gram scratch S(i, k) = v_i^T v_k at Gm[i NB + k] for i < k < kw; every
   // other entry stays zero
 #pragma unroll
@@ -537,7 +544,7 @@ __device__ __forceinline__ void factor_panel_structured(
     for (int u = 0; u < 4; ++u) {
       const int kk = kb + u;
       if (kk >= kw) break;
-      const T rsel = rd4[u];  // head row kk, column j, on the owner lanes
+      const T rsel = rd0[u];  // head row kk, column j, on the owner lanes
       // column kk is final: broadcast it first, so that the LDS round trip
       // overlaps the norm
       if (j == kk) {
@@ -653,6 +660,23 @@ __device__ __forceinline__ void factor_panel_structured(
       Tm[(4 * g + u) * NB + j] = val;
     }
   }
+}
+
+// Structured panel of the stacked QR: columns k0 .. k0+kw-1 of the chunk C
+// under the state's diagonal block (prefetched in rd4).  On exit C and Vp
+// hold the exact reflectors, Tm the T factor, and the state its new rows.
+template <typename T, int RT>
+__device__ __forceinline__ void factor_panel_structured(
+    T* __restrict__ C, int ldc, T* __restrict__ Vp, T* __restrict__ Tm, T* __restrict__ state,
+    int n, int k0, int kw, int lane, const T (&rd4)[4], T* __restrict__ Gm,
+    T* __restrict__ vb) {
+  const int j = lane & 15, g = lane >> 4;
+  T p[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) p[t] = (j < kw) ? C[(g + 4 * t) * ldc + k0 + j] : T(0);
+  T mysc, myscal;
+  T rfin[4] = {rd4[0], rd4[1], rd4[2], rd4[3]};
+  factor_core<T, RT>(p, mysc, myscal, rfin, Tm, kw, lane, Gm, vb);
   // the state diagonal block (R rows of this panel), then C and the exact
   // reflectors (structured: the chunk rows of column j hold v_j)
 #pragma unroll
@@ -996,6 +1020,167 @@ __attribute__((amdgpu_waves_per_eu(VAR == 2 ? 2 : 1, VAR == 2 ? 2 : 1)))
 void k_stacked_qr(QrArgs<T, TI> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   stacked_qr_task<T, TI, RT, VAR>(a, blockIdx.x, blockIdx.y, smem);
+}
+
+// ---------------------------------------------------------------------------
+// wavefront panel QR (column-blocked panels of 2 to 4 sub-panels)
+// ---------------------------------------------------------------------------
+// Panel p of chunk c needs only panel p-1 of the same chunk (it updates the
+// chunk's columns of panel p) and panel p of chunk c-1 (the head rows of
+// the state that chunk left).  Wave w owns the 16-column stripe w of every
+// chunk and, at step tau, works on chunk tau - w: it applies the reflectors
+// of panels 0 .. w-1 of that chunk, read back from the tails and T factors
+// their waves stored in global memory at earlier steps, and factors its own
+// panel.  The factorisations of the panels thus run concurrently on the
+// four waves, and a step is bounded by wave 3 (three tile updates and one
+// panel) instead of the four panels in sequence.
+// LDS: stripe w keeps w + 1 chunk slots (the chunks committed to it but not
+// yet factored), 64 x 17 each; per wave a staging tile for the V and T
+// read back, and its panel scratch.  The head rows of the state stay in the
+// owning wave's registers for the whole leaf.  The next chunk is prefetched
+// into registers one step ahead and committed after the step's barrier.
+// Outputs are those of the stacked QR's column-blocked mode: reflector
+// tails in place of the chunk rows, one T factor per 64-row chunk and
+// sub-panel, and the panel's state rows.
+constexpr int kWfS = 64;  // chunk rows (the trailing update applies per 64-row chunk)
+
+template <typename T>
+__device__ __forceinline__ T* wf_stripe(T* lds, int s, int64_t c) {
+  // stripe s owns slots s(s+1)/2 .. s(s+1)/2 + s
+  return lds + (size_t)((s * (s + 1)) / 2 + (int)(c % (s + 1))) * (kWfS * VPLD);
+}
+
+static size_t wf_lds_bytes(int esize) {
+  return (size_t)(10 * kWfS * VPLD + 4 * (kWfS * VPLD + 3 * NB * NB + kWfS)) * esize;
+}
+
+// Prefetched chunk (element e = tid + 256 t: row e / n, column e % n) into
+// the stripe slots of chunk c.
+template <typename T, int N>
+__device__ __forceinline__ void wf_commit(const T (&pfv)[N], T* lds, int64_t c, int n, int tid) {
+  int i = tid / n, col = tid - (tid / n) * n;
+  const int di = 256 / n, dj = 256 - (256 / n) * n;
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    if (tid + t * 256 < kWfS * n) wf_stripe(lds, col >> 4, c)[i * VPLD + (col & 15)] = pfv[t];
+    col += dj;
+    i += di;
+    if (col >= n) {
+      col -= n;
+      ++i;
+    }
+  }
+}
+
+template <typename T, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void k_panel_wf(QrArgs<T, T> a) {
+  constexpr int S = kWfS, RT = S / 4, SL = S * VPLD, PF = S * 64 / 256;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  const int n = a.n, npan = a.npanels;
+  const int64_t jl = blockIdx.x;
+  const int64_t row0 = jl * a.b;
+  int64_t rows = (jl == a.P - 1) ? (a.m - row0) : a.b;
+  if (a.rows_lim > 0 && rows > a.rows_lim) rows = a.rows_lim;
+  const T* src = a.D + row0 * a.ldd;
+  const int64_t ldv = a.ldv > 0 ? a.ldv : n;
+  T* vout = a.V + row0 * ldv;
+  T* state = a.Rbuf + jl * (int64_t)n * n;
+  T* tout = a.Tleaf + jl * a.nch_leaf * npan * (NB * NB);
+  const int nch = (int)((rows + S - 1) / S);
+  T* Vst = lds + 10 * SL + (size_t)w * (SL + 3 * NB * NB + S);
+  T* Tst = Vst + SL;
+  T* Gm = Tst + NB * NB;
+  T* Yw = Gm + NB * NB;
+  T* vb = Yw + NB * NB;
+  const bool act = w < npan;
+  const int k0 = NB * w;
+  const int kw = act ? ((n - k0 < NB) ? n - k0 : NB) : 0;
+  T rd4[4] = {T(0), T(0), T(0), T(0)};  // diagonal block of stripe w (factor layout)
+  T hd[3][4];                           // head rows of panels 0 .. w-1 in stripe w (MFMA layout)
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hd[p][q] = T(0);
+  if (a.state_mode == 1) {
+    for (int idx = tid; idx < n * n; idx += 256) state[idx] = T(0);
+  } else if (act) {
+    load_diag4<T>(rd4, state, n, k0, lane);
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      if (p < w) load_head4<T>(hd[p], state, n, NB * p, NB, k0, lane);
+  }
+  T pf[PF];
+  chunk_prefetch<T, PF>(pf, src, a.ldd, 0, rows, S, n, tid, 256);
+  wf_commit<T, PF>(pf, lds, 0, n, tid);
+  if (nch > 1) chunk_prefetch<T, PF>(pf, src, a.ldd, 1, rows, S, n, tid, 256);
+  __syncthreads();
+  const int nsteps = nch + npan - 1;
+  for (int tau = 0; tau < nsteps; ++tau) {
+    const int c = tau - w;
+    if (act && c >= 0 && c < nch) {
+      const int64_t r0 = (int64_t)c * S;
+      const int sc = (int)((rows - r0) < S ? (rows - r0) : S);
+      T* st = wf_stripe(lds, w, c);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        if (p < w) {
+          // V and T of panel p of this chunk (stored by wave p at step c + p)
+          const T* vs = vout + r0 * ldv + NB * p;
+          for (int e = lane; e < S * NB; e += 64) {
+            const int r = e >> 4, jj = e & 15;
+            Vst[r * VPLD + jj] = (r < sc) ? vs[r * ldv + jj] : T(0);
+          }
+          const T* ts = tout + ((int64_t)c * npan + p) * (NB * NB);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) Tst[lane + 64 * e] = ts[lane + 64 * e];
+          wave_lds_sync();
+          tile_update<T, RT, true>(st, VPLD, Vst, Tst, Yw, nullptr, n - k0, 0, NB, false, 0,
+                                   hd[p], lane);
+        }
+      }
+      T pv[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) pv[t] = (j < kw) ? st[(g + 4 * t) * VPLD + j] : T(0);
+      T mysc, myscal;
+      factor_core<T, RT>(pv, mysc, myscal, rd4, Tst, kw, lane, Gm, vb);
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int r = g + 4 * t;
+        if (j < kw && r < sc) vout[(r0 + r) * ldv + k0 + j] = (pv[t] * mysc) * myscal;
+      }
+      wave_lds_sync();
+      T* tp = tout + ((int64_t)c * npan + w) * (NB * NB);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tp[lane + 64 * e] = Tst[lane + 64 * e];
+    }
+    __syncthreads();
+    if (tau + 1 < nch) {
+      wf_commit<T, PF>(pf, lds, tau + 1, n, tid);
+      if (tau + 2 < nch) chunk_prefetch<T, PF>(pf, src, a.ldd, tau + 2, rows, S, n, tid, 256);
+    }
+    __syncthreads();
+  }
+  if (act) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = 4 * g + u;
+      if (kk <= j && j < kw) state[(int64_t)(k0 + kk) * n + k0 + j] = rd4[u];
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      if (p < w) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = Mfma<T>::drow(g, q);
+          if (k0 + j < n) state[(int64_t)(NB * p + i) * n + k0 + j] = hd[p][q];
+        }
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1529,6 +1714,19 @@ hipError_t launch_panel_qr(const QrGeom& g, T* Wk, int64_t ldw, int64_t m, int64
   a.state_mode = state_mode; a.ldv = ldw; a.rows_lim = rows_lim;
   if (state_mode != 1 && state_mode != 2) return hipErrorInvalidValue;
   if (P > 0x7fffffff) return hipErrorInvalidValue;
+  if (P > 0 && g.s == kWfS && g.n <= 4 * NB && g.npanels >= 2 && (g.nthr == 0 || g.nthr == 256)) {
+    // wavefront form; FP32 fits two workgroups per CU in LDS and registers
+    const size_t lds = wf_lds_bytes((int)sizeof(T));
+    const bool two = sizeof(T) == 4 && P > device_cus();
+    const void* fn = two ? (const void*)k_panel_wf<T, 2> : (const void*)k_panel_wf<T, 1>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (two)
+      hipLaunchKernelGGL((k_panel_wf<T, 2>), dim3((unsigned)P), dim3(256), lds, st, a);
+    else
+      hipLaunchKernelGGL((k_panel_wf<T, 1>), dim3((unsigned)P), dim3(256), lds, st, a);
+    return hipGetLastError();
+  }
   return launch_qr_any(a, (int)P, qr_lds_bytes(g, (int)sizeof(T)), st);
 }
 template hipError_t launch_panel_qr<double>(const QrGeom&, double*, int64_t, int64_t, int64_t,
