@@ -1128,15 +1128,25 @@ void k_panel_wf(QrArgs<T, T> a) {
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
         if (p < w) {
-          // V and T of panel p of this chunk (stored by wave p at step c + p)
+          // V and T of panel p of this chunk (stored by wave p at step c + p):
+          // every load is issued before the first is stored to LDS
           const T* vs = vout + r0 * ldv + NB * p;
-          for (int e = lane; e < S * NB; e += 64) {
-            const int r = e >> 4, jj = e & 15;
-            Vst[r * VPLD + jj] = (r < sc) ? vs[r * ldv + jj] : T(0);
-          }
           const T* ts = tout + ((int64_t)c * npan + p) * (NB * NB);
+          T vv[S * NB / 64], tt[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) Tst[lane + 64 * e] = ts[lane + 64 * e];
+          for (int e = 0; e < S * NB / 64; ++e) {
+            const int idx = lane + 64 * e, r = idx >> 4;
+            vv[e] = (r < sc) ? vs[r * ldv + (idx & 15)] : T(0);
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) tt[e] = ts[lane + 64 * e];
+#pragma unroll
+          for (int e = 0; e < S * NB / 64; ++e) {
+            const int idx = lane + 64 * e;
+            Vst[(idx >> 4) * VPLD + (idx & 15)] = vv[e];
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) Tst[lane + 64 * e] = tt[e];
           wave_lds_sync();
           tile_update<T, RT, true>(st, VPLD, Vst, Tst, Yw, nullptr, n - k0, 0, NB, false, 0,
                                    hd[p], lane);
