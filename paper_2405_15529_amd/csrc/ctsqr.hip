@@ -417,9 +417,25 @@ __global__ __launch_bounds__(64, 2) void k_cleaf_apply(int64_t m, int64_t P,
   const int64_t node = f * P + leaf;
   const zd* C = Cn + node * kNodeZ;
   const zd* W = Wl + node * kNodeZ;
-  for (int e = lane; e < NB * NB; e += 64) {
-    Cl[(e / NB) * kLd + e % NB] = C[(e / NB) * 16 + e % NB];
-    Wm[(e / NB) * kLd + e % NB] = W[(e / NB) * 16 + e % NB];
+  {
+    // every load issued before the first store
+    constexpr int NE = (NB * NB + 63) / 64;
+    zd cv[NE], wv[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = lane + 64 * i;
+      const bool ok = e < NB * NB;
+      cv[i] = ok ? C[(e / NB) * 16 + e % NB] : zd{0.0, 0.0};
+      wv[i] = ok ? W[(e / NB) * 16 + e % NB] : zd{0.0, 0.0};
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = lane + 64 * i;
+      if (e < NB * NB) {
+        Cl[(e / NB) * kLd + e % NB] = cv[i];
+        Wm[(e / NB) * kLd + e % NB] = wv[i];
+      }
+    }
   }
   const TT* V = reinterpret_cast<const TT*>(Vl) + node * NB * kLeafRows;
   TT a[2][NB];

@@ -203,6 +203,9 @@ __global__ __launch_bounds__(256, 3) void k_spod_fft(int64_t m, int64_t nt, cons
     if constexpr (VEC) {
       const float4* r4 = reinterpret_cast<const float4*>(row);
       const int64_t nt4 = nt / 4;
+      // unrolled so that several loads are in flight; the sum order is the
+      // loop order either way
+#pragma unroll 4
       for (int64_t t = q; t < nt4; t += G) {
         const float4 v = r4[t];
         acc += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);

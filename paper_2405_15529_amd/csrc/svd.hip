@@ -619,10 +619,18 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
       if (tid == 0) step_rot = 0;
       {
         const double* gp0 = a.gp + (int64_t)g * ks * (3 * 256);
-        double m[3] = {0.0, 0.0, 0.0};
-        for (int k = 0; k < ks; ++k)
+        // the ks <= 4 partial Gram matrices, all loads issued before the
+        // sums (in the fixed order k = 0, 1, ...)
+        double pv[4][3];
 #pragma unroll
-          for (int t = 0; t < 3; ++t) m[t] += gp0[k * (3 * 256) + t * 256 + tid];
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int t = 0; t < 3; ++t) pv[k][t] = (k < ks) ? gp0[k * (3 * 256) + t * 256 + tid] : 0.0;
+        double m[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int t = 0; t < 3; ++t) m[t] = (k < ks) ? m[t] + pv[k][t] : m[t];
         const int i = tid >> 4, j = tid & 15;
         Ms[i * LD + j] = m[0];
         Ms[i * LD + 16 + j] = m[1];
