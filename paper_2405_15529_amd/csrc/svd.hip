@@ -742,21 +742,27 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
           const int cl = 4 * s4 + g4;
           coff[s4] = (int64_t)((cl < 16 ? bI : bJ) * BJB + (cl & 15)) * n;
         }
-        // up to TMX tiles of the wave are loaded before any product (one
-        // memory round trip per buffer instead of one per tile)
+        // up to TMX tiles of the wave are loaded from both buffers before any
+        // product or store: one memory round trip for the step, and no wait
+        // for loads issued after stores (a single counter tracks both, in
+        // issue order)
         constexpr int TMX = 8;
+        for (int base = t0 + wave; base < t1; base += 4 * TMX) {
+          double xv[2][TMX][8];
 #pragma unroll
-        for (int buf = 0; buf < 2; ++buf) {
-          double* X = buf ? a.V : a.A;
-          for (int base = t0 + wave; base < t1; base += 4 * TMX) {
-            double xv[TMX][8];
+          for (int buf = 0; buf < 2; ++buf) {
+            const double* X = buf ? a.V : a.A;
 #pragma unroll
             for (int jt = 0; jt < TMX; ++jt) {
               const int tl = base + 4 * jt, rr = 16 * tl + i16;
               const bool ok = tl < t1 && rr < n;
 #pragma unroll
-              for (int s4 = 0; s4 < 8; ++s4) xv[jt][s4] = ok ? X[coff[s4] + rr] : 0.0;
+              for (int s4 = 0; s4 < 8; ++s4) xv[buf][jt][s4] = ok ? X[coff[s4] + rr] : 0.0;
             }
+          }
+#pragma unroll
+          for (int buf = 0; buf < 2; ++buf) {
+            double* X = buf ? a.V : a.A;
 #pragma unroll
             for (int jt = 0; jt < TMX; ++jt) {
               const int tl = base + 4 * jt;
@@ -764,8 +770,8 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
                 v4 o0 = vzero4<double>(), o1 = vzero4<double>();
 #pragma unroll
                 for (int s4 = 0; s4 < 8; ++s4) {
-                  o0 = Mfma<double>::op(xv[jt][s4], wb[0][s4], o0);
-                  o1 = Mfma<double>::op(xv[jt][s4], wb[1][s4], o1);
+                  o0 = Mfma<double>::op(xv[buf][jt][s4], wb[0][s4], o0);
+                  o1 = Mfma<double>::op(xv[buf][jt][s4], wb[1][s4], o1);
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
