@@ -206,9 +206,9 @@ TRAFFIC = {
     # FP64 stacked leaf QR, 1048576 x 256, row blocks 4096 (one launch)
     "stacked_leaf_fp64": {
         "sources": ("tsqr.hip", "common.hpp"),
-        "sources_sha256": "0623733ccd8603f060147c06517f02aa27e381df97a66cca21b98b788aab9a20",
+        "sources_sha256": "9033f1e05e62c6c9dfb3e35820b975f259e7b4b555d5f402f92fb32ddcc9b493",
         "shape": (1048576, 256, 4096),
-        "bytes": 13614639179,  # FETCH 6.575e+09 (x1.99994) + WRITE 7.04e+09 (x1.0)
+        "bytes": 13615113691,  # FETCH 6.575e+09 (x1.99992) + WRITE 7.040e+09 (x1.0)
     },
     # FP32 leaf trailing updates of the column-blocked QR, 4194304 x 1808, row
     # blocks 8192: mean over the 28 launches of one mixed call
