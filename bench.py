@@ -206,7 +206,7 @@ TRAFFIC = {
     # FP64 stacked leaf QR, 1048576 x 256, row blocks 4096 (one launch)
     "stacked_leaf_fp64": {
         "sources": ("tsqr.hip", "common.hpp"),
-        "sources_sha256": "9033f1e05e62c6c9dfb3e35820b975f259e7b4b555d5f402f92fb32ddcc9b493",
+        "sources_sha256": "0b49fd0300209348e07114a140783bae57365fd1073257084b0a0f828fcb92c1",
         "shape": (1048576, 256, 4096),
         "bytes": 13615113691,  # FETCH 6.575e+09 (x1.99992) + WRITE 7.040e+09 (x1.0)
     },

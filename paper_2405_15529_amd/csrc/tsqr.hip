@@ -1025,9 +1025,9 @@ void k_stacked_qr(QrArgs<T, TI> a) {
 // ---------------------------------------------------------------------------
 // wavefront panel QR (column-blocked panels of 2 to 4 sub-panels)
 // ---------------------------------------------------------------------------
-// Panel p of chunk c needs only panel p-1 of the same chunk (it updates the
-// chunk's columns of panel p) and panel p of chunk c-1 (the head rows of
-// the state that chunk left).  Wave w owns the 16-column stripe w of every
+// Sub-panel p of chunk c needs the reflectors of sub-panels 0 .. p-1 of the
+// same chunk (they update its columns) and sub-panel p of chunk c-1 (the
+// head rows of the state that chunk left), nothing else.  Wave w owns the 16-column stripe w of every
 // chunk and, at step tau, works on chunk tau - w: it applies the reflectors
 // of panels 0 .. w-1 of that chunk, read back from the tails and T factors
 // their waves stored in global memory at earlier steps, and factors its own
