@@ -71,8 +71,10 @@ typedef enum {
 /* ---- compute precision ---- */
 typedef enum {
   PYLOM_FP64 = 0,  /* every step in FP64 (FP32 inputs promoted on load)      */
-  PYLOM_MIXED = 1  /* FP32 leaf QR, FP64 tree + small SVD, FP64 Rayleigh-Ritz
-                      refinement against the input (R32 storage only) */
+  PYLOM_MIXED = 1  /* FP32 leaf QR, FP64 final tree combine + small SVD
+                      (lower tree levels: see "mixed_tree"), FP64
+                      Rayleigh-Ritz refinement against the input (R32
+                      storage only) */
 } pylom_prec;
 
 typedef struct pylom_ctx_s* pylom_ctx;
@@ -127,6 +129,13 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
  *                  working copy of D, the reflectors of every panel and the
  *                  tree pairs stay in the workspace.  The stacked QR factors
  *                  at most 1024 columns.
+ *   "mixed_tree"   1 (default): a PYLOM_MIXED call on the column-blocked
+ *                  path combines the FP32 leaf R factors in FP32 on every
+ *                  tree level below the last one (Alg. 1 reduce); the final
+ *                  combine, the root R and its SVD run in FP64.  0: the whole
+ *                  tree in FP64.  The Rayleigh-Ritz refinement against D
+ *                  sets the accuracy of the result either way.  The stacked
+ *                  path always combines in FP64.
  * Read-only (pylom_get_option):
  *   "batch_jacobi_chained"  1 if the last pylom_pod_batched call ordered its
  *                  multi-workgroup Jacobi launches one after another across
@@ -165,7 +174,8 @@ const char* pylom_last_error(pylom_ctx ctx);
  * exactly zero singular value of an exactly rank-deficient panel may come out
  * as zero columns of U).
  * PYLOM_MIXED (D must be R32): FP32 leaf QR without reflector storage, FP64
- * tree and SVD of R, then a Rayleigh-Ritz refinement against D in FP64 on the
+ * tree (below its final combine FP32 on the column-blocked path, see
+ * "mixed_tree") and SVD of R, then a Rayleigh-Ritz refinement against D in FP64 on the
  * k = min(n, N0 + max(8, N0/4)) leading right singular vectors V_k of that SVD
  * (N0 = its truncation): Z = (D - mean 1^T) V_k, the Jacobi eigenpairs
  * (lambda, w) of Z^T Z give S[i] = sqrt(lambda_i) (i < k; S[i] for i >= k is

@@ -38,6 +38,7 @@ struct pylom_ctx_s {
   int64_t ws_cap_mb = 0;
   int64_t blocked_from = 0;  // n at which the column-blocked TSQR takes over (0: automatic)
   int64_t narrow_leaves = 1;  // single-wave 32-row leaves for narrow problems with many leaves
+  int64_t mixed_tree = 1;     // mixed column-blocked tree: 1 = FP32 below the final combine
   int* status_dev = nullptr;  // Jacobi status pairs (sweeps, barrier timeout) of the last call
   int status_valid = 0;
   int status_pairs = 1;        // 2 after a mixed-precision call (SVD of R + Gram eigen)
@@ -304,6 +305,9 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
     if (v != 0 && (v < 2 || v > kMaxN + 1))
       return fail(c, PYLOM_EINVAL, "blocked_from must be 0 or in [2, 2049]");
     c->blocked_from = v;  // part of every batch graph key
+  } else if (!std::strcmp(key, "mixed_tree")) {
+    if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "mixed_tree must be 0 or 1");
+    c->mixed_tree = v;  // part of every batch graph key
   } else if (!std::strcmp(key, "streams")) {
     if (v < 1 || v > 16) return fail(c, PYLOM_EINVAL, "streams must be in [1, 16]");
     c->streams = v;
@@ -354,6 +358,8 @@ extern "C" int pylom_get_option(pylom_ctx c, const char* key, int64_t* v) {
     *v = c->blocked_from;
   else if (!std::strcmp(key, "narrow_leaves"))
     *v = c->narrow_leaves;
+  else if (!std::strcmp(key, "mixed_tree"))
+    *v = c->mixed_tree;
   else if (!std::strcmp(key, "timing"))
     *v = c->timing;
   else if (!std::strcmp(key, "streams"))
@@ -532,11 +538,9 @@ static int64_t blocked_block_rows(int64_t m, int64_t n, int ncu) {
 // on one MI355X: the column-blocked TSQR was 1.1-2x faster for 64 <= n <= 1024
 // at up to 4M rows and 2.4x faster at 1.8e7 x 630, while the stacked QR was
 // faster at 3.6e7 x 160 (many short leaves keep every CU busy and its
-// workspace is smaller).  Batched instances stay on the stacked QR up to
-// n = 1024, the widest it factors.
-static bool use_blocked(const pylom_ctx_s* c, int64_t m, int64_t n, bool batched = false) {
+// workspace is smaller).  Instances of a batch follow the same rule.
+static bool use_blocked(const pylom_ctx_s* c, int64_t m, int64_t n) {
   if (c->blocked_from > 0) return n >= c->blocked_from;
-  if (batched) return n > 1024;
   return n >= 512 || (n >= 64 && m <= ((int64_t)8 << 20));
 }
 
@@ -567,7 +571,7 @@ static int64_t tune_lookup(const pylom_ctx_s* c, bool blocked, bool mixed, int64
 }
 
 static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
-                     bool mixed = false, bool batched = false) {
+                     bool mixed = false) {
   if (n < 1 || m < n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
   if (n > kMaxN) return fail(c, PYLOM_ENOTSUP, "n > 2048 is not supported");
   p->mixed = mixed;
@@ -576,7 +580,7 @@ static int make_plan(pylom_ctx c, int64_t m, int64_t n, bool store_q, Plan* p,
   if (mixed) store_q = false;
   p->m = m;
   p->n = n;
-  if (use_blocked(c, m, n, batched)) return make_blocked_plan(c, p, mixed);
+  if (use_blocked(c, m, n)) return make_blocked_plan(c, p, mixed);
   int64_t b = c->block_rows;
   if (b <= 0) b = tune_lookup(c, false, mixed, m, n);
   if (b <= 0) b = tune_block_rows(c, m, n, mixed);
@@ -1024,43 +1028,48 @@ static int blocked_leaves(pylom_ctx c, hipStream_t st, const Plan& p, char* ws, 
   return PYLOM_OK;
 }
 
-// The reduction tree of Alg. 1 in FP64 on the leaf R's (ws + oR), in place:
-// at level h, pair q combines R_j (j = 2hq, the state) with R_{j+h} (the
+// The reduction tree of Alg. 1 on the leaf R's at R (the FP64 ones at
+// ws + oR, or FP32 ones), in place, over the levels h_lo <= h < h_hi: at
+// level h, pair q combines R_j (j = 2hq, the state) with R_{j+h} (the
 // chunks, rows 0..c0+kw at panel k); R_j becomes the combined R, R_{j+h}
-// keeps the reflector tails.
-static int blocked_tree(pylom_ctx c, hipStream_t st, const Plan& p, char* ws) {
+// keeps the reflector tails.  The T factors and panel states of each level
+// keep their own slots (the propagation reads them), whatever the range.
+template <typename T>
+static int blocked_tree(pylom_ctx c, hipStream_t st, const Plan& p, char* ws, T* R,
+                        int64_t h_lo = 1, int64_t h_hi = -1) {
   const int64_t n = p.n;
-  double* R = (double*)(ws + p.oR);
+  if (h_hi < 0) h_hi = p.P;
   const size_t tps = t_slot(p, true), pps = ps_slot(p, true);
   int64_t base = 0;
-  for (int64_t h = 1; h < p.P; h *= 2) {
+  for (int64_t h = 1; h < h_lo; h *= 2) base += level_pairs(p.P, h);
+  for (int64_t h = h_lo; h < p.P && h < h_hi; h *= 2) {
     const int64_t np = level_pairs(p.P, h);
-    const int64_t rs = 2 * h * n * n;      // pair stride (elements)
-    double* Rb = R + h * n * n;            // R_{j+h} of pair 0, as rows of stride n
-    double* Tb = (double*)(ws + p.oTp) + base * p.nch_p * 4 * kTF;
-    double* PSb = (double*)(ws + p.oPSp) + base * kPW * kPW;
+    const int64_t rs = 2 * h * n * n;  // pair stride (elements)
+    T* Rb = R + h * n * n;             // R_{j+h} of pair 0, as rows of stride n
+    T* Tb = (T*)(ws + p.oTp) + base * p.nch_p * 4 * kTF;
+    T* PSb = (T*)(ws + p.oPSp) + base * kPW * kPW;
     for (int64_t k = 0; k < p.K; ++k) {
       const int64_t c0 = k * kPW;
       const int kw = (int)((n - c0 < kPW) ? n - c0 : kPW);
       const QrGeom& g = (k == p.K - 1) ? p.gpl : p.gp;
       const int64_t rows_lim = c0 + kw;
-      double* Tk = Tb + k * tps;
-      double* PSk = PSb + k * pps;
-      KT(KR_TREE_PANEL, launch_diag_load((int)n, c0, kw, np, R, rs, PSk, st), "pair state");
-      KT(KR_TREE_PANEL, launch_panel_qr<double>(g, Rb + c0, n, np * 2 * h * n, 2 * h * n, np,
-                                                rows_lim, Tk, p.nch_p, PSk, 2, st),
+      T* Tk = Tb + k * tps;
+      T* PSk = PSb + k * pps;
+      KT(KR_TREE_PANEL, launch_diag_load<T>((int)n, c0, kw, np, R, rs, PSk, st), "pair state");
+      KT(KR_TREE_PANEL, launch_panel_qr<T>(g, Rb + c0, n, np * 2 * h * n, 2 * h * n, np,
+                                           rows_lim, Tk, p.nch_p, PSk, 2, st),
          "pair panel QR");
       if (c0 + kw < n) {
-        PanelApplyArgs<double> a{};
+        PanelApplyArgs<T> a{};
         a.kw = kw; a.npan = g.npanels; a.nlv = np; a.b = 2 * h * n; a.m = np * 2 * h * n;
         a.rows_lim = rows_lim; a.V = Rb + c0; a.ldv = n; a.Tf = Tk; a.nch = p.nch_p;
         a.X = Rb + c0 + kw; a.ldx = n; a.ncols = n - c0 - kw; a.nc_dev = nullptr; a.nc_off = 0;
         a.x_zero = 0; a.S = R + c0 * n + c0 + kw; a.s_leaf = rs; a.s_ld = n;
         a.load_state = 1; a.store_state = 1; a.leaf_major = 0;
-        KT(KR_TREE_TRAIL, launch_panel_apply<double>(a, false, st), "pair trailing update");
+        KT(KR_TREE_TRAIL, launch_panel_apply<T>(a, false, st), "pair trailing update");
       }
     }
-    KT(KR_TREE_PANEL, launch_assemble_r<double>((int)n, np, PSb, (int64_t)pps, R, rs, st),
+    KT(KR_TREE_PANEL, launch_assemble_r<T>((int)n, np, PSb, (int64_t)pps, R, rs, st),
        "R assembly");
     base += np;
   }
@@ -1150,7 +1159,7 @@ static int enqueue_fp64_blocked(pylom_ctx c, const Exec& x, const Plan& p, pylom
   int rc = blocked_leaves<double>(c, st, p, x.ws, Rbuf);
   if (rc) return rc;
   EVREC(2);
-  rc = blocked_tree(c, st, p, x.ws);
+  rc = blocked_tree<double>(c, st, p, x.ws, Rbuf);
   if (rc) return rc;
   EVREC(3);
   JAC_BEFORE(p.jp);
@@ -1177,12 +1186,28 @@ static int enqueue_mixed1_blocked(pylom_ctx c, const Exec& x, const Plan& p, con
   KT(KR_WORK, launch_make_work(0, 0, m, (int)n, D, ldd, remove_mean, keep_mean(x, p),
                                x.ws + p.oWk, st), "working copy (FP32)");
   EVREC(1);
-  int rc = blocked_leaves<float>(c, st, p, x.ws, (float*)(x.ws + p.oR32));
+  float* R32 = (float*)(x.ws + p.oR32);
+  double* R64 = (double*)(x.ws + p.oR);
+  int rc = blocked_leaves<float>(c, st, p, x.ws, R32);
   if (rc) return rc;
-  KT(KR_LEAF_PANEL, launch_cast_f32_f64((const float*)(x.ws + p.oR32), (double*)(x.ws + p.oR),
-                                        p.P * n * n, st), "R to FP64");
-  EVREC(2);
-  rc = blocked_tree(c, st, p, x.ws);
+  // tree: every level below the top in FP32 (option mixed_tree = 1) or none;
+  // the final combine, the root R and its SVD in FP64
+  int64_t top = 1;
+  while (top * 2 < p.P) top *= 2;
+  const int64_t h64 = (c->mixed_tree == 1 && p.P > 1) ? top : 1;
+  if (h64 > 1) {
+    EVREC(2);
+    rc = blocked_tree<float>(c, st, p, x.ws, R32, 1, h64);
+    if (rc) return rc;
+    // the two operands of the final combine (R_0 and R_top)
+    KT(KR_TREE_PANEL, launch_cast_f32_f64(R32, R64, n * n, st), "R to FP64");
+    KT(KR_TREE_PANEL, launch_cast_f32_f64(R32 + h64 * n * n, R64 + h64 * n * n, n * n, st),
+       "R to FP64");
+  } else {
+    KT(KR_LEAF_PANEL, launch_cast_f32_f64(R32, R64, p.P * n * n, st), "R to FP64");
+    EVREC(2);
+  }
+  rc = blocked_tree<double>(c, st, p, x.ws, R64, h64);
   if (rc) return rc;
   EVREC(3);
   JAC_BEFORE(p.jp);
@@ -1700,10 +1725,8 @@ extern "C" int pylom_pod_batched(pylom_ctx c, pylom_dtype dtype, pylom_prec prec
     if (q.n < 1 || q.m < q.n) return fail(c, PYLOM_ESHAPE, "need m >= n >= 1");
     if (q.ldd < q.n || q.ldu < q.n || q.ldvt < q.n)
       return fail(c, PYLOM_ESHAPE, "leading dimension < n");
-    rc = make_plan(c, q.m, q.n, !mixed, &L.plans[(size_t)i], mixed, true);
+    rc = make_plan(c, q.m, q.n, !mixed, &L.plans[(size_t)i], mixed);
     if (rc) return rc;
-    if (L.plans[(size_t)i].blocked)
-      return fail(c, PYLOM_ENOTSUP, "batched problems need n below the blocked_from option");
     cost[(size_t)i] = leaf_model(c, q.m, q.n, L.plans[(size_t)i].b, mixed);
   }
   if (count == 0) return PYLOM_OK;
@@ -1781,9 +1804,10 @@ extern "C" int pylom_pod_batched(pylom_ctx c, pylom_dtype dtype, pylom_prec prec
   // (never the raw descriptor bytes, whose padding a C caller may leave
   // uninitialised)
   uint64_t key = 1469598103934665603ull;
-  const int64_t hdr[9] = {(int64_t)dtype, (int64_t)prec, count,           L.K,
-                          c->max_sweeps,  c->block_rows, c->narrow_leaves, c->blocked_from,
-                          L.jac_chain ? 1 : 0};
+  const int64_t hdr[10] = {(int64_t)dtype,   (int64_t)prec,   count,
+                           L.K,             c->max_sweeps,   c->block_rows,
+                           c->narrow_leaves, c->blocked_from, c->mixed_tree,
+                           L.jac_chain ? 1 : 0};
   key = fnv1a(key, hdr, sizeof(hdr));
   const void* wsp = c->ws;
   key = fnv1a(key, &wsp, sizeof(wsp));
@@ -1854,7 +1878,7 @@ extern "C" int pylom_tsqr(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64
            "working copy");
     rc = blocked_leaves<double>(c, st, p, ws, Rbuf);
     if (rc) return rc;
-    rc = blocked_tree(c, st, p, ws);
+    rc = blocked_tree<double>(c, st, p, ws, (double*)(ws + p.oR));
     if (rc) return rc;
     HIPCHK(c, launch_r_out(Rbuf, n, R, ldr, signs, st), "R out");
     if (wq) {
@@ -2066,7 +2090,7 @@ extern "C" int pylom_dmd(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, c
            "working copy");
     rc = blocked_leaves<double>(c, st, p, ws, Rbuf);
     if (rc) return rc;
-    rc = blocked_tree(c, st, p, ws);
+    rc = blocked_tree<double>(c, st, p, ws, (double*)(ws + p.oR));
     if (rc) return rc;
   } else {
     HIPCHK(c, launch_leaf_qr_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws, nullptr,
@@ -2417,7 +2441,7 @@ extern "C" int pylom_pod_host(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, i
     if ((rc = factor(w, k))) return rc;
   }
   // the tree, the SVD of the root R with truncation, the down-tree propagation
-  rc = blocked_tree(c, st, p, ws);
+  rc = blocked_tree<double>(c, st, p, ws, (double*)(ws + p.oR));
   if (rc) return rc;
   double* Sd = (double*)(ws + L.oS);
   double* VTd = (double*)(ws + L.oVT);

@@ -374,15 +374,16 @@ __global__ __launch_bounds__(256) void k_make_work_v(int64_t m, int n, const TI*
 
 // Diagonal block (c0, c0) of R_j, j = 2 h q (R_j at R + q rstride), into
 // the panel state slot of pair q (kw x kw, zeros below the diagonal).
+template <typename T>
 __global__ __launch_bounds__(256) void k_diag_load(int n, int64_t c0, int kw,
-                                                   const double* __restrict__ R, int64_t rstride,
-                                                   double* __restrict__ PS) {
+                                                   const T* __restrict__ R, int64_t rstride,
+                                                   T* __restrict__ PS) {
   const int64_t q = blockIdx.x;
-  const double* src = R + q * rstride + c0 * n + c0;
-  double* dst = PS + q * (int64_t)kw * kw;
+  const T* src = R + q * rstride + c0 * n + c0;
+  T* dst = PS + q * (int64_t)kw * kw;
   for (int idx = threadIdx.x; idx < kw * kw; idx += 256) {
     const int i = idx / kw, j = idx - (idx / kw) * kw;
-    dst[idx] = (j >= i) ? src[(int64_t)i * n + j] : 0.0;
+    dst[idx] = (j >= i) ? src[(int64_t)i * n + j] : T(0);
   }
 }
 
@@ -490,13 +491,18 @@ hipError_t launch_make_work(int in_f64, int out_f64, int64_t m, int n, const voi
   return hipGetLastError();
 }
 
-hipError_t launch_diag_load(int n, int64_t c0, int kw, int64_t npairs, const double* R,
-                            int64_t rstride, double* PS, hipStream_t st) {
+template <typename T>
+hipError_t launch_diag_load(int n, int64_t c0, int kw, int64_t npairs, const T* R,
+                            int64_t rstride, T* PS, hipStream_t st) {
   if (npairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_diag_load, dim3((unsigned)npairs), dim3(256), 0, st, n, c0, kw, R, rstride,
-                     PS);
+  hipLaunchKernelGGL((k_diag_load<T>), dim3((unsigned)npairs), dim3(256), 0, st, n, c0, kw, R,
+                     rstride, PS);
   return hipGetLastError();
 }
+template hipError_t launch_diag_load<double>(int, int64_t, int, int64_t, const double*, int64_t,
+                                             double*, hipStream_t);
+template hipError_t launch_diag_load<float>(int, int64_t, int, int64_t, const float*, int64_t,
+                                            float*, hipStream_t);
 
 template <typename T>
 hipError_t launch_assemble_r(int n, int64_t nprob, const T* PSt, int64_t pstride, T* R,

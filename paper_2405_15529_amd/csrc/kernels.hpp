@@ -67,8 +67,9 @@ template <typename T>
 hipError_t launch_panel_apply(const PanelApplyArgs<T>& a, bool fwd, hipStream_t st);
 // Copies the kw x kw diagonal block at (c0, c0) of R_j (j = 2 h q, upper
 // part, zeros below) into PS + q kw^2 for each of npairs tree pairs.
-hipError_t launch_diag_load(int n, int64_t c0, int kw, int64_t npairs, const double* R,
-                            int64_t rstride, double* PS, hipStream_t st);
+template <typename T>
+hipError_t launch_diag_load(int n, int64_t c0, int kw, int64_t npairs, const T* R,
+                            int64_t rstride, T* PS, hipStream_t st);
 hipError_t launch_make_work(int in_f64, int out_f64, int64_t m, int n, const void* D, int64_t ldd,
                             int remove_mean, double* mean_out, void* W, hipStream_t st);
 template <typename T>

@@ -427,3 +427,16 @@ def test_tuning_file_round_trip(hctx, tmp_path):
         hctx.tune_load(str(bad))
     with pytest.raises(api.PylomError):
         hctx.tune_load(str(tmp_path / "missing.json"))
+
+
+def test_mixed_tree_option(hctx):
+    # 1 (default): FP32 tree levels below the final combine on the mixed
+    # column-blocked path; 0: every level in FP64; nothing else is accepted
+    assert hctx.get_option("mixed_tree") == 1
+    hctx.set_option("mixed_tree", 0)
+    assert hctx.get_option("mixed_tree") == 0
+    for bad in (-1, 2):
+        with pytest.raises(api.PylomError):
+            hctx.set_option("mixed_tree", bad)
+    hctx.set_option("mixed_tree", 1)
+    assert hctx.get_option("mixed_tree") == 1

@@ -28,12 +28,14 @@ def say(msg):
     sys.stdout.flush()
 
 
-def run_blocked(D, remove_mean, r, block_rows, precision="fp64", blocked_from=2):
+def run_blocked(D, remove_mean, r, block_rows, precision="fp64", blocked_from=2, mixed_tree=None):
     import torch
     from paper_2405_15529_amd import api
     ctx = api.Context(0)
     ctx.set_option("blocked_from", blocked_from)
     ctx.set_option("block_rows", block_rows)
+    if mixed_tree is not None:
+        ctx.set_option("mixed_tree", mixed_tree)
     Dg = torch.from_numpy(np.ascontiguousarray(D)).cuda()
     out = api.pod(Dg, remove_mean=remove_mean, r=r, precision=precision, ctx=ctx)
     rc, sweeps = ctx.status()
@@ -153,6 +155,22 @@ def test_blocked_mixed_parity(m, n, b, rm):
     assert_parity(g, ref, r, srel=1e-6, snorm=1e-6, orth=1e-6, vec=1e-5, tie=1e-5)
     if rm:
         np.testing.assert_allclose(g["mean"], ref["mean"], rtol=2.0 ** -23, atol=0)
+
+
+@pytest.mark.parametrize("mixed_tree", [0, 1])
+def test_blocked_mixed_tree_levels(mixed_tree):
+    # 21 leaves (ragged tree, 5 levels): with mixed_tree = 1 the levels
+    # h = 1..8 combine FP32 R factors and only h = 16 runs in FP64; with 0
+    # every level is FP64.  Same bars as the other mixed cases.
+    m, n, b = 20500, 130, 1000
+    say(f"[gpu] blocked mixed tree={mixed_tree} m={m} n={n} b={b}")
+    rng = np.random.default_rng(77)
+    D = (rng.standard_normal((m, n)) * np.exp(-np.arange(n) / 10.0)[None, :] + 0.1)
+    D32 = D.astype(np.float32)
+    r = 0.02
+    ref = oracle.pod(D32.astype(np.float64), remove_mean=True, r=r)
+    g = run_blocked(D32, True, r, b, precision="mixed", mixed_tree=mixed_tree)
+    assert_parity(g, ref, r, srel=1e-6, snorm=1e-6, orth=1e-6, vec=1e-5, tie=1e-5)
 
 
 def test_blocked_wide_known_spectrum():
