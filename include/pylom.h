@@ -136,6 +136,13 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
  *                  tree in FP64.  The Rayleigh-Ritz refinement against D
  *                  sets the accuracy of the result either way.  The stacked
  *                  path always combines in FP64.
+ *   "mixed_svd_tol" 1 (default): the first SVD of R in a PYLOM_MIXED call
+ *                  (Eq. svdqr2 on the R of the FP32 leaves) treats a column
+ *                  pair as orthogonal once its cosine is at most 2^-24, the
+ *                  FP32 unit roundoff that bounds what that R determines;
+ *                  its leading right singular vectors only seed the
+ *                  Rayleigh-Ritz refinement.  0: the FP64 threshold
+ *                  n 2^-53 of every other SVD of R.
  * Read-only (pylom_get_option):
  *   "batch_jacobi_chained"  1 if the last pylom_pod_batched call ordered its
  *                  multi-workgroup Jacobi launches one after another across

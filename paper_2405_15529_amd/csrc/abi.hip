@@ -39,6 +39,7 @@ struct pylom_ctx_s {
   int64_t blocked_from = 0;  // n at which the column-blocked TSQR takes over (0: automatic)
   int64_t narrow_leaves = 1;  // single-wave 32-row leaves for narrow problems with many leaves
   int64_t mixed_tree = 1;     // mixed column-blocked tree: 1 = FP32 below the final combine
+  int64_t mixed_svd_tol = 1;  // mixed first SVD of R: 1 = rotation test at 2^-24, 0 = n 2^-53
   int* status_dev = nullptr;  // Jacobi status pairs (sweeps, barrier timeout) of the last call
   int status_valid = 0;
   int status_pairs = 1;        // 2 after a mixed-precision call (SVD of R + Gram eigen)
@@ -308,6 +309,9 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
   } else if (!std::strcmp(key, "mixed_tree")) {
     if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "mixed_tree must be 0 or 1");
     c->mixed_tree = v;  // part of every batch graph key
+  } else if (!std::strcmp(key, "mixed_svd_tol")) {
+    if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "mixed_svd_tol must be 0 or 1");
+    c->mixed_svd_tol = v;  // part of every batch graph key
   } else if (!std::strcmp(key, "streams")) {
     if (v < 1 || v > 16) return fail(c, PYLOM_EINVAL, "streams must be in [1, 16]");
     c->streams = v;
@@ -360,6 +364,8 @@ extern "C" int pylom_get_option(pylom_ctx c, const char* key, int64_t* v) {
     *v = c->narrow_leaves;
   else if (!std::strcmp(key, "mixed_tree"))
     *v = c->mixed_tree;
+  else if (!std::strcmp(key, "mixed_svd_tol"))
+    *v = c->mixed_svd_tol;
   else if (!std::strcmp(key, "timing"))
     *v = c->timing;
   else if (!std::strcmp(key, "streams"))
@@ -881,6 +887,19 @@ static int jac_after(pylom_ctx c, const Exec& x, const JacobiPlan& jp) {
     if (_r) return _r;                         \
   } while (0)
 
+// Jacobi plan of the first SVD of a mixed-precision call.  Its R comes from
+// FP32 leaves, so the cosines of its column pairs are known only to about
+// the FP32 unit roundoff; rotating further chases rounding noise of the FP32
+// factorisation.  With option mixed_svd_tol = 1 the rotation test stops at
+// 2^-24 instead of n 2^-53.  The leading right singular vectors only seed
+// the Rayleigh-Ritz refinement against D, which sets the accuracy of the
+// result.
+static JacobiPlan mixed_first_jp(const pylom_ctx_s* c, const JacobiPlan& jp) {
+  JacobiPlan j = jp;
+  if (c->mixed_svd_tol == 1) j.tol = 0x1p-24;
+  return j;
+}
+
 // Phase-1 results of the mixed path that phase 2 reads: S0 (n), VT0 (n x n),
 // mean (m), each 256-byte aligned.
 static size_t keep_bytes(int64_t m, int64_t n) {
@@ -1211,8 +1230,9 @@ static int enqueue_mixed1_blocked(pylom_ctx c, const Exec& x, const Plan& p, con
   if (rc) return rc;
   EVREC(3);
   JAC_BEFORE(p.jp);
-  KT(KR_SVD, launch_small_svd(p.jp, (double*)(x.ws + p.oR), x.max_sweeps, x.ws + p.oSvd,
-                              keep_S0(x, p), keep_VT0(x, p), n, (double*)(x.ws + p.oW), residual,
+  KT(KR_SVD, launch_small_svd(mixed_first_jp(c, p.jp), (double*)(x.ws + p.oR), x.max_sweeps,
+                              x.ws + p.oSvd, keep_S0(x, p), keep_VT0(x, p), n,
+                              (double*)(x.ws + p.oW), residual,
                               x.nr0 ? x.nr0 : (int64_t*)(x.ws + p.oNr0), x.status, st, x.coop),
      "small SVD");
   JAC_AFTER(p.jp);
@@ -1240,8 +1260,9 @@ static int enqueue_mixed1(pylom_ctx c, const Exec& x, const Plan& p, const void*
                                                 p.nch_tree, 0, st), "tree combine");
   EVREC(3);
   JAC_BEFORE(p.jp);
-  KT(KR_SVD, launch_small_svd(p.jp, (double*)(x.ws + p.oR), x.max_sweeps, x.ws + p.oSvd,
-                              keep_S0(x, p), keep_VT0(x, p), n, (double*)(x.ws + p.oW), residual,
+  KT(KR_SVD, launch_small_svd(mixed_first_jp(c, p.jp), (double*)(x.ws + p.oR), x.max_sweeps,
+                              x.ws + p.oSvd, keep_S0(x, p), keep_VT0(x, p), n,
+                              (double*)(x.ws + p.oW), residual,
                               x.nr0 ? x.nr0 : (int64_t*)(x.ws + p.oNr0), x.status, st, x.coop),
      "small SVD");
   JAC_AFTER(p.jp);
@@ -1804,10 +1825,10 @@ extern "C" int pylom_pod_batched(pylom_ctx c, pylom_dtype dtype, pylom_prec prec
   // (never the raw descriptor bytes, whose padding a C caller may leave
   // uninitialised)
   uint64_t key = 1469598103934665603ull;
-  const int64_t hdr[10] = {(int64_t)dtype,   (int64_t)prec,   count,
-                           L.K,             c->max_sweeps,   c->block_rows,
-                           c->narrow_leaves, c->blocked_from, c->mixed_tree,
-                           L.jac_chain ? 1 : 0};
+  const int64_t hdr[11] = {(int64_t)dtype,    (int64_t)prec,    count,
+                           L.K,              c->max_sweeps,    c->block_rows,
+                           c->narrow_leaves, c->blocked_from,  c->mixed_tree,
+                           c->mixed_svd_tol, L.jac_chain ? 1 : 0};
   key = fnv1a(key, hdr, sizeof(hdr));
   const void* wsp = c->ws;
   key = fnv1a(key, &wsp, sizeof(wsp));

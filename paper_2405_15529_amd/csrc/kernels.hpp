@@ -175,8 +175,10 @@ struct JacobiPlan {
   int n, npad, w, G, lpp, xcd_stride;
   int block;  // 1: block Jacobi of 16-column blocks (n > 256)
   int ks;     // workgroups per block pair (block Jacobi; grid = G * ks)
+  double tol = 0.0;  // rotation threshold on the cosine of a column pair (0: n 2^-53)
 };
 bool jacobi_plan(int n, JacobiPlan* p);
+double jacobi_tol(const JacobiPlan& p);
 size_t jacobi_ws_bytes(const JacobiPlan& p, int max_sweeps);
 // Workgroups of this plan's Jacobi kernel that one CU holds at once (the
 // occupancy query; 1 if it fails).

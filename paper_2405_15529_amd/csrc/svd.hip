@@ -2,7 +2,8 @@
 //
 // One-sided (Hestenes) Jacobi applied to X = R^T: the columns of X (the rows
 // of R) are rotated pairwise until all pairs are orthogonal to
-// tol = n * 2^-53 (relative).  With X J = W (J the accumulated rotations),
+// tol = n * 2^-53 (relative; a plan may carry a looser threshold, see
+// jacobi_tol).  With X J = W (J the accumulated rotations),
 // R = J W^T = J diag(sigma) (W diag(1/sigma))^T, so sigma_j = |w_j|,
 // U_R = J and V = W diag(1/sigma).  Working on R^T instead of R converges in
 // far fewer sweeps for triangular factors (9 instead of 29 on a 256 x 256 R
@@ -37,8 +38,14 @@ constexpr int BJB = 16;     // column block of the block Jacobi
 // pairwise tournament needs 451 barrier steps per sweep over 4-column blocks.
 constexpr int kBlockJacobiFrom = 256;
 
+// Rotation threshold of a plan: the plan's own, else n 2^-53 (a pair counts
+// as orthogonal once its cosine is at the level of the rounding of n-term
+// FP64 dot products).
+double jacobi_tol(const JacobiPlan& p) { return p.tol > 0.0 ? p.tol : (double)p.n * 0x1p-53; }
+
 bool jacobi_plan(int n, JacobiPlan* p) {
   if (n < 1 || n > 2048) return false;
+  p->tol = 0.0;
   p->block = 0;
   p->ks = 1;
   if (n > kBlockJacobiFrom) {
@@ -296,6 +303,7 @@ __device__ __forceinline__ void store_col(const double (&x)[JR], double* __restr
 
 struct JacobiArgs {
   int n, npad, w, G, xcd_stride, max_sweeps;
+  double tol;  // rotation test: |a_p . a_q| > tol |a_p| |a_q|
   double* A;
   double* V;
   unsigned int* bar;
@@ -325,7 +333,7 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
   const int w = a.w, n = a.n;
   const int grp = tid / LPP, sub = tid % LPP;
   const int rpl = (n + LPP - 1) / LPP;
-  const double tol = (double)n * 0x1p-53;
+  const double tol = a.tol;
   const int nplayers = 2 * a.G;
   unsigned int epoch = 0;
   double ca[JR], cva[JR], cb[JR], cvb[JR];
@@ -469,6 +477,7 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
 // untouched.  A sweep in which no step rotated ends the iteration.
 struct BJArgs {
   int n, npad, G, ks, max_sweeps;
+  double tol;  // rotation test, as in the pairwise kernel
   double* A;
   double* V;
   unsigned int* bar;
@@ -539,7 +548,7 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i16 = lane & 15, g4 = lane >> 4;
   const int n = a.n, ks = a.ks;
-  const double tol = (double)n * 0x1p-53, tol2 = tol * tol;
+  const double tol = a.tol, tol2 = tol * tol;
   const int nplayers = 2 * a.G;
   const unsigned int nwg = (unsigned int)(a.G * ks);
   // this workgroup's rows: 16-row tiles [t0, t1)
@@ -915,7 +924,8 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
   if (e != hipSuccess) return e;
   if (max_sweeps > 0 && p.block) {
     BJArgs b;
-    b.n = p.n; b.npad = p.npad; b.G = p.G; b.ks = p.ks; b.max_sweeps = max_sweeps; b.A = w.A;
+    b.n = p.n; b.npad = p.npad; b.G = p.G; b.ks = p.ks; b.max_sweeps = max_sweeps;
+    b.tol = jacobi_tol(p); b.A = w.A;
     b.V = w.V; b.bar = w.bar; b.flags = w.flags; b.pairc = w.pairc; b.gp = w.gp;
     b.status = status;
     void* args[] = {&b};
@@ -927,7 +937,8 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
   } else if (max_sweeps > 0) {
     JacobiArgs a;
     a.n = p.n; a.npad = p.npad; a.w = p.w; a.G = p.G; a.xcd_stride = p.xcd_stride;
-    a.max_sweeps = max_sweeps; a.A = w.A; a.V = w.V; a.bar = w.bar; a.flags = w.flags;
+    a.max_sweeps = max_sweeps; a.tol = jacobi_tol(p); a.A = w.A; a.V = w.V; a.bar = w.bar;
+    a.flags = w.flags;
     a.status = status;
     a.sWs = 0;
     void* args[] = {&a};
@@ -1035,7 +1046,8 @@ hipError_t launch_small_svd_batched(const JacobiPlan& p, int64_t count, const do
     // plain launch is enough
     JacobiArgs a;
     a.n = p.n; a.npad = p.npad; a.w = p.w; a.G = 1; a.xcd_stride = 1;
-    a.max_sweeps = max_sweeps; a.A = w.A; a.V = w.V; a.bar = w.bar; a.flags = w.flags;
+    a.max_sweeps = max_sweeps; a.tol = jacobi_tol(p); a.A = w.A; a.V = w.V; a.bar = w.bar;
+    a.flags = w.flags;
     a.status = status_each;
     a.sWs = wsb;
     const dim3 grid(1, (unsigned)count), block(JT);

@@ -287,7 +287,10 @@ def test_batched_validation_before_device(hctx):
     assert run([dict(ok, residual=1.5)]) == -1
     assert run([ok], prec=api.MIXED) == -3                                   # mixed needs R32
     assert run([ok], dtype=api.R32, prec=api.MIXED) == -7
-    assert run([dict(ok, m=5000, n=2000, ldd=2000, ldu=2000, ldvt=2000)]) == -6
+    # wide instances plan on the column-blocked TSQR (valid: no device);
+    # n > 2048 is not supported
+    assert run([dict(ok, m=5000, n=2000, ldd=2000, ldu=2000, ldvt=2000)]) == -7
+    assert run([dict(ok, m=5000, n=2100, ldd=2100, ldu=2100, ldvt=2100)]) == -6
     hctx.set_option("streams", 8)
     assert hctx.get_option("streams") == 8
     with pytest.raises(api.PylomError):
@@ -440,3 +443,15 @@ def test_mixed_tree_option(hctx):
             hctx.set_option("mixed_tree", bad)
     hctx.set_option("mixed_tree", 1)
     assert hctx.get_option("mixed_tree") == 1
+
+
+def test_mixed_svd_tol_option(hctx):
+    # 1 (default): the first SVD of a mixed call stops rotating at cosines of
+    # 2^-24; 0: the FP64 threshold n 2^-53
+    assert hctx.get_option("mixed_svd_tol") == 1
+    hctx.set_option("mixed_svd_tol", 0)
+    assert hctx.get_option("mixed_svd_tol") == 0
+    for bad in (-1, 2):
+        with pytest.raises(api.PylomError):
+            hctx.set_option("mixed_svd_tol", bad)
+    hctx.set_option("mixed_svd_tol", 1)
