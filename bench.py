@@ -214,9 +214,9 @@ TRAFFIC = {
     # blocks 8192: mean over the 28 launches of one mixed call
     "blocked_trailing_fp32": {
         "sources": ("blocked.hip", "common.hpp"),
-        "sources_sha256": "2d80b6ae7bcaa2f0ab39684947fe5d7e98d29347433f69d67eb497bc80e97520",
+        "sources_sha256": "d130dda91ab02719273a350d6470c7d90963f4889d613f9de02af993cfe0a61f",
         "shape": (4194304, 1808, 8192),
-        "bytes": 33319203623,  # FETCH 5.057e+11 (x1.99992) + WRITE 4.273e+11 (x1.0), / 28
+        "bytes": 33521389753,  # FETCH 5.115e+11 (x1.99992) + WRITE 4.271e+11 (x1.0), / 28
     },
 }
 
