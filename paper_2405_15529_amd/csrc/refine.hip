@@ -16,6 +16,7 @@
 // FP32 backward error except through that angle.  This replaces the
 // reflector apply of Eq. svdqr3 in the mixed path (the Q of the FP32 QR is
 // never formed).
+#include <type_traits>
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -131,7 +132,10 @@ constexpr int TR = 128;       // rows per workgroup
 constexpr int TK = 16;        // K slab
 constexpr int TALD = TK + 1;
 }  // namespace
-template <typename TI, typename TO, bool BT, int NT>
+// VA (FP32 A with lda and K multiples of 4 and A 16-byte aligned): A is
+// read as 16-byte vectors, four consecutive values of a row per thread, and
+// the mean of each of the thread's two rows is read once per workgroup.
+template <typename TI, typename TO, bool BT, int NT, bool VA>
 __global__ __launch_bounds__(256) void k_tall_gemm_k(int64_t m, int K, int nc_host,
                                                      const int64_t* __restrict__ nc_dev,
                                                      const TI* __restrict__ A, int64_t lda,
@@ -161,21 +165,48 @@ __global__ __launch_bounds__(256) void k_tall_gemm_k(int64_t m, int K, int nc_ho
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[r][c] = vzero4<double>();
   double pa[AE], pb[BE];
+  // VA: vector e of a slab is row (tid + 256 e) / 4, columns 4 ((tid + 256 e)
+  // % 4) + 0..3, the same two rows in every slab
+  constexpr int AV = VA ? AE / 4 : 1;
+  double mrow[AV];
+  if constexpr (VA) {
+#pragma unroll
+    for (int e = 0; e < AV; ++e) {
+      const int64_t gr = r0 + ((tid + 256 * e) >> 2);
+      mrow[e] = (mu && gr < m) ? mu[gr] : 0.0;
+    }
+  }
   // A element e of a slab: row idx / TK, column idx % TK (a row's 16 values
   // are read by 16 consecutive threads); B element: BT walks t fastest
   auto fetch = [&](int k0) {
+    if constexpr (VA) {
 #pragma unroll
-    for (int e = 0; e < AE; ++e) {
-      const int idx = tid + 256 * e;
-      const int r = idx / TK, c = idx % TK;
-      const int64_t gr = r0 + r;
-      const int gc = k0 + c;
-      double v = 0.0;
-      if (gr < m && gc < K) {
-        v = (double)A[gr * lda + gc];
-        if (mu) v -= mu[gr];
+      for (int e = 0; e < AV; ++e) {
+        const int idx = tid + 256 * e;
+        const int64_t gr = r0 + (idx >> 2);
+        const int gc = k0 + 4 * (idx & 3);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gr < m && gc < K) v = *reinterpret_cast<const float4*>(A + gr * lda + gc);
+        const bool live = gr < m && gc < K;
+        pa[4 * e + 0] = live ? (double)v.x - mrow[e] : 0.0;
+        pa[4 * e + 1] = live ? (double)v.y - mrow[e] : 0.0;
+        pa[4 * e + 2] = live ? (double)v.z - mrow[e] : 0.0;
+        pa[4 * e + 3] = live ? (double)v.w - mrow[e] : 0.0;
       }
-      pa[e] = v;
+    } else {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int idx = tid + 256 * e;
+        const int r = idx / TK, c = idx % TK;
+        const int64_t gr = r0 + r;
+        const int gc = k0 + c;
+        double v = 0.0;
+        if (gr < m && gc < K) {
+          v = (double)A[gr * lda + gc];
+          if (mu) v -= mu[gr];
+        }
+        pa[e] = v;
+      }
     }
 #pragma unroll
     for (int e = 0; e < BE; ++e) {
@@ -196,10 +227,20 @@ __global__ __launch_bounds__(256) void k_tall_gemm_k(int64_t m, int K, int nc_ho
     }
   };
   auto commit = [&]() {
+    if constexpr (VA) {
 #pragma unroll
-    for (int e = 0; e < AE; ++e) {
-      const int idx = tid + 256 * e;
-      As[(idx / TK) * TALD + idx % TK] = pa[e];
+      for (int e = 0; e < AV; ++e) {
+        const int idx = tid + 256 * e;
+        double* dst = As + (idx >> 2) * TALD + 4 * (idx & 3);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = pa[4 * e + q];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int idx = tid + 256 * e;
+        As[(idx / TK) * TALD + idx % TK] = pa[e];
+      }
     }
 #pragma unroll
     for (int e = 0; e < BE; ++e) {
@@ -474,8 +515,15 @@ static void launch_tgk(int64_t m, int K, int nc, const int64_t* nc_dev, const TI
                        const double* mu, const double* B, int64_t ldb, TO* C, int64_t ldc,
                        hipStream_t st) {
   const dim3 grid((unsigned)((m + TR - 1) / TR), (unsigned)((nc + 16 * NT - 1) / (16 * NT)));
-  hipLaunchKernelGGL((k_tall_gemm_k<TI, TO, BT, NT>), grid, dim3(256), 0, st, m, K, nc, nc_dev,
-                     A, lda, mu, B, ldb, C, ldc);
+  if constexpr (std::is_same<TI, float>::value) {
+    if (lda % 4 == 0 && K % 4 == 0 && ((uintptr_t)A & 15) == 0) {
+      hipLaunchKernelGGL((k_tall_gemm_k<TI, TO, BT, NT, true>), grid, dim3(256), 0, st, m, K, nc,
+                         nc_dev, A, lda, mu, B, ldb, C, ldc);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_tall_gemm_k<TI, TO, BT, NT, false>), grid, dim3(256), 0, st, m, K, nc,
+                     nc_dev, A, lda, mu, B, ldb, C, ldc);
 }
 
 template <typename TI, typename TO, bool BT>
