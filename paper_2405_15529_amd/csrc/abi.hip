@@ -40,6 +40,8 @@ struct pylom_ctx_s {
   int64_t narrow_leaves = 1;  // single-wave 32-row leaves for narrow problems with many leaves
   int64_t mixed_tree = 1;     // mixed column-blocked tree: 1 = FP32 below the final combine
   int64_t mixed_svd_tol = 1;  // mixed first SVD of R: 1 = rotation test at 2^-24, 0 = n 2^-53
+  int64_t tree_pipeline = 1;  // column-blocked tree levels as a wavefront over lanes
+  std::vector<hipEvent_t> tree_ev;  // (level, panel) completion events of that wavefront
   int* status_dev = nullptr;  // Jacobi status pairs (sweeps, barrier timeout) of the last call
   int status_valid = 0;
   int status_pairs = 1;        // 2 after a mixed-precision call (SVD of R + Gram eigen)
@@ -260,6 +262,7 @@ extern "C" int pylom_destroy(pylom_ctx c) {
     for (hipStream_t q : c->lanes) hipStreamDestroy(q);
     for (hipEvent_t e : c->ev_join) hipEventDestroy(e);
     for (hipEvent_t e : c->jac_ev) hipEventDestroy(e);
+    for (hipEvent_t e : c->tree_ev) hipEventDestroy(e);
     for (hipEvent_t e : c->kev) hipEventDestroy(e);
     for (hipEvent_t e : c->ooc_ev)
       if (e) hipEventDestroy(e);
@@ -309,6 +312,9 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
   } else if (!std::strcmp(key, "mixed_tree")) {
     if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "mixed_tree must be 0 or 1");
     c->mixed_tree = v;  // part of every batch graph key
+  } else if (!std::strcmp(key, "tree_pipeline")) {
+    if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "tree_pipeline must be 0 or 1");
+    c->tree_pipeline = v;
   } else if (!std::strcmp(key, "mixed_svd_tol")) {
     if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "mixed_svd_tol must be 0 or 1");
     c->mixed_svd_tol = v;  // part of every batch graph key
@@ -366,6 +372,8 @@ extern "C" int pylom_get_option(pylom_ctx c, const char* key, int64_t* v) {
     *v = c->mixed_tree;
   else if (!std::strcmp(key, "mixed_svd_tol"))
     *v = c->mixed_svd_tol;
+  else if (!std::strcmp(key, "tree_pipeline"))
+    *v = c->tree_pipeline;
   else if (!std::strcmp(key, "timing"))
     *v = c->timing;
   else if (!std::strcmp(key, "streams"))
@@ -859,6 +867,7 @@ struct Exec {
                         // phase 2 (nullptr: the workspace); layout keep_bytes()
   hipEvent_t* jac_ev;   // batch: events that chain the multi-workgroup Jacobi
   int64_t* jac_next;    //   launches across lanes (nullptr: no chaining)
+  bool batched;         // an instance of a batch (the lanes are taken)
 };
 
 // A batch whose lanes could run more Jacobi workgroups at once than the
@@ -1047,26 +1056,64 @@ static int blocked_leaves(pylom_ctx c, hipStream_t st, const Plan& p, char* ws, 
   return PYLOM_OK;
 }
 
+static int ensure_lanes(pylom_ctx c, int64_t k);
+constexpr int64_t kTreeLanes = 4;  // streams of the tree wavefront
+
 // The reduction tree of Alg. 1 on the leaf R's at R (the FP64 ones at
 // ws + oR, or FP32 ones), in place, over the levels h_lo <= h < h_hi: at
 // level h, pair q combines R_j (j = 2hq, the state) with R_{j+h} (the
 // chunks, rows 0..c0+kw at panel k); R_j becomes the combined R, R_{j+h}
 // keeps the reflector tails.  The T factors and panel states of each level
 // keep their own slots (the propagation reads them), whatever the range.
+//
+// With pipe (and option tree_pipeline), the levels run as a wavefront: level
+// i on lane i mod kTreeLanes, and panel k of level i waits only for panel k
+// of level i - 1.  Panel k of a combine reads rows 0..c0+kw of its two
+// operands, which are final once panel k of the level below has run, its
+// trailing update written those rows right of the panel, and its diagonal
+// block been assembled; later panels of the level below only touch rows
+// below c0+kw of the states and the reflector tails, which this level never
+// reads.  So every level assembles its R per panel.  Without pipe the levels
+// run one after another on st0.
 template <typename T>
-static int blocked_tree(pylom_ctx c, hipStream_t st, const Plan& p, char* ws, T* R,
-                        int64_t h_lo = 1, int64_t h_hi = -1) {
+static int blocked_tree(pylom_ctx c, hipStream_t st0, const Plan& p, char* ws, T* R,
+                        int64_t h_lo = 1, int64_t h_hi = -1, bool pipe = false) {
   const int64_t n = p.n;
   if (h_hi < 0) h_hi = p.P;
   const size_t tps = t_slot(p, true), pps = ps_slot(p, true);
   int64_t base = 0;
   for (int64_t h = 1; h < h_lo; h *= 2) base += level_pairs(p.P, h);
+  std::vector<int64_t> hs, bases;
   for (int64_t h = h_lo; h < p.P && h < h_hi; h *= 2) {
+    hs.push_back(h);
+    bases.push_back(base);
+    base += level_pairs(p.P, h);
+  }
+  const int64_t L = (int64_t)hs.size();
+  if (L == 0) return PYLOM_OK;
+  const bool pl = pipe && c->tree_pipeline && L > 1;
+  const int64_t S = pl ? std::min<int64_t>(L, kTreeLanes) : 1;
+  if (pl) {
+    int rc = ensure_lanes(c, S);
+    if (rc) return rc;
+    const size_t need = (size_t)(L * p.K);
+    while (c->tree_ev.size() < need) {
+      hipEvent_t e = nullptr;
+      HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+      c->tree_ev.push_back(e);
+    }
+    HIPCHK(c, hipEventRecord(c->ev_fork, st0), "hipEventRecord");
+    for (int64_t l = 0; l < S; ++l)
+      HIPCHK(c, hipStreamWaitEvent(c->lanes[(size_t)l], c->ev_fork, 0), "hipStreamWaitEvent");
+  }
+  for (int64_t li = 0; li < L; ++li) {
+    const int64_t h = hs[(size_t)li];
+    hipStream_t st = pl ? c->lanes[(size_t)(li % S)] : st0;
     const int64_t np = level_pairs(p.P, h);
     const int64_t rs = 2 * h * n * n;  // pair stride (elements)
     T* Rb = R + h * n * n;             // R_{j+h} of pair 0, as rows of stride n
-    T* Tb = (T*)(ws + p.oTp) + base * p.nch_p * 4 * kTF;
-    T* PSb = (T*)(ws + p.oPSp) + base * kPW * kPW;
+    T* Tb = (T*)(ws + p.oTp) + bases[(size_t)li] * p.nch_p * 4 * kTF;
+    T* PSb = (T*)(ws + p.oPSp) + bases[(size_t)li] * kPW * kPW;
     for (int64_t k = 0; k < p.K; ++k) {
       const int64_t c0 = k * kPW;
       const int kw = (int)((n - c0 < kPW) ? n - c0 : kPW);
@@ -1074,10 +1121,16 @@ static int blocked_tree(pylom_ctx c, hipStream_t st, const Plan& p, char* ws, T*
       const int64_t rows_lim = c0 + kw;
       T* Tk = Tb + k * tps;
       T* PSk = PSb + k * pps;
+      if (pl && li > 0)
+        HIPCHK(c, hipStreamWaitEvent(st, c->tree_ev[(size_t)((li - 1) * p.K + k)], 0),
+               "hipStreamWaitEvent");
       KT(KR_TREE_PANEL, launch_diag_load<T>((int)n, c0, kw, np, R, rs, PSk, st), "pair state");
       KT(KR_TREE_PANEL, launch_panel_qr<T>(g, Rb + c0, n, np * 2 * h * n, 2 * h * n, np,
                                            rows_lim, Tk, p.nch_p, PSk, 2, st),
          "pair panel QR");
+      if (pl)
+        KT(KR_TREE_PANEL, launch_assemble_r<T>((int)n, np, PSb, (int64_t)pps, R, rs, st, (int)c0,
+                                               kw), "R assembly");
       if (c0 + kw < n) {
         PanelApplyArgs<T> a{};
         a.kw = kw; a.npan = g.npanels; a.nlv = np; a.b = 2 * h * n; a.m = np * 2 * h * n;
@@ -1087,11 +1140,18 @@ static int blocked_tree(pylom_ctx c, hipStream_t st, const Plan& p, char* ws, T*
         a.load_state = 1; a.store_state = 1; a.leaf_major = 0;
         KT(KR_TREE_TRAIL, launch_panel_apply<T>(a, false, st), "pair trailing update");
       }
+      if (pl)
+        HIPCHK(c, hipEventRecord(c->tree_ev[(size_t)(li * p.K + k)], st), "hipEventRecord");
     }
-    KT(KR_TREE_PANEL, launch_assemble_r<T>((int)n, np, PSb, (int64_t)pps, R, rs, st),
-       "R assembly");
-    base += np;
+    if (!pl)
+      KT(KR_TREE_PANEL, launch_assemble_r<T>((int)n, np, PSb, (int64_t)pps, R, rs, st),
+         "R assembly");
   }
+  if (pl)
+    for (int64_t l = 0; l < S; ++l) {
+      HIPCHK(c, hipEventRecord(c->ev_join[(size_t)l], c->lanes[(size_t)l]), "hipEventRecord");
+      HIPCHK(c, hipStreamWaitEvent(st0, c->ev_join[(size_t)l], 0), "hipStreamWaitEvent");
+    }
   return PYLOM_OK;
 }
 
@@ -1178,7 +1238,7 @@ static int enqueue_fp64_blocked(pylom_ctx c, const Exec& x, const Plan& p, pylom
   int rc = blocked_leaves<double>(c, st, p, x.ws, Rbuf);
   if (rc) return rc;
   EVREC(2);
-  rc = blocked_tree<double>(c, st, p, x.ws, Rbuf);
+  rc = blocked_tree<double>(c, st, p, x.ws, Rbuf, 1, -1, !x.batched);
   if (rc) return rc;
   EVREC(3);
   JAC_BEFORE(p.jp);
@@ -1216,7 +1276,7 @@ static int enqueue_mixed1_blocked(pylom_ctx c, const Exec& x, const Plan& p, con
   const int64_t h64 = (c->mixed_tree == 1 && p.P > 1) ? top : 1;
   if (h64 > 1) {
     EVREC(2);
-    rc = blocked_tree<float>(c, st, p, x.ws, R32, 1, h64);
+    rc = blocked_tree<float>(c, st, p, x.ws, R32, 1, h64, !x.batched);
     if (rc) return rc;
     // the two operands of the final combine (R_0 and R_top)
     KT(KR_TREE_PANEL, launch_cast_f32_f64(R32, R64, n * n, st), "R to FP64");
@@ -1226,7 +1286,7 @@ static int enqueue_mixed1_blocked(pylom_ctx c, const Exec& x, const Plan& p, con
     KT(KR_LEAF_PANEL, launch_cast_f32_f64(R32, R64, p.P * n * n, st), "R to FP64");
     EVREC(2);
   }
-  rc = blocked_tree<double>(c, st, p, x.ws, R64, h64);
+  rc = blocked_tree<double>(c, st, p, x.ws, R64, h64, -1, !x.batched);
   if (rc) return rc;
   EVREC(3);
   JAC_BEFORE(p.jp);
@@ -1342,6 +1402,7 @@ static Exec ctx_exec(pylom_ctx c) {
   x.keep = nullptr;
   x.jac_ev = nullptr;
   x.jac_next = nullptr;
+  x.batched = false;
   return x;
 }
 
@@ -1661,6 +1722,7 @@ static int batch_phase(pylom_ctx c, const BatchLayout& L, pylom_dtype dtype, int
     x.keep = L.keep_off.empty() ? nullptr : ws + L.keep_off[(size_t)i];
     x.jac_ev = L.jac_chain ? c->jac_ev.data() : nullptr;
     x.jac_next = L.jac_chain ? &jac_next : nullptr;
+    x.batched = true;
     const pylom_problem& q = pr[i];
     int rc;
     if (phase == 0)
@@ -1899,7 +1961,7 @@ extern "C" int pylom_tsqr(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, int64
            "working copy");
     rc = blocked_leaves<double>(c, st, p, ws, Rbuf);
     if (rc) return rc;
-    rc = blocked_tree<double>(c, st, p, ws, (double*)(ws + p.oR));
+    rc = blocked_tree<double>(c, st, p, ws, (double*)(ws + p.oR), 1, -1, true);
     if (rc) return rc;
     HIPCHK(c, launch_r_out(Rbuf, n, R, ldr, signs, st), "R out");
     if (wq) {
@@ -2111,7 +2173,7 @@ extern "C" int pylom_dmd(pylom_ctx c, pylom_dtype dtype, int64_t m, int64_t n, c
            "working copy");
     rc = blocked_leaves<double>(c, st, p, ws, Rbuf);
     if (rc) return rc;
-    rc = blocked_tree<double>(c, st, p, ws, (double*)(ws + p.oR));
+    rc = blocked_tree<double>(c, st, p, ws, (double*)(ws + p.oR), 1, -1, true);
     if (rc) return rc;
   } else {
     HIPCHK(c, launch_leaf_qr_f64(p.g, D, in64, ldd, m, p.b, p.P, remove_mean, meanws, nullptr,
@@ -2462,7 +2524,7 @@ extern "C" int pylom_pod_host(pylom_ctx c, pylom_dtype dtype, pylom_prec prec, i
     if ((rc = factor(w, k))) return rc;
   }
   // the tree, the SVD of the root R with truncation, the down-tree propagation
-  rc = blocked_tree<double>(c, st, p, ws, (double*)(ws + p.oR));
+  rc = blocked_tree<double>(c, st, p, ws, (double*)(ws + p.oR), 1, -1, true);
   if (rc) return rc;
   double* Sd = (double*)(ws + L.oS);
   double* VTd = (double*)(ws + L.oVT);

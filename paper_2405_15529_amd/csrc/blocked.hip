@@ -391,12 +391,12 @@ __global__ __launch_bounds__(256) void k_diag_load(int n, int64_t c0, int kw,
 // k = r / 64 gets zeros left of the panel and the panel's upper-triangular
 // state block (kw_k x kw_k, row stride kw_k, at PSt + k pstride + l kw_k^2);
 // the part right of the panel was written by the trailing apply.
-// Grid: (n, problems).
+// Grid: (rows, problems), rows r0 .. r0 + rows - 1.
 template <typename T>
-__global__ __launch_bounds__(256) void k_assemble_r(int n, const T* __restrict__ PSt,
+__global__ __launch_bounds__(256) void k_assemble_r(int n, int r0, const T* __restrict__ PSt,
                                                     int64_t pstride, T* __restrict__ R,
                                                     int64_t rstride) {
-  const int r = blockIdx.x;
+  const int r = r0 + blockIdx.x;
   const int64_t l = blockIdx.y;
   const int k = r / PW, i = r - k * PW;
   const int c0 = k * PW;
@@ -506,17 +506,18 @@ template hipError_t launch_diag_load<float>(int, int64_t, int, int64_t, const fl
 
 template <typename T>
 hipError_t launch_assemble_r(int n, int64_t nprob, const T* PSt, int64_t pstride, T* R,
-                             int64_t rstride, hipStream_t st) {
-  if (nprob <= 0) return hipSuccess;
-  if (nprob > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_assemble_r<T>), dim3((unsigned)n, (unsigned)nprob), dim3(256), 0, st, n,
-                     PSt, pstride, R, rstride);
+                             int64_t rstride, hipStream_t st, int r0, int rows) {
+  if (rows < 0) rows = n - r0;
+  if (nprob <= 0 || rows <= 0) return hipSuccess;
+  if (nprob > 65535 || r0 < 0 || r0 + rows > n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_assemble_r<T>), dim3((unsigned)rows, (unsigned)nprob), dim3(256), 0, st,
+                     n, r0, PSt, pstride, R, rstride);
   return hipGetLastError();
 }
 template hipError_t launch_assemble_r<double>(int, int64_t, const double*, int64_t, double*,
-                                              int64_t, hipStream_t);
+                                              int64_t, hipStream_t, int, int);
 template hipError_t launch_assemble_r<float>(int, int64_t, const float*, int64_t, float*, int64_t,
-                                             hipStream_t);
+                                             hipStream_t, int, int);
 
 hipError_t launch_copy_cols(int out_f64, int64_t m, int64_t col0, int64_t ncg, int64_t ncols,
                             const int64_t* nc_dev, const double* X, int64_t ldx, void* U,

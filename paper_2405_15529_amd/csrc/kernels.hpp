@@ -72,9 +72,10 @@ hipError_t launch_diag_load(int n, int64_t c0, int kw, int64_t npairs, const T* 
                             int64_t rstride, T* PS, hipStream_t st);
 hipError_t launch_make_work(int in_f64, int out_f64, int64_t m, int n, const void* D, int64_t ldd,
                             int remove_mean, double* mean_out, void* W, hipStream_t st);
+// Rows r0 .. r0 + rows - 1 of R (rows < 0: through row n - 1).
 template <typename T>
 hipError_t launch_assemble_r(int n, int64_t nprob, const T* PSt, int64_t pstride, T* R,
-                             int64_t rstride, hipStream_t st);
+                             int64_t rstride, hipStream_t st, int r0 = 0, int rows = -1);
 hipError_t launch_copy_cols(int out_f64, int64_t m, int64_t col0, int64_t ncg, int64_t ncols,
                             const int64_t* nc_dev, const double* X, int64_t ldx, void* U,
                             int64_t ldu, hipStream_t st);

@@ -455,3 +455,15 @@ def test_mixed_svd_tol_option(hctx):
         with pytest.raises(api.PylomError):
             hctx.set_option("mixed_svd_tol", bad)
     hctx.set_option("mixed_svd_tol", 1)
+
+
+def test_tree_pipeline_option(hctx):
+    # 1 (default): the column-blocked tree levels as a wavefront over the
+    # library's streams; 0: one level after another
+    assert hctx.get_option("tree_pipeline") == 1
+    hctx.set_option("tree_pipeline", 0)
+    assert hctx.get_option("tree_pipeline") == 0
+    for bad in (-1, 2):
+        with pytest.raises(api.PylomError):
+            hctx.set_option("tree_pipeline", bad)
+    hctx.set_option("tree_pipeline", 1)

@@ -28,7 +28,8 @@ def say(msg):
     sys.stdout.flush()
 
 
-def run_blocked(D, remove_mean, r, block_rows, precision="fp64", blocked_from=2, mixed_tree=None):
+def run_blocked(D, remove_mean, r, block_rows, precision="fp64", blocked_from=2, mixed_tree=None,
+                opts=None):
     import torch
     from paper_2405_15529_amd import api
     ctx = api.Context(0)
@@ -36,6 +37,8 @@ def run_blocked(D, remove_mean, r, block_rows, precision="fp64", blocked_from=2,
     ctx.set_option("block_rows", block_rows)
     if mixed_tree is not None:
         ctx.set_option("mixed_tree", mixed_tree)
+    for k, v in (opts or {}).items():
+        ctx.set_option(k, v)
     Dg = torch.from_numpy(np.ascontiguousarray(D)).cuda()
     out = api.pod(Dg, remove_mean=remove_mean, r=r, precision=precision, ctx=ctx)
     rc, sweeps = ctx.status()
@@ -171,6 +174,32 @@ def test_blocked_mixed_tree_levels(mixed_tree):
     ref = oracle.pod(D32.astype(np.float64), remove_mean=True, r=r)
     g = run_blocked(D32, True, r, b, precision="mixed", mixed_tree=mixed_tree)
     assert_parity(g, ref, r, srel=1e-6, snorm=1e-6, orth=1e-6, vec=1e-5, tie=1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_blocked_tree_wavefront_matches_serial(precision):
+    # 37 leaves (6 tree levels, ragged) of a 3-panel problem: the wavefront
+    # tree over the library's streams (tree_pipeline = 1) runs the same
+    # kernels on the same operands as the serial levels, so every output is
+    # bit-identical; both are also held to the oracle.
+    m, n, b = 9300, 150, 250
+    say(f"[gpu] blocked tree wavefront {precision} m={m} n={n} b={b}")
+    rng = np.random.default_rng(91)
+    D = (rng.standard_normal((m, n)) * np.exp(-np.arange(n) / 12.0)[None, :] + 0.2)
+    if precision == "mixed":
+        D = D.astype(np.float32)
+    r = 0.02
+    ser = run_blocked(D, True, r, b, precision=precision, opts={"tree_pipeline": 0})
+    pip = run_blocked(D, True, r, b, precision=precision, opts={"tree_pipeline": 1})
+    assert ser["nr"] == pip["nr"]
+    np.testing.assert_array_equal(pip["S"], ser["S"])
+    np.testing.assert_array_equal(pip["VT"][:pip["nr"]], ser["VT"][:ser["nr"]])
+    np.testing.assert_array_equal(pip["U"], ser["U"])
+    ref = oracle.pod(np.asarray(D, dtype=np.float64), remove_mean=True, r=r)
+    if precision == "fp64":
+        assert_parity(pip, ref, r)
+    else:
+        assert_parity(pip, ref, r, srel=1e-6, snorm=1e-6, orth=1e-6, vec=1e-5, tie=1e-5)
 
 
 def test_blocked_wide_known_spectrum():
