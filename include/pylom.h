@@ -136,14 +136,15 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
  *                  tree in FP64.  The Rayleigh-Ritz refinement against D
  *                  sets the accuracy of the result either way.  The stacked
  *                  path always combines in FP64.
- *   "tree_pipeline" 1 (default): on the column-blocked path the levels of
- *                  the R-tree (Alg. 1 reduce) run as a wavefront over up to
- *                  four library streams: panel k of level h starts once
- *                  panel k of level h/2 is done, not once that whole level
- *                  is.  The arithmetic and the results are the same as with
- *                  0, which runs the levels one after another on the
- *                  context stream.  Instances of pylom_pod_batched always
- *                  run their levels one after another on their own stream.
+ *   "tree_pipeline" S in [0, 16], default 8: on the column-blocked path
+ *                  the levels of the R-tree (Alg. 1 reduce) run as a
+ *                  wavefront over up to S library streams: panel k of level
+ *                  h starts once panel k of level h/2 is done, not once that
+ *                  whole level is.  The arithmetic and the results are the
+ *                  same as with 0 or 1, which run the levels one after
+ *                  another on the context stream.  Instances of
+ *                  pylom_pod_batched always run their levels one after
+ *                  another on their own stream.
  *   "mixed_svd_tol" 1 (default): the first SVD of R in a PYLOM_MIXED call
  *                  (Eq. svdqr2 on the R of the FP32 leaves) treats a column
  *                  pair as orthogonal once its cosine is at most 2^-24, the

@@ -40,7 +40,7 @@ struct pylom_ctx_s {
   int64_t narrow_leaves = 1;  // single-wave 32-row leaves for narrow problems with many leaves
   int64_t mixed_tree = 1;     // mixed column-blocked tree: 1 = FP32 below the final combine
   int64_t mixed_svd_tol = 1;  // mixed first SVD of R: 1 = rotation test at 2^-24, 0 = n 2^-53
-  int64_t tree_pipeline = 1;  // column-blocked tree levels as a wavefront over lanes
+  int64_t tree_pipeline = 8;  // column-blocked tree levels as a wavefront over this many lanes
   std::vector<hipEvent_t> tree_ev;  // (level, panel) completion events of that wavefront
   int* status_dev = nullptr;  // Jacobi status pairs (sweeps, barrier timeout) of the last call
   int status_valid = 0;
@@ -313,7 +313,7 @@ extern "C" int pylom_set_option(pylom_ctx c, const char* key, int64_t v) {
     if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "mixed_tree must be 0 or 1");
     c->mixed_tree = v;  // part of every batch graph key
   } else if (!std::strcmp(key, "tree_pipeline")) {
-    if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "tree_pipeline must be 0 or 1");
+    if (v < 0 || v > 16) return fail(c, PYLOM_EINVAL, "tree_pipeline must be in [0, 16]");
     c->tree_pipeline = v;
   } else if (!std::strcmp(key, "mixed_svd_tol")) {
     if (v != 0 && v != 1) return fail(c, PYLOM_EINVAL, "mixed_svd_tol must be 0 or 1");
@@ -1057,7 +1057,6 @@ static int blocked_leaves(pylom_ctx c, hipStream_t st, const Plan& p, char* ws, 
 }
 
 static int ensure_lanes(pylom_ctx c, int64_t k);
-constexpr int64_t kTreeLanes = 4;  // streams of the tree wavefront
 
 // The reduction tree of Alg. 1 on the leaf R's at R (the FP64 ones at
 // ws + oR, or FP32 ones), in place, over the levels h_lo <= h < h_hi: at
@@ -1066,9 +1065,9 @@ constexpr int64_t kTreeLanes = 4;  // streams of the tree wavefront
 // keeps the reflector tails.  The T factors and panel states of each level
 // keep their own slots (the propagation reads them), whatever the range.
 //
-// With pipe (and option tree_pipeline), the levels run as a wavefront: level
-// i on lane i mod kTreeLanes, and panel k of level i waits only for panel k
-// of level i - 1.  Panel k of a combine reads rows 0..c0+kw of its two
+// With pipe (and option tree_pipeline = S > 1), the levels run as a
+// wavefront: level i on lane i mod S, and panel k of level i waits only for
+// panel k of level i - 1.  Panel k of a combine reads rows 0..c0+kw of its two
 // operands, which are final once panel k of the level below has run, its
 // trailing update written those rows right of the panel, and its diagonal
 // block been assembled; later panels of the level below only touch rows
@@ -1091,17 +1090,17 @@ static int blocked_tree(pylom_ctx c, hipStream_t st0, const Plan& p, char* ws, T
   }
   const int64_t L = (int64_t)hs.size();
   if (L == 0) return PYLOM_OK;
-  const bool pl = pipe && c->tree_pipeline && L > 1;
-  const int64_t S = pl ? std::min<int64_t>(L, kTreeLanes) : 1;
+  const bool pl = pipe && c->tree_pipeline > 1 && L > 1;
+  const int64_t S = pl ? std::min<int64_t>(L, c->tree_pipeline) : 1;
   if (pl) {
-    int rc = ensure_lanes(c, S);
-    if (rc) return rc;
     const size_t need = (size_t)(L * p.K);
     while (c->tree_ev.size() < need) {
       hipEvent_t e = nullptr;
       HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
       c->tree_ev.push_back(e);
     }
+    const int rc = ensure_lanes(c, S);
+    if (rc) return rc;
     HIPCHK(c, hipEventRecord(c->ev_fork, st0), "hipEventRecord");
     for (int64_t l = 0; l < S; ++l)
       HIPCHK(c, hipStreamWaitEvent(c->lanes[(size_t)l], c->ev_fork, 0), "hipStreamWaitEvent");

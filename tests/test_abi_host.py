@@ -458,12 +458,13 @@ def test_mixed_svd_tol_option(hctx):
 
 
 def test_tree_pipeline_option(hctx):
-    # 1 (default): the column-blocked tree levels as a wavefront over the
-    # library's streams; 0: one level after another
-    assert hctx.get_option("tree_pipeline") == 1
-    hctx.set_option("tree_pipeline", 0)
-    assert hctx.get_option("tree_pipeline") == 0
-    for bad in (-1, 2):
+    # S (default 8): the column-blocked tree levels as a wavefront over up to
+    # S of the library's streams; 0 or 1: one level after another
+    assert hctx.get_option("tree_pipeline") == 8
+    for v in (0, 1, 8, 16):
+        hctx.set_option("tree_pipeline", v)
+        assert hctx.get_option("tree_pipeline") == v
+    for bad in (-1, 17):
         with pytest.raises(api.PylomError):
             hctx.set_option("tree_pipeline", bad)
-    hctx.set_option("tree_pipeline", 1)
+    hctx.set_option("tree_pipeline", 8)

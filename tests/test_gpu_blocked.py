@@ -179,7 +179,7 @@ def test_blocked_mixed_tree_levels(mixed_tree):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_blocked_tree_wavefront_matches_serial(precision):
     # 37 leaves (6 tree levels, ragged) of a 3-panel problem: the wavefront
-    # tree over the library's streams (tree_pipeline = 1) runs the same
+    # tree over four of the library's streams (tree_pipeline = 4) runs the same
     # kernels on the same operands as the serial levels, so every output is
     # bit-identical; both are also held to the oracle.
     m, n, b = 9300, 150, 250
@@ -190,7 +190,7 @@ def test_blocked_tree_wavefront_matches_serial(precision):
         D = D.astype(np.float32)
     r = 0.02
     ser = run_blocked(D, True, r, b, precision=precision, opts={"tree_pipeline": 0})
-    pip = run_blocked(D, True, r, b, precision=precision, opts={"tree_pipeline": 1})
+    pip = run_blocked(D, True, r, b, precision=precision, opts={"tree_pipeline": 4})
     assert ser["nr"] == pip["nr"]
     np.testing.assert_array_equal(pip["S"], ser["S"])
     np.testing.assert_array_equal(pip["VT"][:pip["nr"]], ser["VT"][:ser["nr"]])
