@@ -214,9 +214,9 @@ TRAFFIC = {
     # blocks 8192: mean over the 28 launches of one mixed call
     "blocked_trailing_fp32": {
         "sources": ("blocked.hip", "common.hpp"),
-        "sources_sha256": "d130dda91ab02719273a350d6470c7d90963f4889d613f9de02af993cfe0a61f",
+        "sources_sha256": "75e6e080d46d8080999a088c8f6fd96206012b641062f304d55639085f540e2e",
         "shape": (4194304, 1808, 8192),
-        "bytes": 33521389753,  # FETCH 5.115e+11 (x1.99992) + WRITE 4.271e+11 (x1.0), / 28
+        "bytes": 33617105460,  # FETCH 5.139e+11 (x1.99992) + WRITE 4.274e+11 (x1.0), / 28
     },
 }
 
