@@ -157,6 +157,89 @@ __global__ __launch_bounds__(256) void k_matmul_tn_partial(int64_t m, int64_t p,
   }
 }
 
+// Symmetric products C = A^T A with p <= 128 columns (the Gram matrix of the
+// mixed refinement, Z^T Z): each workgroup reads its slice of rows once, in
+// 32-row slabs staged in LDS, and its four waves share the NB (NB + 1) / 2
+// upper 16 x 16 blocks (wave w takes blocks w, w + 4, ...); each block is
+// written with its mirror.  Slices, slabs and the 4-row MFMA steps follow the
+// same row order as k_matmul_tn_partial, and the same reduce sums the slices.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_gram_partial(int64_t m, int64_t p,
+                                                      const T* __restrict__ A, int64_t lda,
+                                                      double* __restrict__ part, int64_t nsplit) {
+  constexpr int W = 16 * NB;
+  constexpr int LD = W + 1;
+  constexpr int NBLK = NB * (NB + 1) / 2;
+  constexpr int MB = (NBLK + 3) / 4;          // blocks per wave
+  constexpr int EL = (MK * W + 255) / 256;    // slab values per thread
+  __shared__ double Zs[MK * LD];
+  typedef Mfma<double>::v4 v4;
+  const int64_t split = blockIdx.x;
+  const int64_t rows_per = (m + nsplit - 1) / nsplit;
+  const int64_t k0 = split * rows_per;
+  const int64_t k1 = (k0 + rows_per < m) ? k0 + rows_per : m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  // this wave's blocks (bi <= bj), in the order b = wave, wave + 4, ...
+  int bi[MB], bj[MB];
+#pragma unroll
+  for (int u = 0; u < MB; ++u) {
+    int b = wave + 4 * u, r = 0;
+    while (r < NB && b >= NB - r) {
+      b -= NB - r;
+      ++r;
+    }
+    bi[u] = r;
+    bj[u] = r + b;  // r == NB when the wave has no block u
+  }
+  v4 acc[MB];
+#pragma unroll
+  for (int u = 0; u < MB; ++u) acc[u] = vzero4<double>();
+  const int pw = (int)p;
+  double pv[EL];
+  auto fetch = [&](int64_t kk) {
+#pragma unroll
+    for (int e = 0; e < EL; ++e) {
+      const int idx = tid + 256 * e;
+      const int r = idx / W, c = idx - (idx / W) * W;
+      const int64_t gr = kk + r;
+      pv[e] = (idx < MK * W && gr < k1 && c < pw) ? (double)A[gr * lda + c] : 0.0;
+    }
+  };
+  if (k0 < k1) fetch(k0);
+  for (int64_t kk = k0; kk < k1; kk += MK) {
+#pragma unroll
+    for (int e = 0; e < EL; ++e) {
+      const int idx = tid + 256 * e;
+      if (idx < MK * W) Zs[(idx / W) * LD + idx % W] = pv[e];
+    }
+    __syncthreads();
+    if (kk + MK < k1) fetch(kk + MK);
+#pragma unroll
+    for (int kb = 0; kb < MK; kb += 4) {
+      const double* zr = Zs + (kb + g4) * LD + i16;
+#pragma unroll
+      for (int u = 0; u < MB; ++u)
+        if (bi[u] < NB) acc[u] = Mfma<double>::op(zr[16 * bi[u]], zr[16 * bj[u]], acc[u]);
+    }
+    __syncthreads();
+  }
+  double* out = part + split * p * p;
+#pragma unroll
+  for (int u = 0; u < MB; ++u) {
+    if (bi[u] >= NB) continue;
+    const int64_t j = 16 * bj[u] + i16;
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int64_t i = 16 * bi[u] + Mfma<double>::drow(g4, qq);
+      if (i < p && j < p) {
+        out[i * p + j] = acc[u][qq];
+        out[j * p + i] = acc[u][qq];
+      }
+    }
+  }
+}
+
 // Small products (p, q <= 32): one wave per 16x16 tile of C and slice of
 // rows, operands read straight from memory (a 64x64 tile would idle most of
 // its MFMA work and staging on such shapes).
@@ -218,10 +301,44 @@ int64_t matmul_tn_splits(int64_t m, int64_t p, int64_t q) {
   return s;
 }
 
+template <typename T>
+static void launch_gram(int nb, int64_t m, int64_t p, const T* A, int64_t lda, double* partial,
+                        int64_t nsplit, hipStream_t st) {
+  const dim3 grid((unsigned)nsplit), block(256);
+  switch (nb) {
+    case 3:
+      hipLaunchKernelGGL((k_gram_partial<T, 3>), grid, block, 0, st, m, p, A, lda, partial, nsplit);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_gram_partial<T, 4>), grid, block, 0, st, m, p, A, lda, partial, nsplit);
+      break;
+    case 5:
+      hipLaunchKernelGGL((k_gram_partial<T, 5>), grid, block, 0, st, m, p, A, lda, partial, nsplit);
+      break;
+    case 6:
+      hipLaunchKernelGGL((k_gram_partial<T, 6>), grid, block, 0, st, m, p, A, lda, partial, nsplit);
+      break;
+    case 7:
+      hipLaunchKernelGGL((k_gram_partial<T, 7>), grid, block, 0, st, m, p, A, lda, partial, nsplit);
+      break;
+    default:
+      hipLaunchKernelGGL((k_gram_partial<T, 8>), grid, block, 0, st, m, p, A, lda, partial, nsplit);
+      break;
+  }
+}
+
 hipError_t launch_matmul_tn(int f64, int64_t m, int64_t p, int64_t q, const void* A, int64_t lda,
                             const void* B, int64_t ldb, void* C, int64_t ldc, double* partial,
                             int64_t nsplit, hipStream_t st) {
-  if (matmul_small(p, q)) {
+  if (A == B && lda == ldb && p == q && p > 32 && p <= 128) {
+    // A^T A: the symmetric kernel, on the slices the caller planned for the
+    // tiled kernel
+    const int nb = (int)((p + 15) / 16);
+    if (f64)
+      launch_gram<double>(nb, m, p, (const double*)A, lda, partial, nsplit, st);
+    else
+      launch_gram<float>(nb, m, p, (const float*)A, lda, partial, nsplit, st);
+  } else if (matmul_small(p, q)) {
     const int64_t tiles = ((p + 15) / 16) * ((q + 15) / 16);
     const dim3 grid((unsigned)(tiles * nsplit));
     if (f64)

@@ -187,6 +187,29 @@ def test_matmul_exact_integers():
             assert np.array_equal(C2.cpu().numpy().astype(np.float64), ref2)
 
 
+@pytest.mark.parametrize("p", [33, 67, 128])
+def test_matmul_gram_exact_integers(p):
+    # A^T A with the same buffer for both operands and 33 <= p <= 128 takes
+    # the symmetric kernel (upper 16 x 16 blocks written with their mirror):
+    # integers make every partial sum exact, so C equals the oracle's
+    # product bit for bit, is exactly symmetric, and equals the tiled
+    # kernel's A^T B on a copy B of A.
+    torch = _torch()
+    from paper_2405_15529_amd import api
+    rng = np.random.default_rng(40 + p)
+    for dt in (np.float64, np.float32):
+        m = 30011
+        say(f"[gpu] gram {dt.__name__} {m}x{p}")
+        A = rng.integers(-8, 9, size=(m, p)).astype(dt)
+        Ag = torch.from_numpy(A).cuda()
+        C = api.matmul(Ag, Ag, trans_a=True).cpu().numpy().astype(np.float64)
+        ref = oracle.matmul(A.astype(np.float64), A.astype(np.float64), trans_a=True)
+        assert np.array_equal(C, ref)
+        assert np.array_equal(C, C.T)
+        Ct = api.matmul(Ag, Ag.clone(), trans_a=True).cpu().numpy().astype(np.float64)
+        assert np.array_equal(C, Ct)
+
+
 def test_max_sweeps_zero_reports_nonconvergence():
     torch = _torch()
     from paper_2405_15529_amd import api
