@@ -120,8 +120,8 @@ int pylom_set_stream(pylom_ctx ctx, void* hip_stream);
  *   "blocked_from" n at which pod/tsvd/tsqr switch to the column-blocked
  *                  TSQR (2..2049), or 0 (default) for the automatic choice:
  *                  column-blocked when n >= 512, or when n >= 64 and
- *                  m <= 8,388,608; the stacked QR otherwise (and for every
- *                  instance of pylom_pod_batched with n <= 1024).  On the
+ *                  m <= 8,388,608; the stacked QR otherwise (instances of
+ *                  pylom_pod_batched follow the same rule).  On the
  *                  column-blocked path every leaf and every tree combine is a
  *                  blocked Householder QR over panels of 64 columns (the
  *                  local QR of Alg. 1 as LAPACK blocks it), the leaf height
@@ -278,8 +278,7 @@ int pylom_matmul_noalloc(pylom_ctx ctx, pylom_dtype dtype, pylom_prec prec, int 
 
 /* One instance of a batched POD (the arguments of pylom_pod). */
 typedef struct {
-  int64_t m, n;        /* shape, m >= n >= 1, n <= 1024 and, when the
-                          "blocked_from" option is set, n < blocked_from     */
+  int64_t m, n;        /* shape, m >= n >= 1, n <= 2048 (as pylom_pod)      */
   const void* D;       /* m x n snapshots (storage type of the batch), ldd   */
   int64_t ldd;
   int remove_mean;     /* Alg. 2 mean removal                                 */
@@ -297,8 +296,10 @@ typedef struct {
  * for each), with the same dtype and precision.  `problems` is a host array
  * of `count` descriptors; every pointer inside is a device pointer, as for
  * pylom_pod, and the results are those of `count` pylom_pod calls.
- * Each instance's leaf height is the "block_rows" option when set, else the
- * library's autotuned choice (see pylom_tune_block_rows).  Instances are
+ * Each instance takes the TSQR of the "blocked_from" rule (stacked or
+ * column-blocked) and its leaf height is the "block_rows" option when set,
+ * else the library's autotuned choice (see pylom_tune_block_rows).  Instances
+ * run their tree levels one after another on their own stream.  Instances are
  * spread over "streams" (option, default 4) concurrent HIP streams with
  * workspaces of their own, forked from and joined back into the context
  * stream.  use_graph != 0 captures the whole launch sequence into a HIP graph

@@ -147,3 +147,46 @@ def test_batched_wide_jacobi_grids_are_chained():
     assert ctx.status()[0] == 0
     assert ctx.get_option("batch_jacobi_chained") == 0
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_wide_instance_on_blocked_path(precision):
+    # an instance wider than the stacked QR factors (n = 1100) beside a
+    # narrow one: the wide one takes the column-blocked TSQR inside the
+    # batch, eagerly and through the graph (two replays); checked against
+    # the exact spectrum (mixed: FP32 data, the normwise bar of the mixed
+    # tests) and for orthogonality
+    import torch
+    from paper_2405_15529_amd import api, synth
+    shapes = [(4400, 1100), (3000, 40)]
+    say(f"[gpu] batched wide instance {precision} {shapes}")
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    Ds, specs = [], []
+    for i, (m, n) in enumerate(shapes):
+        s = 10.0 ** (-np.arange(n) / (n / 4.0))
+        A, _, _ = synth.known_spectrum(m, n, s, seed=500 + i)
+        Ds.append(torch.from_numpy(A).to(dt).cuda())
+        specs.append(s)
+    ctx = api.Context(0)
+    for use_graph in (False, True):
+        batch = api.PodBatch(Ds, r=0.01, precision=precision, use_graph=use_graph, ctx=ctx)
+        for rep in range(2 if use_graph else 1):
+            batch.run()
+            rc, _ = ctx.status()
+            assert rc == 0, rc
+            for res, s, (m, n) in zip(batch.results(), specs, shapes):
+                S = res.S.cpu().numpy()
+                nw = np.max(np.abs(S - s)) / s[0]
+                k = res.nr
+                U = res.U_full[:, :k].double()
+                oe = torch.linalg.norm(U.T @ U - torch.eye(k, dtype=torch.float64,
+                                                           device=U.device)).item()
+                say(f"  n={n} graph={use_graph} N_r={k} sigma normwise {nw:.2e} "
+                    f"|U^T U - I|_F {oe:.2e}")
+                if precision == "fp64":
+                    assert nw <= 1e-12
+                    assert oe <= 10.0 * n ** 1.5 * 2.0 ** -53
+                else:
+                    assert nw <= 1e-6
+                    assert oe <= 1e-6
+    ctx.close()
