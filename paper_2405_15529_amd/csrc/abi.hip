@@ -902,10 +902,12 @@ static int jac_after(pylom_ctx c, const Exec& x, const JacobiPlan& jp) {
 // factorisation.  With option mixed_svd_tol = 1 the rotation test stops at
 // 2^-24 instead of n 2^-53.  The leading right singular vectors only seed
 // the Rayleigh-Ritz refinement against D, which sets the accuracy of the
-// result.
+// result, and forms U from D itself: the left factor U_R of R is not used,
+// so the Jacobi does not accumulate it.
 static JacobiPlan mixed_first_jp(const pylom_ctx_s* c, const JacobiPlan& jp) {
   JacobiPlan j = jp;
   if (c->mixed_svd_tol == 1) j.tol = 0x1p-24;
+  j.no_ur = 1;
   return j;
 }
 

@@ -177,6 +177,7 @@ struct JacobiPlan {
   int block;  // 1: block Jacobi of 16-column blocks (n > 256)
   int ks;     // workgroups per block pair (block Jacobi; grid = G * ks)
   double tol = 0.0;  // rotation threshold on the cosine of a column pair (0: n 2^-53)
+  int no_ur = 0;     // 1: the caller needs no U_R (launch_small_svd then leaves UR unwritten)
 };
 bool jacobi_plan(int n, JacobiPlan* p);
 double jacobi_tol(const JacobiPlan& p);
@@ -188,7 +189,8 @@ int jacobi_resident_per_cu(const JacobiPlan& p);
 // row-major, ldvt), UR (n x n row-major, ld n; the left factor, sign
 // convention applied) and N_r (device) for residual r; status[0] = sweeps
 // (-1 if not converged, -2 if a singular value is not finite: a non-finite
-// input), status[1] = barrier timeout flag.
+// input), status[1] = barrier timeout flag.  With p.no_ur, UR is not written
+// and the block Jacobi (n > 256) does not accumulate it.
 // coop = false uses a plain launch (for stream capture).
 hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps, void* ws,
                             double* S, double* VT, int64_t ldvt, double* UR, double residual,

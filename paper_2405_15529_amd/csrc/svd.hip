@@ -46,6 +46,7 @@ double jacobi_tol(const JacobiPlan& p) { return p.tol > 0.0 ? p.tol : (double)p.
 bool jacobi_plan(int n, JacobiPlan* p) {
   if (n < 1 || n > 2048) return false;
   p->tol = 0.0;
+  p->no_ur = 0;
   p->block = 0;
   p->ks = 1;
   if (n > kBlockJacobiFrom) {
@@ -536,6 +537,9 @@ __device__ __forceinline__ double rot_cos(double t) {
   return y;
 }
 
+// UV: the rotations are accumulated into V (J, the left factor U_R of R);
+// without UV, V is left as it is (callers that need only sigma and V of R).
+template <bool UV>
 __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
   typedef Mfma<double>::v4 v4;
   constexpr int LD = 33;
@@ -738,7 +742,7 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
           __syncthreads();
         }
         if (kq == 0 && myrot) atomicAdd(&rot_count, myrot);
-        // ---- X_p <- X_p W and V_p <- V_p W on this workgroup's tiles; wave w
+        // ---- X_p <- X_p W and (UV) V_p <- V_p W on this workgroup's tiles; wave w
         // takes the tiles t0 + w, t0 + w + 4, ...; B operand W[4 s + g4][16 h + i16]
         double wb[2][8];
 #pragma unroll
@@ -756,10 +760,11 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
         // for loads issued after stores (a single counter tracks both, in
         // issue order)
         constexpr int TMX = 8;
+        constexpr int NBUF = UV ? 2 : 1;
         for (int base = t0 + wave; base < t1; base += 4 * TMX) {
-          double xv[2][TMX][8];
+          double xv[NBUF][TMX][8];
 #pragma unroll
-          for (int buf = 0; buf < 2; ++buf) {
+          for (int buf = 0; buf < NBUF; ++buf) {
             const double* X = buf ? a.V : a.A;
 #pragma unroll
             for (int jt = 0; jt < TMX; ++jt) {
@@ -770,7 +775,7 @@ __global__ __launch_bounds__(256) void k_bjacobi(BJArgs a) {
             }
           }
 #pragma unroll
-          for (int buf = 0; buf < 2; ++buf) {
+          for (int buf = 0; buf < NBUF; ++buf) {
             double* X = buf ? a.V : a.A;
 #pragma unroll
             for (int jt = 0; jt < TMX; ++jt) {
@@ -830,7 +835,7 @@ __global__ __launch_bounds__(FT) void k_svd_finalize(int n, const double* __rest
     V = (const double*)((const char*)V + pb * sWs);
     S += pb * sS;
     VT += pb * sVT;
-    UR += pb * sUR;
+    if (UR) UR += pb * sUR;
     nr += pb;
     status += 2 * pb;
   }
@@ -873,7 +878,7 @@ __global__ __launch_bounds__(FT) void k_svd_finalize(int n, const double* __rest
     const int rj = rank[j];
     const double sj = sig[j];
     VT[(int64_t)rj * ldvt + i] = (sj > 0.0) ? sgn[j] * A[(int64_t)j * n + i] / sj : 0.0;
-    UR[(int64_t)i * n + rj] = sgn[j] * V[(int64_t)j * n + i];
+    if (UR) UR[(int64_t)i * n + rj] = sgn[j] * V[(int64_t)j * n + i];
   }
   __syncthreads();
   if (tid == 0) {
@@ -929,7 +934,7 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
     b.V = w.V; b.bar = w.bar; b.flags = w.flags; b.pairc = w.pairc; b.gp = w.gp;
     b.status = status;
     void* args[] = {&b};
-    const void* fn = (const void*)k_bjacobi;
+    const void* fn = p.no_ur ? (const void*)k_bjacobi<false> : (const void*)k_bjacobi<true>;
     const dim3 grid((unsigned)(p.G * p.ks));
     e = coop ? hipLaunchCooperativeKernel(fn, grid, dim3(256), args, 0, st)
              : hipLaunchKernel(fn, grid, dim3(256), args, 0, st);
@@ -965,8 +970,10 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
     }
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_svd_finalize, dim3(1), dim3(FT), 0, st, p.n, w.A, w.V, S, VT, ldvt, UR,
-                     residual, nr, (int64_t)0, (int64_t)0, (int64_t)0, (int64_t)0, status);
+  // without U_R (no_ur) the block Jacobi leaves V unrotated: nothing to write
+  hipLaunchKernelGGL(k_svd_finalize, dim3(1), dim3(FT), 0, st, p.n, w.A, w.V, S, VT, ldvt,
+                     p.no_ur ? nullptr : UR, residual, nr, (int64_t)0, (int64_t)0, (int64_t)0,
+                     (int64_t)0, status);
   return hipGetLastError();
 }
 
@@ -974,7 +981,7 @@ int jacobi_resident_per_cu(const JacobiPlan& p) {
   const void* fn = nullptr;
   if (p.block) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_bjacobi, 256, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_bjacobi<true>, 256, 0) !=
             hipSuccess ||
         nb < 1) {
       (void)hipGetLastError();
