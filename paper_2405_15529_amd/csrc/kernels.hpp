@@ -190,7 +190,7 @@ int jacobi_resident_per_cu(const JacobiPlan& p);
 // convention applied) and N_r (device) for residual r; status[0] = sweeps
 // (-1 if not converged, -2 if a singular value is not finite: a non-finite
 // input), status[1] = barrier timeout flag.  With p.no_ur, UR is not written
-// and the block Jacobi (n > 256) does not accumulate it.
+// and the Jacobi does not accumulate it.
 // coop = false uses a plain launch (for stream capture).
 hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps, void* ws,
                             double* S, double* VT, int64_t ldvt, double* UR, double residual,

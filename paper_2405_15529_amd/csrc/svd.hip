@@ -304,6 +304,7 @@ __device__ __forceinline__ void store_col(const double (&x)[JR], double* __restr
 
 struct JacobiArgs {
   int n, npad, w, G, xcd_stride, max_sweeps;
+  int uv;      // 1: accumulate the rotations into V (U_R); 0: V is not touched
   double tol;  // rotation test: |a_p . a_q| > tol |a_p| |a_q|
   double* A;
   double* V;
@@ -335,6 +336,7 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
   const int grp = tid / LPP, sub = tid % LPP;
   const int rpl = (n + LPP - 1) / LPP;
   const double tol = a.tol;
+  const int rv = a.uv ? rpl : 0;  // V rows per lane that the rotations update
   const int nplayers = 2 * a.G;
   unsigned int epoch = 0;
   double ca[JR], cva[JR], cb[JR], cvb[JR];
@@ -388,15 +390,19 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
         const int c1 = rr_player(pi, q, w), c2 = rr_player(w - 1 - pi, q, w);
         const int j1 = which * w + c1, j2 = which * w + c2;
         load_col<LPP, JR>(ca, a.A + (int64_t)j1 * n, n, sub);
-        load_col<LPP, JR>(cva, a.V + (int64_t)j1 * n, n, sub);
         load_col<LPP, JR>(cb, a.A + (int64_t)j2 * n, n, sub);
-        load_col<LPP, JR>(cvb, a.V + (int64_t)j2 * n, n, sub);
+        if (a.uv) {
+          load_col<LPP, JR>(cva, a.V + (int64_t)j1 * n, n, sub);
+          load_col<LPP, JR>(cvb, a.V + (int64_t)j2 * n, n, sub);
+        }
         double na = col_norm2<LPP, JR>(ca, rpl), nb = col_norm2<LPP, JR>(cb, rpl);
-        myrot += jacobi_pair<LPP, JR>(ca, cva, cb, cvb, na, nb, rpl, rpl, tol);
+        myrot += jacobi_pair<LPP, JR>(ca, cva, cb, cvb, na, nb, rpl, rv, tol);
         store_col<LPP, JR>(ca, a.A + (int64_t)j1 * n, n, sub);
-        store_col<LPP, JR>(cva, a.V + (int64_t)j1 * n, n, sub);
         store_col<LPP, JR>(cb, a.A + (int64_t)j2 * n, n, sub);
-        store_col<LPP, JR>(cvb, a.V + (int64_t)j2 * n, n, sub);
+        if (a.uv) {
+          store_col<LPP, JR>(cva, a.V + (int64_t)j1 * n, n, sub);
+          store_col<LPP, JR>(cvb, a.V + (int64_t)j2 * n, n, sub);
+        }
         __syncthreads();
       }
     }
@@ -405,38 +411,44 @@ __global__ __launch_bounds__(JT) void k_jacobi(JacobiArgs a) {
       const int blk_a = rr_player(g, st, nplayers), blk_b = rr_player(nplayers - 1 - g, st, nplayers);
       const int ja = blk_a * w + grp;
       load_col<LPP, JR>(ca, a.A + (int64_t)ja * n, n, sub);
-      load_col<LPP, JR>(cva, a.V + (int64_t)ja * n, n, sub);
       load_col<LPP, JR>(cb, a.A + (int64_t)(blk_b * w + grp) * n, n, sub);
-      load_col<LPP, JR>(cvb, a.V + (int64_t)(blk_b * w + grp) * n, n, sub);
+      if (a.uv) {
+        load_col<LPP, JR>(cva, a.V + (int64_t)ja * n, n, sub);
+        load_col<LPP, JR>(cvb, a.V + (int64_t)(blk_b * w + grp) * n, n, sub);
+      }
       double na = col_norm2<LPP, JR>(ca, rpl), nb = col_norm2<LPP, JR>(cb, rpl);
       for (int q = 0; q < w; ++q) {
-        myrot += jacobi_pair<LPP, JR>(ca, cva, cb, cvb, na, nb, rpl, rpl, tol);
+        myrot += jacobi_pair<LPP, JR>(ca, cva, cb, cvb, na, nb, rpl, rv, tol);
         if (q < w - 1) {
           // pass my b column to group grp-1, take the one of group grp+1; with
           // two alternating buffers one barrier per round suffices
           double* xb = xbuf[q & 1];
           // k-major slots: consecutive lanes touch consecutive doubles
 #pragma unroll
-          for (int k = 0; k < JR; ++k) {
-            xb[k * JT + tid] = cb[k];
-            xb[(JR + k) * JT + tid] = cvb[k];
+          for (int k = 0; k < JR; ++k) xb[k * JT + tid] = cb[k];
+          if (a.uv) {
+#pragma unroll
+            for (int k = 0; k < JR; ++k) xb[(JR + k) * JT + tid] = cvb[k];
           }
           if (sub == 0) xnorm[q & 1][grp] = nb;
           __syncthreads();
           const int src = (grp + 1) % w;
 #pragma unroll
-          for (int k = 0; k < JR; ++k) {
-            cb[k] = xb[k * JT + src * LPP + sub];
-            cvb[k] = xb[(JR + k) * JT + src * LPP + sub];
+          for (int k = 0; k < JR; ++k) cb[k] = xb[k * JT + src * LPP + sub];
+          if (a.uv) {
+#pragma unroll
+            for (int k = 0; k < JR; ++k) cvb[k] = xb[(JR + k) * JT + src * LPP + sub];
           }
           nb = xnorm[q & 1][src];
         }
       }
       store_col<LPP, JR>(ca, a.A + (int64_t)ja * n, n, sub);
-      store_col<LPP, JR>(cva, a.V + (int64_t)ja * n, n, sub);
       const int jb = blk_b * w + (grp + w - 1) % w;
       store_col<LPP, JR>(cb, a.A + (int64_t)jb * n, n, sub);
-      store_col<LPP, JR>(cvb, a.V + (int64_t)jb * n, n, sub);
+      if (a.uv) {
+        store_col<LPP, JR>(cva, a.V + (int64_t)ja * n, n, sub);
+        store_col<LPP, JR>(cvb, a.V + (int64_t)jb * n, n, sub);
+      }
       if (st == nplayers - 2) {
         // count rotations of this sweep before the last barrier
         if (sub == 0 && myrot) atomicAdd(&rot_count, myrot);
@@ -942,7 +954,8 @@ hipError_t launch_small_svd(const JacobiPlan& p, const double* R, int max_sweeps
   } else if (max_sweeps > 0) {
     JacobiArgs a;
     a.n = p.n; a.npad = p.npad; a.w = p.w; a.G = p.G; a.xcd_stride = p.xcd_stride;
-    a.max_sweeps = max_sweeps; a.tol = jacobi_tol(p); a.A = w.A; a.V = w.V; a.bar = w.bar;
+    a.max_sweeps = max_sweeps; a.uv = p.no_ur ? 0 : 1; a.tol = jacobi_tol(p); a.A = w.A;
+    a.V = w.V; a.bar = w.bar;
     a.flags = w.flags;
     a.status = status;
     a.sWs = 0;
@@ -1053,7 +1066,8 @@ hipError_t launch_small_svd_batched(const JacobiPlan& p, int64_t count, const do
     // plain launch is enough
     JacobiArgs a;
     a.n = p.n; a.npad = p.npad; a.w = p.w; a.G = 1; a.xcd_stride = 1;
-    a.max_sweeps = max_sweeps; a.tol = jacobi_tol(p); a.A = w.A; a.V = w.V; a.bar = w.bar;
+    a.max_sweeps = max_sweeps; a.uv = p.no_ur ? 0 : 1; a.tol = jacobi_tol(p); a.A = w.A;
+    a.V = w.V; a.bar = w.bar;
     a.flags = w.flags;
     a.status = status_each;
     a.sWs = wsb;
