@@ -31,11 +31,13 @@ def say(msg):
     sys.stdout.flush()
 
 
-def run_mixed(D32, remove_mean, r, block_rows):
+def run_mixed(D32, remove_mean, r, block_rows, opts=None):
     import torch
     from paper_2405_15529_amd import api
     ctx = api.Context(0)
     ctx.set_option("block_rows", block_rows)
+    for k, v in (opts or {}).items():
+        ctx.set_option(k, v)
     Dg = torch.from_numpy(np.ascontiguousarray(D32)).cuda()
     out = api.pod(Dg, remove_mean=remove_mean, r=r, precision="mixed", ctx=ctx)
     rc, sweeps = ctx.status()
@@ -164,3 +166,24 @@ def test_mixed_matches_fp64_gpu_at_scale():
     say(f"    |U^T U - I|_F {oe:.3e}")
     assert oe <= ORTH
     ctx.close()
+
+
+@pytest.mark.parametrize("m,n,b", [(20000, 120, 2000), (9000, 300, 1500)])
+def test_mixed_first_svd_stopping_rules(m, n, b):
+    # the first SVD of R stops at cosines of 2^-24 and accumulates no U_R
+    # (mixed_svd_tol = 1, the default) or runs to n 2^-53 (0): n = 120 uses
+    # the pairwise Jacobi, n = 300 the block Jacobi; both settings meet the
+    # mixed bars against the oracle, and their spectra agree to 1e-6
+    say(f"[gpu] mixed first-SVD stopping rules m={m} n={n} b={b}")
+    rng = np.random.default_rng(m + n)
+    D = rng.standard_normal((m, n)) * np.exp(-np.arange(n) / 15.0)[None, :] + 0.1
+    D32 = D.astype(np.float32)
+    r = 0.01
+    ref = oracle.pod(D32.astype(np.float64), remove_mean=True, r=r)
+    loose = run_mixed(D32, True, r, b, opts={"mixed_svd_tol": 1})
+    tight = run_mixed(D32, True, r, b, opts={"mixed_svd_tol": 0})
+    for g in (loose, tight):
+        assert_mixed_parity(g, ref, r)
+    say(f"    sweeps loose {loose['sweeps']} tight {tight['sweeps']}")
+    k = min(loose["nr"], tight["nr"])
+    assert np.max(np.abs(loose["S"][:k] - tight["S"][:k]) / tight["S"][:k]) <= 1e-6
